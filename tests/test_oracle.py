@@ -1,0 +1,471 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than its own formulas:
+closed forms, continuum limits of the SPH sums on a perfect lattice,
+characteristic relations of the Riemann problem, symmetry and conservation
+invariants, exact (rational / fsum) arithmetic, and brute force.
+"""
+import json
+import math
+import os
+from collections import Counter
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import csph_inputs as ci
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def lattice_state(orc, n, p=1.0, rho=1.0, v=(0.0, 0.0, 0.0), eos=None, search=1, **cfg_over):
+    w = ci.jittered_block(n, n, n, seed=7, amp=0.0, rho=rho, p=p, v=v, eos=eos)
+    cfg = orc.cfg_for(w, search=search, **cfg_over)
+    return w, cfg, orc.state_from(w, cfg)
+
+
+def lattice_index(n):
+    idx = np.arange(n)
+    k, j, i = np.meshgrid(idx, idx, idx, indexing="ij")
+    return np.stack([i.reshape(-1), j.reshape(-1), k.reshape(-1)], 1)
+
+
+# ---------------------------------------------------------------- kernel (sec. 4.1)
+
+@pytest.mark.parametrize("H", [3.0, 1.936, 0.7])
+def test_kernel_normalised(orc, H):
+    """A 3D smoothing kernel integrates to one over its support."""
+    # 4 pi r^2 W(r) is a degree-7 polynomial on [0, H]: 8-point Gauss-Legendre is exact
+    xg, wg = np.polynomial.legendre.leggauss(8)
+    r = 0.5 * H * (xg + 1.0)
+    val = 0.5 * H * sum(wk * 4.0 * math.pi * rk * rk * orc.kernel_w(rk, H) for rk, wk in zip(r, wg))
+    assert abs(val - 1.0) < 1e-13
+    val2, _ = integrate.quad(lambda q: 4.0 * math.pi * q * q * orc.kernel_w(q, H), 0.0, H)
+    assert abs(val2 - 1.0) < 1e-10
+
+
+@pytest.mark.parametrize("H", [3.0, 1.936])
+def test_kernel_derivative_is_dW_dr(orc, H):
+    """W' used in the rates is the r-derivative of W (central differences)."""
+    for q in (0.05, 0.2, 0.37, 0.5, 0.71, 0.9, 0.98):
+        r = q * H
+        dlt = 1e-6 * H
+        fd = (orc.kernel_w(r + dlt, H) - orc.kernel_w(r - dlt, H)) / (2 * dlt)
+        assert abs(orc.kernel_dw(r, H) - fd) < 1e-8 * (1.0 + abs(fd))
+
+
+def test_kernel_compact_support(orc):
+    """W > 0 only for r < kappa*h (sec. 4.1); C2 at the edge: W, W' vanish there."""
+    H = 3.0
+    assert orc.kernel_w(H, H) == 0.0 and orc.kernel_dw(H, H) == 0.0
+    assert orc.kernel_w(H * (1 + 1e-12), H) == 0.0
+    assert orc.kernel_w(H * (1 - 1e-3), H) > 0.0
+    assert orc.kernel_dw(0.0, H) == 0.0
+    assert orc.kernel_dw(0.5 * H, H) < 0.0
+
+
+# ---------------------------------------------------------------- Riemann problem (sec. 4.1)
+
+def test_riemann_identical_states(orc):
+    vs, ps = orc.riemann(1.3, 1.3, 2.0, 2.0, 0.7, 0.7)
+    assert vs == pytest.approx(0.7, abs=1e-15) and ps == pytest.approx(2.0, abs=1e-15)
+
+
+def test_riemann_symmetric_head_on(orc):
+    """Equal states colliding at +-u: contact at rest, pressure raised by Z u."""
+    Z, P, u = 1.7, 0.9, 0.35
+    vs, ps = orc.riemann(Z, Z, P, P, u, -u)
+    assert vs == 0.0
+    assert ps == pytest.approx(P + Z * u, rel=1e-15)
+
+
+def test_riemann_characteristics(orc):
+    """Across the left wave P+Zv is invariant, across the right wave P-Zv is."""
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        ZL, ZR = rng.uniform(0.1, 5.0, 2)
+        PL, PR = rng.uniform(-1.0, 3.0, 2)
+        vL, vR = rng.uniform(-2.0, 2.0, 2)
+        vs, ps = orc.riemann(ZL, ZR, PL, PR, vL, vR)
+        sc = 1 + abs(PL) + abs(PR) + ZL * abs(vL) + ZR * abs(vR)
+        assert abs((ps + ZL * vs) - (PL + ZL * vL)) < 1e-14 * sc
+        assert abs((ps - ZR * vs) - (PR - ZR * vR)) < 1e-14 * sc
+        # reflected problem: swap sides, flip the axis
+        vs2, ps2 = orc.riemann(ZR, ZL, PR, PL, -vR, -vL)
+        assert abs(ps2 - ps) < 1e-14 * sc and abs(vs2 + vs) < 1e-14 * sc
+
+
+def test_riemann_zero_impedance(orc):
+    vs, ps = orc.riemann(0.0, 0.0, 1.0, 3.0, 0.5, -0.1)
+    assert vs == pytest.approx(0.2) and ps == pytest.approx(2.0)
+
+
+# ---------------------------------------------------------------- EOS
+
+@pytest.mark.parametrize("eos,rho,p", [((0, 1.4, 0.0), 1.0, 1.0), ((0, 1.4, 0.0), 0.125, 0.1),
+                                       ((1, 3.0, 1.0 / 3.0), 1.0, 1e-3),
+                                       ((1, 3.0, 10.0 / 3.0 - 1e-3), 10.0, 1e-3)])
+def test_eos_roundtrip_and_isentropic_sound_speed(orc, eos, rho, p):
+    """E built from (rho, p) gives back p; c^2 is dP/drho along an isentrope (de = P/rho^2 drho)."""
+    cfg = orc.make_cfg([eos])
+    one = lambda a: np.array([a], np.float64)
+    z = one(0.0)
+    mat = np.zeros(1, np.int32)
+    E = orc.init_energy(cfg, one(rho), one(p), one(0.3), z, z, mat)
+    st = dict(rho=one(rho), E=E, vx=one(0.3), vy=z, vz=z, mat=mat)
+    P, c, bad = orc.eos(cfg, st)
+    assert bad == 0 and P[0] == pytest.approx(p, rel=1e-12, abs=1e-15)
+    e = E[0] - 0.5 * 0.09
+    d = 1e-6 * rho
+
+    def pres(r, ee):
+        s2 = dict(rho=one(r), E=one(ee + 0.045), vx=one(0.3), vy=z, vz=z, mat=mat)
+        return orc.eos(cfg, s2)[0][0]
+
+    dP = (pres(rho + d, e + p / rho ** 2 * d) - pres(rho - d, e - p / rho ** 2 * d)) / (2 * d)
+    assert c[0] ** 2 == pytest.approx(dP, rel=1e-7)
+
+
+def test_eos_nonphysical_counted(orc):
+    cfg = orc.make_cfg([(1, 3.0, 1.0)])
+    st = dict(rho=np.array([1.0, 1.0]), E=np.array([-5.0, 2.0]), vx=np.zeros(2), vy=np.zeros(2),
+              vz=np.zeros(2), mat=np.zeros(2, np.int32))
+    P, c, bad = orc.eos(cfg, st)
+    assert bad == 1 and c[0] == 0.0 and c[1] > 0
+
+
+# ---------------------------------------------------------------- neighbours (sec. 4.1-4.2)
+
+def test_lattice_neighbour_counts(orc):
+    """Unit lattice: |v|^2 < 9 has 92 non-zero integer vectors, |v|^2 < 1.936^2 has 26."""
+    gold = json.load(open(os.path.join(GOLD, "lattice_counts.json")))
+    n = 12
+    for case in gold["cases"]:
+        w, cfg, s = lattice_state(orc, n, h=case["h"], kappa=case["kappa"], cell_size=0.0)
+        off, idx = orc.neighbors(cfg, s["x"], s["y"], s["z"])
+        cnt = np.diff(off)
+        I = lattice_index(n)
+        inner = np.all((I >= 3) & (I <= n - 4), 1)
+        assert set(cnt[inner].tolist()) == {case["interior_count"]}
+
+
+def test_support_strict(orc):
+    """A pair at exactly the support radius is not a neighbour (W > 0 only for r < kappa h)."""
+    x = np.array([0.0, 3.0, 0.0]); y = np.array([0.0, 0.0, 2.9999999999999996]); z = np.zeros(3)
+    cfg = orc.make_cfg([(0, 1.4, 0.0)])
+    off, idx = orc.neighbors(cfg, x, y, z)
+    assert off.tolist() == [0, 1, 1, 2] and idx.tolist() == [2, 0]
+
+
+@pytest.mark.parametrize("wl", ["cloud", "sod", "wall"])
+def test_grid_search_equals_brute_force(orc, wl):
+    if wl == "cloud":
+        w = ci.random_cloud(3000, seed=11, box=10.0, n_mat=2)
+        d = None
+    elif wl == "sod":
+        w = ci.config0()
+    else:
+        w = ci.jittered_block(10, 9, 8, seed=5, v=(-0.2, 0.1, 0.0))
+        w.wall = (0.0, 0.4)
+    cb = orc.cfg_for(w, search=0)
+    cg = orc.cfg_for(w, search=1)
+    s = orc.state_from(w, cb)
+    ob, ib = orc.neighbors(cb, s["x"], s["y"], s["z"])
+    og, ig = orc.neighbors(cg, s["x"], s["y"], s["z"])
+    assert np.array_equal(ob, og) and np.array_equal(ib, ig)
+    rb = orc.rates(cb, s, t=0.3)
+    rg = orc.rates(cg, s, t=0.3)
+    for k in ("drho", "dvx", "dvy", "dvz", "dE", "signal", "nbr_count"):
+        assert np.array_equal(rb[k], rg[k]), k
+
+
+def test_brute_force_against_pairwise_distances(orc):
+    """Neighbour sets agree with a direct numpy distance matrix (exact in FP64)."""
+    w = ci.random_cloud(400, seed=2, box=5.0)
+    cfg = orc.cfg_for(w)
+    off, idx = orc.neighbors(cfg, w.x, w.y, w.z)
+    dx = w.x[None, :] - w.x[:, None]
+    dy = w.y[None, :] - w.y[:, None]
+    dz = w.z[None, :] - w.z[:, None]
+    r2 = (dx * dx + dy * dy) + dz * dz
+    adj = r2 < 9.0
+    np.fill_diagonal(adj, False)
+    for i in range(w.n):
+        assert idx[off[i]:off[i + 1]].tolist() == np.nonzero(adj[i])[0].tolist()
+    # symmetric relation
+    assert np.array_equal(adj, adj.T)
+
+
+def test_pair_mode_support(orc):
+    """h_ij = (d_i+d_j)/2 (eq. SmoothingLengthDef) with kappa = 1.936."""
+    w = ci.random_cloud(500, seed=4, box=6.0)
+    d = np.random.default_rng(1).uniform(0.8, 1.2, w.n)
+    cfg = orc.cfg_for(w, h_mode=1, kappa=1.936, search=0)
+    off, idx = orc.neighbors(cfg, w.x, w.y, w.z, d)
+    cfg1 = orc.cfg_for(w, h_mode=1, kappa=1.936, search=1, cell_size=0.0)
+    off1, idx1 = orc.neighbors(cfg1, w.x, w.y, w.z, d)
+    assert np.array_equal(off, off1) and np.array_equal(idx, idx1)
+    for i in range(0, w.n, 37):
+        for j in range(w.n):
+            if j == i:
+                continue
+            H = 1.936 * (0.5 * (d[i] + d[j]))
+            r2 = ((w.x[j] - w.x[i]) ** 2 + (w.y[j] - w.y[i]) ** 2) + (w.z[j] - w.z[i]) ** 2
+            assert (j in set(idx[off[i]:off[i + 1]].tolist())) == (r2 < H * H)
+
+
+# ---------------------------------------------------------------- rates (eqs. SPH:Conti/Pulse/Energy)
+
+def test_uniform_lattice_zero_interior_rates(orc):
+    n = 16
+    w, cfg, s = lattice_state(orc, n, p=1.0)
+    r = orc.rates(cfg, s)
+    I = lattice_index(n)
+    inner = np.all((I >= 2) & (I <= n - 3), 1)
+    assert inner.sum() == 1728
+    for k in ("drho", "dvx", "dvy", "dvz", "dE"):
+        assert np.abs(r[k][inner]).max() < 1e-14, k
+    # edge particles feel the free surface
+    assert np.abs(r["dvx"][~inner]).max() > 1e-3
+
+
+def _linear_field(orc, n, A=None, g=None):
+    w, cfg, s = lattice_state(orc, n, p=1.0)
+    pos = np.stack([s["x"], s["y"], s["z"]], 1) - n / 2.0
+    out = []
+    for sign in (1.0, -1.0):
+        s2 = {k: v.copy() for k, v in s.items()}
+        P = np.ones(w.n)
+        if A is not None:
+            v = sign * pos @ A.T
+            s2["vx"], s2["vy"], s2["vz"] = [np.ascontiguousarray(v[:, k]) for k in range(3)]
+        if g is not None:
+            P = P + sign * pos @ g
+        s2["E"] = orc.init_energy(cfg, s2["rho"], np.ascontiguousarray(P), s2["vx"], s2["vy"],
+                                  s2["vz"], s2["mat"])
+        out.append(orc.rates(cfg, s2))
+    I = lattice_index(n)
+    inner = np.all((I >= 3) & (I <= n - 4), 1)
+    lin = {k: 0.5 * (out[0][k] - out[1][k])[inner] for k in ("drho", "dvx", "dvy", "dvz", "dE")}
+    return lin
+
+
+def test_continuity_limit_divergence(orc):
+    """Linear velocity field: drho/dt -> -rho div v and dE/dt -> -(P/rho) div v (continuum limit)."""
+    A = np.array([[1e-3, 5e-4, 0.0], [0.0, 2e-3, -3e-4], [2e-4, 0.0, -4e-3]])
+    lin = _linear_field(orc, 20, A=A)
+    tr = np.trace(A)
+    assert np.allclose(lin["drho"], -tr, rtol=2e-3, atol=0)
+    assert np.allclose(lin["dE"], -tr, rtol=2e-3, atol=0)
+    assert np.abs(lin["dvx"]).max() < 1e-14
+
+
+def test_momentum_limit_pressure_gradient(orc):
+    """Linear pressure field: dv/dt -> -grad P / rho (continuum limit)."""
+    g = np.array([2e-3, -1e-3, 5e-4])
+    lin = _linear_field(orc, 20, g=g)
+    for k, comp in zip(("dvx", "dvy", "dvz"), g):
+        assert np.allclose(lin[k], -comp, rtol=2e-3, atol=0)
+    # residual is third order in g (impedances vary with P); first order would be ~1e-3
+    assert np.abs(lin["drho"]).max() < 1e-6
+
+
+def test_galilean_identity(orc):
+    """Adding u to every velocity (same internal energy) leaves drho, dv and gives dE' = dE + u.dv."""
+    w = ci.random_cloud(1500, seed=8, box=8.0, n_mat=2)
+    cfg = orc.cfg_for(w, search=1)
+    s = orc.state_from(w, cfg)
+    r0 = orc.rates(cfg, s)
+    u = np.array([0.7, -1.1, 0.4])
+    s2 = {k: v.copy() for k, v in s.items()}
+    s2["vx"] = s["vx"] + u[0]; s2["vy"] = s["vy"] + u[1]; s2["vz"] = s["vz"] + u[2]
+    s2["E"] = orc.init_energy(cfg, s["rho"], np.ascontiguousarray(w.p), s2["vx"], s2["vy"],
+                              s2["vz"], s["mat"])
+    r1 = orc.rates(cfg, s2)
+    for k in ("drho", "dvx", "dvy", "dvz"):
+        sc = np.abs(r0[k]).max()
+        assert np.abs(r1[k] - r0[k]).max() < 1e-12 * sc, k
+    pred = r0["dE"] + u[0] * r0["dvx"] + u[1] * r0["dvy"] + u[2] * r0["dvz"]
+    assert np.abs(r1["dE"] - pred).max() < 1e-12 * np.abs(pred).max()
+
+
+def test_conservation_open_boundaries(orc):
+    """Pairwise antisymmetry: sum m dv/dt = 0 and sum m dE/dt = 0 (round-off)."""
+    w = ci.random_cloud(2500, seed=9, box=9.0, vmax=1.0, n_mat=2)
+    cfg = orc.cfg_for(w, search=1)
+    s = orc.state_from(w, cfg)
+    r = orc.rates(cfg, s)
+    m = s["m"]
+    for k in ("dvx", "dvy", "dvz", "dE"):
+        terms = m * r[k]
+        assert abs(orc.exact_sum(terms)) < 1e-13 * np.abs(terms).sum(), k
+
+
+def test_axis_permutation_covariance(orc):
+    w = ci.random_cloud(800, seed=12, box=6.0)
+    cfg = orc.cfg_for(w)
+    s = orc.state_from(w, cfg)
+    r = orc.rates(cfg, s)
+    s2 = dict(s)
+    s2["x"], s2["y"], s2["z"] = s["y"], s["z"], s["x"]
+    s2["vx"], s2["vy"], s2["vz"] = s["vy"], s["vz"], s["vx"]
+    r2 = orc.rates(cfg, s2)
+    for a, b in (("dvx", "dvy"), ("dvy", "dvz"), ("dvz", "dvx"), ("drho", "drho"), ("dE", "dE")):
+        assert np.abs(r2[a] - r[b]).max() < 1e-13 * (1 + np.abs(r[b]).max())
+
+
+# ---------------------------------------------------------------- piston wall (rigid wall of sec. 7.1)
+
+def test_static_wall_continues_uniform_lattice(orc):
+    """Gas at rest against a static wall halfway between layers: mirror partners
+    complete every neighbourhood, so the near-wall particles see no force."""
+    n = 12
+    w, cfg, s = lattice_state(orc, n, p=1.0, wall=(0.0, 0.0))
+    r = orc.rates(cfg, s)
+    I = lattice_index(n)
+    near_wall = (I[:, 0] <= 2) & np.all((I[:, 1:] >= 3) & (I[:, 1:] <= n - 4), 1)
+    assert near_wall.sum() > 0
+    for k in ("drho", "dvx", "dvy", "dvz", "dE"):
+        assert np.abs(r[k][near_wall]).max() < 1e-14, k
+
+
+def test_wall_single_particle(orc):
+    """One particle and its own mirror: the force vanishes where the particle
+    moves off the wall at v_w + P/Z, is affine in v_x, and the wall does work
+    dE/dt = v_w dv_x/dt (no work on a static wall)."""
+    cfg_static = orc.make_cfg([(0, 1.4, 0.0)], wall=(0.0, 0.0))
+    vw = 0.3
+    cfg = orc.make_cfg([(0, 1.4, 0.0)], wall=(0.0, vw))
+    one = lambda a: np.array([a], np.float64)
+
+    def rate(c, vx):
+        s = dict(x=one(0.8), y=one(0.0), z=one(0.0), vx=one(vx), vy=one(0.0), vz=one(0.0),
+                 rho=one(1.0), m=one(1.0), mat=np.zeros(1, np.int32))
+        s["E"] = orc.init_energy(c, s["rho"], one(1.0), s["vx"], s["vy"], s["vz"], s["mat"])
+        return orc.rates(c, s), s
+
+    r0, s0 = rate(cfg_static, 0.0)
+    assert r0["dvx"][0] > 0 and r0["dE"][0] == 0.0
+    vals = [rate(cfg, v)[0]["dvx"][0] for v in (-0.5, 0.0, 0.5)]
+    assert abs((vals[2] - vals[1]) - (vals[1] - vals[0])) < 1e-12 * abs(vals[1])
+    P, c, _ = orc.eos(cfg, s0)
+    Z = s0["rho"][0] * c[0]
+    vx0 = vw + P[0] / Z
+    assert abs(rate(cfg, vx0)[0]["dvx"][0]) < 1e-12 * abs(vals[1])
+    rr, _ = rate(cfg, 0.1)
+    assert rr["dE"][0] == pytest.approx(vw * rr["dvx"][0], rel=1e-13)
+
+
+# ---------------------------------------------------------------- step and dt (Algorithm 1)
+
+def test_step_conserves_and_uniform_gas_dt(orc):
+    w = ci.config0()
+    cfg = orc.cfg_for(w, search=1)
+    s = orc.state_from(w, cfg)
+    t0 = orc.totals(s)
+    s1, t, dt, cnt = orc.step(cfg, s, 0.0)
+    t1 = orc.totals(s1)
+    assert t1[0] == t0[0]
+    for k in (1, 2, 3, 4):
+        assert abs(t1[k] - t0[k]) < 1e-13 * (np.abs(s["m"]).sum() * (1 + np.abs(s["E"]).max()))
+    assert t == dt > 0
+    # uniform gas at rest: signal speed = sound speed everywhere, dt = cfl h / c
+    w2, cfg2, s2 = lattice_state(orc, 8, p=1.0)
+    _, _, dt2, _ = orc.step(cfg2, s2, 0.0)
+    assert dt2 == pytest.approx(0.3 * 1.5 / math.sqrt(1.4), rel=1e-15)
+
+
+def test_step_ballistic_when_rates_vanish(orc):
+    """Isolated particles (no neighbours) keep v, E, rho and move by dt v."""
+    s = dict(x=np.array([0.0, 10.0]), y=np.zeros(2), z=np.zeros(2), vx=np.array([0.5, -0.25]),
+             vy=np.array([0.0, 1.0]), vz=np.zeros(2), rho=np.ones(2), m=np.ones(2),
+             mat=np.zeros(2, np.int32))
+    cfg = orc.make_cfg([(0, 1.4, 0.0)], cfl=0.0)
+    s["E"] = orc.init_energy(cfg, s["rho"], np.ones(2), s["vx"], s["vy"], s["vz"], s["mat"])
+    s1, t, dt, cnt = orc.step(cfg, s, 1.0, dt_in=0.125)
+    assert dt == 0.125 and t == 1.125 and cnt.tolist() == [0, 0]
+    assert s1["x"].tolist() == [0.0625, 10.0 - 0.03125]
+    assert s1["y"].tolist() == [0.0, 0.125]
+    for k in ("vx", "vy", "vz", "rho", "E"):
+        assert np.array_equal(s1[k], s[k])
+
+
+# ---------------------------------------------------------------- binning (sec. 4.2)
+
+def test_binning_definition_and_stable_order(orc):
+    rng = np.random.default_rng(5)
+    D = 0.75
+    n = 700
+    # many points exactly on cell faces relative to the minimum
+    base = rng.integers(0, 9, size=(n, 3)).astype(np.float64) * D
+    base[::3] += rng.uniform(0, D, size=base[::3].shape)
+    x, y, z = [np.ascontiguousarray(base[:, k] + 1.25) for k in range(3)]
+    b = orc.bin(x, y, z, D)
+    o, dims = b["origin"], b["dims"]
+    assert o.tolist() == [x.min(), y.min(), z.min()]
+    for dim, c in zip(range(3), (x, y, z)):
+        ext = Fraction(c.max()) - Fraction(o[dim])
+        assert dims[dim] == int(ext / Fraction(D)) + 1
+    cells = b["cell"]
+    for i in range(n):
+        for dim, c in enumerate((x, y, z)):
+            rel = Fraction(c[i]) - Fraction(o[dim])
+            exact = min(int(rel / Fraction(D)), int(dims[dim]) - 1)
+            assert cells[i, dim] == exact, (i, dim)
+    key = (cells[:, 2].astype(np.int64) * dims[1] + cells[:, 1]) * dims[0] + cells[:, 0]
+    assert np.array_equal(b["key"], key)
+    order = sorted(range(n), key=lambda i: (key[i], i))
+    assert b["perm"].tolist() == order
+    cs = b["cell_start"]
+    assert np.array_equal(cs, np.searchsorted(key[order], np.arange(b["ncell"] + 1), "left"))
+
+
+def test_morton_key_interleaves(orc):
+    x = np.array([0.5, 1.5, 0.5, 0.5, 3.5]); y = np.array([0.5, 0.5, 1.5, 0.5, 2.5])
+    z = np.array([0.5, 0.5, 0.5, 1.5, 3.5])
+    b = orc.bin(x, y, z, 1.0, key_mode=1)
+    # (cx,cy,cz) = (0,0,0),(1,0,0),(0,1,0),(0,0,1),(3,2,3): bits x->0, y->1, z->2
+    assert b["key"].tolist() == [0, 1, 2, 4, 0b111101]
+
+
+# ---------------------------------------------------------------- Voronoi (eq. VoronoiDefinition)
+
+def test_voronoi_exact_with_ties(orc):
+    rng = np.random.default_rng(17)
+    sites = np.array([[0.0, 0.0, 0.0], [2.0, 0.0, 0.0], [0.0, 2.0, 0.0], [1.0, 1.0, 1.0]])
+    # points on bisectors (exact ties) and random points
+    pts = [[1.0, 0.0, 0.0], [1.0, 1.0, -1.0], [2.0, 2.0, -3.0], [1.0, 0.5, 0.5]]
+    pts += rng.uniform(-1, 3, size=(300, 3)).tolist()
+    P = np.array(pts)
+    x, y, z = [np.ascontiguousarray(P[:, k]) for k in range(3)]
+    cnt = rng.integers(0, 50, size=len(P)).astype(np.int64)
+    owner, sp, spairs = orc.voronoi(x, y, z, sites, cnt)
+    for i, p in enumerate(pts):
+        d = [sum((Fraction(p[a]) - Fraction(s[a])) ** 2 for a in range(3)) for s in sites]
+        best = min(range(len(sites)), key=lambda k: (d[k], k))
+        assert owner[i] == best
+    # exact ties: {0,1} -> 0, {0,1,2} -> 0, {1,2} -> 1
+    assert owner[:3].tolist() == [0, 0, 1]
+    c = Counter(owner.tolist())
+    assert sp.tolist() == [c.get(k, 0) for k in range(4)]
+    assert spairs.tolist() == [int(cnt[owner == k].sum()) for k in range(4)]
+
+
+# ---------------------------------------------------------------- exact totals
+
+def test_totals_exact(orc):
+    rng = np.random.default_rng(0)
+    n = 5000
+    s = dict(m=rng.uniform(0.5, 2, n), vx=rng.normal(size=n) * 1e3, vy=rng.normal(size=n),
+             vz=rng.normal(size=n) * 1e-5, E=rng.uniform(0, 1e8, n))
+    t = orc.totals(s)
+    m = s["m"]
+    assert t[0] == math.fsum(m)
+    assert t[1] == math.fsum(m * s["vx"])
+    assert t[2] == math.fsum(m * s["vy"])
+    assert t[3] == math.fsum(m * s["vz"])
+    assert t[4] == math.fsum(m * s["E"])
+    big = np.array([1e100, 1.0, -1e100, 1e-30])
+    assert orc.exact_sum(big) == math.fsum(big.tolist())
