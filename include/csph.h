@@ -1,0 +1,235 @@
+/*
+ * csph.h - C ABI of the MI355X (gfx950) contact-SPH hot-path library.
+ *
+ * The library computes the per-step particle interaction of the contact SPH
+ * (CSPH) method of Egorova, Dyachkov, Parshikov & Zhakhovsky,
+ * arXiv 1805.05128:
+ *   - uniform cubic mesh binning and cell-ordered numbering (sec. 4.2,
+ *     eq. Dcell and the linked-list cells / renumbering paragraphs);
+ *   - neighbour sets inside the finite support radius (sec. 4.1);
+ *   - the pairwise Riemann-solver rates of eqs. SPH:Conti, SPH:Pulse and
+ *     SPH:Energy with the Wendland C2 kernel (sec. 4.1);
+ *   - the state update and global time step (Algorithm 1, "renew particle
+ *     positions and states and make global synchronization of SPH time
+ *     step");
+ *   - Voronoi ownership (eq. VoronoiDefinition, ties to the smaller index,
+ *     sec. 3.1) and per-subdomain load counts;
+ *   - hand-written adjoints (vector-Jacobian products) of the rates and of
+ *     the step.
+ *
+ * Conventions shared by every entry point
+ *   Pointers.   Array arguments are DEVICE pointers owned by the caller unless
+ *               a comment says "host".  The library never allocates device
+ *               memory: scratch comes from a caller-provided workspace
+ *               (ws, ws_bytes).  When the workspace is too small the call
+ *               returns CSPH_ECAPACITY and, if ws_needed is not NULL, writes
+ *               the required size there (host).  Workspace contents do not
+ *               persist between calls.
+ *   Layout.     Structure of arrays, FP64, one entry per particle, particle
+ *               count n < 2^31; particle indices are int32.
+ *   Streams.    Work is enqueued on `stream` (a hipStream_t; NULL = default
+ *               stream).  Calls that must learn a size on the host (mesh
+ *               dimensions, neighbour count) synchronise that stream; the
+ *               others return as soon as the work is enqueued.
+ *   Errors.     Every call returns a csph_status.  CSPH_EINVAL: a bad
+ *               argument (NULL where required, n < 0, bad parameters);
+ *               CSPH_ECAPACITY: an output or workspace is too small;
+ *               CSPH_EDEVICE: a HIP runtime error.  Nothing is written on
+ *               EINVAL.  csph_last_error() returns a thread-local message.
+ *               Non-physical states (negative or NaN squared sound speed)
+ *               are counted on the device, never trapped.
+ */
+#ifndef CSPH_H
+#define CSPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t csph_status;
+#define CSPH_OK 0
+#define CSPH_EINVAL 1
+#define CSPH_ECAPACITY 2
+#define CSPH_EDEVICE 3
+
+typedef void *csph_stream; /* hipStream_t */
+
+#define CSPH_MAX_EOS 8
+#define CSPH_EOS_IDEAL 0     /* P = (gamma-1) rho e,            c^2 = gamma P / rho          */
+#define CSPH_EOS_STIFFENED 1 /* P = (gamma-1) rho e - gamma P_inf, c^2 = gamma (P+P_inf) / rho */
+
+#define CSPH_FP64 0  /* every operation in FP64 */
+#define CSPH_MIXED 1 /* pair arithmetic in FP32; positions, EOS, integration, totals FP64 */
+
+#define CSPH_H_FIXED 0 /* support H = kappa*h for every pair */
+#define CSPH_H_PAIR 1  /* H_ij = kappa*(d_i+d_j)/2, d_i given per particle (eq. SmoothingLengthDef) */
+
+typedef struct {
+    int32_t type;   /* CSPH_EOS_* */
+    int32_t pad;
+    double gamma;   /* adiabatic index */
+    double p_inf;   /* stiffening pressure (stiffened gas only) */
+} csph_eos;
+
+typedef struct {
+    int32_t precision; /* CSPH_FP64 | CSPH_MIXED */
+    int32_t h_mode;    /* CSPH_H_FIXED | CSPH_H_PAIR */
+    double h;          /* smoothing length (fixed mode); CFL length in both modes when > 0 */
+    double kappa;      /* support radius in units of h (2 for the workloads, 1.936 in sec. 4.1) */
+    double cell_size;  /* mesh cell D; <= 0 selects D = maximum support.  D may be smaller than
+                          the support: the stencil then reaches ceil(H/D) cells each way */
+    double cfl;        /* > 0: dt = cfl * min_i h_i / s_i (s_i the pair signal speed);
+                          <= 0: the caller's dt is used */
+    int32_t n_eos;     /* materials 0..n_eos-1; mat[i] selects eos[mat[i]] */
+    int32_t wall;      /* 1: rigid piston plane x = wall_x0 + wall_v t, fluid at x > plane,
+                          handled by mirror partners (every particle must stay at x >= plane) */
+    double wall_x0;
+    double wall_v;
+    csph_eos eos[CSPH_MAX_EOS];
+    int32_t reorder;   /* csph_step: 1 = write the new state in cell order (renumbering of
+                          sec. 4.2; `id` is carried along); 0 = keep the input order */
+    int32_t pad;
+} csph_params;
+
+/* Particle state.  x..m: FP64 arrays of n entries.  mat: int32 material id
+ * (NULL = material 0).  d: particle size d_i = (m_i/rho_i)^(1/3) used only
+ * when h_mode = CSPH_H_PAIR (NULL otherwise).  id: optional int64 label
+ * permuted together with the state when csph_step reorders. */
+typedef struct {
+    int64_t n;
+    double *x, *y, *z;
+    double *vx, *vy, *vz;
+    double *rho;  /* density */
+    double *E;    /* specific total energy E = e + |v|^2/2 (conservative form, eq. SPH:Energy) */
+    double *m;    /* mass */
+    int32_t *mat;
+    double *d;
+    int64_t *id;
+} csph_state;
+
+/* Uniform cubic mesh: origin = per-axis minimum of the positions,
+ * inv_cell = 1/D (formed once on the host), dims_a = floor((max_a -
+ * origin_a) * inv_cell) + 1, cell of a particle
+ * c_a = min(floor((x_a - origin_a) * inv_cell), dims_a - 1), all in FP64
+ * without contraction.  Linear key (c_z * dims_y + c_y) * dims_x + c_x. */
+typedef struct {
+    double origin[3];
+    double cell;      /* D */
+    double inv_cell;  /* 1.0 / D */
+    int32_t dims[3];
+    int32_t reach;    /* stencil half-width in cells: ceil(max support / D) */
+    int64_t ncell;
+} csph_grid;
+
+/* Rates of eqs. SPH:Conti, SPH:Pulse, SPH:Energy, one FP64 array each. */
+typedef struct {
+    double *drho, *dvx, *dvy, *dvz, *dE;
+} csph_rates_out;
+
+/* Human-readable name of a status code (static storage). */
+const char *csph_status_string(csph_status s);
+/* Thread-local message of the last failing call on this thread (static storage). */
+const char *csph_last_error(void);
+/* Library version string. */
+const char *csph_version(void);
+
+/* Workspace bytes the calls below need for n particles on a mesh of ncell
+ * cells (host; no device work).  csph_bin, csph_neighbors, csph_rates and
+ * csph_step each fit in this size. */
+size_t csph_workspace_size(int64_t n, int64_t ncell, const csph_params *p);
+
+/* Mesh of sec. 4.2 for the given positions (see csph_grid).  Synchronises
+ * the stream to bring the bounds to the host.  Cell size: p->cell_size, or
+ * the maximum support when that is <= 0.  n = 0 gives a 1x1x1 mesh. */
+csph_status csph_grid_build(const double *x, const double *y, const double *z, int64_t n,
+                            const csph_params *p, const double *d, csph_grid *grid /* host out */,
+                            void *ws, size_t ws_bytes, csph_stream stream);
+
+/* Binning and cell-ordered numbering (sec. 4.2).  With *grid from
+ * csph_grid_build (or any mesh that covers the positions), writes
+ *   key[i]   linear cell key of particle i (input order), uint32;
+ *   perm[s]  the input index of the s-th particle in cell order: the stable
+ *            order by (key, input index);
+ *   cell_start[c] = first s with key >= c, for c = 0..ncell
+ *            (cell_start[ncell] = n); cell_start_cap >= ncell+1 entries.
+ * key may be NULL.  Bit-exact: integer results of FP64 comparisons. */
+csph_status csph_bin(const double *x, const double *y, const double *z, int64_t n,
+                     const csph_grid *grid /* host */, uint32_t *key, int32_t *perm,
+                     int32_t *cell_start, int64_t cell_start_cap, void *ws, size_t ws_bytes,
+                     size_t *ws_needed, csph_stream stream);
+
+/* Neighbour sets N(i) = { j != i : ((dx*dx)+(dy*dy))+(dz*dz) < H_ij^2 } in
+ * FP64, H_ij = kappa*h or kappa*(0.5*(d_i+d_j)) (sec. 4.1: W > 0 only for
+ * |r| < kappa h_ij), as CSR over input indices with each row ascending:
+ * offsets[n+1] (int64, device), idx[nnz] (int32, device).  Builds its own
+ * mesh (synchronises).  *nnz (host) receives the pair count.  idx may be
+ * NULL (count only); if idx_cap < nnz the call returns CSPH_ECAPACITY with
+ * offsets and *nnz filled.  A verification export: the rate kernels do not
+ * need it. */
+csph_status csph_neighbors(const csph_state *s, const csph_params *p, int64_t *offsets,
+                           int32_t *idx, int64_t idx_cap, int64_t *nnz /* host */, void *ws,
+                           size_t ws_bytes, size_t *ws_needed, csph_stream stream);
+
+/* Rates of every particle at time t (t places the piston only), in the
+ * input order: for each i and j in N(i), e = (r_j - r_i)/|r_j - r_i|,
+ * v_L = v_i.e, v_R = v_j.e, acoustic Riemann solution
+ *   v* = (Z_i v_L + Z_j v_R + P_i - P_j)/(Z_i+Z_j),
+ *   P* = (Z_j P_i + Z_i P_j + Z_i Z_j (v_L - v_R))/(Z_i+Z_j),  Z = rho c,
+ * W' = dW/dr of the Wendland C2 kernel with support H_ij, and
+ *   drho_i = -2 rho_i sum_j (m_j/rho_j)(v_L - v*) W'
+ *   dv_i   =  (2/rho_i) sum_j (m_j/rho_j) P* W' e
+ *   dE_i   =  (2/rho_i) sum_j (m_j/rho_j) P* v* W'
+ * (eqs. SPH:Conti, SPH:Pulse, SPH:Energy with grad_i W = -e W').  Coincident
+ * particles count as neighbours and contribute nothing.  With a wall, every
+ * particle j within the stencil (j = i included) also acts through its
+ * mirror image x' = 2 x_w - x_j, v_x' = 2 v_w - v_x,j.
+ * signal (optional): s_i = max(c_i, max_j [max(c_i, c_j) + max(0, v_L - v_R)]).
+ * nbr_count (optional): |N(i)| (real partners only).
+ * nonphys (optional, device int64): incremented by the number of particles
+ * whose squared sound speed is negative or NaN (their c is taken as 0).
+ * Synchronises once (mesh bounds). */
+csph_status csph_rates(const csph_state *s, const csph_params *p, double t,
+                       csph_rates_out out, double *signal, int32_t *nbr_count, int64_t *nonphys,
+                       void *ws, size_t ws_bytes, size_t *ws_needed, csph_stream stream);
+
+/* One step (Algorithm 1, state renewal and global time step):
+ *   rates at (s_in, *t);  dt = cfl * min_i h/s_i  (or dt_in when cfl <= 0);
+ *   v += dt dv, E += dt dE, rho += dt drho, then r += dt v_new;  *t += dt.
+ * s_out receives the new state (mat, m, d and id are carried); with
+ * p->reorder = 1 in cell order, otherwise in the input order.  s_out may
+ * alias s_in only when p->reorder = 0.  t (device, in/out), dt_used (device,
+ * optional), totals (device, optional, 10 doubles): (hi, lo) compensated
+ * FP64 sums of m, m vx, m vy, m vz, m E over the new state, in a fixed
+ * reduction order.  nbr_count (optional) in the output order.  nonphys as
+ * in csph_rates.  Synchronises once (mesh bounds). */
+csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_params *p,
+                      double *t, double dt_in, double *dt_used, double *totals,
+                      int32_t *nbr_count, int64_t *nonphys, void *ws, size_t ws_bytes,
+                      size_t *ws_needed, csph_stream stream);
+
+/* Voronoi ownership (eq. VoronoiDefinition): owner[i] = the k minimising
+ * ((x_i-g_kx)^2 + (y_i-g_ky)^2) + (z_i-g_kz)^2 in FP64 without contraction,
+ * a tie going to the smaller k (sec. 3.1).  sites: K x 3 FP64, global
+ * coordinates, 1 <= K <= 4096.  site_particles[k] (int64) = number of owned
+ * particles; site_pairs[k] (int64, optional, needs nbr_count) = sum of
+ * nbr_count over owned particles (interaction counts as the load measure,
+ * sec. 1).  Both count arrays are overwritten.  Bit-exact (integers). */
+csph_status voronoi_assign(const double *x, const double *y, const double *z, int64_t n,
+                           const double *sites, int32_t K, const int32_t *nbr_count,
+                           int32_t *owner, int64_t *site_particles, int64_t *site_pairs,
+                           csph_stream stream);
+
+/* Specific total energy from the primitive state: e from the EOS inverse
+ * (ideal: e = p/((gamma-1) rho); stiffened: e = (p + gamma P_inf)/((gamma-1) rho)),
+ * E = e + |v|^2/2. */
+csph_status csph_init_energy(const double *rho, const double *pres, const double *vx,
+                             const double *vy, const double *vz, const int32_t *mat, int64_t n,
+                             const csph_params *p, double *E, csph_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CSPH_H */

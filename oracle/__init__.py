@@ -88,6 +88,9 @@ def lib():
         L.oracle_neighbors.argtypes = [cp, C.c_int64, dp, dp, dp, dp, lp, ip, C.c_int64]
         L.oracle_rates.restype = C.c_int64
         L.oracle_rates.argtypes = [cp, C.c_int64] + [dp] * 9 + [ip, dp, C.c_double] + [dp] * 6 + [lp]
+        L.oracle_rates_sample.restype = C.c_int64
+        L.oracle_rates_sample.argtypes = ([cp, C.c_int64] + [dp] * 9 + [ip, dp, C.c_double, lp,
+                                          C.c_int64] + [dp] * 6 + [lp])
         L.oracle_dt.restype = C.c_double
         L.oracle_dt.argtypes = [cp, C.c_int64, dp, dp]
         L.oracle_step.restype = C.c_int64
@@ -243,6 +246,23 @@ def rates(cfg: Cfg, s, t: float = 0.0, d=None):
         raise MemoryError
     out["nbr_count"] = cnt
     out["nonphys"] = int(bad)
+    return out
+
+
+def rates_sample(cfg: Cfg, s, sample, t: float = 0.0, d=None):
+    """Rates of the particles listed in ``sample`` (cell-list search recommended)."""
+    sample = np.ascontiguousarray(sample, np.int64)
+    k = sample.shape[0]
+    n = s["x"].shape[0]
+    out = {kk: np.empty(k) for kk in ("drho", "dvx", "dvy", "dvz", "dE", "signal")}
+    cnt = np.empty(k, np.int64)
+    bad = lib().oracle_rates_sample(C.byref(cfg), n, *[_d(s[kk]) for kk in FIELDS],
+                                    _i(s["mat"]), _d(d), t, _l(sample), k, _d(out["drho"]),
+                                    _d(out["dvx"]), _d(out["dvy"]), _d(out["dvz"]), _d(out["dE"]),
+                                    _d(out["signal"]), _l(cnt))
+    if bad < 0:
+        raise MemoryError
+    out["nbr_count"] = cnt
     return out
 
 

@@ -442,6 +442,7 @@ typedef struct {
     double t;
     double *drho, *dvx, *dvy, *dvz, *dE, *signal;
     int64_t *nbr_count;
+    const int64_t *sample; /* NULL: every particle; else output k is particle sample[k] */
 } rates_ctx;
 
 /* One interaction of particle i with a partner at position (xj, yj, zj)
@@ -484,7 +485,8 @@ static void rates_range(void *vctx, int64_t lo, int64_t hi) {
     int64_t cap = sp->n;
     int64_t *buf = (int64_t *)malloc(sizeof(int64_t) * (size_t)(cap > 0 ? cap : 1));
     double xw = cfg->wall_x0 + cfg->wall_v * ctx->t;
-    for (int64_t i = lo; i < hi; ++i) {
+    for (int64_t o = lo; o < hi; ++o) {
+        int64_t i = ctx->sample ? ctx->sample[o] : o;
         double Zi = ctx->rho[i] * ctx->c[i];
         double s_rho = 0.0, s_v[3] = {0.0, 0.0, 0.0}, s_E = 0.0, sig = ctx->c[i];
         int64_t cnt = 0;
@@ -520,13 +522,13 @@ static void rates_range(void *vctx, int64_t lo, int64_t hi) {
             }
         }
         double rho_i = ctx->rho[i];
-        ctx->drho[i] = 2.0 * rho_i * s_rho;
-        ctx->dvx[i] = -(2.0 / rho_i) * s_v[0];
-        ctx->dvy[i] = -(2.0 / rho_i) * s_v[1];
-        ctx->dvz[i] = -(2.0 / rho_i) * s_v[2];
-        ctx->dE[i] = -(2.0 / rho_i) * s_E;
-        if (ctx->signal) ctx->signal[i] = sig;
-        if (ctx->nbr_count) ctx->nbr_count[i] = cnt;
+        ctx->drho[o] = 2.0 * rho_i * s_rho;
+        ctx->dvx[o] = -(2.0 / rho_i) * s_v[0];
+        ctx->dvy[o] = -(2.0 / rho_i) * s_v[1];
+        ctx->dvz[o] = -(2.0 / rho_i) * s_v[2];
+        ctx->dE[o] = -(2.0 / rho_i) * s_E;
+        if (ctx->signal) ctx->signal[o] = sig;
+        if (ctx->nbr_count) ctx->nbr_count[o] = cnt;
     }
     free(buf);
 }
@@ -545,8 +547,32 @@ int64_t oracle_rates(const oracle_cfg *cfg, int64_t n, const double *x, const do
     int64_t bad = oracle_eos(cfg, n, rho, E, vx, vy, vz, mat, P, c);
     nbr_space sp;
     if (space_init(&sp, cfg, n, x, y, z, d) != 0) { free(P); free(c); return -1; }
-    rates_ctx ctx = {&sp, vx, vy, vz, rho, m, P, c, t, drho, dvx, dvy, dvz, dE, signal, nbr_count};
+    rates_ctx ctx = {&sp, vx, vy, vz, rho, m, P, c, t, drho, dvx, dvy, dvz, dE, signal, nbr_count,
+                     NULL};
     parallel_for(cfg->nthreads, n, rates_range, &ctx);
+    space_free(&sp);
+    free(P);
+    free(c);
+    return bad;
+}
+
+/* Rates of the listed particles only (outputs indexed like `sample`): the
+ * same sums as oracle_rates, for spot checks of large particle sets. */
+int64_t oracle_rates_sample(const oracle_cfg *cfg, int64_t n, const double *x, const double *y,
+                            const double *z, const double *vx, const double *vy, const double *vz,
+                            const double *rho, const double *E, const double *m,
+                            const int32_t *mat, const double *d, double t, const int64_t *sample,
+                            int64_t nsample, double *drho, double *dvx, double *dvy, double *dvz,
+                            double *dE, double *signal, int64_t *nbr_count) {
+    double *P = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *c = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!P || !c) { free(P); free(c); return -1; }
+    int64_t bad = oracle_eos(cfg, n, rho, E, vx, vy, vz, mat, P, c);
+    nbr_space sp;
+    if (space_init(&sp, cfg, n, x, y, z, d) != 0) { free(P); free(c); return -1; }
+    rates_ctx ctx = {&sp, vx, vy, vz, rho, m, P, c, t, drho, dvx, dvy, dvz, dE, signal, nbr_count,
+                     sample};
+    parallel_for(cfg->nthreads, nsample, rates_range, &ctx);
     space_free(&sp);
     free(P);
     free(c);

@@ -1,0 +1,335 @@
+"""Python binding of libcsph: the C-ABI calls under the same names.
+
+Only argument marshalling happens here: torch supplies device memory and
+the current HIP stream, and every step of the hot path runs in the HIP
+kernels behind ``include/csph.h``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import torch
+
+from . import _native as N
+
+STATE_FIELDS = ("x", "y", "z", "vx", "vy", "vz", "rho", "E", "m")
+EOS_IDEAL, EOS_STIFFENED = N.CSPH_EOS_IDEAL, N.CSPH_EOS_STIFFENED
+
+
+def _ptr(t: Optional[torch.Tensor], ctype):
+    if t is None:
+        return None
+    return C.cast(C.c_void_p(t.data_ptr()), C.POINTER(ctype))
+
+
+def _dp(t):
+    if t is not None:
+        assert t.dtype == torch.float64 and t.is_contiguous() and t.is_cuda, (t.dtype, t.device)
+    return _ptr(t, C.c_double)
+
+
+def _ip(t):
+    if t is not None:
+        assert t.dtype == torch.int32 and t.is_contiguous() and t.is_cuda
+    return _ptr(t, C.c_int32)
+
+
+def _lp(t):
+    if t is not None:
+        assert t.dtype == torch.int64 and t.is_contiguous() and t.is_cuda
+    return _ptr(t, C.c_int64)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class Params:
+    """Mirror of csph_params."""
+
+    eos: List[Tuple[int, float, float]] = field(default_factory=lambda: [(EOS_IDEAL, 1.4, 0.0)])
+    precision: str = "fp64"  # "fp64" | "mixed"
+    h: float = 1.5
+    kappa: float = 2.0
+    h_mode: str = "fixed"  # "fixed" | "pair"
+    cell_size: float = 0.0
+    cfl: float = 0.3
+    wall: Optional[Tuple[float, float]] = None
+    reorder: bool = True
+
+    def c(self) -> N.CsphParams:
+        p = N.CsphParams()
+        p.precision = N.CSPH_MIXED if self.precision == "mixed" else N.CSPH_FP64
+        p.h_mode = N.CSPH_H_PAIR if self.h_mode == "pair" else N.CSPH_H_FIXED
+        p.h, p.kappa, p.cell_size, p.cfl = self.h, self.kappa, self.cell_size, self.cfl
+        p.n_eos = len(self.eos)
+        for k, (t, g, pinf) in enumerate(self.eos):
+            p.eos[k].type, p.eos[k].gamma, p.eos[k].p_inf = int(t), float(g), float(pinf)
+        if self.wall is not None:
+            p.wall, p.wall_x0, p.wall_v = 1, float(self.wall[0]), float(self.wall[1])
+        p.reorder = 1 if self.reorder else 0
+        return p
+
+    @classmethod
+    def from_workload(cls, w, **over) -> "Params":
+        kw = dict(eos=list(w.eos), h=w.h, kappa=w.kappa, cell_size=w.cell_size, cfl=w.cfl,
+                  wall=w.wall)
+        kw.update(over)
+        return cls(**kw)
+
+
+class State:
+    """Device particle state (FP64 SoA) mirroring csph_state."""
+
+    def __init__(self, tensors: Dict[str, torch.Tensor], mat: Optional[torch.Tensor] = None,
+                 d: Optional[torch.Tensor] = None, id: Optional[torch.Tensor] = None):
+        self.t = {k: tensors[k] for k in STATE_FIELDS}
+        self.mat, self.d, self.id = mat, d, id
+
+    @property
+    def n(self) -> int:
+        return int(self.t["x"].shape[0])
+
+    def __getitem__(self, k):
+        if k in ("mat", "d", "id"):
+            return getattr(self, k)
+        return self.t[k]
+
+    @classmethod
+    def empty(cls, n: int, device="cuda", with_mat=True, with_d=False, with_id=False):
+        t = {k: torch.empty(n, dtype=torch.float64, device=device) for k in STATE_FIELDS}
+        mat = torch.empty(n, dtype=torch.int32, device=device) if with_mat else None
+        d = torch.empty(n, dtype=torch.float64, device=device) if with_d else None
+        ids = torch.empty(n, dtype=torch.int64, device=device) if with_id else None
+        return cls(t, mat, d, ids)
+
+    def like(self) -> "State":
+        return State.empty(self.n, self.t["x"].device, self.mat is not None, self.d is not None,
+                           self.id is not None)
+
+    @classmethod
+    def from_numpy(cls, s: dict, device="cuda", with_id=True):
+        t = {k: torch.as_tensor(s[k], dtype=torch.float64).to(device).contiguous()
+             for k in STATE_FIELDS}
+        mat = torch.as_tensor(s["mat"], dtype=torch.int32).to(device).contiguous()
+        d = None
+        if s.get("d") is not None:
+            d = torch.as_tensor(s["d"], dtype=torch.float64).to(device).contiguous()
+        ids = torch.arange(t["x"].shape[0], dtype=torch.int64, device=device) if with_id else None
+        return cls(t, mat, d, ids)
+
+    def numpy(self) -> dict:
+        out = {k: v.cpu().numpy() for k, v in self.t.items()}
+        if self.mat is not None:
+            out["mat"] = self.mat.cpu().numpy()
+        if self.d is not None:
+            out["d"] = self.d.cpu().numpy()
+        if self.id is not None:
+            out["id"] = self.id.cpu().numpy()
+        return out
+
+    def c(self) -> N.CsphState:
+        s = N.CsphState()
+        s.n = self.n
+        for k in STATE_FIELDS:
+            setattr(s, k, _dp(self.t[k]))
+        s.mat = _ip(self.mat)
+        s.d = _dp(self.d)
+        s.id = _lp(self.id)
+        return s
+
+
+class Workspace:
+    """Caller-owned device scratch for the library (grown on demand)."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.buf = torch.empty(1 << 20, dtype=torch.uint8, device=device)
+
+    def ensure(self, nbytes: int):
+        if self.buf.numel() < nbytes:
+            self.buf = torch.empty(int(nbytes * 1.25) + (1 << 20), dtype=torch.uint8,
+                                   device=self.device)
+
+    @property
+    def ptr(self):
+        return C.c_void_p(self.buf.data_ptr())
+
+    @property
+    def nbytes(self):
+        return int(self.buf.numel())
+
+
+_default_ws: Dict[str, Workspace] = {}
+
+
+def default_workspace(device="cuda") -> Workspace:
+    key = str(torch.device(device))
+    if key not in _default_ws:
+        _default_ws[key] = Workspace(device)
+    return _default_ws[key]
+
+
+def _with_ws(fn, ws: Workspace, where: str):
+    """Call fn(ws_ptr, ws_bytes, needed_ptr); grow the workspace once on CSPH_ECAPACITY."""
+    needed = C.c_size_t(0)
+    for _ in range(3):
+        st = fn(ws.ptr, ws.nbytes, C.byref(needed))
+        if st == N.CSPH_ECAPACITY and needed.value > ws.nbytes:
+            ws.ensure(needed.value)
+            continue
+        N.check(st, where)
+        return
+    N.check(st, where)
+
+
+def version() -> str:
+    return N.load().csph_version().decode()
+
+
+def workspace_size(n: int, ncell: int, params: Params) -> int:
+    p = params.c()
+    return int(N.load().csph_workspace_size(n, ncell, C.byref(p)))
+
+
+def csph_grid_build(x, y, z, params: Params, d=None, ws: Optional[Workspace] = None,
+                    stream=None) -> N.CsphGrid:
+    L = N.load()
+    ws = ws or default_workspace(x.device)
+    g = N.CsphGrid()
+    p = params.c()
+    st = L.csph_grid_build(_dp(x), _dp(y), _dp(z), x.shape[0], C.byref(p), _dp(d), C.byref(g),
+                           ws.ptr, ws.nbytes, _stream(stream))
+    N.check(st, "csph_grid_build")
+    return g
+
+
+def csph_bin(x, y, z, grid: N.CsphGrid, ws: Optional[Workspace] = None, stream=None):
+    """(key uint32-as-int64 view, perm int32, cell_start int32) of sec. 4.2 binning."""
+    L = N.load()
+    ws = ws or default_workspace(x.device)
+    n = x.shape[0]
+    key = torch.empty(max(n, 1), dtype=torch.int32, device=x.device)
+    perm = torch.empty(max(n, 1), dtype=torch.int32, device=x.device)
+    cs = torch.empty(grid.ncell + 1, dtype=torch.int32, device=x.device)
+    _with_ws(lambda w, b, nd: L.csph_bin(_dp(x), _dp(y), _dp(z), n, C.byref(grid),
+                                         C.cast(C.c_void_p(key.data_ptr()), C.POINTER(C.c_uint32)),
+                                         _ip(perm), _ip(cs), cs.shape[0], w, b, nd,
+                                         _stream(stream)), ws, "csph_bin")
+    return key[:n].to(torch.int64) & 0xFFFFFFFF, perm[:n], cs
+
+
+def csph_neighbors(state: State, params: Params, ws: Optional[Workspace] = None, stream=None):
+    """CSR (offsets int64 [n+1], idx int32 [nnz]) of the FP64 neighbour sets."""
+    L = N.load()
+    ws = ws or default_workspace(state["x"].device)
+    n = state.n
+    off = torch.empty(n + 1, dtype=torch.int64, device=state["x"].device)
+    s = state.c()
+    p = params.c()
+    nnz = C.c_int64(0)
+    _with_ws(lambda w, b, nd: L.csph_neighbors(C.byref(s), C.byref(p), _lp(off), None, 0,
+                                               C.byref(nnz), w, b, nd, _stream(stream)), ws,
+             "csph_neighbors(count)")
+    idx = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=state["x"].device)
+    _with_ws(lambda w, b, nd: L.csph_neighbors(C.byref(s), C.byref(p), _lp(off), _ip(idx),
+                                               idx.shape[0], C.byref(nnz), w, b, nd,
+                                               _stream(stream)), ws, "csph_neighbors")
+    return off, idx[:nnz.value]
+
+
+def csph_rates(state: State, params: Params, t: float = 0.0, ws: Optional[Workspace] = None,
+               stream=None, want_signal=True, want_count=True):
+    """Rates (drho, dvx, dvy, dvz, dE) in the state's order, plus signal speed and |N(i)|."""
+    L = N.load()
+    dev = state["x"].device
+    ws = ws or default_workspace(dev)
+    n = state.n
+    out = {k: torch.empty(n, dtype=torch.float64, device=dev)
+           for k in ("drho", "dvx", "dvy", "dvz", "dE")}
+    sig = torch.empty(n, dtype=torch.float64, device=dev) if want_signal else None
+    cnt = torch.empty(n, dtype=torch.int32, device=dev) if want_count else None
+    nonphys = torch.zeros(1, dtype=torch.int64, device=dev)
+    ro = N.CsphRatesOut(*[_dp(out[k]) for k in ("drho", "dvx", "dvy", "dvz", "dE")])
+    s = state.c()
+    p = params.c()
+    _with_ws(lambda w, b, nd: L.csph_rates(C.byref(s), C.byref(p), float(t), ro, _dp(sig),
+                                           _ip(cnt), _lp(nonphys), w, b, nd, _stream(stream)), ws,
+             "csph_rates")
+    if sig is not None:
+        out["signal"] = sig
+    if cnt is not None:
+        out["nbr_count"] = cnt
+    out["nonphys"] = nonphys
+    return out
+
+
+class StepScalars:
+    """Device scalars a run of steps carries: time, last dt, totals, non-physical count."""
+
+    def __init__(self, device="cuda", t0: float = 0.0):
+        self.t = torch.full((1,), float(t0), dtype=torch.float64, device=device)
+        self.dt = torch.zeros(1, dtype=torch.float64, device=device)
+        self.totals = torch.zeros(10, dtype=torch.float64, device=device)
+        self.nonphys = torch.zeros(1, dtype=torch.int64, device=device)
+
+
+def csph_step(s_in: State, params: Params, sc: StepScalars, s_out: Optional[State] = None,
+              dt_in: float = 0.0, nbr_count: Optional[torch.Tensor] = None,
+              ws: Optional[Workspace] = None, stream=None, totals: bool = True) -> State:
+    """One step s_in -> s_out (allocated when None); returns s_out."""
+    L = N.load()
+    ws = ws or default_workspace(s_in["x"].device)
+    if s_out is None:
+        s_out = s_in.like() if params.reorder else s_in
+    a, b_ = s_in.c(), s_out.c()
+    p = params.c()
+    _with_ws(lambda w, nb, nd: L.csph_step(C.byref(a), C.byref(b_), C.byref(p), _dp(sc.t),
+                                           float(dt_in), _dp(sc.dt),
+                                           _dp(sc.totals) if totals else None, _ip(nbr_count),
+                                           _lp(sc.nonphys), w, nb, nd, _stream(stream)), ws,
+             "csph_step")
+    return s_out
+
+
+def voronoi_assign(x, y, z, sites: torch.Tensor, nbr_count: Optional[torch.Tensor] = None,
+                   owner: Optional[torch.Tensor] = None, stream=None):
+    """(owner int32 [n], site_particles int64 [K], site_pairs int64 [K] or None)."""
+    L = N.load()
+    n = x.shape[0]
+    K = sites.shape[0]
+    sites = sites.to(torch.float64).contiguous()
+    if owner is None:
+        owner = torch.empty(max(n, 1), dtype=torch.int32, device=x.device)
+    sp = torch.empty(K, dtype=torch.int64, device=x.device)
+    spairs = torch.empty(K, dtype=torch.int64, device=x.device) if nbr_count is not None else None
+    st = L.voronoi_assign(_dp(x), _dp(y), _dp(z), n, _dp(sites), K, _ip(nbr_count), _ip(owner),
+                          _lp(sp), _lp(spairs), _stream(stream))
+    N.check(st, "voronoi_assign")
+    return owner[:n], sp, spairs
+
+
+def csph_init_energy(rho, pres, vx, vy, vz, mat, params: Params, stream=None):
+    L = N.load()
+    n = rho.shape[0]
+    E = torch.empty(n, dtype=torch.float64, device=rho.device)
+    p = params.c()
+    st = L.csph_init_energy(_dp(rho), _dp(pres), _dp(vx), _dp(vy), _dp(vz), _ip(mat), n,
+                            C.byref(p), _dp(E), _stream(stream))
+    N.check(st, "csph_init_energy")
+    return E
+
+
+def state_from_workload(w, params: Params, device="cuda", with_id=True) -> State:
+    """Device state of a synthetic workload: E built on the GPU from (rho, p, v)."""
+    t = {k: torch.as_tensor(getattr(w, k), dtype=torch.float64).to(device).contiguous()
+         for k in ("x", "y", "z", "vx", "vy", "vz", "rho", "m")}
+    mat = torch.as_tensor(w.mat, dtype=torch.int32).to(device).contiguous()
+    p = torch.as_tensor(w.p, dtype=torch.float64).to(device).contiguous()
+    t["E"] = csph_init_energy(t["rho"], p, t["vx"], t["vy"], t["vz"], mat, params)
+    ids = torch.arange(t["x"].shape[0], dtype=torch.int64, device=device) if with_id else None
+    return State(t, mat, None, ids)

@@ -1,0 +1,428 @@
+// extern "C" entry points of libcsph: argument checks, mesh construction,
+// workspace layout and the launch sequences of each call.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "csph_internal.h"
+
+namespace csph {
+
+static thread_local char g_err[512] = "";
+
+static csph_status fail(csph_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+#define CSPH_HIP(expr)                                                                      \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(CSPH_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+    } while (0)
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t ws_layout(Ws *w, void *base, int64_t n, int64_t ncell) {
+    size_t off = 0;
+    char *b = (char *)base;
+    auto take = [&](size_t bytes) -> void * {
+        void *p = b ? (void *)(b + off) : nullptr;
+        off += align256(bytes > 0 ? bytes : 1);
+        return p;
+    };
+    size_t un = (size_t)(n > 0 ? n : 0);
+    Ws t;
+    t.bounds_part = (double *)take(sizeof(double) * 8 * kReduceBlocks);
+    t.bounds_out = (double *)take(sizeof(double) * 8);
+    t.dtmin = (unsigned long long *)take(sizeof(unsigned long long));
+    t.nonphys = (int64_t *)take(sizeof(int64_t));
+    t.tot_part = (double *)take(sizeof(double) * 10 * kReduceBlocks);
+    int64_t scan_len = (n > ncell ? n : ncell) + 1;
+    t.scan_tmp = (int64_t *)take(sizeof(int64_t) * (size_t)((scan_len + kScanTile - 1) / kScanTile + 1));
+    t.key = (uint32_t *)take(sizeof(uint32_t) * un);
+    t.rank = (uint32_t *)take(sizeof(uint32_t) * un);
+    t.perm = (int32_t *)take(sizeof(int32_t) * un);
+    t.cnt = (int32_t *)take(sizeof(int32_t) * un);
+    t.recA = take(32 * un);
+    t.recB = take(32 * un);
+    t.recC = take(16 * un);
+    for (int k = 0; k < 9; ++k) t.srt[k] = (double *)take(sizeof(double) * un);
+    t.srt_mat = (int32_t *)take(sizeof(int32_t) * un);
+    t.srt_d = (double *)take(sizeof(double) * un);
+    t.srt_id = (int64_t *)take(sizeof(int64_t) * un);
+    for (int k = 0; k < 5; ++k) t.rate[k] = (double *)take(sizeof(double) * un);
+    t.sig = (double *)take(sizeof(double) * un);
+    t.cs = (int32_t *)take(sizeof(int32_t) * (size_t)(ncell + 1));
+    t.bytes = off;
+    if (w) *w = t;
+    return off;
+}
+
+// Bytes of the workspace prefix used before the mesh is known (bounds).
+static size_t ws_prefix() {
+    return align256(sizeof(double) * 8 * kReduceBlocks) + align256(sizeof(double) * 8);
+}
+
+static csph_status check_params(const csph_params *p, bool need_pair_d, const double *d) {
+    if (!p) return fail(CSPH_EINVAL, "params is NULL");
+    if (p->precision != CSPH_FP64 && p->precision != CSPH_MIXED)
+        return fail(CSPH_EINVAL, "precision %d unknown", p->precision);
+    if (p->h_mode != CSPH_H_FIXED && p->h_mode != CSPH_H_PAIR)
+        return fail(CSPH_EINVAL, "h_mode %d unknown", p->h_mode);
+    if (!(p->kappa > 0.0) || !std::isfinite(p->kappa)) return fail(CSPH_EINVAL, "kappa must be > 0");
+    if (p->h_mode == CSPH_H_FIXED && (!(p->h > 0.0) || !std::isfinite(p->h)))
+        return fail(CSPH_EINVAL, "h must be > 0 in fixed-h mode");
+    if (p->h_mode == CSPH_H_PAIR && need_pair_d && !d)
+        return fail(CSPH_EINVAL, "pair-h mode needs the particle size array d");
+    if (p->n_eos < 1 || p->n_eos > CSPH_MAX_EOS)
+        return fail(CSPH_EINVAL, "n_eos must be in [1, %d]", CSPH_MAX_EOS);
+    for (int k = 0; k < p->n_eos; ++k) {
+        const csph_eos &e = p->eos[k];
+        if (e.type != CSPH_EOS_IDEAL && e.type != CSPH_EOS_STIFFENED)
+            return fail(CSPH_EINVAL, "eos[%d].type %d unknown", k, e.type);
+        if (!(e.gamma > 1.0) || !std::isfinite(e.gamma))
+            return fail(CSPH_EINVAL, "eos[%d].gamma must be > 1", k);
+        if (!std::isfinite(e.p_inf)) return fail(CSPH_EINVAL, "eos[%d].p_inf not finite", k);
+    }
+    if (!std::isfinite(p->cell_size)) return fail(CSPH_EINVAL, "cell_size not finite");
+    if (!std::isfinite(p->cfl)) return fail(CSPH_EINVAL, "cfl not finite");
+    if (p->wall && (!std::isfinite(p->wall_x0) || !std::isfinite(p->wall_v)))
+        return fail(CSPH_EINVAL, "wall position/velocity not finite");
+    return CSPH_OK;
+}
+
+static bool state_ok(const csph_state *s) {
+    return s && s->n >= 0 &&
+           (s->n == 0 || (s->x && s->y && s->z && s->vx && s->vy && s->vz && s->rho && s->E && s->m));
+}
+
+static EosDev eos_dev(const csph_params *p) {
+    EosDev e;
+    memset(&e, 0, sizeof(e));
+    e.n = p->n_eos;
+    for (int k = 0; k < p->n_eos; ++k) {
+        e.type[k] = p->eos[k].type;
+        e.gamma[k] = p->eos[k].gamma;
+        e.pinf[k] = p->eos[k].p_inf;
+    }
+    return e;
+}
+
+static PairConst pair_const(const csph_params *p, double dmax) {
+    PairConst c;
+    memset(&c, 0, sizeof(c));
+    c.pair_mode = p->h_mode == CSPH_H_PAIR;
+    c.kappa = p->kappa;
+    double H = c.pair_mode ? p->kappa * dmax : p->kappa * p->h;
+    c.H = H;
+    c.H2 = H * H;
+    c.invH = 1.0 / H;
+    double i2 = c.invH * c.invH;
+    c.dwc = (210.0 / M_PI) * (i2 * i2);
+    c.h_dt = p->h;
+    c.wall = p->wall != 0;
+    c.wall_x0 = p->wall_x0;
+    c.wall_v = p->wall_v;
+    return c;
+}
+
+static GridDev grid_dev(const csph_grid &g) {
+    GridDev d;
+    d.ox = g.origin[0];
+    d.oy = g.origin[1];
+    d.oz = g.origin[2];
+    d.inv = g.inv_cell;
+    d.cell = g.cell;
+    d.dx = g.dims[0];
+    d.dy = g.dims[1];
+    d.dz = g.dims[2];
+    d.reach = g.reach;
+    return d;
+}
+
+// Mesh from device bounds (synchronises `st`); also returns max d.
+static csph_status make_grid(const double *x, const double *y, const double *z, const double *d,
+                             int64_t n, const csph_params *p, void *ws, size_t ws_bytes,
+                             hipStream_t st, csph_grid *g, double *dmax) {
+    if (ws_bytes < ws_prefix() || !ws)
+        return fail(CSPH_ECAPACITY, "workspace smaller than %zu bytes", ws_prefix());
+    double b[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (n > 0) {
+        Ws w;
+        ws_layout(&w, ws, 0, 0);
+        CSPH_HIP(launch_bounds(x, y, z, p->h_mode == CSPH_H_PAIR ? d : nullptr, n, w.bounds_part,
+                               w.bounds_out, st));
+        CSPH_HIP(hipMemcpyAsync(b, w.bounds_out, sizeof(double) * 7, hipMemcpyDeviceToHost, st));
+        CSPH_HIP(hipStreamSynchronize(st));
+    }
+    for (int k = 0; k < 7; ++k)
+        if (!std::isfinite(b[k])) return fail(CSPH_EINVAL, "non-finite particle positions or sizes");
+    *dmax = b[6];
+    double Hmax = p->h_mode == CSPH_H_PAIR ? p->kappa * b[6] : p->kappa * p->h;
+    double D = p->cell_size > 0.0 ? p->cell_size : Hmax;
+    if (!(D > 0.0)) D = 1.0;  // pair mode with all d = 0: any mesh works
+    g->cell = D;
+    g->inv_cell = 1.0 / D;
+    int64_t ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+        g->origin[a] = b[a];
+        double span = floor((b[3 + a] - b[a]) * g->inv_cell);
+        if (!(span < 2.0e9)) return fail(CSPH_EINVAL, "mesh too fine for the particle extent");
+        g->dims[a] = (int32_t)span + 1;
+        ncell *= g->dims[a];
+        if (ncell > 2000000000LL) return fail(CSPH_EINVAL, "mesh has more than 2e9 cells");
+    }
+    double r = ceil(Hmax / D);
+    g->reach = r < 1.0 ? 1 : (int32_t)r;
+    if (g->reach > 64) return fail(CSPH_EINVAL, "cell size below 1/64 of the support");
+    g->ncell = ncell;
+    return CSPH_OK;
+}
+
+static csph_status need_ws(size_t have, int64_t n, int64_t ncell, size_t *ws_needed) {
+    size_t need = ws_layout(nullptr, nullptr, n, ncell);
+    if (ws_needed) *ws_needed = need;
+    if (have < need) return fail(CSPH_ECAPACITY, "workspace needs %zu bytes, got %zu", need, have);
+    return CSPH_OK;
+}
+
+}  // namespace csph
+
+using namespace csph;
+
+extern "C" {
+
+const char *csph_status_string(csph_status s) {
+    switch (s) {
+        case CSPH_OK: return "CSPH_OK";
+        case CSPH_EINVAL: return "CSPH_EINVAL: invalid argument";
+        case CSPH_ECAPACITY: return "CSPH_ECAPACITY: output or workspace too small";
+        case CSPH_EDEVICE: return "CSPH_EDEVICE: HIP runtime error";
+        default: return "unknown csph status";
+    }
+}
+
+const char *csph_last_error(void) { return g_err; }
+
+const char *csph_version(void) { return "csph-gfx950 0.1"; }
+
+size_t csph_workspace_size(int64_t n, int64_t ncell, const csph_params *p) {
+    (void)p;
+    return ws_layout(nullptr, nullptr, n < 0 ? 0 : n, ncell < 1 ? 1 : ncell);
+}
+
+csph_status csph_grid_build(const double *x, const double *y, const double *z, int64_t n,
+                            const csph_params *p, const double *d, csph_grid *grid, void *ws,
+                            size_t ws_bytes, csph_stream stream) {
+    g_err[0] = 0;
+    if (n < 0 || !grid || (n > 0 && (!x || !y || !z))) return fail(CSPH_EINVAL, "bad arguments");
+    csph_status s = check_params(p, n > 0, d);
+    if (s) return s;
+    double dmax;
+    return make_grid(x, y, z, d, n, p, ws, ws_bytes, (hipStream_t)stream, grid, &dmax);
+}
+
+csph_status csph_bin(const double *x, const double *y, const double *z, int64_t n,
+                     const csph_grid *grid, uint32_t *key, int32_t *perm, int32_t *cell_start,
+                     int64_t cell_start_cap, void *ws, size_t ws_bytes, size_t *ws_needed,
+                     csph_stream stream) {
+    g_err[0] = 0;
+    if (n < 0 || n >= INT32_MAX || !grid || !cell_start || (n > 0 && (!x || !y || !z || !perm)))
+        return fail(CSPH_EINVAL, "bad arguments");
+    if (!(grid->inv_cell > 0.0) || grid->dims[0] < 1 || grid->dims[1] < 1 || grid->dims[2] < 1)
+        return fail(CSPH_EINVAL, "bad mesh");
+    int64_t ncell = (int64_t)grid->dims[0] * grid->dims[1] * grid->dims[2];
+    if (ncell != grid->ncell) return fail(CSPH_EINVAL, "grid->ncell does not match dims");
+    if (cell_start_cap < ncell + 1)
+        return fail(CSPH_ECAPACITY, "cell_start needs %lld entries", (long long)(ncell + 1));
+    csph_status s = need_ws(ws_bytes, n, ncell, ws_needed);
+    if (s) return s;
+    Ws w;
+    ws_layout(&w, ws, n, ncell);
+    hipStream_t st = (hipStream_t)stream;
+    CSPH_HIP(launch_bin(x, y, z, n, grid_dev(*grid), w, perm, key, cell_start, st));
+    return CSPH_OK;
+}
+
+csph_status csph_neighbors(const csph_state *s, const csph_params *p, int64_t *offsets,
+                           int32_t *idx, int64_t idx_cap, int64_t *nnz, void *ws, size_t ws_bytes,
+                           size_t *ws_needed, csph_stream stream) {
+    g_err[0] = 0;
+    if (!s || s->n < 0 || s->n >= INT32_MAX || !offsets || !nnz ||
+        (s->n > 0 && (!s->x || !s->y || !s->z)))
+        return fail(CSPH_EINVAL, "bad arguments");
+    csph_status r = check_params(p, s->n > 0, s->d);
+    if (r) return r;
+    hipStream_t st = (hipStream_t)stream;
+    int64_t n = s->n;
+    csph_grid g;
+    double dmax;
+    r = make_grid(s->x, s->y, s->z, s->d, n, p, ws, ws_bytes, st, &g, &dmax);
+    if (r) return r;
+    r = need_ws(ws_bytes, n, g.ncell, ws_needed);
+    if (r) return r;
+    Ws w;
+    ws_layout(&w, ws, n, g.ncell);
+    GridDev gd = grid_dev(g);
+    PairConst pc = pair_const(p, dmax);
+    const double *dd = p->h_mode == CSPH_H_PAIR ? s->d : nullptr;
+    CSPH_HIP(launch_bin(s->x, s->y, s->z, n, gd, w, w.perm, nullptr, w.cs, st));
+    CSPH_HIP(launch_gather_pos(n, w.perm, s->x, s->y, s->z, dd, w, st));
+    CSPH_HIP(launch_nbr_count(n, gd, pc, w.srt[0], w.srt[1], w.srt[2], w.srt_d, w.cs, w.perm,
+                              w.cnt, st));
+    CSPH_HIP((launch_scan_exclusive<int32_t, int64_t>(w.cnt, offsets, n, w.scan_tmp, st)));
+    int64_t total = 0;
+    CSPH_HIP(hipMemcpyAsync(&total, offsets + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    CSPH_HIP(hipStreamSynchronize(st));
+    *nnz = total;
+    if (!idx) return CSPH_OK;
+    if (idx_cap < total)
+        return fail(CSPH_ECAPACITY, "idx needs %lld entries", (long long)total);
+    CSPH_HIP(launch_nbr_fill(n, gd, pc, w.srt[0], w.srt[1], w.srt[2], w.srt_d, w.cs, w.perm,
+                             offsets, idx, st));
+    return CSPH_OK;
+}
+
+csph_status csph_rates(const csph_state *s, const csph_params *p, double t, csph_rates_out out,
+                       double *signal, int32_t *nbr_count, int64_t *nonphys, void *ws,
+                       size_t ws_bytes, size_t *ws_needed, csph_stream stream) {
+    g_err[0] = 0;
+    if (!state_ok(s) || s->n >= INT32_MAX) return fail(CSPH_EINVAL, "bad state");
+    if (s->n > 0 && (!out.drho || !out.dvx || !out.dvy || !out.dvz || !out.dE))
+        return fail(CSPH_EINVAL, "rate outputs must not be NULL");
+    if (!std::isfinite(t)) return fail(CSPH_EINVAL, "t not finite");
+    csph_status r = check_params(p, s->n > 0, s->d);
+    if (r) return r;
+    hipStream_t st = (hipStream_t)stream;
+    int64_t n = s->n;
+    csph_grid g;
+    double dmax;
+    r = make_grid(s->x, s->y, s->z, s->d, n, p, ws, ws_bytes, st, &g, &dmax);
+    if (r) return r;
+    r = need_ws(ws_bytes, n, g.ncell, ws_needed);
+    if (r) return r;
+    if (n == 0) return CSPH_OK;
+    Ws w;
+    ws_layout(&w, ws, n, g.ncell);
+    GridDev gd = grid_dev(g);
+    PairConst pc = pair_const(p, dmax);
+    EosDev eos = eos_dev(p);
+    int mixed = p->precision == CSPH_MIXED;
+    bool pair = p->h_mode == CSPH_H_PAIR;
+    CSPH_HIP(launch_bin(s->x, s->y, s->z, n, gd, w, w.perm, nullptr, w.cs, st));
+    CSPH_HIP(launch_pack(*s, n, w.perm, eos, mixed, gd, w, w.srt, w.srt_mat,
+                         pair ? w.srt_d : nullptr, nullptr, nullptr, nonphys, st));
+    CSPH_HIP(launch_rates(n, mixed, gd, pc, w, w.srt, pair ? w.srt_d : nullptr, nullptr, t, 0,
+                          st));
+    CSPH_HIP(launch_unsort_rates(n, w.perm, w, out, signal, nbr_count, st));
+    return CSPH_OK;
+}
+
+csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_params *p, double *t,
+                      double dt_in, double *dt_used, double *totals, int32_t *nbr_count,
+                      int64_t *nonphys, void *ws, size_t ws_bytes, size_t *ws_needed,
+                      csph_stream stream) {
+    g_err[0] = 0;
+    if (!state_ok(s_in) || !state_ok(s_out) || s_in->n != s_out->n || s_in->n >= INT32_MAX)
+        return fail(CSPH_EINVAL, "bad state");
+    csph_status r = check_params(p, s_in->n > 0, s_in->d);
+    if (r) return r;
+    if (!(p->cfl > 0.0) && !(std::isfinite(dt_in) && dt_in >= 0.0))
+        return fail(CSPH_EINVAL, "cfl <= 0 needs a finite dt_in >= 0");
+    if ((s_in->mat && !s_out->mat) || (s_in->id && !s_out->id) ||
+        (p->h_mode == CSPH_H_PAIR && !s_out->d))
+        return fail(CSPH_EINVAL, "s_out must carry mat/id/d when s_in does");
+    if (p->reorder && s_in->n > 0 &&
+        (s_in->x == s_out->x || s_in->vx == s_out->vx || s_in->rho == s_out->rho ||
+         s_in->E == s_out->E || s_in->m == s_out->m))
+        return fail(CSPH_EINVAL, "reorder = 1 needs s_out distinct from s_in");
+    hipStream_t st = (hipStream_t)stream;
+    int64_t n = s_in->n;
+    csph_grid g;
+    double dmax;
+    r = make_grid(s_in->x, s_in->y, s_in->z, s_in->d, n, p, ws, ws_bytes, st, &g, &dmax);
+    if (r) return r;
+    r = need_ws(ws_bytes, n, g.ncell, ws_needed);
+    if (r) return r;
+    Ws w;
+    ws_layout(&w, ws, n, g.ncell);
+    GridDev gd = grid_dev(g);
+    PairConst pc = pair_const(p, dmax);
+    EosDev eos = eos_dev(p);
+    int mixed = p->precision == CSPH_MIXED;
+    bool pair = p->h_mode == CSPH_H_PAIR;
+    double *dst[9];
+    int32_t *dmat;
+    double *dd;
+    int64_t *did;
+    if (p->reorder) {
+        double *o[9] = {s_out->x, s_out->y, s_out->z, s_out->vx, s_out->vy, s_out->vz,
+                        s_out->rho, s_out->E, s_out->m};
+        for (int k = 0; k < 9; ++k) dst[k] = o[k];
+        dmat = s_out->mat;
+        dd = pair ? s_out->d : nullptr;
+        did = s_out->id;
+    } else {
+        for (int k = 0; k < 9; ++k) dst[k] = w.srt[k];
+        dmat = w.srt_mat;
+        dd = pair ? w.srt_d : nullptr;
+        did = s_in->id ? w.srt_id : nullptr;
+    }
+    if (n > 0) {
+        CSPH_HIP(launch_bin(s_in->x, s_in->y, s_in->z, n, gd, w, w.perm, nullptr, w.cs, st));
+        CSPH_HIP(launch_pack(*s_in, n, w.perm, eos, mixed, gd, w, dst, dmat, dd, did, s_in->id,
+                             nonphys, st));
+    }
+    if (p->cfl > 0.0) CSPH_HIP(launch_fill_u64(w.dtmin, 0x7ff0000000000000ull, 1, st));
+    if (n > 0) {
+        CSPH_HIP(launch_rates(n, mixed, gd, pc, w, dst, dd, t, 0.0, p->cfl > 0.0, st));
+        CSPH_HIP(launch_integrate(n, dst, w, p->cfl, dt_in, st));
+    }
+    CSPH_HIP(launch_finish_step(n, w, p->cfl, dt_in, t, dt_used, totals, st));
+    if (n > 0) {
+        if (p->reorder) {
+            if (nbr_count)
+                CSPH_HIP(hipMemcpyAsync(nbr_count, w.cnt, sizeof(int32_t) * n,
+                                        hipMemcpyDeviceToDevice, st));
+        } else {
+            csph_state o = *s_out;
+            if (!pair) o.d = nullptr;
+            CSPH_HIP(launch_unpermute(n, w.perm, w.srt, s_in->mat ? w.srt_mat : nullptr, dd,
+                                      did, w.cnt, o, nbr_count, st));
+        }
+    }
+    return CSPH_OK;
+}
+
+csph_status voronoi_assign(const double *x, const double *y, const double *z, int64_t n,
+                           const double *sites, int32_t K, const int32_t *nbr_count,
+                           int32_t *owner, int64_t *site_particles, int64_t *site_pairs,
+                           csph_stream stream) {
+    g_err[0] = 0;
+    if (n < 0 || K < 1 || K > kMaxSites || !sites || !site_particles ||
+        (n > 0 && (!x || !y || !z || !owner)))
+        return fail(CSPH_EINVAL, "bad arguments (1 <= K <= %d)", kMaxSites);
+    if (site_pairs && !nbr_count) return fail(CSPH_EINVAL, "site_pairs needs nbr_count");
+    CSPH_HIP(launch_voronoi(x, y, z, n, sites, K, nbr_count, owner, site_particles, site_pairs,
+                            (hipStream_t)stream));
+    return CSPH_OK;
+}
+
+csph_status csph_init_energy(const double *rho, const double *pres, const double *vx,
+                             const double *vy, const double *vz, const int32_t *mat, int64_t n,
+                             const csph_params *p, double *E, csph_stream stream) {
+    g_err[0] = 0;
+    if (n < 0 || (n > 0 && (!rho || !pres || !vx || !vy || !vz || !E)))
+        return fail(CSPH_EINVAL, "bad arguments");
+    csph_status r = check_params(p, false, nullptr);
+    if (r) return r;
+    CSPH_HIP(launch_init_energy(rho, pres, vx, vy, vz, mat, n, eos_dev(p), E, (hipStream_t)stream));
+    return CSPH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,143 @@
+// Internal declarations of the gfx950 contact-SPH library: device helpers,
+// the workspace layout and the host-side launchers of each kernel file.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+
+#include "csph.h"
+
+namespace csph {
+
+constexpr int kBlock = 256;           // threads per workgroup (4 wave64)
+constexpr int kReduceBlocks = 1024;   // partial-reduction blocks (bounds, totals)
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+constexpr int kMaxSites = 2048;       // Voronoi generators held in LDS
+
+// Mesh as the kernels see it.
+struct GridDev {
+    double ox, oy, oz;  // origin
+    double inv;         // 1/D
+    double cell;        // D
+    int dx, dy, dz;     // dims
+    int reach;          // stencil half-width
+};
+
+// Per-call constants of the pair interaction.
+struct PairConst {
+    double H;        // support (fixed mode)
+    double H2;       // H*H (fixed mode)
+    double invH;     // 1/H (fixed mode)
+    double dwc;      // (210/pi)/H^4 (fixed mode)
+    double kappa;    // pair mode: H_ij = kappa * (0.5*(d_i+d_j))
+    double h_dt;     // h in the CFL rule (fixed mode)
+    double wall_x0, wall_v;
+    int pair_mode;
+    int wall;
+};
+
+struct EosDev {
+    int n;
+    int type[CSPH_MAX_EOS];
+    double gamma[CSPH_MAX_EOS];
+    double pinf[CSPH_MAX_EOS];
+};
+
+// Cell coordinate min(floor((v - o) * inv), dim - 1), clamped at 0, FP64
+// without contraction (the library is built with -ffp-contract=off).
+__device__ __forceinline__ int cell_coord(double v, double o, double inv, int dim) {
+    double f = floor((v - o) * inv);
+    f = fmin(fmax(f, 0.0), (double)(dim - 1));
+    return (int)f;
+}
+
+// Bit pattern of a non-negative double orders like the double itself.
+__device__ __forceinline__ unsigned long long dbits(double v) {
+    return (unsigned long long)__double_as_longlong(v);
+}
+
+// ---------------------------------------------------------------- device buffers
+// Carved out of the caller's workspace, each region 256-byte aligned.
+struct Ws {
+    double *bounds_part;          // kReduceBlocks * 8
+    double *bounds_out;           // 8
+    uint32_t *key;                // n
+    uint32_t *rank;               // n
+    int32_t *cs;                  // ncell + 1
+    int64_t *scan_tmp;            // scan tiles
+    int32_t *perm;                // n
+    void *recA, *recB, *recC;     // pair records (FP64: 32+32+16 B; mixed: 16+16+8 B)
+    double *srt[9];               // sorted state copy x y z vx vy vz rho E m
+    int32_t *srt_mat;
+    double *srt_d;
+    int64_t *srt_id;
+    double *rate[5];              // drho dvx dvy dvz dE (cell order)
+    double *sig;                  // signal speed (cell order)
+    int32_t *cnt;                 // neighbour count (cell order)
+    unsigned long long *dtmin;    // bits of min_i h_i/s_i
+    int64_t *nonphys;             // scratch counter
+    double *tot_part;             // kReduceBlocks * 10
+    size_t bytes;
+};
+
+size_t ws_layout(Ws *w, void *base, int64_t n, int64_t ncell);
+
+// ---------------------------------------------------------------- launchers
+// Every launcher enqueues on `st` and returns the HIP status of the launch.
+
+// k_bin.hip
+hipError_t launch_bounds(const double *x, const double *y, const double *z, const double *d,
+                         int64_t n, double *part, double *out, hipStream_t st);
+hipError_t launch_bin(const double *x, const double *y, const double *z, int64_t n,
+                      const GridDev &g, const Ws &w, int32_t *perm, uint32_t *key_out,
+                      int32_t *cell_start, hipStream_t st);
+template <typename TI, typename TO>
+hipError_t launch_scan_exclusive(const TI *in, TO *out, int64_t len, int64_t *tmp, hipStream_t st);
+
+// k_rates.hip
+hipError_t launch_pack(const csph_state &s, int64_t n, const int32_t *perm, const EosDev &eos,
+                       int mixed, const GridDev &g, const Ws &w, double *const dst[9],
+                       int32_t *dst_mat, double *dst_d, int64_t *dst_id, const int64_t *src_id,
+                       int64_t *nonphys, hipStream_t st);
+// sorted: the cell-ordered FP64 state (x y z vx vy vz rho E m) the records were packed from.
+hipError_t launch_rates(int64_t n, int mixed, const GridDev &g, const PairConst &pc,
+                        const Ws &w, double *const sorted[9], const double *d_sorted,
+                        const double *t_dev, double t_host, int want_dt, hipStream_t st);
+hipError_t launch_unsort_rates(int64_t n, const int32_t *perm, const Ws &w, csph_rates_out out,
+                               double *signal, int32_t *nbr_count, hipStream_t st);
+
+// k_step.hip
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t count, hipStream_t st);
+hipError_t launch_integrate(int64_t n, double *const st8[9], const Ws &w, double cfl, double dt_in,
+                            hipStream_t st);
+hipError_t launch_finish_step(int64_t n, const Ws &w, double cfl, double dt_in, double *t, double *dt_used,
+                              double *totals, hipStream_t st);
+hipError_t launch_unpermute(int64_t n, const int32_t *perm, double *const src[9],
+                            const int32_t *src_mat, const double *src_d, const int64_t *src_id,
+                            const int32_t *src_cnt, const csph_state &out, int32_t *out_cnt,
+                            hipStream_t st);
+hipError_t launch_init_energy(const double *rho, const double *pres, const double *vx,
+                              const double *vy, const double *vz, const int32_t *mat, int64_t n,
+                              const EosDev &eos, double *E, hipStream_t st);
+
+// k_voronoi.hip
+hipError_t launch_voronoi(const double *x, const double *y, const double *z, int64_t n,
+                          const double *sites, int K, const int32_t *nbr_count, int32_t *owner,
+                          int64_t *site_particles, int64_t *site_pairs, hipStream_t st);
+
+// k_neighbors.hip
+hipError_t launch_gather_pos(int64_t n, const int32_t *perm, const double *x, const double *y,
+                             const double *z, const double *d, const Ws &w, hipStream_t st);
+hipError_t launch_nbr_count(int64_t n, const GridDev &g, const PairConst &pc, const double *x,
+                            const double *y, const double *z, const double *d, const int32_t *cs,
+                            const int32_t *perm, int32_t *count_orig, hipStream_t st);
+hipError_t launch_nbr_fill(int64_t n, const GridDev &g, const PairConst &pc, const double *x,
+                           const double *y, const double *z, const double *d, const int32_t *cs,
+                           const int32_t *perm, const int64_t *offsets, int32_t *idx,
+                           hipStream_t st);
+
+}  // namespace csph

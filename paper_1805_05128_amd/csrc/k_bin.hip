@@ -1,0 +1,257 @@
+// Mesh bounds, cell keys, counting sort into cell order, cell ranges.
+//
+// Cell-ordered numbering is the GPU form of the linked-list cells and the
+// locality renumbering of sec. 4.2: a counting sort by cell key.  Keys are
+// histogrammed with integer atomics (each particle also gets a provisional
+// rank inside its cell), an exclusive scan of the histogram gives the cell
+// ranges, a scatter places every particle, and each cell's short segment is
+// then sorted by input index so the order is exactly the stable order by
+// (key, input index) whatever order the atomics ran in.
+#include "csph_internal.h"
+
+namespace csph {
+
+// ---------------------------------------------------------------- reductions
+
+__device__ __forceinline__ double wave_min(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// part[b*8 + {0..6}] = min x, min y, min z, max x, max y, max z, max d.
+__global__ __launch_bounds__(kBlock) void k_bounds(const double *__restrict__ x,
+                                                   const double *__restrict__ y,
+                                                   const double *__restrict__ z,
+                                                   const double *__restrict__ d, int64_t n,
+                                                   double *__restrict__ part) {
+    double v[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        double a = x[i], b = y[i], c = z[i];
+        v[0] = fmin(v[0], a); v[1] = fmin(v[1], b); v[2] = fmin(v[2], c);
+        v[3] = fmax(v[3], a); v[4] = fmax(v[4], b); v[5] = fmax(v[5], c);
+        if (d) v[6] = fmax(v[6], d[i]);
+    }
+    __shared__ double sh[kBlock / 64][7];
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int k = 0; k < 7; ++k) {
+        double r = k < 3 ? wave_min(v[k]) : wave_max(v[k]);
+        if (lane == 0) sh[wid][k] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < 7) {
+        int k = threadIdx.x;
+        double r = sh[0][k];
+        for (int q = 1; q < kBlock / 64; ++q) r = k < 3 ? fmin(r, sh[q][k]) : fmax(r, sh[q][k]);
+        part[blockIdx.x * 8 + k] = r;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bounds_final(const double *__restrict__ part,
+                                                         int nblocks, double *__restrict__ out) {
+    double v[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += kBlock)
+        for (int k = 0; k < 7; ++k)
+            v[k] = k < 3 ? fmin(v[k], part[b * 8 + k]) : fmax(v[k], part[b * 8 + k]);
+    __shared__ double sh[kBlock / 64][7];
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int k = 0; k < 7; ++k) {
+        double r = k < 3 ? wave_min(v[k]) : wave_max(v[k]);
+        if (lane == 0) sh[wid][k] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < 7) {
+        int k = threadIdx.x;
+        double r = sh[0][k];
+        for (int q = 1; q < kBlock / 64; ++q) r = k < 3 ? fmin(r, sh[q][k]) : fmax(r, sh[q][k]);
+        out[k] = r;
+    }
+}
+
+hipError_t launch_bounds(const double *x, const double *y, const double *z, const double *d,
+                         int64_t n, double *part, double *out, hipStream_t st) {
+    int64_t want = (n + kBlock - 1) / kBlock;
+    int nb = (int)(want < 1 ? 1 : (want > kReduceBlocks ? kReduceBlocks : want));
+    k_bounds<<<nb, kBlock, 0, st>>>(x, y, z, d, n, part);
+    k_bounds_final<<<1, kBlock, 0, st>>>(part, nb, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- exclusive scan
+
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T *lds, T &total) {
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    T x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        T y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) lds[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T run = 0;
+        for (int k = 0; k < kBlock / 64; ++k) {
+            T t = lds[k];
+            lds[k] = run;
+            run += t;
+        }
+        lds[kBlock / 64] = run;
+    }
+    __syncthreads();
+    T excl = (x - v) + lds[wid];
+    total = lds[kBlock / 64];
+    __syncthreads();
+    return excl;
+}
+
+template <typename TI>
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const TI *__restrict__ in, int64_t len,
+                                                        int64_t *__restrict__ tile_sum) {
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int64_t s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
+        if (i < len) s += (int64_t)in[i];
+    }
+    __shared__ int64_t lds[kBlock / 64 + 1];
+    int64_t total;
+    block_exclusive_scan<int64_t>(s, lds, total);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
+}
+
+// Exclusive scan of the tile sums in one workgroup; out[len] = grand total.
+template <typename TO>
+__global__ __launch_bounds__(kBlock) void k_scan_tops(int64_t *__restrict__ tile_sum,
+                                                      int64_t ntiles, TO *__restrict__ out,
+                                                      int64_t len) {
+    __shared__ int64_t lds[kBlock / 64 + 1];
+    int64_t run = 0;
+    for (int64_t b = 0; b < ntiles; b += kBlock) {
+        int64_t i = b + threadIdx.x;
+        int64_t v = i < ntiles ? tile_sum[i] : 0;
+        int64_t total;
+        int64_t e = block_exclusive_scan<int64_t>(v, lds, total);
+        if (i < ntiles) tile_sum[i] = run + e;
+        run += total;
+    }
+    if (threadIdx.x == 0) out[len] = (TO)run;
+}
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kBlock) void k_scan_apply(const TI *in, TO *out, int64_t len,
+                                                       const int64_t *__restrict__ tile_off) {
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t v[kScanItems];
+    int64_t s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k;
+        v[k] = i < len ? (int64_t)in[i] : 0;
+        s += v[k];
+    }
+    __shared__ int64_t lds[kBlock / 64 + 1];
+    int64_t total;
+    int64_t run = block_exclusive_scan<int64_t>(s, lds, total) + tile_off[blockIdx.x];
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k;
+        if (i < len) out[i] = (TO)run;
+        run += v[k];
+    }
+}
+
+// out[0..len) = exclusive prefix sums of in[0..len), out[len] = total.
+// in may alias out when TI == TO.  tmp holds ceil(len / kScanTile) int64.
+template <typename TI, typename TO>
+hipError_t launch_scan_exclusive(const TI *in, TO *out, int64_t len, int64_t *tmp,
+                                 hipStream_t st) {
+    int64_t ntiles = (len + kScanTile - 1) / kScanTile;
+    if (ntiles > 0) k_scan_reduce<TI><<<(unsigned)ntiles, kBlock, 0, st>>>(in, len, tmp);
+    k_scan_tops<TO><<<1, kBlock, 0, st>>>(tmp, ntiles, out, len);
+    if (ntiles > 0) k_scan_apply<TI, TO><<<(unsigned)ntiles, kBlock, 0, st>>>(in, out, len, tmp);
+    return hipGetLastError();
+}
+
+template hipError_t launch_scan_exclusive<int32_t, int32_t>(const int32_t *, int32_t *, int64_t,
+                                                            int64_t *, hipStream_t);
+template hipError_t launch_scan_exclusive<int32_t, int64_t>(const int32_t *, int64_t *, int64_t,
+                                                            int64_t *, hipStream_t);
+
+// ---------------------------------------------------------------- counting sort by cell
+
+__global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *p, int32_t v, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * kBlock)
+        p[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_keys(const double *__restrict__ x,
+                                                 const double *__restrict__ y,
+                                                 const double *__restrict__ z, int64_t n,
+                                                 GridDev g, uint32_t *__restrict__ key,
+                                                 uint32_t *__restrict__ rank,
+                                                 int32_t *__restrict__ count,
+                                                 uint32_t *__restrict__ key_out) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int cx = cell_coord(x[i], g.ox, g.inv, g.dx);
+    int cy = cell_coord(y[i], g.oy, g.inv, g.dy);
+    int cz = cell_coord(z[i], g.oz, g.inv, g.dz);
+    uint32_t k = ((uint32_t)cz * (uint32_t)g.dy + (uint32_t)cy) * (uint32_t)g.dx + (uint32_t)cx;
+    key[i] = k;
+    rank[i] = (uint32_t)atomicAdd(&count[k], 1);
+    if (key_out) key_out[i] = k;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__ key,
+                                                    const uint32_t *__restrict__ rank,
+                                                    const int32_t *__restrict__ cs, int64_t n,
+                                                    int32_t *__restrict__ perm) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    perm[cs[key[i]] + (int32_t)rank[i]] = (int32_t)i;
+}
+
+// Sort each cell's segment of perm ascending (insertion sort: segments are
+// short and usually already in order).
+__global__ __launch_bounds__(kBlock) void k_cell_sort(const int32_t *__restrict__ cs,
+                                                      int64_t ncell, int32_t *__restrict__ perm) {
+    int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= ncell) return;
+    int a = cs[c], b = cs[c + 1];
+    for (int s = a + 1; s < b; ++s) {
+        int v = perm[s];
+        int t = s - 1;
+        while (t >= a && perm[t] > v) {
+            perm[t + 1] = perm[t];
+            --t;
+        }
+        perm[t + 1] = v;
+    }
+}
+
+static unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+hipError_t launch_bin(const double *x, const double *y, const double *z, int64_t n,
+                      const GridDev &g, const Ws &w, int32_t *perm, uint32_t *key_out,
+                      int32_t *cell_start, hipStream_t st) {
+    int64_t ncell = (int64_t)g.dx * g.dy * g.dz;
+    unsigned fb = blocks_for(ncell + 1);
+    k_fill_i32<<<fb > 65535u ? 65535u : fb, kBlock, 0, st>>>(cell_start, 0, ncell + 1);
+    if (n > 0)
+        k_keys<<<blocks_for(n), kBlock, 0, st>>>(x, y, z, n, g, w.key, w.rank, cell_start,
+                                                 key_out);
+    hipError_t e = launch_scan_exclusive<int32_t, int32_t>(cell_start, cell_start, ncell,
+                                                           w.scan_tmp, st);
+    if (e != hipSuccess) return e;
+    if (n > 0) {
+        k_scatter<<<blocks_for(n), kBlock, 0, st>>>(w.key, w.rank, cell_start, n, perm);
+        k_cell_sort<<<blocks_for(ncell), kBlock, 0, st>>>(cell_start, ncell, perm);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace csph

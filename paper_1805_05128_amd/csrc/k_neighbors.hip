@@ -1,0 +1,131 @@
+// Neighbour-set export N(i) = { j != i : |r_j - r_i|^2 < H_ij^2 } (sec. 4.1)
+// as CSR over input indices, rows ascending.  Verification form only: the
+// rate kernels gather partners on the fly and never materialise this list.
+// The test is the FP64 expression ((dx*dx)+(dy*dy))+(dz*dz) < H*H without
+// contraction, so membership is exact.
+#include "csph_internal.h"
+
+namespace csph {
+
+__global__ __launch_bounds__(kBlock) void k_gather_pos(int64_t n, const int32_t *__restrict__ perm,
+                                                       const double *__restrict__ x,
+                                                       const double *__restrict__ y,
+                                                       const double *__restrict__ z,
+                                                       const double *__restrict__ d,
+                                                       double *__restrict__ xs,
+                                                       double *__restrict__ ys,
+                                                       double *__restrict__ zs,
+                                                       double *__restrict__ ds) {
+    int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    int i = perm[s];
+    xs[s] = x[i];
+    ys[s] = y[i];
+    zs[s] = z[i];
+    if (d) ds[s] = d[i];
+}
+
+hipError_t launch_gather_pos(int64_t n, const int32_t *perm, const double *x, const double *y,
+                             const double *z, const double *d, const Ws &w, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_gather_pos<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+        n, perm, x, y, z, d, w.srt[0], w.srt[1], w.srt[2], w.srt_d);
+    return hipGetLastError();
+}
+
+template <bool PAIR, bool FILL>
+__global__ __launch_bounds__(kBlock) void k_nbr(int64_t n, GridDev g, PairConst pc,
+                                                const double *__restrict__ x,
+                                                const double *__restrict__ y,
+                                                const double *__restrict__ z,
+                                                const double *__restrict__ d,
+                                                const int32_t *__restrict__ cs,
+                                                const int32_t *__restrict__ perm,
+                                                int32_t *__restrict__ count_orig,
+                                                const int64_t *__restrict__ offsets,
+                                                int32_t *__restrict__ idx) {
+    int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    double xi = x[s], yi = y[s], zi = z[s];
+    double di = PAIR ? d[s] : 0.0;
+    int cx = cell_coord(xi, g.ox, g.inv, g.dx);
+    int cy = cell_coord(yi, g.oy, g.inv, g.dy);
+    int cz = cell_coord(zi, g.oz, g.inv, g.dz);
+    const int R = g.reach;
+    const int x0 = max(cx - R, 0), x1 = min(cx + R, g.dx - 1);
+    int i = perm[s];
+    int64_t wpos = FILL ? offsets[i] : 0;
+    int cnt = 0;
+    for (int oz = -R; oz <= R; ++oz) {
+        int zz = cz + oz;
+        if (zz < 0 || zz >= g.dz) continue;
+        for (int oy = -R; oy <= R; ++oy) {
+            int yy = cy + oy;
+            if (yy < 0 || yy >= g.dy) continue;
+            int row = (zz * g.dy + yy) * g.dx;
+            int j0 = cs[row + x0], j1 = cs[row + x1 + 1];
+            for (int j = j0; j < j1; ++j) {
+                if (j == (int)s) continue;
+                double dx = x[j] - xi, dy = y[j] - yi, dz = z[j] - zi;
+                double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
+                double H2;
+                if (PAIR) {
+                    double H = pc.kappa * (0.5 * (di + d[j]));
+                    H2 = H * H;
+                } else {
+                    H2 = pc.H2;
+                }
+                if (r2 < H2) {
+                    if (FILL) idx[wpos + cnt] = perm[j];
+                    ++cnt;
+                }
+            }
+        }
+    }
+    if (FILL) {
+        // insertion sort of this row (rows are short)
+        int32_t *row = idx + wpos;
+        for (int a = 1; a < cnt; ++a) {
+            int v = row[a];
+            int b = a - 1;
+            while (b >= 0 && row[b] > v) {
+                row[b + 1] = row[b];
+                --b;
+            }
+            row[b + 1] = v;
+        }
+    } else {
+        count_orig[i] = cnt;
+    }
+}
+
+hipError_t launch_nbr_count(int64_t n, const GridDev &g, const PairConst &pc, const double *x,
+                            const double *y, const double *z, const double *d, const int32_t *cs,
+                            const int32_t *perm, int32_t *count_orig, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    if (pc.pair_mode)
+        k_nbr<true, false><<<nb, kBlock, 0, st>>>(n, g, pc, x, y, z, d, cs, perm, count_orig,
+                                                  nullptr, nullptr);
+    else
+        k_nbr<false, false><<<nb, kBlock, 0, st>>>(n, g, pc, x, y, z, d, cs, perm, count_orig,
+                                                   nullptr, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_nbr_fill(int64_t n, const GridDev &g, const PairConst &pc, const double *x,
+                           const double *y, const double *z, const double *d, const int32_t *cs,
+                           const int32_t *perm, const int64_t *offsets, int32_t *idx,
+                           hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    if (pc.pair_mode)
+        k_nbr<true, true><<<nb, kBlock, 0, st>>>(n, g, pc, x, y, z, d, cs, perm, nullptr,
+                                                 offsets, idx);
+    else
+        k_nbr<false, true><<<nb, kBlock, 0, st>>>(n, g, pc, x, y, z, d, cs, perm, nullptr,
+                                                  offsets, idx);
+    return hipGetLastError();
+}
+
+}  // namespace csph

@@ -1,0 +1,245 @@
+// State renewal and global time step (Algorithm 1), compensated
+// conservation totals, the return to input order, and the EOS inverse
+// that builds E from (rho, p, v).
+//
+// Integrator: symplectic Euler with one rate evaluation per step,
+//   v += dt dv/dt, E += dt dE/dt, rho += dt drho/dt, then r += dt v_new,
+// dt = cfl * min_i h_i/s_i (a min is exact and order independent) or the
+// caller's dt.  Totals use double-double (TwoSum) accumulation in a fixed
+// reduction tree, so they are reproducible run to run.
+#include "csph_internal.h"
+
+namespace csph {
+
+struct DD {
+    double hi, lo;
+};
+
+// hi + b with the rounding error of the sum kept in lo (Knuth TwoSum).
+__device__ __forceinline__ DD dd_add1(DD a, double b) {
+    double s = a.hi + b;
+    double bb = s - a.hi;
+    double e = (a.hi - (s - bb)) + (b - bb);
+    return DD{s, a.lo + e};
+}
+
+__device__ __forceinline__ DD dd_add(DD a, DD b) {
+    double s = a.hi + b.hi;
+    double bb = s - a.hi;
+    double e = (a.hi - (s - bb)) + (b.hi - bb);
+    e += a.lo + b.lo;
+    double hi = s + e;
+    double lo = e - (hi - s);
+    return DD{hi, lo};
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_u64(unsigned long long *p, unsigned long long v,
+                                                     int64_t count) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t count,
+                           hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    k_fill_u64<<<(unsigned)((count + kBlock - 1) / kBlock), kBlock, 0, st>>>(p, v, count);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ double step_dt(const unsigned long long *dtmin, double cfl,
+                                          double dt_in) {
+    return cfl > 0.0 ? cfl * __longlong_as_double((long long)*dtmin) : dt_in;
+}
+
+struct State9 {
+    double *f[9];
+};
+
+struct Rates5 {
+    const double *f[5];
+};
+
+// Update in place (cell order) and accumulate block partial totals.
+__global__ __launch_bounds__(kBlock) void k_integrate(int64_t n, State9 s, Rates5 r,
+                                                      const unsigned long long *dtmin, double cfl,
+                                                      double dt_in, double *__restrict__ part) {
+    double dt = step_dt(dtmin, cfl, dt_in);
+    DD acc[5];
+    for (int k = 0; k < 5; ++k) acc[k] = DD{0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        double vx = s.f[3][i] + dt * r.f[1][i];
+        double vy = s.f[4][i] + dt * r.f[2][i];
+        double vz = s.f[5][i] + dt * r.f[3][i];
+        double E = s.f[7][i] + dt * r.f[4][i];
+        double rho = s.f[6][i] + dt * r.f[0][i];
+        s.f[0][i] = s.f[0][i] + dt * vx;
+        s.f[1][i] = s.f[1][i] + dt * vy;
+        s.f[2][i] = s.f[2][i] + dt * vz;
+        s.f[3][i] = vx;
+        s.f[4][i] = vy;
+        s.f[5][i] = vz;
+        s.f[6][i] = rho;
+        s.f[7][i] = E;
+        double m = s.f[8][i];
+        acc[0] = dd_add1(acc[0], m);
+        acc[1] = dd_add1(acc[1], m * vx);
+        acc[2] = dd_add1(acc[2], m * vy);
+        acc[3] = dd_add1(acc[3], m * vz);
+        acc[4] = dd_add1(acc[4], m * E);
+    }
+    __shared__ double sh[2][5][kBlock];
+    for (int k = 0; k < 5; ++k) {
+        sh[0][k][threadIdx.x] = acc[k].hi;
+        sh[1][k][threadIdx.x] = acc[k].lo;
+    }
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            for (int k = 0; k < 5; ++k) {
+                DD a{sh[0][k][threadIdx.x], sh[1][k][threadIdx.x]};
+                DD b{sh[0][k][threadIdx.x + w], sh[1][k][threadIdx.x + w]};
+                DD c = dd_add(a, b);
+                sh[0][k][threadIdx.x] = c.hi;
+                sh[1][k][threadIdx.x] = c.lo;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 5) {
+        part[blockIdx.x * 10 + 2 * threadIdx.x] = sh[0][threadIdx.x][0];
+        part[blockIdx.x * 10 + 2 * threadIdx.x + 1] = sh[1][threadIdx.x][0];
+    }
+}
+
+static int integrate_blocks(int64_t n) {
+    int64_t want = (n + kBlock - 1) / kBlock;
+    return (int)(want < 1 ? 1 : (want > kReduceBlocks ? kReduceBlocks : want));
+}
+
+hipError_t launch_integrate(int64_t n, double *const st8[9], const Ws &w, double cfl, double dt_in,
+                            hipStream_t st) {
+    State9 s;
+    for (int k = 0; k < 9; ++k) s.f[k] = st8[k];
+    Rates5 r{{w.rate[0], w.rate[1], w.rate[2], w.rate[3], w.rate[4]}};
+    int nb = integrate_blocks(n);
+    k_integrate<<<nb, kBlock, 0, st>>>(n, s, r, w.dtmin, cfl, dt_in, w.tot_part);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_finish(const double *__restrict__ part, int nblocks,
+                                                   const unsigned long long *dtmin, double cfl,
+                                                   double dt_in, double *t, double *dt_used,
+                                                   double *totals) {
+    __shared__ double sh[2][5][kBlock];
+    DD acc[5];
+    for (int k = 0; k < 5; ++k) acc[k] = DD{0.0, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += kBlock)
+        for (int k = 0; k < 5; ++k) acc[k] = dd_add(acc[k], DD{part[b * 10 + 2 * k], part[b * 10 + 2 * k + 1]});
+    for (int k = 0; k < 5; ++k) {
+        sh[0][k][threadIdx.x] = acc[k].hi;
+        sh[1][k][threadIdx.x] = acc[k].lo;
+    }
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            for (int k = 0; k < 5; ++k) {
+                DD a{sh[0][k][threadIdx.x], sh[1][k][threadIdx.x]};
+                DD bb{sh[0][k][threadIdx.x + w], sh[1][k][threadIdx.x + w]};
+                DD c = dd_add(a, bb);
+                sh[0][k][threadIdx.x] = c.hi;
+                sh[1][k][threadIdx.x] = c.lo;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 5 && totals) {
+        totals[2 * threadIdx.x] = sh[0][threadIdx.x][0];
+        totals[2 * threadIdx.x + 1] = sh[1][threadIdx.x][0];
+    }
+    if (threadIdx.x == 0) {
+        double dt = step_dt(dtmin, cfl, dt_in);
+        if (dt_used) *dt_used = dt;
+        if (t) *t = *t + dt;
+    }
+}
+
+hipError_t launch_finish_step(int64_t n, const Ws &w, double cfl, double dt_in, double *t,
+                                double *dt_used, double *totals, hipStream_t st) {
+    k_finish<<<1, kBlock, 0, st>>>(w.tot_part, integrate_blocks(n), w.dtmin, cfl, dt_in, t,
+                                   dt_used, totals);
+    return hipGetLastError();
+}
+
+struct OutState {
+    double *f[9];
+    int32_t *mat;
+    double *d;
+    int64_t *id;
+};
+
+struct InState {
+    const double *f[9];
+    const int32_t *mat;
+    const double *d;
+    const int64_t *id;
+};
+
+__global__ __launch_bounds__(kBlock) void k_unpermute(int64_t n, const int32_t *__restrict__ perm,
+                                                      InState src, const int32_t *src_cnt,
+                                                      OutState dst, int32_t *out_cnt) {
+    int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    int i = perm[s];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) dst.f[k][i] = src.f[k][s];
+    if (dst.mat && src.mat) dst.mat[i] = src.mat[s];
+    if (dst.d && src.d) dst.d[i] = src.d[s];
+    if (dst.id && src.id) dst.id[i] = src.id[s];
+    if (out_cnt && src_cnt) out_cnt[i] = src_cnt[s];
+}
+
+hipError_t launch_unpermute(int64_t n, const int32_t *perm, double *const src[9],
+                            const int32_t *src_mat, const double *src_d, const int64_t *src_id,
+                            const int32_t *src_cnt, const csph_state &out, int32_t *out_cnt,
+                            hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    InState a;
+    for (int k = 0; k < 9; ++k) a.f[k] = src[k];
+    a.mat = src_mat;
+    a.d = src_d;
+    a.id = src_id;
+    OutState b{{out.x, out.y, out.z, out.vx, out.vy, out.vz, out.rho, out.E, out.m}, out.mat,
+               out.d, out.id};
+    k_unpermute<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(n, perm, a, src_cnt, b,
+                                                                          out_cnt);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_energy(const double *__restrict__ rho,
+                                                        const double *__restrict__ pres,
+                                                        const double *__restrict__ vx,
+                                                        const double *__restrict__ vy,
+                                                        const double *__restrict__ vz,
+                                                        const int32_t *__restrict__ mat, int64_t n,
+                                                        EosDev eos, double *__restrict__ E) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int k = mat ? mat[i] : 0;
+    if (k < 0 || k >= eos.n) k = 0;
+    double g = eos.gamma[k];
+    double e = eos.type[k] == CSPH_EOS_STIFFENED ? (pres[i] + g * eos.pinf[k]) / ((g - 1.0) * rho[i])
+                                                 : pres[i] / ((g - 1.0) * rho[i]);
+    E[i] = e + 0.5 * ((vx[i] * vx[i] + vy[i] * vy[i]) + vz[i] * vz[i]);
+}
+
+hipError_t launch_init_energy(const double *rho, const double *pres, const double *vx,
+                              const double *vy, const double *vz, const int32_t *mat, int64_t n,
+                              const EosDev &eos, double *E, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_init_energy<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(rho, pres, vx, vy, vz,
+                                                                            mat, n, eos, E);
+    return hipGetLastError();
+}
+
+}  // namespace csph

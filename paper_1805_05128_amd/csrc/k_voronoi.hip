@@ -1,0 +1,75 @@
+// Voronoi ownership (eq. VoronoiDefinition, sec. 3.1) and per-site load
+// counts.  Generators sit in LDS; each particle takes the FP64 argmin of
+// its squared distance in a fixed operation order without contraction,
+// scanning k upwards with a strict comparison so a tie keeps the smaller k.
+// Counts are integers (LDS atomics per block, then one global atomic per
+// site and block), hence exact and order independent.
+#include "csph_internal.h"
+
+namespace csph {
+
+__global__ __launch_bounds__(kBlock) void k_zero_u64(unsigned long long *p, int count) {
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < count) p[i] = 0ull;
+}
+
+__global__ __launch_bounds__(kBlock) void k_voronoi(const double *__restrict__ x,
+                                                    const double *__restrict__ y,
+                                                    const double *__restrict__ z, int64_t n,
+                                                    const double *__restrict__ sites, int K,
+                                                    const int32_t *__restrict__ nbr_count,
+                                                    int32_t *__restrict__ owner,
+                                                    unsigned long long *__restrict__ site_part,
+                                                    unsigned long long *__restrict__ site_pairs) {
+    extern __shared__ double smem[];
+    double *gs = smem;                                                  // 3K
+    unsigned long long *hq = (unsigned long long *)(smem + 3 * K);      // K
+    unsigned int *hp = (unsigned int *)(hq + K);                        // K
+    for (int k = threadIdx.x; k < 3 * K; k += kBlock) gs[k] = sites[k];
+    for (int k = threadIdx.x; k < K; k += kBlock) {
+        hp[k] = 0u;
+        hq[k] = 0ull;
+    }
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        double xi = x[i], yi = y[i], zi = z[i];
+        int best = 0;
+        double bd = INFINITY;
+        for (int k = 0; k < K; ++k) {
+            double dx = xi - gs[3 * k], dy = yi - gs[3 * k + 1], dz = zi - gs[3 * k + 2];
+            double d2 = ((dx * dx) + (dy * dy)) + (dz * dz);
+            if (d2 < bd) {
+                bd = d2;
+                best = k;
+            }
+        }
+        owner[i] = best;
+        atomicAdd(&hp[best], 1u);
+        if (nbr_count) atomicAdd(&hq[best], (unsigned long long)nbr_count[i]);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += kBlock) {
+        if (hp[k]) atomicAdd(&site_part[k], (unsigned long long)hp[k]);
+        if (site_pairs && hq[k]) atomicAdd(&site_pairs[k], hq[k]);
+    }
+}
+
+hipError_t launch_voronoi(const double *x, const double *y, const double *z, int64_t n,
+                          const double *sites, int K, const int32_t *nbr_count, int32_t *owner,
+                          int64_t *site_particles, int64_t *site_pairs, hipStream_t st) {
+    unsigned zb = (unsigned)((K + kBlock - 1) / kBlock);
+    k_zero_u64<<<zb, kBlock, 0, st>>>((unsigned long long *)site_particles, K);
+    if (site_pairs) k_zero_u64<<<zb, kBlock, 0, st>>>((unsigned long long *)site_pairs, K);
+    if (n > 0) {
+        int64_t want = (n + kBlock - 1) / kBlock;
+        unsigned nb = (unsigned)(want > kReduceBlocks ? kReduceBlocks : want);
+        size_t shm = (size_t)K * (3 * sizeof(double) + sizeof(unsigned long long) + sizeof(unsigned));
+        k_voronoi<<<nb, kBlock, shm, st>>>(x, y, z, n, sites, K, site_pairs ? nbr_count : nullptr,
+                                           owner, (unsigned long long *)site_particles,
+                                           (unsigned long long *)site_pairs);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace csph

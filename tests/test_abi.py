@@ -1,0 +1,84 @@
+"""C-ABI library checks that need no GPU: it loads, exports every function
+include/csph.h declares, and rejects bad arguments before any device work."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_1805_05128_amd as P
+from paper_1805_05128_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    names = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names += re.findall(r"^[A-Za-z_][\w \*]*?\b(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("defined",)))
+
+
+def test_library_exports_every_declared_function():
+    L = N.load()
+    names = header_functions()
+    assert "csph_step" in names and "voronoi_assign" in names and len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_status_strings_and_version():
+    L = N.load()
+    for s in (0, 1, 2, 3):
+        assert L.csph_status_string(s).decode().startswith("CSPH_")
+    assert P.version().startswith("csph-gfx950")
+
+
+def test_workspace_size_grows():
+    p = P.Params()
+    a = P.workspace_size(1000, 100, p)
+    b = P.workspace_size(2000, 100, p)
+    c = P.workspace_size(2000, 10_000, p)
+    assert 0 < a < b < c
+    assert b - a >= 1000 * 200  # per-particle buffers
+
+
+@pytest.mark.parametrize("bad", [
+    dict(eos=[(0, 1.0, 0.0)]),
+    dict(eos=[(7, 1.4, 0.0)]),
+    dict(eos=[]),
+    dict(h=0.0),
+    dict(kappa=-1.0),
+    dict(precision="half"),
+])
+def test_invalid_params_rejected_without_device_work(bad):
+    L = N.load()
+    kw = dict(eos=[(0, 1.4, 0.0)])
+    prec = bad.pop("precision", None)
+    kw.update(bad)
+    p = P.Params(**kw).c()
+    if prec is not None:
+        p.precision = 9
+    st = L.csph_init_energy(None, None, None, None, None, None, 0, C.byref(p), None, None)
+    assert st == N.CSPH_EINVAL
+    assert L.csph_last_error()
+
+
+def test_invalid_arguments_rejected():
+    L = N.load()
+    p = P.Params().c()
+    assert L.voronoi_assign(None, None, None, 10, None, 4, None, None, None, None,
+                            None) == N.CSPH_EINVAL
+    assert L.voronoi_assign(None, None, None, 0, None, 0, None, None, None, None,
+                            None) == N.CSPH_EINVAL
+    s = N.CsphState()
+    s.n = -1
+    assert L.csph_rates(C.byref(s), C.byref(p), 0.0, N.CsphRatesOut(), None, None, None, None, 0,
+                        None, None) == N.CSPH_EINVAL
+    s.n = 5  # NULL field pointers
+    assert L.csph_step(C.byref(s), C.byref(s), C.byref(p), None, 0.0, None, None, None, None,
+                       None, 0, None, None) == N.CSPH_EINVAL

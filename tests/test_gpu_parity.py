@@ -1,0 +1,356 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Bit-exact: E from (rho, p, v), binning (mesh, keys, cell order, cell
+ranges), neighbour sets, Voronoi ownership and load counts.  FP64 rates and
+step within 1e-12 relative per field; mixed (FP32 pair) rates within 2e-5
+relative per field.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import csph_inputs as ci
+import oracle as O
+import paper_1805_05128_amd as P
+from helpers import RATE_FIELDS, field_relerr, rates_np, to_np
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+FP64_TOL = 1e-12
+MIXED_TOL = 2e-5
+
+
+def _print_case(name, w):
+    print(f"[case] {name} n={w.n}", flush=True)
+
+
+def gpu_state(w, params):
+    return P.state_from_workload(w, params, DEV)
+
+
+def ref_state(w):
+    return O.state_from(w, O.cfg_for(w))
+
+
+def wall_block(seed=5):
+    w = ci.jittered_block(12, 10, 9, seed=seed, v=(-0.2, 0.1, 0.05))
+    w.wall = (0.0, 0.4)
+    return w
+
+
+def two_material_cloud(n=3000, seed=11):
+    w = ci.random_cloud(n, seed=seed, box=10.0, n_mat=2)
+    w.cell_size = 3.0
+    return w
+
+
+CASES = {
+    "sod16": ci.config0,
+    "cloud2mat": two_material_cloud,
+    "wall": wall_block,
+    "ragged": lambda: ci.random_cloud(777, seed=3, box=7.3, vmax=1.0),
+}
+
+
+# ------------------------------------------------------------------ EOS inverse
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_init_energy_bitexact(case):
+    w = CASES[case]()
+    _print_case(case, w)
+    params = P.Params.from_workload(w)
+    g = gpu_state(w, params)
+    r = ref_state(w)
+    assert np.array_equal(to_np(g["E"]), r["E"])
+
+
+# ------------------------------------------------------------------ binning
+
+def _bin_case(x, y, z, D):
+    params = P.Params(cell_size=D)
+    tx, ty, tz = [torch.as_tensor(a, dtype=torch.float64, device=DEV) for a in (x, y, z)]
+    g = P.csph_grid_build(tx, ty, tz, params)
+    key, perm, cs = P.csph_bin(tx, ty, tz, g)
+    torch.cuda.synchronize()
+    ref = O.bin(x, y, z, D)
+    assert list(g.origin) == ref["origin"].tolist()
+    assert list(g.dims) == ref["dims"].tolist()
+    assert g.inv_cell == 1.0 / D and g.ncell == ref["ncell"]
+    assert np.array_equal(to_np(key), ref["key"])
+    assert np.array_equal(to_np(perm).astype(np.int64), ref["perm"])
+    assert np.array_equal(to_np(cs).astype(np.int64), ref["cell_start"])
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_bin_bitexact(case):
+    w = CASES[case]()
+    _print_case(case, w)
+    for D in (3.0, 1.5, 0.7):
+        _bin_case(w.x, w.y, w.z, D)
+
+
+def test_bin_points_on_faces():
+    rng = np.random.default_rng(5)
+    D = 0.75
+    base = rng.integers(0, 9, size=(5000, 3)).astype(np.float64) * D + 1.25
+    base[::3] += rng.uniform(0, D, size=base[::3].shape)
+    _bin_case(*[np.ascontiguousarray(base[:, k]) for k in range(3)], D)
+
+
+def test_bin_one_particle_and_all_in_one_cell():
+    _bin_case(np.array([1.0]), np.array([2.0]), np.array([3.0]), 3.0)
+    rng = np.random.default_rng(1)
+    pts = rng.uniform(0, 1, size=(300, 3))
+    _bin_case(*[np.ascontiguousarray(pts[:, k]) for k in range(3)], 10.0)
+
+
+# ------------------------------------------------------------------ neighbours
+
+def _nbr_case(w, params, cfg_over=None, d=None):
+    g = gpu_state(w, params)
+    if d is not None:
+        g.d = torch.as_tensor(d, dtype=torch.float64, device=DEV)
+    off, idx = P.csph_neighbors(g, params)
+    torch.cuda.synchronize()
+    cfg = O.cfg_for(w, **(cfg_over or {}))
+    ro, ri = O.neighbors(cfg, w.x, w.y, w.z, d)
+    assert np.array_equal(to_np(off), ro)
+    assert np.array_equal(to_np(idx), ri)
+    return ro, ri
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_neighbors_bitexact(case):
+    w = CASES[case]()
+    _print_case(case, w)
+    _nbr_case(w, P.Params.from_workload(w))
+
+
+def test_neighbors_perfect_lattice_ties_at_support():
+    w = ci.jittered_block(10, 10, 10, seed=0, amp=0.0)
+    ro, ri = _nbr_case(w, P.Params.from_workload(w))
+    assert np.diff(ro).max() == 92
+
+
+def test_neighbors_small_cells_and_pair_mode():
+    w = ci.random_cloud(2000, seed=4, box=8.0)
+    _nbr_case(w, P.Params.from_workload(w, cell_size=1.1))
+    d = np.random.default_rng(1).uniform(0.8, 1.2, w.n)
+    params = P.Params.from_workload(w, h_mode="pair", kappa=1.936, cell_size=0.0)
+    _nbr_case(w, params, dict(h_mode=1, kappa=1.936), d=d)
+
+
+def test_neighbors_coincident_and_single():
+    w = ci.random_cloud(3, seed=1, box=1.0)
+    w.x[1], w.y[1], w.z[1] = w.x[0], w.y[0], w.z[0]
+    _nbr_case(w, P.Params.from_workload(w))
+    w1 = ci.random_cloud(1, seed=2, box=1.0)
+    ro, ri = _nbr_case(w1, P.Params.from_workload(w1))
+    assert ro.tolist() == [0, 0]
+
+
+# ------------------------------------------------------------------ rates
+
+def _rates_case(w, precision, t=0.0):
+    params = P.Params.from_workload(w, precision=precision)
+    g = gpu_state(w, params)
+    out = P.csph_rates(g, params, t=t)
+    torch.cuda.synchronize()
+    ref = O.rates(O.cfg_for(w, search=1), ref_state(w), t=t)
+    return rates_np(out), ref
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_rates_fp64(case):
+    w = CASES[case]()
+    _print_case(case, w)
+    got, ref = _rates_case(w, "fp64", t=0.25)
+    err = field_relerr(got, ref)
+    print("fp64 relerr", err)
+    assert max(err.values()) <= FP64_TOL, err
+    assert np.array_equal(got["nbr_count"].astype(np.int64), ref["nbr_count"])
+    assert np.abs(got["signal"] - ref["signal"]).max() <= 1e-13 * ref["signal"].max()
+    assert int(got["nonphys"][0]) == ref["nonphys"] == 0
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_rates_mixed(case):
+    w = CASES[case]()
+    _print_case(case, w)
+    got, ref = _rates_case(w, "mixed", t=0.25)
+    err = field_relerr(got, ref)
+    print("mixed relerr", err)
+    assert max(err.values()) <= MIXED_TOL, err
+    assert np.abs(got["signal"] - ref["signal"]).max() <= 1e-5 * ref["signal"].max()
+
+
+def test_rates_plate_impact_block_mixed_and_fp64():
+    """A 2-material-free impact slice (v_z = -5 projectile) at the contact time."""
+    w = ci.config1()
+    keep = (w.x > 40) & (w.x < 56) & (w.y > 40) & (w.y < 56) & (w.z > 22)
+    for k in ("x", "y", "z", "vx", "vy", "vz", "rho", "p", "m", "mat"):
+        setattr(w, k, np.ascontiguousarray(getattr(w, k)[keep]))
+    w.z[w.z > 33] -= 1.5  # bring the projectile into contact
+    _print_case("impact-slice", w)
+    for prec, tol in (("fp64", FP64_TOL), ("mixed", MIXED_TOL)):
+        got, ref = _rates_case(w, prec)
+        err = field_relerr(got, ref)
+        print(prec, err)
+        assert max(err.values()) <= tol, (prec, err)
+
+
+def test_rates_isolated_and_coincident():
+    w = ci.random_cloud(4, seed=3, box=1.0)
+    w.x[:] = [0.0, 0.0, 50.0, 100.0]
+    w.y[:] = 0.0
+    w.z[:] = 0.0
+    _print_case("isolated+coincident", w)
+    got, ref = _rates_case(w, "fp64")
+    for k in RATE_FIELDS:
+        assert np.array_equal(got[k], ref[k]), k
+        assert np.all(got[k] == 0.0)
+    assert got["nbr_count"].tolist() == [1, 1, 0, 0]
+
+
+def test_nonphysical_counted():
+    w = ci.random_cloud(200, seed=5, box=4.0)
+    w.p[:10] = -5.0  # negative pressure below -p_inf: c^2 < 0
+    w.eos = [(1, 3.0, 0.5)]
+    params = P.Params.from_workload(w)
+    g = gpu_state(w, params)
+    out = P.csph_rates(g, params)
+    ref = O.rates(O.cfg_for(w, search=1), ref_state(w))
+    assert int(out["nonphys"][0]) == ref["nonphys"] == 10
+
+
+def test_rates_deterministic():
+    w = ci.config0()
+    params = P.Params.from_workload(w, precision="mixed")
+    g = gpu_state(w, params)
+    a = rates_np(P.csph_rates(g, params))
+    b = rates_np(P.csph_rates(g, params))
+    for k in RATE_FIELDS:
+        assert np.array_equal(a[k], b[k])
+
+
+# ------------------------------------------------------------------ step
+
+def _check_totals(tot_gpu, s_ref):
+    exact = O.totals(s_ref)
+    scale = [np.abs(s_ref["m"]).sum(), np.abs(s_ref["m"] * s_ref["vx"]).sum(),
+             np.abs(s_ref["m"] * s_ref["vy"]).sum(), np.abs(s_ref["m"] * s_ref["vz"]).sum(),
+             np.abs(s_ref["m"] * s_ref["E"]).sum()]
+    for k in range(5):
+        hi, lo = tot_gpu[2 * k], tot_gpu[2 * k + 1]
+        got = math.fsum([hi, lo])
+        assert abs(got - exact[k]) <= 4 * math.ulp(abs(exact[k])) + 1e-28 * scale[k], (k, got,
+                                                                                      exact[k])
+
+
+@pytest.mark.parametrize("reorder", [False, True])
+@pytest.mark.parametrize("case", ["sod16", "wall", "cloud2mat"])
+def test_step_fp64(case, reorder):
+    w = CASES[case]()
+    _print_case(f"{case} reorder={reorder}", w)
+    params = P.Params.from_workload(w, reorder=reorder)
+    g = gpu_state(w, params)
+    sc = P.StepScalars(DEV, t0=0.125)
+    cnt = torch.empty(w.n, dtype=torch.int32, device=DEV)
+    out = P.csph_step(g, params, sc, nbr_count=cnt)
+    torch.cuda.synchronize()
+    s0 = ref_state(w)
+    s1, t1, dt, ncount = O.step(O.cfg_for(w, search=1), s0, t=0.125)
+    got = out.numpy()
+    ids = got["id"]
+    if not reorder:
+        assert np.array_equal(ids, np.arange(w.n))
+    assert np.array_equal(np.sort(ids), np.arange(w.n))
+    assert abs(to_np(sc.dt)[0] - dt) <= 1e-15 * dt
+    assert abs(to_np(sc.t)[0] - t1) <= 1e-15 * t1
+    for k in ("x", "y", "z", "vx", "vy", "vz", "rho", "E"):
+        a = got[k]
+        b = s1[k][ids]
+        inc = (b - s0[k][ids])
+        den = max(np.abs(inc).max(), 1e-300)
+        assert np.abs(a - b).max() <= FP64_TOL * den + 4 * np.finfo(float).eps * np.abs(b).max(), k
+    assert np.array_equal(got["m"], s0["m"][ids])
+    assert np.array_equal(got["mat"], s0["mat"][ids])
+    assert np.array_equal(to_np(cnt).astype(np.int64), ncount[ids])
+    # the totals are compensated sums over the GPU's own new state
+    _check_totals(to_np(sc.totals), got)
+
+
+def test_step_mixed_rates_within_tolerance():
+    w = ci.config0()
+    params = P.Params.from_workload(w, precision="mixed", reorder=False)
+    g = gpu_state(w, params)
+    s0 = {k: to_np(v).copy() for k, v in g.t.items()}
+    sc = P.StepScalars(DEV)
+    P.csph_step(g, params, sc)
+    dt = float(to_np(sc.dt)[0])
+    got = g.numpy()
+    ref = O.rates(O.cfg_for(w, search=1), ref_state(w))
+    est = {"drho": (got["rho"] - s0["rho"]) / dt, "dvx": (got["vx"] - s0["vx"]) / dt,
+           "dvy": (got["vy"] - s0["vy"]) / dt, "dvz": (got["vz"] - s0["vz"]) / dt,
+           "dE": (got["E"] - s0["E"]) / dt}
+    err = field_relerr(est, ref)
+    assert max(err.values()) <= MIXED_TOL, err
+    assert abs(dt - O.dt(O.cfg_for(w), ref["signal"])) <= 1e-5 * dt
+
+
+def test_step_empty():
+    params = P.Params()
+    s = P.State.empty(0, DEV, with_id=True)
+    sc = P.StepScalars(DEV)
+    P.csph_step(s, params, sc, s_out=P.State.empty(0, DEV, with_id=True))
+    torch.cuda.synchronize()
+    assert to_np(sc.totals).tolist() == [0.0] * 10
+
+
+# ------------------------------------------------------------------ Voronoi
+
+def _voronoi_case(x, y, z, sites, cnt):
+    tx, ty, tz = [torch.as_tensor(a, dtype=torch.float64, device=DEV) for a in (x, y, z)]
+    tc = torch.as_tensor(cnt, dtype=torch.int32, device=DEV)
+    owner, sp, spairs = P.voronoi_assign(tx, ty, tz, torch.as_tensor(sites, device=DEV), tc)
+    torch.cuda.synchronize()
+    ro, rsp, rspairs = O.voronoi(x, y, z, sites, cnt.astype(np.int64))
+    assert np.array_equal(to_np(owner), ro)
+    assert np.array_equal(to_np(sp), rsp)
+    assert np.array_equal(to_np(spairs), rspairs)
+
+
+def test_voronoi_bitexact_random_and_ties():
+    rng = np.random.default_rng(17)
+    pts = rng.uniform(0, 32, size=(20000, 3))
+    sites = rng.uniform(0, 32, size=(64, 3))
+    # exact ties: points on bisector planes of site pairs placed on a grid
+    sites[1] = sites[0] + np.array([2.0, 0.0, 0.0])
+    mid = sites[0] + np.array([1.0, 0.0, 0.0])
+    pts[:5] = mid
+    cnt = rng.integers(0, 130, size=pts.shape[0])
+    _voronoi_case(*[np.ascontiguousarray(pts[:, k]) for k in range(3)], sites, cnt)
+
+
+@pytest.mark.parametrize("K", [1, 7, 2048])
+def test_voronoi_site_counts(K):
+    rng = np.random.default_rng(K)
+    pts = rng.uniform(0, 10, size=(5000, 3))
+    sites = rng.uniform(0, 10, size=(K, 3))
+    cnt = rng.integers(0, 100, size=5000)
+    _voronoi_case(*[np.ascontiguousarray(pts[:, k]) for k in range(3)], sites, cnt)
+
+
+def test_voronoi_with_gpu_neighbour_counts():
+    w = ci.config2(nside=32)
+    _print_case("porous32", w)
+    params = P.Params.from_workload(w)
+    g = gpu_state(w, params)
+    out = P.csph_rates(g, params)
+    cnt = to_np(out["nbr_count"])
+    ref = O.rates(O.cfg_for(w, search=1), ref_state(w))
+    assert np.array_equal(cnt.astype(np.int64), ref["nbr_count"])
+    _voronoi_case(w.x, w.y, w.z, np.ascontiguousarray(w.sites), cnt)
