@@ -213,7 +213,7 @@ csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_para
 /* Voronoi ownership (eq. VoronoiDefinition): owner[i] = the k minimising
  * ((x_i-g_kx)^2 + (y_i-g_ky)^2) + (z_i-g_kz)^2 in FP64 without contraction,
  * a tie going to the smaller k (sec. 3.1).  sites: K x 3 FP64, global
- * coordinates, 1 <= K <= 4096.  site_particles[k] (int64) = number of owned
+ * coordinates, 1 <= K <= 1024.  site_particles[k] (int64) = number of owned
  * particles; site_pairs[k] (int64, optional, needs nbr_count) = sum of
  * nbr_count over owned particles (interaction counts as the load measure,
  * sec. 1).  Both count arrays are overwritten.  Bit-exact (integers). */

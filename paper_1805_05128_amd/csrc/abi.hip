@@ -378,11 +378,11 @@ csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_para
         CSPH_HIP(launch_pack(*s_in, n, w.perm, eos, mixed, gd, w, dst, dmat, dd, did, s_in->id,
                              nonphys, st));
     }
-    if (p->cfl > 0.0) CSPH_HIP(launch_fill_u64(w.dtmin, 0x7ff0000000000000ull, 1, st));
-    if (n > 0) {
-        CSPH_HIP(launch_rates(n, mixed, gd, pc, w, dst, dd, t, 0.0, p->cfl > 0.0, st));
-        CSPH_HIP(launch_integrate(n, dst, w, p->cfl, dt_in, st));
-    }
+    // dt = cfl * min h/s; an empty set takes dt = 0
+    if (p->cfl > 0.0)
+        CSPH_HIP(launch_fill_u64(w.dtmin, n > 0 ? 0x7ff0000000000000ull : 0ull, 1, st));
+    if (n > 0) CSPH_HIP(launch_rates(n, mixed, gd, pc, w, dst, dd, t, 0.0, p->cfl > 0.0, st));
+    CSPH_HIP(launch_integrate(n, dst, w, p->cfl, dt_in, st));  // n = 0 writes zero partials
     CSPH_HIP(launch_finish_step(n, w, p->cfl, dt_in, t, dt_used, totals, st));
     if (n > 0) {
         if (p->reorder) {

@@ -16,7 +16,7 @@ constexpr int kBlock = 256;           // threads per workgroup (4 wave64)
 constexpr int kReduceBlocks = 1024;   // partial-reduction blocks (bounds, totals)
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kBlock * kScanItems;
-constexpr int kMaxSites = 2048;       // Voronoi generators held in LDS
+constexpr int kMaxSites = 1024;       // Voronoi generators held in LDS (36 B each)
 
 // Mesh as the kernels see it.
 struct GridDev {
