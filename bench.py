@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Throughput of the contact-SPH hot path on one MI355X.
+
+A step is one pass of the whole hot path over the particle set: mesh
+bounds, cell binning and cell-ordered renumbering, pack + EOS, pair rates
+(Riemann-solver contact flux), state update with the CFL time step and
+compensated totals, then Voronoi ownership with per-site particle and pair
+counts for 64 generators.
+
+Default workload: porous-sample shock, 256^3 jittered lattice with seeded
+spherical voids (radius 5, 30 % porosity, 11 743 903 particles), ideal gas
+1.4, piston at x = 0 moving at +2, FP32 pair arithmetic with FP64 positions,
+integration and totals.  The plain-FP64 GPU step is timed beside it.
+
+Prints ONE JSON line.  `value` = directed pair interactions per second
+(sum_i |N(i)| per step x steps per second) with the state resident in HBM.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "CSPH pair-interactions/s and steps/s at 16M particles; adjoint/forward time ratio"
+PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector (published)
+PEAK_HBM_GBS = 8000.0
+# algorithmic FP32 operations per directed interacting pair: r, 1/r, e (3),
+# q, 1-q, W' (4), v_L, v_R (10), S, 1/S, v* (6), P* (8), weight (1), the
+# three sums (3 + 7 + 2) and the signal speed (3); see the design doc.
+FLOP_PER_PAIR = 53
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="porous", choices=["porous", "voidfree"])
+    ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-slab", type=float, default=96.0,
+                    help="oracle sample: particles with x < this (same workload)")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_steps(P, torch, state, params, sites, k, ws, sc, count_pairs=True):
+    """k steps of (csph_step, voronoi_assign); returns (state, pairs summed on device)."""
+    n = state.n
+    cnt = torch.empty(n, dtype=torch.int32, device="cuda")
+    owner = torch.empty(n, dtype=torch.int32, device="cuda")
+    pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    other = state.like()
+    for _ in range(k):
+        out = P.csph_step(state, params, sc, s_out=other, nbr_count=cnt, ws=ws)
+        _, sp, spairs = P.voronoi_assign(out["x"], out["y"], out["z"], sites, cnt, owner=owner)
+        if count_pairs:
+            pairs += spairs.sum()
+        state, other = out, state
+    return state, pairs
+
+
+def cpu_baseline(w, slab):
+    import numpy as np
+
+    import oracle as O
+    keep = w.x < slab
+    sub = type(w)(**{**w.__dict__})
+    for k in ("x", "y", "z", "vx", "vy", "vz", "rho", "p", "m", "mat"):
+        setattr(sub, k, np.ascontiguousarray(getattr(w, k)[keep]))
+    cfg = O.cfg_for(sub, search=1)
+    s = O.state_from(sub, cfg)
+    t0 = time.perf_counter()
+    _, _, _, cnt = O.step(cfg, s, 0.0)
+    el = time.perf_counter() - t0
+    pairs = int(cnt.sum())
+    return {"value": pairs / el, "unit": "pair-interactions/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"one full oracle step (cell-list search, FP64) on the slab x < {slab:g} of "
+                      f"the same porous workload: {sub.n} particles, {pairs} directed pairs, "
+                      f"{el:.2f} s",
+            "steps_per_s_sample": 1.0 / el}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "decomposition is described in DESIGN.md, not built", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import csph_inputs as ci
+    import paper_1805_05128_amd as P
+
+    t_gen = time.perf_counter()
+    w = ci.config2(voids=(args.workload == "porous"))
+    log(f"workload {w.name}: {w.n} particles ({time.perf_counter() - t_gen:.1f} s to generate)")
+    torch.cuda.set_device(0)
+    sites = torch.as_tensor(w.sites, dtype=torch.float64, device="cuda")
+    ws = P.Workspace("cuda")
+
+    results = {}
+    for prec, k in (("mixed", args.steps), ("fp64", args.fp64_steps)):
+        if k <= 0:
+            continue
+        params = P.Params.from_workload(w, precision=prec, reorder=True)
+        state = P.state_from_workload(w, params, "cuda", with_id=True)
+        sc = P.StepScalars("cuda")
+        P.profile_enable(True)  # warm-up steps also warm the event pool
+        state, _ = run_steps(P, torch, state, params, sites, args.warmup, ws, sc, False)
+        torch.cuda.synchronize()
+        tot0 = sc.totals.cpu().numpy().copy()
+        P.profile_read()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        state, pairs = run_steps(P, torch, state, params, sites, k, ws, sc)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = P.profile_read()
+        P.profile_enable(False)
+        tot1 = sc.totals.cpu().numpy()
+        npairs = int(pairs.item())
+        results[prec] = dict(ms=1e3 * el / k, pairs_per_step=npairs / k, el=el, k=k, prof=prof,
+                             nonphys=int(sc.nonphys.item()), t=float(sc.t.item()),
+                             tot0=tot0, tot1=tot1)
+        log(f"{prec}: {1e3 * el / k:.3f} ms/step, {npairs / el:.3e} pairs/s, "
+            f"rates kernel {prof['rates'][1] / max(prof['rates'][0], 1):.3f} ms")
+        del state
+
+    m = results["mixed"]
+    rates_launches, rates_ms = m["prof"]["rates"]
+    rates_avg_s = rates_ms / max(rates_launches, 1) / 1e3
+    flops = FLOP_PER_PAIR * m["pairs_per_step"]
+    achieved = flops / rates_avg_s / 1e12
+    kernels = {g: round(v[1] / max(v[0], 1), 4) for g, v in m["prof"].items() if v[0] > 0}
+    e0 = m["tot0"][8] + m["tot0"][9]
+    e1 = m["tot1"][8] + m["tot1"][9]
+    line = {
+        "metric": METRIC,
+        "value": m["pairs_per_step"] * 1e3 / m["ms"],
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": m["ms"],
+        "steps_per_s": 1e3 / m["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pair arithmetic, f64 positions/integration/totals",
+        "data": "synthetic",
+        "config": {"workload": w.name, "particles": w.n, "lattice": "256^3, 30% voids r=5",
+                   "support": "2h = 3 spacings", "piston": "x=0, v=+2", "voronoi_sites": 64,
+                   "eos": "ideal gas 1.4", "cfl": 0.3},
+        "pairs_per_step": m["pairs_per_step"],
+        "kernel_ms": kernels,
+        "roofline": {"bound": "alu", "kernel": "k_rates32 (pair rates, FP32)",
+                     "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "flop_per_pair": FLOP_PER_PAIR},
+        "energy_total_rel_change": (e1 - e0) / abs(e0) if e0 else None,
+        "nonphys": m["nonphys"],
+    }
+    if "fp64" in results:
+        f = results["fp64"]
+        line["fp64"] = {"ms_per_step": f["ms"], "value": f["pairs_per_step"] * 1e3 / f["ms"],
+                        "rates_kernel_ms": f["prof"]["rates"][1] / max(f["prof"]["rates"][0], 1)}
+        line["mixed_speedup_over_fp64"] = f["ms"] / m["ms"]
+    if not args.no_cpu_baseline:
+        log("oracle CPU baseline ...")
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_slab)
+        log(f"oracle: {line['cpu_baseline']['value']:.3e} pairs/s on "
+            f"{line['cpu_baseline']['cores']} cores")
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

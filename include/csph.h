@@ -229,6 +229,29 @@ csph_status csph_init_energy(const double *rho, const double *pres, const double
                              const double *vy, const double *vz, const int32_t *mat, int64_t n,
                              const csph_params *p, double *E, csph_stream stream);
 
+/* Kernel timing.  While enabled, every call records a pair of HIP events
+ * on its stream around each kernel group below; csph_profile_read waits for
+ * the recorded events, returns the summed durations and launch counts
+ * since the previous read, and clears them.  Meant for benchmarks: the
+ * events add a few microseconds per launch.  Not thread-safe across
+ * concurrent callers. */
+#define CSPH_PROF_BIN 0        /* bounds, keys, scan, scatter, per-cell order */
+#define CSPH_PROF_PACK 1       /* gather into cell order + EOS + pair records */
+#define CSPH_PROF_RATES 2      /* the pair-rate kernel */
+#define CSPH_PROF_INTEGRATE 3  /* state update, dt, totals */
+#define CSPH_PROF_VORONOI 4
+#define CSPH_PROF_REORDER 5    /* return to input order */
+#define CSPH_PROF_NEIGHBORS 6
+#define CSPH_PROF_ADJOINT 7
+#define CSPH_PROF_GROUPS 8
+typedef struct {
+    int64_t launches[CSPH_PROF_GROUPS];
+    double ms[CSPH_PROF_GROUPS];
+} csph_profile;
+
+csph_status csph_profile_enable(int32_t on);
+csph_status csph_profile_read(csph_profile *out /* host */);
+
 #ifdef __cplusplus
 }
 #endif

@@ -3,5 +3,5 @@ rates, step, Voronoi ownership and their adjoints, behind the C ABI of
 include/csph.h (libcsph.so, hand-written HIP)."""
 from .api import (EOS_IDEAL, EOS_STIFFENED, Params, State, StepScalars, Workspace,  # noqa: F401
                   csph_bin, csph_grid_build, csph_init_energy, csph_neighbors, csph_rates,
-                  csph_step, default_workspace, state_from_workload, version, voronoi_assign,
+                  csph_step, default_workspace, profile_enable, profile_read, state_from_workload, version, voronoi_assign,
                   workspace_size)

@@ -55,6 +55,13 @@ class CsphRatesOut(C.Structure):
     _fields_ = [(k, _dp) for k in ("drho", "dvx", "dvy", "dvz", "dE")]
 
 
+PROF_GROUPS = ("bin", "pack", "rates", "integrate", "voronoi", "reorder", "neighbors", "adjoint")
+
+
+class CsphProfile(C.Structure):
+    _fields_ = [("launches", C.c_int64 * 8), ("ms", C.c_double * 8)]
+
+
 _lib = None
 
 
@@ -105,6 +112,10 @@ def load():
     L.csph_init_energy.restype = C.c_int32
     L.csph_init_energy.argtypes = [_dp, _dp, _dp, _dp, _dp, _ip, C.c_int64,
                                    C.POINTER(CsphParams), _dp, vp]
+    L.csph_profile_enable.restype = C.c_int32
+    L.csph_profile_enable.argtypes = [C.c_int32]
+    L.csph_profile_read.restype = C.c_int32
+    L.csph_profile_read.argtypes = [C.POINTER(CsphProfile)]
     _lib = L
     return L
 

@@ -187,6 +187,17 @@ def _with_ws(fn, ws: Workspace, where: str):
     N.check(st, where)
 
 
+def profile_enable(on: bool = True):
+    N.check(N.load().csph_profile_enable(1 if on else 0), "csph_profile_enable")
+
+
+def profile_read() -> Dict[str, Tuple[int, float]]:
+    """{group: (launches, total ms)} since the previous read (waits for the events)."""
+    pr = N.CsphProfile()
+    N.check(N.load().csph_profile_read(C.byref(pr)), "csph_profile_read")
+    return {g: (int(pr.launches[k]), float(pr.ms[k])) for k, g in enumerate(N.PROF_GROUPS)}
+
+
 def version() -> str:
     return N.load().csph_version().decode()
 

@@ -3,6 +3,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
+#include <vector>
 
 #include "csph_internal.h"
 
@@ -26,6 +28,58 @@ static csph_status fail(csph_status s, const char *fmt, ...) {
     } while (0)
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// ---------------------------------------------------------------- kernel timing
+
+struct ProfRec {
+    int group;
+    hipEvent_t a, b;
+};
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<ProfRec> g_prof_pending;
+static std::vector<hipEvent_t> g_prof_pool;
+static csph_profile g_prof_acc;
+
+static hipEvent_t prof_event() {
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records a start event on construction and a stop event on stop().
+struct ProfScope {
+    int group;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    ProfScope(int g, hipStream_t s) : group(g), st(s) {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (!g_prof_on) return;
+        a = prof_event();
+        if (a && hipEventRecord(a, st) != hipSuccess) {
+            g_prof_pool.push_back(a);
+            a = nullptr;
+        }
+    }
+    void stop() {
+        if (!a) return;
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        hipEvent_t b = prof_event();
+        if (b && hipEventRecord(b, st) == hipSuccess) {
+            g_prof_pending.push_back(ProfRec{group, a, b});
+        } else {
+            g_prof_pool.push_back(a);
+            if (b) g_prof_pool.push_back(b);
+        }
+        a = nullptr;
+    }
+    ~ProfScope() { stop(); }
+};
 
 size_t ws_layout(Ws *w, void *base, int64_t n, int64_t ncell) {
     size_t off = 0;
@@ -245,6 +299,7 @@ csph_status csph_bin(const double *x, const double *y, const double *z, int64_t 
     Ws w;
     ws_layout(&w, ws, n, ncell);
     hipStream_t st = (hipStream_t)stream;
+    ProfScope pb(CSPH_PROF_BIN, st);
     CSPH_HIP(launch_bin(x, y, z, n, grid_dev(*grid), w, perm, key, cell_start, st));
     return CSPH_OK;
 }
@@ -271,10 +326,12 @@ csph_status csph_neighbors(const csph_state *s, const csph_params *p, int64_t *o
     GridDev gd = grid_dev(g);
     PairConst pc = pair_const(p, dmax);
     const double *dd = p->h_mode == CSPH_H_PAIR ? s->d : nullptr;
+    ProfScope pn(CSPH_PROF_NEIGHBORS, st);
     CSPH_HIP(launch_bin(s->x, s->y, s->z, n, gd, w, w.perm, nullptr, w.cs, st));
     CSPH_HIP(launch_gather_pos(n, w.perm, s->x, s->y, s->z, dd, w, st));
     CSPH_HIP(launch_nbr_count(n, gd, pc, w.srt[0], w.srt[1], w.srt[2], w.srt_d, w.cs, w.perm,
                               w.cnt, st));
+    pn.stop();
     CSPH_HIP((launch_scan_exclusive<int32_t, int64_t>(w.cnt, offsets, n, w.scan_tmp, st)));
     int64_t total = 0;
     CSPH_HIP(hipMemcpyAsync(&total, offsets + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -314,12 +371,24 @@ csph_status csph_rates(const csph_state *s, const csph_params *p, double t, csph
     EosDev eos = eos_dev(p);
     int mixed = p->precision == CSPH_MIXED;
     bool pair = p->h_mode == CSPH_H_PAIR;
-    CSPH_HIP(launch_bin(s->x, s->y, s->z, n, gd, w, w.perm, nullptr, w.cs, st));
-    CSPH_HIP(launch_pack(*s, n, w.perm, eos, mixed, gd, w, w.srt, w.srt_mat,
-                         pair ? w.srt_d : nullptr, nullptr, nullptr, nonphys, st));
-    CSPH_HIP(launch_rates(n, mixed, gd, pc, w, w.srt, pair ? w.srt_d : nullptr, nullptr, t, 0,
-                          st));
-    CSPH_HIP(launch_unsort_rates(n, w.perm, w, out, signal, nbr_count, st));
+    {
+        ProfScope pr(CSPH_PROF_BIN, st);
+        CSPH_HIP(launch_bin(s->x, s->y, s->z, n, gd, w, w.perm, nullptr, w.cs, st));
+    }
+    {
+        ProfScope pr(CSPH_PROF_PACK, st);
+        CSPH_HIP(launch_pack(*s, n, w.perm, eos, mixed, gd, w, w.srt, w.srt_mat,
+                             pair ? w.srt_d : nullptr, nullptr, nullptr, nonphys, st));
+    }
+    {
+        ProfScope pr(CSPH_PROF_RATES, st);
+        CSPH_HIP(launch_rates(n, mixed, gd, pc, w, w.srt, pair ? w.srt_d : nullptr, nullptr, t,
+                              0, st));
+    }
+    {
+        ProfScope pr(CSPH_PROF_REORDER, st);
+        CSPH_HIP(launch_unsort_rates(n, w.perm, w, out, signal, nbr_count, st));
+    }
     return CSPH_OK;
 }
 
@@ -374,16 +443,27 @@ csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_para
         did = s_in->id ? w.srt_id : nullptr;
     }
     if (n > 0) {
-        CSPH_HIP(launch_bin(s_in->x, s_in->y, s_in->z, n, gd, w, w.perm, nullptr, w.cs, st));
+        {
+            ProfScope pr(CSPH_PROF_BIN, st);
+            CSPH_HIP(launch_bin(s_in->x, s_in->y, s_in->z, n, gd, w, w.perm, nullptr, w.cs, st));
+        }
+        ProfScope pr(CSPH_PROF_PACK, st);
         CSPH_HIP(launch_pack(*s_in, n, w.perm, eos, mixed, gd, w, dst, dmat, dd, did, s_in->id,
                              nonphys, st));
     }
     // dt = cfl * min h/s; an empty set takes dt = 0
     if (p->cfl > 0.0)
         CSPH_HIP(launch_fill_u64(w.dtmin, n > 0 ? 0x7ff0000000000000ull : 0ull, 1, st));
-    if (n > 0) CSPH_HIP(launch_rates(n, mixed, gd, pc, w, dst, dd, t, 0.0, p->cfl > 0.0, st));
-    CSPH_HIP(launch_integrate(n, dst, w, p->cfl, dt_in, st));  // n = 0 writes zero partials
-    CSPH_HIP(launch_finish_step(n, w, p->cfl, dt_in, t, dt_used, totals, st));
+    if (n > 0) {
+        ProfScope pr(CSPH_PROF_RATES, st);
+        CSPH_HIP(launch_rates(n, mixed, gd, pc, w, dst, dd, t, 0.0, p->cfl > 0.0, st));
+    }
+    {
+        ProfScope pr(CSPH_PROF_INTEGRATE, st);
+        CSPH_HIP(launch_integrate(n, dst, w, p->cfl, dt_in, st));  // n = 0 writes zero partials
+        CSPH_HIP(launch_finish_step(n, w, p->cfl, dt_in, t, dt_used, totals, st));
+    }
+    ProfScope pro(CSPH_PROF_REORDER, st);
     if (n > 0) {
         if (p->reorder) {
             if (nbr_count)
@@ -408,6 +488,7 @@ csph_status voronoi_assign(const double *x, const double *y, const double *z, in
         (n > 0 && (!x || !y || !z || !owner)))
         return fail(CSPH_EINVAL, "bad arguments (1 <= K <= %d)", kMaxSites);
     if (site_pairs && !nbr_count) return fail(CSPH_EINVAL, "site_pairs needs nbr_count");
+    ProfScope pr(CSPH_PROF_VORONOI, (hipStream_t)stream);
     CSPH_HIP(launch_voronoi(x, y, z, n, sites, K, nbr_count, owner, site_particles, site_pairs,
                             (hipStream_t)stream));
     return CSPH_OK;
@@ -423,6 +504,43 @@ csph_status csph_init_energy(const double *rho, const double *pres, const double
     if (r) return r;
     CSPH_HIP(launch_init_energy(rho, pres, vx, vy, vz, mat, n, eos_dev(p), E, (hipStream_t)stream));
     return CSPH_OK;
+}
+
+csph_status csph_profile_enable(int32_t on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    // create the events up front: first-use creation costs milliseconds
+    while (g_prof_on && g_prof_pool.size() < 256) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return fail(CSPH_EDEVICE, "hipEventCreate failed");
+        g_prof_pool.push_back(e);
+    }
+    return CSPH_OK;
+}
+
+csph_status csph_profile_read(csph_profile *out) {
+    g_err[0] = 0;
+    std::vector<ProfRec> pend;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        pend.swap(g_prof_pending);
+    }
+    csph_status rc = CSPH_OK;
+    for (const ProfRec &r : pend) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+            rc = fail(CSPH_EDEVICE, "event timing failed");
+        g_prof_acc.launches[r.group] += 1;
+        g_prof_acc.ms[r.group] += ms;
+    }
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (const ProfRec &r : pend) {
+        g_prof_pool.push_back(r.a);
+        g_prof_pool.push_back(r.b);
+    }
+    if (out) *out = g_prof_acc;
+    memset(&g_prof_acc, 0, sizeof(g_prof_acc));
+    return rc;
 }
 
 }  // extern "C"
