@@ -81,8 +81,9 @@ typedef struct {
     double kappa;      /* support radius in units of h (2 for the workloads, 1.936 in sec. 4.1) */
     double cell_size;  /* mesh cell D; <= 0 selects D = maximum support.  D may be smaller than
                           the support: the stencil then reaches ceil(H/D) cells each way */
-    double cfl;        /* > 0: dt = cfl * min_i h_i / s_i (s_i the pair signal speed);
-                          <= 0: the caller's dt is used */
+    double cfl;        /* > 0: dt = cfl * min_i min(h_i / s_i, rho_i / |drho_i/dt|) (s_i the
+                          pair signal speed; the second term bounds the relative density
+                          change of one step); <= 0: the caller's dt is used */
     int32_t n_eos;     /* materials 0..n_eos-1; mat[i] selects eos[mat[i]] */
     int32_t wall;      /* 1: rigid piston plane x = wall_x0 + wall_v t, fluid at x > plane,
                           handled by mirror partners (every particle must stay at x >= plane) */
@@ -196,7 +197,8 @@ csph_status csph_rates(const csph_state *s, const csph_params *p, double t,
                        void *ws, size_t ws_bytes, size_t *ws_needed, csph_stream stream);
 
 /* One step (Algorithm 1, state renewal and global time step):
- *   rates at (s_in, *t);  dt = cfl * min_i h/s_i  (or dt_in when cfl <= 0);
+ *   rates at (s_in, *t);  dt = cfl * min_i min(h/s_i, rho_i/|drho_i|)  (or dt_in
+ *   when cfl <= 0);
  *   v += dt dv, E += dt dE, rho += dt drho, then r += dt v_new;  *t += dt.
  * s_out receives the new state (mat, m, d and id are carried); with
  * p->reorder = 1 in cell order, otherwise in the input order.  s_out may
@@ -228,6 +230,43 @@ csph_status voronoi_assign(const double *x, const double *y, const double *z, in
 csph_status csph_init_energy(const double *rho, const double *pres, const double *vx,
                              const double *vy, const double *vz, const int32_t *mat, int64_t n,
                              const csph_params *p, double *E, csph_stream stream);
+
+/* Adjoint (vector-Jacobian products).  Fixed-h mode without a wall; FP64
+ * arithmetic in both precisions (it differentiates the FP64 map).  A
+ * gradient struct holds 8 FP64 arrays in the state's order. */
+typedef struct {
+    double *x, *y, *z, *vx, *vy, *vz, *rho, *E;
+} csph_grad;
+
+/* VJP of csph_rates: with cotangents a of the five rate arrays (input
+ * order), g_state += (d rates / d state)^T a over the eight state arrays,
+ * and g_eos[2k] += dJ/d gamma_k, g_eos[2k+1] += dJ/d p_inf_k (device,
+ * 2*n_eos doubles, optional).  The rates' dependence on (rho, E, v) through
+ * the EOS is included; masses and materials are constants.  Gather form:
+ * it relies on j in N(i) <=> i in N(j).  Where c = 0 the derivative of c
+ * with respect to c^2 is taken as 0.  Synchronises once (mesh bounds). */
+csph_status csph_rates_vjp(const csph_state *s, const csph_params *p, csph_rates_out a,
+                           csph_grad g_state, double *g_eos, void *ws, size_t ws_bytes,
+                           size_t *ws_needed, csph_stream stream);
+
+/* VJP of one csph_step with the time step dt held fixed (the step's own
+ * dt, replayed): s_n is the state the step started from, g_next the
+ * cotangent of the state after it (same particle order, i.e. a step taken
+ * with reorder = 0), g_prev receives (d s_{n+1} / d s_n)^T g_next (it may
+ * alias g_next), g_eos is accumulated as in csph_rates_vjp. */
+csph_status csph_step_vjp(const csph_state *s_n, const csph_params *p, double dt,
+                          csph_grad g_next, csph_grad g_prev, double *g_eos, void *ws,
+                          size_t ws_bytes, size_t *ws_needed, csph_stream stream);
+
+/* VJP of csph_init_energy: with gE the cotangent of E, accumulates
+ * g_vx/g_vy/g_vz += gE v, g_rho += gE de/drho (each optional) and
+ * g_eos (2*n_eos, optional) += the gamma / p_inf parts. */
+csph_status csph_init_energy_vjp(const double *rho, const double *pres, const double *vx,
+                                 const double *vy, const double *vz, const int32_t *mat,
+                                 int64_t n, const csph_params *p, const double *gE, double *g_vx,
+                                 double *g_vy, double *g_vz, double *g_rho, double *g_eos,
+                                 void *ws, size_t ws_bytes, size_t *ws_needed,
+                                 csph_stream stream);
 
 /* Kernel timing.  While enabled, every call records a pair of HIP events
  * on its stream around each kernel group below; csph_profile_read waits for

@@ -92,7 +92,7 @@ def lib():
         L.oracle_rates_sample.argtypes = ([cp, C.c_int64] + [dp] * 9 + [ip, dp, C.c_double, lp,
                                           C.c_int64] + [dp] * 6 + [lp])
         L.oracle_dt.restype = C.c_double
-        L.oracle_dt.argtypes = [cp, C.c_int64, dp, dp]
+        L.oracle_dt.argtypes = [cp, C.c_int64, dp, dp, dp, dp]
         L.oracle_step.restype = C.c_int64
         L.oracle_step.argtypes = [cp, C.c_int64] + [dp] * 9 + [ip, dp, dp, C.c_double, dp, lp]
         L.oracle_totals.restype = None
@@ -266,8 +266,10 @@ def rates_sample(cfg: Cfg, s, sample, t: float = 0.0, d=None):
     return out
 
 
-def dt(cfg: Cfg, signal, d=None) -> float:
-    return float(lib().oracle_dt(C.byref(cfg), signal.shape[0], _d(signal), _d(d)))
+def dt(cfg: Cfg, signal, d=None, rho=None, drho=None) -> float:
+    """cfl * min_i min(h_i/s_i, rho_i/|drho_i|) (density part only when rho, drho are given)."""
+    return float(lib().oracle_dt(C.byref(cfg), signal.shape[0], _d(signal), _d(d), _d(rho),
+                                 _d(drho)))
 
 
 def step(cfg: Cfg, s, t: float = 0.0, dt_in: float = 0.0, d=None):

@@ -29,7 +29,8 @@
  *   oracle_rates            eqs. SPH:Conti, SPH:Pulse, SPH:Energy.
  *   oracle_step             "renew particle positions and states" and the
  *                           global time step (Algorithm 1); symplectic Euler
- *                           with a CFL time step (reading; not printed).
+ *                           with a Courant + density-change time step
+ *                           (reading; the paper prints no time-step rule).
  *   oracle_grid / _bin      uniform cubic mesh of cell size D (sec. 4.2) and
  *                           the cell-ordered particle numbering (sec. 4.2,
  *                           renumbering for locality).
@@ -579,13 +580,21 @@ int64_t oracle_rates_sample(const oracle_cfg *cfg, int64_t n, const double *x, c
     return bad;
 }
 
-/* dt = cfl * min_i h_i / s_i, h_i = h (fixed) or d_i (pair mode). */
-double oracle_dt(const oracle_cfg *cfg, int64_t n, const double *signal, const double *d) {
+/* dt = cfl * min_i min(h_i / s_i, rho_i / |drho_i|), h_i = h (fixed) or
+ * d_i (pair mode): the signal-speed (Courant) limit plus a limit on the
+ * relative density change of one explicit step, which keeps rho > 0 where
+ * free surfaces expand into vacuum.  drho may be NULL (Courant part only). */
+double oracle_dt(const oracle_cfg *cfg, int64_t n, const double *signal, const double *d,
+                 const double *rho, const double *drho) {
     double best = INFINITY;
     for (int64_t i = 0; i < n; ++i) {
         double hi = cfg->h_mode == 1 ? d[i] : cfg->h;
         double v = hi / signal[i];
         if (v < best) best = v;
+        if (drho && rho) {
+            double w = rho[i] / fabs(drho[i]);
+            if (w < best) best = w;
+        }
     }
     return cfg->cfl * best;
 }
@@ -605,7 +614,7 @@ int64_t oracle_step(const oracle_cfg *cfg, int64_t n, double *x, double *y, doub
     if (r0 && r1 && r2 && r3 && r4 && sg) {
         bad = oracle_rates(cfg, n, x, y, z, vx, vy, vz, rho, E, m, mat, d, *t, r0, r1, r2, r3,
                            r4, sg, nbr_count);
-        double dt = cfg->cfl > 0.0 ? oracle_dt(cfg, n, sg, d) : dt_in;
+        double dt = cfg->cfl > 0.0 ? oracle_dt(cfg, n, sg, d, rho, r0) : dt_in;
         for (int64_t i = 0; i < n; ++i) {
             vx[i] = vx[i] + dt * r1[i];
             vy[i] = vy[i] + dt * r2[i];

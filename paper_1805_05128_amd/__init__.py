@@ -4,4 +4,6 @@ include/csph.h (libcsph.so, hand-written HIP)."""
 from .api import (EOS_IDEAL, EOS_STIFFENED, Params, State, StepScalars, Workspace,  # noqa: F401
                   csph_bin, csph_grid_build, csph_init_energy, csph_neighbors, csph_rates,
                   csph_step, default_workspace, profile_enable, profile_read, state_from_workload, version, voronoi_assign,
-                  workspace_size)
+                  workspace_size, csph_rates_vjp, csph_step_vjp, csph_init_energy_vjp,
+                  zeros_grad, GRAD_FIELDS)
+from .autograd import CSPHRollout, rollout  # noqa: F401

@@ -55,6 +55,10 @@ class CsphRatesOut(C.Structure):
     _fields_ = [(k, _dp) for k in ("drho", "dvx", "dvy", "dvz", "dE")]
 
 
+class CsphGrad(C.Structure):
+    _fields_ = [(k, _dp) for k in ("x", "y", "z", "vx", "vy", "vz", "rho", "E")]
+
+
 PROF_GROUPS = ("bin", "pack", "rates", "integrate", "voronoi", "reorder", "neighbors", "adjoint")
 
 
@@ -112,6 +116,16 @@ def load():
     L.csph_init_energy.restype = C.c_int32
     L.csph_init_energy.argtypes = [_dp, _dp, _dp, _dp, _dp, _ip, C.c_int64,
                                    C.POINTER(CsphParams), _dp, vp]
+    L.csph_rates_vjp.restype = C.c_int32
+    L.csph_rates_vjp.argtypes = [C.POINTER(CsphState), C.POINTER(CsphParams), CsphRatesOut,
+                                 CsphGrad, _dp, vp, sz, szp, vp]
+    L.csph_step_vjp.restype = C.c_int32
+    L.csph_step_vjp.argtypes = [C.POINTER(CsphState), C.POINTER(CsphParams), C.c_double,
+                                CsphGrad, CsphGrad, _dp, vp, sz, szp, vp]
+    L.csph_init_energy_vjp.restype = C.c_int32
+    L.csph_init_energy_vjp.argtypes = [_dp, _dp, _dp, _dp, _dp, _ip, C.c_int64,
+                                       C.POINTER(CsphParams), _dp, _dp, _dp, _dp, _dp, _dp, vp,
+                                       sz, szp, vp]
     L.csph_profile_enable.restype = C.c_int32
     L.csph_profile_enable.argtypes = [C.c_int32]
     L.csph_profile_read.restype = C.c_int32

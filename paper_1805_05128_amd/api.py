@@ -335,6 +335,74 @@ def csph_init_energy(rho, pres, vx, vy, vz, mat, params: Params, stream=None):
     return E
 
 
+GRAD_FIELDS = ("x", "y", "z", "vx", "vy", "vz", "rho", "E")
+
+
+def _grad_struct(g: Dict[str, torch.Tensor]) -> N.CsphGrad:
+    return N.CsphGrad(*[_dp(g[k]) for k in GRAD_FIELDS])
+
+
+def zeros_grad(n: int, device="cuda") -> Dict[str, torch.Tensor]:
+    return {k: torch.zeros(n, dtype=torch.float64, device=device) for k in GRAD_FIELDS}
+
+
+def csph_rates_vjp(state: State, params: Params, cot: Dict[str, torch.Tensor],
+                   g_state: Optional[Dict[str, torch.Tensor]] = None,
+                   g_eos: Optional[torch.Tensor] = None, ws: Optional[Workspace] = None,
+                   stream=None):
+    """g_state += (d rates/d state)^T cot, g_eos += EOS-parameter part; returns both."""
+    L = N.load()
+    dev = state["x"].device
+    ws = ws or default_workspace(dev)
+    if g_state is None:
+        g_state = zeros_grad(state.n, dev)
+    if g_eos is None:
+        g_eos = torch.zeros(2 * len(params.eos), dtype=torch.float64, device=dev)
+    a = N.CsphRatesOut(*[_dp(cot[k]) for k in ("drho", "dvx", "dvy", "dvz", "dE")])
+    s = state.c()
+    p = params.c()
+    gs = _grad_struct(g_state)
+    _with_ws(lambda w, b, nd: L.csph_rates_vjp(C.byref(s), C.byref(p), a, gs, _dp(g_eos), w, b,
+                                               nd, _stream(stream)), ws, "csph_rates_vjp")
+    return g_state, g_eos
+
+
+def csph_step_vjp(s_n: State, params: Params, dt: float, g_next: Dict[str, torch.Tensor],
+                  g_prev: Optional[Dict[str, torch.Tensor]] = None,
+                  g_eos: Optional[torch.Tensor] = None, ws: Optional[Workspace] = None,
+                  stream=None):
+    """Cotangent of s_n from that of the state after one step with frozen dt."""
+    L = N.load()
+    dev = s_n["x"].device
+    ws = ws or default_workspace(dev)
+    if g_prev is None:
+        g_prev = g_next
+    if g_eos is None:
+        g_eos = torch.zeros(2 * len(params.eos), dtype=torch.float64, device=dev)
+    s = s_n.c()
+    p = params.c()
+    gn, gp = _grad_struct(g_next), _grad_struct(g_prev)
+    _with_ws(lambda w, b, nd: L.csph_step_vjp(C.byref(s), C.byref(p), float(dt), gn, gp,
+                                              _dp(g_eos), w, b, nd, _stream(stream)), ws,
+             "csph_step_vjp")
+    return g_prev, g_eos
+
+
+def csph_init_energy_vjp(rho, pres, vx, vy, vz, mat, params: Params, gE, g_v=None, g_rho=None,
+                         g_eos=None, ws: Optional[Workspace] = None, stream=None):
+    L = N.load()
+    ws = ws or default_workspace(rho.device)
+    n = rho.shape[0]
+    p = params.c()
+    gv = g_v or (None, None, None)
+    _with_ws(lambda w, b, nd: L.csph_init_energy_vjp(_dp(rho), _dp(pres), _dp(vx), _dp(vy),
+                                                     _dp(vz), _ip(mat), n, C.byref(p), _dp(gE),
+                                                     _dp(gv[0]), _dp(gv[1]), _dp(gv[2]),
+                                                     _dp(g_rho), _dp(g_eos), w, b, nd,
+                                                     _stream(stream)), ws,
+             "csph_init_energy_vjp")
+
+
 def state_from_workload(w, params: Params, device="cuda", with_id=True) -> State:
     """Device state of a synthetic workload: E built on the GPU from (rho, p, v)."""
     t = {k: torch.as_tensor(getattr(w, k), dtype=torch.float64).to(device).contiguous()

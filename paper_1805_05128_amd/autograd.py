@@ -1,0 +1,123 @@
+"""torch.autograd.Function over a CSPH rollout with the hand-written adjoint.
+
+The forward runs ``nsteps`` steps (particle order kept) from initial
+velocities and adiabatic indices, storing the state every ``every`` steps
+and recording the time-step sequence.  The backward walks the segments in
+reverse: it restores a segment's checkpoint, recomputes the segment's
+states with the recorded time steps (bit-identical to the forward), then
+applies csph_step_vjp step by step and finally the VJP of the initial
+energy E0 = e(rho, p; gamma) + |v0|^2/2.  The time steps are held fixed
+(replayed), i.e. the gradient is that of the map at the recorded dt
+sequence.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Dict, List, Optional
+
+import torch
+
+from . import api as A
+
+STATE8 = A.GRAD_FIELDS
+
+
+def _clone_state(s: A.State) -> A.State:
+    """Copy of the evolving fields; mass and material are shared (constant)."""
+    t = {k: (v if k == "m" else v.clone()) for k, v in s.t.items()}
+    return A.State(t, s.mat, None, None)
+
+
+def _with_gamma(params: A.Params, gamma: List[float]) -> A.Params:
+    eos = [(t, float(g), pinf) for (t, _, pinf), g in zip(params.eos, gamma)]
+    return dataclasses.replace(params, eos=eos, reorder=False, precision="fp64")
+
+
+class CSPHRollout(torch.autograd.Function):
+    """(vx0, vy0, vz0, gamma) -> final state (x, y, z, vx, vy, vz, rho, E).
+
+    ``base`` holds the device tensors x, y, z, rho, p, m, mat of the initial
+    state; ``params`` the run parameters (its gammas are replaced by the
+    ``gamma`` tensor); ``dts``, if given, is the list of time steps to use
+    instead of the CFL rule.  After the call, ``info['dts']`` holds the dt
+    sequence and ``info['forward_s']`` the forward wall time.
+    """
+
+    @staticmethod
+    def forward(ctx, vx0, vy0, vz0, gamma, base: Dict[str, torch.Tensor], params: A.Params,
+                nsteps: int, every: int, dts: Optional[List[float]], info: dict):
+        import time
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pg = _with_gamma(params, gamma.detach().cpu().tolist())
+        E0 = A.csph_init_energy(base["rho"], base["p"], vx0, vy0, vz0, base["mat"], pg)
+        st = A.State({"x": base["x"].clone(), "y": base["y"].clone(), "z": base["z"].clone(),
+                      "vx": vx0.detach().clone(), "vy": vy0.detach().clone(),
+                      "vz": vz0.detach().clone(), "rho": base["rho"].clone(), "E": E0,
+                      "m": base["m"]}, base["mat"])
+        sc = A.StepScalars(vx0.device)
+        ckpts = []
+        dt_dev = []
+        replay = dataclasses.replace(pg, cfl=0.0)
+        for k in range(nsteps):
+            if k % every == 0:
+                ckpts.append(_clone_state(st))
+            if dts is None:
+                A.csph_step(st, pg, sc, s_out=st, totals=False)
+            else:
+                A.csph_step(st, replay, sc, s_out=st, dt_in=float(dts[k]), totals=False)
+            dt_dev.append(sc.dt.clone())
+        dt_list = torch.cat(dt_dev).cpu().tolist() if nsteps else []
+        torch.cuda.synchronize()
+        info["dts"] = dt_list
+        info["forward_s"] = time.perf_counter() - t0
+        ctx.ckpts = ckpts
+        ctx.dts = dt_list
+        ctx.params = pg
+        ctx.every = every
+        ctx.nsteps = nsteps
+        ctx.base = base
+        ctx.info = info
+        ctx.save_for_backward(vx0, vy0, vz0)
+        return tuple(st.t[k].clone() for k in STATE8)
+
+    @staticmethod
+    def backward(ctx, *g_final):
+        import time
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        vx0, vy0, vz0 = ctx.saved_tensors
+        dev = vx0.device
+        n = vx0.shape[0]
+        pg = ctx.params
+        g = {k: (gf.contiguous().clone() if gf is not None else torch.zeros(n, dtype=torch.float64, device=dev))
+             for k, gf in zip(STATE8, g_final)}
+        g_eos = torch.zeros(2 * len(pg.eos), dtype=torch.float64, device=dev)
+        replay = dataclasses.replace(pg, cfl=0.0)
+        sc = A.StepScalars(dev)
+        nseg = len(ctx.ckpts)
+        for seg in reversed(range(nseg)):
+            k0 = seg * ctx.every
+            k1 = min(k0 + ctx.every, ctx.nsteps)
+            states = [ctx.ckpts[seg]]
+            s = _clone_state(ctx.ckpts[seg])
+            for k in range(k0, k1 - 1):
+                A.csph_step(s, replay, sc, s_out=s, dt_in=ctx.dts[k], totals=False)
+                states.append(_clone_state(s))
+            for k in reversed(range(k0, k1)):
+                A.csph_step_vjp(states[k - k0], pg, ctx.dts[k], g, g_prev=g, g_eos=g_eos)
+            states.clear()
+        b = ctx.base
+        A.csph_init_energy_vjp(b["rho"], b["p"], vx0, vy0, vz0, b["mat"], pg, g["E"],
+                               g_v=(g["vx"], g["vy"], g["vz"]), g_eos=g_eos)
+        torch.cuda.synchronize()
+        ctx.info["backward_s"] = time.perf_counter() - t0
+        return (g["vx"], g["vy"], g["vz"], g_eos[0::2].clone(), None, None, None, None, None,
+                None)
+
+
+def rollout(vx0, vy0, vz0, gamma, base, params, nsteps, every=10, dts=None, info=None):
+    """Functional form of CSPHRollout.apply; returns a dict of final-state tensors."""
+    info = {} if info is None else info
+    out = CSPHRollout.apply(vx0, vy0, vz0, gamma, base, params, nsteps, every, dts, info)
+    return dict(zip(STATE8, out))

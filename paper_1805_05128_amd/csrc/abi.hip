@@ -105,6 +105,9 @@ size_t ws_layout(Ws *w, void *base, int64_t n, int64_t ncell) {
     t.recA = take(32 * un);
     t.recB = take(32 * un);
     t.recC = take(16 * un);
+    t.recD = take(32 * un);
+    t.recE = (double *)take(sizeof(double) * un);
+    t.eos_part = (double *)take(sizeof(double) * 2 * CSPH_MAX_EOS * ((un + kBlock - 1) / kBlock + 1));
     for (int k = 0; k < 9; ++k) t.srt[k] = (double *)take(sizeof(double) * un);
     t.srt_mat = (int32_t *)take(sizeof(int32_t) * un);
     t.srt_d = (double *)take(sizeof(double) * un);
@@ -503,6 +506,99 @@ csph_status csph_init_energy(const double *rho, const double *pres, const double
     csph_status r = check_params(p, false, nullptr);
     if (r) return r;
     CSPH_HIP(launch_init_energy(rho, pres, vx, vy, vz, mat, n, eos_dev(p), E, (hipStream_t)stream));
+    return CSPH_OK;
+}
+
+static csph_status check_vjp_params(const csph_params *p) {
+    if (p->h_mode != CSPH_H_FIXED) return fail(CSPH_EINVAL, "the adjoint supports fixed-h mode only");
+    if (p->wall) return fail(CSPH_EINVAL, "the adjoint does not support the piston wall");
+    return CSPH_OK;
+}
+
+static bool grad_ok(const csph_grad &g) {
+    return g.x && g.y && g.z && g.vx && g.vy && g.vz && g.rho && g.E;
+}
+
+// shared body of csph_rates_vjp / csph_step_vjp
+static csph_status vjp_common(const csph_state *s, const csph_params *p, const double *const a[5],
+                              const csph_grad *gnext, double dt, csph_grad gout, int accumulate,
+                              double *g_eos, void *ws, size_t ws_bytes, size_t *ws_needed,
+                              hipStream_t st) {
+    if (!state_ok(s) || s->n >= INT32_MAX) return fail(CSPH_EINVAL, "bad state");
+    csph_status r = check_params(p, false, nullptr);
+    if (r) return r;
+    r = check_vjp_params(p);
+    if (r) return r;
+    int64_t n = s->n;
+    if (n > 0 && !grad_ok(gout)) return fail(CSPH_EINVAL, "gradient outputs must not be NULL");
+    csph_grid g;
+    double dmax;
+    r = make_grid(s->x, s->y, s->z, nullptr, n, p, ws, ws_bytes, st, &g, &dmax);
+    if (r) return r;
+    r = need_ws(ws_bytes, n, g.ncell, ws_needed);
+    if (r) return r;
+    if (n == 0) return CSPH_OK;
+    Ws w;
+    ws_layout(&w, ws, n, g.ncell);
+    GridDev gd = grid_dev(g);
+    PairConst pc = pair_const(p, dmax);
+    EosDev eos = eos_dev(p);
+    ProfScope pr(CSPH_PROF_ADJOINT, st);
+    CSPH_HIP(launch_bin(s->x, s->y, s->z, n, gd, w, w.perm, nullptr, w.cs, st));
+    CSPH_HIP(launch_pack(*s, n, w.perm, eos, 0, gd, w, w.srt, w.srt_mat, nullptr, nullptr,
+                         nullptr, nullptr, st));
+    double *go[8] = {gout.x, gout.y, gout.z, gout.vx, gout.vy, gout.vz, gout.rho, gout.E};
+    const double *gn[8];
+    if (gnext) {
+        const double *t[8] = {gnext->x, gnext->y, gnext->z, gnext->vx, gnext->vy, gnext->vz,
+                              gnext->rho, gnext->E};
+        for (int k = 0; k < 8; ++k) gn[k] = t[k];
+    }
+    CSPH_HIP(launch_vjp(n, w.perm, w.cs, gd, pc, eos, w, w.srt, w.srt_mat, a, go,
+                        gnext ? gn : nullptr, dt, accumulate, g_eos, st));
+    return CSPH_OK;
+}
+
+csph_status csph_rates_vjp(const csph_state *s, const csph_params *p, csph_rates_out a,
+                           csph_grad g_state, double *g_eos, void *ws, size_t ws_bytes,
+                           size_t *ws_needed, csph_stream stream) {
+    g_err[0] = 0;
+    if (s && s->n > 0 && (!a.drho || !a.dvx || !a.dvy || !a.dvz || !a.dE))
+        return fail(CSPH_EINVAL, "rate cotangents must not be NULL");
+    const double *ai[5] = {a.drho, a.dvx, a.dvy, a.dvz, a.dE};
+    return vjp_common(s, p, ai, nullptr, 0.0, g_state, 1, g_eos, ws, ws_bytes, ws_needed,
+                      (hipStream_t)stream);
+}
+
+csph_status csph_step_vjp(const csph_state *s_n, const csph_params *p, double dt,
+                          csph_grad g_next, csph_grad g_prev, double *g_eos, void *ws,
+                          size_t ws_bytes, size_t *ws_needed, csph_stream stream) {
+    g_err[0] = 0;
+    if (!std::isfinite(dt) || dt < 0.0) return fail(CSPH_EINVAL, "dt must be finite and >= 0");
+    if (s_n && s_n->n > 0 && !grad_ok(g_next)) return fail(CSPH_EINVAL, "g_next has NULL arrays");
+    return vjp_common(s_n, p, nullptr, &g_next, dt, g_prev, 0, g_eos, ws, ws_bytes, ws_needed,
+                      (hipStream_t)stream);
+}
+
+csph_status csph_init_energy_vjp(const double *rho, const double *pres, const double *vx,
+                                 const double *vy, const double *vz, const int32_t *mat,
+                                 int64_t n, const csph_params *p, const double *gE, double *g_vx,
+                                 double *g_vy, double *g_vz, double *g_rho, double *g_eos,
+                                 void *ws, size_t ws_bytes, size_t *ws_needed,
+                                 csph_stream stream) {
+    g_err[0] = 0;
+    if (n < 0 || n >= INT32_MAX || (n > 0 && (!rho || !pres || !vx || !vy || !vz || !gE)))
+        return fail(CSPH_EINVAL, "bad arguments");
+    csph_status r = check_params(p, false, nullptr);
+    if (r) return r;
+    r = need_ws(ws_bytes, n, 1, ws_needed);
+    if (r) return r;
+    Ws w;
+    ws_layout(&w, ws, n, 1);
+    hipStream_t st = (hipStream_t)stream;
+    ProfScope pr(CSPH_PROF_ADJOINT, st);
+    CSPH_HIP(launch_init_energy_vjp(rho, pres, vx, vy, vz, mat, n, eos_dev(p), gE, g_vx, g_vy,
+                                    g_vz, g_rho, g_eos, w.eos_part, st));
     return CSPH_OK;
 }
 

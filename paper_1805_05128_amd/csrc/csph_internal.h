@@ -71,6 +71,9 @@ struct Ws {
     int64_t *scan_tmp;            // scan tiles
     int32_t *perm;                // n
     void *recA, *recB, *recC;     // pair records (FP64: 32+32+16 B; mixed: 16+16+8 B)
+    void *recD;                   // adjoint pair weights (32 B)
+    double *recE;                 // adjoint energy weight
+    double *eos_part;             // per-block EOS-parameter gradients, ceil(n/kBlock) * 16
     double *srt[9];               // sorted state copy x y z vx vy vz rho E m
     int32_t *srt_mat;
     double *srt_d;
@@ -123,6 +126,19 @@ hipError_t launch_unpermute(int64_t n, const int32_t *perm, double *const src[9]
 hipError_t launch_init_energy(const double *rho, const double *pres, const double *vx,
                               const double *vy, const double *vz, const int32_t *mat, int64_t n,
                               const EosDev &eos, double *E, hipStream_t st);
+
+// k_adjoint.hip
+hipError_t launch_vjp(int64_t n, const int32_t *perm, const int32_t *cs, const GridDev &g,
+                      const PairConst &pc, const EosDev &eos, const Ws &w,
+                      double *const sorted[9], const int32_t *mat_sorted,
+                      const double *const a_in[5], double *const gout[8],
+                      const double *const gnext[8], double dt, int accumulate, double *g_eos,
+                      hipStream_t st);
+hipError_t launch_init_energy_vjp(const double *rho, const double *pres, const double *vx,
+                                  const double *vy, const double *vz, const int32_t *mat,
+                                  int64_t n, const EosDev &eos, const double *gE, double *g_vx,
+                                  double *g_vy, double *g_vz, double *g_rho, double *g_eos,
+                                  double *part, hipStream_t st);
 
 // k_voronoi.hip
 hipError_t launch_voronoi(const double *x, const double *y, const double *z, int64_t n,

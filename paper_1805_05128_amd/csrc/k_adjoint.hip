@@ -1,0 +1,367 @@
+// Hand-written adjoint (vector-Jacobian product) of the CSPH rates of
+// eqs. SPH:Conti, SPH:Pulse, SPH:Energy (sec. 4.1), of the step, and of the
+// EOS inverse that builds E from (rho, p, v).  FP64, fixed smoothing length.
+//
+// With cotangents a_i of the rates, J = sum_i a_i . R_i.  Writing
+// b_rho = -2 rho_i a_rho, b_v = (2/rho_i) a_v, b_E = (2/rho_i) a_E,
+// J = sum over unordered neighbour pairs of
+//   Phi_ij = W'_ij [ V_j (b_rho,i (v_L - v*) + P* b_v,i.e + b_E,i P* v*)
+//                  + V_i (b_rho,j (v* - v_R) - P* b_v,j.e - b_E,j P* v*) ]
+// (e, v_L, v_R, v*, P* seen from i), plus the rho_i prefactors.  Because
+// j in N(i) <=> i in N(j) for a fixed support, dJ/dq_i = sum_{j in N(i)}
+// dPhi_ij/dq_i: every particle gathers its own gradient over its own
+// neighbours, no atomics, fixed summation order.
+#include "csph_internal.h"
+
+namespace csph {
+
+struct VjpIn {
+    const double4 *A;   // x y z V      (cell order)
+    const double4 *B;   // vx vy vz P
+    const double2 *C;   // Z c
+    const double4 *Dw;  // b_rho b_vx b_vy b_vz
+    const double *Ew;   // b_E
+    const double *rho, *E, *m;  // sorted state
+    const int32_t *mat;
+    const double *a[5]; // rate cotangents (cell order): rho vx vy vz E
+};
+
+struct VjpOut {
+    double *g[8];       // x y z vx vy vz rho E, input order (perm)
+    const double *gn[8];  // step VJP: cotangent of the next state (input order), or NULL
+    double dt;          // step VJP: frozen time step
+    int accumulate;     // 1: g += result (rates VJP); 0: g = result (+ identity terms)
+    double *eos_part;   // [gridDim.x][2*CSPH_MAX_EOS]
+};
+
+// Rate cotangents and pair weights in cell order.  For a step VJP the
+// cotangents follow from the next-state cotangent gn: a_rho = dt g_rho',
+// a_v = dt (g_v' + dt g_r'), a_E = dt g_E'.
+__global__ __launch_bounds__(kBlock) void k_vjp_weights(int64_t n,
+                                                        const int32_t *__restrict__ perm,
+                                                        const double *__restrict__ rho_s,
+                                                        VjpOut o, const double *a_in0,
+                                                        const double *a_in1, const double *a_in2,
+                                                        const double *a_in3, const double *a_in4,
+                                                        double *a0, double *a1, double *a2,
+                                                        double *a3, double *a4,
+                                                        double4 *__restrict__ Dw,
+                                                        double *__restrict__ Ew) {
+    int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    int i = perm[s];
+    double ar, ax, ay, az, aE;
+    if (o.gn[0]) {
+        double dt = o.dt;
+        ar = dt * o.gn[6][i];
+        ax = dt * (o.gn[3][i] + dt * o.gn[0][i]);
+        ay = dt * (o.gn[4][i] + dt * o.gn[1][i]);
+        az = dt * (o.gn[5][i] + dt * o.gn[2][i]);
+        aE = dt * o.gn[7][i];
+    } else {
+        ar = a_in0[i];
+        ax = a_in1[i];
+        ay = a_in2[i];
+        az = a_in3[i];
+        aE = a_in4[i];
+    }
+    a0[s] = ar;
+    a1[s] = ax;
+    a2[s] = ay;
+    a3[s] = az;
+    a4[s] = aE;
+    double r = rho_s[s];
+    double k = 2.0 / r;
+    Dw[s] = make_double4(-2.0 * r * ar, k * ax, k * ay, k * az);
+    Ew[s] = k * aE;
+}
+
+__global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
+                                                  const int32_t *__restrict__ perm,
+                                                  const int32_t *__restrict__ cs, GridDev g,
+                                                  PairConst pc, EosDev eos, int n_eos) {
+    int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double ge_gamma = 0.0, ge_pinf = 0.0;
+    int mt = 0;
+    if (s < n) {
+        const double4 ai = in.A[s], bi = in.B[s], di = in.Dw[s];
+        const double2 zi = in.C[s];
+        const double bEi = in.Ew[s];
+        const double Vi = ai.w, Pi = bi.w, Zi = zi.x;
+        int cx = cell_coord(ai.x, g.ox, g.inv, g.dx);
+        int cy = cell_coord(ai.y, g.oy, g.inv, g.dy);
+        int cz = cell_coord(ai.z, g.oz, g.inv, g.dz);
+        double gr0 = 0, gr1 = 0, gr2 = 0, gv0 = 0, gv1 = 0, gv2 = 0, gP = 0, gZ = 0, gV = 0;
+        double Sr = 0, Sv0 = 0, Sv1 = 0, Sv2 = 0, SE = 0;
+        const double invH = pc.invH, dwc = pc.dwc, H2 = pc.H2;
+        const int R = g.reach;
+        const int x0 = max(cx - R, 0), x1 = min(cx + R, g.dx - 1);
+        for (int oz = -R; oz <= R; ++oz) {
+            int zz = cz + oz;
+            if (zz < 0 || zz >= g.dz) continue;
+            for (int oy = -R; oy <= R; ++oy) {
+                int yy = cy + oy;
+                if (yy < 0 || yy >= g.dy) continue;
+                int row = (zz * g.dy + yy) * g.dx;
+                int j0 = cs[row + x0], j1 = cs[row + x1 + 1];
+                for (int j = j0; j < j1; ++j) {
+                    if (j == (int)s) continue;
+                    double4 aj = in.A[j];
+                    double dx = aj.x - ai.x, dy = aj.y - ai.y, dz = aj.z - ai.z;
+                    double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
+                    if (!(r2 < H2) || r2 == 0.0) continue;
+                    double4 bj = in.B[j], dj = in.Dw[j];
+                    double2 zj = in.C[j];
+                    double bEj = in.Ew[j];
+                    double Vj = aj.w, Pj = bj.w, Zj = zj.x;
+                    double r = sqrt(r2), ir = 1.0 / r;
+                    double ex = dx * ir, ey = dy * ir, ez = dz * ir;
+                    double q = r * invH, a1 = 1.0 - q;
+                    double Wp = -dwc * q * (a1 * a1 * a1);
+                    double Wpp = -dwc * invH * (a1 * a1) * (1.0 - 4.0 * q);
+                    double vL = (bi.x * ex + bi.y * ey) + bi.z * ez;
+                    double vR = (bj.x * ex + bj.y * ey) + bj.z * ez;
+                    double S = Zi + Zj;
+                    double vs, ps, dvs_dvL, dvs_dvR, dps_dvL, dps_dvR, dvs_dP, dps_dP, dvs_dZ,
+                        dps_dZ;
+                    if (S != 0.0) {
+                        double iS = 1.0 / S;
+                        vs = ((Zi * vL + Zj * vR) + (Pi - Pj)) * iS;
+                        ps = ((Zj * Pi + Zi * Pj) + Zi * Zj * (vL - vR)) * iS;
+                        dvs_dvL = Zi * iS;
+                        dvs_dvR = Zj * iS;
+                        dps_dvL = Zi * Zj * iS;
+                        dps_dvR = -dps_dvL;
+                        dvs_dP = iS;
+                        dps_dP = Zj * iS;
+                        dvs_dZ = (vL - vs) * iS;
+                        dps_dZ = ((Pj + Zj * (vL - vR)) - ps) * iS;
+                    } else {
+                        vs = 0.5 * (vL + vR);
+                        ps = 0.5 * (Pi + Pj);
+                        dvs_dvL = 0.5;
+                        dvs_dvR = 0.5;
+                        dps_dvL = 0.0;
+                        dps_dvR = 0.0;
+                        dvs_dP = 0.0;
+                        dps_dP = 0.5;
+                        dvs_dZ = 0.0;
+                        dps_dZ = 0.0;
+                    }
+                    double bvie = (di.y * ex + di.z * ey) + di.w * ez;
+                    double bvje = (dj.y * ex + dj.z * ey) + dj.w * ez;
+                    double Gi = di.x * (vL - vs) + ps * bvie + bEi * ps * vs;
+                    double Gj = dj.x * (vs - vR) - ps * bvje - bEj * ps * vs;
+                    double G = Vj * Gi + Vi * Gj;
+                    double Gvs = Vj * (bEi * ps - di.x) + Vi * (dj.x - bEj * ps);
+                    double Gps = Vj * (bvie + bEi * vs) - Vi * (bvje + bEj * vs);
+                    double dGdvL = Vj * di.x + Gvs * dvs_dvL + Gps * dps_dvL;
+                    double dGdvR = -Vi * dj.x + Gvs * dvs_dvR + Gps * dps_dvR;
+                    gV += Wp * Gj;
+                    gP += Wp * (Gvs * dvs_dP + Gps * dps_dP);
+                    gZ += Wp * (Gvs * dvs_dZ + Gps * dps_dZ);
+                    double wv = Wp * dGdvL;
+                    gv0 += wv * ex;
+                    gv1 += wv * ey;
+                    gv2 += wv * ez;
+                    double u0 = (dGdvL * bi.x + dGdvR * bj.x) + ps * (Vj * di.y - Vi * dj.y);
+                    double u1 = (dGdvL * bi.y + dGdvR * bj.y) + ps * (Vj * di.z - Vi * dj.z);
+                    double u2 = (dGdvL * bi.z + dGdvR * bj.z) + ps * (Vj * di.w - Vi * dj.w);
+                    double ue = (u0 * ex + u1 * ey) + u2 * ez;
+                    double k1 = Wpp * G, k2 = Wp * ir;
+                    // dJ/dr_i = -dPhi/dd
+                    gr0 -= k1 * ex + k2 * (u0 - ue * ex);
+                    gr1 -= k1 * ey + k2 * (u1 - ue * ey);
+                    gr2 -= k1 * ez + k2 * (u2 - ue * ez);
+                    double w = Vj * Wp;
+                    Sr += w * (vL - vs);
+                    double f = w * ps;
+                    Sv0 += f * ex;
+                    Sv1 += f * ey;
+                    Sv2 += f * ez;
+                    SE += f * vs;
+                }
+            }
+        }
+        // prefactors rho_i: dJ/drho_i += (a_rho R_rho - a_v.R_v - a_E R_E)/rho_i
+        double rho = in.rho[s], E = in.E[s], m = in.m[s];
+        double ar = in.a[0][s], ax = in.a[1][s], ay = in.a[2][s], az = in.a[3][s],
+               aE = in.a[4][s];
+        double Rr = -2.0 * rho * Sr, pre = 2.0 / rho;
+        double grho = (ar * Rr - pre * ((ax * Sv0 + ay * Sv1) + az * Sv2) - aE * pre * SE) / rho;
+        // V = m/rho, Z = rho c
+        grho += -gV * m / (rho * rho);
+        double c = zi.y;
+        grho += gZ * c;
+        double gc = gZ * rho;
+        double gc2 = c > 0.0 ? gc / (2.0 * c) : 0.0;
+        // EOS: e = E - |v|^2/2, P and c^2 of the material
+        mt = in.mat ? in.mat[s] : 0;
+        if (mt < 0 || mt >= eos.n) mt = 0;
+        double gm = eos.gamma[mt], pinf = eos.pinf[mt];
+        double e = E - 0.5 * ((bi.x * bi.x + bi.y * bi.y) + bi.z * bi.z);
+        double ge;
+        if (eos.type[mt] == CSPH_EOS_STIFFENED) {
+            // P = (g-1) rho e - g pinf ;  c^2 = g (g-1) (e - pinf/rho)
+            ge = gP * (gm - 1.0) * rho + gc2 * gm * (gm - 1.0);
+            grho += gP * (gm - 1.0) * e + gc2 * gm * (gm - 1.0) * pinf / (rho * rho);
+            ge_gamma = gP * (rho * e - pinf) + gc2 * (2.0 * gm - 1.0) * (e - pinf / rho);
+            ge_pinf = -gP * gm - gc2 * gm * (gm - 1.0) / rho;
+        } else {
+            // P = (g-1) rho e ;  c^2 = g (g-1) e
+            ge = gP * (gm - 1.0) * rho + gc2 * gm * (gm - 1.0);
+            grho += gP * (gm - 1.0) * e;
+            ge_gamma = gP * rho * e + gc2 * (2.0 * gm - 1.0) * e;
+        }
+        double gEo = ge;
+        gv0 -= ge * bi.x;
+        gv1 -= ge * bi.y;
+        gv2 -= ge * bi.z;
+        double res[8] = {gr0, gr1, gr2, gv0, gv1, gv2, grho, gEo};
+        int i = perm[s];
+        if (o.gn[0]) {
+            // identity part of the step: r' = r + dt v', v' = v + dt dv, ...
+            double gnx = o.gn[0][i], gny = o.gn[1][i], gnz = o.gn[2][i];
+            res[0] += gnx;
+            res[1] += gny;
+            res[2] += gnz;
+            res[3] += o.gn[3][i] + o.dt * gnx;
+            res[4] += o.gn[4][i] + o.dt * gny;
+            res[5] += o.gn[5][i] + o.dt * gnz;
+            res[6] += o.gn[6][i];
+            res[7] += o.gn[7][i];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) o.g[k][i] = o.accumulate ? o.g[k][i] + res[k] : res[k];
+    }
+    // deterministic per-block sums of the EOS-parameter gradients
+    __shared__ double sh[2 * CSPH_MAX_EOS][kBlock];
+    for (int k = 0; k < 2 * n_eos; ++k) sh[k][threadIdx.x] = 0.0;
+    if (s < n) {
+        sh[2 * mt][threadIdx.x] = ge_gamma;
+        sh[2 * mt + 1][threadIdx.x] = ge_pinf;
+    }
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int k = 0; k < 2 * n_eos; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if ((int)threadIdx.x < 2 * n_eos)
+        o.eos_part[(int64_t)blockIdx.x * 2 * CSPH_MAX_EOS + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// g_eos[k] += sum over blocks of part[b][k], fixed order.
+__global__ __launch_bounds__(kBlock) void k_eos_grad_final(const double *__restrict__ part,
+                                                           int64_t nblocks, int nk,
+                                                           double *__restrict__ g_eos) {
+    __shared__ double sh[kBlock];
+    for (int k = 0; k < nk; ++k) {
+        double acc = 0.0;
+        for (int64_t b = threadIdx.x; b < nblocks; b += kBlock) acc += part[b * 2 * CSPH_MAX_EOS + k];
+        sh[threadIdx.x] = acc;
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) g_eos[k] += sh[0];
+        __syncthreads();
+    }
+}
+
+hipError_t launch_vjp(int64_t n, const int32_t *perm, const int32_t *cs, const GridDev &g,
+                      const PairConst &pc, const EosDev &eos, const Ws &w,
+                      double *const sorted[9], const int32_t *mat_sorted,
+                      const double *const a_in[5], double *const gout[8],
+                      const double *const gnext[8], double dt, int accumulate, double *g_eos,
+                      hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    VjpOut o;
+    for (int k = 0; k < 8; ++k) {
+        o.g[k] = gout[k];
+        o.gn[k] = gnext ? gnext[k] : nullptr;
+    }
+    o.dt = dt;
+    o.accumulate = accumulate;
+    o.eos_part = w.eos_part;
+    k_vjp_weights<<<nb, kBlock, 0, st>>>(n, perm, sorted[6], o, a_in ? a_in[0] : nullptr,
+                                         a_in ? a_in[1] : nullptr, a_in ? a_in[2] : nullptr,
+                                         a_in ? a_in[3] : nullptr, a_in ? a_in[4] : nullptr,
+                                         w.rate[0], w.rate[1], w.rate[2], w.rate[3], w.rate[4],
+                                         (double4 *)w.recD, w.recE);
+    VjpIn in;
+    in.A = (const double4 *)w.recA;
+    in.B = (const double4 *)w.recB;
+    in.C = (const double2 *)w.recC;
+    in.Dw = (const double4 *)w.recD;
+    in.Ew = w.recE;
+    in.rho = sorted[6];
+    in.E = sorted[7];
+    in.m = sorted[8];
+    in.mat = mat_sorted;
+    for (int k = 0; k < 5; ++k) in.a[k] = w.rate[k];
+    k_vjp64<<<nb, kBlock, 0, st>>>(n, in, o, perm, cs, g, pc, eos, eos.n);
+    if (g_eos) k_eos_grad_final<<<1, kBlock, 0, st>>>(w.eos_part, (int64_t)nb, 2 * eos.n, g_eos);
+    return hipGetLastError();
+}
+
+// dE0/d(gamma, p_inf, v, rho) of E0 = e0(rho, p; gamma, p_inf) + |v|^2/2,
+// e0 = p/((g-1) rho) (ideal) or (p + g p_inf)/((g-1) rho) (stiffened).
+__global__ __launch_bounds__(kBlock) void k_init_energy_vjp(
+    const double *__restrict__ rho, const double *__restrict__ pres, const double *__restrict__ vx,
+    const double *__restrict__ vy, const double *__restrict__ vz, const int32_t *__restrict__ mat,
+    int64_t n, EosDev eos, const double *__restrict__ gE, double *g_vx, double *g_vy,
+    double *g_vz, double *g_rho, double *__restrict__ part) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double gg = 0.0, gp = 0.0;
+    int k = 0;
+    if (i < n) {
+        k = mat ? mat[i] : 0;
+        if (k < 0 || k >= eos.n) k = 0;
+        double g = eos.gamma[k], pinf = eos.pinf[k], r = rho[i], p = pres[i], a = gE[i];
+        double e0;
+        if (eos.type[k] == CSPH_EOS_STIFFENED) {
+            e0 = (p + g * pinf) / ((g - 1.0) * r);
+            gg = a * (pinf / ((g - 1.0) * r) - e0 / (g - 1.0));
+            gp = a * (g / ((g - 1.0) * r));
+        } else {
+            e0 = p / ((g - 1.0) * r);
+            gg = a * (-e0 / (g - 1.0));
+        }
+        if (g_vx) g_vx[i] += a * vx[i];
+        if (g_vy) g_vy[i] += a * vy[i];
+        if (g_vz) g_vz[i] += a * vz[i];
+        if (g_rho) g_rho[i] += a * (-e0 / r);
+    }
+    __shared__ double sh[2 * CSPH_MAX_EOS][kBlock];
+    for (int q = 0; q < 2 * eos.n; ++q) sh[q][threadIdx.x] = 0.0;
+    if (i < n) {
+        sh[2 * k][threadIdx.x] = gg;
+        sh[2 * k + 1][threadIdx.x] = gp;
+    }
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 2 * eos.n; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if ((int)threadIdx.x < 2 * eos.n)
+        part[(int64_t)blockIdx.x * 2 * CSPH_MAX_EOS + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+hipError_t launch_init_energy_vjp(const double *rho, const double *pres, const double *vx,
+                                  const double *vy, const double *vz, const int32_t *mat,
+                                  int64_t n, const EosDev &eos, const double *gE, double *g_vx,
+                                  double *g_vy, double *g_vz, double *g_rho, double *g_eos,
+                                  double *part, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    k_init_energy_vjp<<<nb, kBlock, 0, st>>>(rho, pres, vx, vy, vz, mat, n, eos, gE, g_vx, g_vy,
+                                             g_vz, g_rho, part);
+    if (g_eos) k_eos_grad_final<<<1, kBlock, 0, st>>>(part, (int64_t)nb, 2 * eos.n, g_eos);
+    return hipGetLastError();
+}
+
+}  // namespace csph

@@ -260,14 +260,16 @@ __global__ __launch_bounds__(kBlock) void k_rates64(int64_t n, const double4 *__
         }
         double ri = rho[s];
         double pre = 2.0 / ri;
-        o.rho[s] = -2.0 * ri * ar;
+        double drho = -2.0 * ri * ar;
+        o.rho[s] = drho;
         o.vx[s] = pre * avx;
         o.vy[s] = pre * avy;
         o.vz[s] = pre * avz;
         o.E[s] = pre * aE;
         if (o.sig) o.sig[s] = sig;
         if (o.cnt) o.cnt[s] = cnt;
-        dtv = (PAIR ? di : pc.h_dt) / sig;
+        // Courant limit and relative density-change limit of one explicit step
+        dtv = fmin((PAIR ? di : pc.h_dt) / sig, ri / fabs(drho));
     }
     if (want_dt) block_min_to(dtv, o.dtmin);
 }
@@ -404,14 +406,15 @@ __global__ __launch_bounds__(kBlock) void k_rates32(int64_t n, const float4 *__r
         }
         double ri = rho[s];
         double pre = 2.0 / ri;
-        o.rho[s] = -2.0 * ri * (double)ar;
+        double drho = -2.0 * ri * (double)ar;
+        o.rho[s] = drho;
         o.vx[s] = pre * (double)avx;
         o.vy[s] = pre * (double)avy;
         o.vz[s] = pre * (double)avz;
         o.E[s] = pre * (double)aE;
         if (o.sig) o.sig[s] = (double)sig;
         if (o.cnt) o.cnt[s] = cnt;
-        dtv = (PAIR ? di : pc.h_dt) / (double)sig;
+        dtv = fmin((PAIR ? di : pc.h_dt) / (double)sig, ri / fabs(drho));
     }
     if (want_dt) block_min_to(dtv, o.dtmin);
 }

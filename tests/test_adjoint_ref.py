@@ -1,0 +1,119 @@
+"""Pins of the differentiable CPU reference (oracle/torch_ref.py).
+
+Its forward must reproduce the C oracle; its autograd gradients must match
+central finite differences of the C oracle's own step (an independent code
+path), along random directions in state and EOS-parameter space.
+"""
+import numpy as np
+import pytest
+import torch
+
+import csph_inputs as ci
+import oracle as O
+from oracle import torch_ref as T
+
+F8 = T.FIELDS8
+
+
+def system(n=6, seed=3, two_mat=True):
+    w = ci.jittered_block(n, n, n, seed=seed, amp=0.05)
+    rng = np.random.default_rng(seed)
+    w.vx = rng.uniform(-0.3, 0.3, w.n)
+    w.vy = rng.uniform(-0.3, 0.3, w.n)
+    w.vz = rng.uniform(-0.3, 0.3, w.n)
+    w.rho = rng.uniform(0.8, 1.3, w.n)
+    w.p = rng.uniform(0.5, 1.5, w.n)
+    w.m = w.rho.copy()
+    if two_mat:
+        w.mat = (w.x > n / 2).astype(np.int32)
+        w.eos = [(0, 1.4, 0.0), (1, 3.0, 0.4)]
+    return w
+
+
+def tparams(w):
+    gamma = torch.tensor([e[1] for e in w.eos], dtype=torch.float64)
+    pinf = torch.tensor([e[2] for e in w.eos], dtype=torch.float64)
+    return [e[0] for e in w.eos], gamma, pinf
+
+
+def test_torch_rates_match_c_oracle():
+    w = system()
+    cfg = O.cfg_for(w)
+    s = O.state_from(w, cfg)
+    ref = O.rates(cfg, s)
+    et, g, pi = tparams(w)
+    out = T.rates_torch(T.to_torch(s), torch.as_tensor(s["m"]), torch.as_tensor(s["mat"]).long(),
+                        et, g, pi, T.pairs_of(cfg, s), w.kappa * w.h)
+    for k, v in zip(("drho", "dvx", "dvy", "dvz", "dE"), out):
+        scale = np.abs(ref[k]).max()
+        assert np.abs(v.numpy() - ref[k]).max() <= 1e-13 * scale, k
+
+
+def _oracle_step(w, s, eos, dt):
+    cfg = O.make_cfg(eos, h=w.h, kappa=w.kappa, cfl=0.0)
+    s1, _, _, _ = O.step(cfg, s, 0.0, dt_in=dt)
+    return s1
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_step_gradient_matches_oracle_finite_differences(seed):
+    w = system(seed=seed)
+    cfg = O.cfg_for(w)
+    s = O.state_from(w, cfg)
+    dt = 0.05
+    et, g, pi = tparams(w)
+    st = {k: v.clone().requires_grad_(True) for k, v in T.to_torch(s).items()}
+    g = g.clone().requires_grad_(True)
+    pi = pi.clone().requires_grad_(True)
+    m = torch.as_tensor(s["m"])
+    mat = torch.as_tensor(s["mat"]).long()
+    out = T.step_torch(st, m, mat, et, g, pi, T.pairs_of(cfg, s), w.kappa * w.h, dt)
+    rng = np.random.default_rng(seed + 10)
+    lam = {k: rng.standard_normal(w.n) for k in F8}
+    J = sum((out[k] * torch.as_tensor(lam[k])).sum() for k in F8)
+    grads = torch.autograd.grad(J, [st[k] for k in F8] + [g, pi])
+    for trial in range(3):
+        d = {k: rng.standard_normal(w.n) for k in F8}
+        dg = rng.standard_normal(len(w.eos))
+        dpi = rng.standard_normal(len(w.eos)) * np.array([0.0 if e[0] == 0 else 1.0 for e in w.eos])
+        pred = sum(float((grads[a].numpy() * d[k]).sum()) for a, k in enumerate(F8))
+        pred += float((grads[8].numpy() * dg).sum()) + float((grads[9].numpy() * dpi).sum())
+        eps = 1e-6
+
+        def J_at(sign):
+            s2 = {k: (s[k] + sign * eps * d[k]) if k in d else s[k] for k in s}
+            eos2 = [(e[0], e[1] + sign * eps * dg[k], e[2] + sign * eps * dpi[k])
+                    for k, e in enumerate(w.eos)]
+            s1 = _oracle_step(w, s2, eos2, dt)
+            return sum(float((s1[k] * lam[k]).sum()) for k in F8)
+
+        fd = (J_at(1) - J_at(-1)) / (2 * eps)
+        assert abs(fd - pred) <= 1e-6 * max(abs(pred), 1.0), (trial, fd, pred)
+
+
+def test_init_energy_gamma_gradient():
+    w = system(two_mat=True)
+    et, g, pi = tparams(w)
+    g = g.clone().requires_grad_(True)
+    pi = pi.clone().requires_grad_(True)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float64))
+    mat = torch.as_tensor(w.mat).long()
+    E = T.init_energy_torch(t(w.rho), t(w.p), t(w.vx), t(w.vy), t(w.vz), mat, et, g, pi)
+    lam = np.random.default_rng(0).standard_normal(w.n)
+    J = (E * t(lam)).sum()
+    gg, gp = torch.autograd.grad(J, [g, pi])
+    eps = 1e-7
+    for k in range(len(w.eos)):
+        for which, grad in ((1, gg), (2, gp)):
+            if which == 2 and w.eos[k][0] == 0:
+                continue
+
+            def Jat(sign):
+                eos2 = [list(e) for e in w.eos]
+                eos2[k][which] += sign * eps
+                cfg = O.make_cfg([tuple(e) for e in eos2])
+                E2 = O.init_energy(cfg, w.rho, w.p, w.vx, w.vy, w.vz, w.mat)
+                return float((E2 * lam).sum())
+
+            fd = (Jat(1) - Jat(-1)) / (2 * eps)
+            assert abs(fd - float(grad[k])) <= 1e-6 * max(1.0, abs(fd))

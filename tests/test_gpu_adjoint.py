@@ -1,0 +1,234 @@
+"""GPU adjoint: csph_rates_vjp, csph_step_vjp, csph_init_energy_vjp and the
+checkpointed rollout against the FP64 CPU reference gradient (autograd of
+oracle/torch_ref.py) and against central finite differences."""
+import numpy as np
+import pytest
+import torch
+
+import csph_inputs as ci
+import oracle as O
+import paper_1805_05128_amd as P
+from oracle import torch_ref as T
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+F8 = T.FIELDS8
+
+
+def system(n=8, seed=3, two_mat=True):
+    w = ci.jittered_block(n, n, n, seed=seed, amp=0.05)
+    rng = np.random.default_rng(seed)
+    w.vx = rng.uniform(-0.3, 0.3, w.n)
+    w.vy = rng.uniform(-0.3, 0.3, w.n)
+    w.vz = rng.uniform(-0.3, 0.3, w.n)
+    w.rho = rng.uniform(0.8, 1.3, w.n)
+    w.p = rng.uniform(0.5, 1.5, w.n)
+    w.m = w.rho.copy()
+    if two_mat:
+        w.mat = (w.x > n / 2).astype(np.int32)
+        w.eos = [(0, 1.4, 0.0), (1, 3.0, 0.4)]
+    return w
+
+
+def tparams(w, grad=False):
+    g = torch.tensor([e[1] for e in w.eos], dtype=torch.float64, requires_grad=grad)
+    pi = torch.tensor([e[2] for e in w.eos], dtype=torch.float64, requires_grad=grad)
+    return [e[0] for e in w.eos], g, pi
+
+
+def relmax(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def test_rates_vjp_matches_autograd():
+    w = system()
+    params = P.Params.from_workload(w)
+    g = P.state_from_workload(w, params, DEV)
+    s = {k: g[k].cpu().numpy() for k in F8}
+    s["m"] = w.m
+    s["mat"] = w.mat
+    rng = np.random.default_rng(1)
+    cot = {k: rng.standard_normal(w.n) for k in ("drho", "dvx", "dvy", "dvz", "dE")}
+    gs, ge = P.csph_rates_vjp(g, params, {k: torch.as_tensor(v, device=DEV) for k, v in cot.items()})
+    et, gg, pi = tparams(w, True)
+    st = {k: torch.as_tensor(s[k]).clone().requires_grad_(True) for k in F8}
+    cfg = O.cfg_for(w)
+    out = T.rates_torch(st, torch.as_tensor(w.m), torch.as_tensor(w.mat).long(), et, gg, pi,
+                        T.pairs_of(cfg, s), w.kappa * w.h)
+    J = sum((o * torch.as_tensor(cot[k])).sum()
+            for o, k in zip(out, ("drho", "dvx", "dvy", "dvz", "dE")))
+    ref = torch.autograd.grad(J, [st[k] for k in F8] + [gg, pi])
+    for a, k in enumerate(F8):
+        e = relmax(gs[k].cpu().numpy(), ref[a].numpy())
+        assert e <= 1e-10, (k, e)
+    ge = ge.cpu().numpy()
+    assert relmax(ge[0::2], ref[8].numpy()) <= 1e-10
+    assert abs(ge[3] - float(ref[9][1])) <= 1e-10 * abs(float(ref[9][1]))
+
+
+def test_step_vjp_matches_autograd_and_dot_product():
+    w = system(seed=5)
+    params = P.Params.from_workload(w, reorder=False)
+    g = P.state_from_workload(w, params, DEV)
+    s = {k: g[k].cpu().numpy() for k in F8}
+    s["m"] = w.m
+    s["mat"] = w.mat
+    dt = 0.04
+    rng = np.random.default_rng(2)
+    lam = {k: rng.standard_normal(w.n) for k in F8}
+    gn = {k: torch.as_tensor(v, device=DEV).clone() for k, v in lam.items()}
+    gp, ge = P.csph_step_vjp(g, params, dt, gn, g_prev={k: torch.empty_like(v) for k, v in gn.items()})
+    et, gg, pi = tparams(w, True)
+    st = {k: torch.as_tensor(s[k]).clone().requires_grad_(True) for k in F8}
+    out = T.step_torch(st, torch.as_tensor(w.m), torch.as_tensor(w.mat).long(), et, gg, pi,
+                       T.pairs_of(O.cfg_for(w), s), w.kappa * w.h, dt)
+    J = sum((out[k] * torch.as_tensor(lam[k])).sum() for k in F8)
+    ref = torch.autograd.grad(J, [st[k] for k in F8] + [gg, pi])
+    for a, k in enumerate(F8):
+        assert relmax(gp[k].cpu().numpy(), ref[a].numpy()) <= 1e-10, k
+    # dot-product test against the GPU forward step: <lam, J d> = <J^T lam, d>
+    d = {k: rng.standard_normal(w.n) for k in F8}
+    eps = 1e-6
+    replay = P.Params.from_workload(w, reorder=False, cfl=0.0)
+
+    def fwd(sign):
+        t = {k: g[k] + sign * eps * torch.as_tensor(d[k], device=DEV) for k in F8}
+        t["m"] = g["m"]
+        st2 = P.State(t, g.mat)
+        P.csph_step(st2, replay, P.StepScalars(DEV), s_out=st2, dt_in=dt)
+        return {k: st2[k].cpu().numpy() for k in F8}
+
+    fp, fm = fwd(1), fwd(-1)
+    jvp = sum(float(((fp[k] - fm[k]) / (2 * eps) * lam[k]).sum()) for k in F8)
+    vjp = sum(float((gp[k].cpu().numpy() * d[k]).sum()) for k in F8)
+    assert abs(jvp - vjp) <= 1e-7 * max(abs(vjp), 1.0), (jvp, vjp)
+
+
+def test_init_energy_vjp_matches_autograd():
+    w = system()
+    params = P.Params.from_workload(w)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float64), device=DEV)
+    gE = np.random.default_rng(4).standard_normal(w.n)
+    gv = [torch.zeros(w.n, dtype=torch.float64, device=DEV) for _ in range(3)]
+    grho = torch.zeros(w.n, dtype=torch.float64, device=DEV)
+    geos = torch.zeros(4, dtype=torch.float64, device=DEV)
+    P.csph_init_energy_vjp(t(w.rho), t(w.p), t(w.vx), t(w.vy), t(w.vz),
+                           torch.as_tensor(w.mat, device=DEV), params, t(gE), g_v=gv, g_rho=grho,
+                           g_eos=geos)
+    et, gg, pi = tparams(w, True)
+    vx = torch.as_tensor(w.vx).clone().requires_grad_(True)
+    rho = torch.as_tensor(w.rho).clone().requires_grad_(True)
+    E = T.init_energy_torch(rho, torch.as_tensor(w.p), vx, torch.as_tensor(w.vy),
+                            torch.as_tensor(w.vz), torch.as_tensor(w.mat).long(), et, gg, pi)
+    ref = torch.autograd.grad((E * torch.as_tensor(gE)).sum(), [vx, rho, gg, pi])
+    assert relmax(gv[0].cpu().numpy(), ref[0].numpy()) <= 1e-13
+    assert relmax(grho.cpu().numpy(), ref[1].numpy()) <= 1e-13
+    assert relmax(geos.cpu().numpy()[0::2], ref[2].numpy()) <= 1e-12
+    assert abs(geos.cpu().numpy()[3] - float(ref[3][1])) <= 1e-12 * abs(float(ref[3][1]))
+
+
+def _base(w, params):
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float64), device=DEV).contiguous()
+    return dict(x=t(w.x), y=t(w.y), z=t(w.z), rho=t(w.rho), p=t(w.p), m=t(w.m),
+                mat=torch.as_tensor(w.mat, dtype=torch.int32, device=DEV))
+
+
+def _objective(out, mask, m):
+    return (out["vx"][mask] * m[mask]).sum()
+
+
+def test_rollout_gradient_matches_reference_and_fd():
+    w = system(n=8, seed=7)
+    params = P.Params.from_workload(w, cfl=0.3)
+    base = _base(w, params)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float64), device=DEV)
+    v0 = [t(w.vx).requires_grad_(True), t(w.vy).requires_grad_(True), t(w.vz).requires_grad_(True)]
+    gamma = torch.tensor([e[1] for e in w.eos], dtype=torch.float64, device=DEV,
+                         requires_grad=True)
+    nsteps, every = 12, 5
+    info = {}
+    out = P.rollout(*v0, gamma, base, params, nsteps, every, info=info)
+    mask = out["x"].detach() > 4.0
+    J = _objective(out, mask, base["m"])
+    grads = torch.autograd.grad(J, v0 + [gamma])
+    dts = info["dts"]
+    assert len(dts) == nsteps and all(d > 0 for d in dts)
+    # FP64 CPU reference: torch autograd over the same dt sequence
+    et, gg, pi = tparams(w, True)
+    gg = gg.clone().detach().requires_grad_(True)
+    mat = torch.as_tensor(w.mat).long()
+    m = torch.as_tensor(w.m)
+    vr = [torch.as_tensor(a).clone().requires_grad_(True) for a in (w.vx, w.vy, w.vz)]
+    E0 = T.init_energy_torch(torch.as_tensor(w.rho), torch.as_tensor(w.p), *vr, mat, et, gg, pi)
+    st = {"x": torch.as_tensor(w.x), "y": torch.as_tensor(w.y), "z": torch.as_tensor(w.z),
+          "vx": vr[0], "vy": vr[1], "vz": vr[2], "rho": torch.as_tensor(w.rho), "E": E0}
+    cfg = O.cfg_for(w)
+    for k in range(nsteps):
+        pairs = T.pairs_of(cfg, {kk: st[kk].detach().numpy() for kk in ("x", "y", "z")})
+        st = T.step_torch(st, m, mat, et, gg, pi, pairs, w.kappa * w.h, dts[k])
+    mref = st["x"].detach() > 4.0
+    assert torch.equal(mref, mask.cpu())
+    Jr = (st["vx"][mref] * m[mref]).sum()
+    ref = torch.autograd.grad(Jr, vr + [gg])
+    assert abs(float(J) - float(Jr)) <= 1e-11 * abs(float(Jr))
+    for a in range(3):
+        assert relmax(grads[a].cpu().numpy(), ref[a].numpy()) <= 1e-9, a
+    assert relmax(grads[3].cpu().numpy(), ref[3].numpy()) <= 1e-9
+    # central finite differences of the GPU forward with the dt sequence replayed
+    rng = np.random.default_rng(11)
+    for trial in range(4):
+        d = [rng.standard_normal(w.n) for _ in range(3)]
+        dg = rng.standard_normal(2)
+        eps = 1e-6
+
+        def Jat(sign):
+            vv = [v0[a].detach() + sign * eps * t(d[a]) for a in range(3)]
+            gm = gamma.detach() + sign * eps * t(dg)
+            o = P.rollout(*vv, gm, base, params, nsteps, every, dts=dts)
+            return float(_objective(o, mask, base["m"]))
+
+        fd = (Jat(1) - Jat(-1)) / (2 * eps)
+        pred = sum(float((grads[a].cpu().numpy() * d[a]).sum()) for a in range(3)) + \
+            float((grads[3].cpu().numpy() * dg).sum())
+        assert abs(fd - pred) <= 1e-4 * max(abs(pred), 1e-8), (trial, fd, pred)
+
+
+def test_rollout_adjoint_sod64_fd_32_directions():
+    """Sod split on a 64^3 jittered lattice, 100 FP64 steps, checkpoint every 10:
+    d/d(v0, gamma) of the x-momentum of particles with x > 48 at the last step,
+    checked with central differences (eps = 1e-6) along 32 random directions."""
+    w = ci.config3()
+    print(f"[case] {w.name} n={w.n}", flush=True)
+    params = P.Params.from_workload(w, cfl=0.3)
+    base = _base(w, params)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float64), device=DEV)
+    v0 = [t(w.vx).requires_grad_(True), t(w.vy).requires_grad_(True), t(w.vz).requires_grad_(True)]
+    gamma = torch.tensor([1.4], dtype=torch.float64, device=DEV, requires_grad=True)
+    info = {}
+    out = P.rollout(*v0, gamma, base, params, 100, 10, info=info)
+    mask = out["x"].detach() > 48.0
+    J = _objective(out, mask, base["m"])
+    grads = torch.autograd.grad(J, v0 + [gamma])
+    dts = info["dts"]
+    dirs = w.fd_dirs
+    errs = []
+    for k in range(32):
+        d = dirs[k]
+        dv = [d[a * w.n:(a + 1) * w.n] for a in range(3)]
+        dg = d[3 * w.n:]
+        eps = 1e-6
+
+        def Jat(sign):
+            vv = [v0[a].detach() + sign * eps * t(dv[a]) for a in range(3)]
+            gm = gamma.detach() + sign * eps * t(dg)
+            o = P.rollout(*vv, gm, base, params, 100, 10, dts=dts)
+            return float(_objective(o, mask, base["m"]))
+
+        fd = (Jat(1) - Jat(-1)) / (2 * eps)
+        pred = sum(float((grads[a].cpu().numpy() * dv[a]).sum()) for a in range(3)) + \
+            float(grads[3].cpu().numpy()[0] * dg[0])
+        errs.append(abs(fd - pred) / max(abs(pred), 1e-12))
+    print("fd rel errors: max %.2e median %.2e" % (max(errs), float(np.median(errs))), flush=True)
+    assert max(errs) <= 1e-4, errs

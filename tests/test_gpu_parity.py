@@ -298,7 +298,8 @@ def test_step_mixed_rates_within_tolerance():
            "dE": (got["E"] - s0["E"]) / dt}
     err = field_relerr(est, ref)
     assert max(err.values()) <= MIXED_TOL, err
-    assert abs(dt - O.dt(O.cfg_for(w), ref["signal"])) <= 1e-5 * dt
+    s0r = ref_state(w)
+    assert abs(dt - O.dt(O.cfg_for(w), ref["signal"], rho=s0r["rho"], drho=ref["drho"])) <= 1e-5 * dt
 
 
 def test_step_empty():

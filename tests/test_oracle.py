@@ -371,10 +371,17 @@ def test_step_conserves_and_uniform_gas_dt(orc):
     for k in (1, 2, 3, 4):
         assert abs(t1[k] - t0[k]) < 1e-13 * (np.abs(s["m"]).sum() * (1 + np.abs(s["E"]).max()))
     assert t == dt > 0
-    # uniform gas at rest: signal speed = sound speed everywhere, dt = cfl h / c
+    # gas at rest: the signal speed is the sound speed everywhere, so the
+    # Courant part alone is cfl h / c
     w2, cfg2, s2 = lattice_state(orc, 8, p=1.0)
+    r2 = orc.rates(cfg2, s2)
+    assert orc.dt(cfg2, r2["signal"]) == pytest.approx(0.3 * 1.5 / math.sqrt(1.4), rel=1e-15)
+    # the density-change part binds where |drho/dt| > rho c / h (free surfaces)
+    full = orc.dt(cfg2, r2["signal"], rho=s2["rho"], drho=r2["drho"])
+    lim = 0.3 * np.min(s2["rho"] / np.abs(r2["drho"]))
+    assert full == pytest.approx(min(0.3 * 1.5 / math.sqrt(1.4), lim), rel=1e-15)
     _, _, dt2, _ = orc.step(cfg2, s2, 0.0)
-    assert dt2 == pytest.approx(0.3 * 1.5 / math.sqrt(1.4), rel=1e-15)
+    assert dt2 == full
 
 
 def test_step_ballistic_when_rates_vanish(orc):
