@@ -71,9 +71,10 @@ __global__ __launch_bounds__(kBlock) void k_pack(int64_t n, SrcState src,
         float ox = (float)(x - (g.ox + (double)cx * g.cell));
         float oy = (float)(y - (g.oy + (double)cy * g.cell));
         float oz = (float)(z - (g.oz + (double)cz * g.cell));
-        ((float4 *)recA)[s] = make_float4(ox, oy, oz, (float)V);
+        // x offset, y, z offsets from the cell origin and the cell's x index
+        ((float4 *)recA)[s] = make_float4(ox, oy, oz, (float)cx);
         ((float4 *)recB)[s] = make_float4((float)vx, (float)vy, (float)vz, (float)P);
-        ((float2 *)recC)[s] = make_float2((float)Z, (float)c);
+        ((float4 *)recC)[s] = make_float4((float)Z, (float)c, (float)V, 0.0f);
     } else {
         ((double4 *)recA)[s] = make_double4(x, y, z, V);
         ((double4 *)recB)[s] = make_double4(vx, vy, vz, P);
@@ -123,15 +124,94 @@ struct RateOut {
     unsigned long long *dtmin;
 };
 
+// ---------------------------------------------------------------- partner queues
+//
+// A candidate test costs ~20 instructions, a pair interaction ~50.  Testing
+// and interacting in the same loop would run the pair arithmetic whenever
+// any lane of the wave accepts a candidate, with the other lanes idle (a
+// particle accepts ~15-40 % of its candidates).  Instead each lane appends
+// its accepted partners to a small ring in LDS while the wave walks the
+// stencil in lock step, and as soon as some lane's ring is nearly full every
+// lane pops one partner and the wave runs the pair arithmetic with (nearly)
+// all lanes busy.  A lane's partners are summed in the order it popped them,
+// which depends only on the input: results are reproducible.
+//
+// Each stencil row (cells cx-R..cx+R at fixed y, z) is clipped to the chord
+// the support sphere of particle i cuts through it, with a safety margin,
+// so that with cells smaller than the support the lanes test little more
+// than the sphere.  The clipping only drops candidates that cannot be
+// partners; membership is decided by the pair test itself.
+
+constexpr int kQ = 8;  // ring slots per lane
+
+// Load base[idx] with a 32-bit byte offset from a wave-uniform base (records
+// stay below 4 GiB), which keeps the address arithmetic in one VGPR.
+template <typename T>
+__device__ __forceinline__ T ld(const T *__restrict__ base, int idx) {
+    return *(const T *)((const char *)base + (uint32_t)idx * (uint32_t)sizeof(T));
+}
+
+// Per-particle view of the stencil: cell, position in cell units, reach.
+struct Stencil {
+    int cx, cy, cz;
+    float xc, yc, zc;  // (x - origin) / D
+    float w2;          // (support/D)^2 with margin
+    int R;
+};
+
+__device__ __forceinline__ Stencil make_stencil(const GridDev &g, double x, double y, double z,
+                                                double H) {
+    Stencil t;
+    t.cx = cell_coord(x, g.ox, g.inv, g.dx);
+    t.cy = cell_coord(y, g.oy, g.inv, g.dy);
+    t.cz = cell_coord(z, g.oz, g.inv, g.dz);
+    t.xc = (float)((x - g.ox) * g.inv);
+    t.yc = (float)((y - g.oy) * g.inv);
+    t.zc = (float)((z - g.oz) * g.inv);
+    float hc = (float)(H * g.inv) * 1.0001f + 1e-3f;
+    t.w2 = hc * hc;
+    t.R = g.reach;
+    return t;
+}
+
+// Distance in cell units from coordinate c to the slab [k, k+1) (0 inside),
+// shrunk by a margin.
+__device__ __forceinline__ float slab_gap(float c, int k) {
+    float d = fmaxf(fmaxf((float)k - c, c - (float)(k + 1)), 0.0f);
+    return fmaxf(d - 1e-3f, 0.0f);
+}
+
+// Candidate range [j0, j0+len) of row (yy, zz) for a particle: the cells of
+// the row within the chord of its support sphere.  gz2 = squared z gap.
+__device__ __forceinline__ void row_range(const int32_t *__restrict__ cs, const GridDev &g,
+                                          const Stencil &t, bool on, int yy, int zz, float gz2,
+                                          int &j0, int &len) {
+    j0 = 0;
+    len = 0;
+    if (!on || zz < 0 || zz >= g.dz || yy < 0 || yy >= g.dy) return;
+    float gy = slab_gap(t.yc, yy);
+    float rem = t.w2 - (gy * gy + gz2);
+    if (!(rem > 0.0f)) return;
+    float hw = sqrtf(rem) * 1.0001f + 1e-3f;
+    int xa = max(max((int)floorf(t.xc - hw), t.cx - t.R), 0);
+    int xb = min(min((int)floorf(t.xc + hw), t.cx + t.R), g.dx - 1);
+    if (xb < xa) return;
+    int row = (zz * g.dy + yy) * g.dx;
+    j0 = cs[row + xa];
+    len = cs[row + xb + 1] - j0;
+}
+
 // ---------------------------------------------------------------- FP64 rates
 
 // One partner of particle i: Riemann problem along e, kernel slope, sums.
+// The membership test that precedes it is exact; here contraction is allowed.
 __device__ __forceinline__ void pair64(double dx, double dy, double dz, double r2,
                                        const double4 &bi, const double2 &ci,
                                        double vxj, double vyj, double vzj, double Pj, double Zj,
                                        double cj, double Vj, double invH, double dwc,
                                        double &ar, double &avx, double &avy, double &avz,
                                        double &aE, double &sig) {
+#pragma clang fp contract(fast)
     if (r2 == 0.0) return;
     double r = sqrt(r2);
     double ir = 1.0 / r;
@@ -164,6 +244,91 @@ __device__ __forceinline__ void pair64(double dx, double dy, double dz, double r
     sig = sp > sig ? sp : sig;
 }
 
+constexpr int kU = 2;  // candidates tested per lock-step iteration
+
+template <bool PAIR, bool WALL>
+struct Rates64 {
+    const double4 *__restrict__ A;
+    const double4 *__restrict__ B;
+    const double2 *__restrict__ Cz;
+    const double *__restrict__ dsz;
+    const int32_t *__restrict__ cs;
+    GridDev g;
+    PairConst pc;
+    int (*qj)[kBlock];
+    int tid, self;
+    bool live, near_wall;
+    double4 a, b;
+    double2 zc;
+    double di, xw, vw2;
+    Stencil t;
+    double ar = 0.0, avx = 0.0, avy = 0.0, avz = 0.0, aE = 0.0, sig = 0.0;
+    int qw = 0, qr = 0;
+
+    __device__ __forceinline__ void drain() {
+        if (qr < qw) {
+            int e = qj[qr & (kQ - 1)][tid];
+            ++qr;
+            int j = e & 0x7fffffff;
+            bool ghost = e < 0;
+            double4 aj = ld(A, j), bj = ld(B, j);
+            double2 zj = ld(Cz, j);
+            double xj = ghost ? 2.0 * xw - aj.x : aj.x;
+            double dx = xj - a.x, dy = aj.y - a.y, dz = aj.z - a.z;
+            double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
+            double invH = pc.invH, dwc = pc.dwc;
+            if (PAIR) {
+                double H = pc.kappa * (0.5 * (di + dsz[j]));
+                invH = 1.0 / H;
+                double i2 = invH * invH;
+                dwc = (210.0 / M_PI) * (i2 * i2);
+            }
+            pair64(dx, dy, dz, r2, b, zc, ghost ? vw2 - bj.x : bj.x, bj.y, bj.z, bj.w, zj.x, zj.y,
+                   aj.w, invH, dwc, ar, avx, avy, avz, aE, sig);
+        }
+    }
+
+    // one walk over the stencil: real partners, or mirror partners (GHOST)
+    template <bool GHOST>
+    __device__ __forceinline__ void pass() {
+        const bool on = live && (!GHOST || near_wall);
+        for (int oz = -t.R; oz <= t.R; ++oz) {
+            int zz = t.cz + oz;
+            float gz = slab_gap(t.zc, zz);
+            float gz2 = gz * gz;
+            for (int oy = -t.R; oy <= t.R; ++oy) {
+                int j0, len;
+                row_range(cs, g, t, on, t.cy + oy, zz, gz2, j0, len);
+                const int jlast = len > 0 ? j0 + len - 1 : 0;
+                for (int k = 0; __any(k < len); k += kU) {
+                    double4 aj[kU];
+#pragma unroll
+                    for (int u = 0; u < kU; ++u) aj[u] = ld(A, min(j0 + k + u, jlast));
+#pragma unroll
+                    for (int u = 0; u < kU; ++u) {
+                        const int j = j0 + k + u;
+                        double xj = GHOST ? 2.0 * xw - aj[u].x : aj[u].x;
+                        double dx = xj - a.x, dy = aj[u].y - a.y, dz = aj[u].z - a.z;
+                        // exact FP64 membership, no contraction
+                        double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
+                        double H2 = pc.H2;
+                        if (PAIR) {
+                            double H = pc.kappa * (0.5 * (di + ld(dsz, j < jlast ? j : jlast)));
+                            H2 = H * H;
+                        }
+                        const bool acc = (k + u < len) && (GHOST || j != self) && r2 < H2;
+                        // the ring slot qw is free: write always, advance on acceptance
+                        qj[qw & (kQ - 1)][tid] = GHOST ? (j | (int)0x80000000) : j;
+                        qw += acc;
+                    }
+                    // up to kU pushes per iteration: keep every ring at <= kQ - kU
+                    while (__any(qw - qr > kQ - kU)) drain();
+                }
+            }
+        }
+    }
+};
+
 template <bool PAIR, bool WALL>
 __global__ __launch_bounds__(kBlock) void k_rates64(int64_t n, const double4 *__restrict__ A,
                                                     const double4 *__restrict__ B,
@@ -173,103 +338,59 @@ __global__ __launch_bounds__(kBlock) void k_rates64(int64_t n, const double4 *__
                                                     const int32_t *__restrict__ cs, GridDev g,
                                                     PairConst pc, const double *t_dev,
                                                     double t_host, RateOut o, int want_dt) {
-    int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    __shared__ int qj[kQ][kBlock];
+    Rates64<PAIR, WALL> k;
+    k.A = A;
+    k.B = B;
+    k.Cz = Cz;
+    k.dsz = dsz;
+    k.cs = cs;
+    k.g = g;
+    k.pc = pc;
+    k.qj = qj;
+    k.tid = threadIdx.x;
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    k.self = (int)s;
+    k.live = s < n;
+    k.a = make_double4(0.0, 0.0, 0.0, 0.0);
+    k.b = k.a;
+    k.zc = make_double2(0.0, 0.0);
+    k.di = 0.0;
+    if (k.live) {
+        k.a = A[s];
+        k.b = B[s];
+        k.zc = Cz[s];
+        if (PAIR) k.di = dsz[s];
+    }
+    k.t = make_stencil(g, k.a.x, k.a.y, k.a.z, pc.H);
+    k.sig = k.zc.y;
+    k.xw = 0.0;
+    k.vw2 = 0.0;
+    k.near_wall = false;
+    if (WALL) {
+        double tt = t_dev ? *t_dev : t_host;
+        k.xw = pc.wall_x0 + pc.wall_v * tt;
+        k.vw2 = 2.0 * pc.wall_v;
+        k.near_wall = k.live && (k.a.x - k.xw < pc.H);
+    }
+    k.template pass<false>();
+    const int cnt = k.qw;  // real partners accepted
+    if (WALL && __any(k.near_wall)) k.template pass<true>();
+    while (__any(k.qr < k.qw)) k.drain();
     double dtv = INFINITY;
-    if (s < n) {
-        double4 a = A[s], b = B[s];
-        double2 zc = Cz[s];
-        double di = PAIR ? dsz[s] : 0.0;
-        int cx = cell_coord(a.x, g.ox, g.inv, g.dx);
-        int cy = cell_coord(a.y, g.oy, g.inv, g.dy);
-        int cz = cell_coord(a.z, g.oz, g.inv, g.dz);
-        double ar = 0.0, avx = 0.0, avy = 0.0, avz = 0.0, aE = 0.0, sig = zc.y;
-        int cnt = 0;
-        const int R = g.reach;
-        const int x0 = max(cx - R, 0), x1 = min(cx + R, g.dx - 1);
-        for (int oz = -R; oz <= R; ++oz) {
-            int zz = cz + oz;
-            if (zz < 0 || zz >= g.dz) continue;
-            for (int oy = -R; oy <= R; ++oy) {
-                int yy = cy + oy;
-                if (yy < 0 || yy >= g.dy) continue;
-                int row = (zz * g.dy + yy) * g.dx;
-                int j0 = cs[row + x0], j1 = cs[row + x1 + 1];
-                for (int j = j0; j < j1; ++j) {
-                    if (j == (int)s) continue;
-                    double4 aj = A[j];
-                    double dx = aj.x - a.x, dy = aj.y - a.y, dz = aj.z - a.z;
-                    double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
-                    double invH, dwc;
-                    if (PAIR) {
-                        double H = pc.kappa * (0.5 * (di + dsz[j]));
-                        if (!(r2 < H * H)) continue;
-                        invH = 1.0 / H;
-                        double i2 = invH * invH;
-                        dwc = (210.0 / M_PI) * (i2 * i2);
-                    } else {
-                        if (!(r2 < pc.H2)) continue;
-                        invH = pc.invH;
-                        dwc = pc.dwc;
-                    }
-                    ++cnt;
-                    double4 bj = B[j];
-                    double2 zj = Cz[j];
-                    pair64(dx, dy, dz, r2, b, zc, bj.x, bj.y, bj.z, bj.w, zj.x, zj.y, aj.w, invH,
-                           dwc, ar, avx, avy, avz, aE, sig);
-                }
-            }
-        }
-        if (WALL) {
-            double t = t_dev ? *t_dev : t_host;
-            double xw = pc.wall_x0 + pc.wall_v * t;
-            double vw2 = 2.0 * pc.wall_v;
-            if (a.x - xw < pc.H) {
-                for (int oz = -R; oz <= R; ++oz) {
-                    int zz = cz + oz;
-                    if (zz < 0 || zz >= g.dz) continue;
-                    for (int oy = -R; oy <= R; ++oy) {
-                        int yy = cy + oy;
-                        if (yy < 0 || yy >= g.dy) continue;
-                        int row = (zz * g.dy + yy) * g.dx;
-                        int j0 = cs[row + x0], j1 = cs[row + x1 + 1];
-                        for (int j = j0; j < j1; ++j) {
-                            double4 aj = A[j];
-                            double xg = 2.0 * xw - aj.x;
-                            double dx = xg - a.x, dy = aj.y - a.y, dz = aj.z - a.z;
-                            double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
-                            double invH, dwc;
-                            if (PAIR) {
-                                double H = pc.kappa * (0.5 * (di + dsz[j]));
-                                if (!(r2 < H * H)) continue;
-                                invH = 1.0 / H;
-                                double i2 = invH * invH;
-                                dwc = (210.0 / M_PI) * (i2 * i2);
-                            } else {
-                                if (!(r2 < pc.H2)) continue;
-                                invH = pc.invH;
-                                dwc = pc.dwc;
-                            }
-                            double4 bj = B[j];
-                            double2 zj = Cz[j];
-                            pair64(dx, dy, dz, r2, b, zc, vw2 - bj.x, bj.y, bj.z, bj.w, zj.x, zj.y,
-                                   aj.w, invH, dwc, ar, avx, avy, avz, aE, sig);
-                        }
-                    }
-                }
-            }
-        }
+    if (k.live) {
         double ri = rho[s];
         double pre = 2.0 / ri;
-        double drho = -2.0 * ri * ar;
+        double drho = -2.0 * ri * k.ar;
         o.rho[s] = drho;
-        o.vx[s] = pre * avx;
-        o.vy[s] = pre * avy;
-        o.vz[s] = pre * avz;
-        o.E[s] = pre * aE;
-        if (o.sig) o.sig[s] = sig;
+        o.vx[s] = pre * k.avx;
+        o.vy[s] = pre * k.avy;
+        o.vz[s] = pre * k.avz;
+        o.E[s] = pre * k.aE;
+        if (o.sig) o.sig[s] = k.sig;
         if (o.cnt) o.cnt[s] = cnt;
         // Courant limit and relative density-change limit of one explicit step
-        dtv = fmin((PAIR ? di : pc.h_dt) / sig, ri / fabs(drho));
+        dtv = fmin((PAIR ? k.di : pc.h_dt) / k.sig, ri / fabs(drho));
     }
     if (want_dt) block_min_to(dtv, o.dtmin);
 }
@@ -277,10 +398,11 @@ __global__ __launch_bounds__(kBlock) void k_rates64(int64_t n, const double4 *__
 // ---------------------------------------------------------------- mixed rates (FP32 pairs)
 
 __device__ __forceinline__ void pair32(float dx, float dy, float dz, float r2, const float4 &bi,
-                                       const float2 &ci, float vxj, float vyj, float vzj,
+                                       const float4 &ci, float vxj, float vyj, float vzj,
                                        float Pj, float Zj, float cj, float Vj, float invH,
                                        float dwc, float &ar, float &avx, float &avy, float &avz,
                                        float &aE, float &sig) {
+#pragma clang fp contract(fast)
     if (r2 == 0.0f) return;
     float ir = __builtin_amdgcn_rsqf(r2);
     float r = r2 * ir;
@@ -314,10 +436,116 @@ __device__ __forceinline__ void pair32(float dx, float dy, float dz, float r2, c
     sig = sp > sig ? sp : sig;
 }
 
+// Candidates whose FP32 squared distance lies within this relative band of
+// the squared support are re-tested in FP64 from the FP64 positions, so the
+// mixed kernel accepts exactly the FP64 neighbour set (the FP32 error of r^2
+// is below 1e-6 relative for offsets within a few cells).
+constexpr float kBand = 4e-5f;
+
+template <bool PAIR, bool WALL>
+struct Rates32 {
+    const float4 *__restrict__ A;
+    const float4 *__restrict__ B;
+    const float4 *__restrict__ Cz;
+    const double *__restrict__ xs;
+    const double *__restrict__ ys;
+    const double *__restrict__ zs;
+    const double *__restrict__ dsz;
+    const int32_t *__restrict__ cs;
+    GridDev g;
+    PairConst pc;
+    float4 (*qd)[kBlock];
+    int tid, self;
+    bool live, near_wall;
+    float4 a, b, c;
+    double xi, yi, zi, di, xw;
+    float wd, vw2, Df, cxf, lo, hi;
+    Stencil t;
+    float ar = 0.f, avx = 0.f, avy = 0.f, avz = 0.f, aE = 0.f, sig = 0.f;
+    int qw = 0, qr = 0, cnt = 0;
+
+    __device__ __forceinline__ void drain() {
+        if (qr < qw) {
+            float4 q = qd[qr & (kQ - 1)][tid];
+            ++qr;
+            int e = __float_as_int(q.w);
+            int j = e & 0x7fffffff;
+            bool ghost = e < 0;
+            float4 bj = ld(B, j), cj = ld(Cz, j);
+            float invH = (float)pc.invH, dwc = (float)pc.dwc;
+            float H2lo = lo;
+            double H2d = pc.H2;
+            if (PAIR) {
+                double H = pc.kappa * (0.5 * (di + dsz[j]));
+                H2d = H * H;
+                H2lo = (float)H2d * (1.0f - kBand);
+                invH = (float)(1.0 / H);
+                float i2 = invH * invH;
+                dwc = (float)(210.0 / M_PI) * (i2 * i2);
+            }
+            float r2 = (q.x * q.x + q.y * q.y) + q.z * q.z;
+            bool in = true;
+            if (!(r2 < H2lo)) {
+                // near the support: decide membership in FP64 (rare)
+                double xj = ghost ? 2.0 * xw - xs[j] : xs[j];
+                double ex = xj - xi, ey = ys[j] - yi, ez = zs[j] - zi;
+                in = ((ex * ex) + (ey * ey)) + (ez * ez) < H2d;
+            }
+            if (in) {
+                if (!ghost) ++cnt;
+                pair32(q.x, q.y, q.z, r2, b, c, ghost ? vw2 - bj.x : bj.x, bj.y, bj.z, bj.w,
+                       cj.x, cj.y, cj.z, invH, dwc, ar, avx, avy, avz, aE, sig);
+            }
+        }
+    }
+
+    template <bool GHOST>
+    __device__ __forceinline__ void pass() {
+#pragma clang fp contract(fast)
+        const bool on = live && (!GHOST || near_wall);
+        for (int oz = -t.R; oz <= t.R; ++oz) {
+            int zz = t.cz + oz;
+            const float sz = (float)oz * Df;
+            float gz = slab_gap(t.zc, zz);
+            float gz2 = gz * gz;
+            for (int oy = -t.R; oy <= t.R; ++oy) {
+                const float sy = (float)oy * Df;
+                int j0, len;
+                row_range(cs, g, t, on, t.cy + oy, zz, gz2, j0, len);
+                const int jlast = len > 0 ? j0 + len - 1 : 0;
+                const float ay = a.y - sy, az = a.z - sz;
+                for (int k = 0; __any(k < len); k += kU) {
+                    float4 aj[kU];
+#pragma unroll
+                    for (int u = 0; u < kU; ++u) aj[u] = ld(A, min(j0 + k + u, jlast));
+#pragma unroll
+                    for (int u = 0; u < kU; ++u) {
+                        const int j = j0 + k + u;
+                        float dx = (aj[u].x + (aj[u].w - cxf) * Df) - a.x;
+                        float dy = aj[u].y - ay, dz = aj[u].z - az;
+                        if (GHOST) dx = 2.0f * wd - dx;
+                        float r2 = (dx * dx + dy * dy) + dz * dz;
+                        float hj = hi;
+                        if (PAIR) {
+                            double H = pc.kappa * (0.5 * (di + ld(dsz, j < jlast ? j : jlast)));
+                            hj = (float)(H * H) * (1.0f + kBand);
+                        }
+                        const bool acc = (k + u < len) && (GHOST || j != self) && r2 < hj;
+                        qd[qw & (kQ - 1)][tid] = make_float4(
+                            dx, dy, dz, __int_as_float(GHOST ? (j | (int)0x80000000) : j));
+                        qw += acc;
+                    }
+                    while (__any(qw - qr > kQ - kU)) drain();
+                }
+            }
+        }
+    }
+};
+
 template <bool PAIR, bool WALL>
 __global__ __launch_bounds__(kBlock) void k_rates32(int64_t n, const float4 *__restrict__ A,
                                                     const float4 *__restrict__ B,
-                                                    const float2 *__restrict__ Cz,
+                                                    const float4 *__restrict__ Cz,
                                                     const double *__restrict__ xs,
                                                     const double *__restrict__ ys,
                                                     const double *__restrict__ zs,
@@ -326,95 +554,69 @@ __global__ __launch_bounds__(kBlock) void k_rates32(int64_t n, const float4 *__r
                                                     const int32_t *__restrict__ cs, GridDev g,
                                                     PairConst pc, const double *t_dev,
                                                     double t_host, RateOut o, int want_dt) {
-    int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    __shared__ float4 qd[kQ][kBlock];
+    Rates32<PAIR, WALL> k;
+    k.A = A;
+    k.B = B;
+    k.Cz = Cz;
+    k.xs = xs;
+    k.ys = ys;
+    k.zs = zs;
+    k.dsz = dsz;
+    k.cs = cs;
+    k.g = g;
+    k.pc = pc;
+    k.qd = qd;
+    k.tid = threadIdx.x;
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    k.self = (int)s;
+    k.live = s < n;
+    k.a = make_float4(0.f, 0.f, 0.f, 0.f);
+    k.b = k.a;
+    k.c = k.a;
+    k.xi = k.yi = k.zi = k.di = 0.0;
+    if (k.live) {
+        k.a = A[s];
+        k.b = B[s];
+        k.c = Cz[s];
+        k.xi = xs[s];
+        k.yi = ys[s];
+        k.zi = zs[s];
+        if (PAIR) k.di = dsz[s];
+    }
+    k.t = make_stencil(g, k.xi, k.yi, k.zi, pc.H);
+    k.sig = k.c.y;
+    k.Df = (float)g.cell;
+    k.cxf = (float)k.t.cx;
+    k.lo = (float)pc.H2 * (1.0f - kBand);
+    k.hi = (float)pc.H2 * (1.0f + kBand);
+    k.xw = 0.0;
+    k.wd = 0.f;
+    k.vw2 = 0.f;
+    k.near_wall = false;
+    if (WALL) {
+        double tt = t_dev ? *t_dev : t_host;
+        k.xw = pc.wall_x0 + pc.wall_v * tt;
+        k.near_wall = k.live && (k.xi - k.xw < pc.H);
+        k.wd = (float)(k.xw - k.xi);
+        k.vw2 = (float)(2.0 * pc.wall_v);
+    }
+    k.template pass<false>();
+    if (WALL && __any(k.near_wall)) k.template pass<true>();
+    while (__any(k.qr < k.qw)) k.drain();
     double dtv = INFINITY;
-    if (s < n) {
-        float4 a = A[s], b = B[s];
-        float2 zc = Cz[s];
-        double xi = xs[s];
-        double di = PAIR ? dsz[s] : 0.0;
-        int cx = cell_coord(xi, g.ox, g.inv, g.dx);
-        int cy = cell_coord(ys[s], g.oy, g.inv, g.dy);
-        int cz = cell_coord(zs[s], g.oz, g.inv, g.dz);
-        float ar = 0.f, avx = 0.f, avy = 0.f, avz = 0.f, aE = 0.f, sig = zc.y;
-        int cnt = 0;
-        const int R = g.reach;
-        const float Df = (float)g.cell;
-        const float H2f = (float)pc.H2, invHf = (float)pc.invH, dwcf = (float)pc.dwc;
-        bool wall_near = false;
-        float wd = 0.f, vw2 = 0.f;
-        if (WALL) {
-            double t = t_dev ? *t_dev : t_host;
-            double xw = pc.wall_x0 + pc.wall_v * t;
-            wall_near = xi - xw < pc.H;
-            wd = (float)(xw - xi);
-            vw2 = (float)(2.0 * pc.wall_v);
-        }
-        for (int oz = -R; oz <= R; ++oz) {
-            int zz = cz + oz;
-            if (zz < 0 || zz >= g.dz) continue;
-            float sz = (float)oz * Df;
-            for (int oy = -R; oy <= R; ++oy) {
-                int yy = cy + oy;
-                if (yy < 0 || yy >= g.dy) continue;
-                float sy = (float)oy * Df;
-                int row = (zz * g.dy + yy) * g.dx;
-                for (int ox = -R; ox <= R; ++ox) {
-                    int xx = cx + ox;
-                    if (xx < 0 || xx >= g.dx) continue;
-                    float sx = (float)ox * Df;
-                    int j0 = cs[row + xx], j1 = cs[row + xx + 1];
-                    for (int j = j0; j < j1; ++j) {
-                        float4 aj = A[j];
-                        float dx = (aj.x + sx) - a.x, dy = (aj.y + sy) - a.y,
-                              dz = (aj.z + sz) - a.z;
-                        float H2, invH, dwc;
-                        if (PAIR) {
-                            double H = pc.kappa * (0.5 * (di + dsz[j]));
-                            H2 = (float)(H * H);
-                            invH = (float)(1.0 / H);
-                            float i2 = invH * invH;
-                            dwc = (float)(210.0 / M_PI) * (i2 * i2);
-                        } else {
-                            H2 = H2f;
-                            invH = invHf;
-                            dwc = dwcf;
-                        }
-                        if (j != (int)s) {
-                            float r2 = (dx * dx + dy * dy) + dz * dz;
-                            if (r2 < H2) {
-                                ++cnt;
-                                float4 bj = B[j];
-                                float2 zj = Cz[j];
-                                pair32(dx, dy, dz, r2, b, zc, bj.x, bj.y, bj.z, bj.w, zj.x, zj.y,
-                                       aj.w, invH, dwc, ar, avx, avy, avz, aE, sig);
-                            }
-                        }
-                        if (WALL && wall_near) {
-                            float gx = 2.0f * wd - dx;
-                            float r2 = (gx * gx + dy * dy) + dz * dz;
-                            if (r2 < H2) {
-                                float4 bj = B[j];
-                                float2 zj = Cz[j];
-                                pair32(gx, dy, dz, r2, b, zc, vw2 - bj.x, bj.y, bj.z, bj.w, zj.x,
-                                       zj.y, aj.w, invH, dwc, ar, avx, avy, avz, aE, sig);
-                            }
-                        }
-                    }
-                }
-            }
-        }
+    if (k.live) {
         double ri = rho[s];
         double pre = 2.0 / ri;
-        double drho = -2.0 * ri * (double)ar;
+        double drho = -2.0 * ri * (double)k.ar;
         o.rho[s] = drho;
-        o.vx[s] = pre * (double)avx;
-        o.vy[s] = pre * (double)avy;
-        o.vz[s] = pre * (double)avz;
-        o.E[s] = pre * (double)aE;
-        if (o.sig) o.sig[s] = (double)sig;
-        if (o.cnt) o.cnt[s] = cnt;
-        dtv = fmin((PAIR ? di : pc.h_dt) / (double)sig, ri / fabs(drho));
+        o.vx[s] = pre * (double)k.avx;
+        o.vy[s] = pre * (double)k.avy;
+        o.vz[s] = pre * (double)k.avz;
+        o.E[s] = pre * (double)k.aE;
+        if (o.sig) o.sig[s] = (double)k.sig;
+        if (o.cnt) o.cnt[s] = k.cnt;
+        dtv = fmin((PAIR ? k.di : pc.h_dt) / (double)k.sig, ri / fabs(drho));
     }
     if (want_dt) block_min_to(dtv, o.dtmin);
 }
@@ -432,7 +634,7 @@ hipError_t launch_rates(int64_t n, int mixed, const GridDev &g, const PairConst 
         if (mixed)                                                                             \
             k_rates32<P, W><<<nb, kBlock, 0, st>>>(n, (const float4 *)w.recA,                  \
                                                    (const float4 *)w.recB,                     \
-                                                   (const float2 *)w.recC, sorted[0], sorted[1], \
+                                                   (const float4 *)w.recC, sorted[0], sorted[1], \
                                                    sorted[2], rho_sorted, d_sorted, w.cs, g,    \
                                                    pc, t_dev, t_host, o, want_dt);             \
         else                                                                                   \

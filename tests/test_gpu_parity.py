@@ -185,6 +185,20 @@ def test_rates_mixed(case):
     print("mixed relerr", err)
     assert max(err.values()) <= MIXED_TOL, err
     assert np.abs(got["signal"] - ref["signal"]).max() <= 1e-5 * ref["signal"].max()
+    # candidates near the cutoff are re-tested in FP64: the FP64 neighbour counts
+    assert np.array_equal(got["nbr_count"].astype(np.int64), ref["nbr_count"])
+
+
+@pytest.mark.parametrize("D", [1.0, 1.5, 2.2])
+def test_rates_small_cells(D):
+    """Cells smaller than the support (stencil reach ceil(H/D) > 1) give the same rates."""
+    w = wall_block()
+    w.cell_size = D
+    for prec, tol in (("fp64", FP64_TOL), ("mixed", MIXED_TOL)):
+        got, ref = _rates_case(w, prec, t=0.1)
+        err = field_relerr(got, ref)
+        assert max(err.values()) <= tol, (D, prec, err)
+        assert np.array_equal(got["nbr_count"].astype(np.int64), ref["nbr_count"])
 
 
 def test_rates_plate_impact_block_mixed_and_fp64():
