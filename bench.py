@@ -18,6 +18,7 @@ Prints ONE JSON line.  `value` = directed pair interactions per second
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -43,6 +44,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slab", type=float, default=96.0,
                     help="oracle sample: particles with x < this (same workload)")
+    ap.add_argument("--no-adjoint", dest="adjoint", action="store_false",
+                    help="skip the adjoint/forward ratio of the 64^3 checkpointed rollout")
+    ap.add_argument("--cell", type=float, default=1.0,
+                    help="mesh cell size in lattice spacings (results do not depend on it)")
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="first copy a buffer of this many GiB three times (counter calibration)")
     return ap.parse_args()
 
 
@@ -50,20 +57,72 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_steps(P, torch, state, params, sites, k, ws, sc, count_pairs=True):
-    """k steps of (csph_step, voronoi_assign); returns (state, pairs summed on device)."""
-    n = state.n
-    cnt = torch.empty(n, dtype=torch.int32, device="cuda")
-    owner = torch.empty(n, dtype=torch.int32, device="cuda")
-    pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
-    other = state.like()
-    for _ in range(k):
-        out = P.csph_step(state, params, sc, s_out=other, nbr_count=cnt, ws=ws)
-        _, sp, spairs = P.voronoi_assign(out["x"], out["y"], out["z"], sites, cnt, owner=owner)
-        if count_pairs:
-            pairs += spairs.sum()
-        state, other = out, state
-    return state, pairs
+class Runner:
+    """Step loop with every buffer allocated up front (nothing is allocated while timed)."""
+
+    def __init__(self, P, torch, state, params, sites, ws, sc):
+        n = state.n
+        self.P, self.params, self.sites, self.ws, self.sc = P, params, sites, ws, sc
+        self.cnt = torch.empty(n, dtype=torch.int32, device="cuda")
+        self.owner = torch.empty(n, dtype=torch.int32, device="cuda")
+        self.site_particles = torch.empty(sites.shape[0], dtype=torch.int64, device="cuda")
+        self.site_pairs = torch.empty(sites.shape[0], dtype=torch.int64, device="cuda")
+        self.pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+        self.state, self.other = state, state.like()
+
+    def run(self, k, count_pairs=True):
+        """k steps of (csph_step, voronoi_assign); directed pairs summed on the device."""
+        P = self.P
+        for _ in range(k):
+            out = P.csph_step(self.state, self.params, self.sc, s_out=self.other,
+                              nbr_count=self.cnt, ws=self.ws)
+            P.voronoi_assign(out["x"], out["y"], out["z"], self.sites, self.cnt, owner=self.owner,
+                             site_particles=self.site_particles, site_pairs=self.site_pairs)
+            if count_pairs:
+                self.pairs += self.site_pairs.sum()
+            self.state, self.other = out, self.state
+
+
+def traffic_from_profile(kernel_src):
+    """HBM bytes per launch of the pair-rate kernel from the committed counter summary,
+    or None when the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_rates32_porous256.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    fields = dict(re.findall(r"^- (\w+): (\S+)$", text, re.M))
+    sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    if fields.get("source_sha256") != sha:
+        return None
+    return {"read_bytes": float(fields["read_bytes_per_launch"]),
+            "write_bytes": float(fields["write_bytes_per_launch"]),
+            "bytes": float(fields["read_bytes_per_launch"]) + float(fields["write_bytes_per_launch"])}
+
+
+def adjoint_ratio(P, torch, ci):
+    """Adjoint/forward wall-time ratio of the checkpointed 64^3 Sod rollout
+    (100 FP64 steps, checkpoint every 10, objective: x-momentum beyond x = 48)."""
+    import numpy as np
+    w = ci.config3()
+    params = P.Params.from_workload(w)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float64), device="cuda").contiguous()
+    base = dict(x=t(w.x), y=t(w.y), z=t(w.z), rho=t(w.rho), p=t(w.p), m=t(w.m),
+                mat=torch.as_tensor(w.mat, dtype=torch.int32, device="cuda"))
+    gamma = torch.tensor([w.eos[0][1]], dtype=torch.float64, device="cuda", requires_grad=True)
+    best = None
+    for _ in range(2):  # the first rollout also warms the library's code paths
+        v0 = [t(a).requires_grad_(True) for a in (w.vx, w.vy, w.vz)]
+        info = {}
+        out = P.rollout(*v0, gamma, base, params, w.steps, 10, info=info)
+        mask = out["x"].detach() > 48.0
+        J = (out["vx"][mask] * base["m"][mask]).sum()
+        torch.autograd.grad(J, v0 + [gamma])
+        r = {"ratio": info["backward_s"] / info["forward_s"], "forward_s": info["forward_s"],
+             "backward_s": info["backward_s"]}
+        best = r
+    return {"workload": w.name, "particles": w.n, "steps": w.steps, "checkpoint_every": 10,
+            "precision": "fp64", **{k: round(v, 5) for k, v in best.items()}}
 
 
 def cpu_baseline(w, slab):
@@ -100,6 +159,15 @@ def main():
     import csph_inputs as ci
     import paper_1805_05128_amd as P
 
+    if args.copy_probe > 0:
+        nbytes = int(args.copy_probe * (1 << 30))
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: 3 copies of {nbytes} bytes")
+        del src, dst
     t_gen = time.perf_counter()
     w = ci.config2(voids=(args.workload == "porous"))
     log(f"workload {w.name}: {w.n} particles ({time.perf_counter() - t_gen:.1f} s to generate)")
@@ -111,29 +179,32 @@ def main():
     for prec, k in (("mixed", args.steps), ("fp64", args.fp64_steps)):
         if k <= 0:
             continue
-        params = P.Params.from_workload(w, precision=prec, reorder=True)
+        params = P.Params.from_workload(w, precision=prec, reorder=True, cell_size=args.cell)
         state = P.state_from_workload(w, params, "cuda", with_id=True)
         sc = P.StepScalars("cuda")
+        run = Runner(P, torch, state, params, sites, ws, sc)
         P.profile_enable(True)  # warm-up steps also warm the event pool
-        state, _ = run_steps(P, torch, state, params, sites, args.warmup, ws, sc, False)
+        run.run(args.warmup, False)
         torch.cuda.synchronize()
         tot0 = sc.totals.cpu().numpy().copy()
         P.profile_read()
+        run.pairs.zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        state, pairs = run_steps(P, torch, state, params, sites, k, ws, sc)
+        run.run(k)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         prof = P.profile_read()
         P.profile_enable(False)
         tot1 = sc.totals.cpu().numpy()
-        npairs = int(pairs.item())
+        npairs = int(run.pairs.item())
         results[prec] = dict(ms=1e3 * el / k, pairs_per_step=npairs / k, el=el, k=k, prof=prof,
                              nonphys=int(sc.nonphys.item()), t=float(sc.t.item()),
                              tot0=tot0, tot1=tot1)
         log(f"{prec}: {1e3 * el / k:.3f} ms/step, {npairs / el:.3e} pairs/s, "
             f"rates kernel {prof['rates'][1] / max(prof['rates'][0], 1):.3f} ms")
-        del state
+        del state, run
+        torch.cuda.empty_cache()
 
     m = results["mixed"]
     rates_launches, rates_ms = m["prof"]["rates"]
@@ -141,6 +212,10 @@ def main():
     flops = FLOP_PER_PAIR * m["pairs_per_step"]
     achieved = flops / rates_avg_s / 1e12
     kernels = {g: round(v[1] / max(v[0], 1), 4) for g, v in m["prof"].items() if v[0] > 0}
+    traffic = traffic_from_profile(os.path.join(ROOT, "paper_1805_05128_amd", "csrc", "k_rates.hip"))
+    # per particle the pair-rate kernel must read its 48 B FP32 record, FP64 position (24 B)
+    # and density (8 B), and write five FP64 rates, the signal speed and the count (52 B)
+    alg_bytes = w.n * (80 + 52)
     e0 = m["tot0"][8] + m["tot0"][9]
     e1 = m["tot1"][8] + m["tot1"][9]
     line = {
@@ -159,12 +234,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "particles": w.n, "lattice": "256^3, 30% voids r=5",
                    "support": "2h = 3 spacings", "piston": "x=0, v=+2", "voronoi_sites": 64,
-                   "eos": "ideal gas 1.4", "cfl": 0.3},
+                   "eos": "ideal gas 1.4", "cfl": 0.3, "cell": args.cell},
         "pairs_per_step": m["pairs_per_step"],
         "kernel_ms": kernels,
         "roofline": {"bound": "alu", "kernel": "k_rates32 (pair rates, FP32)",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": traffic["bytes"] if traffic else None,
+                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE x2 + WRITE_SIZE)",
+                     "algorithmic_bytes": alg_bytes,
                      "flop_per_pair": FLOP_PER_PAIR},
         "energy_total_rel_change": (e1 - e0) / abs(e0) if e0 else None,
         "nonphys": m["nonphys"],
@@ -174,6 +252,11 @@ def main():
         line["fp64"] = {"ms_per_step": f["ms"], "value": f["pairs_per_step"] * 1e3 / f["ms"],
                         "rates_kernel_ms": f["prof"]["rates"][1] / max(f["prof"]["rates"][0], 1)}
         line["mixed_speedup_over_fp64"] = f["ms"] / m["ms"]
+    if args.adjoint:
+        log("adjoint rollout ...")
+        line["adjoint"] = adjoint_ratio(P, torch, ci)
+        line["adjoint_forward_ratio"] = line["adjoint"]["ratio"]
+        log(f"adjoint/forward {line['adjoint_forward_ratio']:.3f}")
     if not args.no_cpu_baseline:
         log("oracle CPU baseline ...")
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_slab)

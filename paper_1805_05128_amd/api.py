@@ -308,16 +308,33 @@ def csph_step(s_in: State, params: Params, sc: StepScalars, s_out: Optional[Stat
 
 
 def voronoi_assign(x, y, z, sites: torch.Tensor, nbr_count: Optional[torch.Tensor] = None,
-                   owner: Optional[torch.Tensor] = None, stream=None):
-    """(owner int32 [n], site_particles int64 [K], site_pairs int64 [K] or None)."""
+                   owner: Optional[torch.Tensor] = None, stream=None,
+                   site_particles: Optional[torch.Tensor] = None,
+                   site_pairs: Optional[torch.Tensor] = None):
+    """(owner int32 [n], site_particles int64 [K], site_pairs int64 [K] or None).
+
+    Output buffers may be passed in (owner int32 [>= n], site_particles and
+    site_pairs int64 [K]); site_pairs is only written when nbr_count is given.
+    """
     L = N.load()
     n = x.shape[0]
     K = sites.shape[0]
-    sites = sites.to(torch.float64).contiguous()
+    if sites.dtype != torch.float64 or not sites.is_contiguous():
+        sites = sites.to(torch.float64).contiguous()
     if owner is None:
         owner = torch.empty(max(n, 1), dtype=torch.int32, device=x.device)
-    sp = torch.empty(K, dtype=torch.int64, device=x.device)
-    spairs = torch.empty(K, dtype=torch.int64, device=x.device) if nbr_count is not None else None
+    sp = site_particles
+    if sp is None:
+        sp = torch.empty(K, dtype=torch.int64, device=x.device)
+    spairs = None
+    if nbr_count is not None:
+        spairs = site_pairs
+        if spairs is None:
+            spairs = torch.empty(K, dtype=torch.int64, device=x.device)
+    for name, buf, dt, need in (("owner", owner, torch.int32, n), ("site_particles", sp, torch.int64, K),
+                                ("site_pairs", spairs, torch.int64, K)):
+        if buf is not None and (buf.dtype != dt or buf.numel() < need or not buf.is_contiguous()):
+            raise ValueError(f"voronoi_assign: {name} must be contiguous {dt} with >= {need} entries")
     st = L.voronoi_assign(_dp(x), _dp(y), _dp(z), n, _dp(sites), K, _ip(nbr_count), _ip(owner),
                           _lp(sp), _lp(spairs), _stream(stream))
     N.check(st, "voronoi_assign")

@@ -183,65 +183,65 @@ __device__ __forceinline__ float slab_gap(float c, int k) {
 
 // Candidate range [j0, j0+len) of row (yy, zz) for a particle: the cells of
 // the row within the chord of its support sphere.  gz2 = squared z gap.
+// Branch-free: a row off the mesh or missing the sphere gets len = 0.
 __device__ __forceinline__ void row_range(const int32_t *__restrict__ cs, const GridDev &g,
                                           const Stencil &t, bool on, int yy, int zz, float gz2,
                                           int &j0, int &len) {
-    j0 = 0;
-    len = 0;
-    if (!on || zz < 0 || zz >= g.dz || yy < 0 || yy >= g.dy) return;
-    float gy = slab_gap(t.yc, yy);
-    float rem = t.w2 - (gy * gy + gz2);
-    if (!(rem > 0.0f)) return;
-    float hw = sqrtf(rem) * 1.0001f + 1e-3f;
-    int xa = max(max((int)floorf(t.xc - hw), t.cx - t.R), 0);
-    int xb = min(min((int)floorf(t.xc + hw), t.cx + t.R), g.dx - 1);
-    if (xb < xa) return;
-    int row = (zz * g.dy + yy) * g.dx;
-    j0 = cs[row + xa];
-    len = cs[row + xb + 1] - j0;
+    const bool inb = on && zz >= 0 && zz < g.dz && yy >= 0 && yy < g.dy;
+    const float gy = slab_gap(t.yc, yy);
+    const float rem = t.w2 - (gy * gy + gz2);
+    // chord half-width; v_sqrt_f32 (1 ulp) is ample under the margins
+    const float hw = __builtin_amdgcn_sqrtf(fmaxf(rem, 0.0f)) * 1.0001f + 1e-3f;
+    const int xa = max(max((int)floorf(t.xc - hw), t.cx - t.R), 0);
+    const int xb = min(min((int)floorf(t.xc + hw), t.cx + t.R), g.dx - 1);
+    const bool ok = inb && rem > 0.0f && xb >= xa;
+    const int row = (zz * g.dy + yy) * g.dx;
+    const int ia = ok ? row + xa : 0, ib = ok ? row + xb + 1 : 0;
+    j0 = cs[ia];
+    len = cs[ib] - j0;
 }
 
 // ---------------------------------------------------------------- FP64 rates
+//
+// The pair step is written without branches: a lane with no partner to
+// evaluate (empty ring, coincident partner) runs the same instructions on
+// placeholder data and keeps its sums by selection.  Divergent branches in
+// the drain made the compiler shuffle the live sums between registers on
+// every pop.
 
 // One partner of particle i: Riemann problem along e, kernel slope, sums.
 // The membership test that precedes it is exact; here contraction is allowed.
-__device__ __forceinline__ void pair64(double dx, double dy, double dz, double r2,
+__device__ __forceinline__ void pair64(bool use, double dx, double dy, double dz, double r2,
                                        const double4 &bi, const double2 &ci,
                                        double vxj, double vyj, double vzj, double Pj, double Zj,
                                        double cj, double Vj, double invH, double dwc,
                                        double &ar, double &avx, double &avy, double &avz,
                                        double &aE, double &sig) {
 #pragma clang fp contract(fast)
-    if (r2 == 0.0) return;
-    double r = sqrt(r2);
-    double ir = 1.0 / r;
-    double ex = dx * ir, ey = dy * ir, ez = dz * ir;
-    double q = r * invH;
-    double a1 = 1.0 - q;
-    double dW = -dwc * q * (a1 * a1 * a1);
-    double vL = (bi.x * ex + bi.y * ey) + bi.z * ez;
-    double vR = (vxj * ex + vyj * ey) + vzj * ez;
-    double Zi = ci.x, Pi = bi.w;
-    double S = Zi + Zj;
-    double vs, ps;
-    if (S != 0.0) {
-        double iS = 1.0 / S;
-        vs = ((Zi * vL + Zj * vR) + (Pi - Pj)) * iS;
-        ps = ((Zj * Pi + Zi * Pj) + Zi * Zj * (vL - vR)) * iS;
-    } else {
-        vs = 0.5 * (vL + vR);
-        ps = 0.5 * (Pi + Pj);
-    }
-    double wgt = Vj * dW;
-    ar += wgt * (vL - vs);
-    double f = wgt * ps;
-    avx += f * ex;
-    avy += f * ey;
-    avz += f * ez;
-    aE += f * vs;
-    double cl = vL - vR;
-    double sp = fmax(ci.y, cj) + (cl > 0.0 ? cl : 0.0);
-    sig = sp > sig ? sp : sig;
+    const double r = sqrt(use ? r2 : 1.0);
+    const double ir = 1.0 / r;
+    const double ex = dx * ir, ey = dy * ir, ez = dz * ir;
+    const double q = r * invH;
+    const double a1 = 1.0 - q;
+    const double dW = -dwc * q * (a1 * a1 * a1);
+    const double vL = (bi.x * ex + bi.y * ey) + bi.z * ez;
+    const double vR = (vxj * ex + vyj * ey) + vzj * ez;
+    const double Zi = ci.x, Pi = bi.w;
+    const double S = Zi + Zj;
+    const bool sok = S != 0.0;
+    const double iS = 1.0 / (sok ? S : 1.0);
+    const double vs = sok ? ((Zi * vL + Zj * vR) + (Pi - Pj)) * iS : 0.5 * (vL + vR);
+    const double ps = sok ? ((Zj * Pi + Zi * Pj) + Zi * Zj * (vL - vR)) * iS : 0.5 * (Pi + Pj);
+    const double wgt = Vj * dW;
+    const double f = wgt * ps;
+    const double cl = vL - vR;
+    const double sp = fmax(ci.y, cj) + (cl > 0.0 ? cl : 0.0);
+    ar = use ? ar + wgt * (vL - vs) : ar;
+    avx = use ? avx + f * ex : avx;
+    avy = use ? avy + f * ey : avy;
+    avz = use ? avz + f * ez : avz;
+    aE = use ? aE + f * vs : aE;
+    sig = (use && sp > sig) ? sp : sig;
 }
 
 constexpr int kU = 2;  // candidates tested per lock-step iteration
@@ -265,66 +265,75 @@ struct Rates64 {
     double ar = 0.0, avx = 0.0, avy = 0.0, avz = 0.0, aE = 0.0, sig = 0.0;
     int qw = 0, qr = 0;
 
+    // every lane pops its next partner, if it has one
     __device__ __forceinline__ void drain() {
-        if (qr < qw) {
-            int e = qj[qr & (kQ - 1)][tid];
-            ++qr;
-            int j = e & 0x7fffffff;
-            bool ghost = e < 0;
-            double4 aj = ld(A, j), bj = ld(B, j);
-            double2 zj = ld(Cz, j);
-            double xj = ghost ? 2.0 * xw - aj.x : aj.x;
-            double dx = xj - a.x, dy = aj.y - a.y, dz = aj.z - a.z;
-            double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
-            double invH = pc.invH, dwc = pc.dwc;
-            if (PAIR) {
-                double H = pc.kappa * (0.5 * (di + dsz[j]));
-                invH = 1.0 / H;
-                double i2 = invH * invH;
-                dwc = (210.0 / M_PI) * (i2 * i2);
-            }
-            pair64(dx, dy, dz, r2, b, zc, ghost ? vw2 - bj.x : bj.x, bj.y, bj.z, bj.w, zj.x, zj.y,
-                   aj.w, invH, dwc, ar, avx, avy, avz, aE, sig);
+        const bool has = qr < qw;
+        const int e = qj[qr & (kQ - 1)][tid];
+        qr += has ? 1 : 0;
+        const int j = has ? (e & 0x7fffffff) : 0;
+        const bool ghost = WALL && e < 0;
+        const double4 aj = ld(A, j), bj = ld(B, j);
+        const double2 zj = ld(Cz, j);
+        const double xj = ghost ? 2.0 * xw - aj.x : aj.x;
+        const double dx = xj - a.x, dy = aj.y - a.y, dz = aj.z - a.z;
+        const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
+        double invH = pc.invH, dwc = pc.dwc;
+        if (PAIR) {
+            const double H = pc.kappa * (0.5 * (di + dsz[j]));
+            invH = 1.0 / H;
+            const double i2 = invH * invH;
+            dwc = (210.0 / M_PI) * (i2 * i2);
         }
+        pair64(has && r2 != 0.0, dx, dy, dz, r2, b, zc, ghost ? vw2 - bj.x : bj.x, bj.y, bj.z,
+               bj.w, zj.x, zj.y, aj.w, invH, dwc, ar, avx, avy, avz, aE, sig);
     }
 
-    // one walk over the stencil: real partners, or mirror partners (GHOST)
+    // one walk over the stencil: real partners, or mirror partners (GHOST).
+    // One flat loop with wave-uniform branches (drain / next row / test a
+    // chunk), so the sums stay in place across iterations.
     template <bool GHOST>
     __device__ __forceinline__ void pass() {
         const bool on = live && (!GHOST || near_wall);
-        for (int oz = -t.R; oz <= t.R; ++oz) {
-            int zz = t.cz + oz;
-            float gz = slab_gap(t.zc, zz);
-            float gz2 = gz * gz;
-            for (int oy = -t.R; oy <= t.R; ++oy) {
-                int j0, len;
-                row_range(cs, g, t, on, t.cy + oy, zz, gz2, j0, len);
-                const int jlast = len > 0 ? j0 + len - 1 : 0;
-                for (int k = 0; __any(k < len); k += kU) {
-                    double4 aj[kU];
-#pragma unroll
-                    for (int u = 0; u < kU; ++u) aj[u] = ld(A, min(j0 + k + u, jlast));
-#pragma unroll
-                    for (int u = 0; u < kU; ++u) {
-                        const int j = j0 + k + u;
-                        double xj = GHOST ? 2.0 * xw - aj[u].x : aj[u].x;
-                        double dx = xj - a.x, dy = aj[u].y - a.y, dz = aj[u].z - a.z;
-                        // exact FP64 membership, no contraction
-                        double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
-                        double H2 = pc.H2;
-                        if (PAIR) {
-                            double H = pc.kappa * (0.5 * (di + ld(dsz, j < jlast ? j : jlast)));
-                            H2 = H * H;
-                        }
-                        const bool acc = (k + u < len) && (GHOST || j != self) && r2 < H2;
-                        // the ring slot qw is free: write always, advance on acceptance
-                        qj[qw & (kQ - 1)][tid] = GHOST ? (j | (int)0x80000000) : j;
-                        qw += acc;
-                    }
-                    // up to kU pushes per iteration: keep every ring at <= kQ - kU
-                    while (__any(qw - qr > kQ - kU)) drain();
-                }
+        int oy = t.R, oz = -t.R - 1;  // advanced to (-R, -R) before the first row
+        int k = 0, j0 = 0, len = 0, jlast = 0;
+        for (;;) {
+            if (__any(qw - qr > kQ - kU)) {  // keep every ring at <= kQ - kU entries
+                drain();
+                continue;
             }
+            if (!__any(k < len)) {
+                if (++oy > t.R) {
+                    oy = -t.R;
+                    if (++oz > t.R) break;
+                }
+                const int zz = t.cz + oz;
+                const float gz = slab_gap(t.zc, zz);
+                row_range(cs, g, t, on, t.cy + oy, zz, gz * gz, j0, len);
+                jlast = len > 0 ? j0 + len - 1 : 0;
+                k = 0;
+                continue;
+            }
+            double4 aj[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) aj[u] = ld(A, min(j0 + k + u, jlast));
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int j = j0 + k + u;
+                double xj = GHOST ? 2.0 * xw - aj[u].x : aj[u].x;
+                double dx = xj - a.x, dy = aj[u].y - a.y, dz = aj[u].z - a.z;
+                // exact FP64 membership, no contraction
+                double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
+                double H2 = pc.H2;
+                if (PAIR) {
+                    double H = pc.kappa * (0.5 * (di + ld(dsz, j < jlast ? j : jlast)));
+                    H2 = H * H;
+                }
+                const bool acc = (k + u < len) && (GHOST || j != self) && r2 < H2;
+                // the ring slot qw is free: write always, advance on acceptance
+                qj[qw & (kQ - 1)][tid] = GHOST ? (j | (int)0x80000000) : j;
+                qw += acc ? 1 : 0;
+            }
+            k += kU;
         }
     }
 };
@@ -397,43 +406,38 @@ __global__ __launch_bounds__(kBlock) void k_rates64(int64_t n, const double4 *__
 
 // ---------------------------------------------------------------- mixed rates (FP32 pairs)
 
-__device__ __forceinline__ void pair32(float dx, float dy, float dz, float r2, const float4 &bi,
-                                       const float4 &ci, float vxj, float vyj, float vzj,
-                                       float Pj, float Zj, float cj, float Vj, float invH,
-                                       float dwc, float &ar, float &avx, float &avy, float &avz,
-                                       float &aE, float &sig) {
+__device__ __forceinline__ void pair32(bool use, float dx, float dy, float dz, float r2,
+                                       const float4 &bi, const float4 &ci, float vxj, float vyj,
+                                       float vzj, float Pj, float Zj, float cj, float Vj,
+                                       float invH, float dwc, float &ar, float &avx, float &avy,
+                                       float &avz, float &aE, float &sig) {
 #pragma clang fp contract(fast)
-    if (r2 == 0.0f) return;
-    float ir = __builtin_amdgcn_rsqf(r2);
-    float r = r2 * ir;
-    float ex = dx * ir, ey = dy * ir, ez = dz * ir;
-    float q = r * invH;
-    float a1 = 1.0f - q;
-    float dW = -dwc * q * (a1 * a1 * a1);
+    const float ir = __builtin_amdgcn_rsqf(use ? r2 : 1.0f);
+    const float r = r2 * ir;
+    const float ex = dx * ir, ey = dy * ir, ez = dz * ir;
+    const float q = r * invH;
+    const float a1 = 1.0f - q;
+    const float dW = -dwc * q * (a1 * a1 * a1);
     // v_L - v_R from the velocity difference (no cancellation of bulk motion)
-    float vrel = ((bi.x - vxj) * ex + (bi.y - vyj) * ey) + (bi.z - vzj) * ez;
-    float vL = (bi.x * ex + bi.y * ey) + bi.z * ez;
-    float Zi = ci.x, Pi = bi.w;
-    float S = Zi + Zj;
-    float dvl, ps;  // v_L - v*, P*
-    if (S != 0.0f) {
-        float iS = __builtin_amdgcn_rcpf(S);
-        dvl = (Zj * vrel - (Pi - Pj)) * iS;
-        ps = ((Zj * Pi + Zi * Pj) + Zi * Zj * vrel) * iS;
-    } else {
-        dvl = 0.5f * vrel;
-        ps = 0.5f * (Pi + Pj);
-    }
-    float vs = vL - dvl;
-    float wgt = Vj * dW;
-    ar += wgt * dvl;
-    float f = wgt * ps;
-    avx += f * ex;
-    avy += f * ey;
-    avz += f * ez;
-    aE += f * vs;
-    float sp = fmaxf(ci.y, cj) + (vrel > 0.0f ? vrel : 0.0f);
-    sig = sp > sig ? sp : sig;
+    const float vrel = ((bi.x - vxj) * ex + (bi.y - vyj) * ey) + (bi.z - vzj) * ez;
+    const float vL = (bi.x * ex + bi.y * ey) + bi.z * ez;
+    const float Zi = ci.x, Pi = bi.w;
+    const float S = Zi + Zj;
+    const bool sok = S != 0.0f;
+    const float iS = __builtin_amdgcn_rcpf(sok ? S : 1.0f);
+    // v_L - v*, P*
+    const float dvl = sok ? (Zj * vrel - (Pi - Pj)) * iS : 0.5f * vrel;
+    const float ps = sok ? ((Zj * Pi + Zi * Pj) + Zi * Zj * vrel) * iS : 0.5f * (Pi + Pj);
+    const float vs = vL - dvl;
+    const float wgt = Vj * dW;
+    const float f = wgt * ps;
+    const float sp = fmaxf(ci.y, cj) + fmaxf(vrel, 0.0f);
+    ar = use ? ar + wgt * dvl : ar;
+    avx = use ? avx + f * ex : avx;
+    avy = use ? avy + f * ey : avy;
+    avz = use ? avz + f * ez : avz;
+    aE = use ? aE + f * vs : aE;
+    sig = (use && sp > sig) ? sp : sig;
 }
 
 // Candidates whose FP32 squared distance lies within this relative band of
@@ -464,80 +468,87 @@ struct Rates32 {
     float ar = 0.f, avx = 0.f, avy = 0.f, avz = 0.f, aE = 0.f, sig = 0.f;
     int qw = 0, qr = 0, cnt = 0;
 
+    // every lane pops its next partner, if it has one
     __device__ __forceinline__ void drain() {
-        if (qr < qw) {
-            float4 q = qd[qr & (kQ - 1)][tid];
-            ++qr;
-            int e = __float_as_int(q.w);
-            int j = e & 0x7fffffff;
-            bool ghost = e < 0;
-            float4 bj = ld(B, j), cj = ld(Cz, j);
-            float invH = (float)pc.invH, dwc = (float)pc.dwc;
-            float H2lo = lo;
-            double H2d = pc.H2;
-            if (PAIR) {
-                double H = pc.kappa * (0.5 * (di + dsz[j]));
-                H2d = H * H;
-                H2lo = (float)H2d * (1.0f - kBand);
-                invH = (float)(1.0 / H);
-                float i2 = invH * invH;
-                dwc = (float)(210.0 / M_PI) * (i2 * i2);
-            }
-            float r2 = (q.x * q.x + q.y * q.y) + q.z * q.z;
-            bool in = true;
-            if (!(r2 < H2lo)) {
-                // near the support: decide membership in FP64 (rare)
-                double xj = ghost ? 2.0 * xw - xs[j] : xs[j];
-                double ex = xj - xi, ey = ys[j] - yi, ez = zs[j] - zi;
-                in = ((ex * ex) + (ey * ey)) + (ez * ez) < H2d;
-            }
-            if (in) {
-                if (!ghost) ++cnt;
-                pair32(q.x, q.y, q.z, r2, b, c, ghost ? vw2 - bj.x : bj.x, bj.y, bj.z, bj.w,
-                       cj.x, cj.y, cj.z, invH, dwc, ar, avx, avy, avz, aE, sig);
-            }
+        const bool has = qr < qw;
+        const float4 q = qd[qr & (kQ - 1)][tid];
+        qr += has ? 1 : 0;
+        const int e = __float_as_int(q.w);
+        const int j = has ? (e & 0x7fffffff) : 0;
+        const bool ghost = WALL && e < 0;
+        const float4 bj = ld(B, j), cj = ld(Cz, j);
+        float invH = (float)pc.invH, dwc = (float)pc.dwc;
+        float H2lo = lo;
+        double H2d = pc.H2;
+        if (PAIR) {
+            const double H = pc.kappa * (0.5 * (di + dsz[j]));
+            H2d = H * H;
+            H2lo = (float)H2d * (1.0f - kBand);
+            invH = (float)(1.0 / H);
+            const float i2 = invH * invH;
+            dwc = (float)(210.0 / M_PI) * (i2 * i2);
         }
+        const float r2 = (q.x * q.x + q.y * q.y) + q.z * q.z;
+        bool in = has && r2 < H2lo;
+        if (has && !(r2 < H2lo)) {
+            // near the support: decide membership in FP64 (rare)
+            const double xj = ghost ? 2.0 * xw - xs[j] : xs[j];
+            const double ex = xj - xi, ey = ys[j] - yi, ez = zs[j] - zi;
+            in = ((ex * ex) + (ey * ey)) + (ez * ez) < H2d;
+        }
+        cnt += (in && !ghost) ? 1 : 0;
+        pair32(in && r2 != 0.0f, q.x, q.y, q.z, r2, b, c, ghost ? vw2 - bj.x : bj.x, bj.y,
+               bj.z, bj.w, cj.x, cj.y, cj.z, invH, dwc, ar, avx, avy, avz, aE, sig);
     }
 
+    // flat loop as in the FP64 kernel
     template <bool GHOST>
     __device__ __forceinline__ void pass() {
 #pragma clang fp contract(fast)
         const bool on = live && (!GHOST || near_wall);
-        for (int oz = -t.R; oz <= t.R; ++oz) {
-            int zz = t.cz + oz;
-            const float sz = (float)oz * Df;
-            float gz = slab_gap(t.zc, zz);
-            float gz2 = gz * gz;
-            for (int oy = -t.R; oy <= t.R; ++oy) {
-                const float sy = (float)oy * Df;
-                int j0, len;
-                row_range(cs, g, t, on, t.cy + oy, zz, gz2, j0, len);
-                const int jlast = len > 0 ? j0 + len - 1 : 0;
-                const float ay = a.y - sy, az = a.z - sz;
-                for (int k = 0; __any(k < len); k += kU) {
-                    float4 aj[kU];
-#pragma unroll
-                    for (int u = 0; u < kU; ++u) aj[u] = ld(A, min(j0 + k + u, jlast));
-#pragma unroll
-                    for (int u = 0; u < kU; ++u) {
-                        const int j = j0 + k + u;
-                        float dx = (aj[u].x + (aj[u].w - cxf) * Df) - a.x;
-                        float dy = aj[u].y - ay, dz = aj[u].z - az;
-                        if (GHOST) dx = 2.0f * wd - dx;
-                        float r2 = (dx * dx + dy * dy) + dz * dz;
-                        float hj = hi;
-                        if (PAIR) {
-                            double H = pc.kappa * (0.5 * (di + ld(dsz, j < jlast ? j : jlast)));
-                            hj = (float)(H * H) * (1.0f + kBand);
-                        }
-                        const bool acc = (k + u < len) && (GHOST || j != self) && r2 < hj;
-                        qd[qw & (kQ - 1)][tid] = make_float4(
-                            dx, dy, dz, __int_as_float(GHOST ? (j | (int)0x80000000) : j));
-                        qw += acc;
-                    }
-                    while (__any(qw - qr > kQ - kU)) drain();
-                }
+        int oy = t.R, oz = -t.R - 1;
+        int k = 0, j0 = 0, len = 0, jlast = 0;
+        float ay = 0.f, az = 0.f;
+        for (;;) {
+            if (__any(qw - qr > kQ - kU)) {
+                drain();
+                continue;
             }
+            if (!__any(k < len)) {
+                if (++oy > t.R) {
+                    oy = -t.R;
+                    if (++oz > t.R) break;
+                }
+                const int zz = t.cz + oz;
+                const float gz = slab_gap(t.zc, zz);
+                row_range(cs, g, t, on, t.cy + oy, zz, gz * gz, j0, len);
+                jlast = len > 0 ? j0 + len - 1 : 0;
+                ay = a.y - (float)oy * Df;
+                az = a.z - (float)oz * Df;
+                k = 0;
+                continue;
+            }
+            float4 aj[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) aj[u] = ld(A, min(j0 + k + u, jlast));
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int j = j0 + k + u;
+                float dx = (aj[u].x + (aj[u].w - cxf) * Df) - a.x;
+                float dy = aj[u].y - ay, dz = aj[u].z - az;
+                if (GHOST) dx = 2.0f * wd - dx;
+                float r2 = (dx * dx + dy * dy) + dz * dz;
+                float hj = hi;
+                if (PAIR) {
+                    double H = pc.kappa * (0.5 * (di + ld(dsz, j < jlast ? j : jlast)));
+                    hj = (float)(H * H) * (1.0f + kBand);
+                }
+                const bool acc = (k + u < len) && (GHOST || j != self) && r2 < hj;
+                qd[qw & (kQ - 1)][tid] = make_float4(
+                    dx, dy, dz, __int_as_float(GHOST ? (j | (int)0x80000000) : j));
+                qw += acc ? 1 : 0;
+            }
+            k += kU;
         }
     }
 };
