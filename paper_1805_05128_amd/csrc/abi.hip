@@ -188,7 +188,9 @@ static PairConst pair_const(const csph_params *p, double dmax) {
     return c;
 }
 
-static GridDev grid_dev(const csph_grid &g) {
+// slab = false: the plain linear cell key (the key csph_bin reports);
+// slab = true: the y-slab order the internal passes sort by.
+static GridDev grid_dev(const csph_grid &g, bool slab = true) {
     GridDev d;
     d.ox = g.origin[0];
     d.oy = g.origin[1];
@@ -199,6 +201,23 @@ static GridDev grid_dev(const csph_grid &g) {
     d.dy = g.dims[1];
     d.dz = g.dims[2];
     d.reach = g.reach;
+    const uint32_t dx = (uint32_t)d.dx, dy = (uint32_t)d.dy, dz = (uint32_t)d.dz;
+    if (slab && dy > (1u << kSlabShift)) {
+        const uint32_t rows = 1u << kSlabShift;
+        d.ysh = kSlabShift;
+        d.ymask = (int)rows - 1;
+        d.nfull = (int)(dy >> kSlabShift);
+        d.sZf = rows * dx;
+        d.sZr = (dy & (rows - 1)) * dx;
+        d.sY = dz * rows * dx;
+    } else {
+        d.ysh = 31;
+        d.ymask = 0x7fffffff;
+        d.nfull = 1;
+        d.sZf = dy * dx;
+        d.sZr = d.sZf;
+        d.sY = 0;
+    }
     return d;
 }
 
@@ -303,7 +322,7 @@ csph_status csph_bin(const double *x, const double *y, const double *z, int64_t 
     ws_layout(&w, ws, n, ncell);
     hipStream_t st = (hipStream_t)stream;
     ProfScope pb(CSPH_PROF_BIN, st);
-    CSPH_HIP(launch_bin(x, y, z, n, grid_dev(*grid), w, perm, key, cell_start, st));
+    CSPH_HIP(launch_bin(x, y, z, n, grid_dev(*grid, false), w, perm, key, cell_start, st));
     return CSPH_OK;
 }
 

@@ -17,6 +17,8 @@ constexpr int kReduceBlocks = 1024;   // partial-reduction blocks (bounds, total
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kMaxSites = 1024;       // Voronoi generators held in LDS (36 B each)
+constexpr int kXcd = 8;               // accelerator dies; workgroups go to them round robin
+constexpr int kSlabShift = 4;         // cell order: y-slabs of 16 rows (see cell_key)
 
 // Mesh as the kernels see it.
 struct GridDev {
@@ -25,7 +27,31 @@ struct GridDev {
     double cell;        // D
     int dx, dy, dz;     // dims
     int reach;          // stencil half-width
+    // cell order (cell_key): y-slabs of 2^ysh rows, z, then y in slab, then x
+    int ysh, ymask, nfull;      // slab shift and mask; number of full slabs
+    uint32_t sY, sZf, sZr;      // slab stride; z stride in a full / the last slab
 };
+
+// Key of cell (cx, cy, cz).  The mesh is cut along y into slabs of 2^ysh
+// rows (the last one may be shorter); slabs come one after another, and in a
+// slab the cells are ordered by z, then y, then x.  x is fastest, so a
+// stencil row (fixed y, z) is one contiguous key range, while consecutive
+// keys stay within a slab a few rows thick: the stencil neighbourhood of a
+// stretch of particles is small.  With a single slab (ysh >= 31) this is the
+// plain linear key (cz * dy + cy) * dx + cx.  Keys cover [0, dx*dy*dz).
+__host__ __device__ __forceinline__ uint32_t cell_key(const GridDev &g, int cx, int cy, int cz) {
+    const int sl = cy >> g.ysh;
+    return (uint32_t)sl * g.sY + (uint32_t)cz * (sl < g.nfull ? g.sZf : g.sZr) +
+           (uint32_t)(cy & g.ymask) * (uint32_t)g.dx + (uint32_t)cx;
+}
+
+// Workgroups are handed to the dies round robin.  Renumber them so that die
+// k runs one contiguous stretch of workgroups (its L2 then holds the stencil
+// neighbourhood of one stretch of cells instead of pieces of all of them).
+__device__ __forceinline__ int64_t xcd_block(unsigned b, unsigned nb) {
+    const unsigned x = b % kXcd, t = b / kXcd, q = nb / kXcd, r = nb % kXcd;
+    return (int64_t)x * q + (x < r ? x : r) + t;
+}
 
 // Per-call constants of the pair interaction.
 struct PairConst {

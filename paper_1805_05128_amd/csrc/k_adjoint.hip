@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
             for (int oy = -R; oy <= R; ++oy) {
                 int yy = cy + oy;
                 if (yy < 0 || yy >= g.dy) continue;
-                int row = (zz * g.dy + yy) * g.dx;
+                int row = (int)cell_key(g, 0, yy, zz);
                 int j0 = cs[row + x0], j1 = cs[row + x1 + 1];
                 for (int j = j0; j < j1; ++j) {
                     if (j == (int)s) continue;

@@ -200,7 +200,7 @@ __global__ __launch_bounds__(kBlock) void k_keys(const double *__restrict__ x,
     int cx = cell_coord(x[i], g.ox, g.inv, g.dx);
     int cy = cell_coord(y[i], g.oy, g.inv, g.dy);
     int cz = cell_coord(z[i], g.oz, g.inv, g.dz);
-    uint32_t k = ((uint32_t)cz * (uint32_t)g.dy + (uint32_t)cy) * (uint32_t)g.dx + (uint32_t)cx;
+    uint32_t k = cell_key(g, cx, cy, cz);
     key[i] = k;
     rank[i] = (uint32_t)atomicAdd(&count[k], 1);
     if (key_out) key_out[i] = k;

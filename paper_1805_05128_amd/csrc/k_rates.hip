@@ -195,7 +195,7 @@ __device__ __forceinline__ void row_range(const int32_t *__restrict__ cs, const 
     const int xa = max(max((int)floorf(t.xc - hw), t.cx - t.R), 0);
     const int xb = min(min((int)floorf(t.xc + hw), t.cx + t.R), g.dx - 1);
     const bool ok = inb && rem > 0.0f && xb >= xa;
-    const int row = (zz * g.dy + yy) * g.dx;
+    const int row = (int)cell_key(g, 0, yy, zz);
     const int ia = ok ? row + xa : 0, ib = ok ? row + xb + 1 : 0;
     j0 = cs[ia];
     len = cs[ib] - j0;
@@ -358,7 +358,7 @@ __global__ __launch_bounds__(kBlock) void k_rates64(int64_t n, const double4 *__
     k.pc = pc;
     k.qj = qj;
     k.tid = threadIdx.x;
-    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     k.self = (int)s;
     k.live = s < n;
     k.a = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -579,7 +579,7 @@ __global__ __launch_bounds__(kBlock) void k_rates32(int64_t n, const float4 *__r
     k.pc = pc;
     k.qd = qd;
     k.tid = threadIdx.x;
-    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     k.self = (int)s;
     k.live = s < n;
     k.a = make_float4(0.f, 0.f, 0.f, 0.f);

@@ -42,8 +42,26 @@ def relmax(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-def test_rates_vjp_matches_autograd():
-    w = system()
+def slab_system(seed=8):
+    """5 x 24 x 5 block on unit cells (24 cell rows): the internal y-slab cell order
+    has a full 16-row slab and a short one."""
+    w = ci.jittered_block(5, 24, 5, seed=seed, amp=0.05)
+    rng = np.random.default_rng(seed)
+    w.vx = rng.uniform(-0.3, 0.3, w.n)
+    w.vy = rng.uniform(-0.3, 0.3, w.n)
+    w.vz = rng.uniform(-0.3, 0.3, w.n)
+    w.rho = rng.uniform(0.8, 1.3, w.n)
+    w.p = rng.uniform(0.5, 1.5, w.n)
+    w.m = w.rho.copy()
+    w.mat = (w.y > 12).astype(np.int32)
+    w.eos = [(0, 1.4, 0.0), (1, 3.0, 0.4)]
+    w.cell_size = 1.0
+    return w
+
+
+@pytest.mark.parametrize("make", [system, slab_system], ids=["block", "slab"])
+def test_rates_vjp_matches_autograd(make):
+    w = make()
     params = P.Params.from_workload(w)
     g = P.state_from_workload(w, params, DEV)
     s = {k: g[k].cpu().numpy() for k in F8}

@@ -47,8 +47,18 @@ def two_material_cloud(n=3000, seed=11):
     return w
 
 
+def slab_cloud(n=2600, seed=21):
+    """Random cloud stretched along y (8 x 40 x 8) on unit cells: 40 cell rows, so
+    the internal cell order has two full 16-row y-slabs and a short last one."""
+    w = ci.random_cloud(n, seed=seed, box=8.0, vmax=0.5)
+    w.y = w.y * 5.0
+    w.cell_size = 1.0
+    return w
+
+
 CASES = {
     "sod16": ci.config0,
+    "slab": slab_cloud,
     "cloud2mat": two_material_cloud,
     "wall": wall_block,
     "ragged": lambda: ci.random_cloud(777, seed=3, box=7.3, vmax=1.0),
@@ -265,7 +275,7 @@ def _check_totals(tot_gpu, s_ref):
 
 
 @pytest.mark.parametrize("reorder", [False, True])
-@pytest.mark.parametrize("case", ["sod16", "wall", "cloud2mat"])
+@pytest.mark.parametrize("case", ["sod16", "wall", "cloud2mat", "slab"])
 def test_step_fp64(case, reorder):
     w = CASES[case]()
     _print_case(f"{case} reorder={reorder}", w)
