@@ -224,6 +224,56 @@ csph_status voronoi_assign(const double *x, const double *y, const double *z, in
                            int32_t *owner, int64_t *site_particles, int64_t *site_pairs,
                            csph_stream stream);
 
+/* Voronoi load balancer (sec. 3).  Generators, centres: K x 3 row-major
+ * FP64 (device); 1 <= K <= 512.  Adjacency: K rows of W = ceil(K/32)
+ * uint32 words; bit (l % 32) of word [k W + l/32] set iff subdomains k and l
+ * touch. */
+typedef struct {
+    double sigma;  /* weight of the three-body terms, eq. BalancingOffsetPlusRot */
+    double theta;  /* weight of the material motion, eq. TotalOffset (0.25 in sec. 3.4) */
+    double gamma;  /* scale of the balancing displacement, eq. TotalOffset */
+    double dsh;    /* D^sh: half width of the exchange layer; length factor of the two-body
+                      terms, cap of the three-body shift (sec. 3.2, 3.3) */
+} csph_balance_params;
+
+/* Workspace bytes csph_balance_stats needs for K generators. */
+size_t csph_balance_workspace_size(int32_t K);
+
+/* Subdomain statistics of the assignment owner[] (from voronoi_assign with
+ * these generators; entries outside [0, K) are ignored):
+ *   site_particles[k], site_pairs[k] (sum of nbr_count, optional, needs nbr_count);
+ *   centre[k] = mean position of the particles owned by k (eq. VoronoiGeomCenters;
+ *     the generator itself if there are none).  Exact fixed-point sums
+ *     (resolution 2^-32 per coordinate, |x - g_k| < 2^31), deterministic;
+ *   adjacency: k and l touch when some particle owned by one of them has the
+ *     other as its nearest other generator (ties to the smaller index) and
+ *     lies within dsh of their bisector plane, tested as
+ *     (d2_l - d2_k)^2 < (4 dsh^2) |g_l - g_k|^2 in FP64 without contraction;
+ *     bit-exact.
+ * Asynchronous; ws from csph_balance_workspace_size (CSPH_ECAPACITY and
+ * *ws_needed if too small). */
+csph_status csph_balance_stats(const double *x, const double *y, const double *z, int64_t n,
+                               const int32_t *owner, const int32_t *nbr_count,
+                               const double *sites, int32_t K, double dsh,
+                               int64_t *site_particles, int64_t *site_pairs, double *centre,
+                               uint32_t *adjacency, void *ws, size_t ws_bytes, size_t *ws_needed,
+                               csph_stream stream);
+
+/* One generator move: loads[k] (particles or pairs) drive
+ *   dg_k = (1 - sigma) sum_l dsh (L_k - L_l)/(L_k + L_l) (g_k - g_l)/|g_k - g_l|
+ *        + sigma C( sum_{l<m} [M(c_k x c_m, a_m) M(c_k x c_l, a_l) c_k - c_k] ),
+ * over touching l and mutually touching triplets (k, l, m), c_p = g_p - o_klm
+ * (circumcentre), a_l = (pi/3)(L_l - L_k)/(L_k + L_l + L_m), C caps the
+ * length at dsh (eqs. BalancingOffset, BalancingOffsetPlusRot,
+ * BalancingOffsetRot); then g_k' = (1 - theta)(g_k + gamma dg_k) + theta centre_k
+ * (eq. TotalOffset).  sites_out must not alias sites.  *move_sum (device) =
+ * sum_k |g_k' - g_k| (eq. VDConvergence).  Zero-load pairs/triplets and
+ * collinear triplets contribute nothing.  Asynchronous. */
+csph_status csph_balance_move(const double *sites, int32_t K, const int64_t *loads,
+                              const double *centre, const uint32_t *adjacency,
+                              const csph_balance_params *bp, double *sites_out, double *move_sum,
+                              csph_stream stream);
+
 /* Specific total energy from the primitive state: e from the EOS inverse
  * (ideal: e = p/((gamma-1) rho); stiffened: e = (p + gamma P_inf)/((gamma-1) rho)),
  * E = e + |v|^2/2. */
@@ -282,7 +332,8 @@ csph_status csph_init_energy_vjp(const double *rho, const double *pres, const do
 #define CSPH_PROF_REORDER 5    /* return to input order */
 #define CSPH_PROF_NEIGHBORS 6
 #define CSPH_PROF_ADJOINT 7
-#define CSPH_PROF_GROUPS 8
+#define CSPH_PROF_BALANCE 8    /* balancer statistics and generator moves */
+#define CSPH_PROF_GROUPS 9
 typedef struct {
     int64_t launches[CSPH_PROF_GROUPS];
     double ms[CSPH_PROF_GROUPS];

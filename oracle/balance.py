@@ -67,12 +67,16 @@ def stats(x, y, z, owner, sites, dsh, nbr_count=None):
     """Per-subdomain statistics of the current assignment ``owner``.
 
     Returns dict(particles int64 [K], pairs int64 [K], centre float64 [K, 3],
-    adjacency bool [K, K]).
+    adjacency bool [K, K]).  Owners outside [0, K) are ignored.
     """
     x, y, z = (np.asarray(a, np.float64) for a in (x, y, z))
     owner = np.asarray(owner, np.int64)
     sites = np.asarray(sites, np.float64).reshape(-1, 3)
     K = sites.shape[0]
+    ok = (owner >= 0) & (owner < K)          # other entries are ignored
+    if not ok.all():
+        x, y, z, owner = x[ok], y[ok], z[ok], owner[ok]
+        nbr_count = None if nbr_count is None else np.asarray(nbr_count)[ok]
     n = x.shape[0]
     parts = np.bincount(owner, minlength=K).astype(np.int64)
     pairs = np.zeros(K, np.int64)

@@ -5,5 +5,6 @@ from .api import (EOS_IDEAL, EOS_STIFFENED, Params, State, StepScalars, Workspac
                   csph_bin, csph_grid_build, csph_init_energy, csph_neighbors, csph_rates,
                   csph_step, default_workspace, profile_enable, profile_read, state_from_workload, version, voronoi_assign,
                   workspace_size, csph_rates_vjp, csph_step_vjp, csph_init_energy_vjp,
-                  zeros_grad, GRAD_FIELDS)
+                  zeros_grad, GRAD_FIELDS, BalanceParams, csph_balance_stats,
+                  csph_balance_move, adjacency_matrix)
 from .autograd import CSPHRollout, rollout  # noqa: F401

@@ -59,11 +59,17 @@ class CsphGrad(C.Structure):
     _fields_ = [(k, _dp) for k in ("x", "y", "z", "vx", "vy", "vz", "rho", "E")]
 
 
-PROF_GROUPS = ("bin", "pack", "rates", "integrate", "voronoi", "reorder", "neighbors", "adjoint")
+PROF_GROUPS = ("bin", "pack", "rates", "integrate", "voronoi", "reorder", "neighbors", "adjoint",
+               "balance")
 
 
 class CsphProfile(C.Structure):
-    _fields_ = [("launches", C.c_int64 * 8), ("ms", C.c_double * 8)]
+    _fields_ = [("launches", C.c_int64 * len(PROF_GROUPS)), ("ms", C.c_double * len(PROF_GROUPS))]
+
+
+class CsphBalanceParams(C.Structure):
+    _fields_ = [("sigma", C.c_double), ("theta", C.c_double), ("gamma", C.c_double),
+                ("dsh", C.c_double)]
 
 
 _lib = None
@@ -126,6 +132,14 @@ def load():
     L.csph_init_energy_vjp.argtypes = [_dp, _dp, _dp, _dp, _dp, _ip, C.c_int64,
                                        C.POINTER(CsphParams), _dp, _dp, _dp, _dp, _dp, _dp, vp,
                                        sz, szp, vp]
+    L.csph_balance_workspace_size.restype = sz
+    L.csph_balance_workspace_size.argtypes = [C.c_int32]
+    L.csph_balance_stats.restype = C.c_int32
+    L.csph_balance_stats.argtypes = [_dp, _dp, _dp, C.c_int64, _ip, _ip, _dp, C.c_int32,
+                                     C.c_double, _lp, _lp, _dp, _up, vp, sz, szp, vp]
+    L.csph_balance_move.restype = C.c_int32
+    L.csph_balance_move.argtypes = [_dp, C.c_int32, _lp, _dp, _up, C.POINTER(CsphBalanceParams),
+                                    _dp, _dp, vp]
     L.csph_profile_enable.restype = C.c_int32
     L.csph_profile_enable.argtypes = [C.c_int32]
     L.csph_profile_read.restype = C.c_int32

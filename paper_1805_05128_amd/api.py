@@ -429,3 +429,75 @@ def state_from_workload(w, params: Params, device="cuda", with_id=True) -> State
     t["E"] = csph_init_energy(t["rho"], p, t["vx"], t["vy"], t["vz"], mat, params)
     ids = torch.arange(t["x"].shape[0], dtype=torch.int64, device=device) if with_id else None
     return State(t, mat, None, ids)
+
+
+# ------------------------------------------------------------------ Voronoi balancer
+
+@dataclass
+class BalanceParams:
+    """Weights of the generator move (eqs. BalancingOffsetPlusRot and TotalOffset)."""
+    sigma: float = 0.5    # three-body weight
+    theta: float = 0.25   # material-motion weight
+    gamma: float = 1.0    # balancing-displacement scale
+    dsh: float = 3.0      # D^sh, exchange-layer half width
+    load: str = "pairs"   # "pairs" (site_pairs) or "particles" (site_particles)
+
+    def c(self) -> N.CsphBalanceParams:
+        return N.CsphBalanceParams(float(self.sigma), float(self.theta), float(self.gamma),
+                                   float(self.dsh))
+
+
+def _u32p(t):
+    if t is not None:
+        assert t.dtype == torch.int32 and t.is_contiguous() and t.is_cuda
+    return _ptr(t, C.c_uint32)
+
+
+def adjacency_matrix(bits: torch.Tensor, K: int) -> torch.Tensor:
+    """Unpack the K x ceil(K/32) word bit matrix into a bool [K, K] tensor (host copy)."""
+    w = bits.view(K, -1).cpu().to(torch.int64) & 0xFFFFFFFF
+    cols = torch.arange(K)
+    return ((w[:, cols // 32] >> (cols % 32)) & 1).bool()
+
+
+def csph_balance_stats(x, y, z, owner, sites: torch.Tensor, dsh: float,
+                       nbr_count: Optional[torch.Tensor] = None, ws: Optional[Workspace] = None,
+                       stream=None) -> Dict[str, torch.Tensor]:
+    """Loads, centres and the touching-subdomain bit matrix of the assignment ``owner``.
+
+    Returns dict(particles int64 [K], pairs int64 [K] or None, centre float64 [K, 3],
+    adjacency int32 [K, ceil(K/32)] (uint32 bit words)).
+    """
+    L = N.load()
+    ws = ws or default_workspace(x.device)
+    sites = sites.to(torch.float64).contiguous()
+    K = sites.shape[0]
+    n = x.shape[0]
+    dev = x.device
+    out = dict(particles=torch.empty(K, dtype=torch.int64, device=dev),
+               pairs=torch.empty(K, dtype=torch.int64, device=dev) if nbr_count is not None else None,
+               centre=torch.empty(K, 3, dtype=torch.float64, device=dev),
+               adjacency=torch.empty(K, (K + 31) // 32, dtype=torch.int32, device=dev))
+    _with_ws(lambda p, b, nd: L.csph_balance_stats(
+        _dp(x), _dp(y), _dp(z), n, _ip(owner), _ip(nbr_count), _dp(sites), K, float(dsh),
+        _lp(out["particles"]), _lp(out["pairs"]), _dp(out["centre"]), _u32p(out["adjacency"]),
+        p, b, nd, _stream(stream)), ws, "csph_balance_stats")
+    return out
+
+
+def csph_balance_move(sites: torch.Tensor, stats: Dict[str, torch.Tensor], bp: BalanceParams,
+                      stream=None):
+    """One generator move from ``csph_balance_stats`` output: (new sites [K, 3], move_sum [1])."""
+    L = N.load()
+    sites = sites.to(torch.float64).contiguous()
+    K = sites.shape[0]
+    loads = stats["pairs"] if (bp.load == "pairs" and stats.get("pairs") is not None) \
+        else stats["particles"]
+    new = torch.empty_like(sites)
+    ms = torch.empty(1, dtype=torch.float64, device=sites.device)
+    p = bp.c()
+    st = L.csph_balance_move(_dp(sites), K, _lp(loads.contiguous()), _dp(stats["centre"]),
+                             _u32p(stats["adjacency"]), C.byref(p), _dp(new), _dp(ms),
+                             _stream(stream))
+    N.check(st, "csph_balance_move")
+    return new, ms

@@ -516,6 +516,51 @@ csph_status voronoi_assign(const double *x, const double *y, const double *z, in
     return CSPH_OK;
 }
 
+size_t csph_balance_workspace_size(int32_t K) {
+    return K < 1 ? 0 : balance_ws_bytes(K);
+}
+
+csph_status csph_balance_stats(const double *x, const double *y, const double *z, int64_t n,
+                               const int32_t *owner, const int32_t *nbr_count,
+                               const double *sites, int32_t K, double dsh,
+                               int64_t *site_particles, int64_t *site_pairs, double *centre,
+                               uint32_t *adjacency, void *ws, size_t ws_bytes, size_t *ws_needed,
+                               csph_stream stream) {
+    g_err[0] = 0;
+    if (n < 0 || K < 1 || K > kMaxBalanceSites || !sites || !site_particles || !centre ||
+        !adjacency || (n > 0 && (!x || !y || !z || !owner)))
+        return fail(CSPH_EINVAL, "bad arguments (1 <= K <= %d)", kMaxBalanceSites);
+    if (site_pairs && !nbr_count) return fail(CSPH_EINVAL, "site_pairs needs nbr_count");
+    if (!(dsh >= 0.0) || !std::isfinite(dsh)) return fail(CSPH_EINVAL, "dsh must be finite and >= 0");
+    const size_t need = balance_ws_bytes(K);
+    if (ws_needed) *ws_needed = need;
+    if (!ws || ws_bytes < need) return fail(CSPH_ECAPACITY, "workspace needs %zu bytes", need);
+    ProfScope pr(CSPH_PROF_BALANCE, (hipStream_t)stream);
+    CSPH_HIP(launch_balance_stats(x, y, z, n, owner, site_pairs ? nbr_count : nullptr, sites, K,
+                                  dsh, site_particles, site_pairs, centre, adjacency, ws,
+                                  (hipStream_t)stream));
+    return CSPH_OK;
+}
+
+csph_status csph_balance_move(const double *sites, int32_t K, const int64_t *loads,
+                              const double *centre, const uint32_t *adjacency,
+                              const csph_balance_params *bp, double *sites_out, double *move_sum,
+                              csph_stream stream) {
+    g_err[0] = 0;
+    if (K < 1 || K > kMaxBalanceSites || !sites || !loads || !centre || !adjacency || !bp ||
+        !sites_out || !move_sum)
+        return fail(CSPH_EINVAL, "bad arguments (1 <= K <= %d)", kMaxBalanceSites);
+    if (sites_out == sites) return fail(CSPH_EINVAL, "sites_out must not alias sites");
+    const double v[4] = {bp->sigma, bp->theta, bp->gamma, bp->dsh};
+    for (double a : v)
+        if (!std::isfinite(a)) return fail(CSPH_EINVAL, "balance parameters must be finite");
+    if (bp->dsh < 0.0) return fail(CSPH_EINVAL, "dsh must be >= 0");
+    ProfScope pr(CSPH_PROF_BALANCE, (hipStream_t)stream);
+    CSPH_HIP(launch_balance_move(sites, K, loads, centre, adjacency, bp->sigma, bp->theta,
+                                 bp->gamma, bp->dsh, sites_out, move_sum, (hipStream_t)stream));
+    return CSPH_OK;
+}
+
 csph_status csph_init_energy(const double *rho, const double *pres, const double *vx,
                              const double *vy, const double *vz, const int32_t *mat, int64_t n,
                              const csph_params *p, double *E, csph_stream stream) {

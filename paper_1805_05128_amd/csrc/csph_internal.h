@@ -17,6 +17,7 @@ constexpr int kReduceBlocks = 1024;   // partial-reduction blocks (bounds, total
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kMaxSites = 1024;       // Voronoi generators held in LDS (36 B each)
+constexpr int kMaxBalanceSites = 512; // balancer generators held in LDS (84 B each)
 constexpr int kXcd = 8;               // accelerator dies; workgroups go to them round robin
 constexpr int kSlabShift = 4;         // cell order: y-slabs of 16 rows (see cell_key)
 
@@ -167,6 +168,16 @@ hipError_t launch_init_energy_vjp(const double *rho, const double *pres, const d
                                   double *part, hipStream_t st);
 
 // k_voronoi.hip
+size_t balance_ws_bytes(int K);
+hipError_t launch_balance_stats(const double *x, const double *y, const double *z, int64_t n,
+                                const int32_t *owner, const int32_t *nbr_count,
+                                const double *sites, int K, double dsh, int64_t *site_particles,
+                                int64_t *site_pairs, double *centre, uint32_t *adj, void *ws,
+                                hipStream_t st);
+hipError_t launch_balance_move(const double *sites, int K, const int64_t *loads,
+                               const double *centre, const uint32_t *adj, double sigma,
+                               double theta, double gamma, double dsh, double *out,
+                               double *move_sum, hipStream_t st);
 hipError_t launch_voronoi(const double *x, const double *y, const double *z, int64_t n,
                           const double *sites, int K, const int32_t *nbr_count, int32_t *owner,
                           int64_t *site_particles, int64_t *site_pairs, hipStream_t st);
