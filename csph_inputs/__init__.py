@@ -24,6 +24,10 @@ import numpy as np
 
 EOS_IDEAL = 0
 EOS_STIFFENED = 1
+EOS_MIE_GRUNEISEN = 2
+# Mie-Grueneisen materials of sec. 5 as (type, Gamma, 0, rho0 [g/cc], c_a [km/s], s_a)
+MG_LEAD = (EOS_MIE_GRUNEISEN, 1.7, 0.0, 11.35, 2.58, 1.26)
+MG_ALUMINIUM = (EOS_MIE_GRUNEISEN, 1.5, 0.0, 1.593, 3.0, 1.85)
 
 JITTER = 0.01
 H_SMOOTH = 1.5

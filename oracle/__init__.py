@@ -53,6 +53,9 @@ class Cfg(C.Structure):
         ("cell_size", C.c_double),
         ("nthreads", C.c_int32),
         ("pad", C.c_int32),
+        ("eos_rho0", C.c_double * MAX_EOS),
+        ("eos_ca", C.c_double * MAX_EOS),
+        ("eos_sa", C.c_double * MAX_EOS),
     ]
 
 
@@ -136,8 +139,12 @@ def make_cfg(eos, h=1.5, kappa=2.0, h_mode=0, wall=None, cfl=0.3, search=0, cell
     c = Cfg()
     c.h, c.kappa, c.h_mode = h, kappa, h_mode
     c.n_eos = len(eos)
-    for k, (t, g, pinf) in enumerate(eos):
+    for k, e in enumerate(eos):
+        # (type, gamma, p_inf) or, Mie-Grueneisen, (2, Gamma, 0, rho0, c_a, s_a)
+        t, g, pinf = e[:3]
         c.eos_type[k], c.eos_gamma[k], c.eos_pinf[k] = int(t), float(g), float(pinf)
+        if len(e) > 3:
+            c.eos_rho0[k], c.eos_ca[k], c.eos_sa[k] = (float(v) for v in e[3:6])
     if wall is not None:
         c.wall, c.wall_x0, c.wall_v = 1, float(wall[0]), float(wall[1])
     c.cfl, c.search, c.cell_size, c.nthreads = cfl, search, cell_size, nthreads

@@ -21,7 +21,10 @@
  *                           solver form is not printed, the linear acoustic
  *                           (impedance) solver is used.
  *   oracle_eos              e = E - v^2/2 (after eq. SPH:Energy); ideal and
- *                           stiffened-gas pressure and sound speed.
+ *                           stiffened-gas pressure and sound speed, and the
+ *                           Mie-Grueneisen form (eqs. mie_gruneisen_eos,
+ *                           mie_gruneisen_reference) with the sound speed
+ *                           derived from it (not printed in the paper).
  *   oracle_neighbors        N(i) = { j != i : |r_j - r_i| < support }
  *                           (sec. 4.1, the support statement before sec. 4.2);
  *                           brute force over all j is the authority, a cell
@@ -56,7 +59,7 @@ typedef struct {
     double kappa;      /* support radius in units of h */
     int32_t h_mode;    /* 0: support kappa*h for all pairs; 1: kappa*(d_i+d_j)/2 */
     int32_t n_eos;
-    int32_t eos_type[ORACLE_MAX_EOS]; /* 0 ideal, 1 stiffened gas */
+    int32_t eos_type[ORACLE_MAX_EOS]; /* 0 ideal, 1 stiffened gas, 2 Mie-Grueneisen */
     double eos_gamma[ORACLE_MAX_EOS];
     double eos_pinf[ORACLE_MAX_EOS];
     int32_t wall;      /* 1: rigid piston plane x = wall_x0 + wall_v*t, normal +x */
@@ -67,6 +70,10 @@ typedef struct {
     double cell_size;  /* cell-list mode: mesh size D (>= support) */
     int32_t nthreads;  /* 0: all cores this process may use */
     int32_t pad;
+    /* Mie-Grueneisen materials (type 2; Gamma is eos_gamma) */
+    double eos_rho0[ORACLE_MAX_EOS];
+    double eos_ca[ORACLE_MAX_EOS];
+    double eos_sa[ORACLE_MAX_EOS];
 } oracle_cfg;
 
 /* ------------------------------------------------------------------ */
@@ -148,11 +155,40 @@ void oracle_riemann(double ZL, double ZR, double PL, double PR, double vL, doubl
 /* ------------------------------------------------------------------ */
 /* equation of state                                                   */
 
+/* Mie-Grueneisen reference curves of the linear u_s - u_p Hugoniot
+ * (eq. mie_gruneisen_reference) at compression x = rho0/rho:
+ *   P_r = rho0 c_a^2 (1 - x) / [1 - s_a (1 - x)]^2,
+ *   e_r = (c_a^2 / 2) (1 - x)^2 / [1 - s_a (1 - x)]^2.
+ * Returns D = 1 - s_a (1 - x) (the curves exist for D > 0). */
+static double mg_reference(double rho0, double ca, double sa, double rho, double *Pr,
+                           double *er) {
+    double x = rho0 / rho;
+    double eta = 1.0 - x;
+    double D = 1.0 - sa * eta;
+    double D2 = D * D;
+    *Pr = rho0 * ca * ca * eta / D2;
+    *er = 0.5 * ca * ca * eta * eta / D2;
+    return D;
+}
+
 static int eos_eval(const oracle_cfg *cfg, int mat, double rho, double e, double *P, double *c) {
     int k = (mat >= 0 && mat < cfg->n_eos) ? mat : 0;
     double g = cfg->eos_gamma[k], pinf = cfg->eos_pinf[k];
     double p, c2;
-    if (cfg->eos_type[k] == 1) {
+    if (cfg->eos_type[k] == 2) {
+        /* eq. mie_gruneisen_eos, P - P_r = Gamma rho (e - e_r), Gamma = eos_gamma.  The
+         * paper prints no sound speed; c^2 = (dP/drho)_e + (P/rho^2)(dP/de)_rho, with
+         * dP_r/drho = c_a^2 x^2 (1 + s_a eta)/D^3 and rho de_r/drho = c_a^2 eta x/D^3. */
+        double rho0 = cfg->eos_rho0[k], ca = cfg->eos_ca[k], sa = cfg->eos_sa[k];
+        double Pr, er;
+        double D = mg_reference(rho0, ca, sa, rho, &Pr, &er);
+        double x = rho0 / rho, eta = 1.0 - x, D3 = D * D * D;
+        p = Pr + g * rho * (e - er);
+        double dPr = ca * ca * x * x * (1.0 + sa * eta) / D3;
+        double rder = ca * ca * eta * x / D3;
+        c2 = dPr + g * (e - er) - g * rder + g * p / rho;
+        if (!(D > 0.0)) c2 = -1.0; /* beyond the Hugoniot's compression limit */
+    } else if (cfg->eos_type[k] == 1) {
         p = (g - 1.0) * rho * e - g * pinf;
         c2 = g * (p + pinf) / rho;
     } else {
@@ -188,8 +224,16 @@ void oracle_init_energy(const oracle_cfg *cfg, int64_t n, const double *rho, con
         int k = mat ? mat[i] : 0;
         if (k < 0 || k >= cfg->n_eos) k = 0;
         double g = cfg->eos_gamma[k];
-        double e = (cfg->eos_type[k] == 1) ? (p[i] + g * cfg->eos_pinf[k]) / ((g - 1.0) * rho[i])
-                                            : p[i] / ((g - 1.0) * rho[i]);
+        double e;
+        if (cfg->eos_type[k] == 2) {
+            double Pr, er;
+            mg_reference(cfg->eos_rho0[k], cfg->eos_ca[k], cfg->eos_sa[k], rho[i], &Pr, &er);
+            e = er + (p[i] - Pr) / (g * rho[i]);
+        } else if (cfg->eos_type[k] == 1) {
+            e = (p[i] + g * cfg->eos_pinf[k]) / ((g - 1.0) * rho[i]);
+        } else {
+            e = p[i] / ((g - 1.0) * rho[i]);
+        }
         E[i] = e + 0.5 * ((vx[i] * vx[i] + vy[i] * vy[i]) + vz[i] * vz[i]);
     }
 }

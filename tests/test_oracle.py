@@ -476,3 +476,74 @@ def test_totals_exact(orc):
     assert t[4] == math.fsum(m * s["E"])
     big = np.array([1e100, 1.0, -1e100, 1e-30])
     assert orc.exact_sum(big) == math.fsum(big.tolist())
+
+
+# ------------------------------------------------------------------ Mie-Grueneisen (sec. 5)
+
+def _mg_eval(O, mat_eos, rho, e):
+    """P, c, bad from the oracle for one material at (rho, e) arrays."""
+    rho = np.asarray(rho, np.float64)
+    e = np.asarray(e, np.float64)
+    cfg = O.make_cfg([mat_eos])
+    z = np.zeros_like(rho)
+    s = dict(rho=rho, E=e.copy(), vx=z, vy=z, vz=z, mat=np.zeros(rho.shape, np.int32))
+    return O.eos(cfg, s)
+
+
+@pytest.mark.parametrize("mat", [ci.MG_LEAD, ci.MG_ALUMINIUM])
+def test_mg_reference_state(orc, mat):
+    _, G, _, rho0, ca, sa = mat
+    P, c, bad = _mg_eval(orc, mat, [rho0], [0.0])
+    assert P[0] == 0.0 and bad == 0
+    assert abs(c[0] - ca) <= 1e-15 * ca
+
+
+@pytest.mark.parametrize("mat", [ci.MG_LEAD, ci.MG_ALUMINIUM])
+def test_mg_rankine_hugoniot(orc, mat):
+    """On the linear Hugoniot u_s = c_a + s_a u_p the jump conditions give rho = rho0 u_s /
+    (u_s - u_p), P = rho0 u_s u_p, e = u_p^2/2: the EOS must return that P there, and off it
+    P - P_H = Gamma rho (e - e_H)."""
+    _, G, _, rho0, ca, sa = mat
+    up = np.array([0.05, 0.3, 1.0, 2.0])
+    us = ca + sa * up
+    rho = rho0 * us / (us - up)
+    eH = 0.5 * up * up
+    PH = rho0 * us * up
+    P, _, bad = _mg_eval(orc, mat, rho, eH)
+    assert bad == 0
+    assert np.all(np.abs(P - PH) <= 1e-13 * PH)
+    de = np.array([0.01, -0.2, 0.5, 1.0])
+    P2, _, _ = _mg_eval(orc, mat, rho, eH + de)
+    assert np.all(np.abs((P2 - PH) - G * rho * de) <= 1e-12 * np.abs(P2))
+
+
+@pytest.mark.parametrize("mat", [ci.MG_LEAD, ci.MG_ALUMINIUM])
+def test_mg_sound_speed_is_isentropic_slope(orc, mat):
+    """c^2 = dP/drho along the isentrope de = (P/rho^2) drho (central differences)."""
+    _, G, _, rho0, ca, sa = mat
+    for x, e in ((0.8, 0.3), (1.0, 0.0), (1.05, 0.1), (0.9, 1.5)):
+        rho = rho0 / x
+        P, c, bad = _mg_eval(orc, mat, [rho], [e])
+        assert bad == 0
+        h = 1e-5 * rho
+        de = P[0] / (rho * rho) * h
+        Pp, _, _ = _mg_eval(orc, mat, [rho + h], [e + de])
+        Pm, _, _ = _mg_eval(orc, mat, [rho - h], [e - de])
+        slope = (Pp[0] - Pm[0]) / (2 * h)
+        assert abs(slope - c[0] ** 2) <= 1e-6 * c[0] ** 2, (x, e, slope, c[0] ** 2)
+
+
+def test_mg_inverse_and_overcompression(orc):
+    mat = ci.MG_LEAD
+    _, G, _, rho0, ca, sa = mat
+    rng = np.random.default_rng(0)
+    rho = rho0 * rng.uniform(0.9, 1.3, 50)
+    p = rng.uniform(-1.0, 50.0, 50)
+    cfg = orc.make_cfg([mat])
+    z = np.zeros_like(rho)
+    E = orc.init_energy(cfg, rho, p, z, z, z, np.zeros(50, np.int32))
+    P, _, _ = _mg_eval(orc, mat, rho, E)
+    assert np.all(np.abs(P - p) <= 1e-12 * np.maximum(np.abs(p), 1.0))
+    # compression beyond 1 - rho0/rho = 1/s_a: no Hugoniot, counted non-physical with c = 0
+    P, c, bad = _mg_eval(orc, mat, [rho0 / (1.0 - 1.0 / sa) * 1.01], [0.0])
+    assert bad == 1 and c[0] == 0.0
