@@ -83,6 +83,29 @@ class Runner:
             self.state, self.other = out, self.state
 
 
+def balance_timing(P, torch, run, sites, iters=10):
+    """Balancer iteration (subdomain statistics + generator move) on the final state of the
+    timed run with its 64 generators: HIP-event time per iteration."""
+    bp = P.BalanceParams(sigma=0.5, theta=0.25, gamma=1.0, dsh=3.0, load="pairs")
+    s = run.state
+    g = sites.clone()
+    st = P.csph_balance_stats(s["x"], s["y"], s["z"], run.owner, g, bp.dsh, nbr_count=run.cnt)
+    P.csph_balance_move(g, st, bp)
+    torch.cuda.synchronize()
+    P.profile_enable(True)
+    P.profile_read()
+    for _ in range(iters):
+        st = P.csph_balance_stats(s["x"], s["y"], s["z"], run.owner, g, bp.dsh, nbr_count=run.cnt)
+        P.csph_balance_move(g, st, bp)
+    torch.cuda.synchronize()
+    launches, ms = P.profile_read()["balance"]
+    P.profile_enable(False)
+    adj = P.adjacency_matrix(st["adjacency"], g.shape[0])
+    return {"ms_per_iteration": ms / iters, "sites": int(g.shape[0]), "iterations": iters,
+            "touching_pairs": int(adj.sum().item()) // 2,
+            "note": "stats pass over all particles + one-workgroup generator move"}
+
+
 def traffic_from_profile(kernel_src):
     """HBM bytes per launch of the pair-rate kernel from the committed counter summary,
     or None when the kernel source changed since the counters were taken."""
@@ -198,6 +221,8 @@ def main():
         P.profile_enable(False)
         tot1 = sc.totals.cpu().numpy()
         npairs = int(run.pairs.item())
+        if prec == "mixed":
+            results["balance"] = balance_timing(P, torch, run, sites)
         results[prec] = dict(ms=1e3 * el / k, pairs_per_step=npairs / k, el=el, k=k, prof=prof,
                              nonphys=int(sc.nonphys.item()), t=float(sc.t.item()),
                              tot0=tot0, tot1=tot1)
@@ -252,6 +277,8 @@ def main():
         line["fp64"] = {"ms_per_step": f["ms"], "value": f["pairs_per_step"] * 1e3 / f["ms"],
                         "rates_kernel_ms": f["prof"]["rates"][1] / max(f["prof"]["rates"][0], 1)}
         line["mixed_speedup_over_fp64"] = f["ms"] / m["ms"]
+    if "balance" in results:
+        line["balance"] = results["balance"]
     if args.adjoint:
         log("adjoint rollout ...")
         line["adjoint"] = adjoint_ratio(P, torch, ci)

@@ -60,6 +60,13 @@ typedef void *csph_stream; /* hipStream_t */
 #define CSPH_MAX_EOS 8
 #define CSPH_EOS_IDEAL 0     /* P = (gamma-1) rho e,            c^2 = gamma P / rho          */
 #define CSPH_EOS_STIFFENED 1 /* P = (gamma-1) rho e - gamma P_inf, c^2 = gamma (P+P_inf) / rho */
+/* Mie-Grueneisen (eqs. mie_gruneisen_eos, mie_gruneisen_reference), gamma = Gamma:
+ *   x = rho0/rho, eta = 1 - x, D = 1 - s_a eta,
+ *   P_r = rho0 c_a^2 eta / D^2, e_r = c_a^2 eta^2 / (2 D^2), P = P_r + Gamma rho (e - e_r),
+ *   c^2 = c_a^2 x^2 (1 + s_a eta)/D^3 + Gamma (e - e_r) - Gamma c_a^2 eta x / D^3 + Gamma P/rho
+ *   (the sound speed (dP/drho)_s, derived; the paper prints none).  D <= 0 (compression
+ *   beyond the Hugoniot's limit) or c^2 < 0 is non-physical: c = 0, counted. */
+#define CSPH_EOS_MIE_GRUNEISEN 2
 
 #define CSPH_FP64 0  /* every operation in FP64 */
 #define CSPH_MIXED 1 /* pair arithmetic in FP32; positions, EOS, integration, totals FP64 */
@@ -70,8 +77,11 @@ typedef void *csph_stream; /* hipStream_t */
 typedef struct {
     int32_t type;   /* CSPH_EOS_* */
     int32_t pad;
-    double gamma;   /* adiabatic index */
+    double gamma;   /* adiabatic index (ideal, stiffened); Grueneisen Gamma (Mie-Grueneisen) */
     double p_inf;   /* stiffening pressure (stiffened gas only) */
+    double rho0;    /* Mie-Grueneisen: reference density */
+    double c_a;     /* Mie-Grueneisen: u_s = c_a + s_a u_p */
+    double s_a;
 } csph_eos;
 
 typedef struct {
@@ -281,7 +291,8 @@ csph_status csph_init_energy(const double *rho, const double *pres, const double
                              const double *vy, const double *vz, const int32_t *mat, int64_t n,
                              const csph_params *p, double *E, csph_stream stream);
 
-/* Adjoint (vector-Jacobian products).  Fixed-h mode without a wall; FP64
+/* Adjoint (vector-Jacobian products).  Fixed-h mode without a wall, ideal
+ * and stiffened-gas materials (CSPH_EINVAL otherwise); FP64
  * arithmetic in both precisions (it differentiates the FP64 map).  A
  * gradient struct holds 8 FP64 arrays in the state's order. */
 typedef struct {

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(PKG, "libcsph.so")
 
 CSPH_OK, CSPH_EINVAL, CSPH_ECAPACITY, CSPH_EDEVICE = 0, 1, 2, 3
 CSPH_MAX_EOS = 8
-CSPH_EOS_IDEAL, CSPH_EOS_STIFFENED = 0, 1
+CSPH_EOS_IDEAL, CSPH_EOS_STIFFENED, CSPH_EOS_MIE_GRUNEISEN = 0, 1, 2
 CSPH_FP64, CSPH_MIXED = 0, 1
 CSPH_H_FIXED, CSPH_H_PAIR = 0, 1
 
@@ -25,7 +25,8 @@ _up = C.POINTER(C.c_uint32)
 
 class CsphEos(C.Structure):
     _fields_ = [("type", C.c_int32), ("pad", C.c_int32), ("gamma", C.c_double),
-                ("p_inf", C.c_double)]
+                ("p_inf", C.c_double), ("rho0", C.c_double), ("c_a", C.c_double),
+                ("s_a", C.c_double)]
 
 
 class CsphParams(C.Structure):

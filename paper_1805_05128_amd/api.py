@@ -16,6 +16,7 @@ from . import _native as N
 
 STATE_FIELDS = ("x", "y", "z", "vx", "vy", "vz", "rho", "E", "m")
 EOS_IDEAL, EOS_STIFFENED = N.CSPH_EOS_IDEAL, N.CSPH_EOS_STIFFENED
+EOS_MIE_GRUNEISEN = N.CSPH_EOS_MIE_GRUNEISEN
 
 
 def _ptr(t: Optional[torch.Tensor], ctype):
@@ -51,7 +52,7 @@ def _stream(stream=None):
 class Params:
     """Mirror of csph_params."""
 
-    eos: List[Tuple[int, float, float]] = field(default_factory=lambda: [(EOS_IDEAL, 1.4, 0.0)])
+    eos: List[Tuple] = field(default_factory=lambda: [(EOS_IDEAL, 1.4, 0.0)])
     precision: str = "fp64"  # "fp64" | "mixed"
     h: float = 1.5
     kappa: float = 2.0
@@ -67,8 +68,12 @@ class Params:
         p.h_mode = N.CSPH_H_PAIR if self.h_mode == "pair" else N.CSPH_H_FIXED
         p.h, p.kappa, p.cell_size, p.cfl = self.h, self.kappa, self.cell_size, self.cfl
         p.n_eos = len(self.eos)
-        for k, (t, g, pinf) in enumerate(self.eos):
+        for k, e in enumerate(self.eos):
+            # (type, gamma, p_inf), or Mie-Grueneisen (EOS_MIE_GRUNEISEN, Gamma, 0, rho0, c_a, s_a)
+            t, g, pinf = e[:3]
             p.eos[k].type, p.eos[k].gamma, p.eos[k].p_inf = int(t), float(g), float(pinf)
+            if len(e) > 3:
+                p.eos[k].rho0, p.eos[k].c_a, p.eos[k].s_a = (float(v) for v in e[3:6])
         if self.wall is not None:
             p.wall, p.wall_x0, p.wall_v = 1, float(self.wall[0]), float(self.wall[1])
         p.reorder = 1 if self.reorder else 0

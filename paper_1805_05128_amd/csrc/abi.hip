@@ -140,10 +140,18 @@ static csph_status check_params(const csph_params *p, bool need_pair_d, const do
         return fail(CSPH_EINVAL, "n_eos must be in [1, %d]", CSPH_MAX_EOS);
     for (int k = 0; k < p->n_eos; ++k) {
         const csph_eos &e = p->eos[k];
-        if (e.type != CSPH_EOS_IDEAL && e.type != CSPH_EOS_STIFFENED)
+        if (e.type != CSPH_EOS_IDEAL && e.type != CSPH_EOS_STIFFENED &&
+            e.type != CSPH_EOS_MIE_GRUNEISEN)
             return fail(CSPH_EINVAL, "eos[%d].type %d unknown", k, e.type);
-        if (!(e.gamma > 1.0) || !std::isfinite(e.gamma))
+        if (e.type == CSPH_EOS_MIE_GRUNEISEN) {
+            if (!(e.gamma > 0.0) || !std::isfinite(e.gamma))
+                return fail(CSPH_EINVAL, "eos[%d].gamma (Grueneisen) must be > 0", k);
+            if (!(e.rho0 > 0.0) || !std::isfinite(e.rho0) || !(e.c_a > 0.0) ||
+                !std::isfinite(e.c_a) || !(e.s_a >= 0.0) || !std::isfinite(e.s_a))
+                return fail(CSPH_EINVAL, "eos[%d]: need rho0 > 0, c_a > 0, s_a >= 0", k);
+        } else if (!(e.gamma > 1.0) || !std::isfinite(e.gamma)) {
             return fail(CSPH_EINVAL, "eos[%d].gamma must be > 1", k);
+        }
         if (!std::isfinite(e.p_inf)) return fail(CSPH_EINVAL, "eos[%d].p_inf not finite", k);
     }
     if (!std::isfinite(p->cell_size)) return fail(CSPH_EINVAL, "cell_size not finite");
@@ -166,6 +174,9 @@ static EosDev eos_dev(const csph_params *p) {
         e.type[k] = p->eos[k].type;
         e.gamma[k] = p->eos[k].gamma;
         e.pinf[k] = p->eos[k].p_inf;
+        e.rho0[k] = p->eos[k].rho0;
+        e.ca[k] = p->eos[k].c_a;
+        e.sa[k] = p->eos[k].s_a;
     }
     return e;
 }
@@ -575,6 +586,9 @@ csph_status csph_init_energy(const double *rho, const double *pres, const double
 
 static csph_status check_vjp_params(const csph_params *p) {
     if (p->h_mode != CSPH_H_FIXED) return fail(CSPH_EINVAL, "the adjoint supports fixed-h mode only");
+    for (int k = 0; k < p->n_eos; ++k)
+        if (p->eos[k].type == CSPH_EOS_MIE_GRUNEISEN)
+            return fail(CSPH_EINVAL, "the adjoint supports ideal and stiffened gas only");
     if (p->wall) return fail(CSPH_EINVAL, "the adjoint does not support the piston wall");
     return CSPH_OK;
 }
@@ -655,6 +669,9 @@ csph_status csph_init_energy_vjp(const double *rho, const double *pres, const do
         return fail(CSPH_EINVAL, "bad arguments");
     csph_status r = check_params(p, false, nullptr);
     if (r) return r;
+    for (int k = 0; k < p->n_eos; ++k)
+        if (p->eos[k].type == CSPH_EOS_MIE_GRUNEISEN)
+            return fail(CSPH_EINVAL, "the adjoint supports ideal and stiffened gas only");
     r = need_ws(ws_bytes, n, 1, ws_needed);
     if (r) return r;
     Ws w;

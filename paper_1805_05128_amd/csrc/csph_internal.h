@@ -70,9 +70,63 @@ struct PairConst {
 struct EosDev {
     int n;
     int type[CSPH_MAX_EOS];
-    double gamma[CSPH_MAX_EOS];
+    double gamma[CSPH_MAX_EOS];  // adiabatic index, or Grueneisen Gamma
     double pinf[CSPH_MAX_EOS];
+    double rho0[CSPH_MAX_EOS], ca[CSPH_MAX_EOS], sa[CSPH_MAX_EOS];  // Mie-Grueneisen
 };
+
+// Mie-Grueneisen reference curves of the linear u_s - u_p Hugoniot
+// (eq. mie_gruneisen_reference) at x = rho0/rho; returns D = 1 - s_a (1 - x).
+__device__ __forceinline__ double mg_reference(const EosDev &eos, int k, double rho, double &Pr,
+                                               double &er) {
+    const double rho0 = eos.rho0[k], ca = eos.ca[k], sa = eos.sa[k];
+    const double x = rho0 / rho;
+    const double eta = 1.0 - x;
+    const double D = 1.0 - sa * eta;
+    const double D2 = D * D;
+    Pr = rho0 * ca * ca * eta / D2;
+    er = 0.5 * ca * ca * eta * eta / D2;
+    return D;
+}
+
+// Pressure and squared sound speed of material k at (rho, e): ideal gas,
+// stiffened gas, or Mie-Grueneisen (eq. mie_gruneisen_eos with the sound
+// speed c^2 = (dP/drho)_e + (P/rho^2)(dP/de)_rho; -1 past the Hugoniot's
+// compression limit).  FP64, no contraction.
+__device__ __forceinline__ void eos_eval(const EosDev &eos, int k, double rho, double e,
+                                         double &P, double &c2) {
+    const double gm = eos.gamma[k];
+    if (eos.type[k] == CSPH_EOS_MIE_GRUNEISEN) {
+        const double ca = eos.ca[k], sa = eos.sa[k];
+        double Pr, er;
+        const double D = mg_reference(eos, k, rho, Pr, er);
+        const double x = eos.rho0[k] / rho, eta = 1.0 - x, D3 = D * D * D;
+        P = Pr + gm * rho * (e - er);
+        const double dPr = ca * ca * x * x * (1.0 + sa * eta) / D3;
+        const double rder = ca * ca * eta * x / D3;
+        c2 = dPr + gm * (e - er) - gm * rder + gm * P / rho;
+        if (!(D > 0.0)) c2 = -1.0;
+    } else if (eos.type[k] == CSPH_EOS_STIFFENED) {
+        const double pinf = eos.pinf[k];
+        P = (gm - 1.0) * rho * e - gm * pinf;
+        c2 = gm * (P + pinf) / rho;
+    } else {
+        P = (gm - 1.0) * rho * e;
+        c2 = gm * P / rho;
+    }
+}
+
+// Specific internal energy of material k at (rho, P): the EOS inverse.
+__device__ __forceinline__ double eos_energy(const EosDev &eos, int k, double rho, double p) {
+    const double g = eos.gamma[k];
+    if (eos.type[k] == CSPH_EOS_MIE_GRUNEISEN) {
+        double Pr, er;
+        mg_reference(eos, k, rho, Pr, er);
+        return er + (p - Pr) / (g * rho);
+    }
+    if (eos.type[k] == CSPH_EOS_STIFFENED) return (p + g * eos.pinf[k]) / ((g - 1.0) * rho);
+    return p / ((g - 1.0) * rho);
+}
 
 // Cell coordinate min(floor((v - o) * inv), dim - 1), clamped at 0, FP64
 // without contraction (the library is built with -ffp-contract=off).

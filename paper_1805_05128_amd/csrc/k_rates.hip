@@ -27,7 +27,7 @@ struct DstState {
 // ---------------------------------------------------------------- pack
 
 // Gather particle perm[s] into slot s: sorted FP64 state copy, EOS
-// (e = E - |v|^2/2; ideal or stiffened gas), pair record.
+// (e = E - |v|^2/2; ideal gas, stiffened gas or Mie-Grueneisen), pair record.
 template <bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_pack(int64_t n, SrcState src,
                                                  const int32_t *__restrict__ perm, EosDev eos,
@@ -50,16 +50,9 @@ __global__ __launch_bounds__(kBlock) void k_pack(int64_t n, SrcState src,
     double x = v[0], y = v[1], z = v[2], vx = v[3], vy = v[4], vz = v[5], rho = v[6], E = v[7],
            m = v[8];
     int k = (mt >= 0 && mt < eos.n) ? mt : 0;
-    double gm = eos.gamma[k], pinf = eos.pinf[k];
     double e = E - 0.5 * ((vx * vx + vy * vy) + vz * vz);
     double P, c2;
-    if (eos.type[k] == CSPH_EOS_STIFFENED) {
-        P = (gm - 1.0) * rho * e - gm * pinf;
-        c2 = gm * (P + pinf) / rho;
-    } else {
-        P = (gm - 1.0) * rho * e;
-        c2 = gm * P / rho;
-    }
+    eos_eval(eos, k, rho, e, P, c2);
     bool bad = !(c2 >= 0.0);
     double c = bad ? 0.0 : sqrt(c2);
     if (bad && nonphys) atomicAdd((unsigned long long *)nonphys, 1ull);

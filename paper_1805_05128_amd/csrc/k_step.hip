@@ -227,9 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_init_energy(const double *__restrict
     if (i >= n) return;
     int k = mat ? mat[i] : 0;
     if (k < 0 || k >= eos.n) k = 0;
-    double g = eos.gamma[k];
-    double e = eos.type[k] == CSPH_EOS_STIFFENED ? (pres[i] + g * eos.pinf[k]) / ((g - 1.0) * rho[i])
-                                                 : pres[i] / ((g - 1.0) * rho[i]);
+    double e = eos_energy(eos, k, rho[i], pres[i]);
     E[i] = e + 0.5 * ((vx[i] * vx[i] + vy[i] * vy[i]) + vz[i] * vz[i]);
 }
 

@@ -56,9 +56,26 @@ def slab_cloud(n=2600, seed=21):
     return w
 
 
+def mg_block(seed=13):
+    """Lead (x < 5) against aluminium, Mie-Grueneisen (sec. 5 parameters, g/cc, km/s, GPa),
+    compressed 0-20 %, pressures up to 30 GPa, random velocities."""
+    w = ci.jittered_block(10, 9, 8, seed=seed, amp=0.02)
+    rng = np.random.default_rng(seed)
+    lead = w.x < 5.0
+    w.mat = np.where(lead, 0, 1).astype(np.int32)
+    w.eos = [ci.MG_LEAD, ci.MG_ALUMINIUM]
+    rho0 = np.where(lead, ci.MG_LEAD[3], ci.MG_ALUMINIUM[3])
+    w.rho = rho0 * rng.uniform(1.0, 1.2, w.n)
+    w.p = rng.uniform(0.0, 30.0, w.n)
+    w.m = rho0.copy()
+    w.vx, w.vy, w.vz = (rng.uniform(-0.5, 0.5, w.n) for _ in range(3))
+    return w
+
+
 CASES = {
     "sod16": ci.config0,
     "slab": slab_cloud,
+    "mg": mg_block,
     "cloud2mat": two_material_cloud,
     "wall": wall_block,
     "ragged": lambda: ci.random_cloud(777, seed=3, box=7.3, vmax=1.0),
@@ -199,6 +216,26 @@ def test_rates_mixed(case):
     assert np.array_equal(got["nbr_count"].astype(np.int64), ref["nbr_count"])
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+def test_rates_pair_h_mie_grueneisen(prec, tol):
+    """Paper mode: support kappa (d_i + d_j)/2 with kappa = 1.936 and d = (m/rho)^(1/3),
+    Mie-Grueneisen lead against aluminium."""
+    w = mg_block(seed=17)
+    d = np.cbrt(w.m / w.rho)
+    _print_case(f"mg pair-h {prec}", w)
+    params = P.Params.from_workload(w, precision=prec, h_mode="pair", kappa=1.936, cell_size=0.0)
+    g = gpu_state(w, params)
+    g.d = torch.as_tensor(d, dtype=torch.float64, device=DEV)
+    got = rates_np(P.csph_rates(g, params))
+    torch.cuda.synchronize()
+    ref = O.rates(O.cfg_for(w, search=1, h_mode=1, kappa=1.936), ref_state(w), d=d)
+    err = field_relerr(got, ref)
+    print(prec, "relerr", err, "mean |N|", ref["nbr_count"].mean())
+    assert max(err.values()) <= tol, err
+    assert np.array_equal(got["nbr_count"].astype(np.int64), ref["nbr_count"])
+    assert 15 < ref["nbr_count"].mean() < 30
+
+
 @pytest.mark.parametrize("D", [1.0, 1.5, 2.2])
 def test_rates_small_cells(D):
     """Cells smaller than the support (stencil reach ceil(H/D) > 1) give the same rates."""
@@ -275,7 +312,7 @@ def _check_totals(tot_gpu, s_ref):
 
 
 @pytest.mark.parametrize("reorder", [False, True])
-@pytest.mark.parametrize("case", ["sod16", "wall", "cloud2mat", "slab"])
+@pytest.mark.parametrize("case", ["sod16", "wall", "cloud2mat", "slab", "mg"])
 def test_step_fp64(case, reorder):
     w = CASES[case]()
     _print_case(f"{case} reorder={reorder}", w)
