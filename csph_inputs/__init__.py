@@ -193,6 +193,7 @@ def config3(nside: int = 64) -> Workload:
     """
     w = sod(nside, 4, nside / 2.0, f"adjoint_sod_{nside}cubed", steps=100)
     w.cfl = 0.1
+    w.cell_size = 1.0  # unit mesh cells (the neighbour sets do not depend on the mesh)
     r = _streams(4)
     w.fd_dirs = r[3].standard_normal((32, 3 * w.n + 1))
     return w

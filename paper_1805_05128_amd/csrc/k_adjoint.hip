@@ -12,6 +12,7 @@
 // dPhi_ij/dq_i: every particle gathers its own gradient over its own
 // neighbours, no atomics, fixed summation order.
 #include "csph_internal.h"
+#include "stencil.h"
 
 namespace csph {
 
@@ -76,113 +77,157 @@ __global__ __launch_bounds__(kBlock) void k_vjp_weights(int64_t n,
     Ew[s] = k * aE;
 }
 
+// Sums a particle gathers over its partners.
+struct VjpAcc {
+    double gr0 = 0, gr1 = 0, gr2 = 0, gv0 = 0, gv1 = 0, gv2 = 0, gP = 0, gZ = 0, gV = 0;
+    double Sr = 0, Sv0 = 0, Sv1 = 0, Sv2 = 0, SE = 0;
+};
+
+// dPhi_ij/dq_i for one partner j (i's data: ai = x y z V, bi = v P, zi = Z c,
+// di = b_rho b_v, bEi = b_E), plus the plain rate sums S* the prefactor terms
+// need.  Branch-free: a lane without a partner (use = false) computes on
+// placeholder data (r2 = 1) and keeps its sums.
+__device__ __forceinline__ void vjp_pair(bool use, double dx, double dy, double dz, double r2,
+                                         const double4 &ai, const double4 &bi, const double2 &zi,
+                                         const double4 &di, double bEi, const double4 &aj,
+                                         const double4 &bj, const double2 &zj, const double4 &dj,
+                                         double bEj, double invH, double dwc, VjpAcc &A) {
+#pragma clang fp contract(fast)
+    const double Vi = ai.w, Pi = bi.w, Zi = zi.x;
+    const double Vj = aj.w, Pj = bj.w, Zj = zj.x;
+    const double r = sqrt(use ? r2 : 1.0), ir = 1.0 / r;
+    const double ex = dx * ir, ey = dy * ir, ez = dz * ir;
+    const double q = r * invH, a1 = 1.0 - q;
+    const double Wp = -dwc * q * (a1 * a1 * a1);
+    const double Wpp = -dwc * invH * (a1 * a1) * (1.0 - 4.0 * q);
+    const double vL = (bi.x * ex + bi.y * ey) + bi.z * ez;
+    const double vR = (bj.x * ex + bj.y * ey) + bj.z * ez;
+    const double S = Zi + Zj;
+    const bool sok = S != 0.0;
+    const double iS = 1.0 / (sok ? S : 1.0);
+    const double vs = sok ? ((Zi * vL + Zj * vR) + (Pi - Pj)) * iS : 0.5 * (vL + vR);
+    const double ps = sok ? ((Zj * Pi + Zi * Pj) + Zi * Zj * (vL - vR)) * iS : 0.5 * (Pi + Pj);
+    const double dvs_dvL = sok ? Zi * iS : 0.5;
+    const double dvs_dvR = sok ? Zj * iS : 0.5;
+    const double dps_dvL = sok ? Zi * Zj * iS : 0.0;
+    const double dps_dvR = -dps_dvL;
+    const double dvs_dP = sok ? iS : 0.0;
+    const double dps_dP = sok ? Zj * iS : 0.5;
+    const double dvs_dZ = sok ? (vL - vs) * iS : 0.0;
+    const double dps_dZ = sok ? ((Pj + Zj * (vL - vR)) - ps) * iS : 0.0;
+    const double bvie = (di.y * ex + di.z * ey) + di.w * ez;
+    const double bvje = (dj.y * ex + dj.z * ey) + dj.w * ez;
+    const double Gi = di.x * (vL - vs) + ps * bvie + bEi * ps * vs;
+    const double Gj = dj.x * (vs - vR) - ps * bvje - bEj * ps * vs;
+    const double G = Vj * Gi + Vi * Gj;
+    const double Gvs = Vj * (bEi * ps - di.x) + Vi * (dj.x - bEj * ps);
+    const double Gps = Vj * (bvie + bEi * vs) - Vi * (bvje + bEj * vs);
+    const double dGdvL = Vj * di.x + Gvs * dvs_dvL + Gps * dps_dvL;
+    const double dGdvR = -Vi * dj.x + Gvs * dvs_dvR + Gps * dps_dvR;
+    const double wv = Wp * dGdvL;
+    const double u0 = (dGdvL * bi.x + dGdvR * bj.x) + ps * (Vj * di.y - Vi * dj.y);
+    const double u1 = (dGdvL * bi.y + dGdvR * bj.y) + ps * (Vj * di.z - Vi * dj.z);
+    const double u2 = (dGdvL * bi.z + dGdvR * bj.z) + ps * (Vj * di.w - Vi * dj.w);
+    const double ue = (u0 * ex + u1 * ey) + u2 * ez;
+    const double k1 = Wpp * G, k2 = Wp * ir;
+    const double w = Vj * Wp;
+    const double f = w * ps;
+    A.gV = use ? A.gV + Wp * Gj : A.gV;
+    A.gP = use ? A.gP + Wp * (Gvs * dvs_dP + Gps * dps_dP) : A.gP;
+    A.gZ = use ? A.gZ + Wp * (Gvs * dvs_dZ + Gps * dps_dZ) : A.gZ;
+    A.gv0 = use ? A.gv0 + wv * ex : A.gv0;
+    A.gv1 = use ? A.gv1 + wv * ey : A.gv1;
+    A.gv2 = use ? A.gv2 + wv * ez : A.gv2;
+    // dJ/dr_i = -dPhi/dd
+    A.gr0 = use ? A.gr0 - (k1 * ex + k2 * (u0 - ue * ex)) : A.gr0;
+    A.gr1 = use ? A.gr1 - (k1 * ey + k2 * (u1 - ue * ey)) : A.gr1;
+    A.gr2 = use ? A.gr2 - (k1 * ez + k2 * (u2 - ue * ez)) : A.gr2;
+    A.Sr = use ? A.Sr + w * (vL - vs) : A.Sr;
+    A.Sv0 = use ? A.Sv0 + f * ex : A.Sv0;
+    A.Sv1 = use ? A.Sv1 + f * ey : A.Sv1;
+    A.Sv2 = use ? A.Sv2 + f * ez : A.Sv2;
+    A.SE = use ? A.SE + f * vs : A.SE;
+}
+
+// The stencil walk of the FP64 rate kernel (lock-step rows clipped to the
+// support chord, partners queued per lane in LDS, drained with all lanes
+// busy); partners are j != i with 0 < r_ij^2 < H^2 in FP64 without
+// contraction, as in the forward pass.
 __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
                                                   const int32_t *__restrict__ perm,
                                                   const int32_t *__restrict__ cs, GridDev g,
                                                   PairConst pc, EosDev eos, int n_eos) {
-    int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    __shared__ int qj[kQ][kBlock];
+    const int tid = threadIdx.x;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t s = blk * kBlock + tid;
+    const bool live = s < n;
     double ge_gamma = 0.0, ge_pinf = 0.0;
     int mt = 0;
-    if (s < n) {
-        const double4 ai = in.A[s], bi = in.B[s], di = in.Dw[s];
-        const double2 zi = in.C[s];
-        const double bEi = in.Ew[s];
-        const double Vi = ai.w, Pi = bi.w, Zi = zi.x;
-        int cx = cell_coord(ai.x, g.ox, g.inv, g.dx);
-        int cy = cell_coord(ai.y, g.oy, g.inv, g.dy);
-        int cz = cell_coord(ai.z, g.oz, g.inv, g.dz);
-        double gr0 = 0, gr1 = 0, gr2 = 0, gv0 = 0, gv1 = 0, gv2 = 0, gP = 0, gZ = 0, gV = 0;
-        double Sr = 0, Sv0 = 0, Sv1 = 0, Sv2 = 0, SE = 0;
-        const double invH = pc.invH, dwc = pc.dwc, H2 = pc.H2;
-        const int R = g.reach;
-        const int x0 = max(cx - R, 0), x1 = min(cx + R, g.dx - 1);
-        for (int oz = -R; oz <= R; ++oz) {
-            int zz = cz + oz;
-            if (zz < 0 || zz >= g.dz) continue;
-            for (int oy = -R; oy <= R; ++oy) {
-                int yy = cy + oy;
-                if (yy < 0 || yy >= g.dy) continue;
-                int row = (int)cell_key(g, 0, yy, zz);
-                int j0 = cs[row + x0], j1 = cs[row + x1 + 1];
-                for (int j = j0; j < j1; ++j) {
-                    if (j == (int)s) continue;
-                    double4 aj = in.A[j];
-                    double dx = aj.x - ai.x, dy = aj.y - ai.y, dz = aj.z - ai.z;
-                    double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
-                    if (!(r2 < H2) || r2 == 0.0) continue;
-                    double4 bj = in.B[j], dj = in.Dw[j];
-                    double2 zj = in.C[j];
-                    double bEj = in.Ew[j];
-                    double Vj = aj.w, Pj = bj.w, Zj = zj.x;
-                    double r = sqrt(r2), ir = 1.0 / r;
-                    double ex = dx * ir, ey = dy * ir, ez = dz * ir;
-                    double q = r * invH, a1 = 1.0 - q;
-                    double Wp = -dwc * q * (a1 * a1 * a1);
-                    double Wpp = -dwc * invH * (a1 * a1) * (1.0 - 4.0 * q);
-                    double vL = (bi.x * ex + bi.y * ey) + bi.z * ez;
-                    double vR = (bj.x * ex + bj.y * ey) + bj.z * ez;
-                    double S = Zi + Zj;
-                    double vs, ps, dvs_dvL, dvs_dvR, dps_dvL, dps_dvR, dvs_dP, dps_dP, dvs_dZ,
-                        dps_dZ;
-                    if (S != 0.0) {
-                        double iS = 1.0 / S;
-                        vs = ((Zi * vL + Zj * vR) + (Pi - Pj)) * iS;
-                        ps = ((Zj * Pi + Zi * Pj) + Zi * Zj * (vL - vR)) * iS;
-                        dvs_dvL = Zi * iS;
-                        dvs_dvR = Zj * iS;
-                        dps_dvL = Zi * Zj * iS;
-                        dps_dvR = -dps_dvL;
-                        dvs_dP = iS;
-                        dps_dP = Zj * iS;
-                        dvs_dZ = (vL - vs) * iS;
-                        dps_dZ = ((Pj + Zj * (vL - vR)) - ps) * iS;
-                    } else {
-                        vs = 0.5 * (vL + vR);
-                        ps = 0.5 * (Pi + Pj);
-                        dvs_dvL = 0.5;
-                        dvs_dvR = 0.5;
-                        dps_dvL = 0.0;
-                        dps_dvR = 0.0;
-                        dvs_dP = 0.0;
-                        dps_dP = 0.5;
-                        dvs_dZ = 0.0;
-                        dps_dZ = 0.0;
-                    }
-                    double bvie = (di.y * ex + di.z * ey) + di.w * ez;
-                    double bvje = (dj.y * ex + dj.z * ey) + dj.w * ez;
-                    double Gi = di.x * (vL - vs) + ps * bvie + bEi * ps * vs;
-                    double Gj = dj.x * (vs - vR) - ps * bvje - bEj * ps * vs;
-                    double G = Vj * Gi + Vi * Gj;
-                    double Gvs = Vj * (bEi * ps - di.x) + Vi * (dj.x - bEj * ps);
-                    double Gps = Vj * (bvie + bEi * vs) - Vi * (bvje + bEj * vs);
-                    double dGdvL = Vj * di.x + Gvs * dvs_dvL + Gps * dps_dvL;
-                    double dGdvR = -Vi * dj.x + Gvs * dvs_dvR + Gps * dps_dvR;
-                    gV += Wp * Gj;
-                    gP += Wp * (Gvs * dvs_dP + Gps * dps_dP);
-                    gZ += Wp * (Gvs * dvs_dZ + Gps * dps_dZ);
-                    double wv = Wp * dGdvL;
-                    gv0 += wv * ex;
-                    gv1 += wv * ey;
-                    gv2 += wv * ez;
-                    double u0 = (dGdvL * bi.x + dGdvR * bj.x) + ps * (Vj * di.y - Vi * dj.y);
-                    double u1 = (dGdvL * bi.y + dGdvR * bj.y) + ps * (Vj * di.z - Vi * dj.z);
-                    double u2 = (dGdvL * bi.z + dGdvR * bj.z) + ps * (Vj * di.w - Vi * dj.w);
-                    double ue = (u0 * ex + u1 * ey) + u2 * ez;
-                    double k1 = Wpp * G, k2 = Wp * ir;
-                    // dJ/dr_i = -dPhi/dd
-                    gr0 -= k1 * ex + k2 * (u0 - ue * ex);
-                    gr1 -= k1 * ey + k2 * (u1 - ue * ey);
-                    gr2 -= k1 * ez + k2 * (u2 - ue * ez);
-                    double w = Vj * Wp;
-                    Sr += w * (vL - vs);
-                    double f = w * ps;
-                    Sv0 += f * ex;
-                    Sv1 += f * ey;
-                    Sv2 += f * ez;
-                    SE += f * vs;
-                }
-            }
+    double4 ai = make_double4(0.0, 0.0, 0.0, 0.0), bi = ai, di = ai;
+    double2 zi = make_double2(0.0, 0.0);
+    double bEi = 0.0;
+    if (live) {
+        ai = in.A[s];
+        bi = in.B[s];
+        di = in.Dw[s];
+        zi = in.C[s];
+        bEi = in.Ew[s];
+    }
+    const Stencil t = make_stencil(g, ai.x, ai.y, ai.z, pc.H);
+    const double invH = pc.invH, dwc = pc.dwc, H2 = pc.H2;
+    const int self = (int)s;
+    VjpAcc acc;
+    int qw = 0, qr = 0;
+    auto drain = [&]() {
+        const bool has = qr < qw;
+        const int j = has ? qj[qr & (kQ - 1)][tid] : 0;
+        qr += has ? 1 : 0;
+        const double4 aj = ld(in.A, j), bj = ld(in.B, j), dj = ld(in.Dw, j);
+        const double2 zj = ld(in.C, j);
+        const double bEj = ld(in.Ew, j);
+        const double dx = aj.x - ai.x, dy = aj.y - ai.y, dz = aj.z - ai.z;
+        const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
+        vjp_pair(has, dx, dy, dz, r2, ai, bi, zi, di, bEi, aj, bj, zj, dj, bEj, invH, dwc, acc);
+    };
+    int oy = t.R, oz = -t.R - 1;
+    int k = 0, j0 = 0, len = 0, jlast = 0;
+    for (;;) {
+        if (__any(qw - qr > kQ - kU)) {
+            drain();
+            continue;
         }
+        if (!__any(k < len)) {
+            if (++oy > t.R) {
+                oy = -t.R;
+                if (++oz > t.R) break;
+            }
+            const int zz = t.cz + oz;
+            const float gz = slab_gap(t.zc, zz);
+            row_range(cs, g, t, live, t.cy + oy, zz, gz * gz, j0, len);
+            jlast = len > 0 ? j0 + len - 1 : 0;
+            k = 0;
+            continue;
+        }
+        double4 aj[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) aj[u] = ld(in.A, min(j0 + k + u, jlast));
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int j = j0 + k + u;
+            const double dx = aj[u].x - ai.x, dy = aj[u].y - ai.y, dz = aj[u].z - ai.z;
+            const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
+            const bool ok = (k + u < len) && j != self && r2 < H2 && r2 != 0.0;
+            qj[qw & (kQ - 1)][tid] = j;
+            qw += ok ? 1 : 0;
+        }
+        k += kU;
+    }
+    while (__any(qr < qw)) drain();
+    if (live) {
+        double gr0 = acc.gr0, gr1 = acc.gr1, gr2 = acc.gr2, gv0 = acc.gv0, gv1 = acc.gv1,
+               gv2 = acc.gv2, gP = acc.gP, gZ = acc.gZ, gV = acc.gV;
+        const double Sr = acc.Sr, Sv0 = acc.Sv0, Sv1 = acc.Sv1, Sv2 = acc.Sv2, SE = acc.SE;
         // prefactors rho_i: dJ/drho_i += (a_rho R_rho - a_v.R_v - a_E R_E)/rho_i
         double rho = in.rho[s], E = in.E[s], m = in.m[s];
         double ar = in.a[0][s], ax = in.a[1][s], ay = in.a[2][s], az = in.a[3][s],
@@ -248,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
         __syncthreads();
     }
     if ((int)threadIdx.x < 2 * n_eos)
-        o.eos_part[(int64_t)blockIdx.x * 2 * CSPH_MAX_EOS + threadIdx.x] = sh[threadIdx.x][0];
+        o.eos_part[blk * 2 * CSPH_MAX_EOS + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 // g_eos[k] += sum over blocks of part[b][k], fixed order.

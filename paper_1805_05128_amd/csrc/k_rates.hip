@@ -7,6 +7,7 @@
 // particle sums its own partners (gather), so no floating-point atomics are
 // used and results do not depend on scheduling.
 #include "csph_internal.h"
+#include "stencil.h"
 
 namespace csph {
 
@@ -117,83 +118,6 @@ struct RateOut {
     unsigned long long *dtmin;
 };
 
-// ---------------------------------------------------------------- partner queues
-//
-// A candidate test costs ~20 instructions, a pair interaction ~50.  Testing
-// and interacting in the same loop would run the pair arithmetic whenever
-// any lane of the wave accepts a candidate, with the other lanes idle (a
-// particle accepts ~15-40 % of its candidates).  Instead each lane appends
-// its accepted partners to a small ring in LDS while the wave walks the
-// stencil in lock step, and as soon as some lane's ring is nearly full every
-// lane pops one partner and the wave runs the pair arithmetic with (nearly)
-// all lanes busy.  A lane's partners are summed in the order it popped them,
-// which depends only on the input: results are reproducible.
-//
-// Each stencil row (cells cx-R..cx+R at fixed y, z) is clipped to the chord
-// the support sphere of particle i cuts through it, with a safety margin,
-// so that with cells smaller than the support the lanes test little more
-// than the sphere.  The clipping only drops candidates that cannot be
-// partners; membership is decided by the pair test itself.
-
-constexpr int kQ = 8;  // ring slots per lane
-
-// Load base[idx] with a 32-bit byte offset from a wave-uniform base (records
-// stay below 4 GiB), which keeps the address arithmetic in one VGPR.
-template <typename T>
-__device__ __forceinline__ T ld(const T *__restrict__ base, int idx) {
-    return *(const T *)((const char *)base + (uint32_t)idx * (uint32_t)sizeof(T));
-}
-
-// Per-particle view of the stencil: cell, position in cell units, reach.
-struct Stencil {
-    int cx, cy, cz;
-    float xc, yc, zc;  // (x - origin) / D
-    float w2;          // (support/D)^2 with margin
-    int R;
-};
-
-__device__ __forceinline__ Stencil make_stencil(const GridDev &g, double x, double y, double z,
-                                                double H) {
-    Stencil t;
-    t.cx = cell_coord(x, g.ox, g.inv, g.dx);
-    t.cy = cell_coord(y, g.oy, g.inv, g.dy);
-    t.cz = cell_coord(z, g.oz, g.inv, g.dz);
-    t.xc = (float)((x - g.ox) * g.inv);
-    t.yc = (float)((y - g.oy) * g.inv);
-    t.zc = (float)((z - g.oz) * g.inv);
-    float hc = (float)(H * g.inv) * 1.0001f + 1e-3f;
-    t.w2 = hc * hc;
-    t.R = g.reach;
-    return t;
-}
-
-// Distance in cell units from coordinate c to the slab [k, k+1) (0 inside),
-// shrunk by a margin.
-__device__ __forceinline__ float slab_gap(float c, int k) {
-    float d = fmaxf(fmaxf((float)k - c, c - (float)(k + 1)), 0.0f);
-    return fmaxf(d - 1e-3f, 0.0f);
-}
-
-// Candidate range [j0, j0+len) of row (yy, zz) for a particle: the cells of
-// the row within the chord of its support sphere.  gz2 = squared z gap.
-// Branch-free: a row off the mesh or missing the sphere gets len = 0.
-__device__ __forceinline__ void row_range(const int32_t *__restrict__ cs, const GridDev &g,
-                                          const Stencil &t, bool on, int yy, int zz, float gz2,
-                                          int &j0, int &len) {
-    const bool inb = on && zz >= 0 && zz < g.dz && yy >= 0 && yy < g.dy;
-    const float gy = slab_gap(t.yc, yy);
-    const float rem = t.w2 - (gy * gy + gz2);
-    // chord half-width; v_sqrt_f32 (1 ulp) is ample under the margins
-    const float hw = __builtin_amdgcn_sqrtf(fmaxf(rem, 0.0f)) * 1.0001f + 1e-3f;
-    const int xa = max(max((int)floorf(t.xc - hw), t.cx - t.R), 0);
-    const int xb = min(min((int)floorf(t.xc + hw), t.cx + t.R), g.dx - 1);
-    const bool ok = inb && rem > 0.0f && xb >= xa;
-    const int row = (int)cell_key(g, 0, yy, zz);
-    const int ia = ok ? row + xa : 0, ib = ok ? row + xb + 1 : 0;
-    j0 = cs[ia];
-    len = cs[ib] - j0;
-}
-
 // ---------------------------------------------------------------- FP64 rates
 //
 // The pair step is written without branches: a lane with no partner to
@@ -236,8 +160,6 @@ __device__ __forceinline__ void pair64(bool use, double dx, double dy, double dz
     aE = use ? aE + f * vs : aE;
     sig = (use && sp > sig) ? sp : sig;
 }
-
-constexpr int kU = 2;  // candidates tested per lock-step iteration
 
 template <bool PAIR, bool WALL>
 struct Rates64 {
