@@ -149,15 +149,18 @@ __device__ __forceinline__ void pair64(bool use, double dx, double dy, double dz
     const double iS = 1.0 / (sok ? S : 1.0);
     const double vs = sok ? ((Zi * vL + Zj * vR) + (Pi - Pj)) * iS : 0.5 * (vL + vR);
     const double ps = sok ? ((Zj * Pi + Zi * Pj) + Zi * Zj * (vL - vR)) * iS : 0.5 * (Pi + Pj);
-    const double wgt = Vj * dW;
-    const double f = wgt * ps;
+    // a lane without a partner adds exact zeros (weight selected to 0, partner-dependent
+    // factors selected to finite values; offsets and r are finite)
+    const double wgt = use ? Vj * dW : 0.0;
+    const double vsm = use ? vs : vL, psm = use ? ps : 0.0;
+    const double f = wgt * psm;
     const double cl = vL - vR;
     const double sp = fmax(ci.y, cj) + (cl > 0.0 ? cl : 0.0);
-    ar = use ? ar + wgt * (vL - vs) : ar;
-    avx = use ? avx + f * ex : avx;
-    avy = use ? avy + f * ey : avy;
-    avz = use ? avz + f * ez : avz;
-    aE = use ? aE + f * vs : aE;
+    ar += wgt * (vL - vsm);
+    avx += f * ex;
+    avy += f * ey;
+    avz += f * ez;
+    aE += f * vsm;
     sig = (use && sp > sig) ? sp : sig;
 }
 
@@ -338,20 +341,26 @@ __device__ __forceinline__ void pair32(bool use, float dx, float dy, float dz, f
     const float vL = (bi.x * ex + bi.y * ey) + bi.z * ez;
     const float Zi = ci.x, Pi = bi.w;
     const float S = Zi + Zj;
+    // v_L - v* and P*; S = 0 (both impedances zero) takes the mean state, written as
+    // the same expressions with Z_i = Z_j = 1 and the P and (v_L - v_R) terms dropped
     const bool sok = S != 0.0f;
-    const float iS = __builtin_amdgcn_rcpf(sok ? S : 1.0f);
-    // v_L - v*, P*
-    const float dvl = sok ? (Zj * vrel - (Pi - Pj)) * iS : 0.5f * vrel;
-    const float ps = sok ? ((Zj * Pi + Zi * Pj) + Zi * Zj * vrel) * iS : 0.5f * (Pi + Pj);
-    const float vs = vL - dvl;
-    const float wgt = Vj * dW;
-    const float f = wgt * ps;
+    const float iS = __builtin_amdgcn_rcpf(sok ? S : 2.0f);
+    const float Zjd = sok ? Zj : 1.0f, Zid = sok ? Zi : 1.0f;
+    const float dP = sok ? Pi - Pj : 0.0f, ZZ = sok ? Zi * Zj : 0.0f;
+    const float dvl = (Zjd * vrel - dP) * iS;
+    const float ps = ((Zjd * Pi + Zid * Pj) + ZZ * vrel) * iS;
+    // a lane without a partner adds exact zeros: its weight and the two factors that carry
+    // partner data are selected to 0, every other factor is finite (r2 = 1, finite offsets)
+    const float dvlm = use ? dvl : 0.0f, psm = use ? ps : 0.0f;
+    const float wgt = use ? Vj * dW : 0.0f;
+    const float vs = vL - dvlm;
+    const float f = wgt * psm;
     const float sp = fmaxf(ci.y, cj) + fmaxf(vrel, 0.0f);
-    ar = use ? ar + wgt * dvl : ar;
-    avx = use ? avx + f * ex : avx;
-    avy = use ? avy + f * ey : avy;
-    avz = use ? avz + f * ez : avz;
-    aE = use ? aE + f * vs : aE;
+    ar += wgt * dvlm;
+    avx += f * ex;
+    avy += f * ey;
+    avz += f * ez;
+    aE += f * vs;
     sig = (use && sp > sig) ? sp : sig;
 }
 
@@ -385,6 +394,7 @@ struct Rates32 {
 
     // every lane pops its next partner, if it has one
     __device__ __forceinline__ void drain() {
+#pragma clang fp contract(fast)
         const bool has = qr < qw;
         const float4 q = qd[qr & (kQ - 1)][tid];
         qr += has ? 1 : 0;
@@ -481,6 +491,9 @@ __global__ __launch_bounds__(kBlock) void k_rates32(int64_t n, const float4 *__r
                                                     PairConst pc, const double *t_dev,
                                                     double t_host, RateOut o, int want_dt) {
     __shared__ float4 qd[kQ][kBlock];
+    // finite placeholder offsets for lanes that pop from an empty ring
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) qd[q][threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
     Rates32<PAIR, WALL> k;
     k.A = A;
     k.B = B;

@@ -81,8 +81,8 @@ __device__ __forceinline__ void row_range(const int32_t *__restrict__ cs, const 
     const bool ok = inb && rem > 0.0f && xb >= xa;
     const int row = (int)cell_key(g, 0, yy, zz);
     const int ia = ok ? row + xa : 0, ib = ok ? row + xb + 1 : 0;
-    j0 = cs[ia];
-    len = cs[ib] - j0;
+    j0 = ld(cs, ia);
+    len = ld(cs, ib) - j0;
 }
 
 }  // namespace csph
