@@ -234,6 +234,37 @@ csph_status voronoi_assign(const double *x, const double *y, const double *z, in
                            int32_t *owner, int64_t *site_particles, int64_t *site_pairs,
                            csph_stream stream);
 
+/* Verlet lists (sec. 4.2): the partners of each particle within the horizon
+ * R = (1 + beta) H, for reuse over several steps.  Fixed-h mode only.
+ *   s_in -> s_out: the state renumbered into cell order (as csph_step with
+ *     reorder = 1 does; s_out distinct from s_in; mat, id, d carried along).
+ *     The lists index s_out's order.
+ *   vl_count[n]: list lengths; vl_idx[n * cap] (device): the partners of particle
+ *     s at vl_idx[s cap + k], k < vl_count[s]; j != s with r^2 < R^2 in FP64
+ *     without contraction; a partner mirrored across the piston wall (at time *t,
+ *     device) has the sign bit set.
+ *   x_ref[3 n] (device): the positions at build, x..., y..., z....
+ *   *max_count (host, optional): 0, or the longest list when it exceeds cap; then the
+ *     lists are truncated and the call returns CSPH_ECAPACITY.
+ * Synchronises (mesh bounds, wall time, list overflow). */
+csph_status csph_vlist_build(const csph_state *s_in, csph_state *s_out, const csph_params *p,
+                             const double *t, double beta, int32_t cap, int32_t *vl_count,
+                             int32_t *vl_idx, double *x_ref, int32_t *max_count, void *ws,
+                             size_t ws_bytes, size_t *ws_needed, csph_stream stream);
+
+/* One step from Verlet lists, in place on s (in the lists' order): the rates
+ * take the listed partners with r^2 < H^2 (FP64 test), which is N(i) exactly
+ * while no pair can have entered the support from beyond the horizon, i.e.
+ * while 2 max_i |r_i - r_ref,i| + 2 |v_wall| (t - t_build) < beta H; the
+ * caller keeps that true by rebuilding.  Then the update of csph_step (dt,
+ * totals, nbr_count, nonphys as there), and *disp (device, optional) =
+ * max_i |r_i - r_ref,i| after the update.  Asynchronous. */
+csph_status csph_step_vlist(csph_state *s, const csph_params *p, double *t, double dt_in,
+                            double *dt_used, double *totals, int32_t *nbr_count,
+                            int64_t *nonphys, const int32_t *vl_count, const int32_t *vl_idx,
+                            int32_t cap, const double *x_ref, double *disp, void *ws,
+                            size_t ws_bytes, size_t *ws_needed, csph_stream stream);
+
 /* Voronoi load balancer (sec. 3).  Generators, centres: K x 3 row-major
  * FP64 (device); 1 <= K <= 512.  Adjacency: K rows of W = ceil(K/32)
  * uint32 words; bit (l % 32) of word [k W + l/32] set iff subdomains k and l

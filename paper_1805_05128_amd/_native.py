@@ -133,6 +133,14 @@ def load():
     L.csph_init_energy_vjp.argtypes = [_dp, _dp, _dp, _dp, _dp, _ip, C.c_int64,
                                        C.POINTER(CsphParams), _dp, _dp, _dp, _dp, _dp, _dp, vp,
                                        sz, szp, vp]
+    L.csph_vlist_build.restype = C.c_int32
+    L.csph_vlist_build.argtypes = [C.POINTER(CsphState), C.POINTER(CsphState),
+                                   C.POINTER(CsphParams), _dp, C.c_double, C.c_int32, _ip, _ip,
+                                   _dp, C.POINTER(C.c_int32), vp, sz, szp, vp]
+    L.csph_step_vlist.restype = C.c_int32
+    L.csph_step_vlist.argtypes = [C.POINTER(CsphState), C.POINTER(CsphParams), _dp, C.c_double,
+                                  _dp, _dp, _ip, _lp, _ip, _ip, C.c_int32, _dp, _dp, vp, sz,
+                                  szp, vp]
     L.csph_balance_workspace_size.restype = sz
     L.csph_balance_workspace_size.argtypes = [C.c_int32]
     L.csph_balance_stats.restype = C.c_int32

@@ -506,3 +506,109 @@ def csph_balance_move(sites: torch.Tensor, stats: Dict[str, torch.Tensor], bp: B
                              _stream(stream))
     N.check(st, "csph_balance_move")
     return new, ms
+
+
+# ------------------------------------------------------------------ Verlet lists
+
+def csph_vlist_build(s_in: State, s_out: State, params: Params, sc: StepScalars, beta: float,
+                     cap: int, count: torch.Tensor, idx: torch.Tensor, x_ref: torch.Tensor,
+                     ws: Optional[Workspace] = None, stream=None) -> int:
+    """Renumber s_in into cell order in s_out and build the horizon lists; returns 0, or the
+    longest list when it exceeds ``cap`` (the lists are then truncated)."""
+    L = N.load()
+    ws = ws or default_workspace(s_in["x"].device)
+    a, b_ = s_in.c(), s_out.c()
+    p = params.c()
+    mx = C.c_int32(0)
+    needed = C.c_size_t(0)
+    for _ in range(3):
+        st = L.csph_vlist_build(C.byref(a), C.byref(b_), C.byref(p), _dp(sc.t), float(beta),
+                                int(cap), _ip(count), _ip(idx), _dp(x_ref), C.byref(mx), ws.ptr,
+                                ws.nbytes, C.byref(needed), _stream(stream))
+        if st == N.CSPH_ECAPACITY and mx.value == 0 and needed.value > ws.nbytes:
+            ws.ensure(needed.value)
+            continue
+        if st == N.CSPH_ECAPACITY and mx.value > 0:
+            return int(mx.value)
+        N.check(st, "csph_vlist_build")
+        return 0
+    N.check(st, "csph_vlist_build")
+    return 0
+
+
+def csph_step_vlist(s: State, params: Params, sc: StepScalars, count, idx, cap: int, x_ref,
+                    disp: Optional[torch.Tensor] = None, dt_in: float = 0.0,
+                    nbr_count: Optional[torch.Tensor] = None, ws: Optional[Workspace] = None,
+                    stream=None, totals: bool = True) -> State:
+    """One step in place from Verlet lists (s in the lists' order)."""
+    L = N.load()
+    ws = ws or default_workspace(s["x"].device)
+    a = s.c()
+    p = params.c()
+    _with_ws(lambda w, nb, nd: L.csph_step_vlist(
+        C.byref(a), C.byref(p), _dp(sc.t), float(dt_in), _dp(sc.dt),
+        _dp(sc.totals) if totals else None, _ip(nbr_count), _lp(sc.nonphys), _ip(count),
+        _ip(idx), int(cap), _dp(x_ref), _dp(disp), w, nb, nd, _stream(stream)), ws,
+        "csph_step_vlist")
+    return s
+
+
+class VerletRun:
+    """Steps from Verlet lists (sec. 4.2): lists of the partners within (1 + beta) H are
+    rebuilt every ``n_upd`` steps, and earlier when the displacement bound
+    2 max|r - r_ref| + 2 |v_wall| (t - t_build) reaches beta H, so that every step
+    evaluates exactly N(i).  The state is renumbered into cell order at each rebuild.
+    ``cap`` is the list capacity per particle (grown on overflow)."""
+
+    def __init__(self, state: State, params: Params, beta: float = 0.3, n_upd: int = 10,
+                 cap: Optional[int] = None, ws: Optional[Workspace] = None):
+        if params.h_mode != "fixed":
+            raise ValueError("Verlet lists need fixed-h mode")
+        self.params, self.beta, self.n_upd = params, float(beta), int(n_upd)
+        self.ws = ws or default_workspace(state["x"].device)
+        n = state.n
+        dev = state["x"].device
+        H = params.kappa * params.h
+        # partners within (1 + beta) H on a unit-density lattice, with room for compression
+        self.cap = int(cap) if cap else int(4.5 * ((1.0 + self.beta) * H) ** 3) + 32
+        self.state, self.other = state, state.like()
+        self.count = torch.zeros(max(n, 1), dtype=torch.int32, device=dev)
+        self.idx = torch.empty(max(n, 1) * self.cap, dtype=torch.int32, device=dev)
+        self.x_ref = torch.empty(3 * max(n, 1), dtype=torch.float64, device=dev)
+        self.disp = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.since = None
+        self.t_build = 0.0
+        self.builds = 0
+        self.H = H
+
+    def _build(self, sc: StepScalars):
+        while True:
+            over = csph_vlist_build(self.state, self.other, self.params, sc, self.beta, self.cap,
+                                    self.count, self.idx, self.x_ref, ws=self.ws)
+            if over == 0:
+                break
+            self.cap = int(over * 1.25) + 8
+            self.idx = torch.empty(max(self.state.n, 1) * self.cap, dtype=torch.int32,
+                                   device=self.idx.device)
+        self.state, self.other = self.other, self.state
+        self.disp.zero_()
+        self.since = 0
+        self.t_build = float(sc.t.item())
+        self.builds += 1
+
+    def needs_build(self, sc: StepScalars) -> bool:
+        if self.since is None or self.since >= self.n_upd:
+            return True
+        vw = abs(self.params.wall[1]) if self.params.wall is not None else 0.0
+        bound = 2.0 * float(self.disp.item()) + 2.0 * vw * (float(sc.t.item()) - self.t_build)
+        return not (bound < self.beta * self.H)
+
+    def step(self, sc: StepScalars, nbr_count: Optional[torch.Tensor] = None,
+             dt_in: float = 0.0, totals: bool = True) -> State:
+        if self.needs_build(sc):
+            self._build(sc)
+        csph_step_vlist(self.state, self.params, sc, self.count, self.idx, self.cap, self.x_ref,
+                        disp=self.disp, dt_in=dt_in, nbr_count=nbr_count, ws=self.ws,
+                        totals=totals)
+        self.since += 1
+        return self.state

@@ -512,6 +512,129 @@ csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_para
     return CSPH_OK;
 }
 
+csph_status csph_vlist_build(const csph_state *s_in, csph_state *s_out, const csph_params *p,
+                             const double *t, double beta, int32_t cap, int32_t *vl_count,
+                             int32_t *vl_idx, double *x_ref, int32_t *max_count, void *ws,
+                             size_t ws_bytes, size_t *ws_needed, csph_stream stream) {
+    g_err[0] = 0;
+    if (!state_ok(s_in) || !state_ok(s_out) || s_in->n != s_out->n || s_in->n >= INT32_MAX)
+        return fail(CSPH_EINVAL, "bad state");
+    csph_status r = check_params(p, false, nullptr);
+    if (r) return r;
+    if (p->h_mode != CSPH_H_FIXED) return fail(CSPH_EINVAL, "Verlet lists need fixed-h mode");
+    if (!(beta >= 0.0) || !std::isfinite(beta)) return fail(CSPH_EINVAL, "beta must be >= 0");
+    if (cap < 1) return fail(CSPH_EINVAL, "cap must be >= 1");
+    const int64_t n = s_in->n;
+    if (n > 0 && (!vl_count || !vl_idx || !x_ref))
+        return fail(CSPH_EINVAL, "vl_count, vl_idx and x_ref are required");
+    if (n > 0 && (s_in->x == s_out->x || s_in->vx == s_out->vx || s_in->rho == s_out->rho ||
+                  s_in->E == s_out->E || s_in->m == s_out->m))
+        return fail(CSPH_EINVAL, "s_out must be distinct from s_in");
+    if ((s_in->mat && !s_out->mat) || (s_in->id && !s_out->id))
+        return fail(CSPH_EINVAL, "s_out must carry mat/id when s_in does");
+    if (p->wall && !t) return fail(CSPH_EINVAL, "the wall position needs t");
+    hipStream_t st = (hipStream_t)stream;
+    // the mesh must reach the horizon (1 + beta) H
+    csph_params ph = *p;
+    ph.kappa = p->kappa * (1.0 + beta);
+    csph_grid g;
+    double dmax;
+    r = make_grid(s_in->x, s_in->y, s_in->z, nullptr, n, &ph, ws, ws_bytes, st, &g, &dmax);
+    if (r) return r;
+    r = need_ws(ws_bytes, n, g.ncell, ws_needed);
+    if (r) return r;
+    if (max_count) *max_count = 0;
+    if (n == 0) return CSPH_OK;
+    Ws w;
+    ws_layout(&w, ws, n, g.ncell);
+    GridDev gd = grid_dev(g);
+    EosDev eos = eos_dev(p);
+    double *o[9] = {s_out->x, s_out->y, s_out->z, s_out->vx, s_out->vy, s_out->vz,
+                    s_out->rho, s_out->E, s_out->m};
+    double twall = 0.0;
+    if (p->wall) CSPH_HIP(hipMemcpyAsync(&twall, t, sizeof(double), hipMemcpyDeviceToHost, st));
+    {
+        ProfScope pr(CSPH_PROF_BIN, st);
+        CSPH_HIP(launch_bin(s_in->x, s_in->y, s_in->z, n, gd, w, w.perm, nullptr, w.cs, st));
+        CSPH_HIP(launch_pack(*s_in, n, w.perm, eos, 0, gd, w, o, s_out->mat,
+                             s_out->d && s_in->d ? s_out->d : nullptr, s_out->id, s_in->id,
+                             nullptr, st));
+    }
+    CSPH_HIP(hipStreamSynchronize(st));  // twall
+    const double H = p->kappa * p->h;
+    const double R = (1.0 + beta) * H;
+    const double xw = p->wall ? p->wall_x0 + p->wall_v * twall : 0.0;
+    unsigned long long over = 0;
+    {
+        ProfScope pr(CSPH_PROF_NEIGHBORS, st);
+        CSPH_HIP(launch_fill_u64((unsigned long long *)w.nonphys, 0ull, 1, st));
+        CSPH_HIP(launch_vlist(n, s_out->x, s_out->y, s_out->z, w.cs, gd, R, p->wall, xw, cap,
+                              vl_count, vl_idx, (unsigned long long *)w.nonphys, st));
+        for (int a = 0; a < 3; ++a)
+            CSPH_HIP(hipMemcpyAsync(x_ref + a * n, o[a], sizeof(double) * n,
+                                    hipMemcpyDeviceToDevice, st));
+        CSPH_HIP(hipMemcpyAsync(&over, w.nonphys, sizeof(over), hipMemcpyDeviceToHost, st));
+    }
+    CSPH_HIP(hipStreamSynchronize(st));
+    if (max_count) *max_count = (int32_t)(over > (unsigned long long)cap ? over : 0);
+    if (over > (unsigned long long)cap)
+        return fail(CSPH_ECAPACITY, "a Verlet list holds %llu partners, cap is %d", over, cap);
+    return CSPH_OK;
+}
+
+csph_status csph_step_vlist(csph_state *s, const csph_params *p, double *t, double dt_in,
+                            double *dt_used, double *totals, int32_t *nbr_count,
+                            int64_t *nonphys, const int32_t *vl_count, const int32_t *vl_idx,
+                            int32_t cap, const double *x_ref, double *disp, void *ws,
+                            size_t ws_bytes, size_t *ws_needed, csph_stream stream) {
+    g_err[0] = 0;
+    if (!state_ok(s) || s->n >= INT32_MAX) return fail(CSPH_EINVAL, "bad state");
+    csph_status r = check_params(p, false, nullptr);
+    if (r) return r;
+    if (p->h_mode != CSPH_H_FIXED) return fail(CSPH_EINVAL, "Verlet lists need fixed-h mode");
+    if (!(p->cfl > 0.0) && !(std::isfinite(dt_in) && dt_in >= 0.0))
+        return fail(CSPH_EINVAL, "cfl <= 0 needs a finite dt_in >= 0");
+    const int64_t n = s->n;
+    if (n > 0 && (!vl_count || !vl_idx || !x_ref || cap < 1))
+        return fail(CSPH_EINVAL, "vl_count, vl_idx, x_ref and cap >= 1 are required");
+    hipStream_t st = (hipStream_t)stream;
+    r = need_ws(ws_bytes, n, 1, ws_needed);
+    if (r) return r;
+    Ws w;
+    ws_layout(&w, ws, n, 1);
+    GridDev gd;
+    memset(&gd, 0, sizeof(gd));  // no mesh: the lists name the partners
+    PairConst pc = pair_const(p, 0.0);
+    EosDev eos = eos_dev(p);
+    const int mixed = p->precision == CSPH_MIXED;
+    double *cur[9] = {s->x, s->y, s->z, s->vx, s->vy, s->vz, s->rho, s->E, s->m};
+    if (n > 0) {
+        ProfScope pr(CSPH_PROF_PACK, st);
+        CSPH_HIP(launch_pack(*s, n, nullptr, eos, mixed, gd, w, nullptr, nullptr, nullptr,
+                             nullptr, nullptr, nonphys, st));
+    }
+    if (p->cfl > 0.0)
+        CSPH_HIP(launch_fill_u64(w.dtmin, n > 0 ? 0x7ff0000000000000ull : 0ull, 1, st));
+    if (n > 0) {
+        ProfScope pr(CSPH_PROF_RATES, st);
+        CSPH_HIP(launch_rates(n, mixed, gd, pc, w, cur, nullptr, t, 0.0, p->cfl > 0.0, st,
+                              vl_count, vl_idx, cap));
+    }
+    {
+        ProfScope pr(CSPH_PROF_INTEGRATE, st);
+        CSPH_HIP(launch_integrate(n, cur, w, p->cfl, dt_in, st));
+        CSPH_HIP(launch_finish_step(n, w, p->cfl, dt_in, t, dt_used, totals, st));
+        if (disp) {
+            CSPH_HIP(launch_fill_u64((unsigned long long *)disp, 0ull, 1, st));
+            CSPH_HIP(launch_disp(n, s->x, s->y, s->z, x_ref, (unsigned long long *)disp, st));
+        }
+    }
+    if (n > 0 && nbr_count)
+        CSPH_HIP(hipMemcpyAsync(nbr_count, w.cnt, sizeof(int32_t) * n, hipMemcpyDeviceToDevice,
+                                st));
+    return CSPH_OK;
+}
+
 csph_status voronoi_assign(const double *x, const double *y, const double *z, int64_t n,
                            const double *sites, int32_t K, const int32_t *nbr_count,
                            int32_t *owner, int64_t *site_particles, int64_t *site_pairs,

@@ -190,7 +190,16 @@ hipError_t launch_pack(const csph_state &s, int64_t n, const int32_t *perm, cons
 // sorted: the cell-ordered FP64 state (x y z vx vy vz rho E m) the records were packed from.
 hipError_t launch_rates(int64_t n, int mixed, const GridDev &g, const PairConst &pc,
                         const Ws &w, double *const sorted[9], const double *d_sorted,
-                        const double *t_dev, double t_host, int want_dt, hipStream_t st);
+                        const double *t_dev, double t_host, int want_dt, hipStream_t st,
+                        const int32_t *vl_count = nullptr, const int32_t *vl_idx = nullptr,
+                        int vl_cap = 0);
+// k_vlist.hip
+hipError_t launch_vlist(int64_t n, const double *x, const double *y, const double *z,
+                        const int32_t *cs, const GridDev &g, double R, int wall, double xw,
+                        int cap, int32_t *count, int32_t *idx, unsigned long long *over,
+                        hipStream_t st);
+hipError_t launch_disp(int64_t n, const double *x, const double *y, const double *z,
+                       const double *ref, unsigned long long *out, hipStream_t st);
 hipError_t launch_unsort_rates(int64_t n, const int32_t *perm, const Ws &w, csph_rates_out out,
                                double *signal, int32_t *nbr_count, hipStream_t st);
 

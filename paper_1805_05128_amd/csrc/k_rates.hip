@@ -38,12 +38,14 @@ __global__ __launch_bounds__(kBlock) void k_pack(int64_t n, SrcState src,
                                                  int64_t *__restrict__ nonphys) {
     int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s >= n) return;
-    int i = perm[s];
+    const int i = perm ? perm[s] : (int)s;  // no permutation: records of the state in place
     double v[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) v[k] = src.f[k][i];
+    if (dst.f[0]) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) dst.f[k][s] = v[k];
+        for (int k = 0; k < 9; ++k) dst.f[k][s] = v[k];
+    }
     int mt = src.mat ? src.mat[i] : 0;
     if (dst.mat) dst.mat[s] = mt;
     if (src.d && dst.d) dst.d[s] = src.d[i];
@@ -59,6 +61,7 @@ __global__ __launch_bounds__(kBlock) void k_pack(int64_t n, SrcState src,
     if (bad && nonphys) atomicAdd((unsigned long long *)nonphys, 1ull);
     double Z = rho * c, V = m / rho;
     if (MIXED) {
+        if (recA) {  // cell-relative offsets (stencil walks only)
         int cx = cell_coord(x, g.ox, g.inv, g.dx);
         int cy = cell_coord(y, g.oy, g.inv, g.dy);
         int cz = cell_coord(z, g.oz, g.inv, g.dz);
@@ -67,6 +70,7 @@ __global__ __launch_bounds__(kBlock) void k_pack(int64_t n, SrcState src,
         float oz = (float)(z - (g.oz + (double)cz * g.cell));
         // x offset, y, z offsets from the cell origin and the cell's x index
         ((float4 *)recA)[s] = make_float4(ox, oy, oz, (float)cx);
+        }
         ((float4 *)recB)[s] = make_float4((float)vx, (float)vy, (float)vz, (float)P);
         ((float4 *)recC)[s] = make_float4((float)Z, (float)c, (float)V, 0.0f);
     } else {
@@ -83,16 +87,19 @@ hipError_t launch_pack(const csph_state &s, int64_t n, const int32_t *perm, cons
     if (n <= 0) return hipSuccess;
     SrcState src{{s.x, s.y, s.z, s.vx, s.vy, s.vz, s.rho, s.E, s.m}, s.mat, s.d, src_id};
     DstState ds;
-    for (int k = 0; k < 9; ++k) ds.f[k] = dst[k];
+    for (int k = 0; k < 9; ++k) ds.f[k] = dst ? dst[k] : nullptr;
     ds.mat = dst_mat;
     ds.d = dst_d;
     ds.id = dst_id;
+    // perm = NULL: records of the state as it is (Verlet steps); the FP32 cell-relative
+    // A record is then not written
+    void *recA = (mixed && !perm) ? nullptr : w.recA;
     unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
     if (mixed)
-        k_pack<true><<<nb, kBlock, 0, st>>>(n, src, perm, eos, g, w.recA, w.recB, w.recC, ds,
+        k_pack<true><<<nb, kBlock, 0, st>>>(n, src, perm, eos, g, recA, w.recB, w.recC, ds,
                                             nonphys);
     else
-        k_pack<false><<<nb, kBlock, 0, st>>>(n, src, perm, eos, g, w.recA, w.recB, w.recC, ds,
+        k_pack<false><<<nb, kBlock, 0, st>>>(n, src, perm, eos, g, recA, w.recB, w.recC, ds,
                                              nonphys);
     return hipGetLastError();
 }
@@ -111,6 +118,14 @@ __device__ __forceinline__ void block_min_to(double v, unsigned long long *dst) 
         if (r >= 0.0) atomicMin(dst, dbits(r));
     }
 }
+
+// Verlet lists (sec. 4.2): partners of particle s at idx[s*cap .. s*cap+count[s]),
+// a mirror partner with the sign bit set.  Absent (idx = NULL) for stencil walks.
+struct VList {
+    const int32_t *count;
+    const int32_t *idx;
+    int cap;
+};
 
 struct RateOut {
     double *rho, *vx, *vy, *vz, *E, *sig;
@@ -181,7 +196,7 @@ struct Rates64 {
     double di, xw, vw2;
     Stencil t;
     double ar = 0.0, avx = 0.0, avy = 0.0, avz = 0.0, aE = 0.0, sig = 0.0;
-    int qw = 0, qr = 0;
+    int qw = 0, qr = 0, cntl = 0;
 
     // every lane pops its next partner, if it has one
     __device__ __forceinline__ void drain() {
@@ -254,9 +269,40 @@ struct Rates64 {
             k += kU;
         }
     }
+
+    // Verlet-list walk: the lane's own list in chunks of kU, exact FP64 membership
+    // (mirror partners across the wall for flagged entries)
+    __device__ __forceinline__ void pass_list(const int32_t *__restrict__ lst, int len) {
+        int k = 0;
+        for (;;) {
+            if (__any(qw - qr > kQ - kU)) {
+                drain();
+                continue;
+            }
+            if (!__any(k < len)) break;
+            int e[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) e[u] = (k + u < len) ? lst[k + u] : 0;
+            double4 aj[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) aj[u] = ld(A, e[u] & 0x7fffffff);
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const bool ghost = WALL && e[u] < 0;
+                const double xj = ghost ? 2.0 * xw - aj[u].x : aj[u].x;
+                const double dx = xj - a.x, dy = aj[u].y - a.y, dz = aj[u].z - a.z;
+                const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
+                const bool acc = (k + u < len) && r2 < pc.H2;
+                qj[qw & (kQ - 1)][tid] = e[u];
+                qw += acc ? 1 : 0;
+                cntl += (acc && !ghost) ? 1 : 0;
+            }
+            k += kU;
+        }
+    }
 };
 
-template <bool PAIR, bool WALL>
+template <bool PAIR, bool WALL, bool LIST>
 __global__ __launch_bounds__(kBlock) void k_rates64(int64_t n, const double4 *__restrict__ A,
                                                     const double4 *__restrict__ B,
                                                     const double2 *__restrict__ Cz,
@@ -264,7 +310,8 @@ __global__ __launch_bounds__(kBlock) void k_rates64(int64_t n, const double4 *__
                                                     const double *__restrict__ dsz,
                                                     const int32_t *__restrict__ cs, GridDev g,
                                                     PairConst pc, const double *t_dev,
-                                                    double t_host, RateOut o, int want_dt) {
+                                                    double t_host, RateOut o, int want_dt,
+                                                    VList vl) {
     __shared__ int qj[kQ][kBlock];
     Rates64<PAIR, WALL> k;
     k.A = A;
@@ -300,9 +347,16 @@ __global__ __launch_bounds__(kBlock) void k_rates64(int64_t n, const double4 *__
         k.vw2 = 2.0 * pc.wall_v;
         k.near_wall = k.live && (k.a.x - k.xw < pc.H);
     }
-    k.template pass<false>();
-    const int cnt = k.qw;  // real partners accepted
-    if (WALL && __any(k.near_wall)) k.template pass<true>();
+    int cnt;
+    if (LIST) {
+        const int len = k.live ? min(vl.count[s], vl.cap) : 0;
+        k.pass_list(vl.idx + (k.live ? s * (int64_t)vl.cap : 0), len);
+        cnt = k.cntl;
+    } else {
+        k.template pass<false>();
+        cnt = k.qw;  // real partners accepted
+        if (WALL && __any(k.near_wall)) k.template pass<true>();
+    }
     while (__any(k.qr < k.qw)) k.drain();
     double dtv = INFINITY;
     if (k.live) {
@@ -370,7 +424,7 @@ __device__ __forceinline__ void pair32(bool use, float dx, float dy, float dz, f
 // is below 1e-6 relative for offsets within a few cells).
 constexpr float kBand = 4e-5f;
 
-template <bool PAIR, bool WALL>
+template <bool PAIR, bool WALL, bool LIST>
 struct Rates32 {
     const float4 *__restrict__ A;
     const float4 *__restrict__ B;
@@ -414,8 +468,9 @@ struct Rates32 {
             dwc = (float)(210.0 / M_PI) * (i2 * i2);
         }
         const float r2 = (q.x * q.x + q.y * q.y) + q.z * q.z;
-        bool in = has && r2 < H2lo;
-        if (has && !(r2 < H2lo)) {
+        // a list walk queues exact FP64 members only
+        bool in = has && (LIST || r2 < H2lo);
+        if (!LIST && has && !(r2 < H2lo)) {
             // near the support: decide membership in FP64 (rare)
             const double xj = ghost ? 2.0 * xw - xs[j] : xs[j];
             const double ex = xj - xi, ey = ys[j] - yi, ez = zs[j] - zi;
@@ -476,9 +531,39 @@ struct Rates32 {
             k += kU;
         }
     }
+
+    // Verlet-list walk: exact FP64 membership from the FP64 positions; the ring takes
+    // the FP32 offsets (mirrored for flagged entries)
+    __device__ __forceinline__ void pass_list(const int32_t *__restrict__ lst, int len) {
+        int k = 0;
+        for (;;) {
+            if (__any(qw - qr > kQ - kU)) {
+                drain();
+                continue;
+            }
+            if (!__any(k < len)) break;
+            int e[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) e[u] = (k + u < len) ? lst[k + u] : 0;
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int j = e[u] & 0x7fffffff;
+                const bool ghost = WALL && e[u] < 0;
+                const double xr = ld(xs, j);
+                const double xj = ghost ? 2.0 * xw - xr : xr;
+                const double dx = xj - xi, dy = ld(ys, j) - yi, dz = ld(zs, j) - zi;
+                const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
+                const bool acc = (k + u < len) && r2 < pc.H2;
+                qd[qw & (kQ - 1)][tid] =
+                    make_float4((float)dx, (float)dy, (float)dz, __int_as_float(e[u]));
+                qw += acc ? 1 : 0;
+            }
+            k += kU;
+        }
+    }
 };
 
-template <bool PAIR, bool WALL>
+template <bool PAIR, bool WALL, bool LIST>
 __global__ __launch_bounds__(kBlock) void k_rates32(int64_t n, const float4 *__restrict__ A,
                                                     const float4 *__restrict__ B,
                                                     const float4 *__restrict__ Cz,
@@ -489,12 +574,13 @@ __global__ __launch_bounds__(kBlock) void k_rates32(int64_t n, const float4 *__r
                                                     const double *__restrict__ dsz,
                                                     const int32_t *__restrict__ cs, GridDev g,
                                                     PairConst pc, const double *t_dev,
-                                                    double t_host, RateOut o, int want_dt) {
+                                                    double t_host, RateOut o, int want_dt,
+                                                    VList vl) {
     __shared__ float4 qd[kQ][kBlock];
     // finite placeholder offsets for lanes that pop from an empty ring
 #pragma unroll
     for (int q = 0; q < kQ; ++q) qd[q][threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
-    Rates32<PAIR, WALL> k;
+    Rates32<PAIR, WALL, LIST> k;
     k.A = A;
     k.B = B;
     k.Cz = Cz;
@@ -540,8 +626,13 @@ __global__ __launch_bounds__(kBlock) void k_rates32(int64_t n, const float4 *__r
         k.wd = (float)(k.xw - k.xi);
         k.vw2 = (float)(2.0 * pc.wall_v);
     }
-    k.template pass<false>();
-    if (WALL && __any(k.near_wall)) k.template pass<true>();
+    if (LIST) {
+        const int len = k.live ? min(vl.count[s], vl.cap) : 0;
+        k.pass_list(vl.idx + (k.live ? s * (int64_t)vl.cap : 0), len);
+    } else {
+        k.template pass<false>();
+        if (WALL && __any(k.near_wall)) k.template pass<true>();
+    }
     while (__any(k.qr < k.qw)) k.drain();
     double dtv = INFINITY;
     if (k.live) {
@@ -562,31 +653,37 @@ __global__ __launch_bounds__(kBlock) void k_rates32(int64_t n, const float4 *__r
 
 hipError_t launch_rates(int64_t n, int mixed, const GridDev &g, const PairConst &pc,
                         const Ws &w, double *const sorted[9], const double *d_sorted,
-                        const double *t_dev, double t_host, int want_dt, hipStream_t st) {
+                        const double *t_dev, double t_host, int want_dt, hipStream_t st,
+                        const int32_t *vl_count, const int32_t *vl_idx, int vl_cap) {
     if (n <= 0) return hipSuccess;
     const double *rho_sorted = sorted[6];
     RateOut o{w.rate[0], w.rate[1], w.rate[2], w.rate[3], w.rate[4], w.sig, w.cnt, w.dtmin};
+    VList vl{vl_count, vl_idx, vl_cap};
     unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
-    bool pair = pc.pair_mode != 0, wall = pc.wall != 0;
-#define CSPH_RATES_CASE(P, W)                                                                  \
-    if (pair == P && wall == W) {                                                              \
+    const bool pair = pc.pair_mode != 0, wall = pc.wall != 0, list = vl_idx != nullptr;
+    if (list && pair) return hipErrorInvalidValue;
+#define CSPH_RATES_CASE(P, W, L)                                                               \
+    if (pair == P && wall == W && list == L) {                                                 \
         if (mixed)                                                                             \
-            k_rates32<P, W><<<nb, kBlock, 0, st>>>(n, (const float4 *)w.recA,                  \
-                                                   (const float4 *)w.recB,                     \
-                                                   (const float4 *)w.recC, sorted[0], sorted[1], \
-                                                   sorted[2], rho_sorted, d_sorted, w.cs, g,    \
-                                                   pc, t_dev, t_host, o, want_dt);             \
+            k_rates32<P, W, L><<<nb, kBlock, 0, st>>>(n, (const float4 *)w.recA,               \
+                                                      (const float4 *)w.recB,                  \
+                                                      (const float4 *)w.recC, sorted[0],       \
+                                                      sorted[1], sorted[2], rho_sorted,        \
+                                                      d_sorted, w.cs, g, pc, t_dev, t_host, o, \
+                                                      want_dt, vl);                            \
         else                                                                                   \
-            k_rates64<P, W><<<nb, kBlock, 0, st>>>(n, (const double4 *)w.recA,                 \
-                                                   (const double4 *)w.recB,                    \
-                                                   (const double2 *)w.recC, rho_sorted,        \
-                                                   d_sorted, w.cs, g, pc, t_dev, t_host, o,    \
-                                                   want_dt);                                   \
+            k_rates64<P, W, L><<<nb, kBlock, 0, st>>>(n, (const double4 *)w.recA,              \
+                                                      (const double4 *)w.recB,                 \
+                                                      (const double2 *)w.recC, rho_sorted,     \
+                                                      d_sorted, w.cs, g, pc, t_dev, t_host, o, \
+                                                      want_dt, vl);                            \
     }
-    CSPH_RATES_CASE(false, false)
-    CSPH_RATES_CASE(false, true)
-    CSPH_RATES_CASE(true, false)
-    CSPH_RATES_CASE(true, true)
+    CSPH_RATES_CASE(false, false, false)
+    CSPH_RATES_CASE(false, true, false)
+    CSPH_RATES_CASE(true, false, false)
+    CSPH_RATES_CASE(true, true, false)
+    CSPH_RATES_CASE(false, false, true)
+    CSPH_RATES_CASE(false, true, true)
 #undef CSPH_RATES_CASE
     return hipGetLastError();
 }

@@ -1,0 +1,118 @@
+// Verlet lists (sec. 4.2): for each particle, in cell order, the partners
+// within the horizon R = (1 + beta) H, found on the chord-clipped stencil rows
+// of the cell mesh with the exact FP64 test r^2 < R^2 (no contraction), plus
+// mirror partners across the piston wall (sign bit set).  A step then tests
+// only the listed partners (r^2 < H^2), which gives N(i) exactly while no
+// pair can have closed in from beyond R; the displacement kernel below feeds
+// the caller's rebuild test.
+#include "csph_internal.h"
+#include "stencil.h"
+
+namespace csph {
+
+template <bool WALL>
+__global__ __launch_bounds__(kBlock) void k_vlist(int64_t n, const double *__restrict__ x,
+                                                  const double *__restrict__ y,
+                                                  const double *__restrict__ z,
+                                                  const int32_t *__restrict__ cs, GridDev g,
+                                                  double R, double R2, double xw, int cap,
+                                                  int32_t *__restrict__ count,
+                                                  int32_t *__restrict__ idx,
+                                                  unsigned long long *__restrict__ over) {
+    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const bool live = s < n;
+    const double xi = live ? x[s] : 0.0, yi = live ? y[s] : 0.0, zi = live ? z[s] : 0.0;
+    const Stencil t = make_stencil(g, xi, yi, zi, R);
+    const bool near = WALL && live && (xi - xw < R);
+    int32_t *out = idx + (live ? s * (int64_t)cap : 0);
+    int c = 0;
+    for (int pass = 0; pass < (WALL ? 2 : 1); ++pass) {
+        const bool ghost = pass == 1;
+        if (ghost && !__any(near)) break;
+        const bool on = live && (!ghost || near);
+        int oy = t.R, oz = -t.R - 1;
+        int k = 0, j0 = 0, len = 0, jlast = 0;
+        for (;;) {
+            if (!__any(k < len)) {
+                if (++oy > t.R) {
+                    oy = -t.R;
+                    if (++oz > t.R) break;
+                }
+                const int zz = t.cz + oz;
+                const float gz = slab_gap(t.zc, zz);
+                row_range(cs, g, t, on, t.cy + oy, zz, gz * gz, j0, len);
+                jlast = len > 0 ? j0 + len - 1 : 0;
+                k = 0;
+                continue;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int j = min(j0 + k + u, jlast);
+                const double xr = ld(x, j);
+                const double xj = ghost ? 2.0 * xw - xr : xr;
+                const double dx = xj - xi, dy = ld(y, j) - yi, dz = ld(z, j) - zi;
+                const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
+                const bool acc = (k + u < len) && (ghost || j != (int)s) && r2 < R2;
+                if (acc) {
+                    if (c < cap) out[c] = ghost ? (j | (int)0x80000000) : j;
+                    ++c;
+                }
+            }
+            k += kU;
+        }
+    }
+    if (live) {
+        count[s] = c;
+        if (c > cap) atomicMax(over, (unsigned long long)c);
+    }
+}
+
+// max_i |r_i - r_ref,i| into *out (bits of a non-negative double; *out zeroed first).
+__global__ __launch_bounds__(kBlock) void k_disp(int64_t n, const double *__restrict__ x,
+                                                 const double *__restrict__ y,
+                                                 const double *__restrict__ z,
+                                                 const double *__restrict__ ref,
+                                                 unsigned long long *__restrict__ out) {
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const double dx = x[i] - ref[i], dy = y[i] - ref[n + i], dz = z[i] - ref[2 * n + i];
+        const double d = sqrt(((dx * dx) + (dy * dy)) + (dz * dz));
+        m = d > m ? d : m;  // a NaN position leaves m as it is; positions are checked finite
+    }
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    __shared__ double sh[kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = sh[0];
+        for (int q = 1; q < kBlock / 64; ++q) r = fmax(r, sh[q]);
+        atomicMax(out, dbits(r));
+    }
+}
+
+hipError_t launch_vlist(int64_t n, const double *x, const double *y, const double *z,
+                        const int32_t *cs, const GridDev &g, double R, int wall, double xw,
+                        int cap, int32_t *count, int32_t *idx, unsigned long long *over,
+                        hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    const double R2 = R * R;
+    if (wall)
+        k_vlist<true><<<nb, kBlock, 0, st>>>(n, x, y, z, cs, g, R, R2, xw, cap, count, idx, over);
+    else
+        k_vlist<false><<<nb, kBlock, 0, st>>>(n, x, y, z, cs, g, R, R2, xw, cap, count, idx, over);
+    return hipGetLastError();
+}
+
+hipError_t launch_disp(int64_t n, const double *x, const double *y, const double *z,
+                       const double *ref, unsigned long long *out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    int64_t want = (n + kBlock - 1) / kBlock;
+    unsigned nb = (unsigned)(want > kReduceBlocks ? kReduceBlocks : want);
+    k_disp<<<nb, kBlock, 0, st>>>(n, x, y, z, ref, out);
+    return hipGetLastError();
+}
+
+}  // namespace csph
