@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slab", type=float, default=96.0,
                     help="oracle sample: particles with x < this (same workload)")
+    ap.add_argument("--verlet-steps", type=int, default=10,
+                    help="also time this many Verlet-list steps (0: skip)")
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false",
                     help="skip the adjoint/forward ratio of the 64^3 checkpointed rollout")
     ap.add_argument("--cell", type=float, default=1.0,
@@ -104,6 +106,41 @@ def balance_timing(P, torch, run, sites, iters=10):
     return {"ms_per_iteration": ms / iters, "sites": int(g.shape[0]), "iterations": iters,
             "touching_pairs": int(adj.sum().item()) // 2,
             "note": "stats pass over all particles + one-workgroup generator move"}
+
+
+def verlet_timing(P, torch, w, cell, steps, beta=0.3, n_upd=10):
+    """Verlet-list steps (lists within (1 + beta) H, rebuilt every n_upd steps or when the
+    displacement bound requires) on the same workload, mixed precision: the rebuilds are
+    inside the timed steps."""
+    params = P.Params.from_workload(w, precision="mixed", reorder=True, cell_size=cell)
+    state = P.state_from_workload(w, params, "cuda", with_id=False)
+    sc = P.StepScalars("cuda")
+    run = P.VerletRun(state, params, beta=beta, n_upd=n_upd)
+    cnt = torch.empty(w.n, dtype=torch.int32, device="cuda")
+    pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    for _ in range(2):
+        run.step(sc, nbr_count=cnt)
+    torch.cuda.synchronize()
+    b0 = run.builds
+    P.profile_enable(True)
+    P.profile_read()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run.step(sc, nbr_count=cnt)
+        pairs += cnt.sum()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = P.profile_read()
+    P.profile_enable(False)
+    npairs = int(pairs.item())
+    out = {"metric_value": npairs / el, "unit": "pair-interactions/s", "ms_per_step": 1e3 * el / steps,
+           "steps": steps, "beta": beta, "n_upd": n_upd, "rebuilds": run.builds - b0,
+           "list_cap": run.cap,
+           "kernel_ms": {g: round(v[1] / max(v[0], 1), 4) for g, v in prof.items() if v[0] > 0},
+           "note": "rebuild (bin + renumber + list build) counted in 'neighbors' and 'bin'"}
+    del run, state
+    torch.cuda.empty_cache()
+    return out
 
 
 def traffic_from_profile(kernel_src):
@@ -279,6 +316,11 @@ def main():
         line["mixed_speedup_over_fp64"] = f["ms"] / m["ms"]
     if "balance" in results:
         line["balance"] = results["balance"]
+    if args.verlet_steps > 0:
+        log("Verlet-list steps ...")
+        line["verlet"] = verlet_timing(P, torch, w, args.cell, args.verlet_steps)
+        log(f"verlet: {line['verlet']['ms_per_step']:.3f} ms/step, "
+            f"{line['verlet']['rebuilds']} rebuilds in {args.verlet_steps} steps")
     if args.adjoint:
         log("adjoint rollout ...")
         line["adjoint"] = adjoint_ratio(P, torch, ci)

@@ -239,8 +239,9 @@ csph_status voronoi_assign(const double *x, const double *y, const double *z, in
  *   s_in -> s_out: the state renumbered into cell order (as csph_step with
  *     reorder = 1 does; s_out distinct from s_in; mat, id, d carried along).
  *     The lists index s_out's order.
- *   vl_count[n]: list lengths; vl_idx[n * cap] (device): the partners of particle
- *     s at vl_idx[s cap + k], k < vl_count[s]; j != s with r^2 < R^2 in FP64
+ *   vl_count[n]: list lengths; vl_idx[cap * n] (device; cap a multiple of 8): the
+ *     partners of particle s in 8-entry chunks, entry k at vl_idx[((k/8) n + s) 8 + k%8],
+ *     k < vl_count[s]; j != s with r^2 < R^2 in FP64
  *     without contraction; a partner mirrored across the piston wall (at time *t,
  *     device) has the sign bit set.
  *   x_ref[3 n] (device): the positions at build, x..., y..., z....

@@ -570,7 +570,8 @@ class VerletRun:
         dev = state["x"].device
         H = params.kappa * params.h
         # partners within (1 + beta) H on a unit-density lattice, with room for compression
-        self.cap = int(cap) if cap else int(4.5 * ((1.0 + self.beta) * H) ** 3) + 32
+        cap = int(cap) if cap else int(4.5 * ((1.0 + self.beta) * H) ** 3) + 32
+        self.cap = -(-cap // 8) * 8  # whole 8-entry chunks
         self.state, self.other = state, state.like()
         self.count = torch.zeros(max(n, 1), dtype=torch.int32, device=dev)
         self.idx = torch.empty(max(n, 1) * self.cap, dtype=torch.int32, device=dev)
@@ -587,7 +588,7 @@ class VerletRun:
                                     self.count, self.idx, self.x_ref, ws=self.ws)
             if over == 0:
                 break
-            self.cap = int(over * 1.25) + 8
+            self.cap = -(-(int(over * 1.25) + 8) // 8) * 8
             self.idx = torch.empty(max(self.state.n, 1) * self.cap, dtype=torch.int32,
                                    device=self.idx.device)
         self.state, self.other = self.other, self.state

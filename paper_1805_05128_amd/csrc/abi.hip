@@ -523,7 +523,8 @@ csph_status csph_vlist_build(const csph_state *s_in, csph_state *s_out, const cs
     if (r) return r;
     if (p->h_mode != CSPH_H_FIXED) return fail(CSPH_EINVAL, "Verlet lists need fixed-h mode");
     if (!(beta >= 0.0) || !std::isfinite(beta)) return fail(CSPH_EINVAL, "beta must be >= 0");
-    if (cap < 1) return fail(CSPH_EINVAL, "cap must be >= 1");
+    if (cap < kVlChunk || cap % kVlChunk)
+        return fail(CSPH_EINVAL, "cap must be a positive multiple of %d", kVlChunk);
     const int64_t n = s_in->n;
     if (n > 0 && (!vl_count || !vl_idx || !x_ref))
         return fail(CSPH_EINVAL, "vl_count, vl_idx and x_ref are required");
@@ -568,7 +569,7 @@ csph_status csph_vlist_build(const csph_state *s_in, csph_state *s_out, const cs
     {
         ProfScope pr(CSPH_PROF_NEIGHBORS, st);
         CSPH_HIP(launch_fill_u64((unsigned long long *)w.nonphys, 0ull, 1, st));
-        CSPH_HIP(launch_vlist(n, s_out->x, s_out->y, s_out->z, w.cs, gd, R, p->wall, xw, cap,
+        CSPH_HIP(launch_vlist(n, (const double4 *)w.recA, w.cs, gd, R, p->wall, xw, cap,
                               vl_count, vl_idx, (unsigned long long *)w.nonphys, st));
         for (int a = 0; a < 3; ++a)
             CSPH_HIP(hipMemcpyAsync(x_ref + a * n, o[a], sizeof(double) * n,
@@ -595,8 +596,9 @@ csph_status csph_step_vlist(csph_state *s, const csph_params *p, double *t, doub
     if (!(p->cfl > 0.0) && !(std::isfinite(dt_in) && dt_in >= 0.0))
         return fail(CSPH_EINVAL, "cfl <= 0 needs a finite dt_in >= 0");
     const int64_t n = s->n;
-    if (n > 0 && (!vl_count || !vl_idx || !x_ref || cap < 1))
-        return fail(CSPH_EINVAL, "vl_count, vl_idx, x_ref and cap >= 1 are required");
+    if (n > 0 && (!vl_count || !vl_idx || !x_ref || cap < kVlChunk || cap % kVlChunk))
+        return fail(CSPH_EINVAL, "vl_count, vl_idx, x_ref and cap (a multiple of %d) are required",
+                    kVlChunk);
     hipStream_t st = (hipStream_t)stream;
     r = need_ws(ws_bytes, n, 1, ws_needed);
     if (r) return r;

@@ -20,6 +20,7 @@ constexpr int kMaxSites = 1024;       // Voronoi generators held in LDS (36 B ea
 constexpr int kMaxBalanceSites = 512; // balancer generators held in LDS (84 B each)
 constexpr int kXcd = 8;               // accelerator dies; workgroups go to them round robin
 constexpr int kSlabShift = 4;         // cell order: y-slabs of 16 rows (see cell_key)
+constexpr int kVlChunk = 8;           // Verlet-list entries per lane-owned 32-byte chunk
 
 // Mesh as the kernels see it.
 struct GridDev {
@@ -194,10 +195,9 @@ hipError_t launch_rates(int64_t n, int mixed, const GridDev &g, const PairConst 
                         const int32_t *vl_count = nullptr, const int32_t *vl_idx = nullptr,
                         int vl_cap = 0);
 // k_vlist.hip
-hipError_t launch_vlist(int64_t n, const double *x, const double *y, const double *z,
-                        const int32_t *cs, const GridDev &g, double R, int wall, double xw,
-                        int cap, int32_t *count, int32_t *idx, unsigned long long *over,
-                        hipStream_t st);
+hipError_t launch_vlist(int64_t n, const double4 *A, const int32_t *cs, const GridDev &g,
+                        double R, int wall, double xw, int cap, int32_t *count, int32_t *idx,
+                        unsigned long long *over, hipStream_t st);
 hipError_t launch_disp(int64_t n, const double *x, const double *y, const double *z,
                        const double *ref, unsigned long long *out, hipStream_t st);
 hipError_t launch_unsort_rates(int64_t n, const int32_t *perm, const Ws &w, csph_rates_out out,

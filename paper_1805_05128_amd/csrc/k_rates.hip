@@ -60,8 +60,12 @@ __global__ __launch_bounds__(kBlock) void k_pack(int64_t n, SrcState src,
     double c = bad ? 0.0 : sqrt(c2);
     if (bad && nonphys) atomicAdd((unsigned long long *)nonphys, 1ull);
     double Z = rho * c, V = m / rho;
-    if (MIXED) {
-        if (recA) {  // cell-relative offsets (stencil walks only)
+    if (MIXED && !perm) {  // list walks: FP64 position record
+        ((double4 *)recA)[s] = make_double4(x, y, z, V);
+        ((float4 *)recB)[s] = make_float4((float)vx, (float)vy, (float)vz, (float)P);
+        ((float4 *)recC)[s] = make_float4((float)Z, (float)c, (float)V, 0.0f);
+    } else if (MIXED) {
+        {  // cell-relative offsets (stencil walks)
         int cx = cell_coord(x, g.ox, g.inv, g.dx);
         int cy = cell_coord(y, g.oy, g.inv, g.dy);
         int cz = cell_coord(z, g.oz, g.inv, g.dz);
@@ -91,9 +95,9 @@ hipError_t launch_pack(const csph_state &s, int64_t n, const int32_t *perm, cons
     ds.mat = dst_mat;
     ds.d = dst_d;
     ds.id = dst_id;
-    // perm = NULL: records of the state as it is (Verlet steps); the FP32 cell-relative
-    // A record is then not written
-    void *recA = (mixed && !perm) ? nullptr : w.recA;
+    // perm = NULL: records of the state as it is (Verlet steps); the A record then holds
+    // the FP64 position in both precisions
+    void *recA = w.recA;
     unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
     if (mixed)
         k_pack<true><<<nb, kBlock, 0, st>>>(n, src, perm, eos, g, recA, w.recB, w.recC, ds,
@@ -119,8 +123,10 @@ __device__ __forceinline__ void block_min_to(double v, unsigned long long *dst) 
     }
 }
 
-// Verlet lists (sec. 4.2): partners of particle s at idx[s*cap .. s*cap+count[s]),
-// a mirror partner with the sign bit set.  Absent (idx = NULL) for stencil walks.
+// Verlet lists (sec. 4.2): entry k of particle s at idx[((k/8) n + s) 8 + k%8],
+// k < count[s]; a mirror partner has the sign bit set.  Absent (idx = NULL) for
+// stencil walks.  The list walks read two entries per 8-byte load.
+static_assert(kU == 2, "list walks load kU = 2 entries at once");
 struct VList {
     const int32_t *count;
     const int32_t *idx;
@@ -272,7 +278,8 @@ struct Rates64 {
 
     // Verlet-list walk: the lane's own list in chunks of kU, exact FP64 membership
     // (mirror partners across the wall for flagged entries)
-    __device__ __forceinline__ void pass_list(const int32_t *__restrict__ lst, int len) {
+    __device__ __forceinline__ void pass_list(const int32_t *__restrict__ lst, int len,
+                                              int64_t nl) {
         int k = 0;
         for (;;) {
             if (__any(qw - qr > kQ - kU)) {
@@ -280,9 +287,9 @@ struct Rates64 {
                 continue;
             }
             if (!__any(k < len)) break;
-            int e[kU];
-#pragma unroll
-            for (int u = 0; u < kU; ++u) e[u] = (k + u < len) ? lst[k + u] : 0;
+            const int2 ee = *(const int2 *)(lst + (int64_t)(k / kVlChunk) * nl * kVlChunk +
+                                            (k % kVlChunk));
+            int e[kU] = {k < len ? ee.x : 0, k + 1 < len ? ee.y : 0};
             double4 aj[kU];
 #pragma unroll
             for (int u = 0; u < kU; ++u) aj[u] = ld(A, e[u] & 0x7fffffff);
@@ -350,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void k_rates64(int64_t n, const double4 *__
     int cnt;
     if (LIST) {
         const int len = k.live ? min(vl.count[s], vl.cap) : 0;
-        k.pass_list(vl.idx + (k.live ? s * (int64_t)vl.cap : 0), len);
+        k.pass_list(vl.idx + (k.live ? s * kVlChunk : 0), len, n);
         cnt = k.cntl;
     } else {
         k.template pass<false>();
@@ -434,6 +441,7 @@ struct Rates32 {
     const double *__restrict__ zs;
     const double *__restrict__ dsz;
     const int32_t *__restrict__ cs;
+    const double4 *__restrict__ P4;  // list walks: FP64 position record
     GridDev g;
     PairConst pc;
     float4 (*qd)[kBlock];
@@ -534,7 +542,8 @@ struct Rates32 {
 
     // Verlet-list walk: exact FP64 membership from the FP64 positions; the ring takes
     // the FP32 offsets (mirrored for flagged entries)
-    __device__ __forceinline__ void pass_list(const int32_t *__restrict__ lst, int len) {
+    __device__ __forceinline__ void pass_list(const int32_t *__restrict__ lst, int len,
+                                              int64_t nl) {
         int k = 0;
         for (;;) {
             if (__any(qw - qr > kQ - kU)) {
@@ -542,16 +551,18 @@ struct Rates32 {
                 continue;
             }
             if (!__any(k < len)) break;
-            int e[kU];
+            // entries k, k+1 share a chunk (k even): one 8-byte load
+            const int2 ee = *(const int2 *)(lst + (int64_t)(k / kVlChunk) * nl * kVlChunk +
+                                            (k % kVlChunk));
+            int e[kU] = {k < len ? ee.x : 0, k + 1 < len ? ee.y : 0};
+            double4 pj[kU];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) e[u] = (k + u < len) ? lst[k + u] : 0;
+            for (int u = 0; u < kU; ++u) pj[u] = ld(P4, e[u] & 0x7fffffff);
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                const int j = e[u] & 0x7fffffff;
                 const bool ghost = WALL && e[u] < 0;
-                const double xr = ld(xs, j);
-                const double xj = ghost ? 2.0 * xw - xr : xr;
-                const double dx = xj - xi, dy = ld(ys, j) - yi, dz = ld(zs, j) - zi;
+                const double xj = ghost ? 2.0 * xw - pj[u].x : pj[u].x;
+                const double dx = xj - xi, dy = pj[u].y - yi, dz = pj[u].z - zi;
                 const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
                 const bool acc = (k + u < len) && r2 < pc.H2;
                 qd[qw & (kQ - 1)][tid] =
@@ -582,6 +593,7 @@ __global__ __launch_bounds__(kBlock) void k_rates32(int64_t n, const float4 *__r
     for (int q = 0; q < kQ; ++q) qd[q][threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
     Rates32<PAIR, WALL, LIST> k;
     k.A = A;
+    k.P4 = (const double4 *)A;
     k.B = B;
     k.Cz = Cz;
     k.xs = xs;
@@ -628,7 +640,7 @@ __global__ __launch_bounds__(kBlock) void k_rates32(int64_t n, const float4 *__r
     }
     if (LIST) {
         const int len = k.live ? min(vl.count[s], vl.cap) : 0;
-        k.pass_list(vl.idx + (k.live ? s * (int64_t)vl.cap : 0), len);
+        k.pass_list(vl.idx + (k.live ? s * kVlChunk : 0), len, n);
     } else {
         k.template pass<false>();
         if (WALL && __any(k.near_wall)) k.template pass<true>();

@@ -11,9 +11,7 @@
 namespace csph {
 
 template <bool WALL>
-__global__ __launch_bounds__(kBlock) void k_vlist(int64_t n, const double *__restrict__ x,
-                                                  const double *__restrict__ y,
-                                                  const double *__restrict__ z,
+__global__ __launch_bounds__(kBlock) void k_vlist(int64_t n, const double4 *__restrict__ A,
                                                   const int32_t *__restrict__ cs, GridDev g,
                                                   double R, double R2, double xw, int cap,
                                                   int32_t *__restrict__ count,
@@ -21,10 +19,13 @@ __global__ __launch_bounds__(kBlock) void k_vlist(int64_t n, const double *__res
                                                   unsigned long long *__restrict__ over) {
     const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const bool live = s < n;
-    const double xi = live ? x[s] : 0.0, yi = live ? y[s] : 0.0, zi = live ? z[s] : 0.0;
+    const double4 ai = live ? A[s] : make_double4(0.0, 0.0, 0.0, 0.0);
+    const double xi = ai.x, yi = ai.y, zi = ai.z;
     const Stencil t = make_stencil(g, xi, yi, zi, R);
     const bool near = WALL && live && (xi - xw < R);
-    int32_t *out = idx + (live ? s * (int64_t)cap : 0);
+    // blocked: entry c of particle s at idx[((c / 8) n + s) 8 + c % 8]; one lane fills whole
+    // 32-byte chunks and a wave reading its lanes' entry c touches 16 cache lines
+    int32_t *out = idx + (live ? s * kVlChunk : 0);
     int c = 0;
     for (int pass = 0; pass < (WALL ? 2 : 1); ++pass) {
         const bool ghost = pass == 1;
@@ -48,13 +49,15 @@ __global__ __launch_bounds__(kBlock) void k_vlist(int64_t n, const double *__res
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 const int j = min(j0 + k + u, jlast);
-                const double xr = ld(x, j);
-                const double xj = ghost ? 2.0 * xw - xr : xr;
-                const double dx = xj - xi, dy = ld(y, j) - yi, dz = ld(z, j) - zi;
+                const double4 aj = ld(A, j);
+                const double xj = ghost ? 2.0 * xw - aj.x : aj.x;
+                const double dx = xj - xi, dy = aj.y - yi, dz = aj.z - zi;
                 const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
                 const bool acc = (k + u < len) && (ghost || j != (int)s) && r2 < R2;
                 if (acc) {
-                    if (c < cap) out[c] = ghost ? (j | (int)0x80000000) : j;
+                    if (c < cap)
+                        out[(int64_t)(c / kVlChunk) * n * kVlChunk + (c % kVlChunk)] =
+                            ghost ? (j | (int)0x80000000) : j;
                     ++c;
                 }
             }
@@ -92,17 +95,16 @@ __global__ __launch_bounds__(kBlock) void k_disp(int64_t n, const double *__rest
     }
 }
 
-hipError_t launch_vlist(int64_t n, const double *x, const double *y, const double *z,
-                        const int32_t *cs, const GridDev &g, double R, int wall, double xw,
-                        int cap, int32_t *count, int32_t *idx, unsigned long long *over,
-                        hipStream_t st) {
+hipError_t launch_vlist(int64_t n, const double4 *A, const int32_t *cs, const GridDev &g,
+                        double R, int wall, double xw, int cap, int32_t *count, int32_t *idx,
+                        unsigned long long *over, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
     const double R2 = R * R;
     if (wall)
-        k_vlist<true><<<nb, kBlock, 0, st>>>(n, x, y, z, cs, g, R, R2, xw, cap, count, idx, over);
+        k_vlist<true><<<nb, kBlock, 0, st>>>(n, A, cs, g, R, R2, xw, cap, count, idx, over);
     else
-        k_vlist<false><<<nb, kBlock, 0, st>>>(n, x, y, z, cs, g, R, R2, xw, cap, count, idx, over);
+        k_vlist<false><<<nb, kBlock, 0, st>>>(n, A, cs, g, R, R2, xw, cap, count, idx, over);
     return hipGetLastError();
 }
 

@@ -78,7 +78,8 @@ def test_lists_are_the_horizon_pairs(case):
     torch.cuda.synchronize()
     ids = to_np(other.id)
     cnt = to_np(count)
-    lst = to_np(idx).reshape(w.n, cap)
+    # 8-entry chunks: entry k of particle s at [k // 8, s, k % 8]
+    lst = to_np(idx).reshape(cap // 8, w.n, 8).transpose(1, 0, 2).reshape(w.n, cap)
     got = set()
     for s in range(w.n):
         for e in lst[s, :cnt[s]]:
@@ -153,5 +154,5 @@ def test_verlet_run_mixed_follows_oracle(case):
 
 def test_verlet_run_grows_a_small_cap():
     w = ci.config0()
-    run, worst = _run(w, "fp64", beta=0.5, n_upd=4, steps=5, cap=6)
-    assert run.cap > 6 and worst <= 1e-10
+    run, worst = _run(w, "fp64", beta=0.5, n_upd=4, steps=5, cap=8)
+    assert run.cap > 8 and worst <= 1e-10
