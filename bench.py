@@ -143,16 +143,21 @@ def verlet_timing(P, torch, w, cell, steps, beta=0.3, n_upd=10):
     return out
 
 
-def traffic_from_profile(kernel_src):
+KERNEL_SOURCES = ("k_rates.hip", "stencil.h", "csph_internal.h")
+
+
+def traffic_from_profile():
     """HBM bytes per launch of the pair-rate kernel from the committed counter summary,
-    or None when the kernel source changed since the counters were taken."""
+    or None when the kernel sources changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_rates32_porous256.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
     fields = dict(re.findall(r"^- (\w+): (\S+)$", text, re.M))
-    sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    csrc = os.path.join(ROOT, "paper_1805_05128_amd", "csrc")
+    src = "".join(open(os.path.join(csrc, f), "rb").read().decode() for f in KERNEL_SOURCES)
+    sha = hashlib.sha256(src.encode()).hexdigest()
     if fields.get("source_sha256") != sha:
         return None
     return {"read_bytes": float(fields["read_bytes_per_launch"]),
@@ -244,7 +249,7 @@ def main():
         sc = P.StepScalars("cuda")
         run = Runner(P, torch, state, params, sites, ws, sc)
         P.profile_enable(True)  # warm-up steps also warm the event pool
-        run.run(args.warmup, False)
+        run.run(args.warmup)  # the same loop as the timed steps: every kernel loaded
         torch.cuda.synchronize()
         tot0 = sc.totals.cpu().numpy().copy()
         P.profile_read()
@@ -274,7 +279,7 @@ def main():
     flops = FLOP_PER_PAIR * m["pairs_per_step"]
     achieved = flops / rates_avg_s / 1e12
     kernels = {g: round(v[1] / max(v[0], 1), 4) for g, v in m["prof"].items() if v[0] > 0}
-    traffic = traffic_from_profile(os.path.join(ROOT, "paper_1805_05128_amd", "csrc", "k_rates.hip"))
+    traffic = traffic_from_profile()
     # per particle the pair-rate kernel must read its 48 B FP32 record, FP64 position (24 B)
     # and density (8 B), and write five FP64 rates, the signal speed and the count (52 B)
     alg_bytes = w.n * (80 + 52)
