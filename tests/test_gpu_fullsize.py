@@ -1,0 +1,125 @@
+"""GPU parity at the full sizes of the benchmark workloads, in the launch
+configuration bench.py times (cell order, unit mesh cells, both precisions):
+
+* porous shock 256^3 (11 743 903 particles, piston at t = 0.1, x_w = 0.2, in
+  front of every particle as the mirror rule requires): rates of
+  every particle against the oracle (cell-list mode, all host cores);
+* plate impact (589 824 particles): one full step of every particle, both
+  precisions, and the compensated totals;
+* two-body collision (64 000 000 particles): rates of a seeded sample that
+  includes the contact layer, against the oracle computed for the sample.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import csph_inputs as ci
+import oracle as O
+import paper_1805_05128_amd as P
+from helpers import RATE_FIELDS, field_relerr, rates_np, to_np
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+FP64_TOL = 1e-12
+MIXED_TOL = 2e-5
+
+
+def _gpu_rates(w, prec, t, cell=1.0):
+    params = P.Params.from_workload(w, precision=prec, reorder=True, cell_size=cell)
+    g = P.state_from_workload(w, params, DEV, with_id=False)
+    out = rates_np(P.csph_rates(g, params, t=t))
+    torch.cuda.synchronize()
+    del g
+    torch.cuda.empty_cache()
+    return out
+
+
+def test_porous256_rates_every_particle():
+    w = ci.config2()
+    print(f"[case] {w.name} n={w.n}", flush=True)
+    t = 0.1
+    ref = O.rates(O.cfg_for(w, search=1), O.state_from(w, O.cfg_for(w)), t=t)
+    print("oracle pairs", int(ref["nbr_count"].sum()), flush=True)
+    for prec, tol in (("mixed", MIXED_TOL), ("fp64", FP64_TOL)):
+        got = _gpu_rates(w, prec, t)
+        err = field_relerr(got, ref)
+        print(prec, err, flush=True)
+        assert max(err.values()) <= tol, (prec, err)
+        assert np.array_equal(got["nbr_count"].astype(np.int64), ref["nbr_count"]), prec
+        stol = 1e-13 if prec == "fp64" else 1e-5
+        assert np.abs(got["signal"] - ref["signal"]).max() <= stol * ref["signal"].max()
+
+
+def test_plate_impact_step_every_particle():
+    w = ci.config1()
+    # close the gap: the projectile's bottom layer within the support of the target's top
+    w.z[w.z > 33.0] -= 1.5
+    print(f"[case] {w.name} (in contact) n={w.n}", flush=True)
+    cfg = O.cfg_for(w, search=1)
+    s0 = O.state_from(w, cfg)
+    s1, t1, dt, ncount = O.step(cfg, s0, t=0.0)
+    rates = O.rates(cfg, s0)
+    for prec in ("fp64", "mixed"):
+        params = P.Params.from_workload(w, precision=prec, reorder=True, cell_size=1.0)
+        g = P.state_from_workload(w, params, DEV, with_id=True)
+        sc = P.StepScalars(DEV)
+        cnt = torch.empty(w.n, dtype=torch.int32, device=DEV)
+        out = P.csph_step(g, params, sc, nbr_count=cnt)
+        torch.cuda.synchronize()
+        got = out.numpy()
+        ids = got["id"]
+        assert np.array_equal(to_np(cnt).astype(np.int64), ncount[ids]), prec
+        gdt = float(to_np(sc.dt)[0])
+        if prec == "fp64":
+            assert abs(gdt - dt) <= 1e-15 * dt
+            for k in ("x", "y", "z", "vx", "vy", "vz", "rho", "E"):
+                a, b = got[k], s1[k][ids]
+                den = max(np.abs(b - s0[k][ids]).max(), 1e-300)
+                assert np.abs(a - b).max() <= FP64_TOL * den + 4 * np.finfo(float).eps * \
+                    np.abs(b).max(), k
+        else:
+            assert abs(gdt - dt) <= 1e-5 * dt
+            # rates recovered from the update against the oracle's rates of the initial state
+            est = {"drho": (got["rho"] - s0["rho"][ids]) / gdt,
+                   "dvx": (got["vx"] - s0["vx"][ids]) / gdt,
+                   "dvy": (got["vy"] - s0["vy"][ids]) / gdt,
+                   "dvz": (got["vz"] - s0["vz"][ids]) / gdt,
+                   "dE": (got["E"] - s0["E"][ids]) / gdt}
+            ref = {k: rates[k][ids] for k in RATE_FIELDS}
+            err = field_relerr(est, ref)
+            print("mixed step relerr", err, flush=True)
+            assert max(err.values()) <= MIXED_TOL, err
+        # compensated totals of the GPU's own new state
+        tot = to_np(sc.totals)
+        exact = O.totals(got)
+        for k in range(5):
+            assert abs(math.fsum([tot[2 * k], tot[2 * k + 1]]) - exact[k]) <= \
+                4 * math.ulp(abs(exact[k])) + 1e-300, (prec, k)
+        del g, out
+        torch.cuda.empty_cache()
+
+
+def test_collision64m_rates_sampled():
+    w = ci.config4()
+    # close the gap H between the bodies so that the contact layer interacts across materials
+    w.z[w.z > 201.0] -= 1.5
+    print(f"[case] {w.name} (in contact) n={w.n}", flush=True)
+    nb = w.n // 2
+    rng = np.random.default_rng(123)
+    # a uniform sample plus the two layers on each side of the contact (z in 197..204)
+    contact = np.nonzero((w.z > 196.0) & (w.z < 204.0))[0]
+    sample = np.unique(np.concatenate([rng.integers(0, w.n, 1500),
+                                       rng.choice(contact, 1500, replace=False)]))
+    cfg = O.cfg_for(w, search=1)
+    ref = O.rates_sample(cfg, O.state_from(w, cfg), sample)
+    assert ref["nbr_count"].min() > 0
+    for prec, tol in (("mixed", MIXED_TOL), ("fp64", FP64_TOL)):
+        got = _gpu_rates(w, prec, 0.0)
+        sub = {k: got[k][sample] for k in RATE_FIELDS}
+        err = field_relerr(sub, ref)
+        print(prec, err, flush=True)
+        assert max(err.values()) <= tol, (prec, err)
+        assert np.array_equal(got["nbr_count"][sample].astype(np.int64), ref["nbr_count"])
+    assert nb == 32_000_000
