@@ -286,7 +286,7 @@ size_t csph_balance_workspace_size(int32_t K);
  *   site_particles[k], site_pairs[k] (sum of nbr_count, optional, needs nbr_count);
  *   centre[k] = mean position of the particles owned by k (eq. VoronoiGeomCenters;
  *     the generator itself if there are none).  Exact fixed-point sums
- *     (resolution 2^-32 per coordinate, |x - g_k| < 2^31), deterministic;
+ *     (resolution 2^-32 per coordinate, |x - g_k| < 2^24), deterministic;
  *   adjacency: k and l touch when some particle owned by one of them has the
  *     other as its nearest other generator (ties to the smaller index) and
  *     lies within dsh of their bisector plane, tested as

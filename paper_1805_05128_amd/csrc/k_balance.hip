@@ -3,9 +3,9 @@
 // Statistics (one pass over the particles, generators in LDS):
 //   * particle and pair loads per subdomain (integers);
 //   * geometric centres (eq. VoronoiGeomCenters) from fixed-point sums: each
-//     particle adds round((x - g_k) * 2^32) to a 128-bit integer per
-//     coordinate, so the sums are exact and do not depend on the order in
-//     which the atomics run;
+//     particle adds round((x - g_k) * 2^32) (|x - g_k| < 2^24) to a 128-bit
+//     integer per coordinate, so the sums are exact and do not depend on the
+//     order in which the atomics run;
 //   * which subdomains touch: a particle owned by k whose nearest other
 //     generator l lies within D^sh of the k|l bisector plane marks (k, l) and
 //     (l, k) in a K x K bit matrix (the same FP64 expressions as the CPU
@@ -25,6 +25,7 @@ __global__ void k_zero_u64(unsigned long long *p, int count);
 __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t count);
 
 constexpr double kFix = 4294967296.0;  // 2^32: fixed-point scale of the centre sums
+constexpr double kFixMax = 72057594037927936.0;  // 2^56: per-particle bound (|x - g| < 2^24)
 
 // 128-bit two's-complement accumulator {lo, hi}: add a signed 64-bit value.
 __device__ __forceinline__ void add128(unsigned long long *lo, unsigned long long *hi, long long v) {
@@ -59,19 +60,58 @@ __global__ __launch_bounds__(kBlock) void k_balance_stats(
     }
     __syncthreads();
     const double lim = 4.0 * (dsh * dsh);
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
-        const int k = owner[i];
-        if (k < 0 || k >= K) continue;
-        const double p[3] = {x[i], y[i], z[i]};
-        atomicAdd(&s_part[k], 1u);
-        if (nbr_count) atomicAdd(&s_pairs[k], (unsigned long long)nbr_count[i]);
+    // wave-uniform grid-stride loop: every lane of a wave takes part in the shuffles
+    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n;
+         base += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = base + threadIdx.x;
+        const int kr = i < n ? owner[i] : -1;
+        const bool ok = kr >= 0 && kr < K;
+        const int k = ok ? kr : 0;
+        double p[3] = {0.0, 0.0, 0.0};
+        long long v[3] = {0, 0, 0};
+        unsigned long long pc = 0ull;
+        if (ok) {
+            p[0] = x[i];
+            p[1] = y[i];
+            p[2] = z[i];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            double v = (p[d] - gs[3 * k + d]) * kFix;
-            v = fmin(fmax(v, -9.0e18), 9.0e18);  // |x - g| < 2^31 keeps this exact
-            add128(&s_lo[3 * k + d], &s_hi[3 * k + d], __double2ll_rn(v));
+            for (int d = 0; d < 3; ++d) {
+                // |x - g| < 2^24: the value and any 64 of them fit in 63 bits
+                const double f = fmin(fmax((p[d] - gs[3 * k + d]) * kFix, -kFixMax), kFixMax);
+                v[d] = __double2ll_rn(f);
+            }
+            pc = nbr_count ? (unsigned long long)nbr_count[i] : 0ull;
         }
+        const unsigned long long okm = __ballot(ok);
+        if (okm == 0ull) continue;
+        const int lead = __ffsll(okm) - 1;
+        const int k0 = __shfl(k, lead, 64);
+        if (__all(!ok || k == k0)) {
+            // particles are in cell order, so a wave mostly shares one owner: sum the wave
+            // in registers (exact integers; lanes without a particle add zeros) and let one
+            // lane add the totals
+            long long w0 = v[0], w1 = v[1], w2 = v[2];
+            unsigned long long wp = pc;
+            for (int o = 32; o > 0; o >>= 1) {
+                w0 += __shfl_xor(w0, o, 64);
+                w1 += __shfl_xor(w1, o, 64);
+                w2 += __shfl_xor(w2, o, 64);
+                wp += __shfl_xor(wp, o, 64);
+            }
+            if ((int)(threadIdx.x & 63) == lead) {
+                atomicAdd(&s_part[k0], (unsigned)__popcll(okm));
+                if (nbr_count) atomicAdd(&s_pairs[k0], wp);
+                add128(&s_lo[3 * k0], &s_hi[3 * k0], w0);
+                add128(&s_lo[3 * k0 + 1], &s_hi[3 * k0 + 1], w1);
+                add128(&s_lo[3 * k0 + 2], &s_hi[3 * k0 + 2], w2);
+            }
+        } else if (ok) {
+            atomicAdd(&s_part[k], 1u);
+            if (nbr_count) atomicAdd(&s_pairs[k], pc);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) add128(&s_lo[3 * k + d], &s_hi[3 * k + d], v[d]);
+        }
+        if (!ok) continue;
         if (K > 1) {
             // nearest other generator (ties to the smaller index) and the owner's distance
             double d2o = 0.0, bd = INFINITY;
@@ -176,38 +216,57 @@ __global__ __launch_bounds__(1024) void k_balance_move(
     const double *__restrict__ sites, int K, int W, const int64_t *__restrict__ loads,
     const double *__restrict__ centre, const uint32_t *__restrict__ adj, double sigma,
     double theta, double gamma, double dsh, double *__restrict__ out, double *__restrict__ move_sum) {
+    extern __shared__ double sm[];
+    double *sg = sm;                         // 3K generators
+    double *sL = sg + 3 * K;                 // K loads
+    uint32_t *sa = (uint32_t *)(sL + K);     // K x W adjacency words
     __shared__ double red[1024];
+    for (int q = threadIdx.x; q < 3 * K; q += blockDim.x) sg[q] = sites[q];
+    for (int q = threadIdx.x; q < K; q += blockDim.x) sL[q] = (double)loads[q];
+    for (int q = threadIdx.x; q < K * W; q += blockDim.x) sa[q] = adj[q];
+    __syncthreads();
     const int k = threadIdx.x;
     double mv = 0.0;
     if (k < K) {
-        const V3 gk{sites[3 * k], sites[3 * k + 1], sites[3 * k + 2]};
-        const double Lk = (double)loads[k];
+        const V3 gk{sg[3 * k], sg[3 * k + 1], sg[3 * k + 2]};
+        const double Lk = sL[k];
+        const uint32_t *rk = sa + (size_t)k * W;
         V3 two{0.0, 0.0, 0.0}, three{0.0, 0.0, 0.0};
-        for (int l = 0; l < K; ++l) {
-            if (l == k || !touch(adj, W, k, l)) continue;
-            const V3 gl{sites[3 * l], sites[3 * l + 1], sites[3 * l + 2]};
-            const double Ll = (double)loads[l];
-            const V3 gkl = gk - gl;
-            const double nd = sqrt(dot(gkl, gkl));
-            if (Lk + Ll != 0.0 && nd != 0.0)
-                two = two + (dsh * (Lk - Ll) / (Lk + Ll) / nd) * gkl;
-            for (int m = l + 1; m < K; ++m) {
-                if (m == k || !touch(adj, W, k, m) || !touch(adj, W, l, m)) continue;
-                const V3 gm{sites[3 * m], sites[3 * m + 1], sites[3 * m + 2]};
-                const double Lm = (double)loads[m];
-                const double S = Lk + Ll + Lm;
-                // circumcentre of the triangle (g_k, g_l, g_m)
-                const V3 a = gl - gk, b = gm - gk;
-                const V3 nrm = cross(a, b);
-                const double n2 = dot(nrm, nrm);
-                if (S == 0.0 || !(n2 > 1e-24 * dot(a, a) * dot(b, b))) continue;
-                const V3 o = gk + (0.5 / n2) * cross(dot(a, a) * b - dot(b, b) * a, nrm);
-                const V3 ck = gk - o, cl = gl - o, cm = gm - o;
-                const V3 axl = cross(ck, cl), axm = cross(ck, cm);
-                if (dot(axl, axl) == 0.0 || dot(axm, axm) == 0.0) continue;
-                const double al = (M_PI / 3.0) * (Ll - Lk) / S;
-                const double am = (M_PI / 3.0) * (Lm - Lk) / S;
-                three = three + (rotate(rotate(ck, axl, al), axm, am) - ck);
+        for (int wl = 0; wl < W; ++wl) {
+            for (uint32_t bl = rk[wl] & ~(wl == (k >> 5) ? (1u << (k & 31)) : 0u); bl;
+                 bl &= bl - 1) {
+                const int l = wl * 32 + __ffs(bl) - 1;
+                const V3 gl{sg[3 * l], sg[3 * l + 1], sg[3 * l + 2]};
+                const double Ll = sL[l];
+                const V3 gkl = gk - gl;
+                const double nd = sqrt(dot(gkl, gkl));
+                if (Lk + Ll != 0.0 && nd != 0.0)
+                    two = two + (dsh * (Lk - Ll) / (Lk + Ll) / nd) * gkl;
+                // m > l touching both k and l: the intersection of rows k and l
+                const uint32_t *rl = sa + (size_t)l * W;
+                for (int wm = l >> 5; wm < W; ++wm) {
+                    uint32_t bm = rk[wm] & rl[wm];
+                    if (wm == (l >> 5)) bm &= ~((2u << (l & 31)) - 1u);  // m > l
+                    if (wm == (k >> 5)) bm &= ~(1u << (k & 31));         // m != k
+                    for (; bm; bm &= bm - 1) {
+                        const int m = wm * 32 + __ffs(bm) - 1;
+                        const V3 gm{sg[3 * m], sg[3 * m + 1], sg[3 * m + 2]};
+                        const double Lm = sL[m];
+                        const double S = Lk + Ll + Lm;
+                        // circumcentre of the triangle (g_k, g_l, g_m)
+                        const V3 a = gl - gk, b = gm - gk;
+                        const V3 nrm = cross(a, b);
+                        const double n2 = dot(nrm, nrm);
+                        if (S == 0.0 || !(n2 > 1e-24 * dot(a, a) * dot(b, b))) continue;
+                        const V3 o = gk + (0.5 / n2) * cross(dot(a, a) * b - dot(b, b) * a, nrm);
+                        const V3 ck = gk - o, cl = gl - o, cm = gm - o;
+                        const V3 axl = cross(ck, cl), axm = cross(ck, cm);
+                        if (dot(axl, axl) == 0.0 || dot(axm, axm) == 0.0) continue;
+                        const double al = (M_PI / 3.0) * (Ll - Lk) / S;
+                        const double am = (M_PI / 3.0) * (Lm - Lk) / S;
+                        three = three + (rotate(rotate(ck, axl, al), axm, am) - ck);
+                    }
+                }
             }
         }
         const double nt = sqrt(dot(three, three));
@@ -223,8 +282,8 @@ __global__ __launch_bounds__(1024) void k_balance_move(
     }
     red[threadIdx.x] = mv;
     __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
         __syncthreads();
     }
     if (threadIdx.x == 0) *move_sum = red[0];
@@ -263,7 +322,11 @@ hipError_t launch_balance_move(const double *sites, int K, const int64_t *loads,
                                double theta, double gamma, double dsh, double *out,
                                double *move_sum, hipStream_t st) {
     const int W = (K + 31) / 32;
-    k_balance_move<<<1, 1024, 0, st>>>(sites, K, W, loads, centre, adj, sigma, theta, gamma, dsh,
+    // one thread per generator, rounded up to whole waves (block sums in a fixed tree)
+    int nt = 64;
+    while (nt < K) nt *= 2;
+    const size_t shm = sizeof(double) * 4 * (size_t)K + sizeof(uint32_t) * (size_t)K * W;
+    k_balance_move<<<1, nt, shm, st>>>(sites, K, W, loads, centre, adj, sigma, theta, gamma, dsh,
                                        out, move_sum);
     return hipGetLastError();
 }
