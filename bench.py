@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slab", type=float, default=96.0,
                     help="oracle sample: particles with x < this (same workload)")
+    ap.add_argument("--no-extra", dest="extra", action="store_false",
+                    help="skip the void-free twin and the plate-impact runs")
     ap.add_argument("--verlet-steps", type=int, default=10,
                     help="also time this many Verlet-list steps (0: skip)")
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false",
@@ -74,6 +76,15 @@ class Runner:
 
     def run(self, k, count_pairs=True):
         """k steps of (csph_step, voronoi_assign); directed pairs summed on the device."""
+        import gc
+        P = self.P
+        gc.disable()  # no collector pause inside the step loop
+        try:
+            self._run(k, count_pairs)
+        finally:
+            gc.enable()
+
+    def _run(self, k, count_pairs):
         P = self.P
         for _ in range(k):
             out = P.csph_step(self.state, self.params, self.sc, s_out=self.other,
@@ -106,6 +117,75 @@ def balance_timing(P, torch, run, sites, iters=10):
     return {"ms_per_iteration": ms / iters, "sites": int(g.shape[0]), "iterations": iters,
             "touching_pairs": int(adj.sum().item()) // 2,
             "note": "stats pass over all particles + one-workgroup generator move"}
+
+
+def impact_run(P, torch, ci, steps):
+    """Plate impact (589 824 particles, no walls: a closed system), ``steps`` steps from the
+    initial state in each precision: time per step, pair interactions/s, and the drift of the
+    compensated totals of momentum and energy from the first step's state to the last."""
+    w = ci.config1()
+    out = {"workload": w.name, "particles": w.n, "steps": steps}
+    for prec in ("mixed", "fp64"):
+        params = P.Params.from_workload(w, precision=prec, reorder=True, cell_size=1.0)
+        cnt = torch.empty(w.n, dtype=torch.int32, device="cuda")
+        pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+        # warm-up on a throwaway copy, then the timed run from the initial state
+        for warm in (True, False):
+            state = P.state_from_workload(w, params, "cuda", with_id=False)
+            other = state.like()
+            sc = P.StepScalars("cuda")
+            ws = P.Workspace("cuda")
+            k = 3 if warm else steps
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(k):
+                o = P.csph_step(state, params, sc, s_out=other, nbr_count=cnt, ws=ws)
+                if not warm:
+                    pairs += cnt.sum()
+                if i == 0 and not warm:
+                    tot_first = sc.totals.clone()
+                state, other = o, state
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+        t1 = sc.totals.cpu().numpy()
+        t0_ = tot_first.cpu().numpy()
+        tot = lambda t, a: float(t[2 * a]) + float(t[2 * a + 1])
+        mom_scale = float((state["m"] * (state["vx"].abs() + state["vy"].abs() +
+                                         state["vz"].abs())).sum())
+        dmom = max(abs(tot(t1, a) - tot(t0_, a)) for a in (1, 2, 3)) / mom_scale
+        de = (tot(t1, 4) - tot(t0_, 4)) / abs(tot(t0_, 4))
+        out[prec] = {"ms_per_step": 1e3 * el / steps, "pairs_per_s": int(pairs.item()) / el,
+                     "momentum_drift_rel": dmom, "energy_drift_rel": de,
+                     "t_end": float(sc.t.item())}
+        del state, other, ws
+        torch.cuda.empty_cache()
+    out["mixed_speedup_over_fp64"] = out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"]
+    out["note"] = ("drifts of the compensated totals sum(m v), sum(m E) between the states after "
+                   "step 1 and the last step, relative to sum(m|v|) and |sum(m E)|")
+    return out
+
+
+def voidfree_run(P, torch, ci, steps, cell):
+    """The void-free 256^3 twin (16 777 216 particles), mixed, whole step with Voronoi."""
+    w = ci.config2(voids=False)
+    params = P.Params.from_workload(w, precision="mixed", reorder=True, cell_size=cell)
+    state = P.state_from_workload(w, params, "cuda", with_id=False)
+    sc = P.StepScalars("cuda")
+    sites = torch.as_tensor(w.sites, dtype=torch.float64, device="cuda")
+    run = Runner(P, torch, state, params, sites, P.Workspace("cuda"), sc)
+    run.run(3)
+    torch.cuda.synchronize()
+    run.pairs.zero_()
+    t0 = time.perf_counter()
+    run.run(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    npairs = int(run.pairs.item())
+    out = {"workload": w.name, "particles": w.n, "steps": steps, "ms_per_step": 1e3 * el / steps,
+           "steps_per_s": steps / el, "pairs_per_s": npairs / el}
+    del run, state
+    torch.cuda.empty_cache()
+    return out
 
 
 def verlet_timing(P, torch, w, cell, steps, beta=0.3, n_upd=10):
@@ -319,8 +399,17 @@ def main():
         line["fp64"] = {"ms_per_step": f["ms"], "value": f["pairs_per_step"] * 1e3 / f["ms"],
                         "rates_kernel_ms": f["prof"]["rates"][1] / max(f["prof"]["rates"][0], 1)}
         line["mixed_speedup_over_fp64"] = f["ms"] / m["ms"]
+    line["unique_pairs_per_s"] = line["value"] / 2.0
     if "balance" in results:
         line["balance"] = results["balance"]
+    if args.extra:
+        log("void-free 256^3 twin ...")
+        line["voidfree"] = voidfree_run(P, torch, ci, 10, args.cell)
+        log(f"void-free: {line['voidfree']['ms_per_step']:.3f} ms/step")
+        log("plate impact, both precisions ...")
+        line["impact"] = impact_run(P, torch, ci, 200)
+        log(f"impact mixed {line['impact']['mixed']['ms_per_step']:.3f} ms/step, "
+            f"fp64 {line['impact']['fp64']['ms_per_step']:.3f} ms/step")
     if args.verlet_steps > 0:
         log("Verlet-list steps ...")
         line["verlet"] = verlet_timing(P, torch, w, args.cell, args.verlet_steps)

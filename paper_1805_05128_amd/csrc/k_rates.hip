@@ -233,6 +233,8 @@ struct Rates64 {
     template <bool GHOST>
     __device__ __forceinline__ void pass() {
         const bool on = live && (!GHOST || near_wall);
+        // mirror partners lie within the chord around the image of i behind the wall
+        const float xcen = GHOST ? (float)(2.0 * (xw - g.ox) * g.inv) - t.xc : t.xc;
         int oy = t.R, oz = -t.R - 1;  // advanced to (-R, -R) before the first row
         int k = 0, j0 = 0, len = 0, jlast = 0;
         for (;;) {
@@ -247,7 +249,7 @@ struct Rates64 {
                 }
                 const int zz = t.cz + oz;
                 const float gz = slab_gap(t.zc, zz);
-                row_range(cs, g, t, on, t.cy + oy, zz, gz * gz, j0, len);
+                row_range(cs, g, t, on, t.cy + oy, zz, gz * gz, xcen, j0, len);
                 jlast = len > 0 ? j0 + len - 1 : 0;
                 k = 0;
                 continue;
@@ -494,6 +496,7 @@ struct Rates32 {
     __device__ __forceinline__ void pass() {
 #pragma clang fp contract(fast)
         const bool on = live && (!GHOST || near_wall);
+        const float xcen = GHOST ? (float)(2.0 * (xw - g.ox) * g.inv) - t.xc : t.xc;
         int oy = t.R, oz = -t.R - 1;
         int k = 0, j0 = 0, len = 0, jlast = 0;
         float ay = 0.f, az = 0.f;
@@ -509,7 +512,7 @@ struct Rates32 {
                 }
                 const int zz = t.cz + oz;
                 const float gz = slab_gap(t.zc, zz);
-                row_range(cs, g, t, on, t.cy + oy, zz, gz * gz, j0, len);
+                row_range(cs, g, t, on, t.cy + oy, zz, gz * gz, xcen, j0, len);
                 jlast = len > 0 ? j0 + len - 1 : 0;
                 ay = a.y - (float)oy * Df;
                 az = a.z - (float)oz * Df;

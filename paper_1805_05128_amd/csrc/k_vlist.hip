@@ -31,6 +31,8 @@ __global__ __launch_bounds__(kBlock) void k_vlist(int64_t n, const double4 *__re
         const bool ghost = pass == 1;
         if (ghost && !__any(near)) break;
         const bool on = live && (!ghost || near);
+        // mirror partners lie within the chord around the image of i behind the wall
+        const float xcen = ghost ? (float)(2.0 * (xw - g.ox) * g.inv) - t.xc : t.xc;
         int oy = t.R, oz = -t.R - 1;
         int k = 0, j0 = 0, len = 0, jlast = 0;
         for (;;) {
@@ -41,7 +43,7 @@ __global__ __launch_bounds__(kBlock) void k_vlist(int64_t n, const double4 *__re
                 }
                 const int zz = t.cz + oz;
                 const float gz = slab_gap(t.zc, zz);
-                row_range(cs, g, t, on, t.cy + oy, zz, gz * gz, j0, len);
+                row_range(cs, g, t, on, t.cy + oy, zz, gz * gz, xcen, j0, len);
                 jlast = len > 0 ? j0 + len - 1 : 0;
                 k = 0;
                 continue;

@@ -66,23 +66,30 @@ __device__ __forceinline__ float slab_gap(float c, int k) {
 }
 
 // Candidate range [j0, j0+len) of row (yy, zz) for a particle: the cells of
-// the row within the chord of its support sphere.  gz2 = squared z gap.
-// Branch-free: a row off the mesh or missing the sphere gets len = 0.
+// the row within the chord its support sphere cuts through the row, centred
+// at x = xcen in cell units (the particle itself, or for mirror partners its
+// image behind the wall).  gz2 = squared z gap.  Branch-free per lane; a row
+// off the mesh or missing the sphere gets len = 0, and when it does so for
+// every lane of the wave the cell-range loads are skipped.
 __device__ __forceinline__ void row_range(const int32_t *__restrict__ cs, const GridDev &g,
                                           const Stencil &t, bool on, int yy, int zz, float gz2,
-                                          int &j0, int &len) {
+                                          float xcen, int &j0, int &len) {
     const bool inb = on && zz >= 0 && zz < g.dz && yy >= 0 && yy < g.dy;
     const float gy = slab_gap(t.yc, yy);
     const float rem = t.w2 - (gy * gy + gz2);
     // chord half-width; v_sqrt_f32 (1 ulp) is ample under the margins
     const float hw = __builtin_amdgcn_sqrtf(fmaxf(rem, 0.0f)) * 1.0001f + 1e-3f;
-    const int xa = max(max((int)floorf(t.xc - hw), t.cx - t.R), 0);
-    const int xb = min(min((int)floorf(t.xc + hw), t.cx + t.R), g.dx - 1);
+    const int xa = max(max((int)floorf(xcen - hw), t.cx - t.R), 0);
+    const int xb = min(min((int)floorf(xcen + hw), t.cx + t.R), g.dx - 1);
     const bool ok = inb && rem > 0.0f && xb >= xa;
-    const int row = (int)cell_key(g, 0, yy, zz);
-    const int ia = ok ? row + xa : 0, ib = ok ? row + xb + 1 : 0;
-    j0 = ld(cs, ia);
-    len = ld(cs, ib) - j0;
+    j0 = 0;
+    len = 0;
+    if (__any(ok)) {
+        const int row = (int)cell_key(g, 0, yy, zz);
+        const int ia = ok ? row + xa : 0, ib = ok ? row + xb + 1 : 0;
+        j0 = ld(cs, ia);
+        len = ld(cs, ib) - j0;
+    }
 }
 
 }  // namespace csph
