@@ -16,6 +16,8 @@ Prints ONE JSON line.  `value` = directed pair interactions per second
 (sum_i |N(i)| per step x steps per second) with the state resident in HBM.
 """
 import argparse
+import contextlib
+import gc
 import json
 import os
 import re
@@ -40,7 +42,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="porous", choices=["porous", "voidfree"])
-    ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--fp64-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slab", type=float, default=96.0,
                     help="oracle sample: particles with x < this (same workload)")
@@ -61,6 +63,19 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+@contextlib.contextmanager
+def collector_off():
+    """Python's cyclic garbage collector off, after a full collection, for a timed region
+    including its closing device synchronisation: a collection pause (tens of ms with torch
+    loaded) must not land between the start and the stop of the clock."""
+    gc.collect()
+    gc.disable()
+    try:
+        yield
+    finally:
+        gc.enable()
+
+
 class Runner:
     """Step loop with every buffer allocated up front (nothing is allocated while timed)."""
 
@@ -76,15 +91,6 @@ class Runner:
 
     def run(self, k, count_pairs=True):
         """k steps of (csph_step, voronoi_assign); directed pairs summed on the device."""
-        import gc
-        P = self.P
-        gc.disable()  # no collector pause inside the step loop
-        try:
-            self._run(k, count_pairs)
-        finally:
-            gc.enable()
-
-    def _run(self, k, count_pairs):
         P = self.P
         for _ in range(k):
             out = P.csph_step(self.state, self.params, self.sc, s_out=self.other,
@@ -136,17 +142,18 @@ def impact_run(P, torch, ci, steps):
             sc = P.StepScalars("cuda")
             ws = P.Workspace("cuda")
             k = 3 if warm else steps
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for i in range(k):
-                o = P.csph_step(state, params, sc, s_out=other, nbr_count=cnt, ws=ws)
-                if not warm:
-                    pairs += cnt.sum()
-                if i == 0 and not warm:
-                    tot_first = sc.totals.clone()
-                state, other = o, state
-            torch.cuda.synchronize()
-            el = time.perf_counter() - t0
+            with collector_off():
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for i in range(k):
+                    o = P.csph_step(state, params, sc, s_out=other, nbr_count=cnt, ws=ws)
+                    if not warm:
+                        pairs += cnt.sum()
+                    if i == 0 and not warm:
+                        tot_first = sc.totals.clone()
+                    state, other = o, state
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
         t1 = sc.totals.cpu().numpy()
         t0_ = tot_first.cpu().numpy()
         tot = lambda t, a: float(t[2 * a]) + float(t[2 * a + 1])
@@ -173,13 +180,16 @@ def voidfree_run(P, torch, ci, steps, cell):
     sc = P.StepScalars("cuda")
     sites = torch.as_tensor(w.sites, dtype=torch.float64, device="cuda")
     run = Runner(P, torch, state, params, sites, P.Workspace("cuda"), sc)
-    run.run(3)
-    torch.cuda.synchronize()
+    with collector_off():
+        run.run(3)
+        torch.cuda.synchronize()
     run.pairs.zero_()
-    t0 = time.perf_counter()
-    run.run(steps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    with collector_off():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run.run(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
     npairs = int(run.pairs.item())
     out = {"workload": w.name, "particles": w.n, "steps": steps, "ms_per_step": 1e3 * el / steps,
            "steps_per_s": steps / el, "pairs_per_s": npairs / el}
@@ -204,12 +214,14 @@ def verlet_timing(P, torch, w, cell, steps, beta=0.3, n_upd=10):
     b0 = run.builds
     P.profile_enable(True)
     P.profile_read()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        run.step(sc, nbr_count=cnt)
-        pairs += cnt.sum()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    with collector_off():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run.step(sc, nbr_count=cnt)
+            pairs += cnt.sum()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
     prof = P.profile_read()
     P.profile_enable(False)
     npairs = int(pairs.item())
@@ -259,10 +271,11 @@ def adjoint_ratio(P, torch, ci):
     for _ in range(2):  # the first rollout also warms the library's code paths
         v0 = [t(a).requires_grad_(True) for a in (w.vx, w.vy, w.vz)]
         info = {}
-        out = P.rollout(*v0, gamma, base, params, w.steps, 10, info=info)
-        mask = out["x"].detach() > 48.0
-        J = (out["vx"][mask] * base["m"][mask]).sum()
-        torch.autograd.grad(J, v0 + [gamma])
+        with collector_off():
+            out = P.rollout(*v0, gamma, base, params, w.steps, 10, info=info)
+            mask = out["x"].detach() > 48.0
+            J = (out["vx"][mask] * base["m"][mask]).sum()
+            torch.autograd.grad(J, v0 + [gamma])
         r = {"ratio": info["backward_s"] / info["forward_s"], "forward_s": info["forward_s"],
              "backward_s": info["backward_s"]}
         best = r
@@ -329,16 +342,18 @@ def main():
         sc = P.StepScalars("cuda")
         run = Runner(P, torch, state, params, sites, ws, sc)
         P.profile_enable(True)  # warm-up steps also warm the event pool
-        run.run(args.warmup)  # the same loop as the timed steps: every kernel loaded
-        torch.cuda.synchronize()
+        with collector_off():
+            run.run(args.warmup)  # the same loop as the timed steps: every kernel loaded
+            torch.cuda.synchronize()
         tot0 = sc.totals.cpu().numpy().copy()
         P.profile_read()
         run.pairs.zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        run.run(k)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
+        with collector_off():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run.run(k)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
         prof = P.profile_read()
         P.profile_enable(False)
         tot1 = sc.totals.cpu().numpy()
@@ -397,7 +412,9 @@ def main():
     if "fp64" in results:
         f = results["fp64"]
         line["fp64"] = {"ms_per_step": f["ms"], "value": f["pairs_per_step"] * 1e3 / f["ms"],
-                        "rates_kernel_ms": f["prof"]["rates"][1] / max(f["prof"]["rates"][0], 1)}
+                        "rates_kernel_ms": f["prof"]["rates"][1] / max(f["prof"]["rates"][0], 1),
+                        "kernel_ms": {g: round(v[1] / max(v[0], 1), 4)
+                                      for g, v in f["prof"].items() if v[0] > 0}}
         line["mixed_speedup_over_fp64"] = f["ms"] / m["ms"]
     line["unique_pairs_per_s"] = line["value"] / 2.0
     if "balance" in results:
