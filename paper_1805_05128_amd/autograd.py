@@ -6,9 +6,10 @@ and recording the time-step sequence.  The backward walks the segments in
 reverse: it restores a segment's checkpoint, recomputes the segment's
 states with the recorded time steps (bit-identical to the forward), then
 applies csph_step_vjp step by step and finally the VJP of the initial
-energy E0 = e(rho, p; gamma) + |v0|^2/2.  The time steps are held fixed
-(replayed), i.e. the gradient is that of the map at the recorded dt
-sequence.
+energy E0 = e(rho, p; gamma) + |v0|^2/2 when the rollout starts from
+(rho, p) (a window that starts from (rho, E) holds E fixed).  The time
+steps are held fixed (replayed), i.e. the gradient is that of the map at
+the recorded dt sequence.
 """
 from __future__ import annotations
 
@@ -36,11 +37,15 @@ def _with_gamma(params: A.Params, gamma: List[float]) -> A.Params:
 class CSPHRollout(torch.autograd.Function):
     """(vx0, vy0, vz0, gamma) -> final state (x, y, z, vx, vy, vz, rho, E).
 
-    ``base`` holds the device tensors x, y, z, rho, p, m, mat of the initial
-    state; ``params`` the run parameters (its gammas are replaced by the
-    ``gamma`` tensor); ``dts``, if given, is the list of time steps to use
-    instead of the CFL rule.  After the call, ``info['dts']`` holds the dt
-    sequence and ``info['forward_s']`` the forward wall time.
+    ``base`` holds the device tensors x, y, z, rho, m, mat of the initial
+    state and either p (the initial energy is then E0 = e(rho, p; gamma) +
+    |v0|^2/2, differentiated) or E (a window that starts from a state of a
+    longer run: E is held fixed, so the gradient is the partial derivative
+    at fixed specific total energy); ``params`` the run parameters (its
+    gammas are replaced by the ``gamma`` tensor); ``dts``, if given, is the
+    list of time steps to use instead of the CFL rule.  After the call,
+    ``info['dts']`` holds the dt sequence and ``info['forward_s']`` the
+    forward wall time.
     """
 
     @staticmethod
@@ -50,7 +55,10 @@ class CSPHRollout(torch.autograd.Function):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         pg = _with_gamma(params, gamma.detach().cpu().tolist())
-        E0 = A.csph_init_energy(base["rho"], base["p"], vx0, vy0, vz0, base["mat"], pg)
+        if "p" in base:
+            E0 = A.csph_init_energy(base["rho"], base["p"], vx0, vy0, vz0, base["mat"], pg)
+        else:
+            E0 = base["E"].clone()
         st = A.State({"x": base["x"].clone(), "y": base["y"].clone(), "z": base["z"].clone(),
                       "vx": vx0.detach().clone(), "vy": vy0.detach().clone(),
                       "vz": vz0.detach().clone(), "rho": base["rho"].clone(), "E": E0,
@@ -108,8 +116,9 @@ class CSPHRollout(torch.autograd.Function):
                 A.csph_step_vjp(states[k - k0], pg, ctx.dts[k], g, g_prev=g, g_eos=g_eos)
             states.clear()
         b = ctx.base
-        A.csph_init_energy_vjp(b["rho"], b["p"], vx0, vy0, vz0, b["mat"], pg, g["E"],
-                               g_v=(g["vx"], g["vy"], g["vz"]), g_eos=g_eos)
+        if "p" in b:
+            A.csph_init_energy_vjp(b["rho"], b["p"], vx0, vy0, vz0, b["mat"], pg, g["E"],
+                                   g_v=(g["vx"], g["vy"], g["vz"]), g_eos=g_eos)
         torch.cuda.synchronize()
         ctx.info["backward_s"] = time.perf_counter() - t0
         return (g["vx"], g["vy"], g["vz"], g_eos[0::2].clone(), None, None, None, None, None,

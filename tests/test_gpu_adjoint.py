@@ -166,12 +166,20 @@ def test_rollout_gradient_matches_reference_and_fd():
     gamma = torch.tensor([e[1] for e in w.eos], dtype=torch.float64, device=DEV,
                          requires_grad=True)
     nsteps, every = 12, 5
+    # the dt sequence of the oracle's run (CFL rule), replayed by both sides
+    cfg = O.cfg_for(w)
+    so, to, dts = O.state_from(w, cfg), 0.0, []
+    for _ in range(nsteps):
+        so, to, dt, _ = O.step(cfg, so, t=to)
+        dts.append(dt)
     info = {}
     out = P.rollout(*v0, gamma, base, params, nsteps, every, info=info)
+    # the GPU's own CFL steps agree with the oracle's
+    assert np.allclose(info["dts"], dts, rtol=1e-13, atol=0.0)
+    out = P.rollout(*v0, gamma, base, params, nsteps, every, dts=dts)
     mask = out["x"].detach() > 4.0
     J = _objective(out, mask, base["m"])
     grads = torch.autograd.grad(J, v0 + [gamma])
-    dts = info["dts"]
     assert len(dts) == nsteps and all(d > 0 for d in dts)
     # FP64 CPU reference: torch autograd over the same dt sequence
     et, gg, pi = tparams(w, True)
@@ -182,7 +190,6 @@ def test_rollout_gradient_matches_reference_and_fd():
     E0 = T.init_energy_torch(torch.as_tensor(w.rho), torch.as_tensor(w.p), *vr, mat, et, gg, pi)
     st = {"x": torch.as_tensor(w.x), "y": torch.as_tensor(w.y), "z": torch.as_tensor(w.z),
           "vx": vr[0], "vy": vr[1], "vz": vr[2], "rho": torch.as_tensor(w.rho), "E": E0}
-    cfg = O.cfg_for(w)
     for k in range(nsteps):
         pairs = T.pairs_of(cfg, {kk: st[kk].detach().numpy() for kk in ("x", "y", "z")})
         st = T.step_torch(st, m, mat, et, gg, pi, pairs, w.kappa * w.h, dts[k])
@@ -210,6 +217,66 @@ def test_rollout_gradient_matches_reference_and_fd():
         fd = (Jat(1) - Jat(-1)) / (2 * eps)
         pred = sum(float((grads[a].cpu().numpy() * d[a]).sum()) for a in range(3)) + \
             float((grads[3].cpu().numpy() * dg).sum())
+        assert abs(fd - pred) <= 1e-4 * max(abs(pred), 1e-8), (trial, fd, pred)
+
+
+def test_window_rollout_from_a_mid_run_state():
+    """A rollout that starts from a state of a longer run (x, v, rho, E; E held fixed):
+    gradients w.r.t. the window's velocities and gamma against the FP64 CPU reference
+    (autograd over the same dt sequence) and central differences."""
+    w = system(n=8, seed=12)
+    cfg = O.cfg_for(w)
+    s = O.state_from(w, cfg)
+    t0 = 0.0
+    for _ in range(4):  # the run before the window, on the oracle
+        s, t0, _, _ = O.step(cfg, s, t=t0)
+    params = P.Params.from_workload(w, cfl=0.3)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float64), device=DEV).contiguous()
+    base = dict(x=t(s["x"]), y=t(s["y"]), z=t(s["z"]), rho=t(s["rho"]), E=t(s["E"]),
+                m=t(s["m"]), mat=torch.as_tensor(s["mat"], dtype=torch.int32, device=DEV))
+    v0 = [t(s[k]).requires_grad_(True) for k in ("vx", "vy", "vz")]
+    gamma = torch.tensor([e[1] for e in w.eos], dtype=torch.float64, device=DEV,
+                         requires_grad=True)
+    nsteps, every = 5, 5  # one checkpoint, the other states recomputed
+    so, to, dts = s, t0, []
+    for _ in range(nsteps):  # the oracle's dt sequence for the window, replayed by both sides
+        so, to, dt, _ = O.step(cfg, so, t=to)
+        dts.append(dt)
+    out = P.rollout(*v0, gamma, base, params, nsteps, every, dts=dts)
+    mask = out["z"].detach() > 4.0
+    J = (out["vz"][mask] * base["m"][mask]).sum()
+    grads = torch.autograd.grad(J, v0 + [gamma])
+    et, gg, pi = tparams(w, True)
+    gg = gg.clone().detach().requires_grad_(True)
+    mat = torch.as_tensor(s["mat"]).long()
+    m = torch.as_tensor(s["m"])
+    vr = [torch.as_tensor(s[k]).clone().requires_grad_(True) for k in ("vx", "vy", "vz")]
+    st = {"x": torch.as_tensor(s["x"]), "y": torch.as_tensor(s["y"]),
+          "z": torch.as_tensor(s["z"]), "vx": vr[0], "vy": vr[1], "vz": vr[2],
+          "rho": torch.as_tensor(s["rho"]), "E": torch.as_tensor(s["E"])}
+    for k in range(nsteps):
+        pairs = T.pairs_of(cfg, {kk: st[kk].detach().numpy() for kk in ("x", "y", "z")})
+        st = T.step_torch(st, m, mat, et, gg, pi, pairs, w.kappa * w.h, dts[k])
+    mref = st["z"].detach() > 4.0
+    assert torch.equal(mref, mask.cpu())
+    Jr = (st["vz"][mref] * m[mref]).sum()
+    ref = torch.autograd.grad(Jr, vr + [gg])
+    assert abs(float(J.detach()) - float(Jr.detach())) <= 1e-11 * abs(float(Jr.detach()))
+    for a in range(3):
+        assert relmax(grads[a].cpu().numpy(), ref[a].numpy()) <= 1e-9, a
+    assert relmax(grads[3].cpu().numpy(), ref[3].numpy()) <= 1e-9
+    # E is held fixed: the gradient of the final state does not pass through an E0(v0) map
+    rng = np.random.default_rng(5)
+    for trial in range(3):
+        d = [rng.standard_normal(w.n) for _ in range(3)]
+        eps = 1e-6
+
+        def vz_at(sign):
+            vv = [v0[a].detach() + sign * eps * t(d[a]) for a in range(3)]
+            return P.rollout(*vv, gamma.detach(), base, params, nsteps, every, dts=dts)["vz"]
+
+        fd = float((base["m"] * (vz_at(1) - vz_at(-1)))[mask].sum()) / (2 * eps)
+        pred = sum(float((grads[a].cpu().numpy() * d[a]).sum()) for a in range(3))
         assert abs(fd - pred) <= 1e-4 * max(abs(pred), 1e-8), (trial, fd, pred)
 
 

@@ -7,7 +7,10 @@ configuration bench.py times (cell order, unit mesh cells, both precisions):
 * plate impact (589 824 particles): one full step of every particle, both
   precisions, and the compensated totals;
 * two-body collision (64 000 000 particles): rates of a seeded sample that
-  includes the contact layer, against the oracle computed for the sample.
+  includes the contact layer, against the oracle computed for the sample;
+  and the adjoint of the last 5 of its 50 steps (45 mixed steps in cell
+  order, then the FP64 window recomputed from one checkpoint) w.r.t. the
+  window's velocities, against central differences.
 """
 import math
 
@@ -123,3 +126,58 @@ def test_collision64m_rates_sampled():
         assert max(err.values()) <= tol, (prec, err)
         assert np.array_equal(got["nbr_count"][sample].astype(np.int64), ref["nbr_count"])
     assert nb == 32_000_000
+
+
+def test_collision64m_adjoint_last5_steps():
+    w = ci.config4()
+    print(f"[case] {w.name} adjoint of steps 46-50 n={w.n}", flush=True)
+    n = w.n
+    params = P.Params.from_workload(w, precision="mixed", reorder=True, cell_size=1.0)
+    window = P.Params.from_workload(w, precision="fp64", cell_size=1.0)
+    g = P.state_from_workload(w, params, DEV, with_id=False)
+    gamma = torch.tensor([e[1] for e in w.eos], dtype=torch.float64, device=DEV)
+    del w
+    sc = P.StepScalars(DEV)
+    other = g.like()
+    ws = P.Workspace(DEV)
+    for _ in range(45):
+        g, other = P.csph_step(g, params, sc, s_out=other, ws=ws, totals=False), g
+    torch.cuda.synchronize()
+    assert int(sc.nonphys.item()) == 0
+    del other, ws
+    torch.cuda.empty_cache()
+    base = {k: g.t[k] for k in ("x", "y", "z", "rho", "E", "m")}
+    base["mat"] = g.mat
+    m = base["m"]
+    v0 = [g.t[k].clone().requires_grad_(True) for k in ("vx", "vy", "vz")]
+    info = {}
+    out = P.rollout(*v0, gamma, base, window, 5, 5, info=info)
+    body_a = base["mat"] == 1  # objective: z-momentum of the dense body after the window
+    J = (out["vz"][body_a] * m[body_a]).sum()
+    grads = torch.autograd.grad(J, v0)
+    dts = info["dts"]
+    print("window dts", dts, "adjoint/forward %.2f" % (info["backward_s"] / info["forward_s"]),
+          flush=True)
+    del out
+    # directions on the contact layer (|z - z_c| < 8), where the pair terms carry the gradient
+    z = base["z"]
+    zc = 0.5 * (float(z[~body_a].max()) + float(z[body_a].min()))
+    layer = ((z - zc).abs() < 8.0).to(torch.float64)
+    gen = torch.Generator(device=DEV).manual_seed(2024)
+    eps = 1e-6
+    for trial in range(4):
+        d = [torch.randn(n, generator=gen, dtype=torch.float64, device=DEV) * layer
+             for _ in range(3)]
+        pred = sum(float((grads[a] * d[a]).sum()) for a in range(3))
+
+        def vz_at(sign):
+            vv = [v0[a].detach() + sign * eps * d[a] for a in range(3)]
+            return P.rollout(*vv, gamma, base, window, 5, 5, dts=dts)["vz"]
+
+        dvz = vz_at(1) - vz_at(-1)
+        fd = float((m * dvz)[body_a].sum()) / (2 * eps)
+        direct = float((m * d[2])[body_a].sum())
+        print(f"trial {trial}: fd {fd:.10e} adjoint {pred:.10e} (direct part {direct:.4e})",
+              flush=True)
+        assert abs(fd - pred) <= 1e-4 * abs(pred), (trial, fd, pred)
+        del dvz
