@@ -355,15 +355,25 @@ static int cmp_i64(const void *a, const void *b) {
 }
 
 /* Candidate j for particle i (all j, or the cells within reach), ascending. */
-static int64_t candidates(const nbr_space *sp, int64_t i, int64_t *buf, int64_t cap) {
+/* Candidates for partners of a point p (a particle, or the mirror image of one): all
+ * particles (brute force), or those of the cells within the reach of p's cell, clamped to
+ * the mesh (a point off the mesh then gets a superset of the particles within the support
+ * of it).  Ascending j. */
+static int64_t candidates_at(const nbr_space *sp, double px, double py, double pz,
+                             int64_t *buf, int64_t cap) {
     int64_t cnt = 0;
     if (sp->cfg->search == 0) {
         for (int64_t j = 0; j < sp->n && cnt < cap; ++j) buf[cnt++] = j;
         return cnt;
     }
     int32_t ci[3];
-    const double *c[3] = {sp->x, sp->y, sp->z};
-    for (int dd = 0; dd < 3; ++dd) ci[dd] = cell_coord(c[dd][i], sp->origin[dd], sp->inv, sp->dims[dd]);
+    const double p[3] = {px, py, pz};
+    for (int dd = 0; dd < 3; ++dd) {
+        double f = floor((p[dd] - sp->origin[dd]) * sp->inv);
+        if (f < 0.0) f = 0.0;
+        if (f > (double)(sp->dims[dd] - 1)) f = (double)(sp->dims[dd] - 1);
+        ci[dd] = (int32_t)f;
+    }
     int R = sp->reach;
     for (int oz = -R; oz <= R; ++oz) {
         int cz = ci[2] + oz;
@@ -382,6 +392,10 @@ static int64_t candidates(const nbr_space *sp, int64_t i, int64_t *buf, int64_t 
     }
     qsort(buf, (size_t)cnt, sizeof(int64_t), cmp_i64);
     return cnt;
+}
+
+static int64_t candidates(const nbr_space *sp, int64_t i, int64_t *buf, int64_t cap) {
+    return candidates_at(sp, sp->x[i], sp->y[i], sp->z[i], buf, cap);
 }
 
 static double max_support(const oracle_cfg *cfg, int64_t n, const double *d) {
@@ -549,8 +563,11 @@ static void rates_range(void *vctx, int64_t lo, int64_t hi) {
                       ctx->P[j], Zj, ctx->c[j], Vj, support_of(sp, i, j),
                       &s_rho, s_v, &s_E, &sig);
         }
-        /* mirror partners across the piston plane, ascending j (j = i included) */
+        /* mirror partners across the piston plane, ascending j (j = i included): the
+         * particles whose image lies within the support of i, i.e. those within the support
+         * of the image of i */
         if (cfg->wall) {
+            nc = candidates_at(sp, 2.0 * xw - sp->x[i], sp->y[i], sp->z[i], buf, cap);
             for (int64_t k = 0; k < nc; ++k) {
                 int64_t j = buf[k];
                 double xg = 2.0 * xw - sp->x[j];

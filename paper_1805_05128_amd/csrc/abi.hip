@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 #include "csph_internal.h"
@@ -194,9 +195,27 @@ static PairConst pair_const(const csph_params *p, double dmax) {
     c.dwc = (210.0 / M_PI) * (i2 * i2);
     c.h_dt = p->h;
     c.wall = p->wall != 0;
-    c.wall_x0 = p->wall_x0;
+    c.wall_y0 = p->wall_x0;  // the kernels see x and y swapped when there is a wall
     c.wall_v = p->wall_v;
     return c;
+}
+
+// The arrays the kernels see.  With a piston wall (a plane normal to x) the x
+// and y arrays are handed over swapped, so that the wall normal runs along the
+// slab axis of the cell order (PairConst); without one they are the caller's.
+static csph_state kernel_view(const csph_state &s, bool wall) {
+    csph_state v = s;
+    if (wall) {
+        std::swap(v.x, v.y);
+        std::swap(v.vx, v.vy);
+    }
+    return v;
+}
+
+static csph_rates_out kernel_view(const csph_rates_out &o, bool wall) {
+    csph_rates_out v = o;
+    if (wall) std::swap(v.dvx, v.dvy);
+    return v;
 }
 
 // slab = false: the plain linear cell key (the key csph_bin reports);
@@ -390,9 +409,11 @@ csph_status csph_rates(const csph_state *s, const csph_params *p, double t, csph
     if (r) return r;
     hipStream_t st = (hipStream_t)stream;
     int64_t n = s->n;
+    const csph_state sv = kernel_view(*s, p->wall);
+    const csph_rates_out ov = kernel_view(out, p->wall);
     csph_grid g;
     double dmax;
-    r = make_grid(s->x, s->y, s->z, s->d, n, p, ws, ws_bytes, st, &g, &dmax);
+    r = make_grid(sv.x, sv.y, sv.z, sv.d, n, p, ws, ws_bytes, st, &g, &dmax);
     if (r) return r;
     r = need_ws(ws_bytes, n, g.ncell, ws_needed);
     if (r) return r;
@@ -406,11 +427,11 @@ csph_status csph_rates(const csph_state *s, const csph_params *p, double t, csph
     bool pair = p->h_mode == CSPH_H_PAIR;
     {
         ProfScope pr(CSPH_PROF_BIN, st);
-        CSPH_HIP(launch_bin(s->x, s->y, s->z, n, gd, w, w.perm, nullptr, w.cs, st));
+        CSPH_HIP(launch_bin(sv.x, sv.y, sv.z, n, gd, w, w.perm, nullptr, w.cs, st));
     }
     {
         ProfScope pr(CSPH_PROF_PACK, st);
-        CSPH_HIP(launch_pack(*s, n, w.perm, eos, mixed, gd, w, w.srt, w.srt_mat,
+        CSPH_HIP(launch_pack(sv, n, w.perm, eos, mixed, gd, w, w.srt, w.srt_mat,
                              pair ? w.srt_d : nullptr, nullptr, nullptr, nonphys, st));
     }
     {
@@ -420,7 +441,7 @@ csph_status csph_rates(const csph_state *s, const csph_params *p, double t, csph
     }
     {
         ProfScope pr(CSPH_PROF_REORDER, st);
-        CSPH_HIP(launch_unsort_rates(n, w.perm, w, out, signal, nbr_count, st));
+        CSPH_HIP(launch_unsort_rates(n, w.perm, w, ov, signal, nbr_count, st));
     }
     return CSPH_OK;
 }
@@ -445,9 +466,10 @@ csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_para
         return fail(CSPH_EINVAL, "reorder = 1 needs s_out distinct from s_in");
     hipStream_t st = (hipStream_t)stream;
     int64_t n = s_in->n;
+    const csph_state vin = kernel_view(*s_in, p->wall), vout = kernel_view(*s_out, p->wall);
     csph_grid g;
     double dmax;
-    r = make_grid(s_in->x, s_in->y, s_in->z, s_in->d, n, p, ws, ws_bytes, st, &g, &dmax);
+    r = make_grid(vin.x, vin.y, vin.z, vin.d, n, p, ws, ws_bytes, st, &g, &dmax);
     if (r) return r;
     r = need_ws(ws_bytes, n, g.ncell, ws_needed);
     if (r) return r;
@@ -463,25 +485,25 @@ csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_para
     double *dd;
     int64_t *did;
     if (p->reorder) {
-        double *o[9] = {s_out->x, s_out->y, s_out->z, s_out->vx, s_out->vy, s_out->vz,
-                        s_out->rho, s_out->E, s_out->m};
+        double *o[9] = {vout.x, vout.y, vout.z, vout.vx, vout.vy, vout.vz,
+                        vout.rho, vout.E, vout.m};
         for (int k = 0; k < 9; ++k) dst[k] = o[k];
-        dmat = s_out->mat;
-        dd = pair ? s_out->d : nullptr;
-        did = s_out->id;
+        dmat = vout.mat;
+        dd = pair ? vout.d : nullptr;
+        did = vout.id;
     } else {
         for (int k = 0; k < 9; ++k) dst[k] = w.srt[k];
         dmat = w.srt_mat;
         dd = pair ? w.srt_d : nullptr;
-        did = s_in->id ? w.srt_id : nullptr;
+        did = vin.id ? w.srt_id : nullptr;
     }
     if (n > 0) {
         {
             ProfScope pr(CSPH_PROF_BIN, st);
-            CSPH_HIP(launch_bin(s_in->x, s_in->y, s_in->z, n, gd, w, w.perm, nullptr, w.cs, st));
+            CSPH_HIP(launch_bin(vin.x, vin.y, vin.z, n, gd, w, w.perm, nullptr, w.cs, st));
         }
         ProfScope pr(CSPH_PROF_PACK, st);
-        CSPH_HIP(launch_pack(*s_in, n, w.perm, eos, mixed, gd, w, dst, dmat, dd, did, s_in->id,
+        CSPH_HIP(launch_pack(vin, n, w.perm, eos, mixed, gd, w, dst, dmat, dd, did, vin.id,
                              nonphys, st));
     }
     // dt = cfl * min h/s; an empty set takes dt = 0
@@ -494,7 +516,7 @@ csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_para
     {
         ProfScope pr(CSPH_PROF_INTEGRATE, st);
         CSPH_HIP(launch_integrate(n, dst, w, p->cfl, dt_in, st));  // n = 0 writes zero partials
-        CSPH_HIP(launch_finish_step(n, w, p->cfl, dt_in, t, dt_used, totals, st));
+        CSPH_HIP(launch_finish_step(n, w, p->cfl, dt_in, t, dt_used, totals, p->wall, st));
     }
     ProfScope pro(CSPH_PROF_REORDER, st);
     if (n > 0) {
@@ -503,9 +525,9 @@ csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_para
                 CSPH_HIP(hipMemcpyAsync(nbr_count, w.cnt, sizeof(int32_t) * n,
                                         hipMemcpyDeviceToDevice, st));
         } else {
-            csph_state o = *s_out;
+            csph_state o = vout;
             if (!pair) o.d = nullptr;
-            CSPH_HIP(launch_unpermute(n, w.perm, w.srt, s_in->mat ? w.srt_mat : nullptr, dd,
+            CSPH_HIP(launch_unpermute(n, w.perm, w.srt, vin.mat ? w.srt_mat : nullptr, dd,
                                       did, w.cnt, o, nbr_count, st));
         }
     }
@@ -540,7 +562,8 @@ csph_status csph_vlist_build(const csph_state *s_in, csph_state *s_out, const cs
     ph.kappa = p->kappa * (1.0 + beta);
     csph_grid g;
     double dmax;
-    r = make_grid(s_in->x, s_in->y, s_in->z, nullptr, n, &ph, ws, ws_bytes, st, &g, &dmax);
+    const csph_state vin = kernel_view(*s_in, p->wall), vout = kernel_view(*s_out, p->wall);
+    r = make_grid(vin.x, vin.y, vin.z, nullptr, n, &ph, ws, ws_bytes, st, &g, &dmax);
     if (r) return r;
     r = need_ws(ws_bytes, n, g.ncell, ws_needed);
     if (r) return r;
@@ -550,29 +573,30 @@ csph_status csph_vlist_build(const csph_state *s_in, csph_state *s_out, const cs
     ws_layout(&w, ws, n, g.ncell);
     GridDev gd = grid_dev(g);
     EosDev eos = eos_dev(p);
-    double *o[9] = {s_out->x, s_out->y, s_out->z, s_out->vx, s_out->vy, s_out->vz,
-                    s_out->rho, s_out->E, s_out->m};
+    double *o[9] = {vout.x, vout.y, vout.z, vout.vx, vout.vy, vout.vz,
+                    vout.rho, vout.E, vout.m};
     double twall = 0.0;
     if (p->wall) CSPH_HIP(hipMemcpyAsync(&twall, t, sizeof(double), hipMemcpyDeviceToHost, st));
     {
         ProfScope pr(CSPH_PROF_BIN, st);
-        CSPH_HIP(launch_bin(s_in->x, s_in->y, s_in->z, n, gd, w, w.perm, nullptr, w.cs, st));
-        CSPH_HIP(launch_pack(*s_in, n, w.perm, eos, 0, gd, w, o, s_out->mat,
+        CSPH_HIP(launch_bin(vin.x, vin.y, vin.z, n, gd, w, w.perm, nullptr, w.cs, st));
+        CSPH_HIP(launch_pack(vin, n, w.perm, eos, 0, gd, w, o, s_out->mat,
                              s_out->d && s_in->d ? s_out->d : nullptr, s_out->id, s_in->id,
                              nullptr, st));
     }
     CSPH_HIP(hipStreamSynchronize(st));  // twall
     const double H = p->kappa * p->h;
     const double R = (1.0 + beta) * H;
-    const double xw = p->wall ? p->wall_x0 + p->wall_v * twall : 0.0;
+    const double yw = p->wall ? p->wall_x0 + p->wall_v * twall : 0.0;  // along the kernels' y
     unsigned long long over = 0;
     {
         ProfScope pr(CSPH_PROF_NEIGHBORS, st);
         CSPH_HIP(launch_fill_u64((unsigned long long *)w.nonphys, 0ull, 1, st));
-        CSPH_HIP(launch_vlist(n, (const double4 *)w.recA, w.cs, gd, R, p->wall, xw, cap,
+        CSPH_HIP(launch_vlist(n, (const double4 *)w.recA, w.cs, gd, R, p->wall, yw, cap,
                               vl_count, vl_idx, (unsigned long long *)w.nonphys, st));
+        const double *ref[3] = {s_out->x, s_out->y, s_out->z};  // the caller's axes
         for (int a = 0; a < 3; ++a)
-            CSPH_HIP(hipMemcpyAsync(x_ref + a * n, o[a], sizeof(double) * n,
+            CSPH_HIP(hipMemcpyAsync(x_ref + a * n, ref[a], sizeof(double) * n,
                                     hipMemcpyDeviceToDevice, st));
         CSPH_HIP(hipMemcpyAsync(&over, w.nonphys, sizeof(over), hipMemcpyDeviceToHost, st));
     }
@@ -609,10 +633,11 @@ csph_status csph_step_vlist(csph_state *s, const csph_params *p, double *t, doub
     PairConst pc = pair_const(p, 0.0);
     EosDev eos = eos_dev(p);
     const int mixed = p->precision == CSPH_MIXED;
-    double *cur[9] = {s->x, s->y, s->z, s->vx, s->vy, s->vz, s->rho, s->E, s->m};
+    const csph_state sv = kernel_view(*s, p->wall);
+    double *cur[9] = {sv.x, sv.y, sv.z, sv.vx, sv.vy, sv.vz, sv.rho, sv.E, sv.m};
     if (n > 0) {
         ProfScope pr(CSPH_PROF_PACK, st);
-        CSPH_HIP(launch_pack(*s, n, nullptr, eos, mixed, gd, w, nullptr, nullptr, nullptr,
+        CSPH_HIP(launch_pack(sv, n, nullptr, eos, mixed, gd, w, nullptr, nullptr, nullptr,
                              nullptr, nullptr, nonphys, st));
     }
     if (p->cfl > 0.0)
@@ -625,7 +650,7 @@ csph_status csph_step_vlist(csph_state *s, const csph_params *p, double *t, doub
     {
         ProfScope pr(CSPH_PROF_INTEGRATE, st);
         CSPH_HIP(launch_integrate(n, cur, w, p->cfl, dt_in, st));
-        CSPH_HIP(launch_finish_step(n, w, p->cfl, dt_in, t, dt_used, totals, st));
+        CSPH_HIP(launch_finish_step(n, w, p->cfl, dt_in, t, dt_used, totals, p->wall, st));
         if (disp) {
             CSPH_HIP(launch_fill_u64((unsigned long long *)disp, 0ull, 1, st));
             CSPH_HIP(launch_disp(n, s->x, s->y, s->z, x_ref, (unsigned long long *)disp, st));

@@ -63,7 +63,14 @@ struct PairConst {
     double dwc;      // (210/pi)/H^4 (fixed mode)
     double kappa;    // pair mode: H_ij = kappa * (0.5*(d_i+d_j))
     double h_dt;     // h in the CFL rule (fixed mode)
-    double wall_x0, wall_v;
+    // Piston wall y = wall_y0 + wall_v t in the kernels' axes.  The wall of the
+    // interface is normal to x; with a wall the library hands the kernels the
+    // x and y arrays (positions, velocities, rates) swapped, so that the wall
+    // normal runs along the slab axis of the cell order instead of its row
+    // axis: the particles within the support of the wall then fill a few
+    // waves instead of a few lanes of every wave that starts a row.  Squared
+    // distances ((dx dx + dy dy) + dz dz) do not change under the swap.
+    double wall_y0, wall_v;
     int pair_mode;
     int wall;
 };
@@ -196,7 +203,7 @@ hipError_t launch_rates(int64_t n, int mixed, const GridDev &g, const PairConst 
                         int vl_cap = 0);
 // k_vlist.hip
 hipError_t launch_vlist(int64_t n, const double4 *A, const int32_t *cs, const GridDev &g,
-                        double R, int wall, double xw, int cap, int32_t *count, int32_t *idx,
+                        double R, int wall, double yw, int cap, int32_t *count, int32_t *idx,
                         unsigned long long *over, hipStream_t st);
 hipError_t launch_disp(int64_t n, const double *x, const double *y, const double *z,
                        const double *ref, unsigned long long *out, hipStream_t st);
@@ -208,7 +215,7 @@ hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t 
 hipError_t launch_integrate(int64_t n, double *const st8[9], const Ws &w, double cfl, double dt_in,
                             hipStream_t st);
 hipError_t launch_finish_step(int64_t n, const Ws &w, double cfl, double dt_in, double *t, double *dt_used,
-                              double *totals, hipStream_t st);
+                              double *totals, int swap_xy, hipStream_t st);
 hipError_t launch_unpermute(int64_t n, const int32_t *perm, double *const src[9],
                             const int32_t *src_mat, const double *src_d, const int64_t *src_id,
                             const int32_t *src_cnt, const csph_state &out, int32_t *out_cnt,

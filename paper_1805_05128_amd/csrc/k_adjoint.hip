@@ -204,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
             }
             const int zz = t.cz + oz;
             const float gz = slab_gap(t.zc, zz);
-            row_range(cs, g, t, live, t.cy + oy, zz, gz * gz, t.xc, j0, len);
+            row_range(cs, g, t, live, t.cy + oy, zz, gz * gz, j0, len);
             jlast = len > 0 ? j0 + len - 1 : 0;
             k = 0;
             continue;

@@ -199,8 +199,8 @@ struct Rates64 {
     bool live, near_wall;
     double4 a, b;
     double2 zc;
-    double di, xw, vw2;
-    Stencil t;
+    double di, yw, vw2;  // wall position along y, twice its velocity
+    Stencil t, ti;       // stencils of i and of its mirror image
     double ar = 0.0, avx = 0.0, avy = 0.0, avz = 0.0, aE = 0.0, sig = 0.0;
     int qw = 0, qr = 0, cntl = 0;
 
@@ -213,8 +213,8 @@ struct Rates64 {
         const bool ghost = WALL && e < 0;
         const double4 aj = ld(A, j), bj = ld(B, j);
         const double2 zj = ld(Cz, j);
-        const double xj = ghost ? 2.0 * xw - aj.x : aj.x;
-        const double dx = xj - a.x, dy = aj.y - a.y, dz = aj.z - a.z;
+        const double yj = ghost ? 2.0 * yw - aj.y : aj.y;
+        const double dx = aj.x - a.x, dy = yj - a.y, dz = aj.z - a.z;
         const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
         double invH = pc.invH, dwc = pc.dwc;
         if (PAIR) {
@@ -223,7 +223,7 @@ struct Rates64 {
             const double i2 = invH * invH;
             dwc = (210.0 / M_PI) * (i2 * i2);
         }
-        pair64(has && r2 != 0.0, dx, dy, dz, r2, b, zc, ghost ? vw2 - bj.x : bj.x, bj.y, bj.z,
+        pair64(has && r2 != 0.0, dx, dy, dz, r2, b, zc, bj.x, ghost ? vw2 - bj.y : bj.y, bj.z,
                bj.w, zj.x, zj.y, aj.w, invH, dwc, ar, avx, avy, avz, aE, sig);
     }
 
@@ -233,9 +233,9 @@ struct Rates64 {
     template <bool GHOST>
     __device__ __forceinline__ void pass() {
         const bool on = live && (!GHOST || near_wall);
-        // mirror partners lie within the chord around the image of i behind the wall
-        const float xcen = GHOST ? (float)(2.0 * (xw - g.ox) * g.inv) - t.xc : t.xc;
-        int oy = t.R, oz = -t.R - 1;  // advanced to (-R, -R) before the first row
+        // mirror partners: the particles on the stencil around the image of i
+        const Stencil &st = GHOST ? ti : t;
+        int oy = st.R, oz = -st.R - 1;  // advanced to (-R, -R) before the first row
         int k = 0, j0 = 0, len = 0, jlast = 0;
         for (;;) {
             if (__any(qw - qr > kQ - kU)) {  // keep every ring at <= kQ - kU entries
@@ -243,13 +243,13 @@ struct Rates64 {
                 continue;
             }
             if (!__any(k < len)) {
-                if (++oy > t.R) {
-                    oy = -t.R;
-                    if (++oz > t.R) break;
+                if (++oy > st.R) {
+                    oy = -st.R;
+                    if (++oz > st.R) break;
                 }
-                const int zz = t.cz + oz;
-                const float gz = slab_gap(t.zc, zz);
-                row_range(cs, g, t, on, t.cy + oy, zz, gz * gz, xcen, j0, len);
+                const int zz = st.cz + oz;
+                const float gz = slab_gap(st.zc, zz);
+                row_range(cs, g, st, on, st.cy + oy, zz, gz * gz, j0, len);
                 jlast = len > 0 ? j0 + len - 1 : 0;
                 k = 0;
                 continue;
@@ -260,8 +260,8 @@ struct Rates64 {
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 const int j = j0 + k + u;
-                double xj = GHOST ? 2.0 * xw - aj[u].x : aj[u].x;
-                double dx = xj - a.x, dy = aj[u].y - a.y, dz = aj[u].z - a.z;
+                double yj = GHOST ? 2.0 * yw - aj[u].y : aj[u].y;
+                double dx = aj[u].x - a.x, dy = yj - a.y, dz = aj[u].z - a.z;
                 // exact FP64 membership, no contraction
                 double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
                 double H2 = pc.H2;
@@ -298,8 +298,8 @@ struct Rates64 {
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 const bool ghost = WALL && e[u] < 0;
-                const double xj = ghost ? 2.0 * xw - aj[u].x : aj[u].x;
-                const double dx = xj - a.x, dy = aj[u].y - a.y, dz = aj[u].z - a.z;
+                const double yj = ghost ? 2.0 * yw - aj[u].y : aj[u].y;
+                const double dx = aj[u].x - a.x, dy = yj - a.y, dz = aj[u].z - a.z;
                 const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
                 const bool acc = (k + u < len) && r2 < pc.H2;
                 qj[qw & (kQ - 1)][tid] = e[u];
@@ -346,15 +346,17 @@ __global__ __launch_bounds__(kBlock) void k_rates64(int64_t n, const double4 *__
         if (PAIR) k.di = dsz[s];
     }
     k.t = make_stencil(g, k.a.x, k.a.y, k.a.z, pc.H);
+    k.ti = k.t;
     k.sig = k.zc.y;
-    k.xw = 0.0;
+    k.yw = 0.0;
     k.vw2 = 0.0;
     k.near_wall = false;
     if (WALL) {
         double tt = t_dev ? *t_dev : t_host;
-        k.xw = pc.wall_x0 + pc.wall_v * tt;
+        k.yw = pc.wall_y0 + pc.wall_v * tt;
         k.vw2 = 2.0 * pc.wall_v;
-        k.near_wall = k.live && (k.a.x - k.xw < pc.H);
+        k.near_wall = k.live && mirror_band(g, k.a.y, k.yw, pc.H);
+        k.ti = image_stencil(g, k.t, 2.0 * k.yw - k.a.y);
     }
     int cnt;
     if (LIST) {
@@ -450,9 +452,9 @@ struct Rates32 {
     int tid, self;
     bool live, near_wall;
     float4 a, b, c;
-    double xi, yi, zi, di, xw;
+    double xi, yi, zi, di, yw;  // yw: wall position along y
     float wd, vw2, Df, cxf, lo, hi;
-    Stencil t;
+    Stencil t, ti;               // stencils of i and of its mirror image
     float ar = 0.f, avx = 0.f, avy = 0.f, avz = 0.f, aE = 0.f, sig = 0.f;
     int qw = 0, qr = 0, cnt = 0;
 
@@ -482,12 +484,12 @@ struct Rates32 {
         bool in = has && (LIST || r2 < H2lo);
         if (!LIST && has && !(r2 < H2lo)) {
             // near the support: decide membership in FP64 (rare)
-            const double xj = ghost ? 2.0 * xw - xs[j] : xs[j];
-            const double ex = xj - xi, ey = ys[j] - yi, ez = zs[j] - zi;
+            const double yj = ghost ? 2.0 * yw - ys[j] : ys[j];
+            const double ex = xs[j] - xi, ey = yj - yi, ez = zs[j] - zi;
             in = ((ex * ex) + (ey * ey)) + (ez * ez) < H2d;
         }
         cnt += (in && !ghost) ? 1 : 0;
-        pair32(in && r2 != 0.0f, q.x, q.y, q.z, r2, b, c, ghost ? vw2 - bj.x : bj.x, bj.y,
+        pair32(in && r2 != 0.0f, q.x, q.y, q.z, r2, b, c, bj.x, ghost ? vw2 - bj.y : bj.y,
                bj.z, bj.w, cj.x, cj.y, cj.z, invH, dwc, ar, avx, avy, avz, aE, sig);
     }
 
@@ -496,8 +498,9 @@ struct Rates32 {
     __device__ __forceinline__ void pass() {
 #pragma clang fp contract(fast)
         const bool on = live && (!GHOST || near_wall);
-        const float xcen = GHOST ? (float)(2.0 * (xw - g.ox) * g.inv) - t.xc : t.xc;
-        int oy = t.R, oz = -t.R - 1;
+        // mirror partners: the particles on the stencil around the image of i
+        const Stencil &st = GHOST ? ti : t;
+        int oy = st.R, oz = -st.R - 1;
         int k = 0, j0 = 0, len = 0, jlast = 0;
         float ay = 0.f, az = 0.f;
         for (;;) {
@@ -506,15 +509,16 @@ struct Rates32 {
                 continue;
             }
             if (!__any(k < len)) {
-                if (++oy > t.R) {
-                    oy = -t.R;
-                    if (++oz > t.R) break;
+                if (++oy > st.R) {
+                    oy = -st.R;
+                    if (++oz > st.R) break;
                 }
-                const int zz = t.cz + oz;
-                const float gz = slab_gap(t.zc, zz);
-                row_range(cs, g, t, on, t.cy + oy, zz, gz * gz, xcen, j0, len);
+                const int yy = st.cy + oy, zz = st.cz + oz;
+                const float gz = slab_gap(st.zc, zz);
+                row_range(cs, g, st, on, yy, zz, gz * gz, j0, len);
                 jlast = len > 0 ? j0 + len - 1 : 0;
-                ay = a.y - (float)oy * Df;
+                // i's offsets from the row's cell origin (rows counted from i's own cell)
+                ay = a.y - (float)(yy - t.cy) * Df;
                 az = a.z - (float)oz * Df;
                 k = 0;
                 continue;
@@ -527,7 +531,7 @@ struct Rates32 {
                 const int j = j0 + k + u;
                 float dx = (aj[u].x + (aj[u].w - cxf) * Df) - a.x;
                 float dy = aj[u].y - ay, dz = aj[u].z - az;
-                if (GHOST) dx = 2.0f * wd - dx;
+                if (GHOST) dy = 2.0f * wd - dy;
                 float r2 = (dx * dx + dy * dy) + dz * dz;
                 float hj = hi;
                 if (PAIR) {
@@ -564,8 +568,8 @@ struct Rates32 {
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 const bool ghost = WALL && e[u] < 0;
-                const double xj = ghost ? 2.0 * xw - pj[u].x : pj[u].x;
-                const double dx = xj - xi, dy = pj[u].y - yi, dz = pj[u].z - zi;
+                const double yj = ghost ? 2.0 * yw - pj[u].y : pj[u].y;
+                const double dx = pj[u].x - xi, dy = yj - yi, dz = pj[u].z - zi;
                 const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
                 const bool acc = (k + u < len) && r2 < pc.H2;
                 qd[qw & (kQ - 1)][tid] =
@@ -630,16 +634,18 @@ __global__ __launch_bounds__(kBlock) void k_rates32(int64_t n, const float4 *__r
     k.cxf = (float)k.t.cx;
     k.lo = (float)pc.H2 * (1.0f - kBand);
     k.hi = (float)pc.H2 * (1.0f + kBand);
-    k.xw = 0.0;
+    k.ti = k.t;
+    k.yw = 0.0;
     k.wd = 0.f;
     k.vw2 = 0.f;
     k.near_wall = false;
     if (WALL) {
         double tt = t_dev ? *t_dev : t_host;
-        k.xw = pc.wall_x0 + pc.wall_v * tt;
-        k.near_wall = k.live && (k.xi - k.xw < pc.H);
-        k.wd = (float)(k.xw - k.xi);
+        k.yw = pc.wall_y0 + pc.wall_v * tt;
+        k.near_wall = k.live && mirror_band(g, k.yi, k.yw, pc.H);
+        k.wd = (float)(k.yw - k.yi);
         k.vw2 = (float)(2.0 * pc.wall_v);
+        k.ti = image_stencil(g, k.t, 2.0 * k.yw - k.yi);
     }
     if (LIST) {
         const int len = k.live ? min(vl.count[s], vl.cap) : 0;

@@ -130,7 +130,7 @@ hipError_t launch_integrate(int64_t n, double *const st8[9], const Ws &w, double
 __global__ __launch_bounds__(kBlock) void k_finish(const double *__restrict__ part, int nblocks,
                                                    const unsigned long long *dtmin, double cfl,
                                                    double dt_in, double *t, double *dt_used,
-                                                   double *totals) {
+                                                   double *totals, int swap_xy) {
     __shared__ double sh[2][5][kBlock];
     DD acc[5];
     for (int k = 0; k < 5; ++k) acc[k] = DD{0.0, 0.0};
@@ -154,8 +154,11 @@ __global__ __launch_bounds__(kBlock) void k_finish(const double *__restrict__ pa
         __syncthreads();
     }
     if (threadIdx.x < 5 && totals) {
-        totals[2 * threadIdx.x] = sh[0][threadIdx.x][0];
-        totals[2 * threadIdx.x + 1] = sh[1][threadIdx.x][0];
+        // sums k = 1, 2 are the momenta along the state's x and y arrays, which are the
+        // caller's y and x when the library swapped them
+        const int k = threadIdx.x, o = swap_xy && (k == 1 || k == 2) ? 3 - k : k;
+        totals[2 * o] = sh[0][k][0];
+        totals[2 * o + 1] = sh[1][k][0];
     }
     if (threadIdx.x == 0) {
         double dt = step_dt(dtmin, cfl, dt_in);
@@ -165,9 +168,9 @@ __global__ __launch_bounds__(kBlock) void k_finish(const double *__restrict__ pa
 }
 
 hipError_t launch_finish_step(int64_t n, const Ws &w, double cfl, double dt_in, double *t,
-                                double *dt_used, double *totals, hipStream_t st) {
+                                double *dt_used, double *totals, int swap_xy, hipStream_t st) {
     k_finish<<<1, kBlock, 0, st>>>(w.tot_part, integrate_blocks(n), w.dtmin, cfl, dt_in, t,
-                                   dt_used, totals);
+                                   dt_used, totals, swap_xy);
     return hipGetLastError();
 }
 

@@ -1,7 +1,9 @@
 // Verlet lists (sec. 4.2): for each particle, in cell order, the partners
 // within the horizon R = (1 + beta) H, found on the chord-clipped stencil rows
 // of the cell mesh with the exact FP64 test r^2 < R^2 (no contraction), plus
-// mirror partners across the piston wall (sign bit set).  A step then tests
+// mirror partners across the piston wall (sign bit set; the wall is normal to
+// the kernels' y axis, and they are found on the stencil around the image of
+// the particle).  A step then tests
 // only the listed partners (r^2 < H^2), which gives N(i) exactly while no
 // pair can have closed in from beyond R; the displacement kernel below feeds
 // the caller's rebuild test.
@@ -13,7 +15,7 @@ namespace csph {
 template <bool WALL>
 __global__ __launch_bounds__(kBlock) void k_vlist(int64_t n, const double4 *__restrict__ A,
                                                   const int32_t *__restrict__ cs, GridDev g,
-                                                  double R, double R2, double xw, int cap,
+                                                  double R, double R2, double yw, int cap,
                                                   int32_t *__restrict__ count,
                                                   int32_t *__restrict__ idx,
                                                   unsigned long long *__restrict__ over) {
@@ -22,7 +24,8 @@ __global__ __launch_bounds__(kBlock) void k_vlist(int64_t n, const double4 *__re
     const double4 ai = live ? A[s] : make_double4(0.0, 0.0, 0.0, 0.0);
     const double xi = ai.x, yi = ai.y, zi = ai.z;
     const Stencil t = make_stencil(g, xi, yi, zi, R);
-    const bool near = WALL && live && (xi - xw < R);
+    const Stencil ti = WALL ? image_stencil(g, t, 2.0 * yw - yi) : t;
+    const bool near = WALL && live && mirror_band(g, yi, yw, R);
     // blocked: entry c of particle s at idx[((c / 8) n + s) 8 + c % 8]; one lane fills whole
     // 32-byte chunks and a wave reading its lanes' entry c touches 16 cache lines
     int32_t *out = idx + (live ? s * kVlChunk : 0);
@@ -31,19 +34,19 @@ __global__ __launch_bounds__(kBlock) void k_vlist(int64_t n, const double4 *__re
         const bool ghost = pass == 1;
         if (ghost && !__any(near)) break;
         const bool on = live && (!ghost || near);
-        // mirror partners lie within the chord around the image of i behind the wall
-        const float xcen = ghost ? (float)(2.0 * (xw - g.ox) * g.inv) - t.xc : t.xc;
-        int oy = t.R, oz = -t.R - 1;
+        // mirror partners: the particles on the stencil around the image of i
+        const Stencil &st = ghost ? ti : t;
+        int oy = st.R, oz = -st.R - 1;
         int k = 0, j0 = 0, len = 0, jlast = 0;
         for (;;) {
             if (!__any(k < len)) {
-                if (++oy > t.R) {
-                    oy = -t.R;
-                    if (++oz > t.R) break;
+                if (++oy > st.R) {
+                    oy = -st.R;
+                    if (++oz > st.R) break;
                 }
-                const int zz = t.cz + oz;
-                const float gz = slab_gap(t.zc, zz);
-                row_range(cs, g, t, on, t.cy + oy, zz, gz * gz, xcen, j0, len);
+                const int zz = st.cz + oz;
+                const float gz = slab_gap(st.zc, zz);
+                row_range(cs, g, st, on, st.cy + oy, zz, gz * gz, j0, len);
                 jlast = len > 0 ? j0 + len - 1 : 0;
                 k = 0;
                 continue;
@@ -52,8 +55,8 @@ __global__ __launch_bounds__(kBlock) void k_vlist(int64_t n, const double4 *__re
             for (int u = 0; u < kU; ++u) {
                 const int j = min(j0 + k + u, jlast);
                 const double4 aj = ld(A, j);
-                const double xj = ghost ? 2.0 * xw - aj.x : aj.x;
-                const double dx = xj - xi, dy = aj.y - yi, dz = aj.z - zi;
+                const double yj = ghost ? 2.0 * yw - aj.y : aj.y;
+                const double dx = aj.x - xi, dy = yj - yi, dz = aj.z - zi;
                 const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
                 const bool acc = (k + u < len) && (ghost || j != (int)s) && r2 < R2;
                 if (acc) {
@@ -98,15 +101,15 @@ __global__ __launch_bounds__(kBlock) void k_disp(int64_t n, const double *__rest
 }
 
 hipError_t launch_vlist(int64_t n, const double4 *A, const int32_t *cs, const GridDev &g,
-                        double R, int wall, double xw, int cap, int32_t *count, int32_t *idx,
+                        double R, int wall, double yw, int cap, int32_t *count, int32_t *idx,
                         unsigned long long *over, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
     const double R2 = R * R;
     if (wall)
-        k_vlist<true><<<nb, kBlock, 0, st>>>(n, A, cs, g, R, R2, xw, cap, count, idx, over);
+        k_vlist<true><<<nb, kBlock, 0, st>>>(n, A, cs, g, R, R2, yw, cap, count, idx, over);
     else
-        k_vlist<false><<<nb, kBlock, 0, st>>>(n, A, cs, g, R, R2, xw, cap, count, idx, over);
+        k_vlist<false><<<nb, kBlock, 0, st>>>(n, A, cs, g, R, R2, yw, cap, count, idx, over);
     return hipGetLastError();
 }
 

@@ -58,6 +58,29 @@ __device__ __forceinline__ Stencil make_stencil(const GridDev &g, double x, doub
     return t;
 }
 
+// Stencil of the mirror image (x, y', z) of a particle across a wall plane
+// normal to y (the kernels' y axis; see csph_internal.h): the image may lie
+// off the mesh, so its y cell is not clamped (rows off the mesh are skipped);
+// x, z, the chord centre and the reach are the particle's own.  Walking it
+// visits every particle whose mirror image lies within the support of the
+// particle, wherever the particles are relative to the wall.
+__device__ __forceinline__ Stencil image_stencil(const GridDev &g, const Stencil &t,
+                                                 double y_image) {
+    Stencil s = t;
+    const double f = floor((y_image - g.oy) * g.inv);
+    s.cy = (int)fmin(fmax(f, -1048576.0), 1048576.0);
+    s.yc = (float)((y_image - g.oy) * g.inv);
+    return s;
+}
+
+// Whether a particle at y can have mirror partners within support H: some
+// particle's image 2 yw - y_j lies within H of it.  The images lie at or below
+// yw + (yw - min_j y_j), and the mesh origin is that minimum, so particles
+// behind the wall widen the band in front of it.
+__device__ __forceinline__ bool mirror_band(const GridDev &g, double y, double yw, double H) {
+    return y - yw < H + fmax(yw - g.oy, 0.0);
+}
+
 // Distance in cell units from coordinate c to the slab [k, k+1) (0 inside),
 // shrunk by a margin.
 __device__ __forceinline__ float slab_gap(float c, int k) {
@@ -65,22 +88,21 @@ __device__ __forceinline__ float slab_gap(float c, int k) {
     return fmaxf(d - 1e-3f, 0.0f);
 }
 
-// Candidate range [j0, j0+len) of row (yy, zz) for a particle: the cells of
-// the row within the chord its support sphere cuts through the row, centred
-// at x = xcen in cell units (the particle itself, or for mirror partners its
-// image behind the wall).  gz2 = squared z gap.  Branch-free per lane; a row
-// off the mesh or missing the sphere gets len = 0, and when it does so for
-// every lane of the wave the cell-range loads are skipped.
+// Candidate range [j0, j0+len) of row (yy, zz) for a particle (or its
+// image): the cells of the row within the chord its support sphere cuts
+// through the row.  gz2 = squared z gap.  Branch-free per lane; a row off the
+// mesh or missing the sphere gets len = 0, and when it does so for every lane
+// of the wave the cell-range loads are skipped.
 __device__ __forceinline__ void row_range(const int32_t *__restrict__ cs, const GridDev &g,
                                           const Stencil &t, bool on, int yy, int zz, float gz2,
-                                          float xcen, int &j0, int &len) {
+                                          int &j0, int &len) {
     const bool inb = on && zz >= 0 && zz < g.dz && yy >= 0 && yy < g.dy;
     const float gy = slab_gap(t.yc, yy);
     const float rem = t.w2 - (gy * gy + gz2);
     // chord half-width; v_sqrt_f32 (1 ulp) is ample under the margins
     const float hw = __builtin_amdgcn_sqrtf(fmaxf(rem, 0.0f)) * 1.0001f + 1e-3f;
-    const int xa = max(max((int)floorf(xcen - hw), t.cx - t.R), 0);
-    const int xb = min(min((int)floorf(xcen + hw), t.cx + t.R), g.dx - 1);
+    const int xa = max(max((int)floorf(t.xc - hw), t.cx - t.R), 0);
+    const int xb = min(min((int)floorf(t.xc + hw), t.cx + t.R), g.dx - 1);
     const bool ok = inb && rem > 0.0f && xb >= xa;
     j0 = 0;
     len = 0;

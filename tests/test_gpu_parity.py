@@ -41,6 +41,15 @@ def wall_block(seed=5):
     return w
 
 
+def behind_wall_block(seed=7):
+    """The piston wall inside the block (x_w = 5.5 + 0.5 t, particles from x = 0.5 to
+    11.5): particles on both sides of it, some farther behind it than the support, whose
+    mirror partners lie around their image, off the cells around them."""
+    w = ci.jittered_block(12, 10, 9, seed=seed, v=(-0.2, 0.1, 0.05))
+    w.wall = (5.5, 0.5)
+    return w
+
+
 def two_material_cloud(n=3000, seed=11):
     w = ci.random_cloud(n, seed=seed, box=10.0, n_mat=2)
     w.cell_size = 3.0
@@ -78,6 +87,7 @@ CASES = {
     "mg": mg_block,
     "cloud2mat": two_material_cloud,
     "wall": wall_block,
+    "behind": behind_wall_block,
     "ragged": lambda: ci.random_cloud(777, seed=3, box=7.3, vmax=1.0),
 }
 
@@ -236,10 +246,11 @@ def test_rates_pair_h_mie_grueneisen(prec, tol):
     assert 15 < ref["nbr_count"].mean() < 30
 
 
+@pytest.mark.parametrize("make", [wall_block, behind_wall_block])
 @pytest.mark.parametrize("D", [1.0, 1.5, 2.2])
-def test_rates_small_cells(D):
+def test_rates_small_cells(D, make):
     """Cells smaller than the support (stencil reach ceil(H/D) > 1) give the same rates."""
-    w = wall_block()
+    w = make()
     w.cell_size = D
     for prec, tol in (("fp64", FP64_TOL), ("mixed", MIXED_TOL)):
         got, ref = _rates_case(w, prec, t=0.1)
@@ -312,7 +323,7 @@ def _check_totals(tot_gpu, s_ref):
 
 
 @pytest.mark.parametrize("reorder", [False, True])
-@pytest.mark.parametrize("case", ["sod16", "wall", "cloud2mat", "slab", "mg"])
+@pytest.mark.parametrize("case", ["sod16", "wall", "behind", "cloud2mat", "slab", "mg"])
 def test_step_fp64(case, reorder):
     w = CASES[case]()
     _print_case(f"{case} reorder={reorder}", w)

@@ -22,6 +22,14 @@ def wall_block(seed=5):
     return w
 
 
+def behind_block(seed=7):
+    """The wall inside the block: particles on both sides of it, some farther behind it
+    than the horizon (their mirror partners lie around their image)."""
+    w = ci.jittered_block(12, 10, 9, seed=seed, v=(-0.2, 0.1, 0.05))
+    w.wall = (5.5, 0.5)
+    return w
+
+
 def moving_cloud(seed=9):
     """Random cloud with large random velocities: the displacement bound forces rebuilds
     before n_upd steps."""
@@ -36,7 +44,8 @@ def slab_cloud(seed=21):
     return w
 
 
-CASES = {"sod16": ci.config0, "wall": wall_block, "moving": moving_cloud, "slab": slab_cloud}
+CASES = {"sod16": ci.config0, "wall": wall_block, "behind": behind_block,
+         "moving": moving_cloud, "slab": slab_cloud}
 
 
 def horizon_pairs(w, R, t):
@@ -61,7 +70,7 @@ def horizon_pairs(w, R, t):
     return out
 
 
-@pytest.mark.parametrize("case", ["sod16", "wall", "slab"])
+@pytest.mark.parametrize("case", ["sod16", "wall", "behind", "slab"])
 def test_lists_are_the_horizon_pairs(case):
     w = CASES[case]()
     beta = 0.3
@@ -70,7 +79,7 @@ def test_lists_are_the_horizon_pairs(case):
     g = P.state_from_workload(w, params, DEV, with_id=True)
     sc = P.StepScalars(DEV, t0=0.375)
     other = g.like()
-    cap = 400
+    cap = 512  # behind the wall a particle has real and mirror partners all round
     count = torch.zeros(w.n, dtype=torch.int32, device=DEV)
     idx = torch.empty(w.n * cap, dtype=torch.int32, device=DEV)
     xref = torch.empty(3 * w.n, dtype=torch.float64, device=DEV)
@@ -131,7 +140,7 @@ def _run(w, precision, beta, n_upd, steps, cap=None):
     return run, worst
 
 
-@pytest.mark.parametrize("case", ["sod16", "wall", "moving", "slab"])
+@pytest.mark.parametrize("case", ["sod16", "wall", "behind", "moving", "slab"])
 def test_verlet_run_fp64_follows_oracle(case):
     w = CASES[case]()
     print(f"[case] verlet fp64 {case} n={w.n}", flush=True)

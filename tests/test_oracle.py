@@ -159,16 +159,28 @@ def test_support_strict(orc):
     assert off.tolist() == [0, 1, 1, 2] and idx.tolist() == [2, 0]
 
 
-@pytest.mark.parametrize("wl", ["cloud", "sod", "wall"])
+@pytest.mark.parametrize("wl", ["cloud", "sod", "wall", "behind"])
 def test_grid_search_equals_brute_force(orc, wl):
     if wl == "cloud":
         w = ci.random_cloud(3000, seed=11, box=10.0, n_mat=2)
         d = None
     elif wl == "sod":
         w = ci.config0()
-    else:
+    elif wl == "wall":
         w = ci.jittered_block(10, 9, 8, seed=5, v=(-0.2, 0.1, 0.0))
         w.wall = (0.0, 0.4)
+    else:
+        # the wall at x = 6 with particles on both sides: a particle 5.5 behind it has
+        # mirror partners 9 away (near its image), off the cells around the particle
+        w = ci.jittered_block(10, 9, 8, seed=5, v=(-0.2, 0.1, 0.0))
+        w.wall = (6.0, 0.0)
+        H = w.kappa * w.h
+        gx = 2.0 * 6.0 - w.x
+        far = 0
+        for i in np.nonzero(w.x < 1.0)[0]:
+            r2 = ((gx - w.x[i]) ** 2 + (w.y - w.y[i]) ** 2) + (w.z - w.z[i]) ** 2
+            far += int(np.sum((r2 < H * H) & (np.abs(w.x - w.x[i]) > 2.0 * H)))
+        assert far > 0
     cb = orc.cfg_for(w, search=0)
     cg = orc.cfg_for(w, search=1)
     s = orc.state_from(w, cb)
