@@ -204,13 +204,14 @@ struct Rates64 {
     double ar = 0.0, avx = 0.0, avy = 0.0, avz = 0.0, aE = 0.0, sig = 0.0;
     int qw = 0, qr = 0, cntl = 0;
 
-    // every lane pops its next partner, if it has one
+    // every lane pops its next partner, if it has one; MIR: the wave may hold mirror entries
+    template <bool MIR>
     __device__ __forceinline__ void drain() {
         const bool has = qr < qw;
         const int e = qj[qr & (kQ - 1)][tid];
         qr += has ? 1 : 0;
         const int j = has ? (e & 0x7fffffff) : 0;
-        const bool ghost = WALL && e < 0;
+        const bool ghost = MIR && e < 0;
         const double4 aj = ld(A, j), bj = ld(B, j);
         const double2 zj = ld(Cz, j);
         const double yj = ghost ? 2.0 * yw - aj.y : aj.y;
@@ -230,7 +231,7 @@ struct Rates64 {
     // one walk over the stencil: real partners, or mirror partners (GHOST).
     // One flat loop with wave-uniform branches (drain / next row / test a
     // chunk), so the sums stay in place across iterations.
-    template <bool GHOST>
+    template <bool GHOST, bool MIR>
     __device__ __forceinline__ void pass() {
         const bool on = live && (!GHOST || near_wall);
         // mirror partners: the particles on the stencil around the image of i
@@ -239,7 +240,7 @@ struct Rates64 {
         int k = 0, j0 = 0, len = 0, jlast = 0;
         for (;;) {
             if (__any(qw - qr > kQ - kU)) {  // keep every ring at <= kQ - kU entries
-                drain();
+                drain<MIR>();
                 continue;
             }
             if (!__any(k < len)) {
@@ -285,7 +286,7 @@ struct Rates64 {
         int k = 0;
         for (;;) {
             if (__any(qw - qr > kQ - kU)) {
-                drain();
+                drain<WALL>();
                 continue;
             }
             if (!__any(k < len)) break;
@@ -363,12 +364,18 @@ __global__ __launch_bounds__(kBlock) void k_rates64(int64_t n, const double4 *__
         const int len = k.live ? min(vl.count[s], vl.cap) : 0;
         k.pass_list(vl.idx + (k.live ? s * kVlChunk : 0), len, n);
         cnt = k.cntl;
-    } else {
-        k.template pass<false>();
+        while (__any(k.qr < k.qw)) k.template drain<WALL>();
+    } else if (WALL && __any(k.near_wall)) {
+        // a wave with particles in the wall band: real, then mirror partners
+        k.template pass<false, true>();
         cnt = k.qw;  // real partners accepted
-        if (WALL && __any(k.near_wall)) k.template pass<true>();
+        k.template pass<true, true>();
+        while (__any(k.qr < k.qw)) k.template drain<true>();
+    } else {
+        k.template pass<false, false>();
+        cnt = k.qw;
+        while (__any(k.qr < k.qw)) k.template drain<false>();
     }
-    while (__any(k.qr < k.qw)) k.drain();
     double dtv = INFINITY;
     if (k.live) {
         double ri = rho[s];
@@ -389,6 +396,12 @@ __global__ __launch_bounds__(kBlock) void k_rates64(int64_t n, const double4 *__
 
 // ---------------------------------------------------------------- mixed rates (FP32 pairs)
 
+// max of two non-negative floats (sound and signal speeds): their bit patterns order like
+// the values, so an integer max is exact, in one instruction (fmaxf quiets both inputs first)
+__device__ __forceinline__ float fmax_nonneg(float a, float b) {
+    return __int_as_float(max(__float_as_int(a), __float_as_int(b)));
+}
+
 __device__ __forceinline__ void pair32(bool use, float dx, float dy, float dz, float r2,
                                        const float4 &bi, const float4 &ci, float vxj, float vyj,
                                        float vzj, float Pj, float Zj, float cj, float Vj,
@@ -400,7 +413,7 @@ __device__ __forceinline__ void pair32(bool use, float dx, float dy, float dz, f
     const float ex = dx * ir, ey = dy * ir, ez = dz * ir;
     const float q = r * invH;
     const float a1 = 1.0f - q;
-    const float dW = -dwc * q * (a1 * a1 * a1);
+    const float dW = -(use ? dwc : 0.0f) * q * (a1 * a1 * a1);
     // v_L - v_R from the velocity difference (no cancellation of bulk motion)
     const float vrel = ((bi.x - vxj) * ex + (bi.y - vyj) * ey) + (bi.z - vzj) * ez;
     const float vL = (bi.x * ex + bi.y * ey) + bi.z * ez;
@@ -414,19 +427,18 @@ __device__ __forceinline__ void pair32(bool use, float dx, float dy, float dz, f
     const float dP = sok ? Pi - Pj : 0.0f, ZZ = sok ? Zi * Zj : 0.0f;
     const float dvl = (Zjd * vrel - dP) * iS;
     const float ps = ((Zjd * Pi + Zid * Pj) + ZZ * vrel) * iS;
-    // a lane without a partner adds exact zeros: its weight and the two factors that carry
-    // partner data are selected to 0, every other factor is finite (r2 = 1, finite offsets)
-    const float dvlm = use ? dvl : 0.0f, psm = use ? ps : 0.0f;
-    const float wgt = use ? Vj * dW : 0.0f;
-    const float vs = vL - dvlm;
-    const float f = wgt * psm;
-    const float sp = fmaxf(ci.y, cj) + fmaxf(vrel, 0.0f);
-    ar += wgt * dvlm;
+    // a lane without a partner adds exact zeros: its weight is 0 (dW with the kernel constant
+    // selected to 0) and every factor it multiplies is finite (r2 = 1, finite offsets)
+    const float wgt = Vj * dW;
+    const float vs = vL - dvl;
+    const float f = wgt * ps;
+    const float sp = fmax_nonneg(ci.y, cj) + fmaxf(vrel, 0.0f);
+    ar += wgt * dvl;
     avx += f * ex;
     avy += f * ey;
     avz += f * ez;
     aE += f * vs;
-    sig = (use && sp > sig) ? sp : sig;
+    sig = fmax_nonneg(sig, use ? sp : 0.0f);
 }
 
 // Candidates whose FP32 squared distance lies within this relative band of
@@ -458,7 +470,8 @@ struct Rates32 {
     float ar = 0.f, avx = 0.f, avy = 0.f, avz = 0.f, aE = 0.f, sig = 0.f;
     int qw = 0, qr = 0, cnt = 0;
 
-    // every lane pops its next partner, if it has one
+    // every lane pops its next partner, if it has one; MIR: the wave may hold mirror entries
+    template <bool MIR>
     __device__ __forceinline__ void drain() {
 #pragma clang fp contract(fast)
         const bool has = qr < qw;
@@ -466,7 +479,7 @@ struct Rates32 {
         qr += has ? 1 : 0;
         const int e = __float_as_int(q.w);
         const int j = has ? (e & 0x7fffffff) : 0;
-        const bool ghost = WALL && e < 0;
+        const bool ghost = MIR && e < 0;
         const float4 bj = ld(B, j), cj = ld(Cz, j);
         float invH = (float)pc.invH, dwc = (float)pc.dwc;
         float H2lo = lo;
@@ -494,7 +507,7 @@ struct Rates32 {
     }
 
     // flat loop as in the FP64 kernel
-    template <bool GHOST>
+    template <bool GHOST, bool MIR>
     __device__ __forceinline__ void pass() {
 #pragma clang fp contract(fast)
         const bool on = live && (!GHOST || near_wall);
@@ -505,7 +518,7 @@ struct Rates32 {
         float ay = 0.f, az = 0.f;
         for (;;) {
             if (__any(qw - qr > kQ - kU)) {
-                drain();
+                drain<MIR>();
                 continue;
             }
             if (!__any(k < len)) {
@@ -554,7 +567,7 @@ struct Rates32 {
         int k = 0;
         for (;;) {
             if (__any(qw - qr > kQ - kU)) {
-                drain();
+                drain<WALL>();
                 continue;
             }
             if (!__any(k < len)) break;
@@ -650,11 +663,16 @@ __global__ __launch_bounds__(kBlock) void k_rates32(int64_t n, const float4 *__r
     if (LIST) {
         const int len = k.live ? min(vl.count[s], vl.cap) : 0;
         k.pass_list(vl.idx + (k.live ? s * kVlChunk : 0), len, n);
+        while (__any(k.qr < k.qw)) k.template drain<WALL>();
+    } else if (WALL && __any(k.near_wall)) {
+        // a wave with particles in the wall band: real, then mirror partners
+        k.template pass<false, true>();
+        k.template pass<true, true>();
+        while (__any(k.qr < k.qw)) k.template drain<true>();
     } else {
-        k.template pass<false>();
-        if (WALL && __any(k.near_wall)) k.template pass<true>();
+        k.template pass<false, false>();
+        while (__any(k.qr < k.qw)) k.template drain<false>();
     }
-    while (__any(k.qr < k.qw)) k.drain();
     double dtv = INFINITY;
     if (k.live) {
         double ri = rho[s];
