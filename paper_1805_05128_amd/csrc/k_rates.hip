@@ -108,18 +108,22 @@ hipError_t launch_pack(const csph_state &s, int64_t n, const int32_t *perm, cons
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- block min -> global
+// ---------------------------------------------------------------- wave min -> global
 
-__device__ __forceinline__ void block_min_to(double v, unsigned long long *dst) {
+// The FP32 rate kernel runs one wave per workgroup: its occupancy is bound by the LDS rings,
+// and a wave's ring is released as soon as the wave ends (partner counts, hence wave run
+// times, vary widely; a larger workgroup holds its rings until its slowest wave ends).  The
+// FP64 kernel's occupancy is bound by registers; it keeps four-wave workgroups.
+constexpr int kRate32Block = 64;
+constexpr int kRate64Block = kBlock;
+
+// min over the wave of v >= 0 into *dst (bits of a non-negative double); the atomic is
+// skipped when it cannot lower the current value
+__device__ __forceinline__ void wave_min_to(double v, unsigned long long *dst) {
     for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    __shared__ double sh[kBlock / 64];
-    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) sh[wid] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double r = sh[0];
-        for (int q = 1; q < kBlock / 64; ++q) r = fmin(r, sh[q]);
-        if (r >= 0.0) atomicMin(dst, dbits(r));
+    if ((threadIdx.x & 63) == 0 && v >= 0.0) {
+        const unsigned long long b = dbits(v);
+        if (b < __atomic_load_n(dst, __ATOMIC_RELAXED)) atomicMin(dst, b);
     }
 }
 
@@ -194,7 +198,7 @@ struct Rates64 {
     const int32_t *__restrict__ cs;
     GridDev g;
     PairConst pc;
-    int (*qj)[kBlock];
+    int (*qj)[kRate64Block];
     int tid, self;
     bool live, near_wall;
     double4 a, b;
@@ -313,7 +317,7 @@ struct Rates64 {
 };
 
 template <bool PAIR, bool WALL, bool LIST>
-__global__ __launch_bounds__(kBlock) void k_rates64(int64_t n, const double4 *__restrict__ A,
+__global__ __launch_bounds__(kRate64Block) void k_rates64(int64_t n, const double4 *__restrict__ A,
                                                     const double4 *__restrict__ B,
                                                     const double2 *__restrict__ Cz,
                                                     const double *__restrict__ rho,
@@ -322,7 +326,7 @@ __global__ __launch_bounds__(kBlock) void k_rates64(int64_t n, const double4 *__
                                                     PairConst pc, const double *t_dev,
                                                     double t_host, RateOut o, int want_dt,
                                                     VList vl) {
-    __shared__ int qj[kQ][kBlock];
+    __shared__ int qj[kQ][kRate64Block];
     Rates64<PAIR, WALL> k;
     k.A = A;
     k.B = B;
@@ -333,7 +337,7 @@ __global__ __launch_bounds__(kBlock) void k_rates64(int64_t n, const double4 *__
     k.pc = pc;
     k.qj = qj;
     k.tid = threadIdx.x;
-    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kRate64Block + threadIdx.x;
     k.self = (int)s;
     k.live = s < n;
     k.a = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -391,7 +395,7 @@ __global__ __launch_bounds__(kBlock) void k_rates64(int64_t n, const double4 *__
         // Courant limit and relative density-change limit of one explicit step
         dtv = fmin((PAIR ? k.di : pc.h_dt) / k.sig, ri / fabs(drho));
     }
-    if (want_dt) block_min_to(dtv, o.dtmin);
+    if (want_dt) wave_min_to(dtv, o.dtmin);
 }
 
 // ---------------------------------------------------------------- mixed rates (FP32 pairs)
@@ -460,7 +464,7 @@ struct Rates32 {
     const double4 *__restrict__ P4;  // list walks: FP64 position record
     GridDev g;
     PairConst pc;
-    float4 (*qd)[kBlock];
+    float4 (*qd)[kRate32Block];
     int tid, self;
     bool live, near_wall;
     float4 a, b, c;
@@ -595,7 +599,7 @@ struct Rates32 {
 };
 
 template <bool PAIR, bool WALL, bool LIST>
-__global__ __launch_bounds__(kBlock) void k_rates32(int64_t n, const float4 *__restrict__ A,
+__global__ __launch_bounds__(kRate32Block) void k_rates32(int64_t n, const float4 *__restrict__ A,
                                                     const float4 *__restrict__ B,
                                                     const float4 *__restrict__ Cz,
                                                     const double *__restrict__ xs,
@@ -607,7 +611,7 @@ __global__ __launch_bounds__(kBlock) void k_rates32(int64_t n, const float4 *__r
                                                     PairConst pc, const double *t_dev,
                                                     double t_host, RateOut o, int want_dt,
                                                     VList vl) {
-    __shared__ float4 qd[kQ][kBlock];
+    __shared__ float4 qd[kQ][kRate32Block];
     // finite placeholder offsets for lanes that pop from an empty ring
 #pragma unroll
     for (int q = 0; q < kQ; ++q) qd[q][threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -625,7 +629,7 @@ __global__ __launch_bounds__(kBlock) void k_rates32(int64_t n, const float4 *__r
     k.pc = pc;
     k.qd = qd;
     k.tid = threadIdx.x;
-    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kRate32Block + threadIdx.x;
     k.self = (int)s;
     k.live = s < n;
     k.a = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -687,7 +691,7 @@ __global__ __launch_bounds__(kBlock) void k_rates32(int64_t n, const float4 *__r
         if (o.cnt) o.cnt[s] = k.cnt;
         dtv = fmin((PAIR ? k.di : pc.h_dt) / (double)k.sig, ri / fabs(drho));
     }
-    if (want_dt) block_min_to(dtv, o.dtmin);
+    if (want_dt) wave_min_to(dtv, o.dtmin);
 }
 
 hipError_t launch_rates(int64_t n, int mixed, const GridDev &g, const PairConst &pc,
@@ -698,24 +702,22 @@ hipError_t launch_rates(int64_t n, int mixed, const GridDev &g, const PairConst 
     const double *rho_sorted = sorted[6];
     RateOut o{w.rate[0], w.rate[1], w.rate[2], w.rate[3], w.rate[4], w.sig, w.cnt, w.dtmin};
     VList vl{vl_count, vl_idx, vl_cap};
-    unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    const unsigned nb32 = (unsigned)((n + kRate32Block - 1) / kRate32Block);
+    const unsigned nb64 = (unsigned)((n + kRate64Block - 1) / kRate64Block);
     const bool pair = pc.pair_mode != 0, wall = pc.wall != 0, list = vl_idx != nullptr;
     if (list && pair) return hipErrorInvalidValue;
-#define CSPH_RATES_CASE(P, W, L)                                                               \
-    if (pair == P && wall == W && list == L) {                                                 \
-        if (mixed)                                                                             \
-            k_rates32<P, W, L><<<nb, kBlock, 0, st>>>(n, (const float4 *)w.recA,               \
-                                                      (const float4 *)w.recB,                  \
-                                                      (const float4 *)w.recC, sorted[0],       \
-                                                      sorted[1], sorted[2], rho_sorted,        \
-                                                      d_sorted, w.cs, g, pc, t_dev, t_host, o, \
-                                                      want_dt, vl);                            \
-        else                                                                                   \
-            k_rates64<P, W, L><<<nb, kBlock, 0, st>>>(n, (const double4 *)w.recA,              \
-                                                      (const double4 *)w.recB,                 \
-                                                      (const double2 *)w.recC, rho_sorted,     \
-                                                      d_sorted, w.cs, g, pc, t_dev, t_host, o, \
-                                                      want_dt, vl);                            \
+#define CSPH_RATES_CASE(P, W, L)                                                              \
+    if (pair == P && wall == W && list == L) {                                                \
+        if (mixed)                                                                            \
+            k_rates32<P, W, L><<<nb32, kRate32Block, 0, st>>>(                                \
+                n, (const float4 *)w.recA, (const float4 *)w.recB, (const float4 *)w.recC,    \
+                sorted[0], sorted[1], sorted[2], rho_sorted, d_sorted, w.cs, g, pc, t_dev,    \
+                t_host, o, want_dt, vl);                                                      \
+        else                                                                                  \
+            k_rates64<P, W, L><<<nb64, kRate64Block, 0, st>>>(                                \
+                n, (const double4 *)w.recA, (const double4 *)w.recB,                          \
+                (const double2 *)w.recC, rho_sorted, d_sorted, w.cs, g, pc, t_dev, t_host, o, \
+                want_dt, vl);                                                                 \
     }
     CSPH_RATES_CASE(false, false, false)
     CSPH_RATES_CASE(false, true, false)
