@@ -94,7 +94,8 @@ size_t ws_layout(Ws *w, void *base, int64_t n, int64_t ncell) {
     Ws t;
     t.bounds_part = (double *)take(sizeof(double) * 8 * kReduceBlocks);
     t.bounds_out = (double *)take(sizeof(double) * 8);
-    t.dtmin = (unsigned long long *)take(sizeof(unsigned long long));
+    t.dtmin = (unsigned long long *)take(2 * sizeof(unsigned long long));
+    t.zflag = t.dtmin ? t.dtmin + 1 : nullptr;
     t.nonphys = (int64_t *)take(sizeof(int64_t));
     t.tot_part = (double *)take(sizeof(double) * 10 * kReduceBlocks);
     int64_t scan_len = (n > ncell ? n : ncell) + 1;
@@ -429,6 +430,7 @@ csph_status csph_rates(const csph_state *s, const csph_params *p, double t, csph
         ProfScope pr(CSPH_PROF_BIN, st);
         CSPH_HIP(launch_bin(sv.x, sv.y, sv.z, n, gd, w, w.perm, nullptr, w.cs, st));
     }
+    CSPH_HIP(launch_fill_u64(w.dtmin, 0x7ff0000000000000ull, 2, st));  // dt min, Z flag
     {
         ProfScope pr(CSPH_PROF_PACK, st);
         CSPH_HIP(launch_pack(sv, n, w.perm, eos, mixed, gd, w, w.srt, w.srt_mat,
@@ -497,6 +499,8 @@ csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_para
         dd = pair ? w.srt_d : nullptr;
         did = vin.id ? w.srt_id : nullptr;
     }
+    // dt = cfl * min h/s (an empty set takes dt = 0); the pack clears the Z flag
+    CSPH_HIP(launch_fill_u64(w.dtmin, n > 0 ? 0x7ff0000000000000ull : 0ull, 2, st));
     if (n > 0) {
         {
             ProfScope pr(CSPH_PROF_BIN, st);
@@ -506,9 +510,6 @@ csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_para
         CSPH_HIP(launch_pack(vin, n, w.perm, eos, mixed, gd, w, dst, dmat, dd, did, vin.id,
                              nonphys, st));
     }
-    // dt = cfl * min h/s; an empty set takes dt = 0
-    if (p->cfl > 0.0)
-        CSPH_HIP(launch_fill_u64(w.dtmin, n > 0 ? 0x7ff0000000000000ull : 0ull, 1, st));
     if (n > 0) {
         ProfScope pr(CSPH_PROF_RATES, st);
         CSPH_HIP(launch_rates(n, mixed, gd, pc, w, dst, dd, t, 0.0, p->cfl > 0.0, st));
@@ -635,13 +636,13 @@ csph_status csph_step_vlist(csph_state *s, const csph_params *p, double *t, doub
     const int mixed = p->precision == CSPH_MIXED;
     const csph_state sv = kernel_view(*s, p->wall);
     double *cur[9] = {sv.x, sv.y, sv.z, sv.vx, sv.vy, sv.vz, sv.rho, sv.E, sv.m};
+    // dt = cfl * min h/s (an empty set takes dt = 0); the pack clears the Z flag
+    CSPH_HIP(launch_fill_u64(w.dtmin, n > 0 ? 0x7ff0000000000000ull : 0ull, 2, st));
     if (n > 0) {
         ProfScope pr(CSPH_PROF_PACK, st);
         CSPH_HIP(launch_pack(sv, n, nullptr, eos, mixed, gd, w, nullptr, nullptr, nullptr,
                              nullptr, nullptr, nonphys, st));
     }
-    if (p->cfl > 0.0)
-        CSPH_HIP(launch_fill_u64(w.dtmin, n > 0 ? 0x7ff0000000000000ull : 0ull, 1, st));
     if (n > 0) {
         ProfScope pr(CSPH_PROF_RATES, st);
         CSPH_HIP(launch_rates(n, mixed, gd, pc, w, cur, nullptr, t, 0.0, p->cfl > 0.0, st,

@@ -171,6 +171,7 @@ struct Ws {
     double *sig;                  // signal speed (cell order)
     int32_t *cnt;                 // neighbour count (cell order)
     unsigned long long *dtmin;    // bits of min_i h_i/s_i
+    unsigned long long *zflag;    // 0 once the pack meets a zero impedance Z = rho c
     int64_t *nonphys;             // scratch counter
     double *tot_part;             // kReduceBlocks * 10
     size_t bytes;

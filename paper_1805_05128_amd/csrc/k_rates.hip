@@ -35,7 +35,8 @@ __global__ __launch_bounds__(kBlock) void k_pack(int64_t n, SrcState src,
                                                  GridDev g, void *__restrict__ recA,
                                                  void *__restrict__ recB,
                                                  void *__restrict__ recC, DstState dst,
-                                                 int64_t *__restrict__ nonphys) {
+                                                 int64_t *__restrict__ nonphys,
+                                                 unsigned long long *__restrict__ zflag) {
     int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s >= n) return;
     const int i = perm ? perm[s] : (int)s;  // no permutation: records of the state in place
@@ -60,6 +61,9 @@ __global__ __launch_bounds__(kBlock) void k_pack(int64_t n, SrcState src,
     double c = bad ? 0.0 : sqrt(c2);
     if (bad && nonphys) atomicAdd((unsigned long long *)nonphys, 1ull);
     double Z = rho * c, V = m / rho;
+    // a zero impedance (in the precision the pairs use) needs the pair step's Z_i + Z_j = 0
+    // branch; every writer stores the same value
+    if ((MIXED ? (float)Z : Z) == 0.0 && zflag) *zflag = 0ull;
     if (MIXED && !perm) {  // list walks: FP64 position record
         ((double4 *)recA)[s] = make_double4(x, y, z, V);
         ((float4 *)recB)[s] = make_float4((float)vx, (float)vy, (float)vz, (float)P);
@@ -101,10 +105,10 @@ hipError_t launch_pack(const csph_state &s, int64_t n, const int32_t *perm, cons
     unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
     if (mixed)
         k_pack<true><<<nb, kBlock, 0, st>>>(n, src, perm, eos, g, recA, w.recB, w.recC, ds,
-                                            nonphys);
+                                            nonphys, w.zflag);
     else
         k_pack<false><<<nb, kBlock, 0, st>>>(n, src, perm, eos, g, recA, w.recB, w.recC, ds,
-                                             nonphys);
+                                             nonphys, w.zflag);
     return hipGetLastError();
 }
 
@@ -141,6 +145,7 @@ struct RateOut {
     double *rho, *vx, *vy, *vz, *E, *sig;
     int32_t *cnt;
     unsigned long long *dtmin;
+    const unsigned long long *zflag;  // 0: some impedance is zero (see k_pack)
 };
 
 // ---------------------------------------------------------------- FP64 rates
@@ -153,6 +158,9 @@ struct RateOut {
 
 // One partner of particle i: Riemann problem along e, kernel slope, sums.
 // The membership test that precedes it is exact; here contraction is allowed.
+// ZS: some impedance may be zero, so Z_i + Z_j = 0 takes the mean state; otherwise that
+// branch is left out.
+template <bool ZS>
 __device__ __forceinline__ void pair64(bool use, double dx, double dy, double dz, double r2,
                                        const double4 &bi, const double2 &ci,
                                        double vxj, double vyj, double vzj, double Pj, double Zj,
@@ -170,7 +178,7 @@ __device__ __forceinline__ void pair64(bool use, double dx, double dy, double dz
     const double vR = (vxj * ex + vyj * ey) + vzj * ez;
     const double Zi = ci.x, Pi = bi.w;
     const double S = Zi + Zj;
-    const bool sok = S != 0.0;
+    const bool sok = !ZS || S != 0.0;
     const double iS = 1.0 / (sok ? S : 1.0);
     const double vs = sok ? ((Zi * vL + Zj * vR) + (Pi - Pj)) * iS : 0.5 * (vL + vR);
     const double ps = sok ? ((Zj * Pi + Zi * Pj) + Zi * Zj * (vL - vR)) * iS : 0.5 * (Pi + Pj);
@@ -209,7 +217,7 @@ struct Rates64 {
     int qw = 0, qr = 0, cntl = 0;
 
     // every lane pops its next partner, if it has one; MIR: the wave may hold mirror entries
-    template <bool MIR>
+    template <bool MIR, bool ZS>
     __device__ __forceinline__ void drain() {
         const bool has = qr < qw;
         const int e = qj[qr & (kQ - 1)][tid];
@@ -228,14 +236,14 @@ struct Rates64 {
             const double i2 = invH * invH;
             dwc = (210.0 / M_PI) * (i2 * i2);
         }
-        pair64(has && r2 != 0.0, dx, dy, dz, r2, b, zc, bj.x, ghost ? vw2 - bj.y : bj.y, bj.z,
+        pair64<ZS>(has && r2 != 0.0, dx, dy, dz, r2, b, zc, bj.x, ghost ? vw2 - bj.y : bj.y, bj.z,
                bj.w, zj.x, zj.y, aj.w, invH, dwc, ar, avx, avy, avz, aE, sig);
     }
 
     // one walk over the stencil: real partners, or mirror partners (GHOST).
     // One flat loop with wave-uniform branches (drain / next row / test a
     // chunk), so the sums stay in place across iterations.
-    template <bool GHOST, bool MIR>
+    template <bool GHOST, bool MIR, bool ZS>
     __device__ __forceinline__ void pass() {
         const bool on = live && (!GHOST || near_wall);
         // mirror partners: the particles on the stencil around the image of i
@@ -244,7 +252,7 @@ struct Rates64 {
         int k = 0, j0 = 0, len = 0, jlast = 0;
         for (;;) {
             if (__any(qw - qr > kQ - kU)) {  // keep every ring at <= kQ - kU entries
-                drain<MIR>();
+                drain<MIR, ZS>();
                 continue;
             }
             if (!__any(k < len)) {
@@ -283,14 +291,37 @@ struct Rates64 {
         }
     }
 
+    // The whole walk: a Verlet list, or the stencil (and, for a wave with particles in the
+    // wall band, the stencil around their images); every pop drained.  Returns |N(i)|.
+    template <bool LIST, bool ZS>
+    __device__ __forceinline__ int run(const int32_t *__restrict__ lst, int len, int64_t nl) {
+        int cnt;
+        if (LIST) {
+            pass_list<ZS>(lst, len, nl);
+            cnt = cntl;
+            while (__any(qr < qw)) drain<WALL, ZS>();
+        } else if (WALL && __any(near_wall)) {
+            pass<false, true, ZS>();
+            cnt = qw;  // real partners accepted
+            pass<true, true, ZS>();
+            while (__any(qr < qw)) drain<true, ZS>();
+        } else {
+            pass<false, false, ZS>();
+            cnt = qw;
+            while (__any(qr < qw)) drain<false, ZS>();
+        }
+        return cnt;
+    }
+
     // Verlet-list walk: the lane's own list in chunks of kU, exact FP64 membership
     // (mirror partners across the wall for flagged entries)
+    template <bool ZS>
     __device__ __forceinline__ void pass_list(const int32_t *__restrict__ lst, int len,
                                               int64_t nl) {
         int k = 0;
         for (;;) {
             if (__any(qw - qr > kQ - kU)) {
-                drain<WALL>();
+                drain<WALL, ZS>();
                 continue;
             }
             if (!__any(k < len)) break;
@@ -363,23 +394,10 @@ __global__ __launch_bounds__(kRate64Block) void k_rates64(int64_t n, const doubl
         k.near_wall = k.live && mirror_band(g, k.a.y, k.yw, pc.H);
         k.ti = image_stencil(g, k.t, 2.0 * k.yw - k.a.y);
     }
-    int cnt;
-    if (LIST) {
-        const int len = k.live ? min(vl.count[s], vl.cap) : 0;
-        k.pass_list(vl.idx + (k.live ? s * kVlChunk : 0), len, n);
-        cnt = k.cntl;
-        while (__any(k.qr < k.qw)) k.template drain<WALL>();
-    } else if (WALL && __any(k.near_wall)) {
-        // a wave with particles in the wall band: real, then mirror partners
-        k.template pass<false, true>();
-        cnt = k.qw;  // real partners accepted
-        k.template pass<true, true>();
-        while (__any(k.qr < k.qw)) k.template drain<true>();
-    } else {
-        k.template pass<false, false>();
-        cnt = k.qw;
-        while (__any(k.qr < k.qw)) k.template drain<false>();
-    }
+    const int len = LIST && k.live ? min(vl.count[s], vl.cap) : 0;
+    const int32_t *lst = LIST ? vl.idx + (k.live ? s * kVlChunk : 0) : nullptr;
+    const int cnt = *o.zflag == 0 ? k.template run<LIST, true>(lst, len, n)
+                                  : k.template run<LIST, false>(lst, len, n);
     double dtv = INFINITY;
     if (k.live) {
         double ri = rho[s];
@@ -406,6 +424,7 @@ __device__ __forceinline__ float fmax_nonneg(float a, float b) {
     return __int_as_float(max(__float_as_int(a), __float_as_int(b)));
 }
 
+template <bool ZS>
 __device__ __forceinline__ void pair32(bool use, float dx, float dy, float dz, float r2,
                                        const float4 &bi, const float4 &ci, float vxj, float vyj,
                                        float vzj, float Pj, float Zj, float cj, float Vj,
@@ -425,7 +444,7 @@ __device__ __forceinline__ void pair32(bool use, float dx, float dy, float dz, f
     const float S = Zi + Zj;
     // v_L - v* and P*; S = 0 (both impedances zero) takes the mean state, written as
     // the same expressions with Z_i = Z_j = 1 and the P and (v_L - v_R) terms dropped
-    const bool sok = S != 0.0f;
+    const bool sok = !ZS || S != 0.0f;
     const float iS = __builtin_amdgcn_rcpf(sok ? S : 2.0f);
     const float Zjd = sok ? Zj : 1.0f, Zid = sok ? Zi : 1.0f;
     const float dP = sok ? Pi - Pj : 0.0f, ZZ = sok ? Zi * Zj : 0.0f;
@@ -475,7 +494,7 @@ struct Rates32 {
     int qw = 0, qr = 0, cnt = 0;
 
     // every lane pops its next partner, if it has one; MIR: the wave may hold mirror entries
-    template <bool MIR>
+    template <bool MIR, bool ZS>
     __device__ __forceinline__ void drain() {
 #pragma clang fp contract(fast)
         const bool has = qr < qw;
@@ -506,12 +525,12 @@ struct Rates32 {
             in = ((ex * ex) + (ey * ey)) + (ez * ez) < H2d;
         }
         cnt += (in && !ghost) ? 1 : 0;
-        pair32(in && r2 != 0.0f, q.x, q.y, q.z, r2, b, c, bj.x, ghost ? vw2 - bj.y : bj.y,
+        pair32<ZS>(in && r2 != 0.0f, q.x, q.y, q.z, r2, b, c, bj.x, ghost ? vw2 - bj.y : bj.y,
                bj.z, bj.w, cj.x, cj.y, cj.z, invH, dwc, ar, avx, avy, avz, aE, sig);
     }
 
     // flat loop as in the FP64 kernel
-    template <bool GHOST, bool MIR>
+    template <bool GHOST, bool MIR, bool ZS>
     __device__ __forceinline__ void pass() {
 #pragma clang fp contract(fast)
         const bool on = live && (!GHOST || near_wall);
@@ -522,7 +541,7 @@ struct Rates32 {
         float ay = 0.f, az = 0.f;
         for (;;) {
             if (__any(qw - qr > kQ - kU)) {
-                drain<MIR>();
+                drain<MIR, ZS>();
                 continue;
             }
             if (!__any(k < len)) {
@@ -564,14 +583,32 @@ struct Rates32 {
         }
     }
 
+    // The whole walk: a Verlet list, or the stencil (and, for a wave with particles in the
+    // wall band, the stencil around their images); every pop drained.
+    template <bool LIST_, bool ZS>
+    __device__ __forceinline__ void run(const int32_t *__restrict__ lst, int len, int64_t nl) {
+        if (LIST_) {
+            pass_list<ZS>(lst, len, nl);
+            while (__any(qr < qw)) drain<WALL, ZS>();
+        } else if (WALL && __any(near_wall)) {
+            pass<false, true, ZS>();
+            pass<true, true, ZS>();
+            while (__any(qr < qw)) drain<true, ZS>();
+        } else {
+            pass<false, false, ZS>();
+            while (__any(qr < qw)) drain<false, ZS>();
+        }
+    }
+
     // Verlet-list walk: exact FP64 membership from the FP64 positions; the ring takes
     // the FP32 offsets (mirrored for flagged entries)
+    template <bool ZS>
     __device__ __forceinline__ void pass_list(const int32_t *__restrict__ lst, int len,
                                               int64_t nl) {
         int k = 0;
         for (;;) {
             if (__any(qw - qr > kQ - kU)) {
-                drain<WALL>();
+                drain<WALL, ZS>();
                 continue;
             }
             if (!__any(k < len)) break;
@@ -664,19 +701,12 @@ __global__ __launch_bounds__(kRate32Block) void k_rates32(int64_t n, const float
         k.vw2 = (float)(2.0 * pc.wall_v);
         k.ti = image_stencil(g, k.t, 2.0 * k.yw - k.yi);
     }
-    if (LIST) {
-        const int len = k.live ? min(vl.count[s], vl.cap) : 0;
-        k.pass_list(vl.idx + (k.live ? s * kVlChunk : 0), len, n);
-        while (__any(k.qr < k.qw)) k.template drain<WALL>();
-    } else if (WALL && __any(k.near_wall)) {
-        // a wave with particles in the wall band: real, then mirror partners
-        k.template pass<false, true>();
-        k.template pass<true, true>();
-        while (__any(k.qr < k.qw)) k.template drain<true>();
-    } else {
-        k.template pass<false, false>();
-        while (__any(k.qr < k.qw)) k.template drain<false>();
-    }
+    const int len = LIST && k.live ? min(vl.count[s], vl.cap) : 0;
+    const int32_t *lst = LIST ? vl.idx + (k.live ? s * kVlChunk : 0) : nullptr;
+    if (*o.zflag == 0)
+        k.template run<LIST, true>(lst, len, n);
+    else
+        k.template run<LIST, false>(lst, len, n);
     double dtv = INFINITY;
     if (k.live) {
         double ri = rho[s];
@@ -700,7 +730,8 @@ hipError_t launch_rates(int64_t n, int mixed, const GridDev &g, const PairConst 
                         const int32_t *vl_count, const int32_t *vl_idx, int vl_cap) {
     if (n <= 0) return hipSuccess;
     const double *rho_sorted = sorted[6];
-    RateOut o{w.rate[0], w.rate[1], w.rate[2], w.rate[3], w.rate[4], w.sig, w.cnt, w.dtmin};
+    RateOut o{w.rate[0], w.rate[1], w.rate[2], w.rate[3], w.rate[4], w.sig, w.cnt, w.dtmin,
+              w.zflag};
     VList vl{vl_count, vl_idx, vl_cap};
     const unsigned nb32 = (unsigned)((n + kRate32Block - 1) / kRate32Block);
     const unsigned nb64 = (unsigned)((n + kRate64Block - 1) / kRate64Block);
@@ -751,7 +782,8 @@ __global__ __launch_bounds__(kBlock) void k_unsort_rates(int64_t n,
 hipError_t launch_unsort_rates(int64_t n, const int32_t *perm, const Ws &w, csph_rates_out out,
                                double *signal, int32_t *nbr_count, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    RateOut src{w.rate[0], w.rate[1], w.rate[2], w.rate[3], w.rate[4], w.sig, w.cnt, w.dtmin};
+    RateOut src{w.rate[0], w.rate[1], w.rate[2], w.rate[3], w.rate[4], w.sig, w.cnt, w.dtmin,
+                w.zflag};
     k_unsort_rates<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(n, perm, src, out,
                                                                              signal, nbr_count);
     return hipGetLastError();

@@ -50,6 +50,16 @@ def behind_wall_block(seed=7):
     return w
 
 
+def cold_cloud(n=1500, seed=17):
+    """Every third particle a cold ideal gas (p = 0, at rest): c = 0, so Z = rho c = 0, and
+    pairs of two of them take the mean state (Z_i + Z_j = 0)."""
+    w = ci.random_cloud(n, seed=seed, box=7.0, vmax=0.5)
+    cold = np.arange(n) % 3 == 0
+    w.p[cold] = 0.0
+    w.vx[cold] = w.vy[cold] = w.vz[cold] = 0.0
+    return w
+
+
 def two_material_cloud(n=3000, seed=11):
     w = ci.random_cloud(n, seed=seed, box=10.0, n_mat=2)
     w.cell_size = 3.0
@@ -88,6 +98,7 @@ CASES = {
     "cloud2mat": two_material_cloud,
     "wall": wall_block,
     "behind": behind_wall_block,
+    "cold": cold_cloud,
     "ragged": lambda: ci.random_cloud(777, seed=3, box=7.3, vmax=1.0),
 }
 
@@ -323,7 +334,7 @@ def _check_totals(tot_gpu, s_ref):
 
 
 @pytest.mark.parametrize("reorder", [False, True])
-@pytest.mark.parametrize("case", ["sod16", "wall", "behind", "cloud2mat", "slab", "mg"])
+@pytest.mark.parametrize("case", ["sod16", "wall", "behind", "cold", "cloud2mat", "slab", "mg"])
 def test_step_fp64(case, reorder):
     w = CASES[case]()
     _print_case(f"{case} reorder={reorder}", w)
