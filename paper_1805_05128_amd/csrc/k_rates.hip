@@ -540,7 +540,10 @@ struct Rates32 {
         int k = 0, j0 = 0, len = 0, jlast = 0;
         float ay = 0.f, az = 0.f;
         for (;;) {
+            // two pops per trigger: some lane holds kQ - 1 entries, most lanes hold several,
+            // and the loop's copies of the live sums are paid once per two pops
             if (__any(qw - qr > kQ - kU)) {
+                drain<MIR, ZS>();
                 drain<MIR, ZS>();
                 continue;
             }
