@@ -135,6 +135,7 @@ __device__ __forceinline__ void wave_min_to(double v, unsigned long long *dst) {
 // k < count[s]; a mirror partner has the sign bit set.  Absent (idx = NULL) for
 // stencil walks.  The list walks read two entries per 8-byte load.
 static_assert(kU == 2, "list walks load kU = 2 entries at once");
+constexpr int kUS = 3;  // candidates per lock-step iteration of the FP32 stencil walk (measured)
 struct VList {
     const int32_t *count;
     const int32_t *idx;
@@ -542,7 +543,7 @@ struct Rates32 {
         for (;;) {
             // two pops per trigger: some lane holds kQ - 1 entries, most lanes hold several,
             // and the loop's copies of the live sums are paid once per two pops
-            if (__any(qw - qr > kQ - kU)) {
+            if (__any(qw - qr > kQ - kUS)) {
                 drain<MIR, ZS>();
                 drain<MIR, ZS>();
                 continue;
@@ -562,11 +563,11 @@ struct Rates32 {
                 k = 0;
                 continue;
             }
-            float4 aj[kU];
+            float4 aj[kUS];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) aj[u] = ld(A, min(j0 + k + u, jlast));
+            for (int u = 0; u < kUS; ++u) aj[u] = ld(A, min(j0 + k + u, jlast));
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
+            for (int u = 0; u < kUS; ++u) {
                 const int j = j0 + k + u;
                 float dx = (aj[u].x + (aj[u].w - cxf) * Df) - a.x;
                 float dy = aj[u].y - ay, dz = aj[u].z - az;
@@ -582,7 +583,7 @@ struct Rates32 {
                     dx, dy, dz, __int_as_float(GHOST ? (j | (int)0x80000000) : j));
                 qw += acc ? 1 : 0;
             }
-            k += kU;
+            k += kUS;
         }
     }
 
