@@ -96,7 +96,8 @@ typedef struct {
                           change of one step); <= 0: the caller's dt is used */
     int32_t n_eos;     /* materials 0..n_eos-1; mat[i] selects eos[mat[i]] */
     int32_t wall;      /* 1: rigid piston plane x = wall_x0 + wall_v t, fluid at x > plane,
-                          handled by mirror partners (every particle must stay at x >= plane) */
+                          handled by mirror partners (also for particles that have fallen
+                          behind the plane) */
     double wall_x0;
     double wall_v;
     csph_eos eos[CSPH_MAX_EOS];
@@ -194,9 +195,10 @@ csph_status csph_neighbors(const csph_state *s, const csph_params *p, int64_t *o
  *   dv_i   =  (2/rho_i) sum_j (m_j/rho_j) P* W' e
  *   dE_i   =  (2/rho_i) sum_j (m_j/rho_j) P* v* W'
  * (eqs. SPH:Conti, SPH:Pulse, SPH:Energy with grad_i W = -e W').  Coincident
- * particles count as neighbours and contribute nothing.  With a wall, every
- * particle j within the stencil (j = i included) also acts through its
- * mirror image x' = 2 x_w - x_j, v_x' = 2 v_w - v_x,j.
+ * particles count as neighbours and contribute nothing.  With a wall (sec. 7.1
+ * rigid wall), every particle j (j = i included) whose mirror image
+ * x' = 2 x_w - x_j lies within the support of i also acts through it, with
+ * v_x' = 2 v_w - v_x,j and j's other fields, on either side of the wall.
  * signal (optional): s_i = max(c_i, max_j [max(c_i, c_j) + max(0, v_L - v_R)]).
  * nbr_count (optional): |N(i)| (real partners only).
  * nonphys (optional, device int64): incremented by the number of particles
@@ -242,8 +244,8 @@ csph_status voronoi_assign(const double *x, const double *y, const double *z, in
  *   vl_count[n]: list lengths; vl_idx[cap * n] (device; cap a multiple of 8): the
  *     partners of particle s in 8-entry chunks, entry k at vl_idx[((k/8) n + s) 8 + k%8],
  *     k < vl_count[s]; j != s with r^2 < R^2 in FP64
- *     without contraction; a partner mirrored across the piston wall (at time *t,
- *     device) has the sign bit set.
+ *     without contraction; a partner whose mirror image across the piston wall (at
+ *     time *t, device) lies within R of s has the sign bit set.
  *   x_ref[3 n] (device): the positions at build, x..., y..., z....
  *   *max_count (host, optional): 0, or the longest list when it exceeds cap; then the
  *     lists are truncated and the call returns CSPH_ECAPACITY.
