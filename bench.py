@@ -28,12 +28,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "CSPH pair-interactions/s and steps/s at 16M particles; adjoint/forward time ratio"
-PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector (published)
+PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector (published; FMA = 2, packed FP32 = 2x)
 PEAK_HBM_GBS = 8000.0
+# Algorithmic VALU work of the pair-flux step: 7 lane operations per candidate of the method's
+# cell-list search over the 27 cells of size H around a particle (sec. 4.2; the neighbour
+# test r^2 < H^2) and ~50 per interacting directed pair (Riemann solver, kernel slope, sums),
+# against the chip's unpacked lane rate, 256 CUs x 64 lanes x 2.4 GHz = 39.3 T lane-ops/s.
+OPS_PER_CANDIDATE = 7
+OPS_PER_PAIR = 50
+PEAK_LANE_TOPS = 256 * 64 * 2.4e9 / 1e12
 # algorithmic FP32 operations per directed interacting pair: r, 1/r, e (3),
 # q, 1-q, W' (4), v_L, v_R (10), S, 1/S, v* (6), P* (8), weight (1), the
-# three sums (3 + 7 + 2) and the signal speed (3); see the design doc.
+# three sums (3 + 7 + 2) and the signal speed (3)
 FLOP_PER_PAIR = 53
+
+
+def cell27_candidates(x, y, z, H):
+    """sum_i of the particles in the 3^3 mesh cells of size H around i's cell (i included):
+    the candidates of the plain cell-list search with cells of the support's size."""
+    import numpy as np
+    c = [np.floor((a - a.min()) / H).astype(np.int64) for a in (x, y, z)]
+    dims = [int(ci.max()) + 1 for ci in c]
+    cnt = np.bincount((c[2] * dims[1] + c[1]) * dims[0] + c[0],
+                      minlength=dims[0] * dims[1] * dims[2]).reshape(dims[2], dims[1], dims[0])
+    pad = np.pad(cnt.astype(np.int64), 1)
+    near = sum(pad[1 + a:1 + a + dims[2], 1 + b:1 + b + dims[1], 1 + c_:1 + c_ + dims[0]]
+               for a in (-1, 0, 1) for b in (-1, 0, 1) for c_ in (-1, 0, 1))
+    return int((cnt.astype(np.int64) * near).sum())
 
 
 def parse():
@@ -360,6 +381,11 @@ def main():
         npairs = int(run.pairs.item())
         if prec == "mixed":
             results["balance"] = balance_timing(P, torch, run, sites)
+            # the plain 27-cell search's candidates, mean of the first and the last state
+            H = w.kappa * w.h
+            st = run.state
+            cand_end = cell27_candidates(*(st[a].cpu().numpy() for a in ("x", "y", "z")), H)
+            results["candidates"] = 0.5 * (cell27_candidates(w.x, w.y, w.z, H) + cand_end)
         results[prec] = dict(ms=1e3 * el / k, pairs_per_step=npairs / k, el=el, k=k, prof=prof,
                              nonphys=int(sc.nonphys.item()), t=float(sc.t.item()),
                              tot0=tot0, tot1=tot1)
@@ -371,8 +397,10 @@ def main():
     m = results["mixed"]
     rates_launches, rates_ms = m["prof"]["rates"]
     rates_avg_s = rates_ms / max(rates_launches, 1) / 1e3
-    flops = FLOP_PER_PAIR * m["pairs_per_step"]
-    achieved = flops / rates_avg_s / 1e12
+    cand = results["candidates"]
+    lane_ops = OPS_PER_CANDIDATE * cand + OPS_PER_PAIR * m["pairs_per_step"]
+    achieved = lane_ops / rates_avg_s / 1e12
+    pair_tflops = FLOP_PER_PAIR * m["pairs_per_step"] / rates_avg_s / 1e12
     kernels = {g: round(v[1] / max(v[0], 1), 4) for g, v in m["prof"].items() if v[0] > 0}
     traffic = traffic_from_profile()
     # per particle the pair-rate kernel must read its 48 B FP32 record, FP64 position (24 B)
@@ -400,12 +428,18 @@ def main():
         "pairs_per_step": m["pairs_per_step"],
         "kernel_ms": kernels,
         "roofline": {"bound": "alu", "kernel": "k_rates32 (pair rates, FP32)",
-                     "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "achieved": achieved, "peak": PEAK_LANE_TOPS, "unit": "T lane-op/s",
+                     "frac": achieved / PEAK_LANE_TOPS,
                      "traffic": traffic["bytes"] if traffic else None,
                      "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE x2 + WRITE_SIZE)",
                      "algorithmic_bytes": alg_bytes,
-                     "flop_per_pair": FLOP_PER_PAIR},
+                     "algorithmic_lane_ops": lane_ops,
+                     "work": f"{OPS_PER_CANDIDATE} x {cand:.4g} candidates of the 27-cell search "
+                             f"(cells of size H) + {OPS_PER_PAIR} x {m['pairs_per_step']:.4g} "
+                             "directed pairs per launch",
+                     "pair_flops": {"flop_per_pair": FLOP_PER_PAIR, "achieved": pair_tflops,
+                                    "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                                    "frac": pair_tflops / PEAK_FP32_TFLOPS}},
         "energy_total_rel_change": (e1 - e0) / abs(e0) if e0 else None,
         "nonphys": m["nonphys"],
     }
