@@ -259,18 +259,31 @@ def verlet_timing(P, torch, w, cell, steps, beta=0.3, n_upd=10):
 KERNEL_SOURCES = ("k_rates.hip", "stencil.h", "csph_internal.h")
 
 
+def kernel_source_sha(texts=None):
+    """sha256 of the rate kernel's sources with // comments and blank lines removed (comment
+    edits do not change the kernel the counters were taken on)."""
+    import hashlib
+    if texts is None:
+        csrc = os.path.join(ROOT, "paper_1805_05128_amd", "csrc")
+        texts = [open(os.path.join(csrc, f), "rb").read().decode() for f in KERNEL_SOURCES]
+    code = []
+    for t in texts:
+        for line in t.split("\n"):
+            line = re.sub(r"//.*$", "", line).rstrip()
+            if line:
+                code.append(line)
+    return hashlib.sha256("\n".join(code).encode()).hexdigest()
+
+
 def traffic_from_profile():
     """HBM bytes per launch of the pair-rate kernel from the committed counter summary,
     or None when the kernel sources changed since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_rates32_porous256.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
     fields = dict(re.findall(r"^- (\w+): (\S+)$", text, re.M))
-    csrc = os.path.join(ROOT, "paper_1805_05128_amd", "csrc")
-    src = "".join(open(os.path.join(csrc, f), "rb").read().decode() for f in KERNEL_SOURCES)
-    sha = hashlib.sha256(src.encode()).hexdigest()
+    sha = kernel_source_sha()
     if fields.get("source_sha256") != sha:
         return None
     return {"read_bytes": float(fields["read_bytes_per_launch"]),

@@ -2,7 +2,8 @@
 // SPH:Energy of sec. 4.1), FP64 and mixed (FP32 pair arithmetic).
 //
 // Particles are in cell order; each thread owns one particle i and gathers
-// over the (2R+1)^3 stencil of cells around its own.  Cells of one stencil
+// over the (2R+1)^3 stencil of cells around its own (and, with a piston
+// wall, over the stencil around its mirror image).  Cells of one stencil
 // row are contiguous in cell order, so a row is one index range.  Each
 // particle sums its own partners (gather), so no floating-point atomics are
 // used and results do not depend on scheduling.
@@ -243,7 +244,7 @@ struct Rates64 {
 
     // one walk over the stencil: real partners, or mirror partners (GHOST).
     // One flat loop with wave-uniform branches (drain / next row / test a
-    // chunk), so the sums stay in place across iterations.
+    // chunk).
     template <bool GHOST, bool MIR, bool ZS>
     __device__ __forceinline__ void pass() {
         const bool on = live && (!GHOST || near_wall);
