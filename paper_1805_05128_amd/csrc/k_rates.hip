@@ -519,18 +519,26 @@ struct Rates32 {
             const float i2 = invH * invH;
             dwc = (float)(210.0 / M_PI) * (i2 * i2);
         }
-        const float r2 = (q.x * q.x + q.y * q.y) + q.z * q.z;
-        // a list walk queues exact FP64 members only
+        float qx = q.x, qy = q.y, qz = q.z;
+        float r2 = (qx * qx + qy * qy) + qz * qz;
+        // a list walk queues exact FP64 members only, with offsets rounded from FP64
         bool in = has && (LIST || r2 < H2lo);
-        if (!LIST && has && !(r2 < H2lo)) {
-            // near the support: decide membership in FP64 (rare)
+        // (rare) near the support, decide membership in FP64; nearly coincident (r < H/100),
+        // take the offsets from FP64 too: the cell-relative FP32 offsets carry ~1e-7 absolute
+        // error, which would bend the direction e of so short a pair (and with it the
+        // closing speed in the signal speed, which the kernel weight does not damp)
+        if (!LIST && has && (!(r2 < H2lo) || r2 < H2lo * 1e-4f)) {
             const double yj = ghost ? 2.0 * yw - ys[j] : ys[j];
             const double ex = xs[j] - xi, ey = yj - yi, ez = zs[j] - zi;
             in = ((ex * ex) + (ey * ey)) + (ez * ez) < H2d;
+            qx = (float)ex;
+            qy = (float)ey;
+            qz = (float)ez;
+            r2 = (qx * qx + qy * qy) + qz * qz;
         }
         cnt += (in && !ghost) ? 1 : 0;
-        pair32<ZS>(in && r2 != 0.0f, q.x, q.y, q.z, r2, b, c, bj.x, ghost ? vw2 - bj.y : bj.y,
-               bj.z, bj.w, cj.x, cj.y, cj.z, invH, dwc, ar, avx, avy, avz, aE, sig);
+        pair32<ZS>(in && r2 != 0.0f, qx, qy, qz, r2, b, c, bj.x, ghost ? vw2 - bj.y : bj.y,
+                   bj.z, bj.w, cj.x, cj.y, cj.z, invH, dwc, ar, avx, avy, avz, aE, sig);
     }
 
     // flat loop as in the FP64 kernel

@@ -1,9 +1,10 @@
 """GPU parity at the full sizes of the benchmark workloads, in the launch
 configuration bench.py times (cell order, unit mesh cells, both precisions):
 
-* porous shock 256^3 (11 743 903 particles, piston at t = 0.1, x_w = 0.2, in
-  front of every particle as the mirror rule requires): rates of
-  every particle against the oracle (cell-list mode, all host cores);
+* porous shock 256^3 (11 743 903 particles): rates of every particle against
+  the oracle (cell-list mode, all host cores) with the piston at t = 0.1
+  (x_w = 0.2, in front of every particle) and at t = 2.75 (x_w = 5.5: the
+  first layers behind it, as in the later steps of the run);
 * plate impact (589 824 particles): one full step of every particle, both
   precisions, and the compensated totals;
 * two-body collision (64 000 000 particles): rates of a seeded sample that
@@ -39,10 +40,12 @@ def _gpu_rates(w, prec, t, cell=1.0):
     return out
 
 
-def test_porous256_rates_every_particle():
+@pytest.mark.parametrize("t", [0.1, 2.75])
+def test_porous256_rates_every_particle(t):
     w = ci.config2()
-    print(f"[case] {w.name} n={w.n}", flush=True)
-    t = 0.1
+    xw = w.wall[0] + w.wall[1] * t
+    print(f"[case] {w.name} n={w.n} t={t}: {int((w.x < xw).sum())} particles behind the wall",
+          flush=True)
     ref = O.rates(O.cfg_for(w, search=1), O.state_from(w, O.cfg_for(w)), t=t)
     print("oracle pairs", int(ref["nbr_count"].sum()), flush=True)
     for prec, tol in (("mixed", MIXED_TOL), ("fp64", FP64_TOL)):
