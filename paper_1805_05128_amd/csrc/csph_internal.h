@@ -47,12 +47,18 @@ __host__ __device__ __forceinline__ uint32_t cell_key(const GridDev &g, int cx, 
            (uint32_t)(cy & g.ymask) * (uint32_t)g.dx + (uint32_t)cx;
 }
 
-// Workgroups are handed to the dies round robin.  Renumber them so that die
-// k runs one contiguous stretch of workgroups (its L2 then holds the stencil
-// neighbourhood of one stretch of cells instead of pieces of all of them).
+// Workgroups are handed to the dies round robin.  Renumber them so that a die
+// runs chunks of C consecutive workgroups (its L2 then holds the stencil
+// neighbourhood of a stretch of cells instead of scattered pieces), the dies
+// taking the chunks in turn, so that a region of costly particles (the wall
+// band) is shared by all dies instead of falling on one.  Workgroups past the
+// last whole round of chunks keep their number.
+template <unsigned C>
 __device__ __forceinline__ int64_t xcd_block(unsigned b, unsigned nb) {
-    const unsigned x = b % kXcd, t = b / kXcd, q = nb / kXcd, r = nb % kXcd;
-    return (int64_t)x * q + (x < r ? x : r) + t;
+    const unsigned round = kXcd * C, full = nb / round * round;
+    if (b >= full) return b;
+    const unsigned x = b % kXcd, t = b / kXcd;
+    return ((int64_t)(t / C) * kXcd + x) * C + t % C;
 }
 
 // Per-call constants of the pair interaction.

@@ -121,6 +121,10 @@ hipError_t launch_pack(const csph_state &s, int64_t n, const int32_t *perm, cons
 // FP64 kernel's occupancy is bound by registers; it keeps four-wave workgroups.
 constexpr int kRate32Block = 64;
 constexpr int kRate64Block = kBlock;
+// workgroups per die chunk (xcd_block; measured on the porous shock's 100 steps, where the
+// wall band's costly waves made one die the last to finish): ~33 k / ~16 k particles
+constexpr unsigned kRate32Chunk = 512;
+constexpr unsigned kRate64Chunk = 64;
 
 // min over the wave of v >= 0 into *dst (bits of a non-negative double); the atomic is
 // skipped when it cannot lower the current value
@@ -372,7 +376,7 @@ __global__ __launch_bounds__(kRate64Block, 5) void k_rates64(int64_t n, const do
     k.pc = pc;
     k.qj = qj;
     k.tid = threadIdx.x;
-    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kRate64Block + threadIdx.x;
+    const int64_t s = xcd_block<kRate64Chunk>(blockIdx.x, gridDim.x) * kRate64Block + threadIdx.x;
     k.self = (int)s;
     k.live = s < n;
     k.a = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -681,7 +685,7 @@ __global__ __launch_bounds__(kRate32Block) void k_rates32(int64_t n, const float
     k.pc = pc;
     k.qd = qd;
     k.tid = threadIdx.x;
-    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kRate32Block + threadIdx.x;
+    const int64_t s = xcd_block<kRate32Chunk>(blockIdx.x, gridDim.x) * kRate32Block + threadIdx.x;
     k.self = (int)s;
     k.live = s < n;
     k.a = make_float4(0.f, 0.f, 0.f, 0.f);

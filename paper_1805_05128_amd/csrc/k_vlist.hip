@@ -19,7 +19,7 @@ __global__ __launch_bounds__(kBlock) void k_vlist(int64_t n, const double4 *__re
                                                   int32_t *__restrict__ count,
                                                   int32_t *__restrict__ idx,
                                                   unsigned long long *__restrict__ over) {
-    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int64_t s = xcd_block<64>(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const bool live = s < n;
     const double4 ai = live ? A[s] : make_double4(0.0, 0.0, 0.0, 0.0);
     const double xi = ai.x, yi = ai.y, zi = ai.z;
