@@ -26,7 +26,11 @@
  *               the required size there (host).  Workspace contents do not
  *               persist between calls.
  *   Layout.     Structure of arrays, FP64, one entry per particle, particle
- *               count n < 2^31; particle indices are int32.
+ *               count n < 2^31; particle indices are int32.  The calls that
+ *               walk particle pairs (csph_rates, csph_step, csph_vlist_build,
+ *               csph_step_vlist and the vector-Jacobian products) take
+ *               n < 2^27 and return CSPH_EINVAL above: their kernels address
+ *               per-particle records of up to 32 bytes with 32-bit offsets.
  *   Streams.    Work is enqueued on `stream` (a hipStream_t; NULL = default
  *               stream).  Calls that must learn a size on the host (mesh
  *               dimensions, neighbour count) synchronise that stream; the

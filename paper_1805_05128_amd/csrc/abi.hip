@@ -104,7 +104,8 @@ size_t ws_layout(Ws *w, void *base, int64_t n, int64_t ncell) {
     t.rank = (uint32_t *)take(sizeof(uint32_t) * un);
     t.perm = (int32_t *)take(sizeof(int32_t) * un);
     t.cnt = (int32_t *)take(sizeof(int32_t) * un);
-    t.recA = take(32 * un);
+    // A records: FP64 (32 B each), or FP32 (16 B) plus the pack's two zero records
+    t.recA = take(32 * un > 16 * (un + 2) ? 32 * un : 16 * (un + 2));
     t.recB = take(32 * un);
     t.recC = take(16 * un);
     t.recD = take(32 * un);
@@ -403,6 +404,7 @@ csph_status csph_rates(const csph_state *s, const csph_params *p, double t, csph
                        size_t ws_bytes, size_t *ws_needed, csph_stream stream) {
     g_err[0] = 0;
     if (!state_ok(s) || s->n >= INT32_MAX) return fail(CSPH_EINVAL, "bad state");
+    if (s->n >= kMaxPairN) return fail(CSPH_EINVAL, "n >= 2^27 particles");
     if (s->n > 0 && (!out.drho || !out.dvx || !out.dvy || !out.dvz || !out.dE))
         return fail(CSPH_EINVAL, "rate outputs must not be NULL");
     if (!std::isfinite(t)) return fail(CSPH_EINVAL, "t not finite");
@@ -455,6 +457,7 @@ csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_para
     g_err[0] = 0;
     if (!state_ok(s_in) || !state_ok(s_out) || s_in->n != s_out->n || s_in->n >= INT32_MAX)
         return fail(CSPH_EINVAL, "bad state");
+    if (s_in->n >= kMaxPairN) return fail(CSPH_EINVAL, "n >= 2^27 particles");
     csph_status r = check_params(p, s_in->n > 0, s_in->d);
     if (r) return r;
     if (!(p->cfl > 0.0) && !(std::isfinite(dt_in) && dt_in >= 0.0))
@@ -542,6 +545,7 @@ csph_status csph_vlist_build(const csph_state *s_in, csph_state *s_out, const cs
     g_err[0] = 0;
     if (!state_ok(s_in) || !state_ok(s_out) || s_in->n != s_out->n || s_in->n >= INT32_MAX)
         return fail(CSPH_EINVAL, "bad state");
+    if (s_in->n >= kMaxPairN) return fail(CSPH_EINVAL, "n >= 2^27 particles");
     csph_status r = check_params(p, false, nullptr);
     if (r) return r;
     if (p->h_mode != CSPH_H_FIXED) return fail(CSPH_EINVAL, "Verlet lists need fixed-h mode");
@@ -615,6 +619,7 @@ csph_status csph_step_vlist(csph_state *s, const csph_params *p, double *t, doub
                             size_t ws_bytes, size_t *ws_needed, csph_stream stream) {
     g_err[0] = 0;
     if (!state_ok(s) || s->n >= INT32_MAX) return fail(CSPH_EINVAL, "bad state");
+    if (s->n >= kMaxPairN) return fail(CSPH_EINVAL, "n >= 2^27 particles");
     csph_status r = check_params(p, false, nullptr);
     if (r) return r;
     if (p->h_mode != CSPH_H_FIXED) return fail(CSPH_EINVAL, "Verlet lists need fixed-h mode");
@@ -754,6 +759,7 @@ static csph_status vjp_common(const csph_state *s, const csph_params *p, const d
                               double *g_eos, void *ws, size_t ws_bytes, size_t *ws_needed,
                               hipStream_t st) {
     if (!state_ok(s) || s->n >= INT32_MAX) return fail(CSPH_EINVAL, "bad state");
+    if (s->n >= kMaxPairN) return fail(CSPH_EINVAL, "n >= 2^27 particles");
     csph_status r = check_params(p, false, nullptr);
     if (r) return r;
     r = check_vjp_params(p);

@@ -21,6 +21,8 @@ constexpr int kMaxBalanceSites = 512; // balancer generators held in LDS (84 B e
 constexpr int kXcd = 8;               // accelerator dies; workgroups go to them round robin
 constexpr int kSlabShift = 4;         // cell order: y-slabs of 16 rows (see cell_key)
 constexpr int kVlChunk = 8;           // Verlet-list entries per lane-owned 32-byte chunk
+// The pair walks address per-particle records (up to 32 bytes) with 32-bit byte offsets.
+constexpr int64_t kMaxPairN = (int64_t)1 << 27;
 
 // Mesh as the kernels see it.
 struct GridDev {

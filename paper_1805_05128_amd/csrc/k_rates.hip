@@ -30,6 +30,10 @@ struct DstState {
 
 // Gather particle perm[s] into slot s: sorted FP64 state copy, EOS
 // (e = E - |v|^2/2; ideal gas, stiffened gas or Mie-Grueneisen), pair record.
+// Zero records after the n FP32 stencil records: the FP32 stencil walk loads up to kUS - 1
+// records past a row's last one (the A record buffer has room for them)
+constexpr int kRecPad = 2;
+
 template <bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_pack(int64_t n, SrcState src,
                                                  const int32_t *__restrict__ perm, EosDev eos,
@@ -79,6 +83,9 @@ __global__ __launch_bounds__(kBlock) void k_pack(int64_t n, SrcState src,
         float oz = (float)(z - (g.oz + (double)cz * g.cell));
         // x offset, y, z offsets from the cell origin and the cell's x index
         ((float4 *)recA)[s] = make_float4(ox, oy, oz, (float)cx);
+        if (s == n - 1)
+            for (int p = 1; p <= kRecPad; ++p)
+                ((float4 *)recA)[n - 1 + p] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
         ((float4 *)recB)[s] = make_float4((float)vx, (float)vy, (float)vz, (float)P);
         ((float4 *)recC)[s] = make_float4((float)Z, (float)c, (float)V, 0.0f);
@@ -120,6 +127,8 @@ hipError_t launch_pack(const csph_state &s, int64_t n, const int32_t *perm, cons
 // times, vary widely; a larger workgroup holds its rings until its slowest wave ends).  The
 // FP64 kernel's occupancy is bound by registers; it keeps four-wave workgroups.
 constexpr int kRate32Block = 64;
+constexpr int kSlot = kRate32Block * (int)sizeof(float4);  // bytes per ring row
+constexpr int kRing = kQ * kSlot;                        // bytes per wave's rings
 constexpr int kRate64Block = kBlock;
 // workgroups per die chunk (xcd_block; measured on the porous shock's 100 steps, where the
 // wall band's costly waves made one die the last to finish): ~33 k / ~16 k particles
@@ -141,6 +150,7 @@ __device__ __forceinline__ void wave_min_to(double v, unsigned long long *dst) {
 // stencil walks.  The list walks read two entries per 8-byte load.
 static_assert(kU == 2, "list walks load kU = 2 entries at once");
 constexpr int kUS = 3;  // candidates per lock-step iteration of the FP32 stencil walk (measured)
+static_assert(kUS - 1 <= kRecPad, "the stencil walk reads up to kUS - 1 records past a row");
 struct VList {
     const int32_t *count;
     const int32_t *idx;
@@ -447,7 +457,6 @@ __device__ __forceinline__ void pair32(bool use, float dx, float dy, float dz, f
     const float dW = -(use ? dwc : 0.0f) * q * (a1 * a1 * a1);
     // v_L - v_R from the velocity difference (no cancellation of bulk motion)
     const float vrel = ((bi.x - vxj) * ex + (bi.y - vyj) * ey) + (bi.z - vzj) * ez;
-    const float vL = (bi.x * ex + bi.y * ey) + bi.z * ez;
     const float Zi = ci.x, Pi = bi.w;
     const float S = Zi + Zj;
     // v_L - v* and P*; S = 0 (both impedances zero) takes the mean state, written as
@@ -461,14 +470,15 @@ __device__ __forceinline__ void pair32(bool use, float dx, float dy, float dz, f
     // a lane without a partner adds exact zeros: its weight is 0 (dW with the kernel constant
     // selected to 0) and every factor it multiplies is finite (r2 = 1, finite offsets)
     const float wgt = Vj * dW;
-    const float vs = vL - dvl;
     const float f = wgt * ps;
     const float sp = fmax_nonneg(ci.y, cj) + fmaxf(vrel, 0.0f);
     ar += wgt * dvl;
     avx += f * ex;
     avy += f * ey;
     avz += f * ez;
-    aE += f * vs;
+    // energy flux f v* = f v_L - f (v_L - v*); the f v_L part sums to v_i . sum_j f e_ij, which
+    // the kernel adds once from the momentum sums
+    aE -= f * dvl;
     sig = fmax_nonneg(sig, use ? sp : 0.0f);
 }
 
@@ -491,27 +501,40 @@ struct Rates32 {
     const double4 *__restrict__ P4;  // list walks: FP64 position record
     GridDev g;
     PairConst pc;
-    float4 (*qd)[kRate32Block];
-    int tid, self;
+    char *qb;         // the wave's rings: kQ rows of kRate32Block float4 slots
+    int lane16;       // the lane's byte offset in a ring row
+    uint32_t self16;  // byte offset of i's own records
     bool live, near_wall;
     float4 a, b, c;
     double xi, yi, zi, di, yw;  // yw: wall position along y
     float wd, vw2, Df, cxf, lo, hi;
     Stencil t, ti;               // stencils of i and of its mirror image
     float ar = 0.f, avx = 0.f, avy = 0.f, avz = 0.f, aE = 0.f, sig = 0.f;
-    int qw = 0, qr = 0, cnt = 0;
+    // ring write and read counters in bytes, advancing one ring row (kSlot) per entry: a
+    // slot's address is the counter masked to the ring, or'ed with the lane's offset;
+    // unsigned, so that the fill level qw - qr stays exact if the counters wrap
+    unsigned qw = 0, qr = 0;
+    int cnt = 0;
+
+    __device__ __forceinline__ float4 &slot(unsigned q) {
+        return *(float4 *)(qb + ((q & (kRing - 1)) | (unsigned)lane16));
+    }
+    // A ring entry holds the partner's offsets and, in w, the byte offset of its 16-byte
+    // records with bit 0 set for a mirror image.
 
     // every lane pops its next partner, if it has one; MIR: the wave may hold mirror entries
     template <bool MIR, bool ZS>
     __device__ __forceinline__ void drain() {
 #pragma clang fp contract(fast)
-        const bool has = qr < qw;
-        const float4 q = qd[qr & (kQ - 1)][tid];
-        qr += has ? 1 : 0;
-        const int e = __float_as_int(q.w);
-        const int j = has ? (e & 0x7fffffff) : 0;
-        const bool ghost = MIR && e < 0;
-        const float4 bj = ld(B, j), cj = ld(Cz, j);
+        const bool has = qr != qw;
+        const float4 q = slot(qr);
+        qr += has ? kSlot : 0;
+        const uint32_t e = __float_as_uint(q.w);
+        const uint32_t jo = has ? (MIR ? e & ~15u : e) : 0u;
+        const bool ghost = MIR && (e & 1u);
+        const int j = (int)(jo >> 4);
+        const float4 bj = *(const float4 *)((const char *)B + jo);
+        const float4 cj = *(const float4 *)((const char *)Cz + jo);
         float invH = (float)pc.invH, dwc = (float)pc.dwc;
         float H2lo = lo;
         double H2d = pc.H2;
@@ -554,11 +577,11 @@ struct Rates32 {
         const Stencil &st = GHOST ? ti : t;
         int oy = st.R, oz = -st.R - 1;
         int k = 0, j0 = 0, len = 0, jlast = 0;
-        float ay = 0.f, az = 0.f;
+        float ay = 0.f, az = 0.f, gz2 = 0.f;
         for (;;) {
             // two pops per trigger: some lane holds kQ - 1 entries, most lanes hold several,
             // and the loop's copies of the live sums are paid once per two pops
-            if (__any(qw - qr > kQ - kUS)) {
+            if (__any(qw - qr > (kQ - kUS) * kSlot)) {
                 drain<MIR, ZS>();
                 drain<MIR, ZS>();
                 continue;
@@ -567,20 +590,28 @@ struct Rates32 {
                 if (++oy > st.R) {
                     oy = -st.R;
                     if (++oz > st.R) break;
+                    // per plane of rows: squared z gap, i's z offset from the plane's cells
+                    const float gz = slab_gap(st.zc, st.cz + oz);
+                    gz2 = gz * gz;
+                    az = a.z - (float)oz * Df;
                 }
                 const int yy = st.cy + oy, zz = st.cz + oz;
-                const float gz = slab_gap(st.zc, zz);
-                row_range(cs, g, st, on, yy, zz, gz * gz, j0, len);
+                row_range(cs, g, st, on, yy, zz, gz2, j0, len);
                 jlast = len > 0 ? j0 + len - 1 : 0;
-                // i's offsets from the row's cell origin (rows counted from i's own cell)
+                // i's y offset from the row's cell origin (rows counted from i's own cell)
                 ay = a.y - (float)(yy - t.cy) * Df;
-                az = a.z - (float)oz * Df;
                 k = 0;
                 continue;
             }
+            // the slots' records from j0 + k on, the start clamped to the row's last record:
+            // every load then reads a finite record (a lane with nothing left to pop reads the
+            // slot written last), up to kUS - 1 past the row, which the zero records the pack
+            // appends after the n records keep in bounds
+            const uint32_t jbo = (uint32_t)min(j0 + k, jlast) * (uint32_t)sizeof(float4);
+            const float4 *Ab = (const float4 *)((const char *)A + jbo);
             float4 aj[kUS];
 #pragma unroll
-            for (int u = 0; u < kUS; ++u) aj[u] = ld(A, min(j0 + k + u, jlast));
+            for (int u = 0; u < kUS; ++u) aj[u] = Ab[u];
 #pragma unroll
             for (int u = 0; u < kUS; ++u) {
                 const int j = j0 + k + u;
@@ -593,10 +624,12 @@ struct Rates32 {
                     double H = pc.kappa * (0.5 * (di + ld(dsz, j < jlast ? j : jlast)));
                     hj = (float)(H * H) * (1.0f + kBand);
                 }
-                const bool acc = (k + u < len) && (GHOST || j != self) && r2 < hj;
-                qd[qw & (kQ - 1)][tid] = make_float4(
-                    dx, dy, dz, __int_as_float(GHOST ? (j | (int)0x80000000) : j));
-                qw += acc ? 1 : 0;
+                // the entry's record offset (16 j for a slot that can be accepted); one select
+                // per slot: the three tests combine as lane masks
+                const uint32_t jo = jbo + (uint32_t)(u * sizeof(float4));
+                const bool acc = (k + u < len) & (GHOST || jo != self16) & (r2 < hj);
+                slot(qw) = make_float4(dx, dy, dz, __uint_as_float(GHOST ? jo | 1u : jo));
+                qw += acc ? kSlot : 0;
             }
             k += kUS;
         }
@@ -608,14 +641,14 @@ struct Rates32 {
     __device__ __forceinline__ void run(const int32_t *__restrict__ lst, int len, int64_t nl) {
         if (LIST_) {
             pass_list<ZS>(lst, len, nl);
-            while (__any(qr < qw)) drain<WALL, ZS>();
+            while (__any(qr != qw)) drain<WALL, ZS>();
         } else if (WALL && __any(near_wall)) {
             pass<false, true, ZS>();
             pass<true, true, ZS>();
-            while (__any(qr < qw)) drain<true, ZS>();
+            while (__any(qr != qw)) drain<true, ZS>();
         } else {
             pass<false, false, ZS>();
-            while (__any(qr < qw)) drain<false, ZS>();
+            while (__any(qr != qw)) drain<false, ZS>();
         }
     }
 
@@ -626,7 +659,7 @@ struct Rates32 {
                                               int64_t nl) {
         int k = 0;
         for (;;) {
-            if (__any(qw - qr > kQ - kU)) {
+            if (__any(qw - qr > (kQ - kU) * kSlot)) {
                 drain<WALL, ZS>();
                 continue;
             }
@@ -645,9 +678,11 @@ struct Rates32 {
                 const double dx = pj[u].x - xi, dy = yj - yi, dz = pj[u].z - zi;
                 const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
                 const bool acc = (k + u < len) && r2 < pc.H2;
-                qd[qw & (kQ - 1)][tid] =
-                    make_float4((float)dx, (float)dy, (float)dz, __int_as_float(e[u]));
-                qw += acc ? 1 : 0;
+                // list entries carry the mirror flag in the sign bit
+                const uint32_t eu = (uint32_t)e[u];
+                slot(qw) = make_float4((float)dx, (float)dy, (float)dz,
+                                       __uint_as_float(WALL ? (eu << 4) | (eu >> 31) : eu << 4));
+                qw += acc ? kSlot : 0;
             }
             k += kU;
         }
@@ -683,10 +718,10 @@ __global__ __launch_bounds__(kRate32Block) void k_rates32(int64_t n, const float
     k.cs = cs;
     k.g = g;
     k.pc = pc;
-    k.qd = qd;
-    k.tid = threadIdx.x;
+    k.qb = (char *)&qd[0][0];
+    k.lane16 = threadIdx.x * (int)sizeof(float4);
     const int64_t s = xcd_block<kRate32Chunk>(blockIdx.x, gridDim.x) * kRate32Block + threadIdx.x;
-    k.self = (int)s;
+    k.self16 = (uint32_t)s * (uint32_t)sizeof(float4);
     k.live = s < n;
     k.a = make_float4(0.f, 0.f, 0.f, 0.f);
     k.b = k.a;
@@ -735,7 +770,9 @@ __global__ __launch_bounds__(kRate32Block) void k_rates32(int64_t n, const float
         o.vx[s] = pre * (double)k.avx;
         o.vy[s] = pre * (double)k.avy;
         o.vz[s] = pre * (double)k.avz;
-        o.E[s] = pre * (double)k.aE;
+        const double vf = ((double)k.b.x * (double)k.avx + (double)k.b.y * (double)k.avy) +
+                          (double)k.b.z * (double)k.avz;
+        o.E[s] = pre * ((double)k.aE + vf);
         if (o.sig) o.sig[s] = (double)k.sig;
         if (o.cnt) o.cnt[s] = k.cnt;
         dtv = fmin((PAIR ? k.di : pc.h_dt) / (double)k.sig, ri / fabs(drho));

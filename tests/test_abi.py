@@ -82,3 +82,21 @@ def test_invalid_arguments_rejected():
     s.n = 5  # NULL field pointers
     assert L.csph_step(C.byref(s), C.byref(s), C.byref(p), None, 0.0, None, None, None, None,
                        None, 0, None, None) == N.CSPH_EINVAL
+
+
+def test_pair_walks_reject_more_than_2_to_27_particles():
+    """Pair kernels address 32-byte records with 32-bit offsets: n >= 2^27 is refused on the
+    host, before any device work (the field pointers are never dereferenced)."""
+    L = N.load()
+    p = P.Params().c()
+    s = N.CsphState()
+    s.n = 1 << 27
+    for f in ("x", "y", "z", "vx", "vy", "vz", "rho", "E", "m"):
+        setattr(s, f, C.cast(C.c_void_p(4096), C.POINTER(C.c_double)))
+    out = N.CsphRatesOut()
+    assert L.csph_rates(C.byref(s), C.byref(p), 0.0, out, None, None, None, None, 0,
+                        None, None) == N.CSPH_EINVAL
+    assert b"2^27" in L.csph_last_error()
+    assert L.csph_step(C.byref(s), C.byref(s), C.byref(p), None, 0.0, None, None, None, None,
+                       None, 0, None, None) == N.CSPH_EINVAL
+    assert b"2^27" in L.csph_last_error()
