@@ -428,6 +428,23 @@ def test_voronoi_site_counts(K):
     _voronoi_case(*[np.ascontiguousarray(pts[:, k]) for k in range(3)], sites, cnt)
 
 
+@pytest.mark.parametrize("K", [3, 64, 1024])
+def test_voronoi_coherent_order_with_ties(K):
+    """Particles in lattice order (each wave's 64 particles fill a thin box, so the kernel
+    scans only the generators that can be nearest to that box), with exact ties: generator
+    pairs mirrored about lattice sites, and duplicated generators."""
+    rng = np.random.default_rng(100 + K)
+    x, y, z = ci.lattice(48, 40, 24)
+    cnt = rng.integers(0, 200, size=x.shape[0])
+    sites = rng.uniform(0, 40, size=(K, 3))
+    if K >= 3:
+        c = np.array([10.5, 20.5, 12.5])
+        sites[K - 1] = c + np.array([0.0, 1.0, 0.0])  # ties at c between the last two ...
+        sites[K - 2] = c - np.array([0.0, 1.0, 0.0])  # ... generators (smaller k wins)
+        sites[0] = sites[K - 1]                        # and a duplicate of the last one
+    _voronoi_case(x, y, z, sites, cnt)
+
+
 def test_voronoi_with_gpu_neighbour_counts():
     w = ci.config2(nside=32)
     _print_case("porous32", w)
