@@ -446,39 +446,40 @@ template <bool ZS>
 __device__ __forceinline__ void pair32(bool use, float dx, float dy, float dz, float r2,
                                        const float4 &bi, const float4 &ci, float vxj, float vyj,
                                        float vzj, float Pj, float Zj, float cj, float Vj,
-                                       float invH, float dwc, float &ar, float &avx, float &avy,
+                                       float invH, float dwch, float &ar, float &avx, float &avy,
                                        float &avz, float &aE, float &sig) {
 #pragma clang fp contract(fast)
+    // dwch = (210/pi)/H^5, so that dW/dr = -dwch r (1 - r/H)^3
     const float ir = __builtin_amdgcn_rsqf(use ? r2 : 1.0f);
     const float r = r2 * ir;
-    const float ex = dx * ir, ey = dy * ir, ez = dz * ir;
-    const float q = r * invH;
-    const float a1 = 1.0f - q;
-    const float dW = -(use ? dwc : 0.0f) * q * (a1 * a1 * a1);
-    // v_L - v_R from the velocity difference (no cancellation of bulk motion)
-    const float vrel = ((bi.x - vxj) * ex + (bi.y - vyj) * ey) + (bi.z - vzj) * ez;
+    const float a1 = 1.0f - r * invH;
+    const float dWr = -(use ? dwch : 0.0f) * r * (a1 * a1 * a1);
+    // v_L - v_R from the velocity difference and the raw offsets (no cancellation of bulk
+    // motion); e = (dx, dy, dz) / r
+    const float vrel = (((bi.x - vxj) * dx + (bi.y - vyj) * dy) + (bi.z - vzj) * dz) * ir;
     const float Zi = ci.x, Pi = bi.w;
     const float S = Zi + Zj;
-    // v_L - v* and P*; S = 0 (both impedances zero) takes the mean state, written as
+    // (v_L - v*) S and P* S; S = 0 (both impedances zero) takes the mean state, written as
     // the same expressions with Z_i = Z_j = 1 and the P and (v_L - v_R) terms dropped
     const bool sok = !ZS || S != 0.0f;
     const float iS = __builtin_amdgcn_rcpf(sok ? S : 2.0f);
     const float Zjd = sok ? Zj : 1.0f, Zid = sok ? Zi : 1.0f;
     const float dP = sok ? Pi - Pj : 0.0f, ZZ = sok ? Zi * Zj : 0.0f;
-    const float dvl = (Zjd * vrel - dP) * iS;
-    const float ps = ((Zjd * Pi + Zid * Pj) + ZZ * vrel) * iS;
-    // a lane without a partner adds exact zeros: its weight is 0 (dW with the kernel constant
-    // selected to 0) and every factor it multiplies is finite (r2 = 1, finite offsets)
-    const float wgt = Vj * dW;
-    const float f = wgt * ps;
+    const float dvlS = Zjd * vrel - dP;
+    const float psS = (Zjd * Pi + Zid * Pj) + ZZ * vrel;
+    // a lane without a partner adds exact zeros: its weight is 0 (the kernel constant selected
+    // to 0) and every factor it multiplies is finite (r2 = 1, finite offsets)
+    const float wS = (Vj * iS) * dWr;  // V_j dW/dr / S
+    const float f = wS * psS;          // V_j dW/dr P*
+    const float fr = f * ir;
     const float sp = fmax_nonneg(ci.y, cj) + fmaxf(vrel, 0.0f);
-    ar += wgt * dvl;
-    avx += f * ex;
-    avy += f * ey;
-    avz += f * ez;
+    ar += wS * dvlS;
+    avx += fr * dx;
+    avy += fr * dy;
+    avz += fr * dz;
     // energy flux f v* = f v_L - f (v_L - v*); the f v_L part sums to v_i . sum_j f e_ij, which
     // the kernel adds once from the momentum sums
-    aE -= f * dvl;
+    aE -= f * (dvlS * iS);
     sig = fmax_nonneg(sig, use ? sp : 0.0f);
 }
 
@@ -507,7 +508,7 @@ struct Rates32 {
     bool live, near_wall;
     float4 a, b, c;
     double xi, yi, zi, di, yw;  // yw: wall position along y
-    float wd, vw2, Df, cxf, lo, hi;
+    float wd, vw2, Df, cxf, lo, hi, dwch0;
     Stencil t, ti;               // stencils of i and of its mirror image
     float ar = 0.f, avx = 0.f, avy = 0.f, avz = 0.f, aE = 0.f, sig = 0.f;
     // ring write and read counters in bytes, advancing one ring row (kSlot) per entry: a
@@ -535,7 +536,7 @@ struct Rates32 {
         const int j = (int)(jo >> 4);
         const float4 bj = *(const float4 *)((const char *)B + jo);
         const float4 cj = *(const float4 *)((const char *)Cz + jo);
-        float invH = (float)pc.invH, dwc = (float)pc.dwc;
+        float invH = (float)pc.invH, dwch = dwch0;
         float H2lo = lo;
         double H2d = pc.H2;
         if (PAIR) {
@@ -544,7 +545,7 @@ struct Rates32 {
             H2lo = (float)H2d * (1.0f - kBand);
             invH = (float)(1.0 / H);
             const float i2 = invH * invH;
-            dwc = (float)(210.0 / M_PI) * (i2 * i2);
+            dwch = (float)(210.0 / M_PI) * (i2 * i2) * invH;
         }
         float qx = q.x, qy = q.y, qz = q.z;
         float r2 = (qx * qx + qy * qy) + qz * qz;
@@ -565,7 +566,7 @@ struct Rates32 {
         }
         cnt += (in && !ghost) ? 1 : 0;
         pair32<ZS>(in && r2 != 0.0f, qx, qy, qz, r2, b, c, bj.x, ghost ? vw2 - bj.y : bj.y,
-                   bj.z, bj.w, cj.x, cj.y, cj.z, invH, dwc, ar, avx, avy, avz, aE, sig);
+                   bj.z, bj.w, cj.x, cj.y, cj.z, invH, dwch, ar, avx, avy, avz, aE, sig);
     }
 
     // flat loop as in the FP64 kernel
@@ -742,6 +743,7 @@ __global__ __launch_bounds__(kRate32Block) void k_rates32(int64_t n, const float
     k.cxf = (float)k.t.cx;
     k.lo = (float)pc.H2 * (1.0f - kBand);
     k.hi = (float)pc.H2 * (1.0f + kBand);
+    k.dwch0 = (float)(pc.dwc * pc.invH);
     k.ti = k.t;
     k.yw = 0.0;
     k.wd = 0.f;
