@@ -33,6 +33,7 @@ struct DstState {
 // Zero records after the n FP32 stencil records: the FP32 stencil walk loads up to kUS - 1
 // records past a row's last one (the A record buffer has room for them)
 constexpr int kRecPad = 2;
+constexpr int kRecPad64 = 1;  // FP64 stencil walk: kU - 1 records past a row
 
 template <bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_pack(int64_t n, SrcState src,
@@ -93,6 +94,9 @@ __global__ __launch_bounds__(kBlock) void k_pack(int64_t n, SrcState src,
         ((double4 *)recA)[s] = make_double4(x, y, z, V);
         ((double4 *)recB)[s] = make_double4(vx, vy, vz, P);
         ((double2 *)recC)[s] = make_double2(Z, c);
+        if (s == n - 1)
+            for (int p = 1; p <= kRecPad64; ++p)
+                ((double4 *)recA)[n - 1 + p] = make_double4(0.0, 0.0, 0.0, 0.0);
     }
 }
 
@@ -130,6 +134,7 @@ constexpr int kRate32Block = 64;
 constexpr int kSlot = kRate32Block * (int)sizeof(float4);  // bytes per ring row
 constexpr int kRing = kQ * kSlot;                        // bytes per wave's rings
 constexpr int kRate64Block = kBlock;
+constexpr int kSlot64 = kRate64Block * (int)sizeof(int);  // FP64 kernel: bytes per ring row
 // workgroups per die chunk (xcd_block; measured on the porous shock's 100 steps, where the
 // wall band's costly waves made one die the last to finish): ~33 k / ~16 k particles
 constexpr unsigned kRate32Chunk = 512;
@@ -222,26 +227,35 @@ struct Rates64 {
     const int32_t *__restrict__ cs;
     GridDev g;
     PairConst pc;
-    int (*qj)[kRate64Block];
-    int tid, self;
+    char *qb;         // the workgroup's rings: kQ rows of kRate64Block 4-byte slots
+    int lane4;        // the lane's byte offset in a ring row
+    uint32_t self32;  // byte offset of i's own 32-byte records
     bool live, near_wall;
     double4 a, b;
     double2 zc;
     double di, yw, vw2;  // wall position along y, twice its velocity
     Stencil t, ti;       // stencils of i and of its mirror image
     double ar = 0.0, avx = 0.0, avy = 0.0, avz = 0.0, aE = 0.0, sig = 0.0;
+    // ring counters in entries (their count is |N(i)|); an entry is the partner's 32-byte
+    // record offset, bit 0 set for a mirror image
     int qw = 0, qr = 0, cntl = 0;
+
+    __device__ __forceinline__ uint32_t &slot(int q) {
+        return *(uint32_t *)(qb + (((q & (kQ - 1)) * kSlot64) | lane4));
+    }
 
     // every lane pops its next partner, if it has one; MIR: the wave may hold mirror entries
     template <bool MIR, bool ZS>
     __device__ __forceinline__ void drain() {
         const bool has = qr < qw;
-        const int e = qj[qr & (kQ - 1)][tid];
+        const uint32_t e = slot(qr);
         qr += has ? 1 : 0;
-        const int j = has ? (e & 0x7fffffff) : 0;
-        const bool ghost = MIR && e < 0;
-        const double4 aj = ld(A, j), bj = ld(B, j);
-        const double2 zj = ld(Cz, j);
+        const uint32_t jo = has ? (MIR ? e & ~31u : e) : 0u;
+        const bool ghost = MIR && (e & 1u);
+        const int j = (int)(jo >> 5);
+        const double4 aj = *(const double4 *)((const char *)A + jo);
+        const double4 bj = *(const double4 *)((const char *)B + jo);
+        const double2 zj = *(const double2 *)((const char *)Cz + (jo >> 1));
         const double yj = ghost ? 2.0 * yw - aj.y : aj.y;
         const double dx = aj.x - a.x, dy = yj - a.y, dz = aj.z - a.z;
         const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
@@ -266,6 +280,7 @@ struct Rates64 {
         const Stencil &st = GHOST ? ti : t;
         int oy = st.R, oz = -st.R - 1;  // advanced to (-R, -R) before the first row
         int k = 0, j0 = 0, len = 0, jlast = 0;
+        float gz2 = 0.f;
         for (;;) {
             if (__any(qw - qr > kQ - kU)) {  // keep every ring at <= kQ - kU entries
                 drain<MIR, ZS>();
@@ -275,17 +290,21 @@ struct Rates64 {
                 if (++oy > st.R) {
                     oy = -st.R;
                     if (++oz > st.R) break;
+                    const float gz = slab_gap(st.zc, st.cz + oz);  // per plane of rows
+                    gz2 = gz * gz;
                 }
-                const int zz = st.cz + oz;
-                const float gz = slab_gap(st.zc, zz);
-                row_range(cs, g, st, on, st.cy + oy, zz, gz * gz, j0, len);
+                row_range(cs, g, st, on, st.cy + oy, st.cz + oz, gz2, j0, len);
                 jlast = len > 0 ? j0 + len - 1 : 0;
                 k = 0;
                 continue;
             }
+            // the slots' records from j0 + k on, the start clamped to the row's last record
+            // (the pack appends kU - 1 zero records after the n records)
+            const uint32_t jbo = (uint32_t)min(j0 + k, jlast) * (uint32_t)sizeof(double4);
+            const double4 *Ab = (const double4 *)((const char *)A + jbo);
             double4 aj[kU];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) aj[u] = ld(A, min(j0 + k + u, jlast));
+            for (int u = 0; u < kU; ++u) aj[u] = Ab[u];
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 const int j = j0 + k + u;
@@ -298,9 +317,11 @@ struct Rates64 {
                     double H = pc.kappa * (0.5 * (di + ld(dsz, j < jlast ? j : jlast)));
                     H2 = H * H;
                 }
-                const bool acc = (k + u < len) && (GHOST || j != self) && r2 < H2;
+                // the entry's record offset (32 j for a slot that can be accepted)
+                const uint32_t jo = jbo + (uint32_t)(u * sizeof(double4));
+                const bool acc = (k + u < len) & (GHOST || jo != self32) & (r2 < H2);
                 // the ring slot qw is free: write always, advance on acceptance
-                qj[qw & (kQ - 1)][tid] = GHOST ? (j | (int)0x80000000) : j;
+                slot(qw) = GHOST ? jo | 1u : jo;
                 qw += acc ? 1 : 0;
             }
             k += kU;
@@ -354,7 +375,9 @@ struct Rates64 {
                 const double dx = aj[u].x - a.x, dy = yj - a.y, dz = aj[u].z - a.z;
                 const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
                 const bool acc = (k + u < len) && r2 < pc.H2;
-                qj[qw & (kQ - 1)][tid] = e[u];
+                // list entries carry the mirror flag in the sign bit
+                const uint32_t eu = (uint32_t)e[u];
+                slot(qw) = WALL ? (eu << 5) | (eu >> 31) : eu << 5;
                 qw += acc ? 1 : 0;
                 cntl += (acc && !ghost) ? 1 : 0;
             }
@@ -377,6 +400,8 @@ __global__ __launch_bounds__(kRate64Block, 5) void k_rates64(int64_t n, const do
                                                     VList vl) {
     __shared__ int qj[kQ][kRate64Block];
     Rates64<PAIR, WALL> k;
+    k.qb = (char *)&qj[0][0];
+    k.lane4 = threadIdx.x * (int)sizeof(int);
     k.A = A;
     k.B = B;
     k.Cz = Cz;
@@ -384,10 +409,8 @@ __global__ __launch_bounds__(kRate64Block, 5) void k_rates64(int64_t n, const do
     k.cs = cs;
     k.g = g;
     k.pc = pc;
-    k.qj = qj;
-    k.tid = threadIdx.x;
     const int64_t s = xcd_block<kRate64Chunk>(blockIdx.x, gridDim.x) * kRate64Block + threadIdx.x;
-    k.self = (int)s;
+    k.self32 = (uint32_t)s * (uint32_t)sizeof(double4);
     k.live = s < n;
     k.a = make_double4(0.0, 0.0, 0.0, 0.0);
     k.b = k.a;
