@@ -442,6 +442,10 @@ def test_voronoi_coherent_order_with_ties(K):
         sites[K - 1] = c + np.array([0.0, 1.0, 0.0])  # ties at c between the last two ...
         sites[K - 2] = c - np.array([0.0, 1.0, 0.0])  # ... generators (smaller k wins)
         sites[0] = sites[K - 1]                        # and a duplicate of the last one
+    if K >= 8:
+        c2 = np.array([30.5, 8.5, 6.5])  # a tie between an odd k and the next even one
+        sites[5] = c2 + np.array([1.0, 0.0, 0.0])
+        sites[6] = c2 - np.array([1.0, 0.0, 0.0])
     _voronoi_case(x, y, z, sites, cnt)
 
 
