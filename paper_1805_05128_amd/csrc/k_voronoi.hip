@@ -34,35 +34,16 @@ __global__ __launch_bounds__(kBlock) void k_voronoi(const double *__restrict__ x
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock) {
         double xi = x[i], yi = y[i], zi = z[i];
-        // two independent scans (even and odd k), each keeping its first minimum; the merge
-        // keeps the smaller distance, and on a tie the smaller k: the full scan's result
-        int b0 = 0, b1 = 0;
-        double d0 = INFINITY, d1 = INFINITY;
-        int k = 0;
-        for (; k + 1 < K; k += 2) {
-            const double ax = xi - gs[3 * k], ay = yi - gs[3 * k + 1], az = zi - gs[3 * k + 2];
-            const double bx = xi - gs[3 * k + 3], by = yi - gs[3 * k + 4],
-                         bz = zi - gs[3 * k + 5];
-            const double e0 = ((ax * ax) + (ay * ay)) + (az * az);
-            const double e1 = ((bx * bx) + (by * by)) + (bz * bz);
-            if (e0 < d0) {
-                d0 = e0;
-                b0 = k;
-            }
-            if (e1 < d1) {
-                d1 = e1;
-                b1 = k + 1;
+        int best = 0;
+        double bd = INFINITY;
+        for (int k = 0; k < K; ++k) {
+            double dx = xi - gs[3 * k], dy = yi - gs[3 * k + 1], dz = zi - gs[3 * k + 2];
+            double d2 = ((dx * dx) + (dy * dy)) + (dz * dz);
+            if (d2 < bd) {
+                bd = d2;
+                best = k;
             }
         }
-        if (k < K) {
-            const double ax = xi - gs[3 * k], ay = yi - gs[3 * k + 1], az = zi - gs[3 * k + 2];
-            const double e0 = ((ax * ax) + (ay * ay)) + (az * az);
-            if (e0 < d0) {
-                d0 = e0;
-                b0 = k;
-            }
-        }
-        const int best = (d1 < d0 || (d1 == d0 && b1 < b0)) ? b1 : b0;
         owner[i] = best;
         atomicAdd(&hp[best], 1u);
         if (nbr_count) atomicAdd(&hq[best], (unsigned long long)nbr_count[i]);
