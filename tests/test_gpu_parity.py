@@ -285,6 +285,20 @@ def test_rates_plate_impact_block_mixed_and_fp64():
         assert max(err.values()) <= tol, (prec, err)
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 5])
+@pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+def test_rates_few_particles(n, prec, tol):
+    """A handful of particles, all within each other's support: the lock-step walk reads the
+    zero records after the last particle's record (every row ends at the last particle)."""
+    w = ci.random_cloud(n, seed=40 + n, box=1.5)
+    _print_case(f"few{n} {prec}", w)
+    got, ref = _rates_case(w, prec)
+    err = field_relerr(got, ref)
+    assert max(err.values()) <= tol, err
+    assert np.array_equal(got["nbr_count"].astype(np.int64), ref["nbr_count"])
+    assert ref["nbr_count"].tolist() == [n - 1] * n
+
+
 def test_rates_isolated_and_coincident():
     w = ci.random_cloud(4, seed=3, box=1.0)
     w.x[:] = [0.0, 0.0, 50.0, 100.0]
