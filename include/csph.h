@@ -245,9 +245,10 @@ csph_status voronoi_assign(const double *x, const double *y, const double *z, in
  *   s_in -> s_out: the state renumbered into cell order (as csph_step with
  *     reorder = 1 does; s_out distinct from s_in; mat, id, d carried along).
  *     The lists index s_out's order.
- *   vl_count[n]: list lengths; vl_idx[cap * n] (device; cap a multiple of 8): the
- *     partners of particle s in 8-entry chunks, entry k at vl_idx[((k/8) n + s) 8 + k%8],
- *     k < vl_count[s]; j != s with r^2 < R^2 in FP64
+ *   vl_count[n]: list lengths; vl_idx[cap * n] (device, 16-byte aligned; cap a multiple
+ *     of 8): the partners of particle s in 8-entry chunks, entry k at
+ *     vl_idx[((k/8) n + s) 8 + k%8], k < vl_count[s] (entries past the count in the last
+ *     chunk are unspecified); j != s with r^2 < R^2 in FP64
  *     without contraction; a partner whose mirror image across the piston wall (at
  *     time *t, device) lies within R of s has the sign bit set.
  *   x_ref[3 n] (device): the positions at build, x..., y..., z....

@@ -555,6 +555,7 @@ csph_status csph_vlist_build(const csph_state *s_in, csph_state *s_out, const cs
     const int64_t n = s_in->n;
     if (n > 0 && (!vl_count || !vl_idx || !x_ref))
         return fail(CSPH_EINVAL, "vl_count, vl_idx and x_ref are required");
+    if (((uintptr_t)vl_idx & 15) != 0) return fail(CSPH_EINVAL, "vl_idx must be 16-byte aligned");
     if (n > 0 && (s_in->x == s_out->x || s_in->vx == s_out->vx || s_in->rho == s_out->rho ||
                   s_in->E == s_out->E || s_in->m == s_out->m))
         return fail(CSPH_EINVAL, "s_out must be distinct from s_in");

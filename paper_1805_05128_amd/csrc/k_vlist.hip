@@ -19,6 +19,9 @@ __global__ __launch_bounds__(kBlock) void k_vlist(int64_t n, const double4 *__re
                                                   int32_t *__restrict__ count,
                                                   int32_t *__restrict__ idx,
                                                   unsigned long long *__restrict__ over) {
+    // each lane gathers a chunk of 8 entries in LDS and stores it whole (two 16-byte stores)
+    // instead of one scattered 4-byte store per entry
+    __shared__ int stg[kBlock][kVlChunk];
     const int64_t s = xcd_block<64>(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const bool live = s < n;
     const double4 ai = live ? A[s] : make_double4(0.0, 0.0, 0.0, 0.0);
@@ -28,7 +31,10 @@ __global__ __launch_bounds__(kBlock) void k_vlist(int64_t n, const double4 *__re
     const bool near = WALL && live && mirror_band(g, yi, yw, R);
     // blocked: entry c of particle s at idx[((c / 8) n + s) 8 + c % 8]; one lane fills whole
     // 32-byte chunks and a wave reading its lanes' entry c touches 16 cache lines
-    int32_t *out = idx + (live ? s * kVlChunk : 0);
+    static_assert(kVlChunk == 8, "a chunk is two int4");
+    int4 *chunk = (int4 *)(idx + (live ? s * kVlChunk : 0));  // the lane's chunk c / 8
+    const int64_t cstride = n * kVlChunk / 4;                   // int4s from one chunk to the next
+    int *stage = stg[threadIdx.x];
     int c = 0;
     for (int pass = 0; pass < (WALL ? 2 : 1); ++pass) {
         const bool ghost = pass == 1;
@@ -60,16 +66,26 @@ __global__ __launch_bounds__(kBlock) void k_vlist(int64_t n, const double4 *__re
                 const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
                 const bool acc = (k + u < len) && (ghost || j != (int)s) && r2 < R2;
                 if (acc) {
-                    if (c < cap)
-                        out[(int64_t)(c / kVlChunk) * n * kVlChunk + (c % kVlChunk)] =
-                            ghost ? (j | (int)0x80000000) : j;
+                    stage[c & (kVlChunk - 1)] = ghost ? (j | (int)0x80000000) : j;
                     ++c;
+                    if ((c & (kVlChunk - 1)) == 0) {  // chunk full: store it (within cap)
+                        if (c <= cap) {
+                            chunk[0] = make_int4(stage[0], stage[1], stage[2], stage[3]);
+                            chunk[1] = make_int4(stage[4], stage[5], stage[6], stage[7]);
+                        }
+                        chunk += cstride;
+                    }
                 }
             }
             k += kU;
         }
     }
     if (live) {
+        // the last, partly filled chunk (entries past the count are never read)
+        if ((c & (kVlChunk - 1)) != 0 && c < cap) {
+            chunk[0] = make_int4(stage[0], stage[1], stage[2], stage[3]);
+            chunk[1] = make_int4(stage[4], stage[5], stage[6], stage[7]);
+        }
         count[s] = c;
         if (c > cap) atomicMax(over, (unsigned long long)c);
     }
