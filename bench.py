@@ -195,6 +195,58 @@ def impact_run(P, torch, ci, steps):
     return out
 
 
+def paper_mode_run(P, torch, ci, steps, nx=256, ny=256, nz=48):
+    """The paper's material mode at scale: an aluminium plate (v_z = -0.5 km/s) on a lead
+    plate, Mie-Grueneisen (sec. 5 parameters, g/cc, km/s, GPa), support kappa (d_i + d_j)/2
+    with kappa = 1.936 and d = (m/rho)^(1/3); ``steps`` steps from the initial state in each
+    precision after 3 warm-up steps on a throwaway copy."""
+    import numpy as np
+    lx, ly, lz = ci.lattice(nx, ny, nz)
+    ax, ay, az = ci.lattice(nx, ny, nz, shift=(0.0, 0.0, float(nz) + 1.0))
+    w = ci.jittered_block(1, 1, 1, seed=9, eos=[ci.MG_LEAD, ci.MG_ALUMINIUM])
+    r = np.random.default_rng(np.random.SeedSequence(9).spawn(1)[0])
+    x = np.concatenate([lx, ax]); y = np.concatenate([ly, ay]); z = np.concatenate([lz, az])
+    x, y, z = (c + r.uniform(-0.01, 0.01, c.shape) for c in (x, y, z))
+    nl = lx.shape[0]
+    mat = np.concatenate([np.zeros(nl, np.int32), np.ones(nl, np.int32)])
+    rho = np.where(mat == 0, ci.MG_LEAD[3], ci.MG_ALUMINIUM[3]).astype(np.float64)
+    w.x, w.y, w.z, w.mat, w.rho, w.m = x, y, z, mat, rho, rho.copy()
+    w.p = np.zeros_like(rho)
+    w.vx, w.vy = np.zeros_like(rho), np.zeros_like(rho)
+    w.vz = np.where(mat == 1, -0.5, 0.0)
+    d = np.cbrt(w.m / w.rho)
+    out = {"workload": f"mie_grueneisen_plates_{w.n}", "particles": w.n, "steps": steps,
+           "kappa": 1.936, "cell": 1.0}
+    for prec in ("mixed", "fp64"):
+        params = P.Params.from_workload(w, precision=prec, reorder=True, h_mode="pair",
+                                        kappa=1.936, cell_size=1.0, wall=None)
+        cnt = torch.empty(w.n, dtype=torch.int32, device="cuda")
+        pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+        for warm in (True, False):
+            state = P.state_from_workload(w, params, "cuda", with_id=False)
+            state.d = torch.as_tensor(d, dtype=torch.float64, device="cuda")
+            other = state.like()
+            sc = P.StepScalars("cuda")
+            ws = P.Workspace("cuda")
+            k = 3 if warm else steps
+            with collector_off():
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(k):
+                    o = P.csph_step(state, params, sc, s_out=other, nbr_count=cnt, ws=ws)
+                    if not warm:
+                        pairs += cnt.sum()
+                    state, other = o, state
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+        out[prec] = {"ms_per_step": 1e3 * el / steps, "pairs_per_s": int(pairs.item()) / el,
+                     "pairs_per_step": int(pairs.item()) / steps, "t_end": float(sc.t.item())}
+        del state, other, ws
+        torch.cuda.empty_cache()
+    out["mixed_speedup_over_fp64"] = out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"]
+    return out
+
+
 def voidfree_run(P, torch, ci, steps, cell):
     """The void-free 256^3 twin (16 777 216 particles), mixed, whole step with Voronoi: its
     ``steps`` steps from the initial state, after 3 warm-up steps on a throwaway copy."""
@@ -494,6 +546,10 @@ def main():
         line["impact"] = impact_run(P, torch, ci, 200)
         log(f"impact mixed {line['impact']['mixed']['ms_per_step']:.3f} ms/step, "
             f"fp64 {line['impact']['fp64']['ms_per_step']:.3f} ms/step")
+        log("Mie-Grueneisen plates, pair-averaged support, both precisions ...")
+        line["paper_mode"] = paper_mode_run(P, torch, ci, 20)
+        log(f"paper mode mixed {line['paper_mode']['mixed']['ms_per_step']:.3f} ms/step, "
+            f"fp64 {line['paper_mode']['fp64']['ms_per_step']:.3f} ms/step")
     if args.verlet_steps > 0:
         log("Verlet-list steps ...")
         line["verlet"] = verlet_timing(P, torch, w, args.cell, args.verlet_steps)
