@@ -201,21 +201,9 @@ def paper_mode_run(P, torch, ci, steps, nx=256, ny=256, nz=48):
     with kappa = 1.936 and d = (m/rho)^(1/3); ``steps`` steps from the initial state in each
     precision after 3 warm-up steps on a throwaway copy."""
     import numpy as np
-    lx, ly, lz = ci.lattice(nx, ny, nz)
-    ax, ay, az = ci.lattice(nx, ny, nz, shift=(0.0, 0.0, float(nz) + 1.0))
-    w = ci.jittered_block(1, 1, 1, seed=9, eos=[ci.MG_LEAD, ci.MG_ALUMINIUM])
-    r = np.random.default_rng(np.random.SeedSequence(9).spawn(1)[0])
-    x = np.concatenate([lx, ax]); y = np.concatenate([ly, ay]); z = np.concatenate([lz, az])
-    x, y, z = (c + r.uniform(-0.01, 0.01, c.shape) for c in (x, y, z))
-    nl = lx.shape[0]
-    mat = np.concatenate([np.zeros(nl, np.int32), np.ones(nl, np.int32)])
-    rho = np.where(mat == 0, ci.MG_LEAD[3], ci.MG_ALUMINIUM[3]).astype(np.float64)
-    w.x, w.y, w.z, w.mat, w.rho, w.m = x, y, z, mat, rho, rho.copy()
-    w.p = np.zeros_like(rho)
-    w.vx, w.vy = np.zeros_like(rho), np.zeros_like(rho)
-    w.vz = np.where(mat == 1, -0.5, 0.0)
+    w = ci.mg_plates(nx, ny, nz)
     d = np.cbrt(w.m / w.rho)
-    out = {"workload": f"mie_grueneisen_plates_{w.n}", "particles": w.n, "steps": steps,
+    out = {"workload": w.name, "particles": w.n, "steps": steps,
            "kappa": 1.936, "cell": 1.0}
     for prec in ("mixed", "fp64"):
         params = P.Params.from_workload(w, precision=prec, reorder=True, h_mode="pair",

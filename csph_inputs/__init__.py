@@ -219,6 +219,24 @@ def config4(nx: int = 400, ny: int = 400, nz: int = 200) -> Workload:
                     eos=[(EOS_IDEAL, 1.4, 0.0), (EOS_STIFFENED, 3.0, 10.0 / 3.0 - 1e-3)], **st)
 
 
+def mg_plates(nx: int = 256, ny: int = 256, nz: int = 48, gap: float = 2.0,
+              v_impact: float = 0.5, seed: int = 9) -> Workload:
+    """Aluminium plate moving at v_z = -v_impact onto a lead plate of the same lattice size,
+    Mie-Grueneisen materials of sec. 5 (g/cc, km/s, GPa), both at the reference state
+    (P = 0); ``gap`` lattice spacings between the facing layers."""
+    r = _streams(seed)
+    lx, ly, lz = lattice(nx, ny, nz)
+    ax, ay, az = lattice(nx, ny, nz, shift=(0.0, 0.0, float(nz) - 1.0 + gap))
+    x, y, z = jitter(r[0], np.concatenate([lx, ax]), np.concatenate([ly, ay]),
+                     np.concatenate([lz, az]))
+    nl = lx.shape[0]
+    mat = np.concatenate([np.zeros(nl, np.int32), np.ones(nl, np.int32)])
+    rho = np.where(mat == 0, MG_LEAD[3], MG_ALUMINIUM[3]).astype(np.float64)
+    st = _base(x, y, z, rho, 0.0, mat=mat)
+    st["vz"][nl:] = -v_impact
+    return Workload(name=f"mg_plates_{2 * nl}", eos=[MG_LEAD, MG_ALUMINIUM], steps=20, **st)
+
+
 def random_cloud(n: int, seed: int, box: float = 8.0, vmax: float = 0.3,
                  rho_range=(0.5, 2.0), p_range=(0.2, 2.0), n_mat: int = 1) -> Workload:
     """Uniform random particles in [0, box)^3 with random primitive state (edge-case tests)."""

@@ -7,6 +7,8 @@ configuration bench.py times (cell order, unit mesh cells, both precisions):
   first layers behind it, as in the later steps of the run);
 * plate impact (589 824 particles): one full step of every particle, both
   precisions, and the compensated totals;
+* Mie-Grueneisen plates in the pair-averaged support mode (6 291 456
+  particles): rates of a seeded sample including the contact layers;
 * two-body collision (64 000 000 particles): rates of a seeded sample that
   includes the contact layer, against the oracle computed for the sample;
   and the adjoint of the last 5 of its 50 steps (45 mixed steps in cell
@@ -129,6 +131,38 @@ def test_collision64m_rates_sampled():
         assert max(err.values()) <= tol, (prec, err)
         assert np.array_equal(got["nbr_count"][sample].astype(np.int64), ref["nbr_count"])
     assert nb == 32_000_000
+
+
+def test_mg_plates_pair_h_sampled():
+    """The paper's material mode at the bench's size: aluminium onto lead (Mie-Grueneisen,
+    6.29 M particles), support kappa (d_i + d_j)/2 with kappa = 1.936, the plates one spacing
+    apart so that the contact layers interact; rates of a seeded sample (uniform plus the
+    layers at the contact) against the oracle."""
+    w = ci.mg_plates(gap=1.0)
+    d = np.cbrt(w.m / w.rho)
+    print(f"[case] {w.name} pair-h n={w.n}", flush=True)
+    lead_top = w.z[w.mat == 0].max()
+    contact = np.nonzero(np.abs(w.z - (lead_top + 0.5)) < 2.5)[0]
+    rng = np.random.default_rng(7)
+    sample = np.unique(np.concatenate([rng.integers(0, w.n, 1500),
+                                       rng.choice(contact, 1500, replace=False)]))
+    cfg = O.cfg_for(w, search=1, h_mode=1, kappa=1.936)
+    ref = O.rates_sample(cfg, O.state_from(w, cfg), sample, d=d)
+    assert ref["nbr_count"].min() > 0
+    for prec, tol in (("mixed", MIXED_TOL), ("fp64", FP64_TOL)):
+        params = P.Params.from_workload(w, precision=prec, reorder=True, h_mode="pair",
+                                        kappa=1.936, cell_size=1.0)
+        g = P.state_from_workload(w, params, DEV, with_id=False)
+        g.d = torch.as_tensor(d, dtype=torch.float64, device=DEV)
+        got = rates_np(P.csph_rates(g, params))
+        torch.cuda.synchronize()
+        sub = {k: got[k][sample] for k in RATE_FIELDS}
+        err = field_relerr(sub, ref)
+        print(prec, err, flush=True)
+        assert max(err.values()) <= tol, (prec, err)
+        assert np.array_equal(got["nbr_count"][sample].astype(np.int64), ref["nbr_count"])
+        del g
+        torch.cuda.empty_cache()
 
 
 def test_collision64m_adjoint_last5_steps():
