@@ -100,3 +100,21 @@ def test_pair_walks_reject_more_than_2_to_27_particles():
     assert L.csph_step(C.byref(s), C.byref(s), C.byref(p), None, 0.0, None, None, None, None,
                        None, 0, None, None) == N.CSPH_EINVAL
     assert b"2^27" in L.csph_last_error()
+
+
+def test_vlist_build_rejects_misaligned_list_storage():
+    """List chunks are stored as 16-byte vectors: a misaligned vl_idx is refused on the host,
+    before any device work (pointers are never dereferenced)."""
+    L = N.load()
+    p = P.Params().c()
+    a, b = N.CsphState(), N.CsphState()
+    for st, base in ((a, 4096), (b, 8192)):
+        st.n = 100
+        for k, f in enumerate(("x", "y", "z", "vx", "vy", "vz", "rho", "E", "m")):
+            setattr(st, f, C.cast(C.c_void_p(base + 1024 * k), C.POINTER(C.c_double)))
+    dev = lambda addr, t: C.cast(C.c_void_p(addr), C.POINTER(t))
+    st = L.csph_vlist_build(C.byref(a), C.byref(b), C.byref(p), None, 0.3, 64,
+                            dev(65536, C.c_int32), dev(131072 + 4, C.c_int32),
+                            dev(262144, C.c_double), None, None, 0, None, None)
+    assert st == N.CSPH_EINVAL
+    assert b"16-byte aligned" in L.csph_last_error()
