@@ -124,22 +124,25 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const TI *__restrict__ i
     if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
 }
 
-// Exclusive scan of the tile sums in one workgroup; out[len] = grand total.
+// Exclusive scan of the tile sums in one workgroup; out[len] = grand total.  Each thread
+// takes a run of consecutive tiles, so one workgroup scan covers them all.
 template <typename TO>
 __global__ __launch_bounds__(kBlock) void k_scan_tops(int64_t *__restrict__ tile_sum,
                                                       int64_t ntiles, TO *__restrict__ out,
                                                       int64_t len) {
     __shared__ int64_t lds[kBlock / 64 + 1];
-    int64_t run = 0;
-    for (int64_t b = 0; b < ntiles; b += kBlock) {
-        int64_t i = b + threadIdx.x;
-        int64_t v = i < ntiles ? tile_sum[i] : 0;
-        int64_t total;
-        int64_t e = block_exclusive_scan<int64_t>(v, lds, total);
-        if (i < ntiles) tile_sum[i] = run + e;
-        run += total;
+    const int64_t per = (ntiles + kBlock - 1) / kBlock;
+    const int64_t a = (int64_t)threadIdx.x * per, b = a + per < ntiles ? a + per : ntiles;
+    int64_t s = 0;
+    for (int64_t i = a; i < b; ++i) s += tile_sum[i];
+    int64_t total;
+    int64_t run = block_exclusive_scan<int64_t>(s, lds, total);
+    for (int64_t i = a; i < b; ++i) {
+        const int64_t v = tile_sum[i];
+        tile_sum[i] = run;
+        run += v;
     }
-    if (threadIdx.x == 0) out[len] = (TO)run;
+    if (threadIdx.x == 0) out[len] = (TO)total;
 }
 
 template <typename TI, typename TO>
