@@ -145,24 +145,45 @@ __global__ __launch_bounds__(kBlock) void k_scan_tops(int64_t *__restrict__ tile
     if (threadIdx.x == 0) out[len] = (TO)total;
 }
 
+// vec: in and out are 16-byte aligned 32-bit arrays; a thread's kScanItems = 8 values then move
+// as two 16-byte loads and stores (the tail tile goes element by element).
 template <typename TI, typename TO>
 __global__ __launch_bounds__(kBlock) void k_scan_apply(const TI *in, TO *out, int64_t len,
-                                                       const int64_t *__restrict__ tile_off) {
+                                                       const int64_t *__restrict__ tile_off,
+                                                       int vec) {
+    static_assert(kScanItems == 8, "two 16-byte vectors per thread");
     int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    const bool wide = sizeof(TI) == 4 && sizeof(TO) == 4 && vec && base + kScanItems <= len;
     int64_t v[kScanItems];
     int64_t s = 0;
-    for (int k = 0; k < kScanItems; ++k) {
-        int64_t i = base + k;
-        v[k] = i < len ? (int64_t)in[i] : 0;
-        s += v[k];
+    if (wide) {
+        const int4 a = ((const int4 *)(in + base))[0], b = ((const int4 *)(in + base))[1];
+        const int w[kScanItems] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+        for (int k = 0; k < kScanItems; ++k) v[k] = w[k];
+    } else {
+        for (int k = 0; k < kScanItems; ++k) {
+            int64_t i = base + k;
+            v[k] = i < len ? (int64_t)in[i] : 0;
+        }
     }
+    for (int k = 0; k < kScanItems; ++k) s += v[k];
     __shared__ int64_t lds[kBlock / 64 + 1];
     int64_t total;
     int64_t run = block_exclusive_scan<int64_t>(s, lds, total) + tile_off[blockIdx.x];
-    for (int k = 0; k < kScanItems; ++k) {
-        int64_t i = base + k;
-        if (i < len) out[i] = (TO)run;
-        run += v[k];
+    if (wide) {
+        int o[kScanItems];
+        for (int k = 0; k < kScanItems; ++k) {
+            o[k] = (int)run;
+            run += v[k];
+        }
+        ((int4 *)(out + base))[0] = make_int4(o[0], o[1], o[2], o[3]);
+        ((int4 *)(out + base))[1] = make_int4(o[4], o[5], o[6], o[7]);
+    } else {
+        for (int k = 0; k < kScanItems; ++k) {
+            int64_t i = base + k;
+            if (i < len) out[i] = (TO)run;
+            run += v[k];
+        }
     }
 }
 
@@ -174,7 +195,9 @@ hipError_t launch_scan_exclusive(const TI *in, TO *out, int64_t len, int64_t *tm
     int64_t ntiles = (len + kScanTile - 1) / kScanTile;
     if (ntiles > 0) k_scan_reduce<TI><<<(unsigned)ntiles, kBlock, 0, st>>>(in, len, tmp);
     k_scan_tops<TO><<<1, kBlock, 0, st>>>(tmp, ntiles, out, len);
-    if (ntiles > 0) k_scan_apply<TI, TO><<<(unsigned)ntiles, kBlock, 0, st>>>(in, out, len, tmp);
+    const int vec = ((uintptr_t)in % 16 == 0) && ((uintptr_t)out % 16 == 0);
+    if (ntiles > 0)
+        k_scan_apply<TI, TO><<<(unsigned)ntiles, kBlock, 0, st>>>(in, out, len, tmp, vec);
     return hipGetLastError();
 }
 
