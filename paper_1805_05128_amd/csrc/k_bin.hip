@@ -111,12 +111,18 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T *lds, T &total) {
 
 template <typename TI>
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const TI *__restrict__ in, int64_t len,
-                                                        int64_t *__restrict__ tile_sum) {
+                                                        int64_t *__restrict__ tile_sum, int vec) {
     int64_t base = (int64_t)blockIdx.x * kScanTile;
     int64_t s = 0;
-    for (int k = 0; k < kScanItems; ++k) {
-        int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
-        if (i < len) s += (int64_t)in[i];
+    const int64_t own = base + (int64_t)threadIdx.x * kScanItems;  // the apply pass's layout
+    if (sizeof(TI) == 4 && vec && own + kScanItems <= len) {
+        const int4 a = ((const int4 *)(in + own))[0], b = ((const int4 *)(in + own))[1];
+        s = (((int64_t)a.x + a.y) + ((int64_t)a.z + a.w)) + (((int64_t)b.x + b.y) + ((int64_t)b.z + b.w));
+    } else {
+        for (int k = 0; k < kScanItems; ++k) {
+            int64_t i = own + k;
+            if (i < len) s += (int64_t)in[i];
+        }
     }
     __shared__ int64_t lds[kBlock / 64 + 1];
     int64_t total;
@@ -193,9 +199,9 @@ template <typename TI, typename TO>
 hipError_t launch_scan_exclusive(const TI *in, TO *out, int64_t len, int64_t *tmp,
                                  hipStream_t st) {
     int64_t ntiles = (len + kScanTile - 1) / kScanTile;
-    if (ntiles > 0) k_scan_reduce<TI><<<(unsigned)ntiles, kBlock, 0, st>>>(in, len, tmp);
-    k_scan_tops<TO><<<1, kBlock, 0, st>>>(tmp, ntiles, out, len);
     const int vec = ((uintptr_t)in % 16 == 0) && ((uintptr_t)out % 16 == 0);
+    if (ntiles > 0) k_scan_reduce<TI><<<(unsigned)ntiles, kBlock, 0, st>>>(in, len, tmp, vec);
+    k_scan_tops<TO><<<1, kBlock, 0, st>>>(tmp, ntiles, out, len);
     if (ntiles > 0)
         k_scan_apply<TI, TO><<<(unsigned)ntiles, kBlock, 0, st>>>(in, out, len, tmp, vec);
     return hipGetLastError();
