@@ -40,8 +40,13 @@
  *               CSPH_ECAPACITY: an output or workspace is too small;
  *               CSPH_EDEVICE: a HIP runtime error.  Nothing is written on
  *               EINVAL.  csph_last_error() returns a thread-local message.
- *               Non-physical states (negative or NaN squared sound speed)
- *               are counted on the device, never trapped.
+ *               Non-physical states (negative or NaN squared sound speed,
+ *               Mie-Grueneisen compression past its Hugoniot's limit) are
+ *               counted on the device and never trapped: the particle's
+ *               sound speed is taken as 0 and every output is written.
+ *               csph_rates, and csph_step with params.check_nonphys = 1,
+ *               then return CSPH_ENONPHYS after their closing
+ *               synchronisation; an asynchronous csph_step only counts.
  */
 #ifndef CSPH_H
 #define CSPH_H
@@ -58,6 +63,7 @@ typedef int32_t csph_status;
 #define CSPH_EINVAL 1
 #define CSPH_ECAPACITY 2
 #define CSPH_EDEVICE 3
+#define CSPH_ENONPHYS 4 /* outputs written; some particle's state was non-physical */
 
 typedef void *csph_stream; /* hipStream_t */
 
@@ -77,6 +83,13 @@ typedef void *csph_stream; /* hipStream_t */
 
 #define CSPH_H_FIXED 0 /* support H = kappa*h for every pair */
 #define CSPH_H_PAIR 1  /* H_ij = kappa*(d_i+d_j)/2, d_i given per particle (eq. SmoothingLengthDef) */
+
+/* Cell keys csph_bin reports (sec. 4.2 cells, numbered for the renumbering of particles):
+ * LINEAR (c_z dims_y + c_y) dims_x + c_x, over ncell keys; MORTON: the bits of c_x, c_y,
+ * c_z interleaved (bit b of c_x at key bit 3b, of c_y at 3b+1, of c_z at 3b+2), over
+ * 2^(3 bits) keys, bits = ceil(log2(max dims)), dims <= 1024 per axis. */
+#define CSPH_KEY_LINEAR 0
+#define CSPH_KEY_MORTON 1
 
 typedef struct {
     int32_t type;   /* CSPH_EOS_* */
@@ -99,14 +112,18 @@ typedef struct {
                           pair signal speed; the second term bounds the relative density
                           change of one step); <= 0: the caller's dt is used */
     int32_t n_eos;     /* materials 0..n_eos-1; mat[i] selects eos[mat[i]] */
-    int32_t wall;      /* 1: rigid piston plane x = wall_x0 + wall_v t, fluid at x > plane,
-                          handled by mirror partners (also for particles that have fallen
-                          behind the plane) */
+    int32_t wall;      /* 1: rigid piston plane x = wall_x0 + wall_v t, fluid at x > plane:
+                          mirror partners in the rates (for any configuration, particles
+                          behind the plane included), and csph_step reflects a particle
+                          that crosses the plane */
     double wall_x0;
     double wall_v;
     csph_eos eos[CSPH_MAX_EOS];
     int32_t reorder;   /* csph_step: 1 = write the new state in cell order (renumbering of
                           sec. 4.2; `id` is carried along); 0 = keep the input order */
+    int32_t key_mode;  /* CSPH_KEY_LINEAR | CSPH_KEY_MORTON: keys of csph_grid_build's mesh */
+    int32_t check_nonphys; /* csph_step: 1 = wait for the step's kernels and return
+                              CSPH_ENONPHYS if its EOS met a non-physical state */
     int32_t pad;
 } csph_params;
 
@@ -130,14 +147,17 @@ typedef struct {
  * inv_cell = 1/D (formed once on the host), dims_a = floor((max_a -
  * origin_a) * inv_cell) + 1, cell of a particle
  * c_a = min(floor((x_a - origin_a) * inv_cell), dims_a - 1), all in FP64
- * without contraction.  Linear key (c_z * dims_y + c_y) * dims_x + c_x. */
+ * without contraction.  Keys: key_mode (see CSPH_KEY_*), over nkey keys. */
 typedef struct {
     double origin[3];
     double cell;      /* D */
     double inv_cell;  /* 1.0 / D */
     int32_t dims[3];
     int32_t reach;    /* stencil half-width in cells: ceil(max support / D) */
-    int64_t ncell;
+    int64_t ncell;    /* dims[0] dims[1] dims[2] */
+    int32_t key_mode; /* CSPH_KEY_LINEAR | CSPH_KEY_MORTON */
+    int32_t pad;
+    int64_t nkey;     /* key space: ncell (LINEAR) or 2^(3 bits) (MORTON) */
 } csph_grid;
 
 /* Rates of eqs. SPH:Conti, SPH:Pulse, SPH:Energy, one FP64 array each. */
@@ -166,12 +186,13 @@ csph_status csph_grid_build(const double *x, const double *y, const double *z, i
 
 /* Binning and cell-ordered numbering (sec. 4.2).  With *grid from
  * csph_grid_build (or any mesh that covers the positions), writes
- *   key[i]   linear cell key of particle i (input order), uint32;
+ *   key[i]   cell key of particle i (input order, grid->key_mode), uint32;
  *   perm[s]  the input index of the s-th particle in cell order: the stable
  *            order by (key, input index);
- *   cell_start[c] = first s with key >= c, for c = 0..ncell
- *            (cell_start[ncell] = n); cell_start_cap >= ncell+1 entries.
- * key may be NULL.  Bit-exact: integer results of FP64 comparisons. */
+ *   cell_start[c] = first s with key >= c, for c = 0..nkey
+ *            (cell_start[nkey] = n); cell_start_cap >= nkey+1 entries.
+ * key may be NULL.  Bit-exact: integer results of FP64 comparisons.
+ * CSPH_EINVAL when grid->nkey does not match its dims and key_mode. */
 csph_status csph_bin(const double *x, const double *y, const double *z, int64_t n,
                      const csph_grid *grid /* host */, uint32_t *key, int32_t *perm,
                      int32_t *cell_start, int64_t cell_start_cap, void *ws, size_t ws_bytes,
@@ -207,7 +228,8 @@ csph_status csph_neighbors(const csph_state *s, const csph_params *p, int64_t *o
  * nbr_count (optional): |N(i)| (real partners only).
  * nonphys (optional, device int64): incremented by the number of particles
  * whose squared sound speed is negative or NaN (their c is taken as 0).
- * Synchronises once (mesh bounds). */
+ * Synchronises twice (mesh bounds; at the end, for the non-physical count):
+ * returns CSPH_ENONPHYS, every output written, when that count is not 0. */
 csph_status csph_rates(const csph_state *s, const csph_params *p, double t,
                        csph_rates_out out, double *signal, int32_t *nbr_count, int64_t *nonphys,
                        void *ws, size_t ws_bytes, size_t *ws_needed, csph_stream stream);
@@ -222,7 +244,13 @@ csph_status csph_rates(const csph_state *s, const csph_params *p, double t,
  * optional), totals (device, optional, 10 doubles): (hi, lo) compensated
  * FP64 sums of m, m vx, m vy, m vz, m E over the new state, in a fixed
  * reduction order.  nbr_count (optional) in the output order.  nonphys as
- * in csph_rates.  Synchronises once (mesh bounds). */
+ * in csph_rates.  With a wall (p->wall; t is then required), a particle
+ * whose new x lies behind the plane x_w(t + dt) is reflected off it, the
+ * rigid wall of sec. 7.1 stopping it: x <- 2 x_w - x, v_x <- 2 v_w - v_x,
+ * E <- E + (v_x'^2 - v_x^2)/2 (specific internal energy kept).
+ * Synchronises once (mesh bounds); with p->check_nonphys also at the end,
+ * returning CSPH_ENONPHYS (state written) if the EOS met a non-physical
+ * state. */
 csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_params *p,
                       double *t, double dt_in, double *dt_used, double *totals,
                       int32_t *nbr_count, int64_t *nonphys, void *ws, size_t ws_bytes,

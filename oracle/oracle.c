@@ -662,8 +662,13 @@ double oracle_dt(const oracle_cfg *cfg, int64_t n, const double *signal, const d
 
 /* One step: rates at (state, t); dt from the CFL rule (cfl > 0) or dt_in;
  * v += dt dv/dt, E += dt dE/dt, rho += dt drho/dt, then r += dt v(new);
- * t += dt.  State arrays are updated in place.  Returns the non-physical
- * count from the rate evaluation (or -1). */
+ * t += dt.  With the piston (the rigid wall of sec. 7.1, which stops the
+ * particles at the wall), a particle whose new x lies behind the plane
+ * x_w(t + dt) is reflected about it, as off a rigid wall in the wall's
+ * frame: x <- 2 x_w - x, v_x <- 2 v_w - v_x, with its specific internal
+ * energy kept (E changes by the kinetic-energy difference, the wall's work).
+ * State arrays are updated in place.  Returns the non-physical count from
+ * the rate evaluation (or -1). */
 int64_t oracle_step(const oracle_cfg *cfg, int64_t n, double *x, double *y, double *z,
                     double *vx, double *vy, double *vz, double *rho, double *E, const double *m,
                     const int32_t *mat, const double *d, double *t, double dt_in, double *dt_used,
@@ -676,6 +681,8 @@ int64_t oracle_step(const oracle_cfg *cfg, int64_t n, double *x, double *y, doub
         bad = oracle_rates(cfg, n, x, y, z, vx, vy, vz, rho, E, m, mat, d, *t, r0, r1, r2, r3,
                            r4, sg, nbr_count);
         double dt = cfg->cfl > 0.0 ? oracle_dt(cfg, n, sg, d, rho, r0) : dt_in;
+        double t_new = *t + dt;
+        double xw = cfg->wall_x0 + cfg->wall_v * t_new;
         for (int64_t i = 0; i < n; ++i) {
             vx[i] = vx[i] + dt * r1[i];
             vy[i] = vy[i] + dt * r2[i];
@@ -685,8 +692,14 @@ int64_t oracle_step(const oracle_cfg *cfg, int64_t n, double *x, double *y, doub
             x[i] = x[i] + dt * vx[i];
             y[i] = y[i] + dt * vy[i];
             z[i] = z[i] + dt * vz[i];
+            if (cfg->wall && x[i] < xw) {
+                double vr = 2.0 * cfg->wall_v - vx[i];
+                E[i] = E[i] + 0.5 * ((vr * vr) - (vx[i] * vx[i]));
+                vx[i] = vr;
+                x[i] = 2.0 * xw - x[i];
+            }
         }
-        *t = *t + dt;
+        *t = t_new;
         if (dt_used) *dt_used = dt;
     }
     free(r0); free(r1); free(r2); free(r3); free(r4); free(sg);

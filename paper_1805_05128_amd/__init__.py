@@ -1,6 +1,8 @@
 """MI355X (gfx950) contact-SPH hot path: binning, neighbour search, pair
 rates, step, Voronoi ownership and their adjoints, behind the C ABI of
 include/csph.h (libcsph.so, hand-written HIP)."""
+from ._native import (CSPH_OK, CSPH_EINVAL, CSPH_ECAPACITY, CSPH_EDEVICE,  # noqa: F401
+                      CSPH_ENONPHYS, CsphError, NonPhysicalState)
 from .api import (EOS_IDEAL, EOS_STIFFENED, EOS_MIE_GRUNEISEN, Params, State, StepScalars, Workspace,  # noqa: F401
                   csph_bin, csph_grid_build, csph_init_energy, csph_neighbors, csph_rates,
                   csph_step, default_workspace, profile_enable, profile_read, state_from_workload, version, voronoi_assign,

@@ -11,11 +11,12 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libcsph.so")
 
-CSPH_OK, CSPH_EINVAL, CSPH_ECAPACITY, CSPH_EDEVICE = 0, 1, 2, 3
+CSPH_OK, CSPH_EINVAL, CSPH_ECAPACITY, CSPH_EDEVICE, CSPH_ENONPHYS = 0, 1, 2, 3, 4
 CSPH_MAX_EOS = 8
 CSPH_EOS_IDEAL, CSPH_EOS_STIFFENED, CSPH_EOS_MIE_GRUNEISEN = 0, 1, 2
 CSPH_FP64, CSPH_MIXED = 0, 1
 CSPH_H_FIXED, CSPH_H_PAIR = 0, 1
+CSPH_KEY_LINEAR, CSPH_KEY_MORTON = 0, 1
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -37,7 +38,8 @@ class CsphParams(C.Structure):
         ("n_eos", C.c_int32), ("wall", C.c_int32),
         ("wall_x0", C.c_double), ("wall_v", C.c_double),
         ("eos", CsphEos * CSPH_MAX_EOS),
-        ("reorder", C.c_int32), ("pad", C.c_int32),
+        ("reorder", C.c_int32), ("key_mode", C.c_int32), ("check_nonphys", C.c_int32),
+        ("pad", C.c_int32),
     ]
 
 
@@ -49,7 +51,8 @@ class CsphState(C.Structure):
 
 class CsphGrid(C.Structure):
     _fields_ = [("origin", C.c_double * 3), ("cell", C.c_double), ("inv_cell", C.c_double),
-                ("dims", C.c_int32 * 3), ("reach", C.c_int32), ("ncell", C.c_int64)]
+                ("dims", C.c_int32 * 3), ("reach", C.c_int32), ("ncell", C.c_int64),
+                ("key_mode", C.c_int32), ("pad", C.c_int32), ("nkey", C.c_int64)]
 
 
 class CsphRatesOut(C.Structure):
@@ -80,6 +83,11 @@ class CsphError(RuntimeError):
     def __init__(self, status: int, where: str, msg: str):
         super().__init__(f"{where}: status {status}: {msg}")
         self.status = status
+
+
+class NonPhysicalState(CsphError):
+    """CSPH_ENONPHYS: the call wrote its outputs, but some particle's state was non-physical
+    (negative or NaN squared sound speed; its sound speed was taken as 0)."""
 
 
 def load():
@@ -161,4 +169,5 @@ def check(status: int, where: str):
     if status != CSPH_OK:
         L = load()
         msg = (L.csph_last_error() or b"").decode() or L.csph_status_string(status).decode()
-        raise CsphError(status, where, msg)
+        cls = NonPhysicalState if status == CSPH_ENONPHYS else CsphError
+        raise cls(status, where, msg)

@@ -61,6 +61,8 @@ class Params:
     cfl: float = 0.3
     wall: Optional[Tuple[float, float]] = None
     reorder: bool = True
+    key_mode: str = "linear"  # "linear" | "morton": keys csph_bin reports
+    check_nonphys: bool = False  # csph_step: wait and raise NonPhysicalState (state written)
 
     def c(self) -> N.CsphParams:
         p = N.CsphParams()
@@ -77,6 +79,8 @@ class Params:
         if self.wall is not None:
             p.wall, p.wall_x0, p.wall_v = 1, float(self.wall[0]), float(self.wall[1])
         p.reorder = 1 if self.reorder else 0
+        p.key_mode = N.CSPH_KEY_MORTON if self.key_mode == "morton" else N.CSPH_KEY_LINEAR
+        p.check_nonphys = 1 if self.check_nonphys else 0
         return p
 
     @classmethod
@@ -179,17 +183,21 @@ def default_workspace(device="cuda") -> Workspace:
     return _default_ws[key]
 
 
-def _with_ws(fn, ws: Workspace, where: str):
-    """Call fn(ws_ptr, ws_bytes, needed_ptr); grow the workspace once on CSPH_ECAPACITY."""
+def _with_ws(fn, ws: Workspace, where: str, accept=()):
+    """Call fn(ws_ptr, ws_bytes, needed_ptr); grow the workspace once on CSPH_ECAPACITY.
+    Statuses in ``accept`` are returned instead of raised."""
     needed = C.c_size_t(0)
     for _ in range(3):
         st = fn(ws.ptr, ws.nbytes, C.byref(needed))
         if st == N.CSPH_ECAPACITY and needed.value > ws.nbytes:
             ws.ensure(needed.value)
             continue
+        if st in accept:
+            return st
         N.check(st, where)
-        return
+        return st
     N.check(st, where)
+    return st
 
 
 def profile_enable(on: bool = True):
@@ -225,13 +233,14 @@ def csph_grid_build(x, y, z, params: Params, d=None, ws: Optional[Workspace] = N
 
 
 def csph_bin(x, y, z, grid: N.CsphGrid, ws: Optional[Workspace] = None, stream=None):
-    """(key uint32-as-int64 view, perm int32, cell_start int32) of sec. 4.2 binning."""
+    """(key uint32-as-int64 view, perm int32, cell_start int32 [nkey + 1]) of sec. 4.2
+    binning, keys as grid.key_mode (from the params of csph_grid_build) says."""
     L = N.load()
     ws = ws or default_workspace(x.device)
     n = x.shape[0]
     key = torch.empty(max(n, 1), dtype=torch.int32, device=x.device)
     perm = torch.empty(max(n, 1), dtype=torch.int32, device=x.device)
-    cs = torch.empty(grid.ncell + 1, dtype=torch.int32, device=x.device)
+    cs = torch.empty(grid.nkey + 1, dtype=torch.int32, device=x.device)
     _with_ws(lambda w, b, nd: L.csph_bin(_dp(x), _dp(y), _dp(z), n, C.byref(grid),
                                          C.cast(C.c_void_p(key.data_ptr()), C.POINTER(C.c_uint32)),
                                          _ip(perm), _ip(cs), cs.shape[0], w, b, nd,
@@ -260,7 +269,9 @@ def csph_neighbors(state: State, params: Params, ws: Optional[Workspace] = None,
 
 def csph_rates(state: State, params: Params, t: float = 0.0, ws: Optional[Workspace] = None,
                stream=None, want_signal=True, want_count=True):
-    """Rates (drho, dvx, dvy, dvz, dE) in the state's order, plus signal speed and |N(i)|."""
+    """Rates (drho, dvx, dvy, dvz, dE) in the state's order, plus signal speed and |N(i)|.
+    A non-physical state does not raise: out["nonphys"] counts the particles concerned and
+    out["status"] is CSPH_ENONPHYS."""
     L = N.load()
     dev = state["x"].device
     ws = ws or default_workspace(dev)
@@ -273,9 +284,11 @@ def csph_rates(state: State, params: Params, t: float = 0.0, ws: Optional[Worksp
     ro = N.CsphRatesOut(*[_dp(out[k]) for k in ("drho", "dvx", "dvy", "dvz", "dE")])
     s = state.c()
     p = params.c()
-    _with_ws(lambda w, b, nd: L.csph_rates(C.byref(s), C.byref(p), float(t), ro, _dp(sig),
-                                           _ip(cnt), _lp(nonphys), w, b, nd, _stream(stream)), ws,
-             "csph_rates")
+    status = _with_ws(lambda w, b, nd: L.csph_rates(C.byref(s), C.byref(p), float(t), ro,
+                                                    _dp(sig), _ip(cnt), _lp(nonphys), w, b, nd,
+                                                    _stream(stream)), ws, "csph_rates",
+                      accept=(N.CSPH_ENONPHYS,))
+    out["status"] = status
     if sig is not None:
         out["signal"] = sig
     if cnt is not None:
@@ -297,7 +310,9 @@ class StepScalars:
 def csph_step(s_in: State, params: Params, sc: StepScalars, s_out: Optional[State] = None,
               dt_in: float = 0.0, nbr_count: Optional[torch.Tensor] = None,
               ws: Optional[Workspace] = None, stream=None, totals: bool = True) -> State:
-    """One step s_in -> s_out (allocated when None); returns s_out."""
+    """One step s_in -> s_out (allocated when None); returns s_out.  With
+    params.check_nonphys the call waits for its kernels and raises NonPhysicalState (the
+    step is complete) if the EOS met a non-physical state."""
     L = N.load()
     ws = ws or default_workspace(s_in["x"].device)
     if s_out is None:

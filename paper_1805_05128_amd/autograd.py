@@ -126,7 +126,13 @@ class CSPHRollout(torch.autograd.Function):
 
 
 def rollout(vx0, vy0, vz0, gamma, base, params, nsteps, every=10, dts=None, info=None):
-    """Functional form of CSPHRollout.apply; returns a dict of final-state tensors."""
+    """Functional form of CSPHRollout.apply; returns a dict of final-state tensors.
+
+    The gradient is that of the rollout at a FIXED time-step sequence: the forward records
+    the CFL time steps it took (or takes ``dts``), and the backward differentiates the map
+    with those steps held constant.  The dependence of the CFL step on the state and on
+    gamma (through c, the closing speeds and rho/|drho/dt|) is not differentiated, so a
+    finite-difference check must replay the same steps."""
     info = {} if info is None else info
     out = CSPHRollout.apply(vx0, vy0, vz0, gamma, base, params, nsteps, every, dts, info)
     return dict(zip(STATE8, out))

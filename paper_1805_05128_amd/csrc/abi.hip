@@ -157,6 +157,8 @@ static csph_status check_params(const csph_params *p, bool need_pair_d, const do
         }
         if (!std::isfinite(e.p_inf)) return fail(CSPH_EINVAL, "eos[%d].p_inf not finite", k);
     }
+    if (p->key_mode != CSPH_KEY_LINEAR && p->key_mode != CSPH_KEY_MORTON)
+        return fail(CSPH_EINVAL, "key_mode %d unknown", p->key_mode);
     if (!std::isfinite(p->cell_size)) return fail(CSPH_EINVAL, "cell_size not finite");
     if (!std::isfinite(p->cfl)) return fail(CSPH_EINVAL, "cfl not finite");
     if (p->wall && (!std::isfinite(p->wall_x0) || !std::isfinite(p->wall_v)))
@@ -250,7 +252,18 @@ static GridDev grid_dev(const csph_grid &g, bool slab = true) {
         d.sZr = d.sZf;
         d.sY = 0;
     }
+    d.morton = 0;
+    d.nkey = (int64_t)d.dx * d.dy * d.dz;
     return d;
+}
+
+// Bits per axis of the Morton key space of a mesh: ceil(log2(max dims)).
+static int morton_bits(const int32_t dims[3]) {
+    int m = dims[0] > dims[1] ? dims[0] : dims[1];
+    m = m > dims[2] ? m : dims[2];
+    int b = 0;
+    while ((1 << b) < m) ++b;
+    return b;
 }
 
 // Mesh from device bounds (synchronises `st`); also returns max d.
@@ -289,6 +302,14 @@ static csph_status make_grid(const double *x, const double *y, const double *z, 
     g->reach = r < 1.0 ? 1 : (int32_t)r;
     if (g->reach > 64) return fail(CSPH_EINVAL, "cell size below 1/64 of the support");
     g->ncell = ncell;
+    g->key_mode = p->key_mode;
+    g->pad = 0;
+    g->nkey = ncell;
+    if (p->key_mode == CSPH_KEY_MORTON) {
+        if (g->dims[0] > 1024 || g->dims[1] > 1024 || g->dims[2] > 1024)
+            return fail(CSPH_EINVAL, "Morton keys need at most 1024 cells per axis");
+        g->nkey = (int64_t)1 << (3 * morton_bits(g->dims));
+    }
     return CSPH_OK;
 }
 
@@ -296,6 +317,17 @@ static csph_status need_ws(size_t have, int64_t n, int64_t ncell, size_t *ws_nee
     size_t need = ws_layout(nullptr, nullptr, n, ncell);
     if (ws_needed) *ws_needed = need;
     if (have < need) return fail(CSPH_ECAPACITY, "workspace needs %zu bytes, got %zu", need, have);
+    return CSPH_OK;
+}
+
+// The call's own non-physical count (counted into the workspace counter): added to the
+// caller's counter, brought to the host (synchronises), CSPH_ENONPHYS when not 0.
+static csph_status finish_nonphys(const Ws &w, int64_t *nonphys, hipStream_t st) {
+    if (nonphys) CSPH_HIP(launch_add_i64(nonphys, w.nonphys, st));
+    int64_t bad = 0;
+    CSPH_HIP(hipMemcpyAsync(&bad, w.nonphys, sizeof(bad), hipMemcpyDeviceToHost, st));
+    CSPH_HIP(hipStreamSynchronize(st));
+    if (bad > 0) return fail(CSPH_ENONPHYS, "%lld particles in a non-physical state", (long long)bad);
     return CSPH_OK;
 }
 
@@ -311,6 +343,7 @@ const char *csph_status_string(csph_status s) {
         case CSPH_EINVAL: return "CSPH_EINVAL: invalid argument";
         case CSPH_ECAPACITY: return "CSPH_ECAPACITY: output or workspace too small";
         case CSPH_EDEVICE: return "CSPH_EDEVICE: HIP runtime error";
+        case CSPH_ENONPHYS: return "CSPH_ENONPHYS: non-physical state met (outputs written)";
         default: return "unknown csph status";
     }
 }
@@ -346,15 +379,27 @@ csph_status csph_bin(const double *x, const double *y, const double *z, int64_t 
         return fail(CSPH_EINVAL, "bad mesh");
     int64_t ncell = (int64_t)grid->dims[0] * grid->dims[1] * grid->dims[2];
     if (ncell != grid->ncell) return fail(CSPH_EINVAL, "grid->ncell does not match dims");
-    if (cell_start_cap < ncell + 1)
-        return fail(CSPH_ECAPACITY, "cell_start needs %lld entries", (long long)(ncell + 1));
-    csph_status s = need_ws(ws_bytes, n, ncell, ws_needed);
+    int64_t nkey = ncell;
+    if (grid->key_mode == CSPH_KEY_MORTON) {
+        if (grid->dims[0] > 1024 || grid->dims[1] > 1024 || grid->dims[2] > 1024)
+            return fail(CSPH_EINVAL, "Morton keys need at most 1024 cells per axis");
+        nkey = (int64_t)1 << (3 * morton_bits(grid->dims));
+    } else if (grid->key_mode != CSPH_KEY_LINEAR) {
+        return fail(CSPH_EINVAL, "grid->key_mode %d unknown", grid->key_mode);
+    }
+    if (nkey != grid->nkey) return fail(CSPH_EINVAL, "grid->nkey does not match dims and key_mode");
+    if (cell_start_cap < nkey + 1)
+        return fail(CSPH_ECAPACITY, "cell_start needs %lld entries", (long long)(nkey + 1));
+    csph_status s = need_ws(ws_bytes, n, nkey, ws_needed);
     if (s) return s;
     Ws w;
-    ws_layout(&w, ws, n, ncell);
+    ws_layout(&w, ws, n, nkey);
     hipStream_t st = (hipStream_t)stream;
     ProfScope pb(CSPH_PROF_BIN, st);
-    CSPH_HIP(launch_bin(x, y, z, n, grid_dev(*grid, false), w, perm, key, cell_start, st));
+    GridDev gd = grid_dev(*grid, false);
+    gd.morton = grid->key_mode == CSPH_KEY_MORTON;
+    gd.nkey = nkey;
+    CSPH_HIP(launch_bin(x, y, z, n, gd, w, perm, key, cell_start, st));
     return CSPH_OK;
 }
 
@@ -433,10 +478,11 @@ csph_status csph_rates(const csph_state *s, const csph_params *p, double t, csph
         CSPH_HIP(launch_bin(sv.x, sv.y, sv.z, n, gd, w, w.perm, nullptr, w.cs, st));
     }
     CSPH_HIP(launch_fill_u64(w.dtmin, 0x7ff0000000000000ull, 2, st));  // dt min, Z flag
+    CSPH_HIP(launch_fill_u64((unsigned long long *)w.nonphys, 0ull, 1, st));
     {
         ProfScope pr(CSPH_PROF_PACK, st);
         CSPH_HIP(launch_pack(sv, n, w.perm, eos, mixed, gd, w, w.srt, w.srt_mat,
-                             pair ? w.srt_d : nullptr, nullptr, nullptr, nonphys, st));
+                             pair ? w.srt_d : nullptr, nullptr, nullptr, w.nonphys, st));
     }
     {
         ProfScope pr(CSPH_PROF_RATES, st);
@@ -447,7 +493,7 @@ csph_status csph_rates(const csph_state *s, const csph_params *p, double t, csph
         ProfScope pr(CSPH_PROF_REORDER, st);
         CSPH_HIP(launch_unsort_rates(n, w.perm, w, ov, signal, nbr_count, st));
     }
-    return CSPH_OK;
+    return finish_nonphys(w, nonphys, st);
 }
 
 csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_params *p, double *t,
@@ -462,6 +508,7 @@ csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_para
     if (r) return r;
     if (!(p->cfl > 0.0) && !(std::isfinite(dt_in) && dt_in >= 0.0))
         return fail(CSPH_EINVAL, "cfl <= 0 needs a finite dt_in >= 0");
+    if (p->wall && !t) return fail(CSPH_EINVAL, "the wall position needs t");
     if ((s_in->mat && !s_out->mat) || (s_in->id && !s_out->id) ||
         (p->h_mode == CSPH_H_PAIR && !s_out->d))
         return fail(CSPH_EINVAL, "s_out must carry mat/id/d when s_in does");
@@ -504,6 +551,9 @@ csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_para
     }
     // dt = cfl * min h/s (an empty set takes dt = 0); the pack clears the Z flag
     CSPH_HIP(launch_fill_u64(w.dtmin, n > 0 ? 0x7ff0000000000000ull : 0ull, 2, st));
+    // checked: the pack counts into the workspace, read back at the end
+    const bool check = p->check_nonphys != 0;
+    if (check) CSPH_HIP(launch_fill_u64((unsigned long long *)w.nonphys, 0ull, 1, st));
     if (n > 0) {
         {
             ProfScope pr(CSPH_PROF_BIN, st);
@@ -511,7 +561,7 @@ csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_para
         }
         ProfScope pr(CSPH_PROF_PACK, st);
         CSPH_HIP(launch_pack(vin, n, w.perm, eos, mixed, gd, w, dst, dmat, dd, did, vin.id,
-                             nonphys, st));
+                             check ? w.nonphys : nonphys, st));
     }
     if (n > 0) {
         ProfScope pr(CSPH_PROF_RATES, st);
@@ -519,7 +569,8 @@ csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_para
     }
     {
         ProfScope pr(CSPH_PROF_INTEGRATE, st);
-        CSPH_HIP(launch_integrate(n, dst, w, p->cfl, dt_in, st));  // n = 0 writes zero partials
+        // n = 0 writes zero partials
+        CSPH_HIP(launch_integrate(n, dst, w, p->cfl, dt_in, pc, t, st));
         CSPH_HIP(launch_finish_step(n, w, p->cfl, dt_in, t, dt_used, totals, p->wall, st));
     }
     ProfScope pro(CSPH_PROF_REORDER, st);
@@ -535,7 +586,8 @@ csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_para
                                       did, w.cnt, o, nbr_count, st));
         }
     }
-    return CSPH_OK;
+    pro.stop();
+    return check ? finish_nonphys(w, nonphys, st) : CSPH_OK;
 }
 
 csph_status csph_vlist_build(const csph_state *s_in, csph_state *s_out, const csph_params *p,
@@ -626,6 +678,7 @@ csph_status csph_step_vlist(csph_state *s, const csph_params *p, double *t, doub
     if (p->h_mode != CSPH_H_FIXED) return fail(CSPH_EINVAL, "Verlet lists need fixed-h mode");
     if (!(p->cfl > 0.0) && !(std::isfinite(dt_in) && dt_in >= 0.0))
         return fail(CSPH_EINVAL, "cfl <= 0 needs a finite dt_in >= 0");
+    if (p->wall && !t) return fail(CSPH_EINVAL, "the wall position needs t");
     const int64_t n = s->n;
     if (n > 0 && (!vl_count || !vl_idx || !x_ref || cap < kVlChunk || cap % kVlChunk))
         return fail(CSPH_EINVAL, "vl_count, vl_idx, x_ref and cap (a multiple of %d) are required",
@@ -656,7 +709,7 @@ csph_status csph_step_vlist(csph_state *s, const csph_params *p, double *t, doub
     }
     {
         ProfScope pr(CSPH_PROF_INTEGRATE, st);
-        CSPH_HIP(launch_integrate(n, cur, w, p->cfl, dt_in, st));
+        CSPH_HIP(launch_integrate(n, cur, w, p->cfl, dt_in, pc, t, st));
         CSPH_HIP(launch_finish_step(n, w, p->cfl, dt_in, t, dt_used, totals, p->wall, st));
         if (disp) {
             CSPH_HIP(launch_fill_u64((unsigned long long *)disp, 0ull, 1, st));

@@ -34,7 +34,23 @@ struct GridDev {
     // cell order (cell_key): y-slabs of 2^ysh rows, z, then y in slab, then x
     int ysh, ymask, nfull;      // slab shift and mask; number of full slabs
     uint32_t sY, sZf, sZr;      // slab stride; z stride in a full / the last slab
+    int morton;                 // binning keys: 1 = Morton (csph_bin's export only)
+    int64_t nkey;               // key space of the binning (cells, or 2^(3 bits) for Morton)
 };
+
+// Morton key: bit b of cx, cy, cz at key bits 3b, 3b+1, 3b+2 (10 bits each).  Each
+// coordinate's bits are spread to every third position by shifts and masks.
+__host__ __device__ __forceinline__ uint32_t spread3(uint32_t v) {
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+__host__ __device__ __forceinline__ uint32_t morton_key(int cx, int cy, int cz) {
+    return spread3((uint32_t)cx) | (spread3((uint32_t)cy) << 1) | (spread3((uint32_t)cz) << 2);
+}
 
 // Key of cell (cx, cy, cz).  The mesh is cut along y into slabs of 2^ysh
 // rows (the last one may be shorter); slabs come one after another, and in a
@@ -221,8 +237,11 @@ hipError_t launch_unsort_rates(int64_t n, const int32_t *perm, const Ws &w, csph
 
 // k_step.hip
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t count, hipStream_t st);
+hipError_t launch_add_i64(int64_t *dst, const int64_t *src, hipStream_t st);  // *dst += *src
+// With pc.wall (and t, the device time at the step's start), particles behind the piston
+// plane at the new time are reflected off it.
 hipError_t launch_integrate(int64_t n, double *const st8[9], const Ws &w, double cfl, double dt_in,
-                            hipStream_t st);
+                            const PairConst &pc, const double *t, hipStream_t st);
 hipError_t launch_finish_step(int64_t n, const Ws &w, double cfl, double dt_in, double *t, double *dt_used,
                               double *totals, int swap_xy, hipStream_t st);
 hipError_t launch_unpermute(int64_t n, const int32_t *perm, double *const src[9],

@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_keys(const double *__restrict__ x,
     int cx = cell_coord(x[i], g.ox, g.inv, g.dx);
     int cy = cell_coord(y[i], g.oy, g.inv, g.dy);
     int cz = cell_coord(z[i], g.oz, g.inv, g.dz);
-    uint32_t k = cell_key(g, cx, cy, cz);
+    uint32_t k = g.morton ? morton_key(cx, cy, cz) : cell_key(g, cx, cy, cz);
     key[i] = k;
     rank[i] = (uint32_t)atomicAdd(&count[k], 1);
     if (key_out) key_out[i] = k;
@@ -270,7 +270,7 @@ static unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBl
 hipError_t launch_bin(const double *x, const double *y, const double *z, int64_t n,
                       const GridDev &g, const Ws &w, int32_t *perm, uint32_t *key_out,
                       int32_t *cell_start, hipStream_t st) {
-    int64_t ncell = (int64_t)g.dx * g.dy * g.dz;
+    const int64_t ncell = g.nkey;  // keys (cells, or the Morton key space)
     unsigned fb = blocks_for(ncell + 1);
     k_fill_i32<<<fb > 65535u ? 65535u : fb, kBlock, 0, st>>>(cell_start, 0, ncell + 1);
     if (n > 0)

@@ -512,6 +512,14 @@ __device__ __forceinline__ void pair32(bool use, float dx, float dy, float dz, f
 // is below 1e-6 relative for offsets within a few cells).
 constexpr float kBand = 4e-5f;
 
+// The exact FP64 membership test of a pair from its FP64 offsets, rounded as written (a
+// product, a product, a sum, a product, a sum): this function lies outside the
+// fast-contraction scope of the FP32 pair step, so none of it becomes a fused multiply-add
+// when it is inlined there.
+__device__ __forceinline__ bool member64(double ex, double ey, double ez, double H2) {
+    return ((ex * ex) + (ey * ey)) + (ez * ez) < H2;
+}
+
 template <bool PAIR, bool WALL, bool LIST>
 struct Rates32 {
     const float4 *__restrict__ A;
@@ -581,7 +589,7 @@ struct Rates32 {
         if (!LIST && has && (!(r2 < H2lo) || r2 < H2lo * 1e-4f)) {
             const double yj = ghost ? 2.0 * yw - ys[j] : ys[j];
             const double ex = xs[j] - xi, ey = yj - yi, ez = zs[j] - zi;
-            in = ((ex * ex) + (ey * ey)) + (ez * ez) < H2d;
+            in = member64(ex, ey, ez, H2d);
             qx = (float)ex;
             qy = (float)ey;
             qz = (float)ez;

@@ -46,6 +46,13 @@ hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t 
     return hipGetLastError();
 }
 
+__global__ void k_add_i64(int64_t *dst, const int64_t *src) { *dst += *src; }
+
+hipError_t launch_add_i64(int64_t *dst, const int64_t *src, hipStream_t st) {
+    k_add_i64<<<1, 1, 0, st>>>(dst, src);
+    return hipGetLastError();
+}
+
 __device__ __forceinline__ double step_dt(const unsigned long long *dtmin, double cfl,
                                           double dt_in) {
     return cfl > 0.0 ? cfl * __longlong_as_double((long long)*dtmin) : dt_in;
@@ -59,11 +66,23 @@ struct Rates5 {
     const double *f[5];
 };
 
-// Update in place (cell order) and accumulate block partial totals.
+// Update in place (cell order) and accumulate block partial totals.  With the piston
+// (a rigid wall that stops the particles, sec. 7.1), a particle whose new position lies
+// behind the plane at the new time is reflected off it in the wall's frame: position and
+// normal velocity mirrored, specific internal energy kept.  The wall is normal to the
+// state's y array (the kernels' axes; see PairConst).
+struct WallDev {
+    int on;
+    double y0, v;
+    const double *t;  // time at the start of the step (device)
+};
+
 __global__ __launch_bounds__(kBlock) void k_integrate(int64_t n, State9 s, Rates5 r,
                                                       const unsigned long long *dtmin, double cfl,
-                                                      double dt_in, double *__restrict__ part) {
+                                                      double dt_in, WallDev wall,
+                                                      double *__restrict__ part) {
     double dt = step_dt(dtmin, cfl, dt_in);
+    const double yw = wall.on ? wall.y0 + wall.v * (*wall.t + dt) : 0.0;
     DD acc[5];
     for (int k = 0; k < 5; ++k) acc[k] = DD{0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
@@ -73,8 +92,15 @@ __global__ __launch_bounds__(kBlock) void k_integrate(int64_t n, State9 s, Rates
         double vz = s.f[5][i] + dt * r.f[3][i];
         double E = s.f[7][i] + dt * r.f[4][i];
         double rho = s.f[6][i] + dt * r.f[0][i];
+        double y = s.f[1][i] + dt * vy;
+        if (wall.on && y < yw) {
+            const double vr = 2.0 * wall.v - vy;
+            E = E + 0.5 * ((vr * vr) - (vy * vy));
+            vy = vr;
+            y = 2.0 * yw - y;
+        }
         s.f[0][i] = s.f[0][i] + dt * vx;
-        s.f[1][i] = s.f[1][i] + dt * vy;
+        s.f[1][i] = y;
         s.f[2][i] = s.f[2][i] + dt * vz;
         s.f[3][i] = vx;
         s.f[4][i] = vy;
@@ -118,12 +144,13 @@ static int integrate_blocks(int64_t n) {
 }
 
 hipError_t launch_integrate(int64_t n, double *const st8[9], const Ws &w, double cfl, double dt_in,
-                            hipStream_t st) {
+                            const PairConst &pc, const double *t, hipStream_t st) {
     State9 s;
     for (int k = 0; k < 9; ++k) s.f[k] = st8[k];
     Rates5 r{{w.rate[0], w.rate[1], w.rate[2], w.rate[3], w.rate[4]}};
+    WallDev wall{pc.wall && t ? 1 : 0, pc.wall_y0, pc.wall_v, t};
     int nb = integrate_blocks(n);
-    k_integrate<<<nb, kBlock, 0, st>>>(n, s, r, w.dtmin, cfl, dt_in, w.tot_part);
+    k_integrate<<<nb, kBlock, 0, st>>>(n, s, r, w.dtmin, cfl, dt_in, wall, w.tot_part);
     return hipGetLastError();
 }
 

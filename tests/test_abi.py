@@ -33,8 +33,9 @@ def test_library_exports_every_declared_function():
 
 def test_status_strings_and_version():
     L = N.load()
-    for s in (0, 1, 2, 3):
+    for s in (0, 1, 2, 3, 4):
         assert L.csph_status_string(s).decode().startswith("CSPH_")
+    assert b"ENONPHYS" in L.csph_status_string(N.CSPH_ENONPHYS)
     assert P.version().startswith("csph-gfx950")
 
 
@@ -118,3 +119,51 @@ def test_vlist_build_rejects_misaligned_list_storage():
                             dev(262144, C.c_double), None, None, 0, None, None)
     assert st == N.CSPH_EINVAL
     assert b"16-byte aligned" in L.csph_last_error()
+
+
+def _fake_state(base, n=100):
+    s = N.CsphState()
+    s.n = n
+    for k, f in enumerate(("x", "y", "z", "vx", "vy", "vz", "rho", "E", "m")):
+        setattr(s, f, C.cast(C.c_void_p(base + 1024 * k), C.POINTER(C.c_double)))
+    return s
+
+
+def test_wall_steps_need_the_time():
+    """With the piston wall the step places the plane at t: a NULL t is refused on the host,
+    before any device work, by the per-step search and by the Verlet-list step."""
+    L = N.load()
+    p = P.Params(wall=(0.0, 2.0)).c()
+    a, b = _fake_state(4096), _fake_state(65536)
+    st = L.csph_step(C.byref(a), C.byref(b), C.byref(p), None, 0.0, None, None, None, None,
+                     None, 0, None, None)
+    assert st == N.CSPH_EINVAL and b"needs t" in L.csph_last_error()
+    dev = lambda addr, t: C.cast(C.c_void_p(addr), C.POINTER(t))
+    st = L.csph_step_vlist(C.byref(a), C.byref(p), None, 0.0, None, None, None, None,
+                           dev(1 << 20, C.c_int32), dev(1 << 21, C.c_int32), 64,
+                           dev(1 << 22, C.c_double), None, None, 0, None, None)
+    assert st == N.CSPH_EINVAL and b"needs t" in L.csph_last_error()
+
+
+def test_key_mode_checked():
+    L = N.load()
+    p = P.Params().c()
+    p.key_mode = 7
+    st = L.csph_init_energy(None, None, None, None, None, None, 0, C.byref(p), None, None)
+    assert st == N.CSPH_EINVAL and b"key_mode" in L.csph_last_error()
+    # a grid whose key space does not match its dims and key mode
+    g = N.CsphGrid()
+    g.inv_cell, g.cell = 1.0, 1.0
+    g.dims[0], g.dims[1], g.dims[2] = 5, 3, 2
+    g.ncell = 30
+    g.key_mode = N.CSPH_KEY_MORTON
+    g.nkey = 30  # the Morton key space of 5 x 3 x 2 cells is 2^(3*3) = 512
+    dev = lambda addr, t: C.cast(C.c_void_p(addr), C.POINTER(t))
+    x = dev(4096, C.c_double)
+    st = L.csph_bin(x, x, x, 10, C.byref(g), None, dev(8192, C.c_int32),
+                    dev(16384, C.c_int32), 1000, None, 0, None, None)
+    assert st == N.CSPH_EINVAL and b"nkey" in L.csph_last_error()
+    g.nkey = 512
+    st = L.csph_bin(x, x, x, 10, C.byref(g), None, dev(8192, C.c_int32),
+                    dev(16384, C.c_int32), 100, None, 0, None, None)
+    assert st == N.CSPH_ECAPACITY and b"513" in L.csph_last_error()

@@ -140,6 +140,26 @@ def test_bin_bitexact(case):
         _bin_case(w.x, w.y, w.z, D)
 
 
+@pytest.mark.parametrize("case", ["sod16", "slab", "ragged"])
+def test_bin_morton_bitexact(case):
+    """Morton keys (bits of the cell triple interleaved): keys, the stable order by
+    (key, index) and the ranges over the 2^(3 bits) key space, bit-exact."""
+    w = CASES[case]()
+    _print_case(f"morton {case}", w)
+    for D in (3.0, 0.7):
+        params = P.Params(cell_size=D, key_mode="morton")
+        tx, ty, tz = [torch.as_tensor(a, dtype=torch.float64, device=DEV) for a in (w.x, w.y, w.z)]
+        g = P.csph_grid_build(tx, ty, tz, params)
+        assert g.key_mode == 1
+        key, perm, cs = P.csph_bin(tx, ty, tz, g)
+        torch.cuda.synchronize()
+        ref = O.bin(w.x, w.y, w.z, D, key_mode=1)
+        assert g.nkey == ref["ncell"] and g.ncell == int(np.prod(ref["dims"]))
+        assert np.array_equal(to_np(key), ref["key"])
+        assert np.array_equal(to_np(perm).astype(np.int64), ref["perm"])
+        assert np.array_equal(to_np(cs).astype(np.int64), ref["cell_start"])
+
+
 def test_bin_points_on_faces():
     rng = np.random.default_rng(5)
     D = 0.75
@@ -299,6 +319,55 @@ def test_rates_few_particles(n, prec, tol):
     assert ref["nbr_count"].tolist() == [n - 1] * n
 
 
+def boundary_lattice():
+    """Unjittered 10^3 lattice of spacing 0.1 (not a power of two) with support 0.3, three
+    spacings: thousands of pairs have r^2 within a few ulp of H^2, on both sides of it, and
+    for some of them a fused multiply-add in r^2 would flip the membership.  Random
+    velocities and pressures make every pair's contribution and closing speed distinct."""
+    w = ci.jittered_block(10, 10, 10, seed=0, amp=0.0)
+    rng = np.random.default_rng(23)
+    w.x, w.y, w.z = (0.1 * c for c in (w.x, w.y, w.z))
+    w.vx, w.vy, w.vz = (rng.uniform(-0.5, 0.5, w.n) for _ in range(3))
+    w.p = rng.uniform(0.5, 1.5, w.n)
+    w.m = w.rho * 1e-3
+    w.h, w.kappa, w.cell_size = 0.15, 2.0, 0.0
+    return w
+
+
+def _fused_membership_flips(w):
+    """Pairs whose r^2 < H^2 decision differs between the unfused FP64 sum and the fused
+    form fma(ez, ez, fma(ey, ey, ex*ex)), in exact rational arithmetic."""
+    from fractions import Fraction as F
+    P3 = np.stack([w.x, w.y, w.z], 1)
+    H = w.kappa * w.h
+    H2 = H * H
+    flips = 0
+    for i in range(w.n):
+        d = P3 - P3[i]
+        r2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        for j in np.nonzero(np.abs(r2 - H2) < 8 * np.spacing(H2))[0]:
+            ex, ey, ez = (F(v) for v in d[j])
+            fused = float(F(float(ex * ex + F(float(ey * ey)))) + ez * ez)
+            flips += (fused < H2) != (r2[j] < H2)
+    return flips
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_rates_pairs_on_the_support(prec):
+    """Neighbour sets, counts and signal speeds where pairs sit on the support to the last
+    bits: both kernels decide membership from the unfused FP64 r^2, as the oracle does."""
+    w = boundary_lattice()
+    _print_case(f"support-boundary lattice {prec}", w)
+    assert _fused_membership_flips(w) > 0
+    got, ref = _rates_case(w, prec)
+    assert np.array_equal(got["nbr_count"].astype(np.int64), ref["nbr_count"])
+    assert 30 < ref["nbr_count"].max() < 123
+    err = field_relerr(got, ref)
+    tol, stol = (FP64_TOL, 1e-13) if prec == "fp64" else (MIXED_TOL, 1e-5)
+    assert max(err.values()) <= tol, err
+    assert np.abs(got["signal"] - ref["signal"]).max() <= stol * ref["signal"].max()
+
+
 def test_rates_isolated_and_coincident():
     w = ci.random_cloud(4, seed=3, box=1.0)
     w.x[:] = [0.0, 0.0, 50.0, 100.0]
@@ -321,6 +390,23 @@ def test_nonphysical_counted():
     out = P.csph_rates(g, params)
     ref = O.rates(O.cfg_for(w, search=1), ref_state(w))
     assert int(out["nonphys"][0]) == ref["nonphys"] == 10
+    assert out["status"] == P.CSPH_ENONPHYS
+    # the rates are still written (c = 0 for the non-physical particles)
+    err = field_relerr(rates_np(out), ref)
+    assert max(err.values()) <= FP64_TOL, err
+    # a checked step waits and raises, with the step complete; an unchecked one only counts
+    sc = P.StepScalars(DEV)
+    P.csph_step(g, params, sc)
+    torch.cuda.synchronize()
+    assert int(sc.nonphys[0]) == 10
+    checked = P.Params.from_workload(w, check_nonphys=True)
+    sc2 = P.StepScalars(DEV)
+    with pytest.raises(P.NonPhysicalState):
+        P.csph_step(gpu_state(w, checked), checked, sc2)
+    assert int(sc2.nonphys[0]) == 10 and float(sc2.t[0]) > 0.0
+    ok = ci.random_cloud(200, seed=5, box=4.0)
+    P.csph_step(gpu_state(ok, checked), P.Params.from_workload(ok, check_nonphys=True),
+                P.StepScalars(DEV))
 
 
 def test_rates_deterministic():
@@ -378,6 +464,37 @@ def test_step_fp64(case, reorder):
     assert np.array_equal(to_np(cnt).astype(np.int64), ncount[ids])
     # the totals are compensated sums over the GPU's own new state
     _check_totals(to_np(sc.totals), got)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_piston_stops_particles_over_steps(prec):
+    """Porous 24^3 sample with the piston at v = 2 and the recipe's impulsive start: over 12
+    CFL steps no particle ever lies behind the piston (the rigid wall of sec. 7.1 reflects
+    the particles that reach it), and the FP64 run follows the oracle's steps."""
+    w = ci.config2(nside=24)
+    _print_case(f"porous24 piston {prec}", w)
+    params = P.Params.from_workload(w, precision=prec, reorder=True)
+    g = gpu_state(w, params)
+    other = g.like()
+    sc = P.StepScalars(DEV)
+    cfg = O.cfg_for(w, search=1)
+    s_ref = ref_state(w)
+    t_ref = 0.0
+    x0, vw = w.wall
+    for k in range(12):
+        g, other = P.csph_step(g, params, sc, s_out=other), g
+        t = float(to_np(sc.t)[0])
+        assert float(g["x"].min()) >= x0 + vw * t, (k, t)
+        if prec == "fp64":
+            s_ref, t_ref, _, _ = O.step(cfg, s_ref, t_ref)
+    assert int(to_np(sc.nonphys)[0]) == 0
+    if prec == "fp64":
+        assert abs(t - t_ref) <= 1e-13 * t_ref
+        got = g.numpy()
+        ids = got["id"]
+        for k in ("x", "y", "z", "vx", "vy", "vz", "rho", "E"):
+            b = s_ref[k][ids]
+            assert np.abs(got[k] - b).max() <= 1e-11 * (1.0 + np.abs(b).max()), k
 
 
 def test_step_mixed_rates_within_tolerance():
