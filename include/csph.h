@@ -256,6 +256,21 @@ csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_para
                       int32_t *nbr_count, int64_t *nonphys, void *ws, size_t ws_bytes,
                       size_t *ws_needed, csph_stream stream);
 
+/* csph_step for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same step, same kernels and
+ * results, with its workspace in a library-owned device array of 128 MiB per GPU
+ * (enough for about 450 000 particles on a compact mesh) instead of a caller workspace.
+ * The array is held on each GPU the library runs on until the process ends; the call
+ * allocates nothing (no hipMalloc, no timing events: csph_profile_* does not see it).
+ * The caller still passes the state, t and the outputs.  A step whose workspace exceeds
+ * the array returns CSPH_ECAPACITY (the per-particle part is checked before any device
+ * work, the mesh part after the bounds synchronisation), writing nothing.  Every call on
+ * one GPU uses that GPU's one array: calls that overlap in time on one GPU (different
+ * streams or host threads) race and must not be issued.  Synchronises as csph_step. */
+csph_status csph_step_static(const csph_state *s_in, csph_state *s_out, const csph_params *p,
+                             double *t, double dt_in, double *dt_used, double *totals,
+                             int32_t *nbr_count, int64_t *nonphys, csph_stream stream);
+
 /* Voronoi ownership (eq. VoronoiDefinition): owner[i] = the k minimising
  * ((x_i-g_kx)^2 + (y_i-g_ky)^2) + (z_i-g_kz)^2 in FP64 without contraction,
  * a tie going to the smaller k (sec. 3.1).  sites: K x 3 FP64, global

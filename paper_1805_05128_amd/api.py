@@ -327,6 +327,22 @@ def csph_step(s_in: State, params: Params, sc: StepScalars, s_out: Optional[Stat
     return s_out
 
 
+def csph_step_static(s_in: State, params: Params, sc: StepScalars, s_out: State,
+                     dt_in: float = 0.0, nbr_count: Optional[torch.Tensor] = None,
+                     stream=None, totals: bool = True) -> State:
+    """csph_step with the library's own static scratch instead of a caller workspace: the
+    library call allocates nothing (for callers that cannot allocate).  s_out must be given;
+    it may be s_in itself when params.reorder is False."""
+    L = N.load()
+    a, b_ = s_in.c(), s_out.c()
+    p = params.c()
+    st = L.csph_step_static(C.byref(a), C.byref(b_), C.byref(p), _dp(sc.t), float(dt_in),
+                            _dp(sc.dt), _dp(sc.totals) if totals else None, _ip(nbr_count),
+                            _lp(sc.nonphys), _stream(stream))
+    N.check(st, "csph_step_static")
+    return s_out
+
+
 def voronoi_assign(x, y, z, sites: torch.Tensor, nbr_count: Optional[torch.Tensor] = None,
                    owner: Optional[torch.Tensor] = None, stream=None,
                    site_particles: Optional[torch.Tensor] = None,

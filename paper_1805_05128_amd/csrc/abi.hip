@@ -58,7 +58,9 @@ struct ProfScope {
     int group;
     hipStream_t st;
     hipEvent_t a = nullptr;
-    ProfScope(int g, hipStream_t s) : group(g), st(s) {
+    // on = false: no event (the entry point that allocates nothing never creates events)
+    ProfScope(int g, hipStream_t s, bool on = true) : group(g), st(s) {
+        if (!on) return;
         std::lock_guard<std::mutex> lk(g_prof_mu);
         if (!g_prof_on) return;
         a = prof_event();
@@ -331,6 +333,42 @@ static csph_status finish_nonphys(const Ws &w, int64_t *nonphys, hipStream_t st)
     return CSPH_OK;
 }
 
+// ---------------------------------------------------------------- static scratch
+//
+// The workspace of csph_step_static, the entry point for callers that cannot allocate device
+// memory: one array per GPU the library runs on, held from the code object's load until the
+// process ends.  In host code the array's name is only a stand-in for the device symbol, so
+// its device address is looked up once per device, with that device current, and that
+// address is what the kernels receive.
+constexpr size_t kStaticScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch[kMaxDevices];
+
+static csph_status static_scratch(void **out) {
+    int dev = 0;
+    CSPH_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(CSPH_EDEVICE, "device %d: the static scratch serves devices 0..%d", dev,
+                    kMaxDevices - 1);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        CSPH_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(CSPH_EDEVICE, "no device address for the static scratch");
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return CSPH_OK;
+}
+
+// The body of csph_step and csph_step_static (prof = false: no timing events).
+static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const csph_params *p,
+                             double *t, double dt_in, double *dt_used, double *totals,
+                             int32_t *nbr_count, int64_t *nonphys, void *ws, size_t ws_bytes,
+                             size_t *ws_needed, hipStream_t st, bool prof);
+
 }  // namespace csph
 
 using namespace csph;
@@ -501,6 +539,43 @@ csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_para
                       int64_t *nonphys, void *ws, size_t ws_bytes, size_t *ws_needed,
                       csph_stream stream) {
     g_err[0] = 0;
+    return step_impl(s_in, s_out, p, t, dt_in, dt_used, totals, nbr_count, nonphys, ws,
+                     ws_bytes, ws_needed, (hipStream_t)stream, true);
+}
+
+csph_status csph_step_static(const csph_state *s_in, csph_state *s_out, const csph_params *p,
+                             double *t, double dt_in, double *dt_used, double *totals,
+                             int32_t *nbr_count, int64_t *nonphys, csph_stream stream) {
+    g_err[0] = 0;
+    void *ws = nullptr;
+    csph_status r = static_scratch(&ws);
+    if (r) return r;
+    // sizes beyond the scratch are refused before any device work when the per-particle
+    // part alone does not fit; the mesh part is checked once the mesh is known
+    const int64_t n = s_in ? s_in->n : 0;
+    if (n > 0 && ws_layout(nullptr, nullptr, n, 1) > kStaticScratchBytes)
+        return fail(CSPH_ECAPACITY,
+                    "csph_step_static: %lld particles need %zu bytes of scratch, more than its "
+                    "%zu bytes", (long long)n, ws_layout(nullptr, nullptr, n, 1),
+                    kStaticScratchBytes);
+    size_t need = 0;
+    r = step_impl(s_in, s_out, p, t, dt_in, dt_used, totals, nbr_count, nonphys, ws,
+                  kStaticScratchBytes, &need, (hipStream_t)stream, false);
+    if (r == CSPH_ECAPACITY)
+        return fail(CSPH_ECAPACITY,
+                    "csph_step_static: this step needs %zu bytes of scratch, more than its %zu "
+                    "bytes", need, kStaticScratchBytes);
+    return r;
+}
+
+}  // extern "C"
+
+namespace csph {
+
+static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const csph_params *p,
+                             double *t, double dt_in, double *dt_used, double *totals,
+                             int32_t *nbr_count, int64_t *nonphys, void *ws, size_t ws_bytes,
+                             size_t *ws_needed, hipStream_t st, bool prof) {
     if (!state_ok(s_in) || !state_ok(s_out) || s_in->n != s_out->n || s_in->n >= INT32_MAX)
         return fail(CSPH_EINVAL, "bad state");
     if (s_in->n >= kMaxPairN) return fail(CSPH_EINVAL, "n >= 2^27 particles");
@@ -516,7 +591,6 @@ csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_para
         (s_in->x == s_out->x || s_in->vx == s_out->vx || s_in->rho == s_out->rho ||
          s_in->E == s_out->E || s_in->m == s_out->m))
         return fail(CSPH_EINVAL, "reorder = 1 needs s_out distinct from s_in");
-    hipStream_t st = (hipStream_t)stream;
     int64_t n = s_in->n;
     const csph_state vin = kernel_view(*s_in, p->wall), vout = kernel_view(*s_out, p->wall);
     csph_grid g;
@@ -556,24 +630,24 @@ csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_para
     if (check) CSPH_HIP(launch_fill_u64((unsigned long long *)w.nonphys, 0ull, 1, st));
     if (n > 0) {
         {
-            ProfScope pr(CSPH_PROF_BIN, st);
+            ProfScope pr(CSPH_PROF_BIN, st, prof);
             CSPH_HIP(launch_bin(vin.x, vin.y, vin.z, n, gd, w, w.perm, nullptr, w.cs, st));
         }
-        ProfScope pr(CSPH_PROF_PACK, st);
+        ProfScope pr(CSPH_PROF_PACK, st, prof);
         CSPH_HIP(launch_pack(vin, n, w.perm, eos, mixed, gd, w, dst, dmat, dd, did, vin.id,
                              check ? w.nonphys : nonphys, st));
     }
     if (n > 0) {
-        ProfScope pr(CSPH_PROF_RATES, st);
+        ProfScope pr(CSPH_PROF_RATES, st, prof);
         CSPH_HIP(launch_rates(n, mixed, gd, pc, w, dst, dd, t, 0.0, p->cfl > 0.0, st));
     }
     {
-        ProfScope pr(CSPH_PROF_INTEGRATE, st);
+        ProfScope pr(CSPH_PROF_INTEGRATE, st, prof);
         // n = 0 writes zero partials
         CSPH_HIP(launch_integrate(n, dst, w, p->cfl, dt_in, pc, t, st));
         CSPH_HIP(launch_finish_step(n, w, p->cfl, dt_in, t, dt_used, totals, p->wall, st));
     }
-    ProfScope pro(CSPH_PROF_REORDER, st);
+    ProfScope pro(CSPH_PROF_REORDER, st, prof);
     if (n > 0) {
         if (p->reorder) {
             if (nbr_count)
@@ -589,6 +663,11 @@ csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_para
     pro.stop();
     return check ? finish_nonphys(w, nonphys, st) : CSPH_OK;
 }
+
+}  // namespace csph
+
+extern "C" {
+
 
 csph_status csph_vlist_build(const csph_state *s_in, csph_state *s_out, const csph_params *p,
                              const double *t, double beta, int32_t cap, int32_t *vl_count,
