@@ -79,6 +79,8 @@ def parse():
                     help="mesh cell size in lattice spacings (results do not depend on it)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="first copy a buffer of this many GiB three times (counter calibration)")
+    ap.add_argument("--no-collision", dest="collision", action="store_false",
+                    help="skip the 64 M-particle collision leg")
     return ap.parse_args()
 
 
@@ -304,6 +306,93 @@ def verlet_timing(P, torch, w, cell, steps, beta=0.3, n_upd=10):
     return out
 
 
+def collision_run(P, torch, ci, steps=50, window=5):
+    """Heterogeneous collision (64 000 000 particles): ``steps`` mixed steps from the initial
+    state (after 3 warm-up steps on a throwaway copy), and the adjoint of the last ``window``
+    steps w.r.t. the velocities at their start (the FP64 window recomputed from one checkpoint;
+    objective: z-momentum of the dense body), as adjoint/forward wall-time ratio."""
+    t0 = time.perf_counter()
+    w = ci.config4()
+    log(f"collision: {w.n} particles ({time.perf_counter() - t0:.1f} s to generate)")
+    params = P.Params.from_workload(w, precision="mixed", reorder=True, cell_size=1.0)
+    fp64_window = P.Params.from_workload(w, precision="fp64", cell_size=1.0)
+    gamma = torch.tensor([e[1] for e in w.eos], dtype=torch.float64, device="cuda")
+    ws = P.Workspace("cuda")
+    cnt = torch.empty(w.n, dtype=torch.int32, device="cuda")
+    pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    warm = P.state_from_workload(w, params, "cuda", with_id=False)
+    other = warm.like()
+    sc = P.StepScalars("cuda")
+    for _ in range(3):
+        warm, other = P.csph_step(warm, params, sc, s_out=other, nbr_count=cnt, ws=ws), warm
+    torch.cuda.synchronize()
+    state = P.state_from_workload(w, params, "cuda", with_id=False)
+    n = w.n
+    del w, warm
+    sc = P.StepScalars("cuda")
+    ckpt = None
+    el = 0.0
+    with collector_off():
+        for seg in (steps - window, window):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(seg):
+                state, other = P.csph_step(state, params, sc, s_out=other, nbr_count=cnt,
+                                           ws=ws), state
+                pairs += cnt.sum()
+            torch.cuda.synchronize()
+            el += time.perf_counter() - t1
+            if ckpt is None:  # the window's start (outside the timed region)
+                ckpt = {k: state.t[k].clone() for k in ("x", "y", "z", "vx", "vy", "vz", "rho",
+                                                         "E", "m")}
+                ckpt["mat"] = state.mat.clone()
+    out = {"workload": f"collision_{n}", "particles": n, "steps": steps,
+           "ms_per_step": 1e3 * el / steps, "steps_per_s": steps / el,
+           "pairs_per_s": int(pairs.item()) / el, "pairs_per_step": int(pairs.item()) / steps,
+           "nonphys": int(sc.nonphys.item())}
+    del state, other, ws
+    torch.cuda.empty_cache()
+    base = {k: ckpt[k] for k in ("x", "y", "z", "rho", "E", "m", "mat")}
+    v0 = [ckpt[k].requires_grad_(True) for k in ("vx", "vy", "vz")]
+    body_a = base["mat"] == 1
+    info = {}
+    with collector_off():
+        res = P.rollout(*v0, gamma, base, fp64_window, window, window, info=info)
+        J = (res["vz"][body_a] * base["m"][body_a]).sum()
+        torch.autograd.grad(J, v0)
+        torch.cuda.synchronize()
+    out["adjoint_window"] = {"steps": window, "precision": "fp64", "checkpoints": 1,
+                             "forward_s": round(info["forward_s"], 5),
+                             "backward_s": round(info["backward_s"], 5),
+                             "ratio": info["backward_s"] / info["forward_s"]}
+    del res, J, v0, base, ckpt
+    torch.cuda.empty_cache()
+    return out
+
+
+# Algorithmic HBM bytes per particle of the memory-bound kernel groups of a step (what the
+# method must move through memory, not what an implementation happens to move):
+#   bin:       positions read once (24), the cell order written (4) and the cell ranges
+#              (4 per cell, added per particle from the mesh size);
+#   pack:      the state gathered (72 + mat 4 + id 8 + perm 4) and written in cell order
+#              (72 + 4 + 8) with the 48-byte FP32 pair record;
+#   integrate: state (72) and rates (40) read, the 64 evolving bytes written;
+#   voronoi:   positions (24) and the pair count (4) read, the owner (4) written.
+HBM_BYTES = {"bin": 28, "pack": 88 + 132, "integrate": 112 + 64, "voronoi": 32}
+
+
+def hbm_block(kernel_ms, n, ncell):
+    out = {}
+    for g, b in HBM_BYTES.items():
+        if g not in kernel_ms or kernel_ms[g] <= 0:
+            continue
+        per = b + (4.0 * ncell / n if g == "bin" else 0.0)
+        gbs = per * n / (kernel_ms[g] * 1e-3) / 1e9
+        out[g] = {"ms": kernel_ms[g], "alg_bytes_per_particle": round(per, 2),
+                  "achieved_GBps": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}
+    return out
+
+
 KERNEL_SOURCES = ("k_rates.hip", "stencil.h", "csph_internal.h")
 
 
@@ -459,9 +548,15 @@ def main():
             st = run.state
             cand_end = cell27_candidates(*(st[a].cpu().numpy() for a in ("x", "y", "z")), H)
             results["candidates"] = 0.5 * (cell27_candidates(w.x, w.y, w.z, H) + cand_end)
+            # cells of the step's mesh (unit cells on the final state's extent)
+            ext = [float(st[a].max() - st[a].min()) for a in ("x", "y", "z")]
+            results["ncell"] = int(np.prod([int(e / args.cell) + 2 for e in ext]))
+        st = run.state
+        t_end = float(sc.t.item())
+        behind = int((st["x"] < w.wall[0] + w.wall[1] * t_end).sum().item())
         results[prec] = dict(ms=1e3 * el / k, pairs_per_step=npairs / k, el=el, k=k, prof=prof,
-                             nonphys=int(sc.nonphys.item()), t=float(sc.t.item()),
-                             tot0=tot0, tot1=tot1)
+                             nonphys=int(sc.nonphys.item()), t=t_end,
+                             tot0=tot0, tot1=tot1, behind=behind)
         log(f"{prec}: {1e3 * el / k:.3f} ms/step, {npairs / el:.3e} pairs/s, "
             f"rates kernel {prof['rates'][1] / max(prof['rates'][0], 1):.3f} ms")
         del state, run
@@ -503,6 +598,16 @@ def main():
         "roofline": {"bound": "alu", "kernel": "k_rates32 (pair rates, FP32)",
                      "achieved": achieved, "peak": PEAK_LANE_TOPS, "unit": "T lane-op/s",
                      "frac": achieved / PEAK_LANE_TOPS,
+                     "achieved_is": "algorithmic-equivalent work (the method's 27-cell search "
+                                    "and pair arithmetic) / measured kernel time, not counted "
+                                    "instructions: the kernel tests fewer candidates (chord-"
+                                    "clipped rows) and issues more per pair",
+                     "kernel_ms_window": rates_avg_s * 1e3,
+                     "window": f"the {args.steps} timed steps (HIP events on the kernel's "
+                               "stream)",
+                     "hbm_view": {"alg_bytes": alg_bytes,
+                                  "achieved_GBps": alg_bytes / rates_avg_s / 1e9,
+                                  "frac": alg_bytes / rates_avg_s / 1e9 / PEAK_HBM_GBS},
                      "traffic": traffic["bytes"] if traffic else None,
                      "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE x2 + WRITE_SIZE)",
                      "algorithmic_bytes": alg_bytes,
@@ -515,6 +620,12 @@ def main():
                                     "frac": pair_tflops / PEAK_FP32_TFLOPS}},
         "energy_total_rel_change": (e1 - e0) / abs(e0) if e0 else None,
         "nonphys": m["nonphys"],
+        "behind_wall_after_run": m["behind"],
+        "hbm": {"peak_GBps": PEAK_HBM_GBS,
+                "note": "memory-bound kernel groups of the mixed step: algorithmic bytes per "
+                        "particle / HIP-event time; the step as a whole is bound by the "
+                        "pair-rate kernel's instruction issue, so its HBM fraction is low",
+                "kernels": hbm_block(kernels, w.n, results["ncell"])},
     }
     if "fp64" in results:
         f = results["fp64"]
@@ -538,6 +649,11 @@ def main():
         line["paper_mode"] = paper_mode_run(P, torch, ci, 20)
         log(f"paper mode mixed {line['paper_mode']['mixed']['ms_per_step']:.3f} ms/step, "
             f"fp64 {line['paper_mode']['fp64']['ms_per_step']:.3f} ms/step")
+    if args.extra and args.collision:
+        log("two-body collision, 64 M particles ...")
+        line["collision"] = collision_run(P, torch, ci)
+        log(f"collision: {line['collision']['ms_per_step']:.3f} ms/step, adjoint/forward "
+            f"{line['collision']['adjoint_window']['ratio']:.3f}")
     if args.verlet_steps > 0:
         log("Verlet-list steps ...")
         line["verlet"] = verlet_timing(P, torch, w, args.cell, args.verlet_steps)

@@ -226,8 +226,9 @@ static csph_rates_out kernel_view(const csph_rates_out &o, bool wall) {
 
 // slab = false: the plain linear cell key (the key csph_bin reports);
 // slab = true: the y-slab order the internal passes sort by.
-static GridDev grid_dev(const csph_grid &g, bool slab = true) {
+static GridDev grid_dev(const csph_grid &g, bool slab = true, double ymin = 0.0) {
     GridDev d;
+    d.ymin = ymin;
     d.ox = g.origin[0];
     d.oy = g.origin[1];
     d.oz = g.origin[2];
@@ -268,10 +269,17 @@ static int morton_bits(const int32_t dims[3]) {
     return b;
 }
 
-// Mesh from device bounds (synchronises `st`); also returns max d.
+// Mesh from device bounds (synchronises `st`); also returns max d and the minimum y.
+// snap = false: the mesh of sec. 4.2 as csph_grid_build defines it (origin = the minimum
+// position).  snap = true (the library's own passes): the origin is moved down to a whole
+// multiple of D, so that the cells stay fixed in space from one step to the next while the
+// particle set moves (a piston pushing the minimum along by a fraction of a cell per step
+// would otherwise move every particle's cell index and scatter the next step's gather).
+// Results do not depend on the mesh: membership is decided by exact FP64 distances.
 static csph_status make_grid(const double *x, const double *y, const double *z, const double *d,
                              int64_t n, const csph_params *p, void *ws, size_t ws_bytes,
-                             hipStream_t st, csph_grid *g, double *dmax) {
+                             hipStream_t st, csph_grid *g, double *dmax, double *ymin,
+                             bool snap) {
     if (ws_bytes < ws_prefix() || !ws)
         return fail(CSPH_ECAPACITY, "workspace smaller than %zu bytes", ws_prefix());
     double b[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -286,11 +294,18 @@ static csph_status make_grid(const double *x, const double *y, const double *z, 
     for (int k = 0; k < 7; ++k)
         if (!std::isfinite(b[k])) return fail(CSPH_EINVAL, "non-finite particle positions or sizes");
     *dmax = b[6];
+    *ymin = b[1];
     double Hmax = p->h_mode == CSPH_H_PAIR ? p->kappa * b[6] : p->kappa * p->h;
     double D = p->cell_size > 0.0 ? p->cell_size : Hmax;
     if (!(D > 0.0)) D = 1.0;  // pair mode with all d = 0: any mesh works
     g->cell = D;
     g->inv_cell = 1.0 / D;
+    if (snap) {
+        for (int a = 0; a < 3; ++a) {
+            const double o = floor(b[a] * g->inv_cell) * D;
+            if (o <= b[a] && std::isfinite(o)) b[a] = o;  // else keep the minimum itself
+        }
+    }
     int64_t ncell = 1;
     for (int a = 0; a < 3; ++a) {
         g->origin[a] = b[a];
@@ -402,8 +417,9 @@ csph_status csph_grid_build(const double *x, const double *y, const double *z, i
     if (n < 0 || !grid || (n > 0 && (!x || !y || !z))) return fail(CSPH_EINVAL, "bad arguments");
     csph_status s = check_params(p, n > 0, d);
     if (s) return s;
-    double dmax;
-    return make_grid(x, y, z, d, n, p, ws, ws_bytes, (hipStream_t)stream, grid, &dmax);
+    double dmax, ymin;
+    return make_grid(x, y, z, d, n, p, ws, ws_bytes, (hipStream_t)stream, grid, &dmax, &ymin,
+                     false);
 }
 
 csph_status csph_bin(const double *x, const double *y, const double *z, int64_t n,
@@ -453,14 +469,14 @@ csph_status csph_neighbors(const csph_state *s, const csph_params *p, int64_t *o
     hipStream_t st = (hipStream_t)stream;
     int64_t n = s->n;
     csph_grid g;
-    double dmax;
-    r = make_grid(s->x, s->y, s->z, s->d, n, p, ws, ws_bytes, st, &g, &dmax);
+    double dmax, ymin;
+    r = make_grid(s->x, s->y, s->z, s->d, n, p, ws, ws_bytes, st, &g, &dmax, &ymin, true);
     if (r) return r;
     r = need_ws(ws_bytes, n, g.ncell, ws_needed);
     if (r) return r;
     Ws w;
     ws_layout(&w, ws, n, g.ncell);
-    GridDev gd = grid_dev(g);
+    GridDev gd = grid_dev(g, true, ymin);
     PairConst pc = pair_const(p, dmax);
     const double *dd = p->h_mode == CSPH_H_PAIR ? s->d : nullptr;
     ProfScope pn(CSPH_PROF_NEIGHBORS, st);
@@ -498,15 +514,15 @@ csph_status csph_rates(const csph_state *s, const csph_params *p, double t, csph
     const csph_state sv = kernel_view(*s, p->wall);
     const csph_rates_out ov = kernel_view(out, p->wall);
     csph_grid g;
-    double dmax;
-    r = make_grid(sv.x, sv.y, sv.z, sv.d, n, p, ws, ws_bytes, st, &g, &dmax);
+    double dmax, ymin;
+    r = make_grid(sv.x, sv.y, sv.z, sv.d, n, p, ws, ws_bytes, st, &g, &dmax, &ymin, true);
     if (r) return r;
     r = need_ws(ws_bytes, n, g.ncell, ws_needed);
     if (r) return r;
     if (n == 0) return CSPH_OK;
     Ws w;
     ws_layout(&w, ws, n, g.ncell);
-    GridDev gd = grid_dev(g);
+    GridDev gd = grid_dev(g, true, ymin);
     PairConst pc = pair_const(p, dmax);
     EosDev eos = eos_dev(p);
     int mixed = p->precision == CSPH_MIXED;
@@ -594,14 +610,14 @@ static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const cs
     int64_t n = s_in->n;
     const csph_state vin = kernel_view(*s_in, p->wall), vout = kernel_view(*s_out, p->wall);
     csph_grid g;
-    double dmax;
-    r = make_grid(vin.x, vin.y, vin.z, vin.d, n, p, ws, ws_bytes, st, &g, &dmax);
+    double dmax, ymin;
+    r = make_grid(vin.x, vin.y, vin.z, vin.d, n, p, ws, ws_bytes, st, &g, &dmax, &ymin, true);
     if (r) return r;
     r = need_ws(ws_bytes, n, g.ncell, ws_needed);
     if (r) return r;
     Ws w;
     ws_layout(&w, ws, n, g.ncell);
-    GridDev gd = grid_dev(g);
+    GridDev gd = grid_dev(g, true, ymin);
     PairConst pc = pair_const(p, dmax);
     EosDev eos = eos_dev(p);
     int mixed = p->precision == CSPH_MIXED;
@@ -698,9 +714,9 @@ csph_status csph_vlist_build(const csph_state *s_in, csph_state *s_out, const cs
     csph_params ph = *p;
     ph.kappa = p->kappa * (1.0 + beta);
     csph_grid g;
-    double dmax;
+    double dmax, ymin;
     const csph_state vin = kernel_view(*s_in, p->wall), vout = kernel_view(*s_out, p->wall);
-    r = make_grid(vin.x, vin.y, vin.z, nullptr, n, &ph, ws, ws_bytes, st, &g, &dmax);
+    r = make_grid(vin.x, vin.y, vin.z, nullptr, n, &ph, ws, ws_bytes, st, &g, &dmax, &ymin, true);
     if (r) return r;
     r = need_ws(ws_bytes, n, g.ncell, ws_needed);
     if (r) return r;
@@ -708,7 +724,7 @@ csph_status csph_vlist_build(const csph_state *s_in, csph_state *s_out, const cs
     if (n == 0) return CSPH_OK;
     Ws w;
     ws_layout(&w, ws, n, g.ncell);
-    GridDev gd = grid_dev(g);
+    GridDev gd = grid_dev(g, true, ymin);
     EosDev eos = eos_dev(p);
     double *o[9] = {vout.x, vout.y, vout.z, vout.vx, vout.vy, vout.vz,
                     vout.rho, vout.E, vout.m};
@@ -900,15 +916,15 @@ static csph_status vjp_common(const csph_state *s, const csph_params *p, const d
     int64_t n = s->n;
     if (n > 0 && !grad_ok(gout)) return fail(CSPH_EINVAL, "gradient outputs must not be NULL");
     csph_grid g;
-    double dmax;
-    r = make_grid(s->x, s->y, s->z, nullptr, n, p, ws, ws_bytes, st, &g, &dmax);
+    double dmax, ymin;
+    r = make_grid(s->x, s->y, s->z, nullptr, n, p, ws, ws_bytes, st, &g, &dmax, &ymin, true);
     if (r) return r;
     r = need_ws(ws_bytes, n, g.ncell, ws_needed);
     if (r) return r;
     if (n == 0) return CSPH_OK;
     Ws w;
     ws_layout(&w, ws, n, g.ncell);
-    GridDev gd = grid_dev(g);
+    GridDev gd = grid_dev(g, true, ymin);
     PairConst pc = pair_const(p, dmax);
     EosDev eos = eos_dev(p);
     ProfScope pr(CSPH_PROF_ADJOINT, st);

@@ -34,6 +34,7 @@ struct GridDev {
     // cell order (cell_key): y-slabs of 2^ysh rows, z, then y in slab, then x
     int ysh, ymask, nfull;      // slab shift and mask; number of full slabs
     uint32_t sY, sZf, sZr;      // slab stride; z stride in a full / the last slab
+    double ymin;                // minimum y of the particles (the origin may lie below it)
     int morton;                 // binning keys: 1 = Morton (csph_bin's export only)
     int64_t nkey;               // key space of the binning (cells, or 2^(3 bits) for Morton)
 };

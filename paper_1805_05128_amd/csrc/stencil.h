@@ -75,10 +75,9 @@ __device__ __forceinline__ Stencil image_stencil(const GridDev &g, const Stencil
 
 // Whether a particle at y can have mirror partners within support H: some
 // particle's image 2 yw - y_j lies within H of it.  The images lie at or below
-// yw + (yw - min_j y_j), and the mesh origin is that minimum, so particles
-// behind the wall widen the band in front of it.
+// yw + (yw - min_j y_j), so particles behind the wall widen the band in front of it.
 __device__ __forceinline__ bool mirror_band(const GridDev &g, double y, double yw, double H) {
-    return y - yw < H + fmax(yw - g.oy, 0.0);
+    return y - yw < H + fmax(yw - g.ymin, 0.0);
 }
 
 // Distance in cell units from coordinate c to the slab [k, k+1) (0 inside),

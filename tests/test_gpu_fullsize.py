@@ -4,7 +4,9 @@ configuration bench.py times (cell order, unit mesh cells, both precisions):
 * porous shock 256^3 (11 743 903 particles): rates of every particle against
   the oracle (cell-list mode, all host cores) with the piston at t = 0.1
   (x_w = 0.2, in front of every particle) and at t = 2.75 (x_w = 5.5: the
-  first layers behind it, as in the later steps of the run);
+  first layers behind it, a configuration the rates must handle although the
+  step never produces it); and the state after the bench's 100 mixed steps:
+  rates of every particle in both precisions and one FP64 step;
 * plate impact (589 824 particles): one full step of every particle, both
   precisions, and the compensated totals;
 * Mie-Grueneisen plates in the pair-averaged support mode (6 291 456
@@ -58,6 +60,61 @@ def test_porous256_rates_every_particle(t):
         assert np.array_equal(got["nbr_count"].astype(np.int64), ref["nbr_count"]), prec
         stol = 1e-13 if prec == "fp64" else 1e-5
         assert np.abs(got["signal"] - ref["signal"]).max() <= stol * ref["signal"].max()
+
+
+def test_porous256_evolved_state_every_particle():
+    """The state the timed run spends most of its instructions on: the porous 256^3 sample
+    after the bench's 100 mixed steps (shocked, compressed, cells holding 0-2 particles).
+    Every particle's rates in both precisions against the oracle at that state and time,
+    and one FP64 step of every particle against the oracle's step."""
+    w = ci.config2()
+    print(f"[case] {w.name} after 100 mixed steps n={w.n}", flush=True)
+    params = P.Params.from_workload(w, precision="mixed", reorder=True, cell_size=1.0)
+    g = P.state_from_workload(w, params, DEV, with_id=False)
+    other = g.like()
+    sc = P.StepScalars(DEV)
+    ws = P.Workspace(DEV)
+    for _ in range(100):
+        g, other = P.csph_step(g, params, sc, s_out=other, ws=ws, totals=False), g
+    torch.cuda.synchronize()
+    t = float(to_np(sc.t)[0])
+    xw = w.wall[0] + w.wall[1] * t
+    s = g.numpy()
+    s["mat"] = s["mat"].astype(np.int32)
+    del other, ws
+    torch.cuda.empty_cache()
+    assert int(to_np(sc.nonphys)[0]) == 0
+    assert s["x"].min() >= xw, "a particle behind the piston"
+    cfg = O.cfg_for(w, search=1)
+    ref = O.rates(cfg, s, t=t)
+    print(f"t = {t:.4f}, oracle pairs {int(ref['nbr_count'].sum())}", flush=True)
+    for prec, tol in (("mixed", MIXED_TOL), ("fp64", FP64_TOL)):
+        pr = P.Params.from_workload(w, precision=prec, reorder=True, cell_size=1.0)
+        got = rates_np(P.csph_rates(g, pr, t=t))
+        torch.cuda.synchronize()
+        err = field_relerr(got, ref)
+        print(prec, err, flush=True)
+        assert max(err.values()) <= tol, (prec, err)
+        assert np.array_equal(got["nbr_count"].astype(np.int64), ref["nbr_count"]), prec
+        stol = 1e-13 if prec == "fp64" else 1e-5
+        assert np.abs(got["signal"] - ref["signal"]).max() <= stol * ref["signal"].max()
+    # one FP64 step of the evolved state, in its own order
+    p64 = P.Params.from_workload(w, precision="fp64", reorder=False, cell_size=1.0)
+    sc2 = P.StepScalars(DEV, t0=t)
+    cnt = torch.empty(w.n, dtype=torch.int32, device=DEV)
+    P.csph_step(g, p64, sc2, s_out=g, nbr_count=cnt)
+    torch.cuda.synchronize()
+    got = g.numpy()
+    s1, t1, dt, ncount = O.step(cfg, s, t=t)
+    assert abs(float(to_np(sc2.dt)[0]) - dt) <= 1e-15 * dt
+    assert np.array_equal(to_np(cnt).astype(np.int64), ncount)
+    for k in ("x", "y", "z", "vx", "vy", "vz", "rho", "E"):
+        den = max(np.abs(s1[k] - s[k]).max(), 1e-300)
+        err = np.abs(got[k] - s1[k]).max()
+        print(k, err / den, flush=True)
+        assert err <= FP64_TOL * den + 4 * np.finfo(float).eps * np.abs(s1[k]).max(), k
+    del g
+    torch.cuda.empty_cache()
 
 
 def test_plate_impact_step_every_particle():
