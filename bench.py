@@ -4,8 +4,9 @@
 A step is one pass of the whole hot path over the particle set: mesh
 bounds, cell binning and cell-ordered renumbering, pack + EOS, pair rates
 (Riemann-solver contact flux), state update with the CFL time step and
-compensated totals, then Voronoi ownership with per-site particle and pair
-counts for 64 generators.
+compensated totals, and the Voronoi ownership of the new positions with
+per-site particle and pair counts for 64 generators (computed by the update
+kernel: csph_step_voronoi).
 
 Default workload: porous-sample shock, 256^3 jittered lattice with seeded
 spherical voids (radius 5, 30 % porosity, 11 743 903 particles), ideal gas
@@ -118,10 +119,11 @@ class Runner:
         """k steps of (csph_step, voronoi_assign); directed pairs summed on the device."""
         P = self.P
         for _ in range(k):
-            out = P.csph_step(self.state, self.params, self.sc, s_out=self.other,
-                              nbr_count=self.cnt, ws=self.ws)
-            P.voronoi_assign(out["x"], out["y"], out["z"], self.sites, self.cnt, owner=self.owner,
-                             site_particles=self.site_particles, site_pairs=self.site_pairs)
+            # the step and the Voronoi ownership of its result in one call (the ownership is
+            # computed by the step's update kernel; bit-identical to voronoi_assign after it)
+            out = P.csph_step_voronoi(self.state, self.params, self.sc, self.sites, self.owner,
+                                      self.site_particles, self.site_pairs, s_out=self.other,
+                                      nbr_count=self.cnt, ws=self.ws)
             if count_pairs:
                 self.pairs += self.site_pairs.sum()
             self.state, self.other = out, self.state
@@ -222,7 +224,7 @@ def paper_mode_run(P, torch, ci, steps, nx=256, ny=256, nz=48):
             with collector_off():
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                for _ in range(k):
+                for i in range(k):
                     o = P.csph_step(state, params, sc, s_out=other, nbr_count=cnt, ws=ws)
                     if not warm:
                         pairs += cnt.sum()
@@ -323,7 +325,7 @@ def collision_run(P, torch, ci, steps=50, window=5):
     warm = P.state_from_workload(w, params, "cuda", with_id=False)
     other = warm.like()
     sc = P.StepScalars("cuda")
-    for _ in range(3):
+    for i in range(3):
         warm, other = P.csph_step(warm, params, sc, s_out=other, nbr_count=cnt, ws=ws), warm
     torch.cuda.synchronize()
     state = P.state_from_workload(w, params, "cuda", with_id=False)
@@ -376,9 +378,11 @@ def collision_run(P, torch, ci, steps=50, window=5):
 #              (4 per cell, added per particle from the mesh size);
 #   pack:      the state gathered (72 + mat 4 + id 8 + perm 4) and written in cell order
 #              (72 + 4 + 8) with the 48-byte FP32 pair record;
-#   integrate: state (72) and rates (40) read, the 64 evolving bytes written;
+#   integrate: state (72) and rates (40) read, the 64 evolving bytes written, and with the
+#              Voronoi ownership of the new positions (one kernel) the pair count (4) read and
+#              the owner (4) written;
 #   voronoi:   positions (24) and the pair count (4) read, the owner (4) written.
-HBM_BYTES = {"bin": 28, "pack": 88 + 132, "integrate": 112 + 64, "voronoi": 32}
+HBM_BYTES = {"bin": 28, "pack": 88 + 132, "integrate": 112 + 64 + 8, "voronoi": 32}
 
 
 def hbm_block(kernel_ms, n, ncell):

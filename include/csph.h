@@ -256,6 +256,19 @@ csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_para
                       int32_t *nbr_count, int64_t *nonphys, void *ws, size_t ws_bytes,
                       size_t *ws_needed, csph_stream stream);
 
+/* csph_step fused with voronoi_assign of its result: the same step, and the Voronoi
+ * ownership of the NEW positions (eq. VoronoiDefinition, ties to the smaller k, sec. 3.1)
+ * with per-site loads, computed by the step's update kernel.  owner[i] (n, in s_out's
+ * order), site_particles[k] and site_pairs[k] (K each, overwritten; site_pairs optional)
+ * equal those of voronoi_assign(s_out positions, sites, K, nbr_count of this step) bit for
+ * bit.  sites: K x 3 FP64, global coordinates, 1 <= K <= 1024.  Synchronises as csph_step. */
+csph_status csph_step_voronoi(const csph_state *s_in, csph_state *s_out, const csph_params *p,
+                              double *t, double dt_in, double *dt_used, double *totals,
+                              int32_t *nbr_count, int64_t *nonphys, const double *sites,
+                              int32_t K, int32_t *owner, int64_t *site_particles,
+                              int64_t *site_pairs, void *ws, size_t ws_bytes, size_t *ws_needed,
+                              csph_stream stream);
+
 /* csph_step for callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc): the same step, same kernels and
  * results, with its workspace in a library-owned device array of 128 MiB per GPU

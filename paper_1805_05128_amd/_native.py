@@ -125,6 +125,10 @@ def load():
     L.csph_step.restype = C.c_int32
     L.csph_step.argtypes = [C.POINTER(CsphState), C.POINTER(CsphState), C.POINTER(CsphParams),
                             _dp, C.c_double, _dp, _dp, _ip, _lp, vp, sz, szp, vp]
+    L.csph_step_voronoi.restype = C.c_int32
+    L.csph_step_voronoi.argtypes = [C.POINTER(CsphState), C.POINTER(CsphState),
+                                    C.POINTER(CsphParams), _dp, C.c_double, _dp, _dp, _ip, _lp,
+                                    _dp, C.c_int32, _ip, _lp, _lp, vp, sz, szp, vp]
     L.csph_step_static.restype = C.c_int32
     L.csph_step_static.argtypes = [C.POINTER(CsphState), C.POINTER(CsphState),
                                    C.POINTER(CsphParams), _dp, C.c_double, _dp, _dp, _ip, _lp,

@@ -327,6 +327,30 @@ def csph_step(s_in: State, params: Params, sc: StepScalars, s_out: Optional[Stat
     return s_out
 
 
+def csph_step_voronoi(s_in: State, params: Params, sc: StepScalars, sites: torch.Tensor,
+                      owner: torch.Tensor, site_particles: torch.Tensor,
+                      site_pairs: Optional[torch.Tensor] = None, s_out: Optional[State] = None,
+                      dt_in: float = 0.0, nbr_count: Optional[torch.Tensor] = None,
+                      ws: Optional[Workspace] = None, stream=None, totals: bool = True) -> State:
+    """csph_step plus the Voronoi ownership of the new positions (owner int32 [n] in s_out's
+    order, site_particles / site_pairs int64 [K]), computed inside the step's update."""
+    L = N.load()
+    ws = ws or default_workspace(s_in["x"].device)
+    if s_out is None:
+        s_out = s_in.like() if params.reorder else s_in
+    if sites.dtype != torch.float64 or not sites.is_contiguous():
+        sites = sites.to(torch.float64).contiguous()
+    K = sites.shape[0]
+    a, b_ = s_in.c(), s_out.c()
+    p = params.c()
+    _with_ws(lambda w, nb, nd: L.csph_step_voronoi(
+        C.byref(a), C.byref(b_), C.byref(p), _dp(sc.t), float(dt_in), _dp(sc.dt),
+        _dp(sc.totals) if totals else None, _ip(nbr_count), _lp(sc.nonphys), _dp(sites), K,
+        _ip(owner), _lp(site_particles), _lp(site_pairs), w, nb, nd, _stream(stream)), ws,
+        "csph_step_voronoi")
+    return s_out
+
+
 def csph_step_static(s_in: State, params: Params, sc: StepScalars, s_out: State,
                      dt_in: float = 0.0, nbr_count: Optional[torch.Tensor] = None,
                      stream=None, totals: bool = True) -> State:

@@ -378,11 +378,21 @@ static csph_status static_scratch(void **out) {
     return CSPH_OK;
 }
 
-// The body of csph_step and csph_step_static (prof = false: no timing events).
+// Voronoi outputs of csph_step_voronoi.
+struct VoroArgs {
+    const double *sites;
+    int32_t K;
+    int32_t *owner;
+    int64_t *site_particles, *site_pairs;
+};
+
+// The body of csph_step, csph_step_static (prof = false: no timing events) and
+// csph_step_voronoi (va: the ownership of the new positions).
 static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const csph_params *p,
                              double *t, double dt_in, double *dt_used, double *totals,
                              int32_t *nbr_count, int64_t *nonphys, void *ws, size_t ws_bytes,
-                             size_t *ws_needed, hipStream_t st, bool prof);
+                             size_t *ws_needed, hipStream_t st, bool prof,
+                             const VoroArgs *va = nullptr);
 
 }  // namespace csph
 
@@ -559,6 +569,21 @@ csph_status csph_step(const csph_state *s_in, csph_state *s_out, const csph_para
                      ws_bytes, ws_needed, (hipStream_t)stream, true);
 }
 
+csph_status csph_step_voronoi(const csph_state *s_in, csph_state *s_out, const csph_params *p,
+                              double *t, double dt_in, double *dt_used, double *totals,
+                              int32_t *nbr_count, int64_t *nonphys, const double *sites,
+                              int32_t K, int32_t *owner, int64_t *site_particles,
+                              int64_t *site_pairs, void *ws, size_t ws_bytes, size_t *ws_needed,
+                              csph_stream stream) {
+    g_err[0] = 0;
+    if (K < 1 || K > kMaxSites || !sites || !site_particles ||
+        (s_in && s_in->n > 0 && !owner))
+        return fail(CSPH_EINVAL, "bad Voronoi arguments (1 <= K <= %d)", kMaxSites);
+    const VoroArgs va{sites, K, owner, site_particles, site_pairs};
+    return step_impl(s_in, s_out, p, t, dt_in, dt_used, totals, nbr_count, nonphys, ws,
+                     ws_bytes, ws_needed, (hipStream_t)stream, true, &va);
+}
+
 csph_status csph_step_static(const csph_state *s_in, csph_state *s_out, const csph_params *p,
                              double *t, double dt_in, double *dt_used, double *totals,
                              int32_t *nbr_count, int64_t *nonphys, csph_stream stream) {
@@ -591,7 +616,7 @@ namespace csph {
 static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const csph_params *p,
                              double *t, double dt_in, double *dt_used, double *totals,
                              int32_t *nbr_count, int64_t *nonphys, void *ws, size_t ws_bytes,
-                             size_t *ws_needed, hipStream_t st, bool prof) {
+                             size_t *ws_needed, hipStream_t st, bool prof, const VoroArgs *va) {
     if (!state_ok(s_in) || !state_ok(s_out) || s_in->n != s_out->n || s_in->n >= INT32_MAX)
         return fail(CSPH_EINVAL, "bad state");
     if (s_in->n >= kMaxPairN) return fail(CSPH_EINVAL, "n >= 2^27 particles");
@@ -659,8 +684,19 @@ static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const cs
     }
     {
         ProfScope pr(CSPH_PROF_INTEGRATE, st, prof);
+        VoroDev vd{};
+        if (va) {
+            vd.sites = va->sites;
+            vd.K = va->K;
+            vd.swap = p->wall != 0;
+            vd.owner = va->owner;
+            vd.owner_at = p->reorder ? nullptr : w.perm;  // the output order
+            vd.cnt = w.cnt;
+            vd.site_part = (unsigned long long *)va->site_particles;
+            vd.site_pairs = (unsigned long long *)va->site_pairs;
+        }
         // n = 0 writes zero partials
-        CSPH_HIP(launch_integrate(n, dst, w, p->cfl, dt_in, pc, t, st));
+        CSPH_HIP(launch_integrate(n, dst, w, p->cfl, dt_in, pc, t, st, va ? &vd : nullptr));
         CSPH_HIP(launch_finish_step(n, w, p->cfl, dt_in, t, dt_used, totals, p->wall, st));
     }
     ProfScope pro(CSPH_PROF_REORDER, st, prof);

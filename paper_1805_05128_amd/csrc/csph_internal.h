@@ -239,10 +239,23 @@ hipError_t launch_unsort_rates(int64_t n, const int32_t *perm, const Ws &w, csph
 // k_step.hip
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t count, hipStream_t st);
 hipError_t launch_add_i64(int64_t *dst, const int64_t *src, hipStream_t st);  // *dst += *src
+// Voronoi ownership computed by the step's update (csph_step_voronoi): K generators (K x 3,
+// the caller's axes; swap = the kernels see x and y exchanged), owner written at i (cell
+// order) or at owner_at[i], per-site particle and pair counts (cnt, cell order) overwritten.
+struct VoroDev {
+    const double *sites;
+    int K;
+    int swap;
+    int32_t *owner;
+    const int32_t *owner_at;
+    const int32_t *cnt;
+    unsigned long long *site_part, *site_pairs;
+};
 // With pc.wall (and t, the device time at the step's start), particles behind the piston
-// plane at the new time are reflected off it.
+// plane at the new time are reflected off it.  vo (optional): also the Voronoi ownership.
 hipError_t launch_integrate(int64_t n, double *const st8[9], const Ws &w, double cfl, double dt_in,
-                            const PairConst &pc, const double *t, hipStream_t st);
+                            const PairConst &pc, const double *t, hipStream_t st,
+                            const VoroDev *vo = nullptr);
 hipError_t launch_finish_step(int64_t n, const Ws &w, double cfl, double dt_in, double *t, double *dt_used,
                               double *totals, int swap_xy, hipStream_t st);
 hipError_t launch_unpermute(int64_t n, const int32_t *perm, double *const src[9],

@@ -77,10 +77,31 @@ struct WallDev {
     const double *t;  // time at the start of the step (device)
 };
 
+// With VORO the kernel also assigns each particle's new position to its Voronoi generator
+// (eq. VoronoiDefinition: FP64 argmin of ((dx dx) + (dy dy)) + (dz dz) without contraction,
+// k scanned upwards with a strict comparison, so a tie keeps the smaller k) and counts
+// particles and pairs per generator, as k_voronoi does: the VALU-bound scan overlaps the
+// memory-bound update.  The generators come in the kernels' axes (x and y swapped with a
+// wall), which leaves every squared distance unchanged (the sum of the x and y terms is
+// commutative).
 __global__ __launch_bounds__(kBlock) void k_integrate(int64_t n, State9 s, Rates5 r,
                                                       const unsigned long long *dtmin, double cfl,
-                                                      double dt_in, WallDev wall,
+                                                      double dt_in, WallDev wall, VoroDev vo,
                                                       double *__restrict__ part) {
+    extern __shared__ double vsm[];
+    double *gs = vsm;                                                   // 3K
+    unsigned long long *hq = (unsigned long long *)(vsm + 3 * vo.K);    // K
+    unsigned int *hp = (unsigned int *)(hq + vo.K);                     // K
+    if (vo.K > 0) {
+        for (int k = threadIdx.x; k < vo.K; k += kBlock) {
+            gs[3 * k] = vo.sites[3 * k + (vo.swap ? 1 : 0)];
+            gs[3 * k + 1] = vo.sites[3 * k + (vo.swap ? 0 : 1)];
+            gs[3 * k + 2] = vo.sites[3 * k + 2];
+            hp[k] = 0u;
+            hq[k] = 0ull;
+        }
+        __syncthreads();
+    }
     double dt = step_dt(dtmin, cfl, dt_in);
     const double yw = wall.on ? wall.y0 + wall.v * (*wall.t + dt) : 0.0;
     DD acc[5];
@@ -99,9 +120,25 @@ __global__ __launch_bounds__(kBlock) void k_integrate(int64_t n, State9 s, Rates
             vy = vr;
             y = 2.0 * yw - y;
         }
-        s.f[0][i] = s.f[0][i] + dt * vx;
+        const double x = s.f[0][i] + dt * vx, z = s.f[2][i] + dt * vz;
+        s.f[0][i] = x;
         s.f[1][i] = y;
-        s.f[2][i] = s.f[2][i] + dt * vz;
+        s.f[2][i] = z;
+        if (vo.K > 0) {
+            int best = 0;
+            double bd = INFINITY;
+            for (int k = 0; k < vo.K; ++k) {
+                const double dx = x - gs[3 * k], dy = y - gs[3 * k + 1], dz = z - gs[3 * k + 2];
+                const double d2 = ((dx * dx) + (dy * dy)) + (dz * dz);
+                if (d2 < bd) {
+                    bd = d2;
+                    best = k;
+                }
+            }
+            vo.owner[vo.owner_at ? vo.owner_at[i] : (int)i] = best;
+            atomicAdd(&hp[best], 1u);
+            atomicAdd(&hq[best], (unsigned long long)vo.cnt[i]);
+        }
         s.f[3][i] = vx;
         s.f[4][i] = vy;
         s.f[5][i] = vz;
@@ -136,6 +173,12 @@ __global__ __launch_bounds__(kBlock) void k_integrate(int64_t n, State9 s, Rates
         part[blockIdx.x * 10 + 2 * threadIdx.x] = sh[0][threadIdx.x][0];
         part[blockIdx.x * 10 + 2 * threadIdx.x + 1] = sh[1][threadIdx.x][0];
     }
+    if (vo.K > 0) {  // the reduction above ended with a barrier: every count is in LDS
+        for (int k = threadIdx.x; k < vo.K; k += kBlock) {
+            if (hp[k]) atomicAdd(&vo.site_part[k], (unsigned long long)hp[k]);
+            if (hq[k] && vo.site_pairs) atomicAdd(&vo.site_pairs[k], hq[k]);
+        }
+    }
 }
 
 static int integrate_blocks(int64_t n) {
@@ -144,13 +187,22 @@ static int integrate_blocks(int64_t n) {
 }
 
 hipError_t launch_integrate(int64_t n, double *const st8[9], const Ws &w, double cfl, double dt_in,
-                            const PairConst &pc, const double *t, hipStream_t st) {
+                            const PairConst &pc, const double *t, hipStream_t st,
+                            const VoroDev *vo) {
     State9 s;
     for (int k = 0; k < 9; ++k) s.f[k] = st8[k];
     Rates5 r{{w.rate[0], w.rate[1], w.rate[2], w.rate[3], w.rate[4]}};
     WallDev wall{pc.wall && t ? 1 : 0, pc.wall_y0, pc.wall_v, t};
+    VoroDev v{};
+    size_t shm = 0;
+    if (vo && vo->K > 0) {
+        v = *vo;
+        launch_fill_u64(v.site_part, 0ull, v.K, st);
+        if (v.site_pairs) launch_fill_u64(v.site_pairs, 0ull, v.K, st);
+        shm = (size_t)v.K * (3 * sizeof(double) + sizeof(unsigned long long) + sizeof(unsigned));
+    }
     int nb = integrate_blocks(n);
-    k_integrate<<<nb, kBlock, 0, st>>>(n, s, r, w.dtmin, cfl, dt_in, wall, w.tot_part);
+    k_integrate<<<nb, kBlock, shm, st>>>(n, s, r, w.dtmin, cfl, dt_in, wall, v, w.tot_part);
     return hipGetLastError();
 }
 

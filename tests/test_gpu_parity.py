@@ -497,6 +497,53 @@ def test_piston_stops_particles_over_steps(prec):
             assert np.abs(got[k] - b).max() <= 1e-11 * (1.0 + np.abs(b).max()), k
 
 
+@pytest.mark.parametrize("case", ["porous24-mixed-reorder", "cloud-fp64-inputorder"])
+def test_step_voronoi_equals_step_then_assign(case):
+    """The step with the Voronoi ownership computed in its update kernel equals csph_step
+    followed by voronoi_assign of the new positions with the step's counts, bit for bit
+    (state, owner, per-site particle and pair counts), with a duplicated generator (exact
+    ties go to the smaller index)."""
+    if case.startswith("porous"):
+        w = ci.config2(nside=24)
+        params = P.Params.from_workload(w, precision="mixed", reorder=True, cell_size=1.0)
+        sites = np.ascontiguousarray(w.sites[:16] * (24 / 256))
+    else:
+        w = ci.random_cloud(3000, seed=12, box=9.0, n_mat=2)
+        params = P.Params.from_workload(w, precision="fp64", reorder=False)
+        sites = ci.voronoi_sites(9, 4, (9.0, 9.0, 9.0))
+    sites = np.concatenate([sites, sites[2:3]])  # duplicate of generator 2, index K-1
+    _print_case(f"step+voronoi {case}", w)
+    ts = torch.as_tensor(sites, device=DEV)
+    K = sites.shape[0]
+    res = []
+    for fused in (False, True):
+        g = gpu_state(w, params)
+        out_s = g.like() if params.reorder else g
+        sc = P.StepScalars(DEV, t0=0.2)
+        cnt = torch.empty(w.n, dtype=torch.int32, device=DEV)
+        owner = torch.full((w.n,), -1, dtype=torch.int32, device=DEV)
+        sp = torch.full((K,), -7, dtype=torch.int64, device=DEV)
+        spairs = torch.full((K,), -7, dtype=torch.int64, device=DEV)
+        if fused:
+            P.csph_step_voronoi(g, params, sc, ts, owner, sp, spairs, s_out=out_s, nbr_count=cnt)
+        else:
+            P.csph_step(g, params, sc, s_out=out_s, nbr_count=cnt)
+            P.voronoi_assign(out_s["x"], out_s["y"], out_s["z"], ts, cnt, owner=owner,
+                             site_particles=sp, site_pairs=spairs)
+        torch.cuda.synchronize()
+        r = out_s.numpy()
+        r.update(owner=to_np(owner), sp=to_np(sp), spairs=to_np(spairs), cnt=to_np(cnt),
+                 t=to_np(sc.t), tot=to_np(sc.totals))
+        res.append(r)
+    for k, v in res[0].items():
+        assert np.array_equal(v, res[1][k]), k
+    assert res[1]["sp"].sum() == w.n and res[1]["sp"][K - 1] == 0
+    ro, rsp, rspairs = O.voronoi(res[1]["x"], res[1]["y"], res[1]["z"], sites,
+                                 res[1]["cnt"].astype(np.int64))
+    assert np.array_equal(res[1]["owner"], ro) and np.array_equal(res[1]["sp"], rsp)
+    assert np.array_equal(res[1]["spairs"], rspairs)
+
+
 def test_step_mixed_rates_within_tolerance():
     w = ci.config0()
     params = P.Params.from_workload(w, precision="mixed", reorder=False)
