@@ -33,7 +33,7 @@ struct DstState {
 // Zero records after the n FP32 stencil records: the FP32 stencil walk loads up to kUS - 1
 // records past a row's last one (the A record buffer has room for them)
 constexpr int kRecPad = 2;
-constexpr int kRecPad64 = 1;  // FP64 stencil walk: kU - 1 records past a row
+constexpr int kRecPad64 = 2;  // FP64 stencil walk: kUS64 - 1 records past a row
 
 template <bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_pack(int64_t n, SrcState src,
@@ -177,10 +177,42 @@ struct RateOut {
 // the drain made the compiler shuffle the live sums between registers on
 // every pop.
 
+// 1/sqrt(x) and 1/x for x > 0 in FP64: the hardware estimate (v_rsq_f64, v_rcp_f64) refined
+// by two Newton steps.  For 1/sqrt(x) the step is y <- y + (y/2)(1 - x y^2), for 1/x it is
+// y <- y + y (1 - x y); each squares the relative error (up to a factor 3/2 for 1/sqrt), so
+// two steps take the estimate to the last bits of FP64 (the result is within a few ulp, not
+// correctly rounded: the rates are compared with a 1e-12 tolerance).  They replace the
+// compiler's correctly rounded FP64 square root and divisions, which take several times the
+// instructions.
+__device__ __forceinline__ double rsqrt64(double x) {
+#pragma clang fp contract(fast)
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double e = fma(-x * y, y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
+__device__ __forceinline__ double rcp64(double x) {
+#pragma clang fp contract(fast)
+    double y = __builtin_amdgcn_rcp(x);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double e = fma(-x, y, 1.0);
+        y = fma(y, e, y);
+    }
+    return y;
+}
+
 // One partner of particle i: Riemann problem along e, kernel slope, sums.
 // The membership test that precedes it is exact; here contraction is allowed.
 // ZS: some impedance may be zero, so Z_i + Z_j = 0 takes the mean state; otherwise that
-// branch is left out.
+// branch is left out.  As in the FP32 step, 1/(Z_i + Z_j) is folded into the weight, e is
+// taken as the raw offsets times 1/r, and the energy flux sum_j f v* is accumulated as
+// -sum_j f (v_L - v*): its sum_j f v_L part is v_i . sum_j f e_ij, added once from the
+// momentum sums.
 template <bool ZS>
 __device__ __forceinline__ void pair64(bool use, double dx, double dy, double dz, double r2,
                                        const double4 &bi, const double2 &ci,
@@ -189,34 +221,42 @@ __device__ __forceinline__ void pair64(bool use, double dx, double dy, double dz
                                        double &ar, double &avx, double &avy, double &avz,
                                        double &aE, double &sig) {
 #pragma clang fp contract(fast)
-    const double r = sqrt(use ? r2 : 1.0);
-    const double ir = 1.0 / r;
-    const double ex = dx * ir, ey = dy * ir, ez = dz * ir;
+    const double ir = rsqrt64(use ? r2 : 1.0);
+    const double r = r2 * ir;
     const double q = r * invH;
     const double a1 = 1.0 - q;
-    const double dW = -dwc * q * (a1 * a1 * a1);
-    const double vL = (bi.x * ex + bi.y * ey) + bi.z * ez;
-    const double vR = (vxj * ex + vyj * ey) + vzj * ez;
+    // a lane without a partner adds exact zeros: its kernel constant is selected to 0 and
+    // every factor it multiplies is finite (placeholder offsets and r2 finite)
+    const double dW = -(use ? dwc : 0.0) * q * (a1 * a1 * a1);
+    // v_L - v_R from the velocity difference and the raw offsets
+    const double vrel = (((bi.x - vxj) * dx + (bi.y - vyj) * dy) + (bi.z - vzj) * dz) * ir;
     const double Zi = ci.x, Pi = bi.w;
     const double S = Zi + Zj;
+    // (v_L - v*) S and P* S; S = 0 takes the mean state, written as the same expressions
+    // with Z_i = Z_j = 1 and the P and (v_L - v_R) terms dropped
     const bool sok = !ZS || S != 0.0;
-    const double iS = 1.0 / (sok ? S : 1.0);
-    const double vs = sok ? ((Zi * vL + Zj * vR) + (Pi - Pj)) * iS : 0.5 * (vL + vR);
-    const double ps = sok ? ((Zj * Pi + Zi * Pj) + Zi * Zj * (vL - vR)) * iS : 0.5 * (Pi + Pj);
-    // a lane without a partner adds exact zeros (weight selected to 0, partner-dependent
-    // factors selected to finite values; offsets and r are finite)
-    const double wgt = use ? Vj * dW : 0.0;
-    const double vsm = use ? vs : vL, psm = use ? ps : 0.0;
-    const double f = wgt * psm;
-    const double cl = vL - vR;
-    const double sp = fmax(ci.y, cj) + (cl > 0.0 ? cl : 0.0);
-    ar += wgt * (vL - vsm);
-    avx += f * ex;
-    avy += f * ey;
-    avz += f * ez;
-    aE += f * vsm;
+    const double iS = rcp64(sok ? S : 2.0);
+    const double Zjd = sok ? Zj : 1.0, Zid = sok ? Zi : 1.0;
+    const double dP = sok ? Pi - Pj : 0.0, ZZ = sok ? Zi * Zj : 0.0;
+    const double dvlS = Zjd * vrel - dP;
+    const double psS = (Zjd * Pi + Zid * Pj) + ZZ * vrel;
+    const double wS = (Vj * iS) * dW;  // V_j W' / S
+    const double f = wS * psS;         // V_j W' P*
+    const double fr = f * ir;
+    const double sp = fmax(ci.y, cj) + (vrel > 0.0 ? vrel : 0.0);
+    ar += wS * dvlS;
+    avx += fr * dx;
+    avy += fr * dy;
+    avz += fr * dz;
+    aE -= f * (dvlS * iS);
     sig = (use && sp > sig) ? sp : sig;
 }
+
+// FP64 stencil walk: candidates per lock-step iteration, pops per drain trigger (as in the
+// FP32 kernel: the loop's copies of the live sums are paid once per two pops)
+constexpr int kUS64 = 2;
+constexpr int kPop64 = 1;
+static_assert(kUS64 - 1 <= kRecPad64, "the FP64 stencil walk reads up to kUS64 - 1 records past a row");
 
 template <bool PAIR, bool WALL>
 struct Rates64 {
@@ -262,7 +302,7 @@ struct Rates64 {
         double invH = pc.invH, dwc = pc.dwc;
         if (PAIR) {
             const double H = pc.kappa * (0.5 * (di + dsz[j]));
-            invH = 1.0 / H;
+            invH = rcp64(H > 0.0 ? H : 1.0);
             const double i2 = invH * invH;
             dwc = (210.0 / M_PI) * (i2 * i2);
         }
@@ -282,8 +322,9 @@ struct Rates64 {
         int k = 0, j0 = 0, len = 0, jlast = 0;
         float gz2 = 0.f;
         for (;;) {
-            if (__any(qw - qr > kQ - kU)) {  // keep every ring at <= kQ - kU entries
-                drain<MIR, ZS>();
+            if (__any(qw - qr > kQ - kUS64)) {  // keep every ring at <= kQ - kUS64 entries
+#pragma unroll
+                for (int p = 0; p < kPop64; ++p) drain<MIR, ZS>();
                 continue;
             }
             if (!__any(k < len)) {
@@ -299,14 +340,14 @@ struct Rates64 {
                 continue;
             }
             // the slots' records from j0 + k on, the start clamped to the row's last record
-            // (the pack appends kU - 1 zero records after the n records)
+            // (the pack appends kUS64 - 1 zero records after the n records)
             const uint32_t jbo = (uint32_t)min(j0 + k, jlast) * (uint32_t)sizeof(double4);
             const double4 *Ab = (const double4 *)((const char *)A + jbo);
-            double4 aj[kU];
+            double4 aj[kUS64];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) aj[u] = Ab[u];
+            for (int u = 0; u < kUS64; ++u) aj[u] = Ab[u];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
+            for (int u = 0; u < kUS64; ++u) {
                 const int j = j0 + k + u;
                 double yj = GHOST ? 2.0 * yw - aj[u].y : aj[u].y;
                 double dx = aj[u].x - a.x, dy = yj - a.y, dz = aj[u].z - a.z;
@@ -324,7 +365,7 @@ struct Rates64 {
                 slot(qw) = GHOST ? jo | 1u : jo;
                 qw += acc ? 1 : 0;
             }
-            k += kU;
+            k += kUS64;
         }
     }
 
@@ -448,7 +489,9 @@ __global__ __launch_bounds__(kRate64Block, 5) void k_rates64(int64_t n, const do
         o.vx[s] = pre * k.avx;
         o.vy[s] = pre * k.avy;
         o.vz[s] = pre * k.avz;
-        o.E[s] = pre * k.aE;
+        // sum_j f v* = v_i . sum_j f e_ij - sum_j f (v_L - v*)
+        const double vf = (k.b.x * k.avx + k.b.y * k.avy) + k.b.z * k.avz;
+        o.E[s] = pre * (k.aE + vf);
         if (o.sig) o.sig[s] = k.sig;
         if (o.cnt) o.cnt[s] = cnt;
         // Courant limit and relative density-change limit of one explicit step
