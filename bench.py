@@ -279,25 +279,22 @@ def verlet_timing(P, torch, w, cell, steps, beta=0.3, n_upd=10):
     state = P.state_from_workload(w, params, "cuda", with_id=False)
     sc = P.StepScalars("cuda")
     run = P.VerletRun(state, params, beta=beta, n_upd=n_upd)
-    cnt = torch.empty(w.n, dtype=torch.int32, device="cuda")
-    pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
-    for _ in range(2):
-        run.step(sc, nbr_count=cnt)
+    run.advance(sc, 2)
     torch.cuda.synchronize()
-    b0 = run.builds
+    b0, p0 = run.builds, run.pairs
     P.profile_enable(True)
     P.profile_read()
     with collector_off():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
-            run.step(sc, nbr_count=cnt)
-            pairs += cnt.sum()
+        # list steps issued without waiting; one synchronisation per batch (the control
+        # block's read), the device guard deciding the rebuilds
+        run.advance(sc, steps)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
     prof = P.profile_read()
     P.profile_enable(False)
-    npairs = int(pairs.item())
+    npairs = run.pairs - p0
     out = {"metric_value": npairs / el, "unit": "pair-interactions/s", "ms_per_step": 1e3 * el / steps,
            "steps": steps, "beta": beta, "n_upd": n_upd, "rebuilds": run.builds - b0,
            "list_cap": run.cap,

@@ -296,6 +296,19 @@ csph_status voronoi_assign(const double *x, const double *y, const double *z, in
                            int32_t *owner, int64_t *site_particles, int64_t *site_pairs,
                            csph_stream stream);
 
+/* Control block of a set of Verlet lists (device memory, caller-owned, 48 bytes, 8-byte
+ * aligned).  csph_vlist_build fills it; each csph_step_vlist checks it on the device and
+ * updates it, so a driver can issue list steps without waiting for them. */
+typedef struct {
+    double t_build; /* time of the build */
+    double disp;    /* max_i |r_i - r_ref,i| of the current state */
+    double margin;  /* beta H: the horizon margin of the lists */
+    double vw2;     /* 2 |v_wall| (0 without a wall) */
+    int64_t pairs;  /* directed pairs evaluated by the list steps since the build */
+    int32_t steps;  /* list steps taken since the build */
+    int32_t valid;  /* 1 while the lists give N(i) exactly; 0 once a step found them stale */
+} csph_vlist_ctl;
+
 /* Verlet lists (sec. 4.2): the partners of each particle within the horizon
  * R = (1 + beta) H, for reuse over several steps.  Fixed-h mode only.
  *   s_in -> s_out: the state renumbered into cell order (as csph_step with
@@ -308,25 +321,31 @@ csph_status voronoi_assign(const double *x, const double *y, const double *z, in
  *     without contraction; a partner whose mirror image across the piston wall (at
  *     time *t, device) lies within R of s has the sign bit set.
  *   x_ref[3 n] (device): the positions at build, x..., y..., z....
+ *   ctl (device, optional): reset for these lists (t_build = *t, steps = pairs = 0,
+ *     valid = 1, margin = beta H, vw2 = 2 |wall_v|).
  *   *max_count (host, optional): 0, or the longest list when it exceeds cap; then the
  *     lists are truncated and the call returns CSPH_ECAPACITY.
  * Synchronises (mesh bounds, wall time, list overflow). */
 csph_status csph_vlist_build(const csph_state *s_in, csph_state *s_out, const csph_params *p,
                              const double *t, double beta, int32_t cap, int32_t *vl_count,
-                             int32_t *vl_idx, double *x_ref, int32_t *max_count, void *ws,
-                             size_t ws_bytes, size_t *ws_needed, csph_stream stream);
+                             int32_t *vl_idx, double *x_ref, csph_vlist_ctl *ctl,
+                             int32_t *max_count, void *ws, size_t ws_bytes, size_t *ws_needed,
+                             csph_stream stream);
 
-/* One step from Verlet lists, in place on s (in the lists' order): the rates
- * take the listed partners with r^2 < H^2 (FP64 test), which is N(i) exactly
- * while no pair can have entered the support from beyond the horizon, i.e.
- * while 2 max_i |r_i - r_ref,i| + 2 |v_wall| (t - t_build) < beta H; the
- * caller keeps that true by rebuilding.  Then the update of csph_step (dt,
- * totals, nbr_count, nonphys as there), and *disp (device, optional) =
- * max_i |r_i - r_ref,i| after the update.  Asynchronous. */
+/* One step from Verlet lists, in place on s (in the lists' order).  The rates take the
+ * listed partners with r^2 < H^2 (FP64 test), which is N(i) exactly while no pair can
+ * have entered the support from beyond the horizon, i.e. while
+ * 2 max_i |r_i - r_ref,i| + 2 |v_wall| (t - t_build) < beta H.  The step checks that bound
+ * on the device first (ctl->disp is the previous step's displacement; the first step after
+ * a build always passes): when it fails, ctl->valid becomes 0 and this step and every later
+ * one until the next csph_vlist_build leave s, t, dt_used, totals, nbr_count and nonphys
+ * untouched.  Otherwise the update of csph_step (dt, totals, nbr_count, nonphys as there);
+ * then ctl->disp = max_i |r_i - r_ref,i| of the new state, ctl->steps += 1 and
+ * ctl->pairs += sum_i |N(i)|.  Asynchronous: a driver reads ctl when it synchronises. */
 csph_status csph_step_vlist(csph_state *s, const csph_params *p, double *t, double dt_in,
                             double *dt_used, double *totals, int32_t *nbr_count,
                             int64_t *nonphys, const int32_t *vl_count, const int32_t *vl_idx,
-                            int32_t cap, const double *x_ref, double *disp, void *ws,
+                            int32_t cap, const double *x_ref, csph_vlist_ctl *ctl, void *ws,
                             size_t ws_bytes, size_t *ws_needed, csph_stream stream);
 
 /* Voronoi load balancer (sec. 3).  Generators, centres: K x 3 row-major

@@ -9,5 +9,6 @@ from .api import (EOS_IDEAL, EOS_STIFFENED, EOS_MIE_GRUNEISEN, Params, State, St
                   workspace_size, csph_rates_vjp, csph_step_vjp, csph_init_energy_vjp,
                   zeros_grad, GRAD_FIELDS, BalanceParams, csph_balance_stats,
                   csph_balance_move, adjacency_matrix, csph_vlist_build, csph_step_vlist,
-                  VerletRun, csph_step_static, csph_step_voronoi)
+                  VerletRun, csph_step_static, csph_step_voronoi, vlist_ctl,
+                  vlist_ctl_read)
 from .autograd import CSPHRollout, rollout  # noqa: F401

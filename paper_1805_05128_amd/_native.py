@@ -152,10 +152,10 @@ def load():
     L.csph_vlist_build.restype = C.c_int32
     L.csph_vlist_build.argtypes = [C.POINTER(CsphState), C.POINTER(CsphState),
                                    C.POINTER(CsphParams), _dp, C.c_double, C.c_int32, _ip, _ip,
-                                   _dp, C.POINTER(C.c_int32), vp, sz, szp, vp]
+                                   _dp, vp, C.POINTER(C.c_int32), vp, sz, szp, vp]
     L.csph_step_vlist.restype = C.c_int32
     L.csph_step_vlist.argtypes = [C.POINTER(CsphState), C.POINTER(CsphParams), _dp, C.c_double,
-                                  _dp, _dp, _ip, _lp, _ip, _ip, C.c_int32, _dp, _dp, vp, sz,
+                                  _dp, _dp, _ip, _lp, _ip, _ip, C.c_int32, _dp, vp, vp, sz,
                                   szp, vp]
     L.csph_balance_workspace_size.restype = sz
     L.csph_balance_workspace_size.argtypes = [C.c_int32]

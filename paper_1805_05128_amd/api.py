@@ -565,21 +565,42 @@ def csph_balance_move(sites: torch.Tensor, stats: Dict[str, torch.Tensor], bp: B
 
 # ------------------------------------------------------------------ Verlet lists
 
+VLIST_CTL_BYTES = 48  # csph_vlist_ctl
+
+
+def vlist_ctl(device="cuda") -> torch.Tensor:
+    """Device storage for a csph_vlist_ctl (6 x 8 bytes)."""
+    return torch.zeros(VLIST_CTL_BYTES // 8, dtype=torch.int64, device=device)
+
+
+def vlist_ctl_read(ctl: torch.Tensor) -> Dict[str, float]:
+    """Host copy of a csph_vlist_ctl (synchronises)."""
+    import numpy as np
+    raw = ctl.cpu().numpy().view(np.uint8)
+    f = raw[:32].view(np.float64)
+    return {"t_build": float(f[0]), "disp": float(f[1]), "margin": float(f[2]),
+            "vw2": float(f[3]), "pairs": int(raw[32:40].view(np.int64)[0]),
+            "steps": int(raw[40:44].view(np.int32)[0]), "valid": int(raw[44:48].view(np.int32)[0])}
+
+
 def csph_vlist_build(s_in: State, s_out: State, params: Params, sc: StepScalars, beta: float,
                      cap: int, count: torch.Tensor, idx: torch.Tensor, x_ref: torch.Tensor,
-                     ws: Optional[Workspace] = None, stream=None) -> int:
+                     ctl: Optional[torch.Tensor] = None, ws: Optional[Workspace] = None,
+                     stream=None) -> int:
     """Renumber s_in into cell order in s_out and build the horizon lists; returns 0, or the
-    longest list when it exceeds ``cap`` (the lists are then truncated)."""
+    longest list when it exceeds ``cap`` (the lists are then truncated).  ``ctl`` (from
+    vlist_ctl) is reset for these lists."""
     L = N.load()
     ws = ws or default_workspace(s_in["x"].device)
     a, b_ = s_in.c(), s_out.c()
     p = params.c()
     mx = C.c_int32(0)
     needed = C.c_size_t(0)
+    cp = C.c_void_p(ctl.data_ptr()) if ctl is not None else None
     for _ in range(3):
         st = L.csph_vlist_build(C.byref(a), C.byref(b_), C.byref(p), _dp(sc.t), float(beta),
-                                int(cap), _ip(count), _ip(idx), _dp(x_ref), C.byref(mx), ws.ptr,
-                                ws.nbytes, C.byref(needed), _stream(stream))
+                                int(cap), _ip(count), _ip(idx), _dp(x_ref), cp, C.byref(mx),
+                                ws.ptr, ws.nbytes, C.byref(needed), _stream(stream))
         if st == N.CSPH_ECAPACITY and mx.value == 0 and needed.value > ws.nbytes:
             ws.ensure(needed.value)
             continue
@@ -592,18 +613,20 @@ def csph_vlist_build(s_in: State, s_out: State, params: Params, sc: StepScalars,
 
 
 def csph_step_vlist(s: State, params: Params, sc: StepScalars, count, idx, cap: int, x_ref,
-                    disp: Optional[torch.Tensor] = None, dt_in: float = 0.0,
+                    ctl: torch.Tensor, dt_in: float = 0.0,
                     nbr_count: Optional[torch.Tensor] = None, ws: Optional[Workspace] = None,
                     stream=None, totals: bool = True) -> State:
-    """One step in place from Verlet lists (s in the lists' order)."""
+    """One step in place from Verlet lists (s in the lists' order); a no-op once the device
+    guard has found the lists stale (see csph_vlist_ctl)."""
     L = N.load()
     ws = ws or default_workspace(s["x"].device)
     a = s.c()
     p = params.c()
+    cp = C.c_void_p(ctl.data_ptr())
     _with_ws(lambda w, nb, nd: L.csph_step_vlist(
         C.byref(a), C.byref(p), _dp(sc.t), float(dt_in), _dp(sc.dt),
         _dp(sc.totals) if totals else None, _ip(nbr_count), _lp(sc.nonphys), _ip(count),
-        _ip(idx), int(cap), _dp(x_ref), _dp(disp), w, nb, nd, _stream(stream)), ws,
+        _ip(idx), int(cap), _dp(x_ref), cp, w, nb, nd, _stream(stream)), ws,
         "csph_step_vlist")
     return s
 
@@ -612,8 +635,11 @@ class VerletRun:
     """Steps from Verlet lists (sec. 4.2): lists of the partners within (1 + beta) H are
     rebuilt every ``n_upd`` steps, and earlier when the displacement bound
     2 max|r - r_ref| + 2 |v_wall| (t - t_build) reaches beta H, so that every step
-    evaluates exactly N(i).  The state is renumbered into cell order at each rebuild.
-    ``cap`` is the list capacity per particle (grown on overflow)."""
+    evaluates exactly N(i).  The bound is checked by each list step on the device: the
+    driver issues up to ``n_upd`` steps without waiting, then reads the lists' control
+    block once (one synchronisation per batch), and rebuilds and re-issues what a stale
+    list skipped.  The state is renumbered into cell order at each rebuild.  ``cap`` is the
+    list capacity per particle (grown on overflow)."""
 
     def __init__(self, state: State, params: Params, beta: float = 0.3, n_upd: int = 10,
                  cap: Optional[int] = None, ws: Optional[Workspace] = None):
@@ -631,40 +657,49 @@ class VerletRun:
         self.count = torch.zeros(max(n, 1), dtype=torch.int32, device=dev)
         self.idx = torch.empty(max(n, 1) * self.cap, dtype=torch.int32, device=dev)
         self.x_ref = torch.empty(3 * max(n, 1), dtype=torch.float64, device=dev)
-        self.disp = torch.zeros(1, dtype=torch.float64, device=dev)
-        self.since = None
-        self.t_build = 0.0
+        self.ctl = vlist_ctl(dev)
+        self.since = None   # list steps taken since the build (None: no lists yet)
+        self.valid = False
         self.builds = 0
+        self.pairs = 0      # directed pairs evaluated by list steps (read at synchronisations)
         self.H = H
 
     def _build(self, sc: StepScalars):
         while True:
             over = csph_vlist_build(self.state, self.other, self.params, sc, self.beta, self.cap,
-                                    self.count, self.idx, self.x_ref, ws=self.ws)
+                                    self.count, self.idx, self.x_ref, self.ctl, ws=self.ws)
             if over == 0:
                 break
             self.cap = -(-(int(over * 1.25) + 8) // 8) * 8
             self.idx = torch.empty(max(self.state.n, 1) * self.cap, dtype=torch.int32,
                                    device=self.idx.device)
         self.state, self.other = self.other, self.state
-        self.disp.zero_()
         self.since = 0
-        self.t_build = float(sc.t.item())
+        self.valid = True
+        self._pairs_seen = 0  # the control block's pair count restarts at a build
         self.builds += 1
 
-    def needs_build(self, sc: StepScalars) -> bool:
-        if self.since is None or self.since >= self.n_upd:
-            return True
-        vw = abs(self.params.wall[1]) if self.params.wall is not None else 0.0
-        bound = 2.0 * float(self.disp.item()) + 2.0 * vw * (float(sc.t.item()) - self.t_build)
-        return not (bound < self.beta * self.H)
+    def advance(self, sc: StepScalars, k: int, nbr_count: Optional[torch.Tensor] = None,
+                dt_in: float = 0.0, totals: bool = True) -> State:
+        """k exact steps; one synchronisation per batch of up to n_upd list steps."""
+        done = 0
+        while done < k:
+            if self.since is None or self.since >= self.n_upd or not self.valid:
+                self._build(sc)
+            m = min(k - done, self.n_upd - self.since)
+            for _ in range(m):
+                csph_step_vlist(self.state, self.params, sc, self.count, self.idx, self.cap,
+                                self.x_ref, self.ctl, dt_in=dt_in, nbr_count=nbr_count,
+                                ws=self.ws, totals=totals)
+            c = vlist_ctl_read(self.ctl)
+            taken = c["steps"] - self.since
+            self.pairs += c["pairs"] - self._pairs_seen
+            self._pairs_seen = c["pairs"]
+            self.since = c["steps"]
+            self.valid = bool(c["valid"])
+            done += taken
+        return self.state
 
     def step(self, sc: StepScalars, nbr_count: Optional[torch.Tensor] = None,
              dt_in: float = 0.0, totals: bool = True) -> State:
-        if self.needs_build(sc):
-            self._build(sc)
-        csph_step_vlist(self.state, self.params, sc, self.count, self.idx, self.cap, self.x_ref,
-                        disp=self.disp, dt_in=dt_in, nbr_count=nbr_count, ws=self.ws,
-                        totals=totals)
-        self.since += 1
-        return self.state
+        return self.advance(sc, 1, nbr_count=nbr_count, dt_in=dt_in, totals=totals)

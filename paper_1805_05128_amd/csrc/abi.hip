@@ -723,8 +723,9 @@ extern "C" {
 
 csph_status csph_vlist_build(const csph_state *s_in, csph_state *s_out, const csph_params *p,
                              const double *t, double beta, int32_t cap, int32_t *vl_count,
-                             int32_t *vl_idx, double *x_ref, int32_t *max_count, void *ws,
-                             size_t ws_bytes, size_t *ws_needed, csph_stream stream) {
+                             int32_t *vl_idx, double *x_ref, csph_vlist_ctl *ctl,
+                             int32_t *max_count, void *ws, size_t ws_bytes, size_t *ws_needed,
+                             csph_stream stream) {
     g_err[0] = 0;
     if (!state_ok(s_in) || !state_ok(s_out) || s_in->n != s_out->n || s_in->n >= INT32_MAX)
         return fail(CSPH_EINVAL, "bad state");
@@ -739,6 +740,7 @@ csph_status csph_vlist_build(const csph_state *s_in, csph_state *s_out, const cs
     if (n > 0 && (!vl_count || !vl_idx || !x_ref))
         return fail(CSPH_EINVAL, "vl_count, vl_idx and x_ref are required");
     if (((uintptr_t)vl_idx & 15) != 0) return fail(CSPH_EINVAL, "vl_idx must be 16-byte aligned");
+    if (((uintptr_t)ctl & 7) != 0) return fail(CSPH_EINVAL, "ctl must be 8-byte aligned");
     if (n > 0 && (s_in->x == s_out->x || s_in->vx == s_out->vx || s_in->rho == s_out->rho ||
                   s_in->E == s_out->E || s_in->m == s_out->m))
         return fail(CSPH_EINVAL, "s_out must be distinct from s_in");
@@ -757,6 +759,9 @@ csph_status csph_vlist_build(const csph_state *s_in, csph_state *s_out, const cs
     r = need_ws(ws_bytes, n, g.ncell, ws_needed);
     if (r) return r;
     if (max_count) *max_count = 0;
+    const double H = p->kappa * p->h;
+    if (ctl)
+        CSPH_HIP(launch_vl_init(ctl, t, beta * H, p->wall ? 2.0 * std::fabs(p->wall_v) : 0.0, st));
     if (n == 0) return CSPH_OK;
     Ws w;
     ws_layout(&w, ws, n, g.ncell);
@@ -774,7 +779,6 @@ csph_status csph_vlist_build(const csph_state *s_in, csph_state *s_out, const cs
                              nullptr, st));
     }
     CSPH_HIP(hipStreamSynchronize(st));  // twall
-    const double H = p->kappa * p->h;
     const double R = (1.0 + beta) * H;
     const double yw = p->wall ? p->wall_x0 + p->wall_v * twall : 0.0;  // along the kernels' y
     unsigned long long over = 0;
@@ -799,7 +803,7 @@ csph_status csph_vlist_build(const csph_state *s_in, csph_state *s_out, const cs
 csph_status csph_step_vlist(csph_state *s, const csph_params *p, double *t, double dt_in,
                             double *dt_used, double *totals, int32_t *nbr_count,
                             int64_t *nonphys, const int32_t *vl_count, const int32_t *vl_idx,
-                            int32_t cap, const double *x_ref, double *disp, void *ws,
+                            int32_t cap, const double *x_ref, csph_vlist_ctl *ctl, void *ws,
                             size_t ws_bytes, size_t *ws_needed, csph_stream stream) {
     g_err[0] = 0;
     if (!state_ok(s) || s->n >= INT32_MAX) return fail(CSPH_EINVAL, "bad state");
@@ -814,6 +818,8 @@ csph_status csph_step_vlist(csph_state *s, const csph_params *p, double *t, doub
     if (n > 0 && (!vl_count || !vl_idx || !x_ref || cap < kVlChunk || cap % kVlChunk))
         return fail(CSPH_EINVAL, "vl_count, vl_idx, x_ref and cap (a multiple of %d) are required",
                     kVlChunk);
+    if (!ctl || ((uintptr_t)ctl & 7) != 0)
+        return fail(CSPH_EINVAL, "ctl (the lists' control block, 8-byte aligned) is required");
     hipStream_t st = (hipStream_t)stream;
     r = need_ws(ws_bytes, n, 1, ws_needed);
     if (r) return r;
@@ -826,30 +832,31 @@ csph_status csph_step_vlist(csph_state *s, const csph_params *p, double *t, doub
     const int mixed = p->precision == CSPH_MIXED;
     const csph_state sv = kernel_view(*s, p->wall);
     double *cur[9] = {sv.x, sv.y, sv.z, sv.vx, sv.vy, sv.vz, sv.rho, sv.E, sv.m};
+    // the lists' exactness bound, checked on the device; every kernel below does nothing once
+    // the lists are stale
+    CSPH_HIP(launch_vl_guard(ctl, t, st));
+    const int32_t *gate = &ctl->valid;
+    const ListGate lg{gate, w.cnt, (unsigned long long *)&ctl->pairs, &ctl->steps};
     // dt = cfl * min h/s (an empty set takes dt = 0); the pack clears the Z flag
     CSPH_HIP(launch_fill_u64(w.dtmin, n > 0 ? 0x7ff0000000000000ull : 0ull, 2, st));
     if (n > 0) {
         ProfScope pr(CSPH_PROF_PACK, st);
         CSPH_HIP(launch_pack(sv, n, nullptr, eos, mixed, gd, w, nullptr, nullptr, nullptr,
-                             nullptr, nullptr, nonphys, st));
+                             nullptr, nullptr, nonphys, st, gate));
     }
     if (n > 0) {
         ProfScope pr(CSPH_PROF_RATES, st);
         CSPH_HIP(launch_rates(n, mixed, gd, pc, w, cur, nullptr, t, 0.0, p->cfl > 0.0, st,
-                              vl_count, vl_idx, cap));
+                              vl_count, vl_idx, cap, gate));
     }
     {
         ProfScope pr(CSPH_PROF_INTEGRATE, st);
-        CSPH_HIP(launch_integrate(n, cur, w, p->cfl, dt_in, pc, t, st));
-        CSPH_HIP(launch_finish_step(n, w, p->cfl, dt_in, t, dt_used, totals, p->wall, st));
-        if (disp) {
-            CSPH_HIP(launch_fill_u64((unsigned long long *)disp, 0ull, 1, st));
-            CSPH_HIP(launch_disp(n, s->x, s->y, s->z, x_ref, (unsigned long long *)disp, st));
-        }
+        CSPH_HIP(launch_integrate(n, cur, w, p->cfl, dt_in, pc, t, st, nullptr, &lg));
+        CSPH_HIP(launch_finish_step(n, w, p->cfl, dt_in, t, dt_used, totals, p->wall, st, &lg));
+        CSPH_HIP(launch_disp(n, s->x, s->y, s->z, x_ref, (unsigned long long *)&ctl->disp, st,
+                             gate));
     }
-    if (n > 0 && nbr_count)
-        CSPH_HIP(hipMemcpyAsync(nbr_count, w.cnt, sizeof(int32_t) * n, hipMemcpyDeviceToDevice,
-                                st));
+    if (n > 0 && nbr_count) CSPH_HIP(launch_copy_i32(nbr_count, w.cnt, n, gate, st));
     return CSPH_OK;
 }
 

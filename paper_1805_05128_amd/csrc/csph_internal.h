@@ -217,22 +217,31 @@ template <typename TI, typename TO>
 hipError_t launch_scan_exclusive(const TI *in, TO *out, int64_t len, int64_t *tmp, hipStream_t st);
 
 // k_rates.hip
+// gate (optional, device): the kernel does nothing while *gate == 0 (a Verlet-list step whose
+// lists were found stale; csph_vlist_ctl::valid)
 hipError_t launch_pack(const csph_state &s, int64_t n, const int32_t *perm, const EosDev &eos,
                        int mixed, const GridDev &g, const Ws &w, double *const dst[9],
                        int32_t *dst_mat, double *dst_d, int64_t *dst_id, const int64_t *src_id,
-                       int64_t *nonphys, hipStream_t st);
+                       int64_t *nonphys, hipStream_t st, const int32_t *gate = nullptr);
 // sorted: the cell-ordered FP64 state (x y z vx vy vz rho E m) the records were packed from.
 hipError_t launch_rates(int64_t n, int mixed, const GridDev &g, const PairConst &pc,
                         const Ws &w, double *const sorted[9], const double *d_sorted,
                         const double *t_dev, double t_host, int want_dt, hipStream_t st,
                         const int32_t *vl_count = nullptr, const int32_t *vl_idx = nullptr,
-                        int vl_cap = 0);
+                        int vl_cap = 0, const int32_t *gate = nullptr);
+// Verlet-list control block: reset at a build; the per-step guard (csph_step_vlist).
+hipError_t launch_vl_init(csph_vlist_ctl *ctl, const double *t, double margin, double vw2,
+                          hipStream_t st);
+hipError_t launch_vl_guard(csph_vlist_ctl *ctl, const double *t, hipStream_t st);
+hipError_t launch_copy_i32(int32_t *dst, const int32_t *src, int64_t n, const int32_t *gate,
+                           hipStream_t st);
 // k_vlist.hip
 hipError_t launch_vlist(int64_t n, const double4 *A, const int32_t *cs, const GridDev &g,
                         double R, int wall, double yw, int cap, int32_t *count, int32_t *idx,
                         unsigned long long *over, hipStream_t st);
 hipError_t launch_disp(int64_t n, const double *x, const double *y, const double *z,
-                       const double *ref, unsigned long long *out, hipStream_t st);
+                       const double *ref, unsigned long long *out, hipStream_t st,
+                       const int32_t *gate = nullptr);
 hipError_t launch_unsort_rates(int64_t n, const int32_t *perm, const Ws &w, csph_rates_out out,
                                double *signal, int32_t *nbr_count, hipStream_t st);
 
@@ -251,13 +260,22 @@ struct VoroDev {
     const int32_t *cnt;
     unsigned long long *site_part, *site_pairs;
 };
+// A Verlet-list step's gate and counters: the update does nothing while *gate == 0; otherwise
+// it adds sum_i cnt[i] to *pairs and the finishing kernel adds 1 to *steps.
+struct ListGate {
+    const int32_t *gate;
+    const int32_t *cnt;
+    unsigned long long *pairs;
+    int32_t *steps;
+};
 // With pc.wall (and t, the device time at the step's start), particles behind the piston
 // plane at the new time are reflected off it.  vo (optional): also the Voronoi ownership.
 hipError_t launch_integrate(int64_t n, double *const st8[9], const Ws &w, double cfl, double dt_in,
                             const PairConst &pc, const double *t, hipStream_t st,
-                            const VoroDev *vo = nullptr);
+                            const VoroDev *vo = nullptr, const ListGate *lg = nullptr);
 hipError_t launch_finish_step(int64_t n, const Ws &w, double cfl, double dt_in, double *t, double *dt_used,
-                              double *totals, int swap_xy, hipStream_t st);
+                              double *totals, int swap_xy, hipStream_t st,
+                              const ListGate *lg = nullptr);
 hipError_t launch_unpermute(int64_t n, const int32_t *perm, double *const src[9],
                             const int32_t *src_mat, const double *src_d, const int64_t *src_id,
                             const int32_t *src_cnt, const csph_state &out, int32_t *out_cnt,

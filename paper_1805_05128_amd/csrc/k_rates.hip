@@ -42,7 +42,9 @@ __global__ __launch_bounds__(kBlock) void k_pack(int64_t n, SrcState src,
                                                  void *__restrict__ recB,
                                                  void *__restrict__ recC, DstState dst,
                                                  int64_t *__restrict__ nonphys,
-                                                 unsigned long long *__restrict__ zflag) {
+                                                 unsigned long long *__restrict__ zflag,
+                                                 const int32_t *__restrict__ gate) {
+    if (gate && *gate == 0) return;
     int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s >= n) return;
     const int i = perm ? perm[s] : (int)s;  // no permutation: records of the state in place
@@ -103,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_pack(int64_t n, SrcState src,
 hipError_t launch_pack(const csph_state &s, int64_t n, const int32_t *perm, const EosDev &eos,
                        int mixed, const GridDev &g, const Ws &w, double *const dst[9],
                        int32_t *dst_mat, double *dst_d, int64_t *dst_id, const int64_t *src_id,
-                       int64_t *nonphys, hipStream_t st) {
+                       int64_t *nonphys, hipStream_t st, const int32_t *gate) {
     if (n <= 0) return hipSuccess;
     SrcState src{{s.x, s.y, s.z, s.vx, s.vy, s.vz, s.rho, s.E, s.m}, s.mat, s.d, src_id};
     DstState ds;
@@ -117,10 +119,10 @@ hipError_t launch_pack(const csph_state &s, int64_t n, const int32_t *perm, cons
     unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
     if (mixed)
         k_pack<true><<<nb, kBlock, 0, st>>>(n, src, perm, eos, g, recA, w.recB, w.recC, ds,
-                                            nonphys, w.zflag);
+                                            nonphys, w.zflag, gate);
     else
         k_pack<false><<<nb, kBlock, 0, st>>>(n, src, perm, eos, g, recA, w.recB, w.recC, ds,
-                                             nonphys, w.zflag);
+                                             nonphys, w.zflag, gate);
     return hipGetLastError();
 }
 
@@ -160,6 +162,7 @@ struct VList {
     const int32_t *count;
     const int32_t *idx;
     int cap;
+    const int32_t *gate;  // list steps: nothing to do while *gate == 0
 };
 
 struct RateOut {
@@ -439,6 +442,7 @@ __global__ __launch_bounds__(kRate64Block, 5) void k_rates64(int64_t n, const do
                                                     PairConst pc, const double *t_dev,
                                                     double t_host, RateOut o, int want_dt,
                                                     VList vl) {
+    if (LIST && vl.gate && *vl.gate == 0) return;
     __shared__ int qj[kQ][kRate64Block];
     Rates64<PAIR, WALL> k;
     k.qb = (char *)&qj[0][0];
@@ -777,6 +781,7 @@ __global__ __launch_bounds__(kRate32Block) void k_rates32(int64_t n, const float
                                                     PairConst pc, const double *t_dev,
                                                     double t_host, RateOut o, int want_dt,
                                                     VList vl) {
+    if (LIST && vl.gate && *vl.gate == 0) return;
     __shared__ float4 qd[kQ][kRate32Block];
     // finite placeholder offsets for lanes that pop from an empty ring
 #pragma unroll
@@ -859,12 +864,13 @@ __global__ __launch_bounds__(kRate32Block) void k_rates32(int64_t n, const float
 hipError_t launch_rates(int64_t n, int mixed, const GridDev &g, const PairConst &pc,
                         const Ws &w, double *const sorted[9], const double *d_sorted,
                         const double *t_dev, double t_host, int want_dt, hipStream_t st,
-                        const int32_t *vl_count, const int32_t *vl_idx, int vl_cap) {
+                        const int32_t *vl_count, const int32_t *vl_idx, int vl_cap,
+                        const int32_t *gate) {
     if (n <= 0) return hipSuccess;
     const double *rho_sorted = sorted[6];
     RateOut o{w.rate[0], w.rate[1], w.rate[2], w.rate[3], w.rate[4], w.sig, w.cnt, w.dtmin,
               w.zflag};
-    VList vl{vl_count, vl_idx, vl_cap};
+    VList vl{vl_count, vl_idx, vl_cap, gate};
     const unsigned nb32 = (unsigned)((n + kRate32Block - 1) / kRate32Block);
     const unsigned nb64 = (unsigned)((n + kRate64Block - 1) / kRate64Block);
     const bool pair = pc.pair_mode != 0, wall = pc.wall != 0, list = vl_idx != nullptr;

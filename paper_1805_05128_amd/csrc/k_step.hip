@@ -87,7 +87,8 @@ struct WallDev {
 __global__ __launch_bounds__(kBlock) void k_integrate(int64_t n, State9 s, Rates5 r,
                                                       const unsigned long long *dtmin, double cfl,
                                                       double dt_in, WallDev wall, VoroDev vo,
-                                                      double *__restrict__ part) {
+                                                      ListGate lg, double *__restrict__ part) {
+    if (lg.gate && *lg.gate == 0) return;
     extern __shared__ double vsm[];
     double *gs = vsm;                                                   // 3K
     unsigned long long *hq = (unsigned long long *)(vsm + 3 * vo.K);    // K
@@ -106,8 +107,10 @@ __global__ __launch_bounds__(kBlock) void k_integrate(int64_t n, State9 s, Rates
     const double yw = wall.on ? wall.y0 + wall.v * (*wall.t + dt) : 0.0;
     DD acc[5];
     for (int k = 0; k < 5; ++k) acc[k] = DD{0.0, 0.0};
+    unsigned long long npairs = 0;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock) {
+        if (lg.pairs) npairs += (unsigned long long)lg.cnt[i];
         double vx = s.f[3][i] + dt * r.f[1][i];
         double vy = s.f[4][i] + dt * r.f[2][i];
         double vz = s.f[5][i] + dt * r.f[3][i];
@@ -173,6 +176,10 @@ __global__ __launch_bounds__(kBlock) void k_integrate(int64_t n, State9 s, Rates
         part[blockIdx.x * 10 + 2 * threadIdx.x] = sh[0][threadIdx.x][0];
         part[blockIdx.x * 10 + 2 * threadIdx.x + 1] = sh[1][threadIdx.x][0];
     }
+    if (lg.pairs) {  // integer sums: exact in any order
+        for (int o = 32; o > 0; o >>= 1) npairs += __shfl_xor(npairs, o, 64);
+        if ((threadIdx.x & 63) == 0 && npairs) atomicAdd(lg.pairs, npairs);
+    }
     if (vo.K > 0) {  // the reduction above ended with a barrier: every count is in LDS
         for (int k = threadIdx.x; k < vo.K; k += kBlock) {
             if (hp[k]) atomicAdd(&vo.site_part[k], (unsigned long long)hp[k]);
@@ -188,7 +195,7 @@ static int integrate_blocks(int64_t n) {
 
 hipError_t launch_integrate(int64_t n, double *const st8[9], const Ws &w, double cfl, double dt_in,
                             const PairConst &pc, const double *t, hipStream_t st,
-                            const VoroDev *vo) {
+                            const VoroDev *vo, const ListGate *lg) {
     State9 s;
     for (int k = 0; k < 9; ++k) s.f[k] = st8[k];
     Rates5 r{{w.rate[0], w.rate[1], w.rate[2], w.rate[3], w.rate[4]}};
@@ -201,15 +208,17 @@ hipError_t launch_integrate(int64_t n, double *const st8[9], const Ws &w, double
         if (v.site_pairs) launch_fill_u64(v.site_pairs, 0ull, v.K, st);
         shm = (size_t)v.K * (3 * sizeof(double) + sizeof(unsigned long long) + sizeof(unsigned));
     }
+    const ListGate g = lg ? *lg : ListGate{nullptr, nullptr, nullptr, nullptr};
     int nb = integrate_blocks(n);
-    k_integrate<<<nb, kBlock, shm, st>>>(n, s, r, w.dtmin, cfl, dt_in, wall, v, w.tot_part);
+    k_integrate<<<nb, kBlock, shm, st>>>(n, s, r, w.dtmin, cfl, dt_in, wall, v, g, w.tot_part);
     return hipGetLastError();
 }
 
 __global__ __launch_bounds__(kBlock) void k_finish(const double *__restrict__ part, int nblocks,
                                                    const unsigned long long *dtmin, double cfl,
                                                    double dt_in, double *t, double *dt_used,
-                                                   double *totals, int swap_xy) {
+                                                   double *totals, int swap_xy, ListGate lg) {
+    if (lg.gate && *lg.gate == 0) return;
     __shared__ double sh[2][5][kBlock];
     DD acc[5];
     for (int k = 0; k < 5; ++k) acc[k] = DD{0.0, 0.0};
@@ -243,13 +252,16 @@ __global__ __launch_bounds__(kBlock) void k_finish(const double *__restrict__ pa
         double dt = step_dt(dtmin, cfl, dt_in);
         if (dt_used) *dt_used = dt;
         if (t) *t = *t + dt;
+        if (lg.steps) *lg.steps += 1;
     }
 }
 
 hipError_t launch_finish_step(int64_t n, const Ws &w, double cfl, double dt_in, double *t,
-                                double *dt_used, double *totals, int swap_xy, hipStream_t st) {
+                                double *dt_used, double *totals, int swap_xy, hipStream_t st,
+                                const ListGate *lg) {
+    const ListGate g = lg ? *lg : ListGate{nullptr, nullptr, nullptr, nullptr};
     k_finish<<<1, kBlock, 0, st>>>(w.tot_part, integrate_blocks(n), w.dtmin, cfl, dt_in, t,
-                                   dt_used, totals, swap_xy);
+                                   dt_used, totals, swap_xy, g);
     return hipGetLastError();
 }
 

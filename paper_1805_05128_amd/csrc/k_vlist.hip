@@ -96,7 +96,9 @@ __global__ __launch_bounds__(kBlock) void k_disp(int64_t n, const double *__rest
                                                  const double *__restrict__ y,
                                                  const double *__restrict__ z,
                                                  const double *__restrict__ ref,
-                                                 unsigned long long *__restrict__ out) {
+                                                 unsigned long long *__restrict__ out,
+                                                 const int32_t *__restrict__ gate) {
+    if (gate && *gate == 0) return;
     double m = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock) {
@@ -130,11 +132,63 @@ hipError_t launch_vlist(int64_t n, const double4 *A, const int32_t *cs, const Gr
 }
 
 hipError_t launch_disp(int64_t n, const double *x, const double *y, const double *z,
-                       const double *ref, unsigned long long *out, hipStream_t st) {
+                       const double *ref, unsigned long long *out, hipStream_t st,
+                       const int32_t *gate) {
     if (n <= 0) return hipSuccess;
     int64_t want = (n + kBlock - 1) / kBlock;
     unsigned nb = (unsigned)(want > kReduceBlocks ? kReduceBlocks : want);
-    k_disp<<<nb, kBlock, 0, st>>>(n, x, y, z, ref, out);
+    k_disp<<<nb, kBlock, 0, st>>>(n, x, y, z, ref, out, gate);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- list control block
+
+__global__ void k_vl_init(csph_vlist_ctl *ctl, const double *t, double margin, double vw2) {
+    ctl->t_build = t ? *t : 0.0;
+    ctl->disp = 0.0;
+    ctl->margin = margin;
+    ctl->vw2 = vw2;
+    ctl->pairs = 0;
+    ctl->steps = 0;
+    ctl->valid = 1;
+}
+
+// Before a list step: the lists give N(i) exactly while no pair can have entered the support
+// from beyond the horizon, 2 max|r - r_ref| + 2 |v_wall| (t - t_build) < beta H (the first
+// step after a build sees the build's own positions and wall); once that fails the lists stay
+// stale until the next build.  A passing step's displacement is then taken afresh.
+__global__ void k_vl_guard(csph_vlist_ctl *ctl, const double *t) {
+    const double tt = t ? *t : ctl->t_build;
+    const bool ok = ctl->valid != 0 &&
+                    (ctl->steps == 0 ||
+                     2.0 * ctl->disp + ctl->vw2 * (tt - ctl->t_build) < ctl->margin);
+    ctl->valid = ok ? 1 : 0;
+    if (ok) ctl->disp = 0.0;
+}
+
+hipError_t launch_vl_init(csph_vlist_ctl *ctl, const double *t, double margin, double vw2,
+                          hipStream_t st) {
+    k_vl_init<<<1, 1, 0, st>>>(ctl, t, margin, vw2);
+    return hipGetLastError();
+}
+
+hipError_t launch_vl_guard(csph_vlist_ctl *ctl, const double *t, hipStream_t st) {
+    k_vl_guard<<<1, 1, 0, st>>>(ctl, t);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy_i32(int32_t *__restrict__ dst,
+                                                     const int32_t *__restrict__ src, int64_t n,
+                                                     const int32_t *__restrict__ gate) {
+    if (gate && *gate == 0) return;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+hipError_t launch_copy_i32(int32_t *dst, const int32_t *src, int64_t n, const int32_t *gate,
+                           hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_copy_i32<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(dst, src, n, gate);
     return hipGetLastError();
 }
 

@@ -116,7 +116,7 @@ def test_vlist_build_rejects_misaligned_list_storage():
     dev = lambda addr, t: C.cast(C.c_void_p(addr), C.POINTER(t))
     st = L.csph_vlist_build(C.byref(a), C.byref(b), C.byref(p), None, 0.3, 64,
                             dev(65536, C.c_int32), dev(131072 + 4, C.c_int32),
-                            dev(262144, C.c_double), None, None, 0, None, None)
+                            dev(262144, C.c_double), None, None, None, 0, None, None)
     assert st == N.CSPH_EINVAL
     assert b"16-byte aligned" in L.csph_last_error()
 
@@ -167,3 +167,17 @@ def test_key_mode_checked():
     st = L.csph_bin(x, x, x, 10, C.byref(g), None, dev(8192, C.c_int32),
                     dev(16384, C.c_int32), 100, None, 0, None, None)
     assert st == N.CSPH_ECAPACITY and b"513" in L.csph_last_error()
+
+
+def test_list_step_needs_its_control_block():
+    """csph_step_vlist checks the lists' exactness bound on the device, in their control
+    block: a missing or misaligned block is refused on the host, before any device work."""
+    L = N.load()
+    p = P.Params().c()
+    a = _fake_state(4096)
+    dev = lambda addr, t: C.cast(C.c_void_p(addr), C.POINTER(t))
+    for ctl in (None, C.c_void_p(1 << 23 | 4)):
+        st = L.csph_step_vlist(C.byref(a), C.byref(p), dev(1 << 24, C.c_double), 0.0, None, None,
+                               None, None, dev(1 << 20, C.c_int32), dev(1 << 21, C.c_int32), 64,
+                               dev(1 << 22, C.c_double), ctl, None, 0, None, None)
+        assert st == N.CSPH_EINVAL and b"ctl" in L.csph_last_error()

@@ -161,6 +161,39 @@ def test_verlet_run_mixed_follows_oracle(case):
     assert worst <= 1e-4
 
 
+@pytest.mark.parametrize("case", ["moving", "wall"])
+def test_verlet_advance_batches_equal_single_steps(case):
+    """advance(k) issues the list steps without waiting and lets the device guard stop a
+    stale list; it gives bit for bit the states of k single steps (the same rebuilds at the
+    same steps), and the control block's pair counts add up to the steps' neighbour counts."""
+    w = CASES[case]()
+    print(f"[case] verlet advance {case} n={w.n}", flush=True)
+    params = P.Params.from_workload(w, precision="fp64", reorder=True)
+    out = []
+    for batched in (False, True):
+        g = P.state_from_workload(w, params, DEV, with_id=True)
+        sc = P.StepScalars(DEV, t0=0.0)
+        run = P.VerletRun(g, params, beta=0.3, n_upd=5)
+        cnt = torch.empty(w.n, dtype=torch.int32, device=DEV)
+        total = 0
+        if batched:
+            st = run.advance(sc, 12, nbr_count=cnt)
+        else:
+            for _ in range(12):
+                st = run.step(sc, nbr_count=cnt)
+                total += int(cnt.sum().item())
+        torch.cuda.synchronize()
+        r = st.numpy()
+        r.update(t=to_np(sc.t), tot=to_np(sc.totals))
+        out.append((r, run.builds, run.pairs, total))
+    (a, ba, pa, ta), (b, bb, pb, _) = out
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    assert ba == bb and pa == pb == ta
+    if case == "moving":
+        assert ba > 3  # the guard stopped lists before n_upd steps
+
+
 def test_verlet_run_grows_a_small_cap():
     w = ci.config0()
     run, worst = _run(w, "fp64", beta=0.5, n_upd=4, steps=5, cap=8)
