@@ -55,6 +55,8 @@ class Workload:
     kappa: float = KAPPA
     cell_size: float = H_SMOOTH * KAPPA
     wall: Optional[Tuple[float, float]] = None  # (x0, velocity) of a +x-facing piston
+    periodic: int = 0  # bit mask of periodic axes (1 x, 2 y, 4 z) ...
+    box: Optional[Tuple[Tuple[float, float, float], Tuple[float, float, float]]] = None  # ... box
     cfl: float = 0.3
     steps: int = 1
     sites: Optional[np.ndarray] = None  # (K, 3) Voronoi generators
@@ -264,6 +266,17 @@ def jittered_block(nx: int, ny: int, nz: int, seed: int, rho=1.0, p=1.0,
         x, y, z = jitter(r[0], x, y, z, amp=amp)
     st = _base(x, y, z, rho, p, v=v)
     return Workload(name=f"block{nx}x{ny}x{nz}_s{seed}", eos=eos or [(EOS_IDEAL, 1.4, 0.0)], **st)
+
+
+def periodic_block(nx: int, ny: int, nz: int, seed: int, periodic: int = 7, amp=JITTER,
+                   rho=1.0, p=1.0, v=(0.0, 0.0, 0.0), eos=None) -> Workload:
+    """Jittered lattice filling the box [0, n)^3 exactly (spacing 1, sites at i + 1/2), periodic
+    along the axes of the bit mask ``periodic`` (1 x, 2 y, 4 z)."""
+    w = jittered_block(nx, ny, nz, seed=seed, rho=rho, p=p, v=v, eos=eos, amp=amp)
+    w.periodic = int(periodic)
+    w.box = ((0.0, 0.0, 0.0), (float(nx), float(ny), float(nz)))
+    w.name = f"periodic{periodic}_{nx}x{ny}x{nz}_s{seed}"
+    return w
 
 
 def voronoi_sites(k: int, seed: int, box) -> np.ndarray:

@@ -56,6 +56,10 @@ class Cfg(C.Structure):
         ("eos_rho0", C.c_double * MAX_EOS),
         ("eos_ca", C.c_double * MAX_EOS),
         ("eos_sa", C.c_double * MAX_EOS),
+        ("periodic", C.c_int32),
+        ("pad2", C.c_int32),
+        ("box_lo", C.c_double * 3),
+        ("box_hi", C.c_double * 3),
     ]
 
 
@@ -135,7 +139,8 @@ def num_threads() -> int:
 
 
 def make_cfg(eos, h=1.5, kappa=2.0, h_mode=0, wall=None, cfl=0.3, search=0, cell_size=0.0,
-             nthreads=0) -> Cfg:
+             nthreads=0, periodic=0, box=None) -> Cfg:
+    """periodic: bit mask of periodic axes (1 x, 2 y, 4 z) with box = (lo[3], hi[3])."""
     c = Cfg()
     c.h, c.kappa, c.h_mode = h, kappa, h_mode
     c.n_eos = len(eos)
@@ -148,12 +153,16 @@ def make_cfg(eos, h=1.5, kappa=2.0, h_mode=0, wall=None, cfl=0.3, search=0, cell
     if wall is not None:
         c.wall, c.wall_x0, c.wall_v = 1, float(wall[0]), float(wall[1])
     c.cfl, c.search, c.cell_size, c.nthreads = cfl, search, cell_size, nthreads
+    c.periodic = int(periodic)
+    if box is not None:
+        for a in range(3):
+            c.box_lo[a], c.box_hi[a] = float(box[0][a]), float(box[1][a])
     return c
 
 
 def cfg_for(w, search=0, nthreads=0, **over) -> Cfg:
     kw = dict(eos=w.eos, h=w.h, kappa=w.kappa, wall=w.wall, cfl=w.cfl, search=search,
-              cell_size=w.cell_size, nthreads=nthreads)
+              cell_size=w.cell_size, nthreads=nthreads, periodic=w.periodic, box=w.box)
     kw.update(over)
     return make_cfg(**kw)
 

@@ -29,6 +29,10 @@
  *                           (sec. 4.1, the support statement before sec. 4.2);
  *                           brute force over all j is the authority, a cell
  *                           list (sec. 4.2, eq. Dcell) gives the same sets.
+ *                           With periodic axes (the PBC of the paper's static
+ *                           and ejecta tests, secs. 6 and 7.1) partners are the
+ *                           images of j: displacement (x_j - x_i) - k L per
+ *                           periodic axis, k in {-1, 0, 1}.
  *   oracle_rates            eqs. SPH:Conti, SPH:Pulse, SPH:Energy.
  *   oracle_step             "renew particle positions and states" and the
  *                           global time step (Algorithm 1); symplectic Euler
@@ -74,6 +78,12 @@ typedef struct {
     double eos_rho0[ORACLE_MAX_EOS];
     double eos_ca[ORACLE_MAX_EOS];
     double eos_sa[ORACLE_MAX_EOS];
+    /* periodic boundaries: bit a of `periodic` makes axis a periodic with period
+     * box_hi[a] - box_lo[a] (every particle inside [box_lo, box_hi) along it) */
+    int32_t periodic;
+    int32_t pad2;
+    double box_lo[3];
+    double box_hi[3];
 } oracle_cfg;
 
 /* ------------------------------------------------------------------ */
@@ -343,10 +353,16 @@ static double support_of(const nbr_space *sp, int64_t i, int64_t j) {
     return cfg->h_mode == 1 ? cfg->kappa * (0.5 * (sp->d[i] + sp->d[j])) : cfg->kappa * cfg->h;
 }
 
-static int in_support(const nbr_space *sp, int64_t i, int64_t j) {
-    double dx = sp->x[j] - sp->x[i], dy = sp->y[j] - sp->y[i], dz = sp->z[j] - sp->z[i];
-    double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
-    return r2 < support_sq(sp, i, j);
+/* Period of axis a, or 0 when it is not periodic. */
+static double period(const oracle_cfg *cfg, int a) {
+    return (cfg->periodic >> a) & 1 ? cfg->box_hi[a] - cfg->box_lo[a] : 0.0;
+}
+
+/* Component a of the displacement from i to image k of j: (x_j - x_i) - k L.  The difference
+ * comes first, so swapping i and j (and k to -k) negates it exactly. */
+static double disp(double xj, double xi, int k, double L) {
+    double d = xj - xi;
+    return k ? d - (double)k * L : d;
 }
 
 static int cmp_i64(const void *a, const void *b) {
@@ -394,8 +410,63 @@ static int64_t candidates_at(const nbr_space *sp, double px, double py, double p
     return cnt;
 }
 
-static int64_t candidates(const nbr_space *sp, int64_t i, int64_t *buf, int64_t cap) {
-    return candidates_at(sp, sp->x[i], sp->y[i], sp->z[i], buf, cap);
+/* Partners of particle i: the images (j, k) with |d| < H_ij, d_a = (x_j,a - x_i,a) - k_a L_a
+ * (k_a = 0 on non-periodic axes), (j, k) != (i, 0); candidates are all j (brute force) or
+ * the cells around the image point x_i + k L.  The partners go to s->pr with their image
+ * shifts, ordered by j (each j appears at most once when every period exceeds twice the
+ * support).  Returns the count. */
+typedef struct { int64_t j; int k[3]; } partner;
+
+static int cmp_partner(const void *a, const void *b) {
+    const partner *p = (const partner *)a, *q = (const partner *)b;
+    if (p->j != q->j) return p->j < q->j ? -1 : 1;
+    for (int c = 0; c < 3; ++c)
+        if (p->k[c] != q->k[c]) return p->k[c] < q->k[c] ? -1 : 1;
+    return 0;
+}
+
+/* scratch of one worker: candidate indices, and the partners of one particle (grown on
+ * demand) */
+typedef struct { int64_t *buf; partner *pr; int64_t cap, pcap; } nbr_scratch;
+
+static int64_t partners_of(const nbr_space *sp, int64_t i, nbr_scratch *s) {
+    int64_t *buf = s->buf, cap = s->cap;
+    const oracle_cfg *cfg = sp->cfg;
+    const double L[3] = {period(cfg, 0), period(cfg, 1), period(cfg, 2)};
+    int64_t cnt = 0;
+    for (int kz = -1; kz <= 1; ++kz) {
+        if (kz && !L[2]) continue;
+        for (int ky = -1; ky <= 1; ++ky) {
+            if (ky && !L[1]) continue;
+            for (int kx = -1; kx <= 1; ++kx) {
+                if (kx && !L[0]) continue;
+                int64_t nc = candidates_at(sp, sp->x[i] + kx * L[0], sp->y[i] + ky * L[1],
+                                           sp->z[i] + kz * L[2], buf, cap);
+                for (int64_t q = 0; q < nc; ++q) {
+                    int64_t j = buf[q];
+                    if (j == i && !kx && !ky && !kz) continue;
+                    double dx = disp(sp->x[j], sp->x[i], kx, L[0]);
+                    double dy = disp(sp->y[j], sp->y[i], ky, L[1]);
+                    double dz = disp(sp->z[j], sp->z[i], kz, L[2]);
+                    double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
+                    if (!(r2 < support_sq(sp, i, j))) continue;
+                    if (cnt == s->pcap) {
+                        s->pcap *= 2;
+                        s->pr = (partner *)realloc(s->pr, sizeof(partner) * (size_t)s->pcap);
+                        if (!s->pr) abort();
+                    }
+                    partner *out = s->pr;
+                    out[cnt].j = j;
+                    out[cnt].k[0] = kx;
+                    out[cnt].k[1] = ky;
+                    out[cnt].k[2] = kz;
+                    ++cnt;
+                }
+            }
+        }
+    }
+    qsort(s->pr, (size_t)cnt, sizeof(partner), cmp_partner);
+    return cnt;
 }
 
 static double max_support(const oracle_cfg *cfg, int64_t n, const double *d) {
@@ -438,35 +509,38 @@ typedef struct {
     const int64_t *offsets; int32_t *idx;  /* pass 2 */
 } nbr_ctx;
 
+static int scratch_init(nbr_scratch *s, int64_t n) {
+    s->cap = n > 0 ? n : 1;
+    s->pcap = 1024;
+    s->buf = (int64_t *)malloc(sizeof(int64_t) * (size_t)s->cap);
+    s->pr = (partner *)malloc(sizeof(partner) * (size_t)s->pcap);
+    return s->buf && s->pr ? 0 : -1;
+}
+
+static void scratch_free(nbr_scratch *s) {
+    free(s->buf);
+    free(s->pr);
+}
+
 static void nbr_count_range(void *vctx, int64_t lo, int64_t hi) {
     nbr_ctx *ctx = (nbr_ctx *)vctx;
     nbr_space *sp = ctx->sp;
-    int64_t cap = sp->n;
-    int64_t *buf = (int64_t *)malloc(sizeof(int64_t) * (size_t)(cap > 0 ? cap : 1));
-    for (int64_t i = lo; i < hi; ++i) {
-        int64_t nc = candidates(sp, i, buf, cap), cnt = 0;
-        for (int64_t k = 0; k < nc; ++k) {
-            int64_t j = buf[k];
-            if (j != i && in_support(sp, i, j)) ++cnt;
-        }
-        ctx->count[i] = cnt;
-    }
-    free(buf);
+    nbr_scratch s;
+    if (scratch_init(&s, sp->n) != 0) { scratch_free(&s); return; }
+    for (int64_t i = lo; i < hi; ++i) ctx->count[i] = partners_of(sp, i, &s);
+    scratch_free(&s);
 }
 
 static void nbr_fill_range(void *vctx, int64_t lo, int64_t hi) {
     nbr_ctx *ctx = (nbr_ctx *)vctx;
     nbr_space *sp = ctx->sp;
-    int64_t cap = sp->n;
-    int64_t *buf = (int64_t *)malloc(sizeof(int64_t) * (size_t)(cap > 0 ? cap : 1));
+    nbr_scratch s;
+    if (scratch_init(&s, sp->n) != 0) { scratch_free(&s); return; }
     for (int64_t i = lo; i < hi; ++i) {
-        int64_t nc = candidates(sp, i, buf, cap), w = ctx->offsets[i];
-        for (int64_t k = 0; k < nc; ++k) {
-            int64_t j = buf[k];
-            if (j != i && in_support(sp, i, j)) ctx->idx[w++] = (int32_t)j;
-        }
+        int64_t np = partners_of(sp, i, &s), w = ctx->offsets[i];
+        for (int64_t q = 0; q < np; ++q) ctx->idx[w++] = (int32_t)s.pr[q].j;
     }
-    free(buf);
+    scratch_free(&s);
 }
 
 /* CSR of N(i) = { j != i : ((dx*dx)+(dy*dy))+(dz*dz) < H_ij^2 }, rows ascending.
@@ -504,19 +578,17 @@ typedef struct {
     const int64_t *sample; /* NULL: every particle; else output k is particle sample[k] */
 } rates_ctx;
 
-/* One interaction of particle i with a partner at position (xj, yj, zj)
- * moving with (vxj, vyj, vzj) that carries j's P, Z = rho c, m/rho.
+/* One interaction of particle i with a partner at displacement (dx, dy, dz)
+ * from it, moving with (vxj, vyj, vzj), that carries j's P, Z = rho c, m/rho.
  * Adds to the three j-sums of eqs. SPH:Conti / SPH:Pulse / SPH:Energy:
  *   s_rho += (m_j/rho_j) (v_i^R - v*) e.gradW
  *   s_v   += (m_j/rho_j) P* gradW
  *   s_E   += (m_j/rho_j) P* v* e.gradW
  * with gradW = grad_i W_ij = -e^R W'_ij.  Also updates the signal speed. */
-static void pair_term(double xi, double yi, double zi, double vxi, double vyi, double vzi,
-                      double Pi, double Zi, double ci,
-                      double xj, double yj, double zj, double vxj, double vyj, double vzj,
+static void pair_term(double dx, double dy, double dz, double vxi, double vyi, double vzi,
+                      double Pi, double Zi, double ci, double vxj, double vyj, double vzj,
                       double Pj, double Zj, double cj, double Vj, double H,
                       double *s_rho, double s_v[3], double *s_E, double *sig) {
-    double dx = xj - xi, dy = yj - yi, dz = zj - zi;
     double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
     if (r2 == 0.0) return; /* coincident: e undefined, W'(0) = 0 */
     double r = sqrt(r2);
@@ -541,46 +613,55 @@ static void rates_range(void *vctx, int64_t lo, int64_t hi) {
     rates_ctx *ctx = (rates_ctx *)vctx;
     nbr_space *sp = ctx->sp;
     const oracle_cfg *cfg = sp->cfg;
-    int64_t cap = sp->n;
-    int64_t *buf = (int64_t *)malloc(sizeof(int64_t) * (size_t)(cap > 0 ? cap : 1));
+    nbr_scratch scr;
+    if (scratch_init(&scr, sp->n) != 0) { scratch_free(&scr); return; }
+    int64_t cap = scr.cap, *buf = scr.buf;
+    const double L[3] = {period(cfg, 0), period(cfg, 1), period(cfg, 2)};
     double xw = cfg->wall_x0 + cfg->wall_v * ctx->t;
     for (int64_t o = lo; o < hi; ++o) {
         int64_t i = ctx->sample ? ctx->sample[o] : o;
         double Zi = ctx->rho[i] * ctx->c[i];
         double s_rho = 0.0, s_v[3] = {0.0, 0.0, 0.0}, s_E = 0.0, sig = ctx->c[i];
-        int64_t cnt = 0;
-        int64_t nc = candidates(sp, i, buf, cap);
-        /* real neighbours, ascending j */
-        for (int64_t k = 0; k < nc; ++k) {
-            int64_t j = buf[k];
-            if (j == i || !in_support(sp, i, j)) continue;
-            ++cnt;
+        /* real neighbours (periodic images included), ascending j */
+        int64_t cnt = partners_of(sp, i, &scr);
+        for (int64_t q = 0; q < cnt; ++q) {
+            int64_t j = scr.pr[q].j;
             double Zj = ctx->rho[j] * ctx->c[j];
             double Vj = ctx->m[j] / ctx->rho[j];
-            pair_term(sp->x[i], sp->y[i], sp->z[i], ctx->vx[i], ctx->vy[i], ctx->vz[i],
-                      ctx->P[i], Zi, ctx->c[i],
-                      sp->x[j], sp->y[j], sp->z[j], ctx->vx[j], ctx->vy[j], ctx->vz[j],
+            pair_term(disp(sp->x[j], sp->x[i], scr.pr[q].k[0], L[0]),
+                      disp(sp->y[j], sp->y[i], scr.pr[q].k[1], L[1]),
+                      disp(sp->z[j], sp->z[i], scr.pr[q].k[2], L[2]), ctx->vx[i], ctx->vy[i],
+                      ctx->vz[i], ctx->P[i], Zi, ctx->c[i], ctx->vx[j], ctx->vy[j], ctx->vz[j],
                       ctx->P[j], Zj, ctx->c[j], Vj, support_of(sp, i, j),
                       &s_rho, s_v, &s_E, &sig);
         }
-        /* mirror partners across the piston plane, ascending j (j = i included): the
-         * particles whose image lies within the support of i, i.e. those within the support
-         * of the image of i */
+        /* mirror partners across the piston plane (j = i included): the particles whose
+         * image lies within the support of i, i.e. those within the support of the image of
+         * i; with periodic y or z, also the translated images of those (the wall's own axis
+         * x is never periodic).  Ascending (k_z, k_y), then j. */
         if (cfg->wall) {
-            nc = candidates_at(sp, 2.0 * xw - sp->x[i], sp->y[i], sp->z[i], buf, cap);
-            for (int64_t k = 0; k < nc; ++k) {
-                int64_t j = buf[k];
-                double xg = 2.0 * xw - sp->x[j];
-                double dx = xg - sp->x[i], dy = sp->y[j] - sp->y[i], dz = sp->z[j] - sp->z[i];
-                double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
-                if (!(r2 < support_sq(sp, i, j))) continue;
-                double Zj = ctx->rho[j] * ctx->c[j];
-                double Vj = ctx->m[j] / ctx->rho[j];
-                pair_term(sp->x[i], sp->y[i], sp->z[i], ctx->vx[i], ctx->vy[i], ctx->vz[i],
-                          ctx->P[i], Zi, ctx->c[i],
-                          xg, sp->y[j], sp->z[j], 2.0 * cfg->wall_v - ctx->vx[j], ctx->vy[j],
-                          ctx->vz[j], ctx->P[j], Zj, ctx->c[j], Vj, support_of(sp, i, j),
-                          &s_rho, s_v, &s_E, &sig);
+            for (int kz = -1; kz <= 1; ++kz) {
+                if (kz && !L[2]) continue;
+                for (int ky = -1; ky <= 1; ++ky) {
+                    if (ky && !L[1]) continue;
+                    int64_t nc = candidates_at(sp, 2.0 * xw - sp->x[i], sp->y[i] + ky * L[1],
+                                               sp->z[i] + kz * L[2], buf, cap);
+                    for (int64_t k = 0; k < nc; ++k) {
+                        int64_t j = buf[k];
+                        double xg = 2.0 * xw - sp->x[j];
+                        double dx = xg - sp->x[i];
+                        double dy = disp(sp->y[j], sp->y[i], ky, L[1]);
+                        double dz = disp(sp->z[j], sp->z[i], kz, L[2]);
+                        double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
+                        if (!(r2 < support_sq(sp, i, j))) continue;
+                        double Zj = ctx->rho[j] * ctx->c[j];
+                        double Vj = ctx->m[j] / ctx->rho[j];
+                        pair_term(dx, dy, dz, ctx->vx[i], ctx->vy[i], ctx->vz[i], ctx->P[i], Zi,
+                                  ctx->c[i], 2.0 * cfg->wall_v - ctx->vx[j], ctx->vy[j],
+                                  ctx->vz[j], ctx->P[j], Zj, ctx->c[j], Vj, support_of(sp, i, j),
+                                  &s_rho, s_v, &s_E, &sig);
+                    }
+                }
             }
         }
         double rho_i = ctx->rho[i];
@@ -592,7 +673,7 @@ static void rates_range(void *vctx, int64_t lo, int64_t hi) {
         if (ctx->signal) ctx->signal[o] = sig;
         if (ctx->nbr_count) ctx->nbr_count[o] = cnt;
     }
-    free(buf);
+    scratch_free(&scr);
 }
 
 /* Rates of every particle at time t (t only places the piston).  Returns the
@@ -667,6 +748,7 @@ double oracle_dt(const oracle_cfg *cfg, int64_t n, const double *signal, const d
  * x_w(t + dt) is reflected about it, as off a rigid wall in the wall's
  * frame: x <- 2 x_w - x, v_x <- 2 v_w - v_x, with its specific internal
  * energy kept (E changes by the kinetic-energy difference, the wall's work).
+ * Periodic axes wrap the new positions back into the box.
  * State arrays are updated in place.  Returns the non-physical count from
  * the rate evaluation (or -1). */
 int64_t oracle_step(const oracle_cfg *cfg, int64_t n, double *x, double *y, double *z,
@@ -697,6 +779,15 @@ int64_t oracle_step(const oracle_cfg *cfg, int64_t n, double *x, double *y, doub
                 E[i] = E[i] + 0.5 * ((vr * vr) - (vx[i] * vx[i]));
                 vx[i] = vr;
                 x[i] = 2.0 * xw - x[i];
+            }
+            /* periodic axes: back into [box_lo, box_hi) (a particle moves less than a period
+             * per step) */
+            double *pos[3] = {x, y, z};
+            for (int a = 0; a < 3; ++a) {
+                double Lp = period(cfg, a);
+                if (!Lp) continue;
+                if (pos[a][i] >= cfg->box_hi[a]) pos[a][i] = pos[a][i] - Lp;
+                else if (pos[a][i] < cfg->box_lo[a]) pos[a][i] = pos[a][i] + Lp;
             }
         }
         *t = t_new;
