@@ -124,7 +124,18 @@ typedef struct {
     int32_t key_mode;  /* CSPH_KEY_LINEAR | CSPH_KEY_MORTON: keys of csph_grid_build's mesh */
     int32_t check_nonphys; /* csph_step: 1 = wait for the step's kernels and return
                               CSPH_ENONPHYS if its EOS met a non-physical state */
-    int32_t pad;
+    int32_t periodic;  /* periodic boundaries (secs. 6 and 7.1 run their plates periodic
+                          across the impact direction): bit a (1 x, 2 y, 4 z) makes axis a
+                          periodic on [box_lo[a], box_hi[a]) with period L_a = box_hi[a] -
+                          box_lo[a].  The partners of i are the images (j, k) with
+                          d_a = (x_j,a - x_i,a) - k_a L_a, k_a in {-1, 0, 1} (0 on the other
+                          axes), |d| < H_ij, (j, k) != (i, 0); csph_step wraps a new position
+                          x >= box_hi to x - L, x < box_lo to x + L.  Needs L_a > 2 H (1 +
+                          1e-6) (H the maximum support), every position within [box_lo,
+                          box_hi] on the periodic axes, and x not periodic with the wall;
+                          else CSPH_EINVAL.  Not taken by the Verlet-list and adjoint calls
+                          (CSPH_EINVAL).  0: open boundaries */
+    double box_lo[3], box_hi[3]; /* the periodic box (read on the periodic axes only) */
 } csph_params;
 
 /* Particle state.  x..m: FP64 arrays of n entries.  mat: int32 material id

@@ -39,7 +39,7 @@ class CsphParams(C.Structure):
         ("wall_x0", C.c_double), ("wall_v", C.c_double),
         ("eos", CsphEos * CSPH_MAX_EOS),
         ("reorder", C.c_int32), ("key_mode", C.c_int32), ("check_nonphys", C.c_int32),
-        ("pad", C.c_int32),
+        ("periodic", C.c_int32), ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
     ]
 
 

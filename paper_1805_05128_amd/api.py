@@ -63,6 +63,8 @@ class Params:
     reorder: bool = True
     key_mode: str = "linear"  # "linear" | "morton": keys csph_bin reports
     check_nonphys: bool = False  # csph_step: wait and raise NonPhysicalState (state written)
+    periodic: int = 0  # bit mask of periodic axes (1 x, 2 y, 4 z) ...
+    box: Optional[Tuple[Tuple[float, float, float], Tuple[float, float, float]]] = None  # ... box
 
     def c(self) -> N.CsphParams:
         p = N.CsphParams()
@@ -81,12 +83,16 @@ class Params:
         p.reorder = 1 if self.reorder else 0
         p.key_mode = N.CSPH_KEY_MORTON if self.key_mode == "morton" else N.CSPH_KEY_LINEAR
         p.check_nonphys = 1 if self.check_nonphys else 0
+        p.periodic = int(self.periodic)
+        if self.box is not None:
+            for a in range(3):
+                p.box_lo[a], p.box_hi[a] = float(self.box[0][a]), float(self.box[1][a])
         return p
 
     @classmethod
     def from_workload(cls, w, **over) -> "Params":
         kw = dict(eos=list(w.eos), h=w.h, kappa=w.kappa, cell_size=w.cell_size, cfl=w.cfl,
-                  wall=w.wall)
+                  wall=w.wall, periodic=getattr(w, "periodic", 0), box=getattr(w, "box", None))
         kw.update(over)
         return cls(**kw)
 

@@ -165,6 +165,38 @@ static csph_status check_params(const csph_params *p, bool need_pair_d, const do
     if (!std::isfinite(p->cfl)) return fail(CSPH_EINVAL, "cfl not finite");
     if (p->wall && (!std::isfinite(p->wall_x0) || !std::isfinite(p->wall_v)))
         return fail(CSPH_EINVAL, "wall position/velocity not finite");
+    if (p->periodic < 0 || p->periodic > 7) return fail(CSPH_EINVAL, "periodic mask %d unknown", p->periodic);
+    if (p->wall && (p->periodic & 1)) return fail(CSPH_EINVAL, "the wall's axis x cannot be periodic");
+    for (int a = 0; a < 3; ++a)
+        if (((p->periodic >> a) & 1) &&
+            !(std::isfinite(p->box_lo[a]) && std::isfinite(p->box_hi[a]) && p->box_hi[a] > p->box_lo[a]))
+            return fail(CSPH_EINVAL, "periodic axis %d needs a finite box with box_hi > box_lo", a);
+    return CSPH_OK;
+}
+
+// Near-face band of the periodic image search: the support with a relative margin (a pair's
+// FP64 offset carries a few ulp of the period).
+static double periodic_band(double H) { return H * (1.0 + 1e-6); }
+
+// Periodic boxes against the particle bounds (b: min x, y, z, max x, y, z in the kernels'
+// axes, which swap x and y when there is a wall) and the maximum support: each period must
+// exceed twice the near-face band (so a particle has images across one face per axis at most,
+// and no pair of particles more than one image of each other) and the positions must lie in
+// the box.
+static csph_status check_box(const csph_params *p, const double b[6], double Hmax, int64_t n) {
+    if (!p->periodic || n == 0) return CSPH_OK;
+    const double hb = periodic_band(Hmax);
+    for (int a = 0; a < 3; ++a) {
+        if (!((p->periodic >> a) & 1)) continue;
+        const int k = p->wall && a < 2 ? 1 - a : a;  // the kernels' axis of the caller's axis a
+        const double L = p->box_hi[a] - p->box_lo[a];
+        if (!(L > 2.0 * hb))
+            return fail(CSPH_EINVAL, "period %g of axis %d must exceed twice the support %g (1 + 1e-6)",
+                        L, a, Hmax);
+        if (!(b[k] >= p->box_lo[a] && b[3 + k] <= p->box_hi[a]))
+            return fail(CSPH_EINVAL, "positions along periodic axis %d lie outside [%g, %g]", a,
+                        p->box_lo[a], p->box_hi[a]);
+    }
     return CSPH_OK;
 }
 
@@ -203,6 +235,17 @@ static PairConst pair_const(const csph_params *p, double dmax) {
     c.wall = p->wall != 0;
     c.wall_y0 = p->wall_x0;  // the kernels see x and y swapped when there is a wall
     c.wall_v = p->wall_v;
+    c.per = 0;
+    c.hb = periodic_band(H);
+    for (int a = 0; a < 3; ++a) {
+        const int k = p->wall && a < 2 ? 1 - a : a;
+        if ((p->periodic >> a) & 1) {
+            c.per |= 1 << k;
+            c.lo[k] = p->box_lo[a];
+            c.hi[k] = p->box_hi[a];
+            c.L[k] = p->box_hi[a] - p->box_lo[a];
+        }
+    }
     return c;
 }
 
@@ -276,6 +319,8 @@ static int morton_bits(const int32_t dims[3]) {
 // particle set moves (a piston pushing the minimum along by a fraction of a cell per step
 // would otherwise move every particle's cell index and scatter the next step's gather).
 // Results do not depend on the mesh: membership is decided by exact FP64 distances.
+// snap = true also checks the periodic box against the bounds (the arrays are then in the
+// kernels' axes, x and y swapped when p has a wall).
 static csph_status make_grid(const double *x, const double *y, const double *z, const double *d,
                              int64_t n, const csph_params *p, void *ws, size_t ws_bytes,
                              hipStream_t st, csph_grid *g, double *dmax, double *ymin,
@@ -296,6 +341,10 @@ static csph_status make_grid(const double *x, const double *y, const double *z, 
     *dmax = b[6];
     *ymin = b[1];
     double Hmax = p->h_mode == CSPH_H_PAIR ? p->kappa * b[6] : p->kappa * p->h;
+    if (snap) {
+        csph_status r = check_box(p, b, Hmax, n);
+        if (r) return r;
+    }
     double D = p->cell_size > 0.0 ? p->cell_size : Hmax;
     if (!(D > 0.0)) D = 1.0;  // pair mode with all d = 0: any mesh works
     g->cell = D;
@@ -480,6 +529,9 @@ csph_status csph_neighbors(const csph_state *s, const csph_params *p, int64_t *o
     int64_t n = s->n;
     csph_grid g;
     double dmax, ymin;
+    csph_params pn0 = *p;  // N(i) has no mirror partners: the caller's axes, no wall
+    pn0.wall = 0;
+    p = &pn0;
     r = make_grid(s->x, s->y, s->z, s->d, n, p, ws, ws_bytes, st, &g, &dmax, &ymin, true);
     if (r) return r;
     r = need_ws(ws_bytes, n, g.ncell, ws_needed);
@@ -733,6 +785,7 @@ csph_status csph_vlist_build(const csph_state *s_in, csph_state *s_out, const cs
     csph_status r = check_params(p, false, nullptr);
     if (r) return r;
     if (p->h_mode != CSPH_H_FIXED) return fail(CSPH_EINVAL, "Verlet lists need fixed-h mode");
+    if (p->periodic) return fail(CSPH_EINVAL, "Verlet lists do not support periodic boundaries");
     if (!(beta >= 0.0) || !std::isfinite(beta)) return fail(CSPH_EINVAL, "beta must be >= 0");
     if (cap < kVlChunk || cap % kVlChunk)
         return fail(CSPH_EINVAL, "cap must be a positive multiple of %d", kVlChunk);
@@ -811,6 +864,7 @@ csph_status csph_step_vlist(csph_state *s, const csph_params *p, double *t, doub
     csph_status r = check_params(p, false, nullptr);
     if (r) return r;
     if (p->h_mode != CSPH_H_FIXED) return fail(CSPH_EINVAL, "Verlet lists need fixed-h mode");
+    if (p->periodic) return fail(CSPH_EINVAL, "Verlet lists do not support periodic boundaries");
     if (!(p->cfl > 0.0) && !(std::isfinite(dt_in) && dt_in >= 0.0))
         return fail(CSPH_EINVAL, "cfl <= 0 needs a finite dt_in >= 0");
     if (p->wall && !t) return fail(CSPH_EINVAL, "the wall position needs t");
@@ -938,6 +992,7 @@ static csph_status check_vjp_params(const csph_params *p) {
         if (p->eos[k].type == CSPH_EOS_MIE_GRUNEISEN)
             return fail(CSPH_EINVAL, "the adjoint supports ideal and stiffened gas only");
     if (p->wall) return fail(CSPH_EINVAL, "the adjoint does not support the piston wall");
+    if (p->periodic) return fail(CSPH_EINVAL, "the adjoint does not support periodic boundaries");
     return CSPH_OK;
 }
 

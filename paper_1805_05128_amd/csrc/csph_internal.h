@@ -98,6 +98,14 @@ struct PairConst {
     double wall_y0, wall_v;
     int pair_mode;
     int wall;
+    // Periodic axes in the kernels' axes (bit a), the box [lo, hi) of each and its period
+    // L = hi - lo; hb: the near-face band (the support with a relative margin of 1e-6).  A
+    // particle within hb of the low face of a periodic axis has its image partners across that
+    // face at x_j - L (shift k = +1), one within hb of the high face at x_j + L (k = -1); the
+    // library requires L > 2 hb, so no particle is near both faces of an axis.
+    int per;
+    double hb;
+    double lo[3], hi[3], L[3];
 };
 
 struct EosDev {

@@ -2,8 +2,11 @@
 // as CSR over input indices, rows ascending.  Verification form only: the
 // rate kernels gather partners on the fly and never materialise this list.
 // The test is the FP64 expression ((dx*dx)+(dy*dy))+(dz*dz) < H*H without
-// contraction, so membership is exact.
+// contraction, so membership is exact.  With periodic axes the partners
+// include the periodic images, d = (r_j - r_i) - k L (each j appears once:
+// the periods exceed twice the support).
 #include "csph_internal.h"
+#include "stencil.h"
 
 namespace csph {
 
@@ -33,7 +36,7 @@ hipError_t launch_gather_pos(int64_t n, const int32_t *perm, const double *x, co
     return hipGetLastError();
 }
 
-template <bool PAIR, bool FILL>
+template <bool PAIR, bool FILL, bool PER>
 __global__ __launch_bounds__(kBlock) void k_nbr(int64_t n, GridDev g, PairConst pc,
                                                 const double *__restrict__ x,
                                                 const double *__restrict__ y,
@@ -48,36 +51,49 @@ __global__ __launch_bounds__(kBlock) void k_nbr(int64_t n, GridDev g, PairConst 
     if (s >= n) return;
     double xi = x[s], yi = y[s], zi = z[s];
     double di = PAIR ? d[s] : 0.0;
-    int cx = cell_coord(xi, g.ox, g.inv, g.dx);
-    int cy = cell_coord(yi, g.oy, g.inv, g.dy);
-    int cz = cell_coord(zi, g.oz, g.inv, g.dz);
     const int R = g.reach;
-    const int x0 = max(cx - R, 0), x1 = min(cx + R, g.dx - 1);
+    const int nf = PER ? image_faces(pc, xi, yi, zi) : 0;
     int i = perm[s];
     int64_t wpos = FILL ? offsets[i] : 0;
     int cnt = 0;
-    for (int oz = -R; oz <= R; ++oz) {
-        int zz = cz + oz;
-        if (zz < 0 || zz >= g.dz) continue;
-        for (int oy = -R; oy <= R; ++oy) {
-            int yy = cy + oy;
-            if (yy < 0 || yy >= g.dy) continue;
-            int row = (int)cell_key(g, 0, yy, zz);
-            int j0 = cs[row + x0], j1 = cs[row + x1 + 1];
-            for (int j = j0; j < j1; ++j) {
-                if (j == (int)s) continue;
-                double dx = x[j] - xi, dy = y[j] - yi, dz = z[j] - zi;
-                double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
-                double H2;
-                if (PAIR) {
-                    double H = pc.kappa * (0.5 * (di + d[j]));
-                    H2 = H * H;
-                } else {
-                    H2 = pc.H2;
-                }
-                if (r2 < H2) {
-                    if (FILL) idx[wpos + cnt] = perm[j];
-                    ++cnt;
+    // image m = 0: i itself; m > 0: the periodic image of i across the faces of mask m
+    for (int m = 0; m < (PER ? 8 : 1); ++m) {
+        if ((nf & m) != m) continue;
+        const double shx = image_shift(pc, nf, m, 0), shy = image_shift(pc, nf, m, 1),
+                     shz = image_shift(pc, nf, m, 2);
+        const int cx = m & 1 ? free_cell(xi + shx, g.ox, g.inv) : cell_coord(xi, g.ox, g.inv, g.dx);
+        const int cy = m & 2 ? free_cell(yi + shy, g.oy, g.inv) : cell_coord(yi, g.oy, g.inv, g.dy);
+        const int cz = m & 4 ? free_cell(zi + shz, g.oz, g.inv) : cell_coord(zi, g.oz, g.inv, g.dz);
+        const int x0 = max(cx - R, 0), x1 = min(cx + R, g.dx - 1);
+        if (x0 > x1) continue;
+        for (int oz = -R; oz <= R; ++oz) {
+            int zz = cz + oz;
+            if (zz < 0 || zz >= g.dz) continue;
+            for (int oy = -R; oy <= R; ++oy) {
+                int yy = cy + oy;
+                if (yy < 0 || yy >= g.dy) continue;
+                int row = (int)cell_key(g, 0, yy, zz);
+                int j0 = cs[row + x0], j1 = cs[row + x1 + 1];
+                for (int j = j0; j < j1; ++j) {
+                    if (m == 0 && j == (int)s) continue;
+                    double dx = x[j] - xi, dy = y[j] - yi, dz = z[j] - zi;
+                    if (PER) {
+                        dx = dx - shx;
+                        dy = dy - shy;
+                        dz = dz - shz;
+                    }
+                    double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
+                    double H2;
+                    if (PAIR) {
+                        double H = pc.kappa * (0.5 * (di + d[j]));
+                        H2 = H * H;
+                    } else {
+                        H2 = pc.H2;
+                    }
+                    if (r2 < H2) {
+                        if (FILL) idx[wpos + cnt] = perm[j];
+                        ++cnt;
+                    }
                 }
             }
         }
@@ -104,12 +120,15 @@ hipError_t launch_nbr_count(int64_t n, const GridDev &g, const PairConst &pc, co
                             const int32_t *perm, int32_t *count_orig, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
-    if (pc.pair_mode)
-        k_nbr<true, false><<<nb, kBlock, 0, st>>>(n, g, pc, x, y, z, d, cs, perm, count_orig,
+#define CSPH_NBR(P, X)                                                                    \
+    if (!!pc.pair_mode == P && !!pc.per == X)                                             \
+        k_nbr<P, false, X><<<nb, kBlock, 0, st>>>(n, g, pc, x, y, z, d, cs, perm, count_orig, \
                                                   nullptr, nullptr);
-    else
-        k_nbr<false, false><<<nb, kBlock, 0, st>>>(n, g, pc, x, y, z, d, cs, perm, count_orig,
-                                                   nullptr, nullptr);
+    CSPH_NBR(false, false)
+    CSPH_NBR(true, false)
+    CSPH_NBR(false, true)
+    CSPH_NBR(true, true)
+#undef CSPH_NBR
     return hipGetLastError();
 }
 
@@ -119,12 +138,15 @@ hipError_t launch_nbr_fill(int64_t n, const GridDev &g, const PairConst &pc, con
                            hipStream_t st) {
     if (n <= 0) return hipSuccess;
     unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
-    if (pc.pair_mode)
-        k_nbr<true, true><<<nb, kBlock, 0, st>>>(n, g, pc, x, y, z, d, cs, perm, nullptr,
+#define CSPH_NBR(P, X)                                                                    \
+    if (!!pc.pair_mode == P && !!pc.per == X)                                             \
+        k_nbr<P, true, X><<<nb, kBlock, 0, st>>>(n, g, pc, x, y, z, d, cs, perm, nullptr,    \
                                                  offsets, idx);
-    else
-        k_nbr<false, true><<<nb, kBlock, 0, st>>>(n, g, pc, x, y, z, d, cs, perm, nullptr,
-                                                  offsets, idx);
+    CSPH_NBR(false, false)
+    CSPH_NBR(true, false)
+    CSPH_NBR(false, true)
+    CSPH_NBR(true, true)
+#undef CSPH_NBR
     return hipGetLastError();
 }
 

@@ -261,7 +261,7 @@ constexpr int kUS64 = 2;
 constexpr int kPop64 = 1;
 static_assert(kUS64 - 1 <= kRecPad64, "the FP64 stencil walk reads up to kUS64 - 1 records past a row");
 
-template <bool PAIR, bool WALL>
+template <bool PAIR, bool WALL, bool PER>
 struct Rates64 {
     const double4 *__restrict__ A;
     const double4 *__restrict__ B;
@@ -278,9 +278,13 @@ struct Rates64 {
     double2 zc;
     double di, yw, vw2;  // wall position along y, twice its velocity
     Stencil t, ti;       // stencils of i and of its mirror image
+    // periodic images: i's faces (image_faces), the image the walk is on (wave-uniform mask)
+    // and its stencil
+    int nf = 0, im = 0;
+    Stencil tm;
     double ar = 0.0, avx = 0.0, avy = 0.0, avz = 0.0, aE = 0.0, sig = 0.0;
     // ring counters in entries (their count is |N(i)|); an entry is the partner's 32-byte
-    // record offset, bit 0 set for a mirror image
+    // record offset, bit 0 set for a mirror image, bits 1-3 the periodic image mask
     int qw = 0, qr = 0, cntl = 0;
 
     __device__ __forceinline__ uint32_t &slot(int q) {
@@ -295,12 +299,18 @@ struct Rates64 {
         qr += has ? 1 : 0;
         const uint32_t jo = has ? (MIR ? e & ~31u : e) : 0u;
         const bool ghost = MIR && (e & 1u);
+        const int mm = PER && MIR ? (int)((e >> 1) & 7u) : 0;
         const int j = (int)(jo >> 5);
         const double4 aj = *(const double4 *)((const char *)A + jo);
         const double4 bj = *(const double4 *)((const char *)B + jo);
         const double2 zj = *(const double2 *)((const char *)Cz + (jo >> 1));
         const double yj = ghost ? 2.0 * yw - aj.y : aj.y;
-        const double dx = aj.x - a.x, dy = yj - a.y, dz = aj.z - a.z;
+        double dx = aj.x - a.x, dy = yj - a.y, dz = aj.z - a.z;
+        if (PER) {  // image mm: d = (x_j - x_i) - k L
+            dx = dx - image_shift(pc, nf, mm, 0);
+            dy = dy - image_shift(pc, nf, mm, 1);
+            dz = dz - image_shift(pc, nf, mm, 2);
+        }
         const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
         double invH = pc.invH, dwc = pc.dwc;
         if (PAIR) {
@@ -313,14 +323,19 @@ struct Rates64 {
                bj.w, zj.x, zj.y, aj.w, invH, dwc, ar, avx, avy, avz, aE, sig);
     }
 
-    // one walk over the stencil: real partners, or mirror partners (GHOST).
+    // one walk over the stencil: real partners, or mirror partners (GHOST); IMG: the walk
+    // around periodic image im of i (or of its mirror image).
     // One flat loop with wave-uniform branches (drain / next row / test a
     // chunk).
-    template <bool GHOST, bool MIR, bool ZS>
+    template <bool GHOST, bool MIR, bool ZS, bool IMG>
     __device__ __forceinline__ void pass() {
-        const bool on = live && (!GHOST || near_wall);
+        const bool on = live && (!GHOST || near_wall) && (!IMG || (nf & im) == im);
         // mirror partners: the particles on the stencil around the image of i
-        const Stencil &st = GHOST ? ti : t;
+        const Stencil &st = IMG ? tm : GHOST ? ti : t;
+        const double shx = IMG ? image_shift(pc, nf, im, 0) : 0.0;
+        const double shy = IMG ? image_shift(pc, nf, im, 1) : 0.0;
+        const double shz = IMG ? image_shift(pc, nf, im, 2) : 0.0;
+        const uint32_t tag = (GHOST ? 1u : 0u) | (IMG ? (uint32_t)im << 1 : 0u);
         int oy = st.R, oz = -st.R - 1;  // advanced to (-R, -R) before the first row
         int k = 0, j0 = 0, len = 0, jlast = 0;
         float gz2 = 0.f;
@@ -354,6 +369,11 @@ struct Rates64 {
                 const int j = j0 + k + u;
                 double yj = GHOST ? 2.0 * yw - aj[u].y : aj[u].y;
                 double dx = aj[u].x - a.x, dy = yj - a.y, dz = aj[u].z - a.z;
+                if (IMG) {
+                    dx = dx - shx;
+                    dy = dy - shy;
+                    dz = dz - shz;
+                }
                 // exact FP64 membership, no contraction
                 double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
                 double H2 = pc.H2;
@@ -363,31 +383,52 @@ struct Rates64 {
                 }
                 // the entry's record offset (32 j for a slot that can be accepted)
                 const uint32_t jo = jbo + (uint32_t)(u * sizeof(double4));
-                const bool acc = (k + u < len) & (GHOST || jo != self32) & (r2 < H2);
+                const bool acc = (k + u < len) & (GHOST || IMG || jo != self32) & (r2 < H2);
                 // the ring slot qw is free: write always, advance on acceptance
-                slot(qw) = GHOST ? jo | 1u : jo;
+                slot(qw) = jo | tag;
                 qw += acc ? 1 : 0;
             }
             k += kUS64;
         }
     }
 
+    // the walks around every periodic image some lane of the wave has (GHOST: around the
+    // images of its mirror image)
+    template <bool GHOST, bool ZS>
+    __device__ __forceinline__ void images() {
+        for (int m = 1; m < 8; ++m) {
+            if (!__any(live && (!GHOST || near_wall) && (nf & m) == m)) continue;
+            im = m;
+            const double px = a.x + image_shift(pc, nf, m, 0);
+            const double py = (GHOST ? 2.0 * yw - a.y : a.y) + image_shift(pc, nf, m, 1);
+            const double pz = a.z + image_shift(pc, nf, m, 2);
+            tm = shifted_stencil(g, GHOST ? ti : t, m, px, py, pz);
+            pass<GHOST, true, ZS, true>();
+        }
+    }
+
     // The whole walk: a Verlet list, or the stencil (and, for a wave with particles in the
-    // wall band, the stencil around their images); every pop drained.  Returns |N(i)|.
+    // wall band, the stencil around their images; for a wave with particles near periodic
+    // faces, the stencils around their periodic images); every pop drained.  Returns |N(i)|.
     template <bool LIST, bool ZS>
     __device__ __forceinline__ int run(const int32_t *__restrict__ lst, int len, int64_t nl) {
         int cnt;
+        const bool anyw = WALL && __any(near_wall);
         if (LIST) {
             pass_list<ZS>(lst, len, nl);
             cnt = cntl;
             while (__any(qr < qw)) drain<WALL, ZS>();
-        } else if (WALL && __any(near_wall)) {
-            pass<false, true, ZS>();
-            cnt = qw;  // real partners accepted
-            pass<true, true, ZS>();
+        } else if (anyw || (PER && __any(nf != 0))) {
+            pass<false, true, ZS, false>();
+            if (PER) images<false, ZS>();
+            cnt = qw;  // real partners accepted (periodic images included)
+            if (anyw) {
+                pass<true, true, ZS, false>();
+                if (PER) images<true, ZS>();
+            }
             while (__any(qr < qw)) drain<true, ZS>();
         } else {
-            pass<false, false, ZS>();
+            pass<false, false, ZS, false>();
             cnt = qw;
             while (__any(qr < qw)) drain<false, ZS>();
         }
@@ -431,9 +472,10 @@ struct Rates64 {
 };
 
 // Register-bound: the occupancy hint (5 waves per SIMD) holds the common variants at 96 VGPRs
-// without spills instead of 118 (4 waves); measured 1.6 % faster on the porous shock.
-template <bool PAIR, bool WALL, bool LIST>
-__global__ __launch_bounds__(kRate64Block, 5) void k_rates64(int64_t n, const double4 *__restrict__ A,
+// without spills instead of 118 (4 waves); measured 1.6 % faster on the porous shock.  The
+// periodic variants (the image walks' shifts and stencil) would spill at 96: 4 waves.
+template <bool PAIR, bool WALL, bool LIST, bool PER>
+__global__ __launch_bounds__(kRate64Block, PER ? 4 : 5) void k_rates64(int64_t n, const double4 *__restrict__ A,
                                                     const double4 *__restrict__ B,
                                                     const double2 *__restrict__ Cz,
                                                     const double *__restrict__ rho,
@@ -444,7 +486,7 @@ __global__ __launch_bounds__(kRate64Block, 5) void k_rates64(int64_t n, const do
                                                     VList vl) {
     if (LIST && vl.gate && *vl.gate == 0) return;
     __shared__ int qj[kQ][kRate64Block];
-    Rates64<PAIR, WALL> k;
+    Rates64<PAIR, WALL, PER> k;
     k.qb = (char *)&qj[0][0];
     k.lane4 = threadIdx.x * (int)sizeof(int);
     k.A = A;
@@ -480,6 +522,8 @@ __global__ __launch_bounds__(kRate64Block, 5) void k_rates64(int64_t n, const do
         k.near_wall = k.live && mirror_band(g, k.a.y, k.yw, pc.H);
         k.ti = image_stencil(g, k.t, 2.0 * k.yw - k.a.y);
     }
+    k.tm = k.t;
+    if (PER && k.live) k.nf = image_faces(pc, k.a.x, k.a.y, k.a.z);
     const int len = LIST && k.live ? min(vl.count[s], vl.cap) : 0;
     const int32_t *lst = LIST ? vl.idx + (k.live ? s * kVlChunk : 0) : nullptr;
     const int cnt = *o.zflag == 0 ? k.template run<LIST, true>(lst, len, n)
@@ -567,7 +611,7 @@ __device__ __forceinline__ bool member64(double ex, double ey, double ez, double
     return ((ex * ex) + (ey * ey)) + (ez * ez) < H2;
 }
 
-template <bool PAIR, bool WALL, bool LIST>
+template <bool PAIR, bool WALL, bool LIST, bool PER>
 struct Rates32 {
     const float4 *__restrict__ A;
     const float4 *__restrict__ B;
@@ -588,6 +632,11 @@ struct Rates32 {
     double xi, yi, zi, di, yw;  // yw: wall position along y
     float wd, vw2, Df, cxf, lo, hi, dwch0;
     Stencil t, ti;               // stencils of i and of its mirror image
+    // periodic images: i's faces (image_faces); the image the walk is on (wave-uniform mask),
+    // its stencil, i's offsets from the image point's cell origin and that cell's x index
+    int nf = 0, im = 0;
+    Stencil tm;
+    float amx = 0.f, amy = 0.f, amz = 0.f, cxm = 0.f;
     float ar = 0.f, avx = 0.f, avy = 0.f, avz = 0.f, aE = 0.f, sig = 0.f;
     // ring write and read counters in bytes, advancing one ring row (kSlot) per entry: a
     // slot's address is the counter masked to the ring, or'ed with the lane's offset;
@@ -599,7 +648,7 @@ struct Rates32 {
         return *(float4 *)(qb + ((q & (kRing - 1)) | (unsigned)lane16));
     }
     // A ring entry holds the partner's offsets and, in w, the byte offset of its 16-byte
-    // records with bit 0 set for a mirror image.
+    // records with bit 0 set for a mirror image and bits 1-3 holding the periodic image mask.
 
     // every lane pops its next partner, if it has one; MIR: the wave may hold mirror entries
     template <bool MIR, bool ZS>
@@ -611,6 +660,7 @@ struct Rates32 {
         const uint32_t e = __float_as_uint(q.w);
         const uint32_t jo = has ? (MIR ? e & ~15u : e) : 0u;
         const bool ghost = MIR && (e & 1u);
+        const int mm = PER && MIR ? (int)((e >> 1) & 7u) : 0;
         const int j = (int)(jo >> 4);
         const float4 bj = *(const float4 *)((const char *)B + jo);
         const float4 cj = *(const float4 *)((const char *)Cz + jo);
@@ -635,7 +685,12 @@ struct Rates32 {
         // closing speed in the signal speed, which the kernel weight does not damp)
         if (!LIST && has && (!(r2 < H2lo) || r2 < H2lo * 1e-4f)) {
             const double yj = ghost ? 2.0 * yw - ys[j] : ys[j];
-            const double ex = xs[j] - xi, ey = yj - yi, ez = zs[j] - zi;
+            double ex = xs[j] - xi, ey = yj - yi, ez = zs[j] - zi;
+            if (PER) {  // image mm: d = (x_j - x_i) - k L
+                ex = ex - image_shift(pc, nf, mm, 0);
+                ey = ey - image_shift(pc, nf, mm, 1);
+                ez = ez - image_shift(pc, nf, mm, 2);
+            }
             in = member64(ex, ey, ez, H2d);
             qx = (float)ex;
             qy = (float)ey;
@@ -647,13 +702,19 @@ struct Rates32 {
                    bj.z, bj.w, cj.x, cj.y, cj.z, invH, dwch, ar, avx, avy, avz, aE, sig);
     }
 
-    // flat loop as in the FP64 kernel
-    template <bool GHOST, bool MIR, bool ZS>
+    // flat loop as in the FP64 kernel.  IMG: the walk around image point im of i (or of its
+    // mirror image), offsets relative to that point's cells; the wall axis y is never periodic,
+    // so a mirror walk keeps i's own y offsets.
+    template <bool GHOST, bool MIR, bool ZS, bool IMG>
     __device__ __forceinline__ void pass() {
 #pragma clang fp contract(fast)
-        const bool on = live && (!GHOST || near_wall);
+        const bool on = live && (!GHOST || near_wall) && (!IMG || (nf & im) == im);
         // mirror partners: the particles on the stencil around the image of i
-        const Stencil &st = GHOST ? ti : t;
+        const Stencil &st = IMG ? tm : GHOST ? ti : t;
+        const float ax0 = IMG ? amx : a.x, az0 = IMG ? amz : a.z, cx0 = IMG ? cxm : cxf;
+        const float ay0 = IMG && !GHOST ? amy : a.y;
+        const int cy0 = IMG && !GHOST ? tm.cy : t.cy;
+        const uint32_t tag = (GHOST ? 1u : 0u) | (IMG ? (uint32_t)im << 1 : 0u);
         int oy = st.R, oz = -st.R - 1;
         int k = 0, j0 = 0, len = 0, jlast = 0;
         float ay = 0.f, az = 0.f, gz2 = 0.f;
@@ -672,13 +733,13 @@ struct Rates32 {
                     // per plane of rows: squared z gap, i's z offset from the plane's cells
                     const float gz = slab_gap(st.zc, st.cz + oz);
                     gz2 = gz * gz;
-                    az = a.z - (float)oz * Df;
+                    az = az0 - (float)oz * Df;
                 }
                 const int yy = st.cy + oy, zz = st.cz + oz;
                 row_range(cs, g, st, on, yy, zz, gz2, j0, len);
                 jlast = len > 0 ? j0 + len - 1 : 0;
                 // i's y offset from the row's cell origin (rows counted from i's own cell)
-                ay = a.y - (float)(yy - t.cy) * Df;
+                ay = ay0 - (float)(yy - cy0) * Df;
                 k = 0;
                 continue;
             }
@@ -694,7 +755,7 @@ struct Rates32 {
 #pragma unroll
             for (int u = 0; u < kUS; ++u) {
                 const int j = j0 + k + u;
-                float dx = (aj[u].x + (aj[u].w - cxf) * Df) - a.x;
+                float dx = (aj[u].x + (aj[u].w - cx0) * Df) - ax0;
                 float dy = aj[u].y - ay, dz = aj[u].z - az;
                 if (GHOST) dy = 2.0f * wd - dy;
                 float r2 = (dx * dx + dy * dy) + dz * dz;
@@ -706,27 +767,57 @@ struct Rates32 {
                 // the entry's record offset (16 j for a slot that can be accepted); one select
                 // per slot: the three tests combine as lane masks
                 const uint32_t jo = jbo + (uint32_t)(u * sizeof(float4));
-                const bool acc = (k + u < len) & (GHOST || jo != self16) & (r2 < hj);
-                slot(qw) = make_float4(dx, dy, dz, __uint_as_float(GHOST ? jo | 1u : jo));
+                const bool acc = (k + u < len) & (GHOST || IMG || jo != self16) & (r2 < hj);
+                slot(qw) = make_float4(dx, dy, dz, __uint_as_float(jo | tag));
                 qw += acc ? kSlot : 0;
             }
             k += kUS;
         }
     }
 
+    // Point of image m of i (GHOST: of its mirror image) and its stencil and offsets.
+    template <bool GHOST>
+    __device__ __forceinline__ void set_image(int m) {
+        im = m;
+        const double px = xi + image_shift(pc, nf, m, 0);
+        const double py = (GHOST ? 2.0 * yw - yi : yi) + image_shift(pc, nf, m, 1);
+        const double pz = zi + image_shift(pc, nf, m, 2);
+        tm = shifted_stencil(g, GHOST ? ti : t, m, px, py, pz);
+        amx = m & 1 ? (float)(px - (g.ox + (double)tm.cx * g.cell)) : a.x;
+        amy = m & 2 ? (float)(py - (g.oy + (double)tm.cy * g.cell)) : a.y;
+        amz = m & 4 ? (float)(pz - (g.oz + (double)tm.cz * g.cell)) : a.z;
+        cxm = (float)tm.cx;
+    }
+
+    // the walks around every periodic image some lane of the wave has
+    template <bool GHOST, bool ZS>
+    __device__ __forceinline__ void images() {
+        for (int m = 1; m < 8; ++m) {
+            if (!__any(live && (!GHOST || near_wall) && (nf & m) == m)) continue;
+            set_image<GHOST>(m);
+            pass<GHOST, true, ZS, true>();
+        }
+    }
+
     // The whole walk: a Verlet list, or the stencil (and, for a wave with particles in the
-    // wall band, the stencil around their images); every pop drained.
+    // wall band, the stencil around their images; for a wave with particles near periodic
+    // faces, the stencils around their periodic images); every pop drained.
     template <bool LIST_, bool ZS>
     __device__ __forceinline__ void run(const int32_t *__restrict__ lst, int len, int64_t nl) {
+        const bool anyw = WALL && __any(near_wall);
         if (LIST_) {
             pass_list<ZS>(lst, len, nl);
             while (__any(qr != qw)) drain<WALL, ZS>();
-        } else if (WALL && __any(near_wall)) {
-            pass<false, true, ZS>();
-            pass<true, true, ZS>();
+        } else if (anyw || (PER && __any(nf != 0))) {
+            pass<false, true, ZS, false>();
+            if (PER) images<false, ZS>();
+            if (anyw) {
+                pass<true, true, ZS, false>();
+                if (PER) images<true, ZS>();
+            }
             while (__any(qr != qw)) drain<true, ZS>();
         } else {
-            pass<false, false, ZS>();
+            pass<false, false, ZS, false>();
             while (__any(qr != qw)) drain<false, ZS>();
         }
     }
@@ -768,7 +859,7 @@ struct Rates32 {
     }
 };
 
-template <bool PAIR, bool WALL, bool LIST>
+template <bool PAIR, bool WALL, bool LIST, bool PER>
 __global__ __launch_bounds__(kRate32Block) void k_rates32(int64_t n, const float4 *__restrict__ A,
                                                     const float4 *__restrict__ B,
                                                     const float4 *__restrict__ Cz,
@@ -786,7 +877,7 @@ __global__ __launch_bounds__(kRate32Block) void k_rates32(int64_t n, const float
     // finite placeholder offsets for lanes that pop from an empty ring
 #pragma unroll
     for (int q = 0; q < kQ; ++q) qd[q][threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
-    Rates32<PAIR, WALL, LIST> k;
+    Rates32<PAIR, WALL, LIST, PER> k;
     k.A = A;
     k.P4 = (const double4 *)A;
     k.B = B;
@@ -836,6 +927,8 @@ __global__ __launch_bounds__(kRate32Block) void k_rates32(int64_t n, const float
         k.vw2 = (float)(2.0 * pc.wall_v);
         k.ti = image_stencil(g, k.t, 2.0 * k.yw - k.yi);
     }
+    k.tm = k.t;
+    if (PER && k.live) k.nf = image_faces(pc, k.xi, k.yi, k.zi);
     const int len = LIST && k.live ? min(vl.count[s], vl.cap) : 0;
     const int32_t *lst = LIST ? vl.idx + (k.live ? s * kVlChunk : 0) : nullptr;
     if (*o.zflag == 0)
@@ -874,26 +967,31 @@ hipError_t launch_rates(int64_t n, int mixed, const GridDev &g, const PairConst 
     const unsigned nb32 = (unsigned)((n + kRate32Block - 1) / kRate32Block);
     const unsigned nb64 = (unsigned)((n + kRate64Block - 1) / kRate64Block);
     const bool pair = pc.pair_mode != 0, wall = pc.wall != 0, list = vl_idx != nullptr;
-    if (list && pair) return hipErrorInvalidValue;
-#define CSPH_RATES_CASE(P, W, L)                                                              \
-    if (pair == P && wall == W && list == L) {                                                \
+    const bool per = pc.per != 0;
+    if (list && (pair || per)) return hipErrorInvalidValue;
+#define CSPH_RATES_CASE(P, W, L, X)                                                           \
+    if (pair == P && wall == W && list == L && per == X) {                                    \
         if (mixed)                                                                            \
-            k_rates32<P, W, L><<<nb32, kRate32Block, 0, st>>>(                                \
+            k_rates32<P, W, L, X><<<nb32, kRate32Block, 0, st>>>(                             \
                 n, (const float4 *)w.recA, (const float4 *)w.recB, (const float4 *)w.recC,    \
                 sorted[0], sorted[1], sorted[2], rho_sorted, d_sorted, w.cs, g, pc, t_dev,    \
                 t_host, o, want_dt, vl);                                                      \
         else                                                                                  \
-            k_rates64<P, W, L><<<nb64, kRate64Block, 0, st>>>(                                \
+            k_rates64<P, W, L, X><<<nb64, kRate64Block, 0, st>>>(                             \
                 n, (const double4 *)w.recA, (const double4 *)w.recB,                          \
                 (const double2 *)w.recC, rho_sorted, d_sorted, w.cs, g, pc, t_dev, t_host, o, \
                 want_dt, vl);                                                                 \
     }
-    CSPH_RATES_CASE(false, false, false)
-    CSPH_RATES_CASE(false, true, false)
-    CSPH_RATES_CASE(true, false, false)
-    CSPH_RATES_CASE(true, true, false)
-    CSPH_RATES_CASE(false, false, true)
-    CSPH_RATES_CASE(false, true, true)
+    CSPH_RATES_CASE(false, false, false, false)
+    CSPH_RATES_CASE(false, true, false, false)
+    CSPH_RATES_CASE(true, false, false, false)
+    CSPH_RATES_CASE(true, true, false, false)
+    CSPH_RATES_CASE(false, false, true, false)
+    CSPH_RATES_CASE(false, true, true, false)
+    CSPH_RATES_CASE(false, false, false, true)
+    CSPH_RATES_CASE(false, true, false, true)
+    CSPH_RATES_CASE(true, false, false, true)
+    CSPH_RATES_CASE(true, true, false, true)
 #undef CSPH_RATES_CASE
     return hipGetLastError();
 }

@@ -77,6 +77,20 @@ struct WallDev {
     const double *t;  // time at the start of the step (device)
 };
 
+// Periodic axes (kernels' axes, bit a): a new position at or above hi moves down by the period,
+// one below lo up by it (a particle moves less than a period per step).
+struct PerDev {
+    int mask;
+    double lo[3], hi[3], L[3];
+};
+
+__device__ __forceinline__ double wrap_axis(const PerDev &p, int a, double v) {
+    if (!((p.mask >> a) & 1)) return v;
+    if (v >= p.hi[a]) return v - p.L[a];
+    if (v < p.lo[a]) return v + p.L[a];
+    return v;
+}
+
 // With VORO the kernel also assigns each particle's new position to its Voronoi generator
 // (eq. VoronoiDefinition: FP64 argmin of ((dx dx) + (dy dy)) + (dz dz) without contraction,
 // k scanned upwards with a strict comparison, so a tie keeps the smaller k) and counts
@@ -86,8 +100,9 @@ struct WallDev {
 // commutative).
 __global__ __launch_bounds__(kBlock) void k_integrate(int64_t n, State9 s, Rates5 r,
                                                       const unsigned long long *dtmin, double cfl,
-                                                      double dt_in, WallDev wall, VoroDev vo,
-                                                      ListGate lg, double *__restrict__ part) {
+                                                      double dt_in, WallDev wall, PerDev per,
+                                                      VoroDev vo, ListGate lg,
+                                                      double *__restrict__ part) {
     if (lg.gate && *lg.gate == 0) return;
     extern __shared__ double vsm[];
     double *gs = vsm;                                                   // 3K
@@ -123,7 +138,12 @@ __global__ __launch_bounds__(kBlock) void k_integrate(int64_t n, State9 s, Rates
             vy = vr;
             y = 2.0 * yw - y;
         }
-        const double x = s.f[0][i] + dt * vx, z = s.f[2][i] + dt * vz;
+        double x = s.f[0][i] + dt * vx, z = s.f[2][i] + dt * vz;
+        if (per.mask) {  // after the reflection, as the wall's axis is never periodic
+            x = wrap_axis(per, 0, x);
+            y = wrap_axis(per, 1, y);
+            z = wrap_axis(per, 2, z);
+        }
         s.f[0][i] = x;
         s.f[1][i] = y;
         s.f[2][i] = z;
@@ -200,6 +220,13 @@ hipError_t launch_integrate(int64_t n, double *const st8[9], const Ws &w, double
     for (int k = 0; k < 9; ++k) s.f[k] = st8[k];
     Rates5 r{{w.rate[0], w.rate[1], w.rate[2], w.rate[3], w.rate[4]}};
     WallDev wall{pc.wall && t ? 1 : 0, pc.wall_y0, pc.wall_v, t};
+    PerDev per{};
+    per.mask = pc.per;
+    for (int a = 0; a < 3; ++a) {
+        per.lo[a] = pc.lo[a];
+        per.hi[a] = pc.hi[a];
+        per.L[a] = pc.L[a];
+    }
     VoroDev v{};
     size_t shm = 0;
     if (vo && vo->K > 0) {
@@ -210,7 +237,8 @@ hipError_t launch_integrate(int64_t n, double *const st8[9], const Ws &w, double
     }
     const ListGate g = lg ? *lg : ListGate{nullptr, nullptr, nullptr, nullptr};
     int nb = integrate_blocks(n);
-    k_integrate<<<nb, kBlock, shm, st>>>(n, s, r, w.dtmin, cfl, dt_in, wall, v, g, w.tot_part);
+    k_integrate<<<nb, kBlock, shm, st>>>(n, s, r, w.dtmin, cfl, dt_in, wall, per, v, g,
+                                         w.tot_part);
     return hipGetLastError();
 }
 

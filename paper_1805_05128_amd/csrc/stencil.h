@@ -73,6 +73,56 @@ __device__ __forceinline__ Stencil image_stencil(const GridDev &g, const Stencil
     return s;
 }
 
+// Periodic images (PairConst).  Faces of particle i: bit a set when axis a is periodic and i
+// lies within the near-face band of one of its faces, bit 3 + a when that is the high face
+// (shift k_a = -1) rather than the low one (k_a = +1).  An image is a non-empty mask m of
+// such axes: the partners j at (x_j - k L) along the axes of m.
+__device__ __forceinline__ int image_faces(const PairConst &pc, double x, double y, double z) {
+    const double p[3] = {x, y, z};
+    int f = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (!((pc.per >> a) & 1)) continue;
+        if (p[a] - pc.lo[a] < pc.hb)
+            f |= 1 << a;
+        else if (pc.hi[a] - p[a] < pc.hb)
+            f |= 9 << a;
+    }
+    return f;
+}
+
+// k_a L_a of image m along axis a (0 when m does not shift axis a): the displacement to the
+// image of j is d_a = (x_j,a - x_i,a) - k_a L_a, formed in that order.
+__device__ __forceinline__ double image_shift(const PairConst &pc, int f, int m, int a) {
+    return ((m >> a) & 1) ? (((f >> (3 + a)) & 1) ? -pc.L[a] : pc.L[a]) : 0.0;
+}
+
+// Cell index of coordinate v, not clamped to the mesh (an image point lies off it; rows off
+// the mesh are skipped), bounded to keep the integer arithmetic finite.
+__device__ __forceinline__ int free_cell(double v, double o, double inv) {
+    return (int)fmin(fmax(floor((v - o) * inv), -1048576.0), 1048576.0);
+}
+
+// Stencil around the image point p = (x_i, y_i, z_i) + k L of image m, starting from stencil s
+// (of i, or of its mirror image, whose y it keeps): the shifted axes take the point's own
+// unclamped cells and chord centres.
+__device__ __forceinline__ Stencil shifted_stencil(const GridDev &g, Stencil s, int m, double px,
+                                                   double py, double pz) {
+    if (m & 1) {
+        s.cx = free_cell(px, g.ox, g.inv);
+        s.xc = (float)((px - g.ox) * g.inv);
+    }
+    if (m & 2) {
+        s.cy = free_cell(py, g.oy, g.inv);
+        s.yc = (float)((py - g.oy) * g.inv);
+    }
+    if (m & 4) {
+        s.cz = free_cell(pz, g.oz, g.inv);
+        s.zc = (float)((pz - g.oz) * g.inv);
+    }
+    return s;
+}
+
 // Whether a particle at y can have mirror partners within support H: some
 // particle's image 2 yw - y_j lies within H of it.  The images lie at or below
 // yw + (yw - min_j y_j), so particles behind the wall widen the band in front of it.

@@ -181,3 +181,34 @@ def test_list_step_needs_its_control_block():
                                None, None, dev(1 << 20, C.c_int32), dev(1 << 21, C.c_int32), 64,
                                dev(1 << 22, C.c_double), ctl, None, 0, None, None)
         assert st == N.CSPH_EINVAL and b"ctl" in L.csph_last_error()
+
+
+def test_periodic_params_checked_on_the_host():
+    """Periodic boundaries: an unknown axis mask, an empty box, a periodic wall axis, and the
+    calls that do not take periodic boundaries (Verlet lists, the adjoint) are refused before
+    any device work."""
+    L = N.load()
+    box = ((0.0, 0.0, 0.0), (10.0, 10.0, 10.0))
+    for kw, msg in ((dict(periodic=9, box=box), b"periodic mask"),
+                    (dict(periodic=2, box=((0.0, 5.0, 0.0), (10.0, 5.0, 10.0))), b"box_hi > box_lo"),
+                    (dict(periodic=1, box=box, wall=(0.0, 1.0)), b"wall's axis")):
+        p = P.Params(**kw).c()
+        st = L.csph_init_energy(None, None, None, None, None, None, 0, C.byref(p), None, None)
+        assert st == N.CSPH_EINVAL and msg in L.csph_last_error(), kw
+    p = P.Params(periodic=6, box=box, wall=(0.0, 1.0)).c()  # periodic across the wall: valid
+    assert L.csph_init_energy(None, None, None, None, None, None, 0, C.byref(p), None,
+                              None) == N.CSPH_OK
+    p = P.Params(periodic=7, box=box).c()
+    a, b = _fake_state(4096), _fake_state(65536)
+    dev = lambda addr, t: C.cast(C.c_void_p(addr), C.POINTER(t))
+    st = L.csph_vlist_build(C.byref(a), C.byref(b), C.byref(p), None, 0.3, 64,
+                            dev(1 << 20, C.c_int32), dev(1 << 21, C.c_int32),
+                            dev(1 << 22, C.c_double), None, None, None, 0, None, None)
+    assert st == N.CSPH_EINVAL and b"periodic" in L.csph_last_error()
+    st = L.csph_step_vlist(C.byref(a), C.byref(p), dev(1 << 24, C.c_double), 0.0, None, None,
+                           None, None, dev(1 << 20, C.c_int32), dev(1 << 21, C.c_int32), 64,
+                           dev(1 << 22, C.c_double), C.c_void_p(1 << 23), None, 0, None, None)
+    assert st == N.CSPH_EINVAL and b"periodic" in L.csph_last_error()
+    g = N.CsphGrad(*[dev((1 << 25) + 1024 * k, C.c_double) for k in range(8)])
+    st = L.csph_step_vjp(C.byref(a), C.byref(p), 0.1, g, g, None, None, 0, None, None)
+    assert st == N.CSPH_EINVAL and b"periodic" in L.csph_last_error()
