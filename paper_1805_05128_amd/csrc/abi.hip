@@ -105,6 +105,7 @@ size_t ws_layout(Ws *w, void *base, int64_t n, int64_t ncell) {
     t.key = (uint32_t *)take(sizeof(uint32_t) * un);
     t.rank = (uint32_t *)take(sizeof(uint32_t) * un);
     t.perm = (int32_t *)take(sizeof(int32_t) * un);
+    t.bin_tmp = (int32_t *)take(sizeof(int32_t) * un);
     t.cnt = (int32_t *)take(sizeof(int32_t) * un);
     // A records: FP64 (32 B each) or FP32 (16 B), each followed by two zero records
     t.recA = take(32 * (un + 2));

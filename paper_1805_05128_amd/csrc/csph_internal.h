@@ -192,6 +192,7 @@ struct Ws {
     int32_t *cs;                  // ncell + 1
     int64_t *scan_tmp;            // scan tiles
     int32_t *perm;                // n
+    int32_t *bin_tmp;             // n: cell order before the in-cell ranking (binning only)
     void *recA, *recB, *recC;     // pair records (FP64: 32+32+16 B; mixed: 16+16+8 B)
     void *recD;                   // adjoint pair weights (32 B)
     double *recE;                 // adjoint energy weight

@@ -4,9 +4,10 @@
 // locality renumbering of sec. 4.2: a counting sort by cell key.  Keys are
 // histogrammed with integer atomics (each particle also gets a provisional
 // rank inside its cell), an exclusive scan of the histogram gives the cell
-// ranges, a scatter places every particle, and each cell's short segment is
-// then sorted by input index so the order is exactly the stable order by
-// (key, input index) whatever order the atomics ran in.
+// ranges, a scatter places every particle in its cell's segment, and each
+// particle's final place in the segment is the number of the segment's
+// particles with a smaller input index, so the order is exactly the stable
+// order by (key, input index) whatever order the atomics ran in.
 #include "csph_internal.h"
 
 namespace csph {
@@ -241,28 +242,28 @@ __global__ __launch_bounds__(kBlock) void k_keys(const double *__restrict__ x,
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__ key,
                                                     const uint32_t *__restrict__ rank,
                                                     const int32_t *__restrict__ cs, int64_t n,
-                                                    int32_t *__restrict__ perm) {
+                                                    int32_t *__restrict__ tmp) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    perm[cs[key[i]] + (int32_t)rank[i]] = (int32_t)i;
+    tmp[cs[key[i]] + (int32_t)rank[i]] = (int32_t)i;
 }
 
-// Sort each cell's segment of perm ascending (insertion sort: segments are
-// short and usually already in order).
-__global__ __launch_bounds__(kBlock) void k_cell_sort(const int32_t *__restrict__ cs,
-                                                      int64_t ncell, int32_t *__restrict__ perm) {
-    int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (c >= ncell) return;
-    int a = cs[c], b = cs[c + 1];
-    for (int s = a + 1; s < b; ++s) {
-        int v = perm[s];
-        int t = s - 1;
-        while (t >= a && perm[t] > v) {
-            perm[t + 1] = perm[t];
-            --t;
-        }
-        perm[t + 1] = v;
-    }
+// Final place of the particle in slot s of the scattered order: its cell segment's start plus
+// the number of the segment's particles with a smaller input index.  O(k) per particle for a
+// cell of k particles, all particles in parallel (an in-cell sort by one thread per cell would
+// cost O(k^2) for a dense cell).
+__global__ __launch_bounds__(kBlock) void k_cell_rank(const uint32_t *__restrict__ key,
+                                                      const int32_t *__restrict__ cs, int64_t n,
+                                                      const int32_t *__restrict__ tmp,
+                                                      int32_t *__restrict__ perm) {
+    int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    const int p = tmp[s];
+    const uint32_t k = key[p];
+    const int a = cs[k], b = cs[k + 1];
+    int r = 0;
+    for (int t = a; t < b; ++t) r += tmp[t] < p ? 1 : 0;
+    perm[a + r] = p;
 }
 
 static unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -280,8 +281,8 @@ hipError_t launch_bin(const double *x, const double *y, const double *z, int64_t
                                                            w.scan_tmp, st);
     if (e != hipSuccess) return e;
     if (n > 0) {
-        k_scatter<<<blocks_for(n), kBlock, 0, st>>>(w.key, w.rank, cell_start, n, perm);
-        k_cell_sort<<<blocks_for(ncell), kBlock, 0, st>>>(cell_start, ncell, perm);
+        k_scatter<<<blocks_for(n), kBlock, 0, st>>>(w.key, w.rank, cell_start, n, w.bin_tmp);
+        k_cell_rank<<<blocks_for(n), kBlock, 0, st>>>(w.key, cell_start, n, w.bin_tmp, perm);
     }
     return hipGetLastError();
 }

@@ -36,6 +36,30 @@ hipError_t launch_gather_pos(int64_t n, const int32_t *perm, const double *x, co
     return hipGetLastError();
 }
 
+// In-place heapsort of a[0..c) ascending (a max-heap, then the maximum moved to the end).
+__device__ __forceinline__ void sift_down(int32_t *a, int root, int end) {
+    const int v = a[root];
+    for (;;) {
+        int ch = 2 * root + 1;
+        if (ch >= end) break;
+        if (ch + 1 < end && a[ch + 1] > a[ch]) ++ch;
+        if (a[ch] <= v) break;
+        a[root] = a[ch];
+        root = ch;
+    }
+    a[root] = v;
+}
+
+__device__ void heap_sort(int32_t *a, int c) {
+    for (int r = c / 2 - 1; r >= 0; --r) sift_down(a, r, c);
+    for (int e = c - 1; e > 0; --e) {
+        const int t = a[0];
+        a[0] = a[e];
+        a[e] = t;
+        sift_down(a, 0, e);
+    }
+}
+
 template <bool PAIR, bool FILL, bool PER>
 __global__ __launch_bounds__(kBlock) void k_nbr(int64_t n, GridDev g, PairConst pc,
                                                 const double *__restrict__ x,
@@ -98,21 +122,8 @@ __global__ __launch_bounds__(kBlock) void k_nbr(int64_t n, GridDev g, PairConst 
             }
         }
     }
-    if (FILL) {
-        // insertion sort of this row (rows are short)
-        int32_t *row = idx + wpos;
-        for (int a = 1; a < cnt; ++a) {
-            int v = row[a];
-            int b = a - 1;
-            while (b >= 0 && row[b] > v) {
-                row[b + 1] = row[b];
-                --b;
-            }
-            row[b + 1] = v;
-        }
-    } else {
-        count_orig[i] = cnt;
-    }
+    if (FILL) heap_sort(idx + wpos, cnt);  // the row ascending, O(c log c)
+    if (!FILL) count_orig[i] = cnt;
 }
 
 hipError_t launch_nbr_count(int64_t n, const GridDev &g, const PairConst &pc, const double *x,

@@ -175,6 +175,26 @@ def test_bin_one_particle_and_all_in_one_cell():
     _bin_case(*[np.ascontiguousarray(pts[:, k]) for k in range(3)], 10.0)
 
 
+def test_bin_dense_cells():
+    """Cells holding thousands of particles (the in-cell order is ranked per particle, not
+    sorted per cell): 60 000 particles in 2 x 2 x 2 cells, and a 12-cell mesh where one cell
+    holds half of them."""
+    rng = np.random.default_rng(3)
+    pts = rng.uniform(0, 2, size=(60000, 3))
+    _bin_case(*[np.ascontiguousarray(pts[:, k]) for k in range(3)], 1.0)
+    pts[: 30000] = rng.uniform(0, 0.3, size=(30000, 3))
+    pts[30000:] = rng.uniform(0, 3.0, size=(30000, 3))
+    _bin_case(*[np.ascontiguousarray(pts[:, k]) for k in range(3)], 1.5)
+
+
+def test_neighbors_long_rows():
+    """Rows of ~900 partners (support 6 on the unit lattice): the CSR rows are sorted in
+    place per particle."""
+    w = ci.jittered_block(14, 14, 14, seed=2)
+    params = P.Params.from_workload(w, h=3.0)
+    _nbr_case(w, params, dict(h=3.0))
+
+
 # ------------------------------------------------------------------ neighbours
 
 def _nbr_case(w, params, cfg_over=None, d=None):
