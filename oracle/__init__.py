@@ -60,6 +60,8 @@ class Cfg(C.Structure):
         ("pad2", C.c_int32),
         ("box_lo", C.c_double * 3),
         ("box_hi", C.c_double * 3),
+        ("integrator", C.c_int32),
+        ("pad3", C.c_int32),
     ]
 
 
@@ -139,8 +141,9 @@ def num_threads() -> int:
 
 
 def make_cfg(eos, h=1.5, kappa=2.0, h_mode=0, wall=None, cfl=0.3, search=0, cell_size=0.0,
-             nthreads=0, periodic=0, box=None) -> Cfg:
-    """periodic: bit mask of periodic axes (1 x, 2 y, 4 z) with box = (lo[3], hi[3])."""
+             nthreads=0, periodic=0, box=None, integrator=0) -> Cfg:
+    """periodic: bit mask of periodic axes (1 x, 2 y, 4 z) with box = (lo[3], hi[3]);
+    integrator: 0 symplectic Euler, 1 two-stage Runge-Kutta."""
     c = Cfg()
     c.h, c.kappa, c.h_mode = h, kappa, h_mode
     c.n_eos = len(eos)
@@ -154,6 +157,7 @@ def make_cfg(eos, h=1.5, kappa=2.0, h_mode=0, wall=None, cfl=0.3, search=0, cell
         c.wall, c.wall_x0, c.wall_v = 1, float(wall[0]), float(wall[1])
     c.cfl, c.search, c.cell_size, c.nthreads = cfl, search, cell_size, nthreads
     c.periodic = int(periodic)
+    c.integrator = int(integrator)
     if box is not None:
         for a in range(3):
             c.box_lo[a], c.box_hi[a] = float(box[0][a]), float(box[1][a])

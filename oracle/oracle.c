@@ -37,7 +37,9 @@
  *   oracle_step             "renew particle positions and states" and the
  *                           global time step (Algorithm 1); symplectic Euler
  *                           with a Courant + density-change time step
- *                           (reading; the paper prints no time-step rule).
+ *                           (reading; the paper prints no time-step rule),
+ *                           or a two-stage Runge-Kutta step (the paper names
+ *                           no integrator).
  *   oracle_grid / _bin      uniform cubic mesh of cell size D (sec. 4.2) and
  *                           the cell-ordered particle numbering (sec. 4.2,
  *                           renumbering for locality).
@@ -84,6 +86,9 @@ typedef struct {
     int32_t pad2;
     double box_lo[3];
     double box_hi[3];
+    /* 0: symplectic Euler; 1: two-stage strong-stability-preserving Runge-Kutta */
+    int32_t integrator;
+    int32_t pad3;
 } oracle_cfg;
 
 /* ------------------------------------------------------------------ */
@@ -741,6 +746,106 @@ double oracle_dt(const oracle_cfg *cfg, int64_t n, const double *signal, const d
     return cfg->cfl * best;
 }
 
+/* The constraints on a new position (shared by both integrators): a particle behind the
+ * piston plane xw is reflected off it in the wall's frame (x <- 2 xw - x, v_x <- 2 v_w - v_x,
+ * E changed by the kinetic-energy difference), then periodic axes wrap it back into
+ * [box_lo, box_hi) (a particle moves less than a period per step). */
+static void constrain(const oracle_cfg *cfg, double xw, double *x, double *y, double *z,
+                      double *vx, double *E) {
+    if (cfg->wall && *x < xw) {
+        double vr = 2.0 * cfg->wall_v - *vx;
+        *E = *E + 0.5 * ((vr * vr) - (*vx * *vx));
+        *vx = vr;
+        *x = 2.0 * xw - *x;
+    }
+    double *pos[3] = {x, y, z};
+    for (int a = 0; a < 3; ++a) {
+        double Lp = period(cfg, a);
+        if (!Lp) continue;
+        if (*pos[a] >= cfg->box_hi[a]) *pos[a] = *pos[a] - Lp;
+        else if (*pos[a] < cfg->box_lo[a]) *pos[a] = *pos[a] + Lp;
+    }
+}
+
+/* Two-stage strong-stability-preserving Runge-Kutta step (Heun's method in Shu and Osher's
+ * convex form; a reading: the paper names no integrator).  With F the rates of
+ * (v, E, rho) and v the rate of r:
+ *   U1 = U + dt F(U, t),                  r1 = r + dt v
+ *   U' = U/2 + (U1 + dt F(U1, t + dt))/2, r' = r/2 + (r1 + dt v1)/2
+ * (each product and sum rounded as written).  dt comes from the rates of U, as in the Euler
+ * step, and serves both stages.  The second stage evaluates the rates at U1 with its
+ * positions wrapped into the periodic box (and the piston at x_w(t + dt)); the combination
+ * takes r1 unwrapped.  The new state is then constrained as the Euler step's.  nbr_count is
+ * that of U; the non-physical count sums both evaluations. */
+static int64_t step_rk2(const oracle_cfg *cfg, int64_t n, double *x, double *y, double *z,
+                        double *vx, double *vy, double *vz, double *rho, double *E,
+                        const double *m, const int32_t *mat, const double *d, double *t,
+                        double dt_in, double *dt_used, int64_t *nbr_count) {
+    size_t sz = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    enum { NBUF = 23 };
+    double *b[NBUF];
+    int ok = 1;
+    for (int k = 0; k < NBUF; ++k) ok &= (b[k] = (double *)malloc(sz)) != NULL;
+    int64_t bad = -1;
+    if (ok) {
+        double *f0 = b[0], *f1 = b[1], *f2 = b[2], *f3 = b[3], *f4 = b[4], *sg = b[5];
+        double *x1 = b[6], *y1 = b[7], *z1 = b[8], *vx1 = b[9], *vy1 = b[10], *vz1 = b[11];
+        double *rho1 = b[12], *E1 = b[13], *xe = b[14], *ye = b[15], *ze = b[16];
+        double *q0 = b[17], *q1 = b[18], *q2 = b[19], *q3 = b[20], *q4 = b[21];
+        bad = oracle_rates(cfg, n, x, y, z, vx, vy, vz, rho, E, m, mat, d, *t, f0, f1, f2, f3,
+                           f4, sg, nbr_count);
+        double dt = cfg->cfl > 0.0 ? oracle_dt(cfg, n, sg, d, rho, f0) : dt_in;
+        for (int64_t i = 0; i < n; ++i) {
+            vx1[i] = vx[i] + dt * f1[i];
+            vy1[i] = vy[i] + dt * f2[i];
+            vz1[i] = vz[i] + dt * f3[i];
+            E1[i] = E[i] + dt * f4[i];
+            rho1[i] = rho[i] + dt * f0[i];
+            x1[i] = x[i] + dt * vx[i];
+            y1[i] = y[i] + dt * vy[i];
+            z1[i] = z[i] + dt * vz[i];
+            double pe[3] = {x1[i], y1[i], z1[i]};
+            for (int a = 0; a < 3; ++a) {
+                double Lp = period(cfg, a);
+                if (!Lp) continue;
+                if (pe[a] >= cfg->box_hi[a]) pe[a] = pe[a] - Lp;
+                else if (pe[a] < cfg->box_lo[a]) pe[a] = pe[a] + Lp;
+            }
+            xe[i] = pe[0];
+            ye[i] = pe[1];
+            ze[i] = pe[2];
+        }
+        int64_t bad2 = bad < 0 ? -1
+                               : oracle_rates(cfg, n, xe, ye, ze, vx1, vy1, vz1, rho1, E1, m, mat,
+                                              d, *t + dt, q0, q1, q2, q3, q4, NULL, NULL);
+        if (bad2 < 0) {
+            bad = -1;
+        } else {
+            bad += bad2;
+            double t_new = *t + dt;
+            double xw = cfg->wall_x0 + cfg->wall_v * t_new;
+            for (int64_t i = 0; i < n; ++i) {
+                double nvx = 0.5 * vx[i] + 0.5 * (vx1[i] + dt * q1[i]);
+                double nvy = 0.5 * vy[i] + 0.5 * (vy1[i] + dt * q2[i]);
+                double nvz = 0.5 * vz[i] + 0.5 * (vz1[i] + dt * q3[i]);
+                double nE = 0.5 * E[i] + 0.5 * (E1[i] + dt * q4[i]);
+                double nrho = 0.5 * rho[i] + 0.5 * (rho1[i] + dt * q0[i]);
+                double nx = 0.5 * x[i] + 0.5 * (x1[i] + dt * vx1[i]);
+                double ny = 0.5 * y[i] + 0.5 * (y1[i] + dt * vy1[i]);
+                double nz = 0.5 * z[i] + 0.5 * (z1[i] + dt * vz1[i]);
+                constrain(cfg, xw, &nx, &ny, &nz, &nvx, &nE);
+                x[i] = nx; y[i] = ny; z[i] = nz;
+                vx[i] = nvx; vy[i] = nvy; vz[i] = nvz;
+                E[i] = nE; rho[i] = nrho;
+            }
+            *t = t_new;
+            if (dt_used) *dt_used = dt;
+        }
+    }
+    for (int k = 0; k < NBUF; ++k) free(b[k]);
+    return bad;
+}
+
 /* One step: rates at (state, t); dt from the CFL rule (cfl > 0) or dt_in;
  * v += dt dv/dt, E += dt dE/dt, rho += dt drho/dt, then r += dt v(new);
  * t += dt.  With the piston (the rigid wall of sec. 7.1, which stops the
@@ -749,12 +854,16 @@ double oracle_dt(const oracle_cfg *cfg, int64_t n, const double *signal, const d
  * frame: x <- 2 x_w - x, v_x <- 2 v_w - v_x, with its specific internal
  * energy kept (E changes by the kinetic-energy difference, the wall's work).
  * Periodic axes wrap the new positions back into the box.
+ * integrator = 1 takes the two-stage Runge-Kutta step above instead.
  * State arrays are updated in place.  Returns the non-physical count from
  * the rate evaluation (or -1). */
 int64_t oracle_step(const oracle_cfg *cfg, int64_t n, double *x, double *y, double *z,
                     double *vx, double *vy, double *vz, double *rho, double *E, const double *m,
                     const int32_t *mat, const double *d, double *t, double dt_in, double *dt_used,
                     int64_t *nbr_count) {
+    if (cfg->integrator == 1)
+        return step_rk2(cfg, n, x, y, z, vx, vy, vz, rho, E, m, mat, d, t, dt_in, dt_used,
+                        nbr_count);
     size_t sz = sizeof(double) * (size_t)(n > 0 ? n : 1);
     double *r0 = malloc(sz), *r1 = malloc(sz), *r2 = malloc(sz), *r3 = malloc(sz),
            *r4 = malloc(sz), *sg = malloc(sz);
@@ -774,21 +883,7 @@ int64_t oracle_step(const oracle_cfg *cfg, int64_t n, double *x, double *y, doub
             x[i] = x[i] + dt * vx[i];
             y[i] = y[i] + dt * vy[i];
             z[i] = z[i] + dt * vz[i];
-            if (cfg->wall && x[i] < xw) {
-                double vr = 2.0 * cfg->wall_v - vx[i];
-                E[i] = E[i] + 0.5 * ((vr * vr) - (vx[i] * vx[i]));
-                vx[i] = vr;
-                x[i] = 2.0 * xw - x[i];
-            }
-            /* periodic axes: back into [box_lo, box_hi) (a particle moves less than a period
-             * per step) */
-            double *pos[3] = {x, y, z};
-            for (int a = 0; a < 3; ++a) {
-                double Lp = period(cfg, a);
-                if (!Lp) continue;
-                if (pos[a][i] >= cfg->box_hi[a]) pos[a][i] = pos[a][i] - Lp;
-                else if (pos[a][i] < cfg->box_lo[a]) pos[a][i] = pos[a][i] + Lp;
-            }
+            constrain(cfg, xw, &x[i], &y[i], &z[i], &vx[i], &E[i]);
         }
         *t = t_new;
         if (dt_used) *dt_used = dt;
