@@ -91,6 +91,17 @@ typedef void *csph_stream; /* hipStream_t */
 #define CSPH_KEY_LINEAR 0
 #define CSPH_KEY_MORTON 1
 
+/* Integrators of csph_step (Algorithm 1 renews the state; the paper names no integrator):
+ * EULER: symplectic Euler, v, E, rho += dt F(U), then r += dt v_new (one rate evaluation).
+ * RK2: two-stage strong-stability-preserving Runge-Kutta (Heun's method in Shu and Osher's
+ * convex form), U1 = U + dt F(U, t) with r1 = r + dt v, U' = U/2 + (U1 + dt F(U1, t + dt))/2
+ * with r' = r/2 + (r1 + dt v1)/2; dt from F(U) for both stages; the second evaluation takes
+ * r1 wrapped into a periodic box and the piston at t + dt; the new state is reflected off the
+ * piston and wrapped as the Euler step's.  Two rate evaluations (two binnings, two mesh
+ * synchronisations); nbr_count is that of U, the non-physical count sums both evaluations. */
+#define CSPH_INT_EULER 0
+#define CSPH_INT_RK2 1
+
 typedef struct {
     int32_t type;   /* CSPH_EOS_* */
     int32_t pad;
@@ -136,6 +147,10 @@ typedef struct {
                           else CSPH_EINVAL.  Not taken by the Verlet-list and adjoint calls
                           (CSPH_EINVAL).  0: open boundaries */
     double box_lo[3], box_hi[3]; /* the periodic box (read on the periodic axes only) */
+    int32_t integrator; /* CSPH_INT_EULER | CSPH_INT_RK2 (csph_step, csph_step_static; the
+                           Voronoi, Verlet-list and adjoint steps take EULER only, else
+                           CSPH_EINVAL) */
+    int32_t pad2;
 } csph_params;
 
 /* Particle state.  x..m: FP64 arrays of n entries.  mat: int32 material id
@@ -185,7 +200,8 @@ const char *csph_version(void);
 
 /* Workspace bytes the calls below need for n particles on a mesh of ncell
  * cells (host; no device work).  csph_bin, csph_neighbors, csph_rates and
- * csph_step each fit in this size. */
+ * csph_step each fit in this size (p->integrator = CSPH_INT_RK2 adds the second
+ * stage's buffers; p may be NULL for the Euler step). */
 size_t csph_workspace_size(int64_t n, int64_t ncell, const csph_params *p);
 
 /* Mesh of sec. 4.2 for the given positions (see csph_grid).  Synchronises

@@ -17,6 +17,7 @@ CSPH_EOS_IDEAL, CSPH_EOS_STIFFENED, CSPH_EOS_MIE_GRUNEISEN = 0, 1, 2
 CSPH_FP64, CSPH_MIXED = 0, 1
 CSPH_H_FIXED, CSPH_H_PAIR = 0, 1
 CSPH_KEY_LINEAR, CSPH_KEY_MORTON = 0, 1
+CSPH_INT_EULER, CSPH_INT_RK2 = 0, 1
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -40,6 +41,7 @@ class CsphParams(C.Structure):
         ("eos", CsphEos * CSPH_MAX_EOS),
         ("reorder", C.c_int32), ("key_mode", C.c_int32), ("check_nonphys", C.c_int32),
         ("periodic", C.c_int32), ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
+        ("integrator", C.c_int32), ("pad2", C.c_int32),
     ]
 
 

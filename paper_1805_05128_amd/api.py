@@ -65,6 +65,7 @@ class Params:
     check_nonphys: bool = False  # csph_step: wait and raise NonPhysicalState (state written)
     periodic: int = 0  # bit mask of periodic axes (1 x, 2 y, 4 z) ...
     box: Optional[Tuple[Tuple[float, float, float], Tuple[float, float, float]]] = None  # ... box
+    integrator: str = "euler"  # "euler" (symplectic Euler) | "rk2" (two-stage Runge-Kutta)
 
     def c(self) -> N.CsphParams:
         p = N.CsphParams()
@@ -84,6 +85,7 @@ class Params:
         p.key_mode = N.CSPH_KEY_MORTON if self.key_mode == "morton" else N.CSPH_KEY_LINEAR
         p.check_nonphys = 1 if self.check_nonphys else 0
         p.periodic = int(self.periodic)
+        p.integrator = N.CSPH_INT_RK2 if self.integrator == "rk2" else N.CSPH_INT_EULER
         if self.box is not None:
             for a in range(3):
                 p.box_lo[a], p.box_hi[a] = float(self.box[0][a]), float(self.box[1][a])

@@ -84,7 +84,7 @@ struct ProfScope {
     ~ProfScope() { stop(); }
 };
 
-size_t ws_layout(Ws *w, void *base, int64_t n, int64_t ncell) {
+size_t ws_layout(Ws *w, void *base, int64_t n, int64_t ncell, bool rk2, int64_t ncell2) {
     size_t off = 0;
     char *b = (char *)base;
     auto take = [&](size_t bytes) -> void * {
@@ -121,6 +121,26 @@ size_t ws_layout(Ws *w, void *base, int64_t n, int64_t ncell) {
     for (int k = 0; k < 5; ++k) t.rate[k] = (double *)take(sizeof(double) * un);
     t.sig = (double *)take(sizeof(double) * un);
     t.cs = (int32_t *)take(sizeof(int32_t) * (size_t)(ncell + 1));
+    for (int k = 0; k < 8; ++k) t.stg[k] = nullptr;
+    for (int k = 0; k < 9; ++k) t.srt2[k] = nullptr;
+    t.srt2_d = nullptr;
+    t.perm2 = t.rk_cnt = t.cs2 = nullptr;
+    t.scan_tmp2 = nullptr;
+    t.t2 = nullptr;
+    if (rk2) {
+        for (int k = 0; k < 8; ++k) t.stg[k] = (double *)take(sizeof(double) * un);
+        for (int k = 0; k < 9; ++k) t.srt2[k] = (double *)take(sizeof(double) * un);
+        t.srt2_d = (double *)take(sizeof(double) * un);
+        t.perm2 = (int32_t *)take(sizeof(int32_t) * un);
+        t.rk_cnt = (int32_t *)take(sizeof(int32_t) * un);
+        t.t2 = (double *)take(sizeof(double));
+        // last, so that laying the workspace out again with the second mesh's size moves
+        // nothing the first stage wrote
+        const int64_t nc2 = ncell2 > 0 ? ncell2 : ncell;
+        t.cs2 = (int32_t *)take(sizeof(int32_t) * (size_t)(nc2 + 1));
+        const int64_t len2 = (n > nc2 ? n : nc2) + 1;
+        t.scan_tmp2 = (int64_t *)take(sizeof(int64_t) * (size_t)((len2 + kScanTile - 1) / kScanTile + 1));
+    }
     t.bytes = off;
     if (w) *w = t;
     return off;
@@ -166,6 +186,8 @@ static csph_status check_params(const csph_params *p, bool need_pair_d, const do
     if (!std::isfinite(p->cfl)) return fail(CSPH_EINVAL, "cfl not finite");
     if (p->wall && (!std::isfinite(p->wall_x0) || !std::isfinite(p->wall_v)))
         return fail(CSPH_EINVAL, "wall position/velocity not finite");
+    if (p->integrator != CSPH_INT_EULER && p->integrator != CSPH_INT_RK2)
+        return fail(CSPH_EINVAL, "integrator %d unknown", p->integrator);
     if (p->periodic < 0 || p->periodic > 7) return fail(CSPH_EINVAL, "periodic mask %d unknown", p->periodic);
     if (p->wall && (p->periodic & 1)) return fail(CSPH_EINVAL, "the wall's axis x cannot be periodic");
     for (int a = 0; a < 3; ++a)
@@ -380,8 +402,9 @@ static csph_status make_grid(const double *x, const double *y, const double *z, 
     return CSPH_OK;
 }
 
-static csph_status need_ws(size_t have, int64_t n, int64_t ncell, size_t *ws_needed) {
-    size_t need = ws_layout(nullptr, nullptr, n, ncell);
+static csph_status need_ws(size_t have, int64_t n, int64_t ncell, size_t *ws_needed,
+                           bool rk2 = false, int64_t ncell2 = 0) {
+    size_t need = ws_layout(nullptr, nullptr, n, ncell, rk2, ncell2);
     if (ws_needed) *ws_needed = need;
     if (have < need) return fail(CSPH_ECAPACITY, "workspace needs %zu bytes, got %zu", need, have);
     return CSPH_OK;
@@ -466,8 +489,8 @@ const char *csph_last_error(void) { return g_err; }
 const char *csph_version(void) { return "csph-gfx950 0.1"; }
 
 size_t csph_workspace_size(int64_t n, int64_t ncell, const csph_params *p) {
-    (void)p;
-    return ws_layout(nullptr, nullptr, n < 0 ? 0 : n, ncell < 1 ? 1 : ncell);
+    const bool rk2 = p && p->integrator == CSPH_INT_RK2;
+    return ws_layout(nullptr, nullptr, n < 0 ? 0 : n, ncell < 1 ? 1 : ncell, rk2);
 }
 
 csph_status csph_grid_build(const double *x, const double *y, const double *z, int64_t n,
@@ -678,6 +701,8 @@ static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const cs
     if (!(p->cfl > 0.0) && !(std::isfinite(dt_in) && dt_in >= 0.0))
         return fail(CSPH_EINVAL, "cfl <= 0 needs a finite dt_in >= 0");
     if (p->wall && !t) return fail(CSPH_EINVAL, "the wall position needs t");
+    const bool rk2 = p->integrator == CSPH_INT_RK2;
+    if (rk2 && va) return fail(CSPH_EINVAL, "csph_step_voronoi takes the Euler step only");
     if ((s_in->mat && !s_out->mat) || (s_in->id && !s_out->id) ||
         (p->h_mode == CSPH_H_PAIR && !s_out->d))
         return fail(CSPH_EINVAL, "s_out must carry mat/id/d when s_in does");
@@ -691,10 +716,10 @@ static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const cs
     double dmax, ymin;
     r = make_grid(vin.x, vin.y, vin.z, vin.d, n, p, ws, ws_bytes, st, &g, &dmax, &ymin, true);
     if (r) return r;
-    r = need_ws(ws_bytes, n, g.ncell, ws_needed);
+    r = need_ws(ws_bytes, n, g.ncell, ws_needed, rk2);
     if (r) return r;
     Ws w;
-    ws_layout(&w, ws, n, g.ncell);
+    ws_layout(&w, ws, n, g.ncell, rk2);
     GridDev gd = grid_dev(g, true, ymin);
     PairConst pc = pair_const(p, dmax);
     EosDev eos = eos_dev(p);
@@ -735,7 +760,50 @@ static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const cs
         ProfScope pr(CSPH_PROF_RATES, st, prof);
         CSPH_HIP(launch_rates(n, mixed, gd, pc, w, dst, dd, t, 0.0, p->cfl > 0.0, st));
     }
-    {
+    const int32_t *cnt_out = w.cnt;  // the neighbour counts of U (in the first stage's order)
+    if (rk2 && n > 0) {
+        {
+            ProfScope pr(CSPH_PROF_INTEGRATE, st, prof);
+            CSPH_HIP(launch_rk2_predict(n, dst, w, p->cfl, dt_in, pc, t, st));
+        }
+        cnt_out = w.rk_cnt;
+        // second evaluation, at U1: its own mesh, order and records
+        double *d1 = pair ? dd : nullptr;
+        csph_grid g2;
+        double dmax2, ymin2;
+        r = make_grid(w.stg[0], w.stg[1], w.stg[2], d1, n, p, ws, ws_bytes, st, &g2, &dmax2,
+                      &ymin2, true);
+        if (r) return r;
+        r = need_ws(ws_bytes, n, g.ncell, ws_needed, true, g2.ncell);
+        if (r) return r;
+        ws_layout(&w, ws, n, g.ncell, true, g2.ncell);
+        Ws w2 = w;
+        w2.cs = w.cs2;
+        w2.scan_tmp = w.scan_tmp2;
+        GridDev gd2 = grid_dev(g2, true, ymin2);
+        PairConst pc2 = pair_const(p, dmax2);
+        csph_state u1{n,       w.stg[0], w.stg[1], w.stg[2], w.stg[3], w.stg[4], w.stg[5],
+                      w.stg[6], w.stg[7], dst[8],   dmat,     d1,       nullptr};
+        {
+            ProfScope pr(CSPH_PROF_BIN, st, prof);
+            CSPH_HIP(launch_bin(u1.x, u1.y, u1.z, n, gd2, w2, w.perm2, nullptr, w.cs2, st));
+        }
+        {
+            ProfScope pr(CSPH_PROF_PACK, st, prof);
+            CSPH_HIP(launch_fill_u64(w.zflag, 0x7ff0000000000000ull, 1, st));
+            CSPH_HIP(launch_pack(u1, n, w.perm2, eos, mixed, gd2, w2, w.srt2, nullptr,
+                                 pair ? w.srt2_d : nullptr, nullptr, nullptr,
+                                 check ? w.nonphys : nonphys, st));
+        }
+        {
+            ProfScope pr(CSPH_PROF_RATES, st, prof);
+            CSPH_HIP(launch_rates(n, mixed, gd2, pc2, w2, w.srt2, pair ? w.srt2_d : nullptr,
+                                  w.t2, 0.0, 0, st));
+        }
+        ProfScope pr(CSPH_PROF_INTEGRATE, st, prof);
+        CSPH_HIP(launch_rk2_combine(n, dst, w, p->cfl, dt_in, pc, t, st));
+        CSPH_HIP(launch_finish_step(n, w, p->cfl, dt_in, t, dt_used, totals, p->wall, st));
+    } else {
         ProfScope pr(CSPH_PROF_INTEGRATE, st, prof);
         VoroDev vd{};
         if (va) {
@@ -756,13 +824,13 @@ static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const cs
     if (n > 0) {
         if (p->reorder) {
             if (nbr_count)
-                CSPH_HIP(hipMemcpyAsync(nbr_count, w.cnt, sizeof(int32_t) * n,
+                CSPH_HIP(hipMemcpyAsync(nbr_count, cnt_out, sizeof(int32_t) * n,
                                         hipMemcpyDeviceToDevice, st));
         } else {
             csph_state o = vout;
             if (!pair) o.d = nullptr;
             CSPH_HIP(launch_unpermute(n, w.perm, w.srt, vin.mat ? w.srt_mat : nullptr, dd,
-                                      did, w.cnt, o, nbr_count, st));
+                                      did, cnt_out, o, nbr_count, st));
         }
     }
     pro.stop();
@@ -866,6 +934,8 @@ csph_status csph_step_vlist(csph_state *s, const csph_params *p, double *t, doub
     if (r) return r;
     if (p->h_mode != CSPH_H_FIXED) return fail(CSPH_EINVAL, "Verlet lists need fixed-h mode");
     if (p->periodic) return fail(CSPH_EINVAL, "Verlet lists do not support periodic boundaries");
+    if (p->integrator != CSPH_INT_EULER)
+        return fail(CSPH_EINVAL, "Verlet-list steps take the Euler step only");
     if (!(p->cfl > 0.0) && !(std::isfinite(dt_in) && dt_in >= 0.0))
         return fail(CSPH_EINVAL, "cfl <= 0 needs a finite dt_in >= 0");
     if (p->wall && !t) return fail(CSPH_EINVAL, "the wall position needs t");
@@ -1059,6 +1129,8 @@ csph_status csph_step_vjp(const csph_state *s_n, const csph_params *p, double dt
     g_err[0] = 0;
     if (!std::isfinite(dt) || dt < 0.0) return fail(CSPH_EINVAL, "dt must be finite and >= 0");
     if (s_n && s_n->n > 0 && !grad_ok(g_next)) return fail(CSPH_EINVAL, "g_next has NULL arrays");
+    if (p && p->integrator != CSPH_INT_EULER)
+        return fail(CSPH_EINVAL, "the step's adjoint is that of the Euler step only");
     return vjp_common(s_n, p, nullptr, &g_next, dt, g_prev, 0, g_eos, ws, ws_bytes, ws_needed,
                       (hipStream_t)stream);
 }

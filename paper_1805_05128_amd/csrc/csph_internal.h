@@ -208,10 +208,23 @@ struct Ws {
     unsigned long long *zflag;    // 0 once the pack meets a zero impedance Z = rho c
     int64_t *nonphys;             // scratch counter
     double *tot_part;             // kReduceBlocks * 10
+    // two-stage Runge-Kutta steps only (ws_layout with rk2): the predicted state U1 in the
+    // first stage's cell order (x, y, z wrapped into a periodic box; vx vy vz rho E), the
+    // second stage's sorted copy, order and cell ranges, the first stage's neighbour counts
+    // and the second stage's time t + dt
+    double *stg[8];
+    double *srt2[9];
+    double *srt2_d;
+    int32_t *perm2;
+    int32_t *rk_cnt;
+    double *t2;
+    int32_t *cs2;                 // ncell2 + 1
+    int64_t *scan_tmp2;           // scan tiles of the second mesh
     size_t bytes;
 };
 
-size_t ws_layout(Ws *w, void *base, int64_t n, int64_t ncell);
+size_t ws_layout(Ws *w, void *base, int64_t n, int64_t ncell, bool rk2 = false,
+                 int64_t ncell2 = 0);
 
 // ---------------------------------------------------------------- launchers
 // Every launcher enqueues on `st` and returns the HIP status of the launch.
@@ -279,6 +292,13 @@ struct ListGate {
 };
 // With pc.wall (and t, the device time at the step's start), particles behind the piston
 // plane at the new time are reflected off it.  vo (optional): also the Voronoi ownership.
+// Two-stage Runge-Kutta: the predicted state U1 (into w.stg, with the first stage's counts
+// saved and t + dt) and the convex combination of the second stage (in place in st8, the first
+// stage's cell order, with block partial totals).
+hipError_t launch_rk2_predict(int64_t n, double *const st8[9], const Ws &w, double cfl,
+                              double dt_in, const PairConst &pc, const double *t, hipStream_t st);
+hipError_t launch_rk2_combine(int64_t n, double *const st8[9], const Ws &w, double cfl,
+                              double dt_in, const PairConst &pc, const double *t, hipStream_t st);
 hipError_t launch_integrate(int64_t n, double *const st8[9], const Ws &w, double cfl, double dt_in,
                             const PairConst &pc, const double *t, hipStream_t st,
                             const VoroDev *vo = nullptr, const ListGate *lg = nullptr);

@@ -91,6 +91,46 @@ __device__ __forceinline__ double wrap_axis(const PerDev &p, int a, double v) {
     return v;
 }
 
+// The workgroup's double-double sums (m, m vx, m vy, m vz, m E) reduced in a fixed tree into
+// part[block * 10 ..] as (hi, lo) pairs; ends with a barrier.
+__device__ __forceinline__ void block_totals(const DD acc[5], double *__restrict__ part) {
+    __shared__ double sh[2][5][kBlock];
+    for (int k = 0; k < 5; ++k) {
+        sh[0][k][threadIdx.x] = acc[k].hi;
+        sh[1][k][threadIdx.x] = acc[k].lo;
+    }
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            for (int k = 0; k < 5; ++k) {
+                DD a{sh[0][k][threadIdx.x], sh[1][k][threadIdx.x]};
+                DD b{sh[0][k][threadIdx.x + w], sh[1][k][threadIdx.x + w]};
+                DD c = dd_add(a, b);
+                sh[0][k][threadIdx.x] = c.hi;
+                sh[1][k][threadIdx.x] = c.lo;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 5) {
+        part[blockIdx.x * 10 + 2 * threadIdx.x] = sh[0][threadIdx.x][0];
+        part[blockIdx.x * 10 + 2 * threadIdx.x + 1] = sh[1][threadIdx.x][0];
+    }
+}
+
+// The piston's reflection of a new position (normal axis y in the kernels' axes) in the
+// wall's frame: y <- 2 yw - y, v_y <- 2 v_w - v_y, E changed by the kinetic-energy difference
+// (the specific internal energy kept).
+__device__ __forceinline__ void reflect(const WallDev &wall, double yw, double &y, double &vy,
+                                        double &E) {
+    if (wall.on && y < yw) {
+        const double vr = 2.0 * wall.v - vy;
+        E = E + 0.5 * ((vr * vr) - (vy * vy));
+        vy = vr;
+        y = 2.0 * yw - y;
+    }
+}
+
 // With VORO the kernel also assigns each particle's new position to its Voronoi generator
 // (eq. VoronoiDefinition: FP64 argmin of ((dx dx) + (dy dy)) + (dz dz) without contraction,
 // k scanned upwards with a strict comparison, so a tie keeps the smaller k) and counts
@@ -132,12 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(int64_t n, State9 s, Rates
         double E = s.f[7][i] + dt * r.f[4][i];
         double rho = s.f[6][i] + dt * r.f[0][i];
         double y = s.f[1][i] + dt * vy;
-        if (wall.on && y < yw) {
-            const double vr = 2.0 * wall.v - vy;
-            E = E + 0.5 * ((vr * vr) - (vy * vy));
-            vy = vr;
-            y = 2.0 * yw - y;
-        }
+        reflect(wall, yw, y, vy, E);
         double x = s.f[0][i] + dt * vx, z = s.f[2][i] + dt * vz;
         if (per.mask) {  // after the reflection, as the wall's axis is never periodic
             x = wrap_axis(per, 0, x);
@@ -174,28 +209,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(int64_t n, State9 s, Rates
         acc[3] = dd_add1(acc[3], m * vz);
         acc[4] = dd_add1(acc[4], m * E);
     }
-    __shared__ double sh[2][5][kBlock];
-    for (int k = 0; k < 5; ++k) {
-        sh[0][k][threadIdx.x] = acc[k].hi;
-        sh[1][k][threadIdx.x] = acc[k].lo;
-    }
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            for (int k = 0; k < 5; ++k) {
-                DD a{sh[0][k][threadIdx.x], sh[1][k][threadIdx.x]};
-                DD b{sh[0][k][threadIdx.x + w], sh[1][k][threadIdx.x + w]};
-                DD c = dd_add(a, b);
-                sh[0][k][threadIdx.x] = c.hi;
-                sh[1][k][threadIdx.x] = c.lo;
-            }
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x < 5) {
-        part[blockIdx.x * 10 + 2 * threadIdx.x] = sh[0][threadIdx.x][0];
-        part[blockIdx.x * 10 + 2 * threadIdx.x + 1] = sh[1][threadIdx.x][0];
-    }
+    block_totals(acc, part);
     if (lg.pairs) {  // integer sums: exact in any order
         for (int o = 32; o > 0; o >>= 1) npairs += __shfl_xor(npairs, o, 64);
         if ((threadIdx.x & 63) == 0 && npairs) atomicAdd(lg.pairs, npairs);
@@ -206,6 +220,103 @@ __global__ __launch_bounds__(kBlock) void k_integrate(int64_t n, State9 s, Rates
             if (hq[k] && vo.site_pairs) atomicAdd(&vo.site_pairs[k], hq[k]);
         }
     }
+}
+
+// Two-stage Runge-Kutta, first stage: U1 = U + dt F(U) with r1 = r + dt v (the old velocity),
+// positions wrapped into a periodic box for the second evaluation; the first stage's neighbour
+// counts are kept (the second evaluation overwrites them) and t + dt stored for the second
+// evaluation's piston position.
+struct Stage8 {
+    double *f[8];  // x y z vx vy vz rho E
+};
+
+__global__ __launch_bounds__(kBlock) void k_rk2_predict(int64_t n, State9 s, Rates5 r,
+                                                        const unsigned long long *dtmin,
+                                                        double cfl, double dt_in, PerDev per,
+                                                        const double *t, double *t2,
+                                                        const int32_t *__restrict__ cnt,
+                                                        int32_t *__restrict__ cnt_save,
+                                                        Stage8 u1) {
+    const double dt = step_dt(dtmin, cfl, dt_in);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *t2 = (t ? *t : 0.0) + dt;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const double vx = s.f[3][i], vy = s.f[4][i], vz = s.f[5][i];
+        u1.f[0][i] = wrap_axis(per, 0, s.f[0][i] + dt * vx);
+        u1.f[1][i] = wrap_axis(per, 1, s.f[1][i] + dt * vy);
+        u1.f[2][i] = wrap_axis(per, 2, s.f[2][i] + dt * vz);
+        u1.f[3][i] = vx + dt * r.f[1][i];
+        u1.f[4][i] = vy + dt * r.f[2][i];
+        u1.f[5][i] = vz + dt * r.f[3][i];
+        u1.f[6][i] = s.f[6][i] + dt * r.f[0][i];
+        u1.f[7][i] = s.f[7][i] + dt * r.f[4][i];
+        cnt_save[i] = cnt[i];
+    }
+}
+
+// Second stage: for slot q of the second evaluation's cell order (its particle i in the first
+// stage's order, perm2[q] = i), U' = U/2 + (U1 + dt F(U1))/2 and r' = r/2 + (r1 + dt v1)/2, with
+// r1 = r + dt v formed again exactly as the first stage formed it (unwrapped), then the
+// piston's reflection at t + dt and the periodic wrap; written over U in place, with the block
+// partial totals of the new state.
+__global__ __launch_bounds__(kBlock) void k_rk2_combine(int64_t n, State9 s, Rates5 r2,
+                                                        const unsigned long long *dtmin,
+                                                        double cfl, double dt_in, WallDev wall,
+                                                        PerDev per,
+                                                        const int32_t *__restrict__ perm2,
+                                                        Stage8 u1, double *__restrict__ part) {
+    const double dt = step_dt(dtmin, cfl, dt_in);
+    const double yw = wall.on ? wall.y0 + wall.v * (*wall.t + dt) : 0.0;
+    DD acc[5];
+    for (int k = 0; k < 5; ++k) acc[k] = DD{0.0, 0.0};
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * kBlock) {
+        const int i = perm2[q];
+        const double x = s.f[0][i], y = s.f[1][i], z = s.f[2][i];
+        const double vx = s.f[3][i], vy = s.f[4][i], vz = s.f[5][i];
+        const double vx1 = u1.f[3][i], vy1 = u1.f[4][i], vz1 = u1.f[5][i];
+        const double x1 = x + dt * vx, y1 = y + dt * vy, z1 = z + dt * vz;
+        double nvx = 0.5 * vx + 0.5 * (vx1 + dt * r2.f[1][q]);
+        double nvy = 0.5 * vy + 0.5 * (vy1 + dt * r2.f[2][q]);
+        double nvz = 0.5 * vz + 0.5 * (vz1 + dt * r2.f[3][q]);
+        double nE = 0.5 * s.f[7][i] + 0.5 * (u1.f[7][i] + dt * r2.f[4][q]);
+        const double nrho = 0.5 * s.f[6][i] + 0.5 * (u1.f[6][i] + dt * r2.f[0][q]);
+        double nx = 0.5 * x + 0.5 * (x1 + dt * vx1);
+        double ny = 0.5 * y + 0.5 * (y1 + dt * vy1);
+        double nz = 0.5 * z + 0.5 * (z1 + dt * vz1);
+        reflect(wall, yw, ny, nvy, nE);
+        if (per.mask) {
+            nx = wrap_axis(per, 0, nx);
+            ny = wrap_axis(per, 1, ny);
+            nz = wrap_axis(per, 2, nz);
+        }
+        s.f[0][i] = nx;
+        s.f[1][i] = ny;
+        s.f[2][i] = nz;
+        s.f[3][i] = nvx;
+        s.f[4][i] = nvy;
+        s.f[5][i] = nvz;
+        s.f[6][i] = nrho;
+        s.f[7][i] = nE;
+        const double m = s.f[8][i];
+        acc[0] = dd_add1(acc[0], m);
+        acc[1] = dd_add1(acc[1], m * nvx);
+        acc[2] = dd_add1(acc[2], m * nvy);
+        acc[3] = dd_add1(acc[3], m * nvz);
+        acc[4] = dd_add1(acc[4], m * nE);
+    }
+    block_totals(acc, part);
+}
+
+static PerDev per_dev(const PairConst &pc) {
+    PerDev per{};
+    per.mask = pc.per;
+    for (int a = 0; a < 3; ++a) {
+        per.lo[a] = pc.lo[a];
+        per.hi[a] = pc.hi[a];
+        per.L[a] = pc.L[a];
+    }
+    return per;
 }
 
 static int integrate_blocks(int64_t n) {
@@ -220,13 +331,7 @@ hipError_t launch_integrate(int64_t n, double *const st8[9], const Ws &w, double
     for (int k = 0; k < 9; ++k) s.f[k] = st8[k];
     Rates5 r{{w.rate[0], w.rate[1], w.rate[2], w.rate[3], w.rate[4]}};
     WallDev wall{pc.wall && t ? 1 : 0, pc.wall_y0, pc.wall_v, t};
-    PerDev per{};
-    per.mask = pc.per;
-    for (int a = 0; a < 3; ++a) {
-        per.lo[a] = pc.lo[a];
-        per.hi[a] = pc.hi[a];
-        per.L[a] = pc.L[a];
-    }
+    const PerDev per = per_dev(pc);
     VoroDev v{};
     size_t shm = 0;
     if (vo && vo->K > 0) {
@@ -239,6 +344,33 @@ hipError_t launch_integrate(int64_t n, double *const st8[9], const Ws &w, double
     int nb = integrate_blocks(n);
     k_integrate<<<nb, kBlock, shm, st>>>(n, s, r, w.dtmin, cfl, dt_in, wall, per, v, g,
                                          w.tot_part);
+    return hipGetLastError();
+}
+
+hipError_t launch_rk2_predict(int64_t n, double *const st8[9], const Ws &w, double cfl,
+                              double dt_in, const PairConst &pc, const double *t, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    State9 s;
+    for (int k = 0; k < 9; ++k) s.f[k] = st8[k];
+    Rates5 r{{w.rate[0], w.rate[1], w.rate[2], w.rate[3], w.rate[4]}};
+    Stage8 u1;
+    for (int k = 0; k < 8; ++k) u1.f[k] = w.stg[k];
+    k_rk2_predict<<<integrate_blocks(n), kBlock, 0, st>>>(n, s, r, w.dtmin, cfl, dt_in,
+                                                          per_dev(pc), t, w.t2, w.cnt, w.rk_cnt,
+                                                          u1);
+    return hipGetLastError();
+}
+
+hipError_t launch_rk2_combine(int64_t n, double *const st8[9], const Ws &w, double cfl,
+                              double dt_in, const PairConst &pc, const double *t, hipStream_t st) {
+    State9 s;
+    for (int k = 0; k < 9; ++k) s.f[k] = st8[k];
+    Rates5 r{{w.rate[0], w.rate[1], w.rate[2], w.rate[3], w.rate[4]}};
+    Stage8 u1;
+    for (int k = 0; k < 8; ++k) u1.f[k] = w.stg[k];
+    WallDev wall{pc.wall && t ? 1 : 0, pc.wall_y0, pc.wall_v, t};
+    k_rk2_combine<<<integrate_blocks(n), kBlock, 0, st>>>(n, s, r, w.dtmin, cfl, dt_in, wall,
+                                                          per_dev(pc), w.perm2, u1, w.tot_part);
     return hipGetLastError();
 }
 

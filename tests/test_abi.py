@@ -212,3 +212,26 @@ def test_periodic_params_checked_on_the_host():
     g = N.CsphGrad(*[dev((1 << 25) + 1024 * k, C.c_double) for k in range(8)])
     st = L.csph_step_vjp(C.byref(a), C.byref(p), 0.1, g, g, None, None, 0, None, None)
     assert st == N.CSPH_EINVAL and b"periodic" in L.csph_last_error()
+
+
+def test_integrator_checked_on_the_host():
+    """An unknown integrator, and the two-stage Runge-Kutta step where only the Euler step is
+    taken (Verlet-list steps, the step's adjoint), are refused before any device work; the
+    workspace of a Runge-Kutta step is larger."""
+    L = N.load()
+    p = P.Params().c()
+    p.integrator = 5
+    st = L.csph_init_energy(None, None, None, None, None, None, 0, C.byref(p), None, None)
+    assert st == N.CSPH_EINVAL and b"integrator" in L.csph_last_error()
+    p = P.Params(integrator="rk2").c()
+    a = _fake_state(4096)
+    dev = lambda addr, t: C.cast(C.c_void_p(addr), C.POINTER(t))
+    st = L.csph_step_vlist(C.byref(a), C.byref(p), dev(1 << 24, C.c_double), 0.0, None, None,
+                           None, None, dev(1 << 20, C.c_int32), dev(1 << 21, C.c_int32), 64,
+                           dev(1 << 22, C.c_double), C.c_void_p(1 << 23), None, 0, None, None)
+    assert st == N.CSPH_EINVAL and b"Euler" in L.csph_last_error()
+    g = N.CsphGrad(*[dev((1 << 25) + 1024 * k, C.c_double) for k in range(8)])
+    st = L.csph_step_vjp(C.byref(a), C.byref(p), 0.1, g, g, None, None, 0, None, None)
+    assert st == N.CSPH_EINVAL and b"Euler" in L.csph_last_error()
+    assert P.workspace_size(1000, 100, P.Params(integrator="rk2")) > \
+        P.workspace_size(1000, 100, P.Params()) + 1000 * 150
