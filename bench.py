@@ -154,12 +154,18 @@ def balance_timing(P, torch, run, sites, iters=10):
 
 def impact_run(P, torch, ci, steps):
     """Plate impact (589 824 particles, no walls: a closed system), ``steps`` steps from the
-    initial state in each precision: time per step, pair interactions/s, and the drift of the
-    compensated totals of momentum and energy from the first step's state to the last."""
+    initial state in each precision, and in mixed precision with the target's lateral faces
+    periodic (the paper's plate tests are periodic across the impact direction): time per
+    step, pair interactions/s, and the drift of the compensated totals of momentum and energy
+    from the first step's state to the last."""
     w = ci.config1()
     out = {"workload": w.name, "particles": w.n, "steps": steps}
-    for prec in ("mixed", "fp64"):
-        params = P.Params.from_workload(w, precision=prec, reorder=True, cell_size=1.0)
+    for prec in ("mixed", "fp64", "mixed_periodic_xy"):
+        over = {}
+        if prec == "mixed_periodic_xy":
+            over = dict(periodic=3, box=((0.0, 0.0, 0.0), (128.0, 128.0, 0.0)))
+        params = P.Params.from_workload(w, precision=prec[:5], reorder=True, cell_size=1.0,
+                                        **over)
         cnt = torch.empty(w.n, dtype=torch.int32, device="cuda")
         pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
         # warm-up on a throwaway copy, then the timed run from the initial state
@@ -196,6 +202,49 @@ def impact_run(P, torch, ci, steps):
     out["mixed_speedup_over_fp64"] = out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"]
     out["note"] = ("drifts of the compensated totals sum(m v), sum(m E) between the states after "
                    "step 1 and the last step, relative to sum(m|v|) and |sum(m E)|")
+    return out
+
+
+def rk2_run(P, torch, w, cell, steps):
+    """The two-stage Runge-Kutta step (two rate evaluations per step) on the porous shock in
+    mixed precision, ``steps`` steps from the initial state after 3 warm-up steps on a
+    throwaway copy: time per step and the directed pairs of the first evaluation."""
+    params = P.Params.from_workload(w, precision="mixed", reorder=True, cell_size=cell,
+                                    integrator="rk2")
+    cnt = torch.empty(w.n, dtype=torch.int32, device="cuda")
+    pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ws = P.Workspace("cuda")
+    for warm in (True, False):
+        state = P.state_from_workload(w, params, "cuda", with_id=False)
+        other = state.like()
+        sc = P.StepScalars("cuda")
+        k = 3 if warm else steps
+        P.profile_enable(True)
+        P.profile_read()
+        with collector_off():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(k):
+                o = P.csph_step(state, params, sc, s_out=other, nbr_count=cnt, ws=ws)
+                if not warm:
+                    pairs += cnt.sum()
+                state, other = o, state
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+        prof = P.profile_read()
+        P.profile_enable(False)
+    behind = int((state["x"] < w.wall[0] + w.wall[1] * float(sc.t.item())).sum().item())
+    out = {"workload": w.name, "particles": w.n, "steps": steps, "precision": "mixed",
+           "rate_evaluations_per_step": 2, "ms_per_step": 1e3 * el / steps,
+           "pairs_per_step": int(pairs.item()) / steps,
+           "pairs_per_s": 2 * int(pairs.item()) / el,
+           "kernel_ms": {g: round(v[1] / max(v[0], 1), 4) for g, v in prof.items() if v[0] > 0},
+           "t_end": float(sc.t.item()), "behind_wall_after_run": behind,
+           "note": "pairs_per_s counts both evaluations (the second's pairs taken equal to the "
+                   "first's); kernel_ms are per launch, two launches of bin, pack and rates "
+                   "per step"}
+    del state, other, ws
+    torch.cuda.empty_cache()
     return out
 
 
@@ -650,6 +699,9 @@ def main():
         line["paper_mode"] = paper_mode_run(P, torch, ci, 20)
         log(f"paper mode mixed {line['paper_mode']['mixed']['ms_per_step']:.3f} ms/step, "
             f"fp64 {line['paper_mode']['fp64']['ms_per_step']:.3f} ms/step")
+        log("two-stage Runge-Kutta steps ...")
+        line["rk2"] = rk2_run(P, torch, w, args.cell, 20)
+        log(f"rk2 mixed {line['rk2']['ms_per_step']:.3f} ms/step")
     if args.extra and args.collision:
         log("two-body collision, 64 M particles ...")
         line["collision"] = collision_run(P, torch, ci)
