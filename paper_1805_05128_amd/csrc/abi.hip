@@ -111,6 +111,7 @@ size_t ws_layout(Ws *w, void *base, int64_t n, int64_t ncell, bool rk2, int64_t 
     t.recA = take(32 * (un + 2));
     t.recB = take(32 * un);
     t.recC = take(16 * un);
+    t.recF = take(16 * (un + 2));  // followed by two zero records, as the mixed A records
     t.recD = take(32 * un);
     t.recE = (double *)take(sizeof(double) * un);
     t.eos_part = (double *)take(sizeof(double) * 2 * CSPH_MAX_EOS * ((un + kBlock - 1) / kBlock + 1));

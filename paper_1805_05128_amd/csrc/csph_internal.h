@@ -194,6 +194,7 @@ struct Ws {
     int32_t *perm;                // n
     int32_t *bin_tmp;             // n: cell order before the in-cell ranking (binning only)
     void *recA, *recB, *recC;     // pair records (FP64: 32+32+16 B; mixed: 16+16+8 B)
+    void *recF;                   // FP64 stencil walks: cell-relative FP32 records (16 B)
     void *recD;                   // adjoint pair weights (32 B)
     double *recE;                 // adjoint energy weight
     double *eos_part;             // per-block EOS-parameter gradients, ceil(n/kBlock) * 16

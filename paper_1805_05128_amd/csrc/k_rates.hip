@@ -30,10 +30,9 @@ struct DstState {
 
 // Gather particle perm[s] into slot s: sorted FP64 state copy, EOS
 // (e = E - |v|^2/2; ideal gas, stiffened gas or Mie-Grueneisen), pair record.
-// Zero records after the n FP32 stencil records: the FP32 stencil walk loads up to kUS - 1
-// records past a row's last one (the A record buffer has room for them)
+// Zero records after the n FP32 stencil records (cell-relative offsets, read by the candidate
+// tests of both kernels): a walk loads up to kUS - 1 (kUS64 - 1) records past a row's last one
 constexpr int kRecPad = 2;
-constexpr int kRecPad64 = 2;  // FP64 stencil walk: kUS64 - 1 records past a row
 
 template <bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_pack(int64_t n, SrcState src,
@@ -43,7 +42,8 @@ __global__ __launch_bounds__(kBlock) void k_pack(int64_t n, SrcState src,
                                                  void *__restrict__ recC, DstState dst,
                                                  int64_t *__restrict__ nonphys,
                                                  unsigned long long *__restrict__ zflag,
-                                                 const int32_t *__restrict__ gate) {
+                                                 const int32_t *__restrict__ gate,
+                                                 float4 *__restrict__ recF) {
     if (gate && *gate == 0) return;
     int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s >= n) return;
@@ -76,29 +76,28 @@ __global__ __launch_bounds__(kBlock) void k_pack(int64_t n, SrcState src,
         ((double4 *)recA)[s] = make_double4(x, y, z, V);
         ((float4 *)recB)[s] = make_float4((float)vx, (float)vy, (float)vz, (float)P);
         ((float4 *)recC)[s] = make_float4((float)Z, (float)c, (float)V, 0.0f);
-    } else if (MIXED) {
-        {  // cell-relative offsets (stencil walks)
-        int cx = cell_coord(x, g.ox, g.inv, g.dx);
-        int cy = cell_coord(y, g.oy, g.inv, g.dy);
-        int cz = cell_coord(z, g.oz, g.inv, g.dz);
-        float ox = (float)(x - (g.ox + (double)cx * g.cell));
-        float oy = (float)(y - (g.oy + (double)cy * g.cell));
-        float oz = (float)(z - (g.oz + (double)cz * g.cell));
-        // x offset, y, z offsets from the cell origin and the cell's x index
-        ((float4 *)recA)[s] = make_float4(ox, oy, oz, (float)cx);
-        if (s == n - 1)
-            for (int p = 1; p <= kRecPad; ++p)
-                ((float4 *)recA)[n - 1 + p] = make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-        ((float4 *)recB)[s] = make_float4((float)vx, (float)vy, (float)vz, (float)P);
-        ((float4 *)recC)[s] = make_float4((float)Z, (float)c, (float)V, 0.0f);
     } else {
-        ((double4 *)recA)[s] = make_double4(x, y, z, V);
-        ((double4 *)recB)[s] = make_double4(vx, vy, vz, P);
-        ((double2 *)recC)[s] = make_double2(Z, c);
-        if (s == n - 1)
-            for (int p = 1; p <= kRecPad64; ++p)
-                ((double4 *)recA)[n - 1 + p] = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (perm) {  // stencil walks: cell-relative FP32 offsets (the FP64 walk tests with them)
+            int cx = cell_coord(x, g.ox, g.inv, g.dx);
+            int cy = cell_coord(y, g.oy, g.inv, g.dy);
+            int cz = cell_coord(z, g.oz, g.inv, g.dz);
+            float ox = (float)(x - (g.ox + (double)cx * g.cell));
+            float oy = (float)(y - (g.oy + (double)cy * g.cell));
+            float oz = (float)(z - (g.oz + (double)cz * g.cell));
+            // x offset, y, z offsets from the cell origin and the cell's x index
+            float4 *F = MIXED ? (float4 *)recA : recF;
+            F[s] = make_float4(ox, oy, oz, (float)cx);
+            if (s == n - 1)
+                for (int p = 1; p <= kRecPad; ++p) F[n - 1 + p] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        if (MIXED) {
+            ((float4 *)recB)[s] = make_float4((float)vx, (float)vy, (float)vz, (float)P);
+            ((float4 *)recC)[s] = make_float4((float)Z, (float)c, (float)V, 0.0f);
+        } else {
+            ((double4 *)recA)[s] = make_double4(x, y, z, V);
+            ((double4 *)recB)[s] = make_double4(vx, vy, vz, P);
+            ((double2 *)recC)[s] = make_double2(Z, c);
+        }
     }
 }
 
@@ -119,10 +118,10 @@ hipError_t launch_pack(const csph_state &s, int64_t n, const int32_t *perm, cons
     unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
     if (mixed)
         k_pack<true><<<nb, kBlock, 0, st>>>(n, src, perm, eos, g, recA, w.recB, w.recC, ds,
-                                            nonphys, w.zflag, gate);
+                                            nonphys, w.zflag, gate, nullptr);
     else
         k_pack<false><<<nb, kBlock, 0, st>>>(n, src, perm, eos, g, recA, w.recB, w.recC, ds,
-                                             nonphys, w.zflag, gate);
+                                             nonphys, w.zflag, gate, (float4 *)w.recF);
     return hipGetLastError();
 }
 
@@ -171,6 +170,13 @@ struct RateOut {
     unsigned long long *dtmin;
     const unsigned long long *zflag;  // 0: some impedance is zero (see k_pack)
 };
+
+// Candidates whose FP32 squared distance lies within this relative band of
+// the squared support are decided in FP64 from the FP64 positions (the mixed
+// kernel re-tests them at the pop; the FP64 kernel queues them and decides
+// every pop in FP64), so both accept exactly the FP64 neighbour set (the FP32
+// error of r^2 is below 1e-6 relative for offsets within a few cells).
+constexpr float kBand = 4e-5f;
 
 // ---------------------------------------------------------------- FP64 rates
 //
@@ -257,15 +263,16 @@ __device__ __forceinline__ void pair64(bool use, double dx, double dy, double dz
 
 // FP64 stencil walk: candidates per lock-step iteration, pops per drain trigger (as in the
 // FP32 kernel: the loop's copies of the live sums are paid once per two pops)
-constexpr int kUS64 = 2;
-constexpr int kPop64 = 1;
-static_assert(kUS64 - 1 <= kRecPad64, "the FP64 stencil walk reads up to kUS64 - 1 records past a row");
+constexpr int kUS64 = 3;
+constexpr int kPop64 = 2;
+static_assert(kUS64 - 1 <= kRecPad, "the FP64 stencil walk reads up to kUS64 - 1 FP32 records past a row");
 
 template <bool PAIR, bool WALL, bool PER>
 struct Rates64 {
     const double4 *__restrict__ A;
     const double4 *__restrict__ B;
     const double2 *__restrict__ Cz;
+    const float4 *__restrict__ F;  // stencil walks: cell-relative FP32 records (the test)
     const double *__restrict__ dsz;
     const int32_t *__restrict__ cs;
     GridDev g;
@@ -278,14 +285,20 @@ struct Rates64 {
     double2 zc;
     double di, yw, vw2;  // wall position along y, twice its velocity
     Stencil t, ti;       // stencils of i and of its mirror image
-    // periodic images: i's faces (image_faces), the image the walk is on (wave-uniform mask)
-    // and its stencil
+    // the candidate test in FP32 from cell-relative records, as in the mixed kernel: i's
+    // record (offsets and its cell's x index), D, the support bound (squared, with the band)
+    // and the wall's distance
+    float4 a32;
+    float Df, hi32, wd;
+    // periodic images: i's faces (image_faces), the image the walk is on (wave-uniform mask),
+    // its stencil, i's FP32 offsets from the image point's cell origin and that cell's x index
     int nf = 0, im = 0;
     Stencil tm;
+    float amx = 0.f, amy = 0.f, amz = 0.f, cxm = 0.f;
     double ar = 0.0, avx = 0.0, avy = 0.0, avz = 0.0, aE = 0.0, sig = 0.0;
-    // ring counters in entries (their count is |N(i)|); an entry is the partner's 32-byte
-    // record offset, bit 0 set for a mirror image, bits 1-3 the periodic image mask
-    int qw = 0, qr = 0, cntl = 0;
+    // ring counters in entries; an entry is the partner's 32-byte record offset, bit 0 set for
+    // a mirror image, bits 1-3 the periodic image mask.  cnt: the exact members popped, |N(i)|
+    int qw = 0, qr = 0, cnt = 0;
 
     __device__ __forceinline__ uint32_t &slot(int q) {
         return *(uint32_t *)(qb + (((q & (kQ - 1)) * kSlot64) | lane4));
@@ -311,34 +324,42 @@ struct Rates64 {
             dy = dy - image_shift(pc, nf, mm, 1);
             dz = dz - image_shift(pc, nf, mm, 2);
         }
+        // exact FP64 membership (the walk queued every candidate within the FP32 band of the
+        // support), no contraction
         const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
-        double invH = pc.invH, dwc = pc.dwc;
+        double invH = pc.invH, dwc = pc.dwc, H2 = pc.H2;
         if (PAIR) {
             const double H = pc.kappa * (0.5 * (di + dsz[j]));
+            H2 = H * H;
             invH = rcp64(H > 0.0 ? H : 1.0);
             const double i2 = invH * invH;
             dwc = (210.0 / M_PI) * (i2 * i2);
         }
-        pair64<ZS>(has && r2 != 0.0, dx, dy, dz, r2, b, zc, bj.x, ghost ? vw2 - bj.y : bj.y, bj.z,
+        const bool in = has && r2 < H2;
+        cnt += (in && !ghost) ? 1 : 0;
+        pair64<ZS>(in && r2 != 0.0, dx, dy, dz, r2, b, zc, bj.x, ghost ? vw2 - bj.y : bj.y, bj.z,
                bj.w, zj.x, zj.y, aj.w, invH, dwc, ar, avx, avy, avz, aE, sig);
     }
 
     // one walk over the stencil: real partners, or mirror partners (GHOST); IMG: the walk
-    // around periodic image im of i (or of its mirror image).
+    // around periodic image im of i (or of its mirror image).  The candidates are tested in
+    // FP32 from the cell-relative records, as in the mixed kernel, and every one within the
+    // band of the support is queued: the pop decides membership exactly, in FP64.
     // One flat loop with wave-uniform branches (drain / next row / test a
     // chunk).
     template <bool GHOST, bool MIR, bool ZS, bool IMG>
     __device__ __forceinline__ void pass() {
+#pragma clang fp contract(fast)
         const bool on = live && (!GHOST || near_wall) && (!IMG || (nf & im) == im);
         // mirror partners: the particles on the stencil around the image of i
         const Stencil &st = IMG ? tm : GHOST ? ti : t;
-        const double shx = IMG ? image_shift(pc, nf, im, 0) : 0.0;
-        const double shy = IMG ? image_shift(pc, nf, im, 1) : 0.0;
-        const double shz = IMG ? image_shift(pc, nf, im, 2) : 0.0;
+        const float ax0 = IMG ? amx : a32.x, az0 = IMG ? amz : a32.z, cx0 = IMG ? cxm : a32.w;
+        const float ay0 = IMG && !GHOST ? amy : a32.y;
+        const int cy0 = IMG && !GHOST ? tm.cy : t.cy;
         const uint32_t tag = (GHOST ? 1u : 0u) | (IMG ? (uint32_t)im << 1 : 0u);
         int oy = st.R, oz = -st.R - 1;  // advanced to (-R, -R) before the first row
         int k = 0, j0 = 0, len = 0, jlast = 0;
-        float gz2 = 0.f;
+        float ay = 0.f, az = 0.f, gz2 = 0.f;
         for (;;) {
             if (__any(qw - qr > kQ - kUS64)) {  // keep every ring at <= kQ - kUS64 entries
 #pragma unroll
@@ -351,39 +372,37 @@ struct Rates64 {
                     if (++oz > st.R) break;
                     const float gz = slab_gap(st.zc, st.cz + oz);  // per plane of rows
                     gz2 = gz * gz;
+                    az = az0 - (float)oz * Df;
                 }
-                row_range(cs, g, st, on, st.cy + oy, st.cz + oz, gz2, j0, len);
+                const int yy = st.cy + oy, zz = st.cz + oz;
+                row_range(cs, g, st, on, yy, zz, gz2, j0, len);
                 jlast = len > 0 ? j0 + len - 1 : 0;
+                ay = ay0 - (float)(yy - cy0) * Df;
                 k = 0;
                 continue;
             }
             // the slots' records from j0 + k on, the start clamped to the row's last record
             // (the pack appends kUS64 - 1 zero records after the n records)
-            const uint32_t jbo = (uint32_t)min(j0 + k, jlast) * (uint32_t)sizeof(double4);
-            const double4 *Ab = (const double4 *)((const char *)A + jbo);
-            double4 aj[kUS64];
+            const uint32_t jb = (uint32_t)min(j0 + k, jlast);
+            const float4 *Fb = (const float4 *)((const char *)F + jb * (uint32_t)sizeof(float4));
+            float4 aj[kUS64];
 #pragma unroll
-            for (int u = 0; u < kUS64; ++u) aj[u] = Ab[u];
+            for (int u = 0; u < kUS64; ++u) aj[u] = Fb[u];
 #pragma unroll
             for (int u = 0; u < kUS64; ++u) {
                 const int j = j0 + k + u;
-                double yj = GHOST ? 2.0 * yw - aj[u].y : aj[u].y;
-                double dx = aj[u].x - a.x, dy = yj - a.y, dz = aj[u].z - a.z;
-                if (IMG) {
-                    dx = dx - shx;
-                    dy = dy - shy;
-                    dz = dz - shz;
-                }
-                // exact FP64 membership, no contraction
-                double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
-                double H2 = pc.H2;
+                float dx = (aj[u].x + (aj[u].w - cx0) * Df) - ax0;
+                float dy = aj[u].y - ay, dz = aj[u].z - az;
+                if (GHOST) dy = 2.0f * wd - dy;
+                const float r2 = (dx * dx + dy * dy) + dz * dz;
+                float hj = hi32;
                 if (PAIR) {
-                    double H = pc.kappa * (0.5 * (di + ld(dsz, j < jlast ? j : jlast)));
-                    H2 = H * H;
+                    const double H = pc.kappa * (0.5 * (di + ld(dsz, j < jlast ? j : jlast)));
+                    hj = (float)(H * H) * (1.0f + kBand);
                 }
-                // the entry's record offset (32 j for a slot that can be accepted)
-                const uint32_t jo = jbo + (uint32_t)(u * sizeof(double4));
-                const bool acc = (k + u < len) & (GHOST || IMG || jo != self32) & (r2 < H2);
+                // the entry's FP64 record offset (32 j for a slot that can be accepted)
+                const uint32_t jo = (jb + (uint32_t)u) * (uint32_t)sizeof(double4);
+                const bool acc = (k + u < len) & (GHOST || IMG || jo != self32) & (r2 < hj);
                 // the ring slot qw is free: write always, advance on acceptance
                 slot(qw) = jo | tag;
                 qw += acc ? 1 : 0;
@@ -403,6 +422,10 @@ struct Rates64 {
             const double py = (GHOST ? 2.0 * yw - a.y : a.y) + image_shift(pc, nf, m, 1);
             const double pz = a.z + image_shift(pc, nf, m, 2);
             tm = shifted_stencil(g, GHOST ? ti : t, m, px, py, pz);
+            amx = m & 1 ? (float)(px - (g.ox + (double)tm.cx * g.cell)) : a32.x;
+            amy = m & 2 ? (float)(py - (g.oy + (double)tm.cy * g.cell)) : a32.y;
+            amz = m & 4 ? (float)(pz - (g.oz + (double)tm.cz * g.cell)) : a32.z;
+            cxm = (float)tm.cx;
             pass<GHOST, true, ZS, true>();
         }
     }
@@ -412,16 +435,13 @@ struct Rates64 {
     // faces, the stencils around their periodic images); every pop drained.  Returns |N(i)|.
     template <bool LIST, bool ZS>
     __device__ __forceinline__ int run(const int32_t *__restrict__ lst, int len, int64_t nl) {
-        int cnt;
         const bool anyw = WALL && __any(near_wall);
         if (LIST) {
             pass_list<ZS>(lst, len, nl);
-            cnt = cntl;
             while (__any(qr < qw)) drain<WALL, ZS>();
         } else if (anyw || (PER && __any(nf != 0))) {
             pass<false, true, ZS, false>();
             if (PER) images<false, ZS>();
-            cnt = qw;  // real partners accepted (periodic images included)
             if (anyw) {
                 pass<true, true, ZS, false>();
                 if (PER) images<true, ZS>();
@@ -429,10 +449,9 @@ struct Rates64 {
             while (__any(qr < qw)) drain<true, ZS>();
         } else {
             pass<false, false, ZS, false>();
-            cnt = qw;
             while (__any(qr < qw)) drain<false, ZS>();
         }
-        return cnt;
+        return cnt;  // real partners (periodic images included), counted at the pops
     }
 
     // Verlet-list walk: the lane's own list in chunks of kU, exact FP64 membership
@@ -464,20 +483,20 @@ struct Rates64 {
                 const uint32_t eu = (uint32_t)e[u];
                 slot(qw) = WALL ? (eu << 5) | (eu >> 31) : eu << 5;
                 qw += acc ? 1 : 0;
-                cntl += (acc && !ghost) ? 1 : 0;
             }
             k += kU;
         }
     }
 };
 
-// Register-bound: the occupancy hint (5 waves per SIMD) holds the common variants at 96 VGPRs
-// without spills instead of 118 (4 waves); measured 1.6 % faster on the porous shock.  The
-// periodic variants (the image walks' shifts and stencil) would spill at 96: 4 waves.
+// Occupancy hint of 4 waves per SIMD (up to 128 VGPRs): with the FP32 candidate test the
+// kernel would spill at the 96 VGPRs of 5 waves (measured 9.22 against 7.72 ms on the porous
+// shock's first 20 steps).
 template <bool PAIR, bool WALL, bool LIST, bool PER>
-__global__ __launch_bounds__(kRate64Block, PER ? 4 : 5) void k_rates64(int64_t n, const double4 *__restrict__ A,
+__global__ __launch_bounds__(kRate64Block, 4) void k_rates64(int64_t n, const double4 *__restrict__ A,
                                                     const double4 *__restrict__ B,
                                                     const double2 *__restrict__ Cz,
+                                                    const float4 *__restrict__ F,
                                                     const double *__restrict__ rho,
                                                     const double *__restrict__ dsz,
                                                     const int32_t *__restrict__ cs, GridDev g,
@@ -492,6 +511,7 @@ __global__ __launch_bounds__(kRate64Block, PER ? 4 : 5) void k_rates64(int64_t n
     k.A = A;
     k.B = B;
     k.Cz = Cz;
+    k.F = F;
     k.dsz = dsz;
     k.cs = cs;
     k.g = g;
@@ -502,24 +522,30 @@ __global__ __launch_bounds__(kRate64Block, PER ? 4 : 5) void k_rates64(int64_t n
     k.a = make_double4(0.0, 0.0, 0.0, 0.0);
     k.b = k.a;
     k.zc = make_double2(0.0, 0.0);
+    k.a32 = make_float4(0.f, 0.f, 0.f, 0.f);
     k.di = 0.0;
     if (k.live) {
         k.a = A[s];
         k.b = B[s];
         k.zc = Cz[s];
+        if (!LIST) k.a32 = F[s];
         if (PAIR) k.di = dsz[s];
     }
     k.t = make_stencil(g, k.a.x, k.a.y, k.a.z, pc.H);
     k.ti = k.t;
     k.sig = k.zc.y;
+    k.Df = (float)g.cell;
+    k.hi32 = (float)pc.H2 * (1.0f + kBand);
     k.yw = 0.0;
     k.vw2 = 0.0;
+    k.wd = 0.f;
     k.near_wall = false;
     if (WALL) {
         double tt = t_dev ? *t_dev : t_host;
         k.yw = pc.wall_y0 + pc.wall_v * tt;
         k.vw2 = 2.0 * pc.wall_v;
         k.near_wall = k.live && mirror_band(g, k.a.y, k.yw, pc.H);
+        k.wd = (float)(k.yw - k.a.y);
         k.ti = image_stencil(g, k.t, 2.0 * k.yw - k.a.y);
     }
     k.tm = k.t;
@@ -597,11 +623,6 @@ __device__ __forceinline__ void pair32(bool use, float dx, float dy, float dz, f
     sig = fmax_nonneg(sig, use ? sp : 0.0f);
 }
 
-// Candidates whose FP32 squared distance lies within this relative band of
-// the squared support are re-tested in FP64 from the FP64 positions, so the
-// mixed kernel accepts exactly the FP64 neighbour set (the FP32 error of r^2
-// is below 1e-6 relative for offsets within a few cells).
-constexpr float kBand = 4e-5f;
 
 // The exact FP64 membership test of a pair from its FP64 offsets, rounded as written (a
 // product, a product, a sum, a product, a sum): this function lies outside the
@@ -979,8 +1000,8 @@ hipError_t launch_rates(int64_t n, int mixed, const GridDev &g, const PairConst 
         else                                                                                  \
             k_rates64<P, W, L, X><<<nb64, kRate64Block, 0, st>>>(                             \
                 n, (const double4 *)w.recA, (const double4 *)w.recB,                          \
-                (const double2 *)w.recC, rho_sorted, d_sorted, w.cs, g, pc, t_dev, t_host, o, \
-                want_dt, vl);                                                                 \
+                (const double2 *)w.recC, (const float4 *)w.recF, rho_sorted, d_sorted, w.cs,  \
+                g, pc, t_dev, t_host, o, want_dt, vl);                                        \
     }
     CSPH_RATES_CASE(false, false, false, false)
     CSPH_RATES_CASE(false, true, false, false)
