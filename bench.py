@@ -199,9 +199,47 @@ def impact_run(P, torch, ci, steps):
                      "t_end": float(sc.t.item())}
         del state, other, ws
         torch.cuda.empty_cache()
+    out["mixed_graph"] = impact_graph_run(P, torch, w, steps)
     out["mixed_speedup_over_fp64"] = out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"]
     out["note"] = ("drifts of the compensated totals sum(m v), sum(m E) between the states after "
                    "step 1 and the last step, relative to sum(m|v|) and |sum(m E)|")
+    return out
+
+
+def impact_graph_run(P, torch, w, steps, k=10):
+    """The plate impact's mixed steps on a fixed domain mesh (csph_step_mesh: no bounds pass,
+    no host synchronisation), ``k`` steps captured in one graph and replayed steps / k times
+    from the initial state: time per step, and the particles that left the mesh (0: every step
+    was exact)."""
+    params = P.Params.from_workload(w, precision="mixed", reorder=True, cell_size=1.0)
+    mesh = P.domain_mesh((-32.0, -32.0, -32.0), (160.0, 160.0, 96.0), params)
+    ws = P.Workspace("cuda")
+    warm = P.state_from_workload(w, params, "cuda", with_id=False)
+    P.csph_step_mesh(warm, params, P.StepScalars("cuda"), mesh, s_out=warm.like(), ws=ws)
+    del warm
+    a = P.state_from_workload(w, params, "cuda", with_id=False)
+    b = a.like()
+    sc = P.StepScalars("cuda")
+    outside = torch.zeros(1, dtype=torch.int64, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        for i in range(k):
+            src, dst = (a, b) if i % 2 == 0 else (b, a)
+            P.csph_step_mesh(src, params, sc, mesh, s_out=dst, outside=outside, ws=ws)
+    with collector_off():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps // k):
+            graph.replay()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    out = {"ms_per_step": 1e3 * el / (steps // k * k), "steps_per_graph": k,
+           "mesh": {"origin": list(mesh.origin), "dims": list(mesh.dims), "cell": mesh.cell},
+           "outside_after_run": int(outside.item()), "t_end": float(sc.t.item())}
+    del graph, a, b, ws
+    torch.cuda.empty_cache()
     return out
 
 
@@ -350,6 +388,55 @@ def verlet_timing(P, torch, w, cell, steps, beta=0.3, n_upd=10):
            "kernel_ms": {g: round(v[1] / max(v[0], 1), 4) for g, v in prof.items() if v[0] > 0},
            "note": "rebuild (bin + renumber + list build) counted in 'neighbors' and 'bin'"}
     del run, state
+    torch.cuda.empty_cache()
+    return out
+
+
+def verlet_vs_search(P, torch, w, steps, beta=0.3, n_upd=10):
+    """Verlet-list steps against the per-step search on one workload (mixed precision, both
+    from the initial state after 3 warm-up steps on a throwaway copy): a list step needs no
+    mesh, no binning and no host synchronisation, so it pays where particles move little per
+    step and launches and the mesh synchronisation weigh on the per-step search."""
+    params = P.Params.from_workload(w, precision="mixed", reorder=True)
+    out = {"workload": w.name, "particles": w.n, "steps": steps, "beta": beta, "n_upd": n_upd,
+           "cfl": w.cfl}
+    ws = P.Workspace("cuda")
+    for warm in (True, False):
+        state = P.state_from_workload(w, params, "cuda", with_id=True)
+        other = state.like()
+        sc = P.StepScalars("cuda")
+        cnt = torch.empty(w.n, dtype=torch.int32, device="cuda")
+        k = 3 if warm else steps
+        with collector_off():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(k):
+                o = P.csph_step(state, params, sc, s_out=other, nbr_count=cnt, ws=ws)
+                state, other = o, state
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+    out["search_ms_per_step"] = 1e3 * el / steps
+    x_search = state["x"][torch.argsort(state.id)].clone()
+    del state, other
+    for warm in (True, False):
+        state = P.state_from_workload(w, params, "cuda", with_id=True)
+        sc = P.StepScalars("cuda")
+        run = P.VerletRun(state, params, beta=beta, n_upd=n_upd, ws=ws)
+        k = 3 if warm else steps
+        with collector_off():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run.advance(sc, k)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+    out["verlet_ms_per_step"] = 1e3 * el / steps
+    out["rebuilds"] = run.builds
+    out["verlet_over_search"] = out["verlet_ms_per_step"] / out["search_ms_per_step"]
+    # the same steps through both paths (mixed precision: the two walks round their FP32
+    # offsets differently, so the positions agree to the FP32 rate tolerance, not bitwise)
+    st = run.state
+    out["max_abs_x_difference"] = float((st["x"][torch.argsort(st.id)] - x_search).abs().max())
+    del run, state, ws
     torch.cuda.empty_cache()
     return out
 
@@ -694,7 +781,8 @@ def main():
         log("plate impact, both precisions ...")
         line["impact"] = impact_run(P, torch, ci, 200)
         log(f"impact mixed {line['impact']['mixed']['ms_per_step']:.3f} ms/step, "
-            f"fp64 {line['impact']['fp64']['ms_per_step']:.3f} ms/step")
+            f"fp64 {line['impact']['fp64']['ms_per_step']:.3f} ms/step, mixed on a fixed mesh "
+            f"in graphs {line['impact']['mixed_graph']['ms_per_step']:.3f} ms/step")
         log("Mie-Grueneisen plates, pair-averaged support, both precisions ...")
         line["paper_mode"] = paper_mode_run(P, torch, ci, 20)
         log(f"paper mode mixed {line['paper_mode']['mixed']['ms_per_step']:.3f} ms/step, "
@@ -712,6 +800,11 @@ def main():
         line["verlet"] = verlet_timing(P, torch, w, args.cell, args.verlet_steps)
         log(f"verlet: {line['verlet']['ms_per_step']:.3f} ms/step, "
             f"{line['verlet']['rebuilds']} rebuilds in {args.verlet_steps} steps")
+        log("Verlet-list steps against the per-step search, Sod 64^3 ...")
+        line["verlet_sod64"] = verlet_vs_search(P, torch, ci.config3(), 100)
+        log(f"sod64: search {line['verlet_sod64']['search_ms_per_step']:.3f} ms/step, lists "
+            f"{line['verlet_sod64']['verlet_ms_per_step']:.3f} ms/step, "
+            f"{line['verlet_sod64']['rebuilds']} rebuilds")
     if args.adjoint:
         log("adjoint rollout ...")
         line["adjoint"] = adjoint_ratio(P, torch, ci)

@@ -311,6 +311,27 @@ csph_status csph_step_static(const csph_state *s_in, csph_state *s_out, const cs
                              double *t, double dt_in, double *dt_used, double *totals,
                              int32_t *nbr_count, int64_t *nonphys, csph_stream stream);
 
+/* csph_step on a mesh the caller gives, for callers that step many times over a known domain
+ * and for graph capture (sec. 4.2's cells fixed over the domain instead of re-sized to the
+ * particles each step): no bounds pass and no host synchronisation, so every kernel is
+ * enqueued on `stream` and a caller may capture a sequence of these steps in a HIP graph and
+ * replay it.  mesh (host): a csph_grid from csph_grid_build over points spanning the domain
+ * (origin, cell, dims, reach in the caller's axes; its key_mode is not used); reach * cell
+ * must cover the support (fixed-h mode only).  The results are those of csph_step while every
+ * position lies on the mesh (and, along periodic axes, in the box): the binning counts the
+ * particles that do not into *outside (device int64, optional, accumulated over calls, as
+ * *nonphys); cells are clamped to the mesh, so nothing is read out of bounds for them, but
+ * their partners may be missed.  With the piston the band of particles with mirror partners
+ * is found on the device.  RK2 steps bin their second stage on the same mesh.
+ * CSPH_EINVAL for pair-h mode, check_nonphys = 1 (it would synchronise) or a mesh whose reach
+ * does not cover the support; otherwise as csph_step.  Capturing: size the workspace first
+ * (an eager call), since a short one returns CSPH_ECAPACITY. */
+csph_status csph_step_mesh(const csph_state *s_in, csph_state *s_out, const csph_params *p,
+                           const csph_grid *mesh, double *t, double dt_in, double *dt_used,
+                           double *totals, int32_t *nbr_count, int64_t *nonphys,
+                           int64_t *outside, void *ws, size_t ws_bytes, size_t *ws_needed,
+                           csph_stream stream);
+
 /* Voronoi ownership (eq. VoronoiDefinition): owner[i] = the k minimising
  * ((x_i-g_kx)^2 + (y_i-g_ky)^2) + (z_i-g_kz)^2 in FP64 without contraction,
  * a tie going to the smaller k (sec. 3.1).  sites: K x 3 FP64, global

@@ -10,5 +10,5 @@ from .api import (EOS_IDEAL, EOS_STIFFENED, EOS_MIE_GRUNEISEN, Params, State, St
                   zeros_grad, GRAD_FIELDS, BalanceParams, csph_balance_stats,
                   csph_balance_move, adjacency_matrix, csph_vlist_build, csph_step_vlist,
                   VerletRun, csph_step_static, csph_step_voronoi, vlist_ctl,
-                  vlist_ctl_read)
+                  vlist_ctl_read, csph_step_mesh, domain_mesh)
 from .autograd import CSPHRollout, rollout  # noqa: F401

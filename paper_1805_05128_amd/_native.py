@@ -135,6 +135,10 @@ def load():
     L.csph_step_static.argtypes = [C.POINTER(CsphState), C.POINTER(CsphState),
                                    C.POINTER(CsphParams), _dp, C.c_double, _dp, _dp, _ip, _lp,
                                    vp]
+    L.csph_step_mesh.restype = C.c_int32
+    L.csph_step_mesh.argtypes = [C.POINTER(CsphState), C.POINTER(CsphState),
+                                 C.POINTER(CsphParams), C.POINTER(CsphGrid), _dp, C.c_double,
+                                 _dp, _dp, _ip, _lp, _lp, vp, sz, szp, vp]
     L.voronoi_assign.restype = C.c_int32
     L.voronoi_assign.argtypes = [_dp, _dp, _dp, C.c_int64, _dp, C.c_int32, _ip, _ip, _lp, _lp,
                                  vp]

@@ -375,6 +375,37 @@ def csph_step_static(s_in: State, params: Params, sc: StepScalars, s_out: State,
     return s_out
 
 
+def domain_mesh(lo, hi, params: Params, device="cuda", ws: Optional[Workspace] = None,
+                stream=None) -> N.CsphGrid:
+    """The mesh csph_grid_build makes for the box [lo, hi] (its two corners as the points), for
+    csph_step_mesh: cells of params.cell_size (or the support), covering the box."""
+    pts = torch.tensor([lo, hi], dtype=torch.float64, device=device)
+    return csph_grid_build(pts[:, 0].contiguous(), pts[:, 1].contiguous(),
+                           pts[:, 2].contiguous(), params, ws=ws, stream=stream)
+
+
+def csph_step_mesh(s_in: State, params: Params, sc: StepScalars, mesh: N.CsphGrid,
+                   s_out: Optional[State] = None, dt_in: float = 0.0,
+                   nbr_count: Optional[torch.Tensor] = None,
+                   outside: Optional[torch.Tensor] = None, ws: Optional[Workspace] = None,
+                   stream=None, totals: bool = True) -> State:
+    """csph_step on the caller's mesh (e.g. domain_mesh): no host synchronisation, so a
+    sequence of these calls can be captured in a graph (size ``ws`` with an eager call first).
+    ``outside`` (int64 [1], device, accumulated) counts the particles off the mesh."""
+    L = N.load()
+    ws = ws or default_workspace(s_in["x"].device)
+    if s_out is None:
+        s_out = s_in.like() if params.reorder else s_in
+    a, b_ = s_in.c(), s_out.c()
+    p = params.c()
+    _with_ws(lambda w, nb, nd: L.csph_step_mesh(C.byref(a), C.byref(b_), C.byref(p),
+                                                C.byref(mesh), _dp(sc.t), float(dt_in),
+                                                _dp(sc.dt), _dp(sc.totals) if totals else None,
+                                                _ip(nbr_count), _lp(sc.nonphys), _lp(outside), w,
+                                                nb, nd, _stream(stream)), ws, "csph_step_mesh")
+    return s_out
+
+
 def voronoi_assign(x, y, z, sites: torch.Tensor, nbr_count: Optional[torch.Tensor] = None,
                    owner: Optional[torch.Tensor] = None, stream=None,
                    site_particles: Optional[torch.Tensor] = None,

@@ -99,6 +99,7 @@ size_t ws_layout(Ws *w, void *base, int64_t n, int64_t ncell, bool rk2, int64_t 
     t.dtmin = (unsigned long long *)take(2 * sizeof(unsigned long long));
     t.zflag = t.dtmin ? t.dtmin + 1 : nullptr;
     t.nonphys = (int64_t *)take(sizeof(int64_t));
+    t.yenc = (unsigned long long *)take(sizeof(unsigned long long));
     t.tot_part = (double *)take(sizeof(double) * 10 * kReduceBlocks);
     int64_t scan_len = (n > ncell ? n : ncell) + 1;
     t.scan_tmp = (int64_t *)take(sizeof(int64_t) * (size_t)((scan_len + kScanTile - 1) / kScanTile + 1));
@@ -324,6 +325,7 @@ static GridDev grid_dev(const csph_grid &g, bool slab = true, double ymin = 0.0)
     }
     d.morton = 0;
     d.nkey = (int64_t)d.dx * d.dy * d.dz;
+    d.yenc = nullptr;
     return d;
 }
 
@@ -411,6 +413,25 @@ static csph_status need_ws(size_t have, int64_t n, int64_t ncell, size_t *ws_nee
     return CSPH_OK;
 }
 
+// A mesh the caller gives for a step (csph_step_mesh): a positive cell, consistent dims and
+// cell count, and a stencil reach covering the support H.
+static csph_status check_mesh(const csph_grid *m, double H) {
+    if (!m) return fail(CSPH_EINVAL, "mesh is NULL");
+    if (!(m->cell > 0.0) || !std::isfinite(m->cell) || m->inv_cell != 1.0 / m->cell)
+        return fail(CSPH_EINVAL, "mesh: need cell > 0 and inv_cell = 1/cell");
+    int64_t nc = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (m->dims[a] < 1 || !std::isfinite(m->origin[a]))
+            return fail(CSPH_EINVAL, "mesh: dims must be >= 1 and the origin finite");
+        nc *= m->dims[a];
+        if (nc > 2000000000LL) return fail(CSPH_EINVAL, "mesh has more than 2e9 cells");
+    }
+    if (nc != m->ncell) return fail(CSPH_EINVAL, "mesh: ncell does not match dims");
+    if (m->reach < 1 || m->reach > 64 || (double)m->reach * m->cell < H)
+        return fail(CSPH_EINVAL, "mesh: reach * cell must cover the support (reach <= 64)");
+    return CSPH_OK;
+}
+
 // The call's own non-physical count (counted into the workspace counter): added to the
 // caller's counter, brought to the host (synchronises), CSPH_ENONPHYS when not 0.
 static csph_status finish_nonphys(const Ws &w, int64_t *nonphys, hipStream_t st) {
@@ -466,7 +487,8 @@ static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const cs
                              double *t, double dt_in, double *dt_used, double *totals,
                              int32_t *nbr_count, int64_t *nonphys, void *ws, size_t ws_bytes,
                              size_t *ws_needed, hipStream_t st, bool prof,
-                             const VoroArgs *va = nullptr);
+                             const VoroArgs *va = nullptr, const csph_grid *mesh = nullptr,
+                             int64_t *outside = nullptr);
 
 }  // namespace csph
 
@@ -686,6 +708,17 @@ csph_status csph_step_static(const csph_state *s_in, csph_state *s_out, const cs
     return r;
 }
 
+csph_status csph_step_mesh(const csph_state *s_in, csph_state *s_out, const csph_params *p,
+                           const csph_grid *mesh, double *t, double dt_in, double *dt_used,
+                           double *totals, int32_t *nbr_count, int64_t *nonphys,
+                           int64_t *outside, void *ws, size_t ws_bytes, size_t *ws_needed,
+                           csph_stream stream) {
+    g_err[0] = 0;
+    if (!mesh) return fail(CSPH_EINVAL, "mesh is NULL");
+    return step_impl(s_in, s_out, p, t, dt_in, dt_used, totals, nbr_count, nonphys, ws,
+                     ws_bytes, ws_needed, (hipStream_t)stream, true, nullptr, mesh, outside);
+}
+
 }  // extern "C"
 
 namespace csph {
@@ -693,7 +726,8 @@ namespace csph {
 static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const csph_params *p,
                              double *t, double dt_in, double *dt_used, double *totals,
                              int32_t *nbr_count, int64_t *nonphys, void *ws, size_t ws_bytes,
-                             size_t *ws_needed, hipStream_t st, bool prof, const VoroArgs *va) {
+                             size_t *ws_needed, hipStream_t st, bool prof, const VoroArgs *va,
+                             const csph_grid *mesh, int64_t *outside) {
     if (!state_ok(s_in) || !state_ok(s_out) || s_in->n != s_out->n || s_in->n >= INT32_MAX)
         return fail(CSPH_EINVAL, "bad state");
     if (s_in->n >= kMaxPairN) return fail(CSPH_EINVAL, "n >= 2^27 particles");
@@ -702,6 +736,14 @@ static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const cs
     if (!(p->cfl > 0.0) && !(std::isfinite(dt_in) && dt_in >= 0.0))
         return fail(CSPH_EINVAL, "cfl <= 0 needs a finite dt_in >= 0");
     if (p->wall && !t) return fail(CSPH_EINVAL, "the wall position needs t");
+    if (mesh) {
+        if (p->h_mode != CSPH_H_FIXED)
+            return fail(CSPH_EINVAL, "a step on a given mesh takes fixed-h mode");
+        if (p->check_nonphys)
+            return fail(CSPH_EINVAL, "a step on a given mesh does not wait: check_nonphys must be 0");
+        r = check_mesh(mesh, p->kappa * p->h);
+        if (r) return r;
+    }
     const bool rk2 = p->integrator == CSPH_INT_RK2;
     if (rk2 && va) return fail(CSPH_EINVAL, "csph_step_voronoi takes the Euler step only");
     if ((s_in->mat && !s_out->mat) || (s_in->id && !s_out->id) ||
@@ -714,15 +756,36 @@ static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const cs
     int64_t n = s_in->n;
     const csph_state vin = kernel_view(*s_in, p->wall), vout = kernel_view(*s_out, p->wall);
     csph_grid g;
-    double dmax, ymin;
-    r = make_grid(vin.x, vin.y, vin.z, vin.d, n, p, ws, ws_bytes, st, &g, &dmax, &ymin, true);
-    if (r) return r;
+    double dmax = 0.0, ymin = 0.0;
+    if (mesh) {  // the caller's mesh, in the kernels' axes
+        g = *mesh;
+        if (p->wall) {
+            std::swap(g.origin[0], g.origin[1]);
+            std::swap(g.dims[0], g.dims[1]);
+        }
+    } else {
+        r = make_grid(vin.x, vin.y, vin.z, vin.d, n, p, ws, ws_bytes, st, &g, &dmax, &ymin, true);
+        if (r) return r;
+    }
     r = need_ws(ws_bytes, n, g.ncell, ws_needed, rk2);
     if (r) return r;
     Ws w;
     ws_layout(&w, ws, n, g.ncell, rk2);
     GridDev gd = grid_dev(g, true, ymin);
+    // on a given mesh the binning finds the wall band's minimum y on the device and counts the
+    // particles off the mesh (or outside a periodic box)
+    BinCheck chk{nullptr, nullptr, 0, {0, 0, 0}, {0, 0, 0}};
+    if (mesh) {
+        if (p->wall) chk.yenc = w.yenc;
+        chk.outside = (unsigned long long *)outside;
+        gd.yenc = chk.yenc;
+    }
     PairConst pc = pair_const(p, dmax);
+    chk.per = mesh ? pc.per : 0;
+    for (int a = 0; a < 3; ++a) {
+        chk.lo[a] = pc.lo[a];
+        chk.hi[a] = pc.hi[a];
+    }
     EosDev eos = eos_dev(p);
     int mixed = p->precision == CSPH_MIXED;
     bool pair = p->h_mode == CSPH_H_PAIR;
@@ -751,7 +814,9 @@ static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const cs
     if (n > 0) {
         {
             ProfScope pr(CSPH_PROF_BIN, st, prof);
-            CSPH_HIP(launch_bin(vin.x, vin.y, vin.z, n, gd, w, w.perm, nullptr, w.cs, st));
+            if (chk.yenc) CSPH_HIP(launch_fill_u64(chk.yenc, ~0ull, 1, st));
+            CSPH_HIP(launch_bin(vin.x, vin.y, vin.z, n, gd, w, w.perm, nullptr, w.cs, st,
+                                mesh ? &chk : nullptr));
         }
         ProfScope pr(CSPH_PROF_PACK, st, prof);
         CSPH_HIP(launch_pack(vin, n, w.perm, eos, mixed, gd, w, dst, dmat, dd, did, vin.id,
@@ -770,11 +835,13 @@ static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const cs
         cnt_out = w.rk_cnt;
         // second evaluation, at U1: its own mesh, order and records
         double *d1 = pair ? dd : nullptr;
-        csph_grid g2;
-        double dmax2, ymin2;
-        r = make_grid(w.stg[0], w.stg[1], w.stg[2], d1, n, p, ws, ws_bytes, st, &g2, &dmax2,
-                      &ymin2, true);
-        if (r) return r;
+        csph_grid g2 = g;  // on a given mesh, the same mesh (no synchronisation)
+        double dmax2 = dmax, ymin2 = ymin;
+        if (!mesh) {
+            r = make_grid(w.stg[0], w.stg[1], w.stg[2], d1, n, p, ws, ws_bytes, st, &g2, &dmax2,
+                          &ymin2, true);
+            if (r) return r;
+        }
         r = need_ws(ws_bytes, n, g.ncell, ws_needed, true, g2.ncell);
         if (r) return r;
         ws_layout(&w, ws, n, g.ncell, true, g2.ncell);
@@ -782,12 +849,17 @@ static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const cs
         w2.cs = w.cs2;
         w2.scan_tmp = w.scan_tmp2;
         GridDev gd2 = grid_dev(g2, true, ymin2);
+        gd2.yenc = gd.yenc;  // found again from U1 by the second binning
+        BinCheck chk2 = chk;
+        chk2.outside = nullptr;  // counted at U only
         PairConst pc2 = pair_const(p, dmax2);
         csph_state u1{n,       w.stg[0], w.stg[1], w.stg[2], w.stg[3], w.stg[4], w.stg[5],
                       w.stg[6], w.stg[7], dst[8],   dmat,     d1,       nullptr};
         {
             ProfScope pr(CSPH_PROF_BIN, st, prof);
-            CSPH_HIP(launch_bin(u1.x, u1.y, u1.z, n, gd2, w2, w.perm2, nullptr, w.cs2, st));
+            if (chk2.yenc) CSPH_HIP(launch_fill_u64(chk2.yenc, ~0ull, 1, st));
+            CSPH_HIP(launch_bin(u1.x, u1.y, u1.z, n, gd2, w2, w.perm2, nullptr, w.cs2, st,
+                                mesh ? &chk2 : nullptr));
         }
         {
             ProfScope pr(CSPH_PROF_PACK, st, prof);

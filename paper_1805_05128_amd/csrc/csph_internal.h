@@ -37,6 +37,30 @@ struct GridDev {
     double ymin;                // minimum y of the particles (the origin may lie below it)
     int morton;                 // binning keys: 1 = Morton (csph_bin's export only)
     int64_t nkey;               // key space of the binning (cells, or 2^(3 bits) for Morton)
+    // the minimum y found on the device by the binning (order_enc), for steps on a mesh the
+    // caller gives; null: ymin
+    const unsigned long long *yenc;
+};
+
+// A double as an unsigned integer of the same order (the sign bit set for v >= 0, every bit
+// flipped for v < 0), so that integer atomics take minima of doubles.
+__device__ __forceinline__ unsigned long long order_enc(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double order_dec(unsigned long long e) {
+    const unsigned long long b = (e >> 63) ? (e & 0x7fffffffffffffffull) : ~e;
+    return __longlong_as_double((long long)b);
+}
+
+// Checks the binning makes for a step on a mesh the caller gives (no bounds pass): the minimum
+// y (yenc, reset to ~0 before), and the count of particles outside the mesh or, along a
+// periodic axis (per, in the kernels' axes), outside the box [lo, hi].  Null pointers skip.
+struct BinCheck {
+    unsigned long long *yenc;
+    unsigned long long *outside;
+    int per;
+    double lo[3], hi[3];
 };
 
 // Morton key: bit b of cx, cy, cz at key bits 3b, 3b+1, 3b+2 (10 bits each).  Each
@@ -208,6 +232,7 @@ struct Ws {
     unsigned long long *dtmin;    // bits of min_i h_i/s_i
     unsigned long long *zflag;    // 0 once the pack meets a zero impedance Z = rho c
     int64_t *nonphys;             // scratch counter
+    unsigned long long *yenc;     // steps on a caller's mesh: the particles' minimum y (order_enc)
     double *tot_part;             // kReduceBlocks * 10
     // two-stage Runge-Kutta steps only (ws_layout with rk2): the predicted state U1 in the
     // first stage's cell order (x, y, z wrapped into a periodic box; vx vy vz rho E), the
@@ -235,7 +260,7 @@ hipError_t launch_bounds(const double *x, const double *y, const double *z, cons
                          int64_t n, double *part, double *out, hipStream_t st);
 hipError_t launch_bin(const double *x, const double *y, const double *z, int64_t n,
                       const GridDev &g, const Ws &w, int32_t *perm, uint32_t *key_out,
-                      int32_t *cell_start, hipStream_t st);
+                      int32_t *cell_start, hipStream_t st, const BinCheck *chk = nullptr);
 template <typename TI, typename TO>
 hipError_t launch_scan_exclusive(const TI *in, TO *out, int64_t len, int64_t *tmp, hipStream_t st);
 

@@ -221,22 +221,53 @@ __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *p, int32_t v, int6
         p[i] = v;
 }
 
+// Whether coordinate v lies on the mesh axis (origin o, 1/D inv, dim cells), in the cell
+// arithmetic of cell_coord.
+__device__ __forceinline__ bool on_axis(double v, double o, double inv, int dim) {
+    const double f = floor((v - o) * inv);
+    return f >= 0.0 && f < (double)dim;
+}
+
 __global__ __launch_bounds__(kBlock) void k_keys(const double *__restrict__ x,
                                                  const double *__restrict__ y,
                                                  const double *__restrict__ z, int64_t n,
                                                  GridDev g, uint32_t *__restrict__ key,
                                                  uint32_t *__restrict__ rank,
                                                  int32_t *__restrict__ count,
-                                                 uint32_t *__restrict__ key_out) {
+                                                 uint32_t *__restrict__ key_out, BinCheck chk) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    int cx = cell_coord(x[i], g.ox, g.inv, g.dx);
-    int cy = cell_coord(y[i], g.oy, g.inv, g.dy);
-    int cz = cell_coord(z[i], g.oz, g.inv, g.dz);
-    uint32_t k = g.morton ? morton_key(cx, cy, cz) : cell_key(g, cx, cy, cz);
-    key[i] = k;
-    rank[i] = (uint32_t)atomicAdd(&count[k], 1);
-    if (key_out) key_out[i] = k;
+    const bool live = i < n;
+    double xi = 0.0, yi = 0.0, zi = 0.0;
+    if (live) {
+        xi = x[i];
+        yi = y[i];
+        zi = z[i];
+        int cx = cell_coord(xi, g.ox, g.inv, g.dx);
+        int cy = cell_coord(yi, g.oy, g.inv, g.dy);
+        int cz = cell_coord(zi, g.oz, g.inv, g.dz);
+        uint32_t k = g.morton ? morton_key(cx, cy, cz) : cell_key(g, cx, cy, cz);
+        key[i] = k;
+        rank[i] = (uint32_t)atomicAdd(&count[k], 1);
+        if (key_out) key_out[i] = k;
+    }
+    if (chk.yenc) {  // the wave's minimum y, one atomic per wave
+        unsigned long long e = live ? order_enc(yi) : ~0ull;
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long f = __shfl_xor(e, o, 64);
+            e = f < e ? f : e;
+        }
+        if ((threadIdx.x & 63) == 0 && e != ~0ull) atomicMin(chk.yenc, e);
+    }
+    if (chk.outside) {
+        bool out = live && !(on_axis(xi, g.ox, g.inv, g.dx) && on_axis(yi, g.oy, g.inv, g.dy) &&
+                             on_axis(zi, g.oz, g.inv, g.dz));
+        const double p[3] = {xi, yi, zi};
+        for (int a = 0; a < 3; ++a)
+            if (live && ((chk.per >> a) & 1) && !(p[a] >= chk.lo[a] && p[a] <= chk.hi[a]))
+                out = true;
+        const unsigned long long c = __popcll(__ballot(out));
+        if ((threadIdx.x & 63) == 0 && c) atomicAdd(chk.outside, c);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__ key,
@@ -270,13 +301,14 @@ static unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBl
 
 hipError_t launch_bin(const double *x, const double *y, const double *z, int64_t n,
                       const GridDev &g, const Ws &w, int32_t *perm, uint32_t *key_out,
-                      int32_t *cell_start, hipStream_t st) {
+                      int32_t *cell_start, hipStream_t st, const BinCheck *chk) {
+    const BinCheck c = chk ? *chk : BinCheck{nullptr, nullptr, 0, {0, 0, 0}, {0, 0, 0}};
     const int64_t ncell = g.nkey;  // keys (cells, or the Morton key space)
     unsigned fb = blocks_for(ncell + 1);
     k_fill_i32<<<fb > 65535u ? 65535u : fb, kBlock, 0, st>>>(cell_start, 0, ncell + 1);
     if (n > 0)
         k_keys<<<blocks_for(n), kBlock, 0, st>>>(x, y, z, n, g, w.key, w.rank, cell_start,
-                                                 key_out);
+                                                 key_out, c);
     hipError_t e = launch_scan_exclusive<int32_t, int32_t>(cell_start, cell_start, ncell,
                                                            w.scan_tmp, st);
     if (e != hipSuccess) return e;

@@ -127,7 +127,8 @@ __device__ __forceinline__ Stencil shifted_stencil(const GridDev &g, Stencil s, 
 // particle's image 2 yw - y_j lies within H of it.  The images lie at or below
 // yw + (yw - min_j y_j), so particles behind the wall widen the band in front of it.
 __device__ __forceinline__ bool mirror_band(const GridDev &g, double y, double yw, double H) {
-    return y - yw < H + fmax(yw - g.ymin, 0.0);
+    const double ymin = g.yenc ? order_dec(*g.yenc) : g.ymin;
+    return y - yw < H + fmax(yw - ymin, 0.0);
 }
 
 // Distance in cell units from coordinate c to the slab [k, k+1) (0 inside),

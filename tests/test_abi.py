@@ -235,3 +235,31 @@ def test_integrator_checked_on_the_host():
     assert st == N.CSPH_EINVAL and b"Euler" in L.csph_last_error()
     assert P.workspace_size(1000, 100, P.Params(integrator="rk2")) > \
         P.workspace_size(1000, 100, P.Params()) + 1000 * 150
+
+
+def test_step_mesh_checked_on_the_host():
+    """csph_step_mesh refuses, before any device work: no mesh, pair-h mode, check_nonphys
+    (it would wait), and a mesh whose reach does not cover the support."""
+    L = N.load()
+    a, b = _fake_state(4096), _fake_state(65536)
+    g = N.CsphGrid()
+    g.cell, g.inv_cell = 1.0, 1.0
+    g.dims[0] = g.dims[1] = g.dims[2] = 4
+    g.ncell, g.reach = 64, 3
+    call = lambda p, mesh: L.csph_step_mesh(C.byref(a), C.byref(b), C.byref(p), mesh, None,
+                                            0.1, None, None, None, None, None, None, 0, None,
+                                            None)
+    assert call(P.Params(cfl=0.0).c(), None) == N.CSPH_EINVAL
+    assert b"mesh" in L.csph_last_error()
+    a.d = b.d = C.cast(C.c_void_p(1 << 26), C.POINTER(C.c_double))  # pair-h mode needs d
+    assert call(P.Params(cfl=0.0, h_mode="pair").c(), C.byref(g)) == N.CSPH_EINVAL
+    assert b"fixed-h" in L.csph_last_error()
+    a.d = b.d = None
+    assert call(P.Params(cfl=0.0, check_nonphys=True).c(), C.byref(g)) == N.CSPH_EINVAL
+    assert b"check_nonphys" in L.csph_last_error()
+    g.reach = 2
+    assert call(P.Params(cfl=0.0).c(), C.byref(g)) == N.CSPH_EINVAL
+    assert b"reach" in L.csph_last_error()
+    g.reach, g.ncell = 3, 65
+    assert call(P.Params(cfl=0.0).c(), C.byref(g)) == N.CSPH_EINVAL
+    assert b"ncell" in L.csph_last_error()
