@@ -199,12 +199,34 @@ static csph_status check_params(const csph_params *p, bool need_pair_d, const do
     return CSPH_OK;
 }
 
+// The caller's axis each of the kernels' axes takes (k[a] for kernel axis a).  The kernels walk
+// stencil rows along their x axis and cut the cell order into slabs along y, so a boundary
+// normal to their x axis puts particles within its support at both ends of every row, in a few
+// lanes of most waves.  With a piston the wall normal (the caller's x) is handed over as y, so
+// that the particles with mirror partners fill a few waves; without one a periodic x is handed
+// over as y when y is open, so that the waves with periodic image walks are the few at the
+// slab faces.  Only x and y are ever exchanged: the exact decisions sum squared offsets as
+// ((x x) + (y y)) + (z z), whose rounding an exchange of the first two terms leaves unchanged.
+struct Axes {
+    int k[3];
+};
+
+static Axes kernel_axes(const csph_params *p) {
+    if (p->wall || ((p->periodic & 1) && !(p->periodic & 2))) return Axes{{1, 0, 2}};
+    return Axes{{0, 1, 2}};
+}
+
+// the kernels' axis that takes the caller's axis a
+static int kernel_axis_of(const Axes &ax, int a) {
+    return ax.k[0] == a ? 0 : ax.k[1] == a ? 1 : 2;
+}
+
 // Near-face band of the periodic image search: the support with a relative margin (a pair's
 // FP64 offset carries a few ulp of the period).
 static double periodic_band(double H) { return H * (1.0 + 1e-6); }
 
 // Periodic boxes against the particle bounds (b: min x, y, z, max x, y, z in the kernels'
-// axes, which swap x and y when there is a wall) and the maximum support: each period must
+// axes, kernel_axes) and the maximum support: each period must
 // exceed twice the near-face band (so a particle has images across one face per axis at most,
 // and no pair of particles more than one image of each other) and the positions must lie in
 // the box.
@@ -213,7 +235,7 @@ static csph_status check_box(const csph_params *p, const double b[6], double Hma
     const double hb = periodic_band(Hmax);
     for (int a = 0; a < 3; ++a) {
         if (!((p->periodic >> a) & 1)) continue;
-        const int k = p->wall && a < 2 ? 1 - a : a;  // the kernels' axis of the caller's axis a
+        const int k = kernel_axis_of(kernel_axes(p), a);
         const double L = p->box_hi[a] - p->box_lo[a];
         if (!(L > 2.0 * hb))
             return fail(CSPH_EINVAL, "period %g of axis %d must exceed twice the support %g (1 + 1e-6)",
@@ -258,12 +280,13 @@ static PairConst pair_const(const csph_params *p, double dmax) {
     c.dwc = (210.0 / M_PI) * (i2 * i2);
     c.h_dt = p->h;
     c.wall = p->wall != 0;
-    c.wall_y0 = p->wall_x0;  // the kernels see x and y swapped when there is a wall
+    c.wall_y0 = p->wall_x0;  // the wall normal is the kernels' y axis (kernel_axes)
     c.wall_v = p->wall_v;
     c.per = 0;
     c.hb = periodic_band(H);
+    const Axes ax = kernel_axes(p);
     for (int a = 0; a < 3; ++a) {
-        const int k = p->wall && a < 2 ? 1 - a : a;
+        const int k = kernel_axis_of(ax, a);
         if ((p->periodic >> a) & 1) {
             c.per |= 1 << k;
             c.lo[k] = p->box_lo[a];
@@ -274,21 +297,26 @@ static PairConst pair_const(const csph_params *p, double dmax) {
     return c;
 }
 
-// The arrays the kernels see.  With a piston wall (a plane normal to x) the x
-// and y arrays are handed over swapped, so that the wall normal runs along the
-// slab axis of the cell order (PairConst); without one they are the caller's.
-static csph_state kernel_view(const csph_state &s, bool wall) {
+// The arrays the kernels see: the caller's position, velocity and rate arrays in the kernels'
+// axes (kernel_axes).
+static csph_state kernel_view(const csph_state &s, const Axes &ax) {
     csph_state v = s;
-    if (wall) {
-        std::swap(v.x, v.y);
-        std::swap(v.vx, v.vy);
-    }
+    double *const pos[3] = {s.x, s.y, s.z}, *const vel[3] = {s.vx, s.vy, s.vz};
+    v.x = pos[ax.k[0]];
+    v.y = pos[ax.k[1]];
+    v.z = pos[ax.k[2]];
+    v.vx = vel[ax.k[0]];
+    v.vy = vel[ax.k[1]];
+    v.vz = vel[ax.k[2]];
     return v;
 }
 
-static csph_rates_out kernel_view(const csph_rates_out &o, bool wall) {
+static csph_rates_out kernel_view(const csph_rates_out &o, const Axes &ax) {
     csph_rates_out v = o;
-    if (wall) std::swap(v.dvx, v.dvy);
+    double *const dv[3] = {o.dvx, o.dvy, o.dvz};
+    v.dvx = dv[ax.k[0]];
+    v.dvy = dv[ax.k[1]];
+    v.dvz = dv[ax.k[2]];
     return v;
 }
 
@@ -576,10 +604,12 @@ csph_status csph_neighbors(const csph_state *s, const csph_params *p, int64_t *o
     int64_t n = s->n;
     csph_grid g;
     double dmax, ymin;
-    csph_params pn0 = *p;  // N(i) has no mirror partners: the caller's axes, no wall
+    csph_params pn0 = *p;  // N(i) has no mirror partners: no wall
     pn0.wall = 0;
     p = &pn0;
-    r = make_grid(s->x, s->y, s->z, s->d, n, p, ws, ws_bytes, st, &g, &dmax, &ymin, true);
+    // positions in the kernels' axes (N(i) does not depend on them)
+    const csph_state sv = kernel_view(*s, kernel_axes(p));
+    r = make_grid(sv.x, sv.y, sv.z, s->d, n, p, ws, ws_bytes, st, &g, &dmax, &ymin, true);
     if (r) return r;
     r = need_ws(ws_bytes, n, g.ncell, ws_needed);
     if (r) return r;
@@ -589,8 +619,8 @@ csph_status csph_neighbors(const csph_state *s, const csph_params *p, int64_t *o
     PairConst pc = pair_const(p, dmax);
     const double *dd = p->h_mode == CSPH_H_PAIR ? s->d : nullptr;
     ProfScope pn(CSPH_PROF_NEIGHBORS, st);
-    CSPH_HIP(launch_bin(s->x, s->y, s->z, n, gd, w, w.perm, nullptr, w.cs, st));
-    CSPH_HIP(launch_gather_pos(n, w.perm, s->x, s->y, s->z, dd, w, st));
+    CSPH_HIP(launch_bin(sv.x, sv.y, sv.z, n, gd, w, w.perm, nullptr, w.cs, st));
+    CSPH_HIP(launch_gather_pos(n, w.perm, sv.x, sv.y, sv.z, dd, w, st));
     CSPH_HIP(launch_nbr_count(n, gd, pc, w.srt[0], w.srt[1], w.srt[2], w.srt_d, w.cs, w.perm,
                               w.cnt, st));
     pn.stop();
@@ -620,8 +650,9 @@ csph_status csph_rates(const csph_state *s, const csph_params *p, double t, csph
     if (r) return r;
     hipStream_t st = (hipStream_t)stream;
     int64_t n = s->n;
-    const csph_state sv = kernel_view(*s, p->wall);
-    const csph_rates_out ov = kernel_view(out, p->wall);
+    const Axes ax = kernel_axes(p);
+    const csph_state sv = kernel_view(*s, ax);
+    const csph_rates_out ov = kernel_view(out, ax);
     csph_grid g;
     double dmax, ymin;
     r = make_grid(sv.x, sv.y, sv.z, sv.d, n, p, ws, ws_bytes, st, &g, &dmax, &ymin, true);
@@ -754,14 +785,15 @@ static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const cs
          s_in->E == s_out->E || s_in->m == s_out->m))
         return fail(CSPH_EINVAL, "reorder = 1 needs s_out distinct from s_in");
     int64_t n = s_in->n;
-    const csph_state vin = kernel_view(*s_in, p->wall), vout = kernel_view(*s_out, p->wall);
+    const Axes ax = kernel_axes(p);
+    const csph_state vin = kernel_view(*s_in, ax), vout = kernel_view(*s_out, ax);
     csph_grid g;
     double dmax = 0.0, ymin = 0.0;
     if (mesh) {  // the caller's mesh, in the kernels' axes
         g = *mesh;
-        if (p->wall) {
-            std::swap(g.origin[0], g.origin[1]);
-            std::swap(g.dims[0], g.dims[1]);
+        for (int a = 0; a < 3; ++a) {
+            g.origin[a] = mesh->origin[ax.k[a]];
+            g.dims[a] = mesh->dims[ax.k[a]];
         }
     } else {
         r = make_grid(vin.x, vin.y, vin.z, vin.d, n, p, ws, ws_bytes, st, &g, &dmax, &ymin, true);
@@ -875,14 +907,14 @@ static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const cs
         }
         ProfScope pr(CSPH_PROF_INTEGRATE, st, prof);
         CSPH_HIP(launch_rk2_combine(n, dst, w, p->cfl, dt_in, pc, t, st));
-        CSPH_HIP(launch_finish_step(n, w, p->cfl, dt_in, t, dt_used, totals, p->wall, st));
+        CSPH_HIP(launch_finish_step(n, w, p->cfl, dt_in, t, dt_used, totals, ax.k, st));
     } else {
         ProfScope pr(CSPH_PROF_INTEGRATE, st, prof);
         VoroDev vd{};
         if (va) {
             vd.sites = va->sites;
             vd.K = va->K;
-            vd.swap = p->wall != 0;
+            for (int a = 0; a < 3; ++a) vd.ax[a] = ax.k[a];
             vd.owner = va->owner;
             vd.owner_at = p->reorder ? nullptr : w.perm;  // the output order
             vd.cnt = w.cnt;
@@ -891,7 +923,7 @@ static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const cs
         }
         // n = 0 writes zero partials
         CSPH_HIP(launch_integrate(n, dst, w, p->cfl, dt_in, pc, t, st, va ? &vd : nullptr));
-        CSPH_HIP(launch_finish_step(n, w, p->cfl, dt_in, t, dt_used, totals, p->wall, st));
+        CSPH_HIP(launch_finish_step(n, w, p->cfl, dt_in, t, dt_used, totals, ax.k, st));
     }
     ProfScope pro(CSPH_PROF_REORDER, st, prof);
     if (n > 0) {
@@ -948,7 +980,8 @@ csph_status csph_vlist_build(const csph_state *s_in, csph_state *s_out, const cs
     ph.kappa = p->kappa * (1.0 + beta);
     csph_grid g;
     double dmax, ymin;
-    const csph_state vin = kernel_view(*s_in, p->wall), vout = kernel_view(*s_out, p->wall);
+    const Axes ax = kernel_axes(p);
+    const csph_state vin = kernel_view(*s_in, ax), vout = kernel_view(*s_out, ax);
     r = make_grid(vin.x, vin.y, vin.z, nullptr, n, &ph, ws, ws_bytes, st, &g, &dmax, &ymin, true);
     if (r) return r;
     r = need_ws(ws_bytes, n, g.ncell, ws_needed);
@@ -1028,7 +1061,8 @@ csph_status csph_step_vlist(csph_state *s, const csph_params *p, double *t, doub
     PairConst pc = pair_const(p, 0.0);
     EosDev eos = eos_dev(p);
     const int mixed = p->precision == CSPH_MIXED;
-    const csph_state sv = kernel_view(*s, p->wall);
+    const Axes ax = kernel_axes(p);
+    const csph_state sv = kernel_view(*s, ax);
     double *cur[9] = {sv.x, sv.y, sv.z, sv.vx, sv.vy, sv.vz, sv.rho, sv.E, sv.m};
     // the lists' exactness bound, checked on the device; every kernel below does nothing once
     // the lists are stale
@@ -1050,7 +1084,7 @@ csph_status csph_step_vlist(csph_state *s, const csph_params *p, double *t, doub
     {
         ProfScope pr(CSPH_PROF_INTEGRATE, st);
         CSPH_HIP(launch_integrate(n, cur, w, p->cfl, dt_in, pc, t, st, nullptr, &lg));
-        CSPH_HIP(launch_finish_step(n, w, p->cfl, dt_in, t, dt_used, totals, p->wall, st, &lg));
+        CSPH_HIP(launch_finish_step(n, w, p->cfl, dt_in, t, dt_used, totals, ax.k, st, &lg));
         CSPH_HIP(launch_disp(n, s->x, s->y, s->z, x_ref, (unsigned long long *)&ctl->disp, st,
                              gate));
     }

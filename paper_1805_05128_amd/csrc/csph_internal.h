@@ -113,12 +113,13 @@ struct PairConst {
     double kappa;    // pair mode: H_ij = kappa * (0.5*(d_i+d_j))
     double h_dt;     // h in the CFL rule (fixed mode)
     // Piston wall y = wall_y0 + wall_v t in the kernels' axes.  The wall of the
-    // interface is normal to x; with a wall the library hands the kernels the
-    // x and y arrays (positions, velocities, rates) swapped, so that the wall
-    // normal runs along the slab axis of the cell order instead of its row
-    // axis: the particles within the support of the wall then fill a few
-    // waves instead of a few lanes of every wave that starts a row.  Squared
-    // distances ((dx dx + dy dy) + dz dz) do not change under the swap.
+    // interface is normal to x; with a wall (and with a periodic x and an open y)
+    // the library hands the kernels the x and y arrays (positions, velocities,
+    // rates) swapped, so that the boundary's normal runs along the slab axis of
+    // the cell order instead of its row axis: the particles within its support
+    // then fill a few waves instead of a few lanes of every wave that starts a
+    // row.  Squared distances ((dx dx + dy dy) + dz dz) do not change under the
+    // swap, to the last bit.
     double wall_y0, wall_v;
     int pair_mode;
     int wall;
@@ -302,7 +303,7 @@ hipError_t launch_add_i64(int64_t *dst, const int64_t *src, hipStream_t st);  //
 struct VoroDev {
     const double *sites;
     int K;
-    int swap;
+    int ax[3];  // the caller's axis of each of the kernels' axes
     int32_t *owner;
     const int32_t *owner_at;
     const int32_t *cnt;
@@ -329,7 +330,7 @@ hipError_t launch_integrate(int64_t n, double *const st8[9], const Ws &w, double
                             const PairConst &pc, const double *t, hipStream_t st,
                             const VoroDev *vo = nullptr, const ListGate *lg = nullptr);
 hipError_t launch_finish_step(int64_t n, const Ws &w, double cfl, double dt_in, double *t, double *dt_used,
-                              double *totals, int swap_xy, hipStream_t st,
+                              double *totals, const int ax[3], hipStream_t st,
                               const ListGate *lg = nullptr);
 hipError_t launch_unpermute(int64_t n, const int32_t *perm, double *const src[9],
                             const int32_t *src_mat, const double *src_d, const int64_t *src_id,

@@ -135,9 +135,9 @@ __device__ __forceinline__ void reflect(const WallDev &wall, double yw, double &
 // (eq. VoronoiDefinition: FP64 argmin of ((dx dx) + (dy dy)) + (dz dz) without contraction,
 // k scanned upwards with a strict comparison, so a tie keeps the smaller k) and counts
 // particles and pairs per generator, as k_voronoi does: the VALU-bound scan overlaps the
-// memory-bound update.  The generators come in the kernels' axes (x and y swapped with a
-// wall), which leaves every squared distance unchanged (the sum of the x and y terms is
-// commutative).
+// memory-bound update.  The generators come in the kernels' axes (x and y exchanged when the
+// library hands the kernels the caller's y as x), which leaves every squared distance
+// unchanged (the sum of the x and y terms is commutative).
 __global__ __launch_bounds__(kBlock) void k_integrate(int64_t n, State9 s, Rates5 r,
                                                       const unsigned long long *dtmin, double cfl,
                                                       double dt_in, WallDev wall, PerDev per,
@@ -150,9 +150,9 @@ __global__ __launch_bounds__(kBlock) void k_integrate(int64_t n, State9 s, Rates
     unsigned int *hp = (unsigned int *)(hq + vo.K);                     // K
     if (vo.K > 0) {
         for (int k = threadIdx.x; k < vo.K; k += kBlock) {
-            gs[3 * k] = vo.sites[3 * k + (vo.swap ? 1 : 0)];
-            gs[3 * k + 1] = vo.sites[3 * k + (vo.swap ? 0 : 1)];
-            gs[3 * k + 2] = vo.sites[3 * k + 2];
+            gs[3 * k] = vo.sites[3 * k + vo.ax[0]];
+            gs[3 * k + 1] = vo.sites[3 * k + vo.ax[1]];
+            gs[3 * k + 2] = vo.sites[3 * k + vo.ax[2]];
             hp[k] = 0u;
             hq[k] = 0ull;
         }
@@ -374,10 +374,15 @@ hipError_t launch_rk2_combine(int64_t n, double *const st8[9], const Ws &w, doub
     return hipGetLastError();
 }
 
+// the caller's axis of each of the kernels' axes, by value
+struct Ax3 {
+    int k[3];
+};
+
 __global__ __launch_bounds__(kBlock) void k_finish(const double *__restrict__ part, int nblocks,
                                                    const unsigned long long *dtmin, double cfl,
                                                    double dt_in, double *t, double *dt_used,
-                                                   double *totals, int swap_xy, ListGate lg) {
+                                                   double *totals, Ax3 ax, ListGate lg) {
     if (lg.gate && *lg.gate == 0) return;
     __shared__ double sh[2][5][kBlock];
     DD acc[5];
@@ -402,9 +407,9 @@ __global__ __launch_bounds__(kBlock) void k_finish(const double *__restrict__ pa
         __syncthreads();
     }
     if (threadIdx.x < 5 && totals) {
-        // sums k = 1, 2 are the momenta along the state's x and y arrays, which are the
-        // caller's y and x when the library swapped them
-        const int k = threadIdx.x, o = swap_xy && (k == 1 || k == 2) ? 3 - k : k;
+        // sums k = 1, 2, 3 are the momenta along the state's x, y, z arrays, which are the
+        // caller's axes ax.k[0], ax.k[1], ax.k[2]
+        const int k = threadIdx.x, o = (k >= 1 && k <= 3) ? 1 + ax.k[k - 1] : k;
         totals[2 * o] = sh[0][k][0];
         totals[2 * o + 1] = sh[1][k][0];
     }
@@ -417,11 +422,12 @@ __global__ __launch_bounds__(kBlock) void k_finish(const double *__restrict__ pa
 }
 
 hipError_t launch_finish_step(int64_t n, const Ws &w, double cfl, double dt_in, double *t,
-                                double *dt_used, double *totals, int swap_xy, hipStream_t st,
+                                double *dt_used, double *totals, const int ax[3], hipStream_t st,
                                 const ListGate *lg) {
     const ListGate g = lg ? *lg : ListGate{nullptr, nullptr, nullptr, nullptr};
+    const Ax3 a3{{ax[0], ax[1], ax[2]}};
     k_finish<<<1, kBlock, 0, st>>>(w.tot_part, integrate_blocks(n), w.dtmin, cfl, dt_in, t,
-                                   dt_used, totals, swap_xy, g);
+                                   dt_used, totals, a3, g);
     return hipGetLastError();
 }
 

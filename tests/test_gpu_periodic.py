@@ -134,9 +134,11 @@ def _fast_box(seed, periodic=7):
 
 
 @pytest.mark.parametrize("reorder", [False, True])
-@pytest.mark.parametrize("case", ["fast-xyz", "yz+wall"])
+@pytest.mark.parametrize("case", ["fast-xyz", "fast-xz", "yz+wall"])
 def test_periodic_step_fp64(case, reorder):
-    w = _fast_box(8) if case == "fast-xyz" else yz_wall()
+    """fast-xz: x periodic with y open, which the library hands to the kernels as their x."""
+    w = {"fast-xyz": lambda: _fast_box(8), "fast-xz": lambda: _fast_box(8, periodic=5),
+         "yz+wall": yz_wall}[case]()
     _print_case(f"step {case} reorder={reorder}", w)
     params = P.Params.from_workload(w, reorder=reorder)
     g = P.state_from_workload(w, params, DEV)
@@ -151,9 +153,10 @@ def test_periodic_step_fp64(case, reorder):
     ids = got["id"]
     assert np.array_equal(np.sort(ids), np.arange(w.n))
     assert abs(to_np(sc.dt)[0] - dt) <= 1e-15 * dt
-    if case == "fast-xyz":  # some particles crossed each face pair
-        for k, L in (("x", 10.0), ("y", 9.0), ("z", 11.0)):
-            assert np.sum(np.abs(s1[k] - s0[k]) > L / 2) > 10, k
+    if case.startswith("fast"):  # some particles crossed each periodic face pair
+        for a, (k, L) in enumerate((("x", 10.0), ("y", 9.0), ("z", 11.0))):
+            if (w.periodic >> a) & 1:
+                assert np.sum(np.abs(s1[k] - s0[k]) > L / 2) > 10, k
     for k in ("x", "y", "z", "vx", "vy", "vz", "rho", "E"):
         a, b = got[k], s1[k][ids]
         inc = b - s0[k][ids]
@@ -168,9 +171,11 @@ def test_periodic_step_fp64(case, reorder):
             assert got[k].min() >= lo[a] and got[k].max() < hi[a], k
 
 
-def test_periodic_step_mixed_and_voronoi():
-    """Mixed-precision step with the fused Voronoi ownership of the wrapped positions."""
-    w = _fast_box(9)
+@pytest.mark.parametrize("mask", [7, 5])
+def test_periodic_step_mixed_and_voronoi(mask):
+    """Mixed-precision step with the fused Voronoi ownership of the wrapped positions (mask 5:
+    the kernels take the caller's y as x)."""
+    w = _fast_box(9, periodic=mask)
     params = P.Params.from_workload(w, precision="mixed", reorder=True)
     g = P.state_from_workload(w, params, DEV)
     sites = torch.as_tensor(ci.voronoi_sites(37, seed=9, box=(10.0, 9.0, 11.0)), device=DEV)
