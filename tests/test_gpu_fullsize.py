@@ -11,6 +11,10 @@ configuration bench.py times (cell order, unit mesh cells, both precisions):
   precisions, and the compensated totals;
 * Mie-Grueneisen plates in the pair-averaged support mode (6 291 456
   particles): rates of a seeded sample including the contact layers;
+* plate impact with periodic lateral faces: one step of every particle through
+  csph_step and through csph_step_mesh on the bench's fixed mesh (FP64 and mixed);
+* porous shock 256^3: one RK2 step of every particle from the initial state, both
+  precisions;
 * two-body collision (64 000 000 particles): rates of a seeded sample that
   includes the contact layer, against the oracle computed for the sample;
   and the adjoint of the last 5 of its 50 steps (45 mixed steps in cell
@@ -162,6 +166,85 @@ def test_plate_impact_step_every_particle():
         for k in range(5):
             assert abs(math.fsum([tot[2 * k], tot[2 * k + 1]]) - exact[k]) <= \
                 4 * math.ulp(abs(exact[k])) + 1e-300, (prec, k)
+        del g, out
+        torch.cuda.empty_cache()
+
+
+def _check_step(got, s0, s1, tol, tag):
+    ids = got["id"]
+    for k in ("x", "y", "z", "vx", "vy", "vz", "rho", "E"):
+        a, b = got[k], s1[k][ids]
+        inc = b - s0[k][ids]
+        if k in ("x", "y", "z"):  # a wrapped position's increment is the unwrapped one
+            inc = np.where(np.abs(inc) > 16.0, 0.0, inc)
+        den = max(np.abs(inc).max(), 1e-300)
+        err = np.abs(a - b)
+        if k in ("x", "y"):  # positions wrapped on one side and not the other (mixed only)
+            err = np.minimum(err, np.abs(err - 128.0))
+        assert err.max() <= tol * den + 4 * np.finfo(float).eps * np.abs(b).max(), (tag, k)
+
+
+def test_plate_impact_periodic_step_every_particle():
+    """The plate impact in contact with the target's lateral faces periodic (the paper's plates
+    are periodic across the impact direction), one FP64 step of every particle through
+    csph_step and through csph_step_mesh on the fixed mesh the bench's graph leg uses, and
+    one mixed step through csph_step_mesh, against the oracle's periodic step."""
+    w = ci.config1()
+    w.z[w.z > 33.0] -= 1.5
+    w.periodic = 3
+    w.box = ((0.0, 0.0, -96.0), (128.0, 128.0, 96.0))
+    print(f"[case] {w.name} periodic xy (in contact) n={w.n}", flush=True)
+    cfg = O.cfg_for(w, search=1)
+    s0 = O.state_from(w, cfg)
+    s1, t1, dt, ncount = O.step(cfg, s0, t=0.0)
+    for how, prec, tol in (("step", "fp64", FP64_TOL), ("mesh", "fp64", FP64_TOL),
+                           ("mesh", "mixed", 5e-5)):
+        params = P.Params.from_workload(w, precision=prec, reorder=True, cell_size=1.0)
+        g = P.state_from_workload(w, params, DEV, with_id=True)
+        sc = P.StepScalars(DEV)
+        cnt = torch.empty(w.n, dtype=torch.int32, device=DEV)
+        if how == "step":
+            out = P.csph_step(g, params, sc, nbr_count=cnt)
+        else:
+            outside = torch.zeros(1, dtype=torch.int64, device=DEV)
+            mesh = P.domain_mesh(w.box[0], w.box[1], params)
+            out = P.csph_step_mesh(g, params, sc, mesh, nbr_count=cnt, outside=outside)
+            torch.cuda.synchronize()
+            assert int(outside.item()) == 0
+        torch.cuda.synchronize()
+        got = out.numpy()
+        assert np.array_equal(to_np(cnt).astype(np.int64), ncount[got["id"]]), (how, prec)
+        gdt = float(to_np(sc.dt)[0])
+        assert abs(gdt - dt) <= (1e-15 if prec == "fp64" else 1e-5) * dt
+        s1c = s1 if prec == "fp64" else O.step(cfg, s0, t=0.0, dt_in=gdt)[0]
+        _check_step(got, s0, s1c, tol, (how, prec))
+        del g, out
+        torch.cuda.empty_cache()
+
+
+def test_porous256_rk2_step_every_particle():
+    """One two-stage Runge-Kutta step of the porous shock 256^3 from its initial state (the
+    bench's rk2 leg), every particle, against the oracle's RK2 step (two full evaluations)."""
+    w = ci.config2()
+    print(f"[case] {w.name} rk2 n={w.n}", flush=True)
+    cfg = O.cfg_for(w, search=1, integrator=1)
+    s0 = O.state_from(w, cfg)
+    s1, t1, dt, ncount = O.step(cfg, s0, t=0.0)
+    for prec, tol in (("fp64", FP64_TOL), ("mixed", 5e-5)):
+        params = P.Params.from_workload(w, precision=prec, reorder=True, cell_size=1.0,
+                                        integrator="rk2")
+        g = P.state_from_workload(w, params, DEV, with_id=True)
+        sc = P.StepScalars(DEV)
+        cnt = torch.empty(w.n, dtype=torch.int32, device=DEV)
+        out = P.csph_step(g, params, sc, nbr_count=cnt)
+        torch.cuda.synchronize()
+        got = out.numpy()
+        assert np.array_equal(to_np(cnt).astype(np.int64), ncount[got["id"]]), prec
+        gdt = float(to_np(sc.dt)[0])
+        assert abs(gdt - dt) <= (1e-15 if prec == "fp64" else 1e-5) * dt
+        s1c = s1 if prec == "fp64" else O.step(cfg, s0, t=0.0, dt_in=gdt)[0]
+        _check_step(got, s0, s1c, tol, prec)
+        assert np.all(got["x"] >= w.wall[0] + w.wall[1] * gdt)
         del g, out
         torch.cuda.empty_cache()
 
