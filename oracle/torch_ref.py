@@ -5,7 +5,10 @@ the same equations as ``oracle.c`` (sec. 4.1, eqs. SPH:Conti, SPH:Pulse,
 SPH:Energy, acoustic pairwise Riemann solver, Wendland C2 kernel) so that
 ``torch.autograd`` supplies exact reference gradients for the hand-written
 GPU adjoint.  Pair lists come from the C oracle's brute-force neighbour
-sets.  The time step dt is an input (frozen), fixed-h mode only, no wall.
+sets; with the piston (the rigid wall of sec. 7.1) the mirror pairs come from
+a brute-force test of the reflected positions written as the oracle writes it,
+and the step reflects the particles that cross the plane.  The time step dt is
+an input (frozen), fixed-h mode only.
 
 Only the tests may import this module.
 """
@@ -30,6 +33,20 @@ def pairs_of(cfg, s) -> Tuple[torch.Tensor, torch.Tensor]:
     return torch.as_tensor(i, dtype=torch.long), torch.as_tensor(idx.astype(np.int64))
 
 
+def mirror_pairs_of(s, H: float, xw: float) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Directed mirror pairs (i, j), j = i included: the reflected position of j,
+    (2 xw - x_j, y_j, z_j), within the support of i; brute force over all j, the squared
+    distance formed as the oracle forms it (((dx dx) + (dy dy)) + dz dz, dx = xg - x_i)."""
+    x, y, z = (np.asarray(s[k], np.float64) for k in ("x", "y", "z"))
+    xg = 2.0 * xw - x
+    dx = xg[None, :] - x[:, None]
+    dy = y[None, :] - y[:, None]
+    dz = z[None, :] - z[:, None]
+    r2 = ((dx * dx) + (dy * dy)) + (dz * dz)
+    i, j = np.nonzero(r2 < H * H)
+    return torch.as_tensor(i.astype(np.int64)), torch.as_tensor(j.astype(np.int64))
+
+
 def eos_torch(rho, E, vx, vy, vz, mat, eos_type: Sequence[int], gamma, pinf):
     """P and c from e = E - |v|^2/2 (ideal or stiffened gas), per-material gamma/p_inf tensors."""
     e = E - 0.5 * ((vx * vx + vy * vy) + vz * vz)
@@ -50,14 +67,10 @@ def init_energy_torch(rho, p, vx, vy, vz, mat, eos_type, gamma, pinf):
     return e + 0.5 * ((vx * vx + vy * vy) + vz * vz)
 
 
-def rates_torch(st: Dict[str, torch.Tensor], m, mat, eos_type, gamma, pinf, pairs, H: float):
-    """(drho, dvx, dvy, dvz, dE) of every particle for the directed pair list."""
-    x, y, z, vx, vy, vz, rho, E = (st[k] for k in FIELDS8)
-    P, c = eos_torch(rho, E, vx, vy, vz, mat, eos_type, gamma, pinf)
-    Z = rho * c
-    V = m / rho
-    i, j = pairs
-    dx, dy, dz = x[j] - x[i], y[j] - y[i], z[j] - z[i]
+def _pair_sums(x, y, z, vx, vy, vz, P, Z, V, i, j, xj, vxj, H: float):
+    """Per-pair terms of i's sums for partners j whose position's x and velocity's x are
+    ``xj`` and ``vxj`` (the particle's own, or its mirror image's)."""
+    dx, dy, dz = xj - x[i], y[j] - y[i], z[j] - z[i]
     r2 = (dx * dx + dy * dy) + dz * dz
     nz = r2 > 0
     r = torch.sqrt(torch.where(nz, r2, torch.ones_like(r2)))
@@ -66,33 +79,68 @@ def rates_torch(st: Dict[str, torch.Tensor], m, mat, eos_type, gamma, pinf, pair
     a = 1.0 - q
     dW = torch.where(nz, -(210.0 / (math.pi * H ** 4)) * q * a ** 3, torch.zeros_like(r))
     vL = (vx[i] * ex + vy[i] * ey) + vz[i] * ez
-    vR = (vx[j] * ex + vy[j] * ey) + vz[j] * ez
+    vR = (vxj * ex + vy[j] * ey) + vz[j] * ez
     Zi, Zj, Pi, Pj = Z[i], Z[j], P[i], P[j]
     S = Zi + Zj
     Ss = torch.where(S != 0, S, torch.ones_like(S))
     vs = torch.where(S != 0, ((Zi * vL + Zj * vR) + (Pi - Pj)) / Ss, 0.5 * (vL + vR))
     ps = torch.where(S != 0, ((Zj * Pi + Zi * Pj) + Zi * Zj * (vL - vR)) / Ss, 0.5 * (Pi + Pj))
     w = V[j] * dW
+    f = w * ps
+    return w * (vL - vs), f * ex, f * ey, f * ez, f * vs
+
+
+def rates_torch(st: Dict[str, torch.Tensor], m, mat, eos_type, gamma, pinf, pairs, H: float,
+                mirror=None, wall=None):
+    """(drho, dvx, dvy, dvz, dE) of every particle for the directed pair list, plus, with the
+    piston wall = (x_w, v_w) at the evaluation time, the directed mirror pairs: j's mirror image
+    at 2 x_w - x_j with x-velocity 2 v_w - vx_j and j's other fields."""
+    x, y, z, vx, vy, vz, rho, E = (st[k] for k in FIELDS8)
+    P, c = eos_torch(rho, E, vx, vy, vz, mat, eos_type, gamma, pinf)
+    Z = rho * c
+    V = m / rho
     n = x.shape[0]
     z0 = torch.zeros(n, dtype=x.dtype)
-    s_rho = z0.index_add(0, i, w * (vL - vs))
-    f = w * ps
-    s_vx = z0.index_add(0, i, f * ex)
-    s_vy = z0.index_add(0, i, f * ey)
-    s_vz = z0.index_add(0, i, f * ez)
-    s_E = z0.index_add(0, i, f * vs)
+    sums = [z0] * 5
+    i, j = pairs
+    for k, t in enumerate(_pair_sums(x, y, z, vx, vy, vz, P, Z, V, i, j, x[j], vx[j], H)):
+        sums[k] = sums[k].index_add(0, i, t)
+    if mirror is not None:
+        xw, vw = wall
+        i, j = mirror
+        terms = _pair_sums(x, y, z, vx, vy, vz, P, Z, V, i, j, 2.0 * xw - x[j],
+                           2.0 * vw - vx[j], H)
+        for k, t in enumerate(terms):
+            sums[k] = sums[k].index_add(0, i, t)
+    s_rho, s_vx, s_vy, s_vz, s_E = sums
     return (-2.0 * rho * s_rho, (2.0 / rho) * s_vx, (2.0 / rho) * s_vy, (2.0 / rho) * s_vz,
             (2.0 / rho) * s_E)
 
 
-def step_torch(st, m, mat, eos_type, gamma, pinf, pairs, H: float, dt: float):
-    """Symplectic Euler with frozen dt: v, E, rho += dt rates, then r += dt v_new."""
-    drho, dvx, dvy, dvz, dE = rates_torch(st, m, mat, eos_type, gamma, pinf, pairs, H)
+def step_torch(st, m, mat, eos_type, gamma, pinf, pairs, H: float, dt: float, mirror=None,
+               wall=None, t: float = 0.0):
+    """Symplectic Euler with frozen dt: v, E, rho += dt rates, then r += dt v_new.  With the
+    piston wall = (x_w0, v_w): mirror pairs at x_w(t), and a particle whose new x lies behind
+    x_w(t + dt) is reflected (x <- 2 x_w - x, v_x <- 2 v_w - v_x, E changed by the kinetic
+    energy difference); which particles reflect is decided on the values (a fixed branch for
+    the gradient)."""
+    w_now = None if wall is None else (wall[0] + wall[1] * t, wall[1])
+    drho, dvx, dvy, dvz, dE = rates_torch(st, m, mat, eos_type, gamma, pinf, pairs, H,
+                                          mirror=mirror, wall=w_now)
     vx = st["vx"] + dt * dvx
     vy = st["vy"] + dt * dvy
     vz = st["vz"] + dt * dvz
-    return {"x": st["x"] + dt * vx, "y": st["y"] + dt * vy, "z": st["z"] + dt * vz,
-            "vx": vx, "vy": vy, "vz": vz, "rho": st["rho"] + dt * drho, "E": st["E"] + dt * dE}
+    x = st["x"] + dt * vx
+    E = st["E"] + dt * dE
+    if wall is not None:
+        xw = wall[0] + wall[1] * (t + dt)
+        behind = (x < xw).detach()
+        vr = 2.0 * wall[1] - vx
+        E = torch.where(behind, E + 0.5 * ((vr * vr) - (vx * vx)), E)
+        vx = torch.where(behind, vr, vx)
+        x = torch.where(behind, 2.0 * xw - x, x)
+    return {"x": x, "y": st["y"] + dt * vy, "z": st["z"] + dt * vz,
+            "vx": vx, "vy": vy, "vz": vz, "rho": st["rho"] + dt * drho, "E": E}
 
 
 def to_torch(s) -> Dict[str, torch.Tensor]:

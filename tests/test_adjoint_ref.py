@@ -117,3 +117,76 @@ def test_init_energy_gamma_gradient():
 
             fd = (Jat(1) - Jat(-1)) / (2 * eps)
             assert abs(fd - float(grad[k])) <= 1e-6 * max(1.0, abs(fd))
+
+
+def wall_system(seed=5):
+    """The block moving onto the piston (x_w = 0.2 + 0.4 t): at t = 0.3 the first layers have
+    mirror partners, and a step of 0.2 reflects about half of the first layer."""
+    w = system(n=6, seed=seed)
+    w.vx = w.vx - 0.5
+    w.wall = (0.2, 0.4)
+    return w
+
+
+def test_torch_rates_with_the_piston_match_c_oracle():
+    w = wall_system()
+    cfg = O.cfg_for(w)
+    s = O.state_from(w, cfg)
+    t = 0.3
+    ref = O.rates(cfg, s, t=t)
+    et, g, pi = tparams(w)
+    xw = w.wall[0] + w.wall[1] * t
+    mir = T.mirror_pairs_of(s, w.kappa * w.h, xw)
+    assert len(mir[0]) > 20
+    out = T.rates_torch(T.to_torch(s), torch.as_tensor(s["m"]), torch.as_tensor(s["mat"]).long(),
+                        et, g, pi, T.pairs_of(cfg, s), w.kappa * w.h, mirror=mir,
+                        wall=(xw, w.wall[1]))
+    for k, v in zip(("drho", "dvx", "dvy", "dvz", "dE"), out):
+        scale = np.abs(ref[k]).max()
+        assert np.abs(v.numpy() - ref[k]).max() <= 1e-13 * scale, k
+
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_step_with_the_piston_gradient_matches_oracle_finite_differences(seed):
+    """Mirror partners and reflections in the step: the reference's gradient (reflection
+    branches and mirror pairs fixed at the base state) against central differences of the
+    C oracle's step with the piston."""
+    w = wall_system(seed)
+    cfg = O.cfg_for(w, cfl=0.0)  # the step takes dt_in as given
+    s = O.state_from(w, cfg)
+    t, dt = 0.3, 0.2
+    s1_base, _, _, _ = O.step(cfg, s, t, dt_in=dt)
+    assert np.sum(s1_base["vx"] > 0.3) > 3  # some particles were reflected
+    et, g, pi = tparams(w)
+    st = {k: v.clone().requires_grad_(True) for k, v in T.to_torch(s).items()}
+    g = g.clone().requires_grad_(True)
+    pi = pi.clone().requires_grad_(True)
+    m = torch.as_tensor(s["m"])
+    mat = torch.as_tensor(s["mat"]).long()
+    mir = T.mirror_pairs_of(s, w.kappa * w.h, w.wall[0] + w.wall[1] * t)
+    out = T.step_torch(st, m, mat, et, g, pi, T.pairs_of(cfg, s), w.kappa * w.h, dt,
+                       mirror=mir, wall=w.wall, t=t)
+    for k in F8:
+        assert np.abs(out[k].detach().numpy() - s1_base[k]).max() <= 1e-13 * (1 + np.abs(s1_base[k]).max()), k
+    rng = np.random.default_rng(seed + 20)
+    lam = {k: rng.standard_normal(w.n) for k in F8}
+    J = sum((out[k] * torch.as_tensor(lam[k])).sum() for k in F8)
+    grads = torch.autograd.grad(J, [st[k] for k in F8] + [g, pi])
+    for trial in range(3):
+        d = {k: rng.standard_normal(w.n) for k in F8}
+        dg = rng.standard_normal(len(w.eos))
+        dpi = rng.standard_normal(len(w.eos)) * np.array([0.0 if e[0] == 0 else 1.0 for e in w.eos])
+        pred = sum(float((grads[a].numpy() * d[k]).sum()) for a, k in enumerate(F8))
+        pred += float((grads[8].numpy() * dg).sum()) + float((grads[9].numpy() * dpi).sum())
+        eps = 1e-6
+
+        def J_at(sign):
+            s2 = {k: (s[k] + sign * eps * d[k]) if k in d else s[k] for k in s}
+            eos2 = [(e[0], e[1] + sign * eps * dg[k], e[2] + sign * eps * dpi[k])
+                    for k, e in enumerate(w.eos)]
+            c2 = O.make_cfg(eos2, h=w.h, kappa=w.kappa, cfl=0.0, wall=w.wall)
+            s1, _, _, _ = O.step(c2, s2, t, dt_in=dt)
+            return sum(float((s1[k] * lam[k]).sum()) for k in F8)
+
+        fd = (J_at(1) - J_at(-1)) / (2 * eps)
+        assert abs(fd - pred) <= 1e-6 * max(abs(pred), 1.0), (trial, fd, pred)
