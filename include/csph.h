@@ -453,31 +453,39 @@ csph_status csph_init_energy(const double *rho, const double *pres, const double
                              const double *vy, const double *vz, const int32_t *mat, int64_t n,
                              const csph_params *p, double *E, csph_stream stream);
 
-/* Adjoint (vector-Jacobian products).  Fixed-h mode without a wall, ideal
- * and stiffened-gas materials (CSPH_EINVAL otherwise); FP64
- * arithmetic in both precisions (it differentiates the FP64 map).  A
- * gradient struct holds 8 FP64 arrays in the state's order. */
+/* Adjoint (vector-Jacobian products).  Fixed-h mode, open boundaries or the
+ * piston, ideal and stiffened-gas materials (CSPH_EINVAL otherwise: pair-h mode,
+ * periodic axes, Mie-Grueneisen materials); FP64 arithmetic in both precisions
+ * (it differentiates the FP64 map).  A gradient struct holds 8 FP64 arrays in
+ * the state's order. */
 typedef struct {
     double *x, *y, *z, *vx, *vy, *vz, *rho, *E;
 } csph_grad;
 
-/* VJP of csph_rates: with cotangents a of the five rate arrays (input
- * order), g_state += (d rates / d state)^T a over the eight state arrays,
- * and g_eos[2k] += dJ/d gamma_k, g_eos[2k+1] += dJ/d p_inf_k (device,
- * 2*n_eos doubles, optional).  The rates' dependence on (rho, E, v) through
- * the EOS is included; masses and materials are constants.  Gather form:
- * it relies on j in N(i) <=> i in N(j).  Where c = 0 the derivative of c
- * with respect to c^2 is taken as 0.  Synchronises once (mesh bounds). */
-csph_status csph_rates_vjp(const csph_state *s, const csph_params *p, csph_rates_out a,
-                           csph_grad g_state, double *g_eos, void *ws, size_t ws_bytes,
-                           size_t *ws_needed, csph_stream stream);
+/* VJP of csph_rates at time t (the piston's position; ignored without it):
+ * with cotangents a of the five rate arrays (input order), g_state +=
+ * (d rates / d state)^T a over the eight state arrays, and g_eos[2k] +=
+ * dJ/d gamma_k, g_eos[2k+1] += dJ/d p_inf_k (device, 2*n_eos doubles,
+ * optional).  The rates' dependence on (rho, E, v) through the EOS is
+ * included; masses, materials and the piston's motion are constants.
+ * Gather form: it relies on j in N(i) <=> i in N(j), and with the piston on
+ * j's mirror image lying within the support of i <=> i's within that of j
+ * (sec. 7.1).  Where c = 0 the derivative of c with respect to c^2 is taken
+ * as 0.  Synchronises once (mesh bounds). */
+csph_status csph_rates_vjp(const csph_state *s, const csph_params *p, double t,
+                           csph_rates_out a, csph_grad g_state, double *g_eos, void *ws,
+                           size_t ws_bytes, size_t *ws_needed, csph_stream stream);
 
-/* VJP of one csph_step with the time step dt held fixed (the step's own
- * dt, replayed): s_n is the state the step started from, g_next the
- * cotangent of the state after it (same particle order, i.e. a step taken
- * with reorder = 0), g_prev receives (d s_{n+1} / d s_n)^T g_next (it may
- * alias g_next), g_eos is accumulated as in csph_rates_vjp. */
-csph_status csph_step_vjp(const csph_state *s_n, const csph_params *p, double dt,
+/* VJP of one Euler csph_step taken at time t with the time step dt held
+ * fixed (the step's own dt, replayed): s_n is the state the step started
+ * from, g_next the cotangent of the state after it (same particle order,
+ * i.e. a step taken with reorder = 0), g_prev receives (d s_{n+1} / d s_n)^T
+ * g_next (it may alias g_next), g_eos is accumulated as in csph_rates_vjp.
+ * With the piston, the particles the step reflected off the wall at t + dt
+ * are found again from an FP64 evaluation of the rates at t (the step's own
+ * test, x + dt (v_x + dt R_vx) < x_w(t + dt)), and the reflection's Jacobian is
+ * applied to their cotangents; the branch itself is not differentiated. */
+csph_status csph_step_vjp(const csph_state *s_n, const csph_params *p, double t, double dt,
                           csph_grad g_next, csph_grad g_prev, double *g_eos, void *ws,
                           size_t ws_bytes, size_t *ws_needed, csph_stream stream);
 

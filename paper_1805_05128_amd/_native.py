@@ -146,11 +146,11 @@ def load():
     L.csph_init_energy.argtypes = [_dp, _dp, _dp, _dp, _dp, _ip, C.c_int64,
                                    C.POINTER(CsphParams), _dp, vp]
     L.csph_rates_vjp.restype = C.c_int32
-    L.csph_rates_vjp.argtypes = [C.POINTER(CsphState), C.POINTER(CsphParams), CsphRatesOut,
-                                 CsphGrad, _dp, vp, sz, szp, vp]
+    L.csph_rates_vjp.argtypes = [C.POINTER(CsphState), C.POINTER(CsphParams), C.c_double,
+                                 CsphRatesOut, CsphGrad, _dp, vp, sz, szp, vp]
     L.csph_step_vjp.restype = C.c_int32
     L.csph_step_vjp.argtypes = [C.POINTER(CsphState), C.POINTER(CsphParams), C.c_double,
-                                CsphGrad, CsphGrad, _dp, vp, sz, szp, vp]
+                                C.c_double, CsphGrad, CsphGrad, _dp, vp, sz, szp, vp]
     L.csph_init_energy_vjp.restype = C.c_int32
     L.csph_init_energy_vjp.argtypes = [_dp, _dp, _dp, _dp, _dp, _ip, C.c_int64,
                                        C.POINTER(CsphParams), _dp, _dp, _dp, _dp, _dp, _dp, vp,

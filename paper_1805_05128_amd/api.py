@@ -465,8 +465,9 @@ def zeros_grad(n: int, device="cuda") -> Dict[str, torch.Tensor]:
 def csph_rates_vjp(state: State, params: Params, cot: Dict[str, torch.Tensor],
                    g_state: Optional[Dict[str, torch.Tensor]] = None,
                    g_eos: Optional[torch.Tensor] = None, ws: Optional[Workspace] = None,
-                   stream=None):
-    """g_state += (d rates/d state)^T cot, g_eos += EOS-parameter part; returns both."""
+                   stream=None, t: float = 0.0):
+    """g_state += (d rates/d state)^T cot, g_eos += EOS-parameter part; returns both.
+    ``t``: the time of the rates (the piston's position)."""
     L = N.load()
     dev = state["x"].device
     ws = ws or default_workspace(dev)
@@ -478,16 +479,18 @@ def csph_rates_vjp(state: State, params: Params, cot: Dict[str, torch.Tensor],
     s = state.c()
     p = params.c()
     gs = _grad_struct(g_state)
-    _with_ws(lambda w, b, nd: L.csph_rates_vjp(C.byref(s), C.byref(p), a, gs, _dp(g_eos), w, b,
-                                               nd, _stream(stream)), ws, "csph_rates_vjp")
+    _with_ws(lambda w, b, nd: L.csph_rates_vjp(C.byref(s), C.byref(p), float(t), a, gs,
+                                               _dp(g_eos), w, b, nd, _stream(stream)), ws,
+             "csph_rates_vjp")
     return g_state, g_eos
 
 
 def csph_step_vjp(s_n: State, params: Params, dt: float, g_next: Dict[str, torch.Tensor],
                   g_prev: Optional[Dict[str, torch.Tensor]] = None,
                   g_eos: Optional[torch.Tensor] = None, ws: Optional[Workspace] = None,
-                  stream=None):
-    """Cotangent of s_n from that of the state after one step with frozen dt."""
+                  stream=None, t: float = 0.0):
+    """Cotangent of s_n from that of the state after one step taken at time ``t`` with frozen
+    dt."""
     L = N.load()
     dev = s_n["x"].device
     ws = ws or default_workspace(dev)
@@ -498,8 +501,8 @@ def csph_step_vjp(s_n: State, params: Params, dt: float, g_next: Dict[str, torch
     s = s_n.c()
     p = params.c()
     gn, gp = _grad_struct(g_next), _grad_struct(g_prev)
-    _with_ws(lambda w, b, nd: L.csph_step_vjp(C.byref(s), C.byref(p), float(dt), gn, gp,
-                                              _dp(g_eos), w, b, nd, _stream(stream)), ws,
+    _with_ws(lambda w, b, nd: L.csph_step_vjp(C.byref(s), C.byref(p), float(t), float(dt), gn,
+                                              gp, _dp(g_eos), w, b, nd, _stream(stream)), ws,
              "csph_step_vjp")
     return g_prev, g_eos
 

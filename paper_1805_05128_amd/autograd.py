@@ -9,7 +9,9 @@ applies csph_step_vjp step by step and finally the VJP of the initial
 energy E0 = e(rho, p; gamma) + |v0|^2/2 when the rollout starts from
 (rho, p) (a window that starts from (rho, E) holds E fixed).  The time
 steps are held fixed (replayed), i.e. the gradient is that of the map at
-the recorded dt sequence.
+the recorded dt sequence.  The start time of every step is recorded too:
+with the piston, the segments are replayed from their own start times and
+each step's VJP places the wall where the step did.
 """
 from __future__ import annotations
 
@@ -43,17 +45,18 @@ class CSPHRollout(torch.autograd.Function):
     longer run: E is held fixed, so the gradient is the partial derivative
     at fixed specific total energy); ``params`` the run parameters (its
     gammas are replaced by the ``gamma`` tensor); ``dts``, if given, is the
-    list of time steps to use instead of the CFL rule.  After the call,
-    ``info['dts']`` holds the dt sequence and ``info['forward_s']`` the
-    forward wall time.
+    list of time steps to use instead of the CFL rule; ``t0`` the start time
+    (the piston's position).  After the call, ``info['dts']`` holds the dt
+    sequence and ``info['forward_s']`` the forward wall time.
     """
 
     @staticmethod
     def forward(ctx, vx0, vy0, vz0, gamma, base: Dict[str, torch.Tensor], params: A.Params,
-                nsteps: int, every: int, dts: Optional[List[float]], info: dict):
+                nsteps: int, every: int, dts: Optional[List[float]], info: dict,
+                t0: float = 0.0):
         import time
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        tic = time.perf_counter()
         pg = _with_gamma(params, gamma.detach().cpu().tolist())
         if "p" in base:
             E0 = A.csph_init_energy(base["rho"], base["p"], vx0, vy0, vz0, base["mat"], pg)
@@ -63,24 +66,27 @@ class CSPHRollout(torch.autograd.Function):
                       "vx": vx0.detach().clone(), "vy": vy0.detach().clone(),
                       "vz": vz0.detach().clone(), "rho": base["rho"].clone(), "E": E0,
                       "m": base["m"]}, base["mat"])
-        sc = A.StepScalars(vx0.device)
+        sc = A.StepScalars(vx0.device, t0=t0)
         ckpts = []
-        dt_dev = []
+        dt_dev, t_dev = [], []
         replay = dataclasses.replace(pg, cfl=0.0)
         for k in range(nsteps):
             if k % every == 0:
                 ckpts.append(_clone_state(st))
+            t_dev.append(sc.t.clone())
             if dts is None:
                 A.csph_step(st, pg, sc, s_out=st, totals=False)
             else:
                 A.csph_step(st, replay, sc, s_out=st, dt_in=float(dts[k]), totals=False)
             dt_dev.append(sc.dt.clone())
         dt_list = torch.cat(dt_dev).cpu().tolist() if nsteps else []
+        t_list = torch.cat(t_dev).cpu().tolist() if nsteps else []
         torch.cuda.synchronize()
         info["dts"] = dt_list
-        info["forward_s"] = time.perf_counter() - t0
+        info["forward_s"] = time.perf_counter() - tic
         ctx.ckpts = ckpts
         ctx.dts = dt_list
+        ctx.ts = t_list
         ctx.params = pg
         ctx.every = every
         ctx.nsteps = nsteps
@@ -93,7 +99,7 @@ class CSPHRollout(torch.autograd.Function):
     def backward(ctx, *g_final):
         import time
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        tic = time.perf_counter()
         vx0, vy0, vz0 = ctx.saved_tensors
         dev = vx0.device
         n = vx0.shape[0]
@@ -102,30 +108,34 @@ class CSPHRollout(torch.autograd.Function):
              for k, gf in zip(STATE8, g_final)}
         g_eos = torch.zeros(2 * len(pg.eos), dtype=torch.float64, device=dev)
         replay = dataclasses.replace(pg, cfl=0.0)
-        sc = A.StepScalars(dev)
         nseg = len(ctx.ckpts)
         for seg in reversed(range(nseg)):
             k0 = seg * ctx.every
             k1 = min(k0 + ctx.every, ctx.nsteps)
+            # the segment's replay starts at its recorded time; t + dt then repeats the
+            # forward's times bit for bit
+            sc = A.StepScalars(dev, t0=ctx.ts[k0])
             states = [ctx.ckpts[seg]]
             s = _clone_state(ctx.ckpts[seg])
             for k in range(k0, k1 - 1):
                 A.csph_step(s, replay, sc, s_out=s, dt_in=ctx.dts[k], totals=False)
                 states.append(_clone_state(s))
             for k in reversed(range(k0, k1)):
-                A.csph_step_vjp(states[k - k0], pg, ctx.dts[k], g, g_prev=g, g_eos=g_eos)
+                A.csph_step_vjp(states[k - k0], pg, ctx.dts[k], g, g_prev=g, g_eos=g_eos,
+                                t=ctx.ts[k])
             states.clear()
         b = ctx.base
         if "p" in b:
             A.csph_init_energy_vjp(b["rho"], b["p"], vx0, vy0, vz0, b["mat"], pg, g["E"],
                                    g_v=(g["vx"], g["vy"], g["vz"]), g_eos=g_eos)
         torch.cuda.synchronize()
-        ctx.info["backward_s"] = time.perf_counter() - t0
+        ctx.info["backward_s"] = time.perf_counter() - tic
         return (g["vx"], g["vy"], g["vz"], g_eos[0::2].clone(), None, None, None, None, None,
-                None)
+                None, None)
 
 
-def rollout(vx0, vy0, vz0, gamma, base, params, nsteps, every=10, dts=None, info=None):
+def rollout(vx0, vy0, vz0, gamma, base, params, nsteps, every=10, dts=None, info=None,
+            t0: float = 0.0):
     """Functional form of CSPHRollout.apply; returns a dict of final-state tensors.
 
     The gradient is that of the rollout at a FIXED time-step sequence: the forward records
@@ -134,5 +144,5 @@ def rollout(vx0, vy0, vz0, gamma, base, params, nsteps, every=10, dts=None, info
     gamma (through c, the closing speeds and rho/|drho/dt|) is not differentiated, so a
     finite-difference check must replay the same steps."""
     info = {} if info is None else info
-    out = CSPHRollout.apply(vx0, vy0, vz0, gamma, base, params, nsteps, every, dts, info)
+    out = CSPHRollout.apply(vx0, vy0, vz0, gamma, base, params, nsteps, every, dts, info, t0)
     return dict(zip(STATE8, out))

@@ -1169,7 +1169,6 @@ static csph_status check_vjp_params(const csph_params *p) {
     for (int k = 0; k < p->n_eos; ++k)
         if (p->eos[k].type == CSPH_EOS_MIE_GRUNEISEN)
             return fail(CSPH_EINVAL, "the adjoint supports ideal and stiffened gas only");
-    if (p->wall) return fail(CSPH_EINVAL, "the adjoint does not support the piston wall");
     if (p->periodic) return fail(CSPH_EINVAL, "the adjoint does not support periodic boundaries");
     return CSPH_OK;
 }
@@ -1178,11 +1177,25 @@ static bool grad_ok(const csph_grad &g) {
     return g.x && g.y && g.z && g.vx && g.vy && g.vz && g.rho && g.E;
 }
 
-// shared body of csph_rates_vjp / csph_step_vjp
-static csph_status vjp_common(const csph_state *s, const csph_params *p, const double *const a[5],
-                              const csph_grad *gnext, double dt, csph_grad gout, int accumulate,
-                              double *g_eos, void *ws, size_t ws_bytes, size_t *ws_needed,
-                              hipStream_t st) {
+// A gradient struct in the kernels' axes (kernel_axes).
+static csph_grad kernel_view(const csph_grad &gr, const Axes &ax) {
+    csph_grad v = gr;
+    double *const pos[3] = {gr.x, gr.y, gr.z}, *const vel[3] = {gr.vx, gr.vy, gr.vz};
+    v.x = pos[ax.k[0]];
+    v.y = pos[ax.k[1]];
+    v.z = pos[ax.k[2]];
+    v.vx = vel[ax.k[0]];
+    v.vy = vel[ax.k[1]];
+    v.vz = vel[ax.k[2]];
+    return v;
+}
+
+// shared body of csph_rates_vjp / csph_step_vjp (t: the time of the rates)
+static csph_status vjp_common(const csph_state *s_in, const csph_params *p, double t,
+                              const double *const a_in[5], const csph_grad *gnext_in, double dt,
+                              csph_grad gout_in, int accumulate, double *g_eos, void *ws,
+                              size_t ws_bytes, size_t *ws_needed, hipStream_t st) {
+    const csph_state *s = s_in;
     if (!state_ok(s) || s->n >= INT32_MAX) return fail(CSPH_EINVAL, "bad state");
     if (s->n >= kMaxPairN) return fail(CSPH_EINVAL, "n >= 2^27 particles");
     csph_status r = check_params(p, false, nullptr);
@@ -1190,7 +1203,28 @@ static csph_status vjp_common(const csph_state *s, const csph_params *p, const d
     r = check_vjp_params(p);
     if (r) return r;
     int64_t n = s->n;
-    if (n > 0 && !grad_ok(gout)) return fail(CSPH_EINVAL, "gradient outputs must not be NULL");
+    if (n > 0 && !grad_ok(gout_in)) return fail(CSPH_EINVAL, "gradient outputs must not be NULL");
+    if (!std::isfinite(t)) return fail(CSPH_EINVAL, "t not finite");
+    // the kernels' axes: the state, the rate cotangents and the gradients swapped alike
+    const Axes ax = kernel_axes(p);
+    const csph_state sv = kernel_view(*s_in, ax);
+    s = &sv;
+    const csph_grad gout = kernel_view(gout_in, ax);
+    csph_grad gnv;
+    const csph_grad *gnext = nullptr;
+    if (gnext_in) {
+        gnv = kernel_view(*gnext_in, ax);
+        gnext = &gnv;
+    }
+    const double *a[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    if (a_in) {
+        const double *const av[3] = {a_in[1], a_in[2], a_in[3]};
+        a[0] = a_in[0];
+        a[1] = av[ax.k[0]];
+        a[2] = av[ax.k[1]];
+        a[3] = av[ax.k[2]];
+        a[4] = a_in[4];
+    }
     csph_grid g;
     double dmax, ymin;
     r = make_grid(s->x, s->y, s->z, nullptr, n, p, ws, ws_bytes, st, &g, &dmax, &ymin, true);
@@ -1210,27 +1244,42 @@ static csph_status vjp_common(const csph_state *s, const csph_params *p, const d
     double *go[8] = {gout.x, gout.y, gout.z, gout.vx, gout.vy, gout.vz, gout.rho, gout.E};
     const double *gn[8];
     if (gnext) {
-        const double *t[8] = {gnext->x, gnext->y, gnext->z, gnext->vx, gnext->vy, gnext->vz,
-                              gnext->rho, gnext->E};
-        for (int k = 0; k < 8; ++k) gn[k] = t[k];
+        const double *tn[8] = {gnext->x, gnext->y, gnext->z, gnext->vx, gnext->vy, gnext->vz,
+                               gnext->rho, gnext->E};
+        for (int k = 0; k < 8; ++k) gn[k] = tn[k];
     }
+    const bool wall = p->wall != 0;
+    if (wall && gnext) {
+        // the step's reflections, found again from the FP64 rates at t; the cotangents of the
+        // pre-reflection y and v_y go to two arrays the adjoint leaves unused otherwise (it
+        // packs no smoothing lengths or ids)
+        CSPH_HIP(launch_fill_u64(w.dtmin, 0x7ff0000000000000ull, 2, st));
+        CSPH_HIP(launch_rates(n, 0, gd, pc, w, w.srt, nullptr, nullptr, t, 0, st));
+        double *gy = w.srt_d, *gvy = (double *)w.srt_id;
+        const double yw1 = p->wall_x0 + p->wall_v * (t + dt);
+        CSPH_HIP(launch_vjp_reflect(n, w.perm, w.srt[1], w.srt[4], w.rate[2], dt, yw1, p->wall_v,
+                                    gn[1], gn[4], gn[7], gy, gvy, st));
+        gn[1] = gy;
+        gn[4] = gvy;
+    }
+    const double yw = wall ? p->wall_x0 + p->wall_v * t : 0.0;
     CSPH_HIP(launch_vjp(n, w.perm, w.cs, gd, pc, eos, w, w.srt, w.srt_mat, a, go,
-                        gnext ? gn : nullptr, dt, accumulate, g_eos, st));
+                        gnext ? gn : nullptr, dt, accumulate, g_eos, wall, yw, p->wall_v, st));
     return CSPH_OK;
 }
 
-csph_status csph_rates_vjp(const csph_state *s, const csph_params *p, csph_rates_out a,
-                           csph_grad g_state, double *g_eos, void *ws, size_t ws_bytes,
-                           size_t *ws_needed, csph_stream stream) {
+csph_status csph_rates_vjp(const csph_state *s, const csph_params *p, double t,
+                           csph_rates_out a, csph_grad g_state, double *g_eos, void *ws,
+                           size_t ws_bytes, size_t *ws_needed, csph_stream stream) {
     g_err[0] = 0;
     if (s && s->n > 0 && (!a.drho || !a.dvx || !a.dvy || !a.dvz || !a.dE))
         return fail(CSPH_EINVAL, "rate cotangents must not be NULL");
     const double *ai[5] = {a.drho, a.dvx, a.dvy, a.dvz, a.dE};
-    return vjp_common(s, p, ai, nullptr, 0.0, g_state, 1, g_eos, ws, ws_bytes, ws_needed,
+    return vjp_common(s, p, t, ai, nullptr, 0.0, g_state, 1, g_eos, ws, ws_bytes, ws_needed,
                       (hipStream_t)stream);
 }
 
-csph_status csph_step_vjp(const csph_state *s_n, const csph_params *p, double dt,
+csph_status csph_step_vjp(const csph_state *s_n, const csph_params *p, double t, double dt,
                           csph_grad g_next, csph_grad g_prev, double *g_eos, void *ws,
                           size_t ws_bytes, size_t *ws_needed, csph_stream stream) {
     g_err[0] = 0;
@@ -1238,8 +1287,8 @@ csph_status csph_step_vjp(const csph_state *s_n, const csph_params *p, double dt
     if (s_n && s_n->n > 0 && !grad_ok(g_next)) return fail(CSPH_EINVAL, "g_next has NULL arrays");
     if (p && p->integrator != CSPH_INT_EULER)
         return fail(CSPH_EINVAL, "the step's adjoint is that of the Euler step only");
-    return vjp_common(s_n, p, nullptr, &g_next, dt, g_prev, 0, g_eos, ws, ws_bytes, ws_needed,
-                      (hipStream_t)stream);
+    return vjp_common(s_n, p, t, nullptr, &g_next, dt, g_prev, 0, g_eos, ws, ws_bytes,
+                      ws_needed, (hipStream_t)stream);
 }
 
 csph_status csph_init_energy_vjp(const double *rho, const double *pres, const double *vx,

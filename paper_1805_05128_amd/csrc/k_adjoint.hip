@@ -11,6 +11,15 @@
 // j in N(i) <=> i in N(j) for a fixed support, dJ/dq_i = sum_{j in N(i)}
 // dPhi_ij/dq_i: every particle gathers its own gradient over its own
 // neighbours, no atomics, fixed summation order.
+//
+// With the piston (sec. 7.1), a mirror pair (i, image of j) adds to J only i's side:
+// Phi^m_ij = W'_ij V_j (b_rho,i (v_L - v*) + P* b_v,i.e + b_E,i P* v*), the image of j at
+// (x_j, 2 y_w - y_j, z_j) with normal velocity 2 v_w - v_y,j (kernels' axes: the wall is normal
+// to y).  Reflection is an isometry and an involution, so i's image lies within the support
+// of j exactly when j's image lies within that of i: the walk around i's own image finds
+// both the pairs (i, image of j), differentiated in q_i directly, and the pairs (j, image of
+// i), differentiated in the image's q and mapped back (y and v_y change sign).  Each of the
+// two is a member under the forward pass's own rounding of its offset.
 #include "csph_internal.h"
 #include "stencil.h"
 
@@ -25,6 +34,11 @@ struct VjpIn {
     const double *rho, *E, *m;  // sorted state
     const int32_t *mat;
     const double *a[5]; // rate cotangents (cell order): rho vx vy vz E
+};
+
+// The piston at the time of the rates: position along the kernels' y, twice its velocity.
+struct VjpWall {
+    double yw, vw2;
 };
 
 struct VjpOut {
@@ -152,11 +166,14 @@ __device__ __forceinline__ void vjp_pair(bool use, double dx, double dy, double 
 // The stencil walk of the FP64 rate kernel (lock-step rows clipped to the
 // support chord, partners queued per lane in LDS, drained with all lanes
 // busy); partners are j != i with 0 < r_ij^2 < H^2 in FP64 without
-// contraction, as in the forward pass.
+// contraction, as in the forward pass.  WALL: a second walk, around i's
+// mirror image, for the lanes within the wall's band.
+template <bool WALL>
 __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
                                                   const int32_t *__restrict__ perm,
                                                   const int32_t *__restrict__ cs, GridDev g,
-                                                  PairConst pc, EosDev eos, int n_eos) {
+                                                  PairConst pc, EosDev eos, int n_eos,
+                                                  VjpWall wl) {
     __shared__ int qj[kQ][kBlock];
     const int tid = threadIdx.x;
     const int64_t blk = xcd_block<64>(blockIdx.x, gridDim.x);
@@ -177,53 +194,103 @@ __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
     const Stencil t = make_stencil(g, ai.x, ai.y, ai.z, pc.H);
     const double invH = pc.invH, dwc = pc.dwc, H2 = pc.H2;
     const int self = (int)s;
-    VjpAcc acc;
+    // i's mirror image (its y, and its velocity record with the normal component mirrored),
+    // zero weights for the side of a pair that has no rate
+    const double yim = WALL ? 2.0 * wl.yw - ai.y : 0.0;
+    const double4 bim = make_double4(bi.x, wl.vw2 - bi.y, bi.z, bi.w);
+    const double4 d0 = make_double4(0.0, 0.0, 0.0, 0.0);
+    VjpAcc acc, accm;  // accm: the pairs (j, image of i), in the image's q
     int qw = 0, qr = 0;
-    auto drain = [&]() {
+    auto drain = [&](bool ghost) {
         const bool has = qr < qw;
         const int j = has ? qj[qr & (kQ - 1)][tid] : 0;
         qr += has ? 1 : 0;
         const double4 aj = ld(in.A, j), bj = ld(in.B, j), dj = ld(in.Dw, j);
         const double2 zj = ld(in.C, j);
         const double bEj = ld(in.Ew, j);
-        const double dx = aj.x - ai.x, dy = aj.y - ai.y, dz = aj.z - ai.z;
-        const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
-        vjp_pair(has, dx, dy, dz, r2, ai, bi, zi, di, bEi, aj, bj, zj, dj, bEj, invH, dwc, acc);
-    };
-    int oy = t.R, oz = -t.R - 1;
-    int k = 0, j0 = 0, len = 0, jlast = 0;
-    for (;;) {
-        if (__any(qw - qr > kQ - kU)) {
-            drain();
-            continue;
-        }
-        if (!__any(k < len)) {
-            if (++oy > t.R) {
-                oy = -t.R;
-                if (++oz > t.R) break;
-            }
-            const int zz = t.cz + oz;
-            const float gz = slab_gap(t.zc, zz);
-            row_range(cs, g, t, live, t.cy + oy, zz, gz * gz, j0, len);
-            jlast = len > 0 ? j0 + len - 1 : 0;
-            k = 0;
-            continue;
-        }
-        double4 aj[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) aj[u] = ld(in.A, min(j0 + k + u, jlast));
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int j = j0 + k + u;
-            const double dx = aj[u].x - ai.x, dy = aj[u].y - ai.y, dz = aj[u].z - ai.z;
+        const double dx = aj.x - ai.x, dz = aj.z - ai.z;
+        if (!ghost) {
+            const double dy = aj.y - ai.y;
             const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
-            const bool ok = (k + u < len) && j != self && r2 < H2 && r2 != 0.0;
-            qj[qw & (kQ - 1)][tid] = j;
-            qw += ok ? 1 : 0;
+            vjp_pair(has, dx, dy, dz, r2, ai, bi, zi, di, bEi, aj, bj, zj, dj, bEj, invH, dwc,
+                     acc);
+            return;
         }
-        k += kU;
+        // (i, image of j): offset (2 y_w - y_j) - y_i, as the forward pass forms it
+        const double dya = (2.0 * wl.yw - aj.y) - ai.y;
+        const double r2a = ((dx * dx) + (dya * dya)) + (dz * dz);
+        const double4 bjm = make_double4(bj.x, wl.vw2 - bj.y, bj.z, bj.w);
+        vjp_pair(has && r2a < H2 && r2a != 0.0, dx, dya, dz, r2a, ai, bi, zi, di, bEi, aj, bjm,
+                 zj, d0, 0.0, invH, dwc, acc);
+        // (j, image of i): j's forward offset (2 y_w - y_i) - y_j, negated exactly
+        const double dyb = aj.y - yim;
+        const double r2b = ((dx * dx) + (dyb * dyb)) + (dz * dz);
+        vjp_pair(has && r2b < H2 && r2b != 0.0, dx, dyb, dz, r2b, ai, bim, zi, d0, 0.0, aj, bj,
+                 zj, dj, bEj, invH, dwc, accm);
+    };
+    // one walk over stencil st (ghost: the stencil around i's mirror image, whose partners
+    // are tested as both kinds of mirror pair), every entry drained before it returns
+    auto walk = [&](const Stencil &st, bool ghost, bool on) {
+        int oy = st.R, oz = -st.R - 1;
+        int k = 0, j0 = 0, len = 0, jlast = 0;
+        for (;;) {
+            if (__any(qw - qr > kQ - kU)) {
+                drain(ghost);
+                continue;
+            }
+            if (!__any(k < len)) {
+                if (++oy > st.R) {
+                    oy = -st.R;
+                    if (++oz > st.R) break;
+                }
+                const int zz = st.cz + oz;
+                const float gz = slab_gap(st.zc, zz);
+                row_range(cs, g, st, on, st.cy + oy, zz, gz * gz, j0, len);
+                jlast = len > 0 ? j0 + len - 1 : 0;
+                k = 0;
+                continue;
+            }
+            double4 aj[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) aj[u] = ld(in.A, min(j0 + k + u, jlast));
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int j = j0 + k + u;
+                const double dx = aj[u].x - ai.x, dz = aj[u].z - ai.z;
+                bool ok;
+                if (!ghost) {
+                    const double dy = aj[u].y - ai.y;
+                    const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
+                    ok = (k + u < len) && j != self && r2 < H2 && r2 != 0.0;
+                } else {
+                    const double dya = (2.0 * wl.yw - aj[u].y) - ai.y, dyb = aj[u].y - yim;
+                    const double dxz = (dx * dx);
+                    const double r2a = (dxz + (dya * dya)) + (dz * dz);
+                    const double r2b = (dxz + (dyb * dyb)) + (dz * dz);
+                    ok = (k + u < len) && ((r2a < H2 && r2a != 0.0) || (r2b < H2 && r2b != 0.0));
+                }
+                qj[qw & (kQ - 1)][tid] = j;
+                qw += ok ? 1 : 0;
+            }
+            k += kU;
+        }
+        while (__any(qr < qw)) drain(ghost);
+    };
+    walk(t, false, live);
+    if (WALL) {
+        const bool near = live && mirror_band(g, ai.y, wl.yw, pc.H);
+        if (__any(near)) walk(image_stencil(g, t, yim), true, near);
+        // the image's q back to i's: y and v_y change sign, P, Z and V are i's own
+        acc.gr0 += accm.gr0;
+        acc.gr1 -= accm.gr1;
+        acc.gr2 += accm.gr2;
+        acc.gv0 += accm.gv0;
+        acc.gv1 -= accm.gv1;
+        acc.gv2 += accm.gv2;
+        acc.gP += accm.gP;
+        acc.gZ += accm.gZ;
+        acc.gV += accm.gV;
     }
-    while (__any(qr < qw)) drain();
     if (live) {
         double gr0 = acc.gr0, gr1 = acc.gr1, gr2 = acc.gr2, gv0 = acc.gv0, gv1 = acc.gv1,
                gv2 = acc.gv2, gP = acc.gP, gZ = acc.gZ, gV = acc.gV;
@@ -320,7 +387,7 @@ hipError_t launch_vjp(int64_t n, const int32_t *perm, const int32_t *cs, const G
                       double *const sorted[9], const int32_t *mat_sorted,
                       const double *const a_in[5], double *const gout[8],
                       const double *const gnext[8], double dt, int accumulate, double *g_eos,
-                      hipStream_t st) {
+                      int wall, double yw, double vw, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
     VjpOut o;
@@ -347,8 +414,45 @@ hipError_t launch_vjp(int64_t n, const int32_t *perm, const int32_t *cs, const G
     in.m = sorted[8];
     in.mat = mat_sorted;
     for (int k = 0; k < 5; ++k) in.a[k] = w.rate[k];
-    k_vjp64<<<nb, kBlock, 0, st>>>(n, in, o, perm, cs, g, pc, eos, eos.n);
+    const VjpWall wl{yw, 2.0 * vw};
+    if (wall)
+        k_vjp64<true><<<nb, kBlock, 0, st>>>(n, in, o, perm, cs, g, pc, eos, eos.n, wl);
+    else
+        k_vjp64<false><<<nb, kBlock, 0, st>>>(n, in, o, perm, cs, g, pc, eos, eos.n, wl);
     if (g_eos) k_eos_grad_final<<<1, kBlock, 0, st>>>(w.eos_part, (int64_t)nb, 2 * eos.n, g_eos);
+    return hipGetLastError();
+}
+
+// The step's reflection off the piston, transposed.  A particle whose new position y' =
+// y + dt (v_y + dt R_vy) lies behind the wall at the step's end, yw1, left the step with
+// y'' = 2 yw1 - y', v_y'' = 2 v_w - v_y', E'' = E' + ((v_y'')^2 - (v_y')^2)/2 = E' + 2 v_w^2
+// - 2 v_w v_y'; the cotangents of (y', v_y') follow from those of the step's output:
+// g_y' = -g_y'', g_vy' = -g_vy'' - 2 v_w g_E'' (g_E' = g_E'', the other fields unchanged).
+// Slot s in cell order (state and rates there, formed as the step forms them); the
+// cotangents in input order.
+__global__ __launch_bounds__(kBlock) void k_vjp_reflect(
+    int64_t n, const int32_t *__restrict__ perm, const double *__restrict__ y_s,
+    const double *__restrict__ vy_s, const double *__restrict__ dvy_s, double dt, double yw1,
+    double vw, const double *__restrict__ gy, const double *__restrict__ gvy,
+    const double *__restrict__ gE, double *__restrict__ gy_out, double *__restrict__ gvy_out) {
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    const int i = perm[s];
+    const double vy = vy_s[s] + dt * dvy_s[s];
+    const double y = y_s[s] + dt * vy;
+    const bool behind = y < yw1;
+    gy_out[i] = behind ? -gy[i] : gy[i];
+    gvy_out[i] = behind ? -gvy[i] - 2.0 * vw * gE[i] : gvy[i];
+}
+
+hipError_t launch_vjp_reflect(int64_t n, const int32_t *perm, const double *y_s,
+                              const double *vy_s, const double *dvy_s, double dt, double yw1,
+                              double vw, const double *gy, const double *gvy, const double *gE,
+                              double *gy_out, double *gvy_out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    k_vjp_reflect<<<nb, kBlock, 0, st>>>(n, perm, y_s, vy_s, dvy_s, dt, yw1, vw, gy, gvy, gE,
+                                         gy_out, gvy_out);
     return hipGetLastError();
 }
 

@@ -210,7 +210,7 @@ def test_periodic_params_checked_on_the_host():
                            dev(1 << 22, C.c_double), C.c_void_p(1 << 23), None, 0, None, None)
     assert st == N.CSPH_EINVAL and b"periodic" in L.csph_last_error()
     g = N.CsphGrad(*[dev((1 << 25) + 1024 * k, C.c_double) for k in range(8)])
-    st = L.csph_step_vjp(C.byref(a), C.byref(p), 0.1, g, g, None, None, 0, None, None)
+    st = L.csph_step_vjp(C.byref(a), C.byref(p), 0.0, 0.1, g, g, None, None, 0, None, None)
     assert st == N.CSPH_EINVAL and b"periodic" in L.csph_last_error()
 
 
@@ -231,7 +231,7 @@ def test_integrator_checked_on_the_host():
                            dev(1 << 22, C.c_double), C.c_void_p(1 << 23), None, 0, None, None)
     assert st == N.CSPH_EINVAL and b"Euler" in L.csph_last_error()
     g = N.CsphGrad(*[dev((1 << 25) + 1024 * k, C.c_double) for k in range(8)])
-    st = L.csph_step_vjp(C.byref(a), C.byref(p), 0.1, g, g, None, None, 0, None, None)
+    st = L.csph_step_vjp(C.byref(a), C.byref(p), 0.0, 0.1, g, g, None, None, 0, None, None)
     assert st == N.CSPH_EINVAL and b"Euler" in L.csph_last_error()
     assert P.workspace_size(1000, 100, P.Params(integrator="rk2")) > \
         P.workspace_size(1000, 100, P.Params()) + 1000 * 150

@@ -319,3 +319,169 @@ def test_rollout_adjoint_sod64_fd_32_directions():
     print("fd rel errors: max %.2e median %.2e; adjoint/forward %.2f" %
           (max(errs), float(np.median(errs)), info["backward_s"] / info["forward_s"]), flush=True)
     assert max(errs) <= 1e-4, errs
+
+
+def piston_system(n=8, seed=5):
+    """The block moving onto the piston (x_w = 0.2 + 0.4 t): at t = 0.3 the first layers have
+    mirror partners, and a step of 0.2 reflects some of the first layer."""
+    w = system(n=n, seed=seed)
+    w.vx = w.vx - 0.5
+    w.wall = (0.2, 0.4)
+    return w
+
+
+def _np_state(g, w):
+    s = {k: g[k].cpu().numpy() for k in F8}
+    s["m"] = w.m
+    s["mat"] = w.mat
+    return s
+
+
+def test_rates_vjp_with_the_piston_matches_autograd():
+    """Mirror partners: the GPU VJP of the rates at t against autograd of the FP64 reference
+    with the mirror pairs (j's image at 2 x_w - x_j, x-velocity 2 v_w - v_x,j)."""
+    w = piston_system()
+    t = 0.3
+    xw = w.wall[0] + w.wall[1] * t
+    params = P.Params.from_workload(w)
+    g = P.state_from_workload(w, params, DEV)
+    s = _np_state(g, w)
+    mir = T.mirror_pairs_of(s, w.kappa * w.h, xw)
+    assert len(mir[0]) > 100 and int((mir[0] == mir[1]).sum()) > 10  # self-images among them
+    rng = np.random.default_rng(21)
+    cot = {k: rng.standard_normal(w.n) for k in ("drho", "dvx", "dvy", "dvz", "dE")}
+    gs, ge = P.csph_rates_vjp(g, params, {k: torch.as_tensor(v, device=DEV) for k, v in cot.items()},
+                              t=t)
+    et, gg, pi = tparams(w, True)
+    st = {k: torch.as_tensor(s[k]).clone().requires_grad_(True) for k in F8}
+    out = T.rates_torch(st, torch.as_tensor(w.m), torch.as_tensor(w.mat).long(), et, gg, pi,
+                        T.pairs_of(O.cfg_for(w), s), w.kappa * w.h, mirror=mir,
+                        wall=(xw, w.wall[1]))
+    J = sum((o * torch.as_tensor(cot[k])).sum()
+            for o, k in zip(out, ("drho", "dvx", "dvy", "dvz", "dE")))
+    ref = torch.autograd.grad(J, [st[k] for k in F8] + [gg, pi])
+    for a, k in enumerate(F8):
+        e = relmax(gs[k].cpu().numpy(), ref[a].numpy())
+        assert e <= 1e-10, (k, e)
+    ge = ge.cpu().numpy()
+    assert relmax(ge[0::2], ref[8].numpy()) <= 1e-10
+    assert abs(ge[3] - float(ref[9][1])) <= 1e-10 * abs(float(ref[9][1]))
+
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_step_vjp_with_the_piston_matches_autograd_and_dot_product(seed):
+    """The step with mirror partners at x_w(t) and reflections off x_w(t + dt): the GPU VJP
+    against autograd of the FP64 reference (the branch taken at the base state), and the
+    dot-product test against the GPU's own forward step."""
+    w = piston_system(seed=seed)
+    t, dt = 0.3, 0.2
+    params = P.Params.from_workload(w, reorder=False)
+    g = P.state_from_workload(w, params, DEV)
+    s = _np_state(g, w)
+    replay = P.Params.from_workload(w, reorder=False, cfl=0.0)
+
+    def fwd(delta=None, eps=0.0):
+        tt = {k: g[k] + (eps * torch.as_tensor(delta[k], device=DEV) if delta else 0.0)
+              for k in F8}
+        tt["m"] = g["m"]
+        st2 = P.State(tt, g.mat)
+        P.csph_step(st2, replay, P.StepScalars(DEV, t0=t), s_out=st2, dt_in=dt)
+        return {k: st2[k].cpu().numpy() for k in F8}
+
+    base = fwd()
+    xw1 = w.wall[0] + w.wall[1] * (t + dt)
+    assert np.sum(base["vx"] > 0.3) > 3 and np.all(base["x"] >= xw1)  # reflections happened
+    rng = np.random.default_rng(seed + 30)
+    lam = {k: rng.standard_normal(w.n) for k in F8}
+    gn = {k: torch.as_tensor(v, device=DEV).clone() for k, v in lam.items()}
+    gp, ge = P.csph_step_vjp(g, params, dt, gn, g_prev={k: torch.empty_like(v) for k, v in gn.items()},
+                             t=t)
+    et, gg, pi = tparams(w, True)
+    st = {k: torch.as_tensor(s[k]).clone().requires_grad_(True) for k in F8}
+    mir = T.mirror_pairs_of(s, w.kappa * w.h, w.wall[0] + w.wall[1] * t)
+    out = T.step_torch(st, torch.as_tensor(w.m), torch.as_tensor(w.mat).long(), et, gg, pi,
+                       T.pairs_of(O.cfg_for(w), s), w.kappa * w.h, dt, mirror=mir, wall=w.wall,
+                       t=t)
+    for k in F8:  # the reference takes the GPU step's branches
+        assert np.abs(out[k].detach().numpy() - base[k]).max() <= 1e-12 * (1 + np.abs(base[k]).max()), k
+    J = sum((out[k] * torch.as_tensor(lam[k])).sum() for k in F8)
+    ref = torch.autograd.grad(J, [st[k] for k in F8] + [gg, pi])
+    for a, k in enumerate(F8):
+        assert relmax(gp[k].cpu().numpy(), ref[a].numpy()) <= 1e-10, k
+    ge = ge.cpu().numpy()
+    assert relmax(ge[0::2], ref[8].numpy()) <= 1e-10
+    d = {k: rng.standard_normal(w.n) for k in F8}
+    eps = 1e-6
+    fp, fm = fwd(d, eps), fwd(d, -eps)
+    jvp = sum(float(((fp[k] - fm[k]) / (2 * eps) * lam[k]).sum()) for k in F8)
+    vjp = sum(float((gp[k].cpu().numpy() * d[k]).sum()) for k in F8)
+    assert abs(jvp - vjp) <= 1e-7 * max(abs(vjp), 1.0), (jvp, vjp)
+
+
+def test_rollout_with_the_piston_matches_reference_and_fd():
+    """Porous 12^3 sample driven by the piston, 10 FP64 CFL steps from t0 = 0.05, checkpoint
+    every 4: d/d(v0, gamma) of the x-momentum of the particles beyond the middle against the
+    FP64 CPU reference (autograd over the same dt sequence, mirror pairs and reflections) and
+    central differences of the GPU forward."""
+    w = ci.config2(nside=12)
+    print(f"[case] piston rollout n={w.n}", flush=True)
+    params = P.Params.from_workload(w, cfl=0.3)
+    base = _base(w, params)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float64), device=DEV)
+    v0 = [t(w.vx).requires_grad_(True), t(w.vy).requires_grad_(True), t(w.vz).requires_grad_(True)]
+    gamma = torch.tensor([e[1] for e in w.eos], dtype=torch.float64, device=DEV,
+                         requires_grad=True)
+    nsteps, every, t0 = 10, 4, 0.05
+    info = {}
+    P.rollout(*v0, gamma, base, params, nsteps, every, info=info, t0=t0)
+    dts = info["dts"]
+    out = P.rollout(*v0, gamma, base, params, nsteps, every, dts=dts, t0=t0)
+    xmid = float(np.median(w.x))
+    mask = out["x"].detach() > xmid
+    J = _objective(out, mask, base["m"])
+    grads = torch.autograd.grad(J, v0 + [gamma])
+    # FP64 CPU reference over the same steps: mirror pairs at each step's start time
+    cfg = O.cfg_for(w)
+    et, gg, pi = tparams(w, True)
+    gg = gg.clone().detach().requires_grad_(True)
+    mat = torch.as_tensor(w.mat).long()
+    m = torch.as_tensor(w.m)
+    vr = [torch.as_tensor(a).clone().requires_grad_(True) for a in (w.vx, w.vy, w.vz)]
+    E0 = T.init_energy_torch(torch.as_tensor(w.rho), torch.as_tensor(w.p), *vr, mat, et, gg, pi)
+    st = {"x": torch.as_tensor(w.x), "y": torch.as_tensor(w.y), "z": torch.as_tensor(w.z),
+          "vx": vr[0], "vy": vr[1], "vz": vr[2], "rho": torch.as_tensor(w.rho), "E": E0}
+    H = w.kappa * w.h
+    tk = t0
+    nmir = 0
+    for k in range(nsteps):
+        sn = {kk: st[kk].detach().numpy() for kk in ("x", "y", "z")}
+        mir = T.mirror_pairs_of(sn, H, w.wall[0] + w.wall[1] * tk)
+        nmir += len(mir[0])
+        st = T.step_torch(st, m, mat, et, gg, pi, T.pairs_of(cfg, sn), H, dts[k], mirror=mir,
+                          wall=w.wall, t=tk)
+        tk = tk + dts[k]
+    assert nmir > 1000
+    mref = st["x"].detach() > xmid
+    assert torch.equal(mref, mask.cpu())
+    Jr = (st["vx"][mref] * m[mref]).sum()
+    ref = torch.autograd.grad(Jr, vr + [gg])
+    assert abs(float(J.detach()) - float(Jr.detach())) <= 1e-11 * abs(float(Jr.detach()))
+    for a in range(3):
+        assert relmax(grads[a].cpu().numpy(), ref[a].numpy()) <= 1e-9, a
+    assert relmax(grads[3].cpu().numpy(), ref[3].numpy()) <= 1e-9
+    rng = np.random.default_rng(13)
+    for trial in range(4):
+        d = [rng.standard_normal(w.n) for _ in range(3)]
+        dg = rng.standard_normal(len(w.eos))
+        eps = 1e-6
+
+        def Jat(sign):
+            vv = [v0[a].detach() + sign * eps * t(d[a]) for a in range(3)]
+            gm = gamma.detach() + sign * eps * t(dg)
+            o = P.rollout(*vv, gm, base, params, nsteps, every, dts=dts, t0=t0)
+            return float(_objective(o, mask, base["m"]))
+
+        fd = (Jat(1) - Jat(-1)) / (2 * eps)
+        pred = sum(float((grads[a].cpu().numpy() * d[a]).sum()) for a in range(3)) + \
+            float((grads[3].cpu().numpy() * dg).sum())
+        assert abs(fd - pred) <= 1e-4 * max(abs(pred), 1e-8), (trial, fd, pred)
