@@ -454,10 +454,12 @@ csph_status csph_init_energy(const double *rho, const double *pres, const double
                              const csph_params *p, double *E, csph_stream stream);
 
 /* Adjoint (vector-Jacobian products).  Fixed-h mode, open boundaries or the
- * piston, ideal and stiffened-gas materials (CSPH_EINVAL otherwise: pair-h mode,
- * periodic axes, Mie-Grueneisen materials); FP64 arithmetic in both precisions
- * (it differentiates the FP64 map).  A gradient struct holds 8 FP64 arrays in
- * the state's order. */
+ * piston, every material (CSPH_EINVAL otherwise: pair-h mode, periodic axes);
+ * FP64 arithmetic in both precisions (it differentiates the FP64 map).  A
+ * gradient struct holds 8 FP64 arrays in the state's order.  The EOS-parameter
+ * gradients are those of gamma and p_inf; for a Mie-Grueneisen material the
+ * gamma slot holds d/dGamma and the p_inf slot stays 0 (rho0, c_a and s_a are
+ * constants). */
 typedef struct {
     double *x, *y, *z, *vx, *vy, *vz, *rho, *E;
 } csph_grad;

@@ -7,8 +7,10 @@ SPH:Energy, acoustic pairwise Riemann solver, Wendland C2 kernel) so that
 GPU adjoint.  Pair lists come from the C oracle's brute-force neighbour
 sets; with the piston (the rigid wall of sec. 7.1) the mirror pairs come from
 a brute-force test of the reflected positions written as the oracle writes it,
-and the step reflects the particles that cross the plane.  The time step dt is
-an input (frozen), fixed-h mode only.
+and the step reflects the particles that cross the plane.  The materials are
+ideal gas, stiffened gas, or Mie-Grueneisen (eqs. mie_gruneisen_eos,
+mie_gruneisen_reference, with the sound speed the oracle derives from them).
+The time step dt is an input (frozen), fixed-h mode only.
 
 Only the tests may import this module.
 """
@@ -47,14 +49,49 @@ def mirror_pairs_of(s, H: float, xw: float) -> Tuple[torch.Tensor, torch.Tensor]
     return torch.as_tensor(i.astype(np.int64)), torch.as_tensor(j.astype(np.int64))
 
 
-def eos_torch(rho, E, vx, vy, vz, mat, eos_type: Sequence[int], gamma, pinf):
-    """P and c from e = E - |v|^2/2 (ideal or stiffened gas), per-material gamma/p_inf tensors."""
+def _materials(eos_type, mat):
+    """Per-particle type codes and Mie-Grueneisen constants (rho0, c_a, s_a).  ``eos_type``
+    holds, per material, its type code or its whole tuple (type, gamma, p_inf[, rho0, c_a,
+    s_a]); materials of other types take the harmless constants (1, 1, 0)."""
+    types, mg = [], []
+    for e in eos_type:
+        t = int(e[0]) if isinstance(e, (tuple, list)) else int(e)
+        types.append(t)
+        mg.append(tuple(float(v) for v in e[3:6]) if t == 2 else (1.0, 1.0, 0.0))
+    ty = torch.as_tensor(types, dtype=torch.int64)[mat]
+    k = torch.as_tensor(mg, dtype=torch.float64)[mat]
+    return ty, k[:, 0], k[:, 1], k[:, 2]
+
+
+def _mg_reference(rho, rho0, ca, sa):
+    """Reference curves of the linear u_s - u_p Hugoniot at x = rho0/rho: (P_r, e_r, D, x, eta)
+    with D = 1 - s_a (1 - x)."""
+    x = rho0 / rho
+    eta = 1.0 - x
+    D = 1.0 - sa * eta
+    D2 = D * D
+    return rho0 * ca * ca * eta / D2, 0.5 * ca * ca * eta * eta / D2, D, x, eta
+
+
+def eos_torch(rho, E, vx, vy, vz, mat, eos_type: Sequence, gamma, pinf):
+    """P and c from e = E - |v|^2/2, per-material gamma (Gamma) / p_inf tensors."""
     e = E - 0.5 * ((vx * vx + vy * vy) + vz * vz)
     g = gamma[mat]
     pi = pinf[mat]
-    stiff = torch.as_tensor([t == 1 for t in eos_type], dtype=torch.bool)[mat]
-    P = torch.where(stiff, (g - 1.0) * rho * e - g * pi, (g - 1.0) * rho * e)
-    c2 = torch.where(stiff, g * (P + pi) / rho, g * P / rho)
+    ty, rho0, ca, sa = _materials(eos_type, mat)
+    P = torch.where(ty == 1, (g - 1.0) * rho * e - g * pi, (g - 1.0) * rho * e)
+    c2 = torch.where(ty == 1, g * (P + pi) / rho, g * P / rho)
+    if bool((ty == 2).any()):
+        # P = P_r + Gamma rho (e - e_r); c^2 = (dP/drho)_e + (P/rho^2)(dP/de)_rho
+        Pr, er, D, x, eta = _mg_reference(rho, rho0, ca, sa)
+        D3 = D * D * D
+        Pm = Pr + g * rho * (e - er)
+        dPr = ca * ca * x * x * (1.0 + sa * eta) / D3
+        rder = ca * ca * eta * x / D3
+        c2m = dPr + g * (e - er) - g * rder + g * Pm / rho
+        c2m = torch.where(D > 0.0, c2m, torch.full_like(c2m, -1.0))
+        P = torch.where(ty == 2, Pm, P)
+        c2 = torch.where(ty == 2, c2m, c2)
     c = torch.sqrt(torch.clamp(c2, min=0.0))
     return P, c
 
@@ -62,8 +99,14 @@ def eos_torch(rho, E, vx, vy, vz, mat, eos_type: Sequence[int], gamma, pinf):
 def init_energy_torch(rho, p, vx, vy, vz, mat, eos_type, gamma, pinf):
     g = gamma[mat]
     pi = pinf[mat]
-    stiff = torch.as_tensor([t == 1 for t in eos_type], dtype=torch.bool)[mat]
-    e = torch.where(stiff, (p + g * pi) / ((g - 1.0) * rho), p / ((g - 1.0) * rho))
+    ty, rho0, ca, sa = _materials(eos_type, mat)
+    # the gas forms divide by gamma - 1: a Mie-Grueneisen particle (whose Gamma may be 1)
+    # evaluates them, unused, at gamma = 2, keeping their gradients finite
+    gg = torch.where(ty == 2, torch.full_like(g, 2.0), g)
+    e = torch.where(ty == 1, (p + gg * pi) / ((gg - 1.0) * rho), p / ((gg - 1.0) * rho))
+    if bool((ty == 2).any()):
+        Pr, er, _, _, _ = _mg_reference(rho, rho0, ca, sa)
+        e = torch.where(ty == 2, er + (p - Pr) / (g * rho), e)
     return e + 0.5 * ((vx * vx + vy * vy) + vz * vz)
 
 

@@ -32,7 +32,9 @@ def _clone_state(s: A.State) -> A.State:
 
 
 def _with_gamma(params: A.Params, gamma: List[float]) -> A.Params:
-    eos = [(t, float(g), pinf) for (t, _, pinf), g in zip(params.eos, gamma)]
+    """The run's parameters with each material's gamma (Grueneisen Gamma for a Mie-Grueneisen
+    material) replaced; its other constants kept."""
+    eos = [(e[0], float(g)) + tuple(e[2:]) for e, g in zip(params.eos, gamma)]
     return dataclasses.replace(params, eos=eos, reorder=False, precision="fp64")
 
 

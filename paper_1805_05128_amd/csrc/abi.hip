@@ -1166,9 +1166,6 @@ csph_status csph_init_energy(const double *rho, const double *pres, const double
 
 static csph_status check_vjp_params(const csph_params *p) {
     if (p->h_mode != CSPH_H_FIXED) return fail(CSPH_EINVAL, "the adjoint supports fixed-h mode only");
-    for (int k = 0; k < p->n_eos; ++k)
-        if (p->eos[k].type == CSPH_EOS_MIE_GRUNEISEN)
-            return fail(CSPH_EINVAL, "the adjoint supports ideal and stiffened gas only");
     if (p->periodic) return fail(CSPH_EINVAL, "the adjoint does not support periodic boundaries");
     return CSPH_OK;
 }
@@ -1302,9 +1299,6 @@ csph_status csph_init_energy_vjp(const double *rho, const double *pres, const do
         return fail(CSPH_EINVAL, "bad arguments");
     csph_status r = check_params(p, false, nullptr);
     if (r) return r;
-    for (int k = 0; k < p->n_eos; ++k)
-        if (p->eos[k].type == CSPH_EOS_MIE_GRUNEISEN)
-            return fail(CSPH_EINVAL, "the adjoint supports ideal and stiffened gas only");
     r = need_ws(ws_bytes, n, 1, ws_needed);
     if (r) return r;
     Ws w;

@@ -91,6 +91,46 @@ __global__ __launch_bounds__(kBlock) void k_vjp_weights(int64_t n,
     Ew[s] = k * aE;
 }
 
+// A value with its partial derivatives in (rho, e, Gamma): forward-mode differentiation of
+// the Mie-Grueneisen EOS, whose sound speed is too long an expression to differentiate by
+// hand reliably.
+struct Dual3 {
+    double v, dr, de, dg;
+};
+__device__ __forceinline__ Dual3 operator+(Dual3 a, Dual3 b) {
+    return {a.v + b.v, a.dr + b.dr, a.de + b.de, a.dg + b.dg};
+}
+__device__ __forceinline__ Dual3 operator-(Dual3 a, Dual3 b) {
+    return {a.v - b.v, a.dr - b.dr, a.de - b.de, a.dg - b.dg};
+}
+__device__ __forceinline__ Dual3 operator*(Dual3 a, Dual3 b) {
+    return {a.v * b.v, a.dr * b.v + a.v * b.dr, a.de * b.v + a.v * b.de, a.dg * b.v + a.v * b.dg};
+}
+__device__ __forceinline__ Dual3 operator/(Dual3 a, Dual3 b) {
+    const double q = a.v / b.v, ib = 1.0 / b.v;
+    return {q, (a.dr - q * b.dr) * ib, (a.de - q * b.de) * ib, (a.dg - q * b.dg) * ib};
+}
+__device__ __forceinline__ Dual3 cst(double c) { return {c, 0.0, 0.0, 0.0}; }
+
+// Mie-Grueneisen (eqs. mie_gruneisen_eos, mie_gruneisen_reference) at (rho, e) with Gamma,
+// each with its partials: x = rho0/rho, eta = 1 - x, D = 1 - s_a eta,
+// P_r = rho0 c_a^2 eta / D^2, e_r = c_a^2 eta^2 / (2 D^2), P = P_r + Gamma rho (e - e_r),
+// c^2 = c_a^2 x^2 (1 + s_a eta)/D^3 + Gamma (e - e_r) - Gamma c_a^2 eta x / D^3 + Gamma P / rho
+// (the forward pass's sound speed: (dP/drho)_e + (P/rho^2)(dP/de)_rho).
+__device__ __forceinline__ void mg_eos_dual(const EosDev &eos, int k, double rho_v, double e_v,
+                                            Dual3 &P, Dual3 &c2) {
+    const Dual3 rho{rho_v, 1.0, 0.0, 0.0}, e{e_v, 0.0, 1.0, 0.0}, g{eos.gamma[k], 0.0, 0.0, 1.0};
+    const double rho0 = eos.rho0[k], ca2 = eos.ca[k] * eos.ca[k], sa = eos.sa[k];
+    const Dual3 x = cst(rho0) / rho, eta = cst(1.0) - x;
+    const Dual3 D = cst(1.0) - cst(sa) * eta, D2 = D * D, D3 = D2 * D;
+    const Dual3 Pr = cst(rho0 * ca2) * eta / D2;
+    const Dual3 er = cst(0.5 * ca2) * eta * eta / D2;
+    P = Pr + g * rho * (e - er);
+    const Dual3 dPr = cst(ca2) * x * x * (cst(1.0) + cst(sa) * eta) / D3;
+    const Dual3 rder = cst(ca2) * eta * x / D3;
+    c2 = dPr + g * (e - er) - g * rder + g * P / rho;
+}
+
 // Sums a particle gathers over its partners.
 struct VjpAcc {
     double gr0 = 0, gr1 = 0, gr2 = 0, gv0 = 0, gv1 = 0, gv2 = 0, gP = 0, gZ = 0, gV = 0;
@@ -313,7 +353,14 @@ __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
         double gm = eos.gamma[mt], pinf = eos.pinf[mt];
         double e = E - 0.5 * ((bi.x * bi.x + bi.y * bi.y) + bi.z * bi.z);
         double ge;
-        if (eos.type[mt] == CSPH_EOS_STIFFENED) {
+        if (eos.type[mt] == CSPH_EOS_MIE_GRUNEISEN) {
+            // partial derivatives in (rho, e, Gamma) carried forward through the EOS
+            Dual3 P, c2;
+            mg_eos_dual(eos, mt, rho, e, P, c2);
+            ge = gP * P.de + gc2 * c2.de;
+            grho += gP * P.dr + gc2 * c2.dr;
+            ge_gamma = gP * P.dg + gc2 * c2.dg;
+        } else if (eos.type[mt] == CSPH_EOS_STIFFENED) {
             // P = (g-1) rho e - g pinf ;  c^2 = g (g-1) (e - pinf/rho)
             ge = gP * (gm - 1.0) * rho + gc2 * gm * (gm - 1.0);
             grho += gP * (gm - 1.0) * e + gc2 * gm * (gm - 1.0) * pinf / (rho * rho);
@@ -457,7 +504,8 @@ hipError_t launch_vjp_reflect(int64_t n, const int32_t *perm, const double *y_s,
 }
 
 // dE0/d(gamma, p_inf, v, rho) of E0 = e0(rho, p; gamma, p_inf) + |v|^2/2,
-// e0 = p/((g-1) rho) (ideal) or (p + g p_inf)/((g-1) rho) (stiffened).
+// e0 = p/((g-1) rho) (ideal), (p + g p_inf)/((g-1) rho) (stiffened), or
+// e_r + (p - P_r)/(Gamma rho) (Mie-Grueneisen: d/dGamma in the gamma slot).
 __global__ __launch_bounds__(kBlock) void k_init_energy_vjp(
     const double *__restrict__ rho, const double *__restrict__ pres, const double *__restrict__ vx,
     const double *__restrict__ vy, const double *__restrict__ vz, const int32_t *__restrict__ mat,
@@ -470,19 +518,33 @@ __global__ __launch_bounds__(kBlock) void k_init_energy_vjp(
         k = mat ? mat[i] : 0;
         if (k < 0 || k >= eos.n) k = 0;
         double g = eos.gamma[k], pinf = eos.pinf[k], r = rho[i], p = pres[i], a = gE[i];
-        double e0;
-        if (eos.type[k] == CSPH_EOS_STIFFENED) {
+        double e0, de0;  // e0 and de0/drho
+        if (eos.type[k] == CSPH_EOS_MIE_GRUNEISEN) {
+            // e0 = e_r + (p - P_r)/(Gamma rho), with its partials in (rho, Gamma)
+            const Dual3 rr{r, 1.0, 0.0, 0.0}, gd{g, 0.0, 0.0, 1.0};
+            const double rho0 = eos.rho0[k], ca2 = eos.ca[k] * eos.ca[k], sa = eos.sa[k];
+            const Dual3 x = cst(rho0) / rr, eta = cst(1.0) - x;
+            const Dual3 D = cst(1.0) - cst(sa) * eta, D2 = D * D;
+            const Dual3 Pr = cst(rho0 * ca2) * eta / D2;
+            const Dual3 er = cst(0.5 * ca2) * eta * eta / D2;
+            const Dual3 ed = er + (cst(p) - Pr) / (gd * rr);
+            e0 = ed.v;
+            de0 = ed.dr;
+            gg = a * ed.dg;
+        } else if (eos.type[k] == CSPH_EOS_STIFFENED) {
             e0 = (p + g * pinf) / ((g - 1.0) * r);
+            de0 = -e0 / r;
             gg = a * (pinf / ((g - 1.0) * r) - e0 / (g - 1.0));
             gp = a * (g / ((g - 1.0) * r));
         } else {
             e0 = p / ((g - 1.0) * r);
+            de0 = -e0 / r;
             gg = a * (-e0 / (g - 1.0));
         }
         if (g_vx) g_vx[i] += a * vx[i];
         if (g_vy) g_vy[i] += a * vy[i];
         if (g_vz) g_vz[i] += a * vz[i];
-        if (g_rho) g_rho[i] += a * (-e0 / r);
+        if (g_rho) g_rho[i] += a * de0;
     }
     __shared__ double sh[2 * CSPH_MAX_EOS][kBlock];
     for (int q = 0; q < 2 * eos.n; ++q) sh[q][threadIdx.x] = 0.0;

@@ -190,3 +190,118 @@ def test_step_with_the_piston_gradient_matches_oracle_finite_differences(seed):
 
         fd = (J_at(1) - J_at(-1)) / (2 * eps)
         assert abs(fd - pred) <= 1e-6 * max(abs(pred), 1.0), (trial, fd, pred)
+
+
+def mg_system(n=6, seed=7):
+    """An ideal gas and a Mie-Grueneisen solid (aluminium-like constants) side by side, the
+    solid compressed by 0-8 % or expanded by up to 3 % against rho0."""
+    w = system(n=n, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    solid = w.mat == 1
+    w.rho = np.where(solid, ci.MG_ALUMINIUM[3] * rng.uniform(0.97, 1.08, w.n), w.rho)
+    w.m = w.rho.copy()
+    w.eos = [(0, 1.4, 0.0), ci.MG_ALUMINIUM]
+    return w
+
+
+def _eos_shifted(eos, sign, eps, dg, dpi):
+    """The materials with gamma (Gamma) and p_inf moved along (dg, dpi); other constants kept."""
+    return [(e[0], e[1] + sign * eps * dg[k], e[2] + sign * eps * dpi[k]) + tuple(e[3:])
+            for k, e in enumerate(eos)]
+
+
+def test_torch_rates_with_mie_grueneisen_match_c_oracle():
+    w = mg_system()
+    cfg = O.cfg_for(w)
+    s = O.state_from(w, cfg)
+    P, c, bad = O.eos(cfg, s)
+    assert bad == 0 and np.all(c > 0.0)
+    ref = O.rates(cfg, s)
+    _, g, pi = tparams(w)
+    st = T.to_torch(s)
+    mat = torch.as_tensor(s["mat"]).long()
+    Pt, ct = T.eos_torch(st["rho"], st["E"], st["vx"], st["vy"], st["vz"], mat, list(w.eos), g,
+                         pi)
+    assert np.abs(Pt.numpy() - P).max() <= 1e-13 * np.abs(P).max()
+    assert np.abs(ct.numpy() - c).max() <= 1e-13 * np.abs(c).max()
+    out = T.rates_torch(st, torch.as_tensor(s["m"]), mat, list(w.eos), g, pi, T.pairs_of(cfg, s),
+                        w.kappa * w.h)
+    for k, v in zip(("drho", "dvx", "dvy", "dvz", "dE"), out):
+        scale = np.abs(ref[k]).max()
+        assert np.abs(v.numpy() - ref[k]).max() <= 1e-12 * scale, k
+
+
+@pytest.mark.parametrize("seed", [7, 8])
+def test_step_with_mie_grueneisen_gradient_matches_oracle_finite_differences(seed):
+    """Gradients through the Mie-Grueneisen pressure and sound speed (and Gamma) against
+    central differences of the C oracle's step."""
+    w = mg_system(seed=seed)
+    cfg = O.cfg_for(w, cfl=0.0)
+    s = O.state_from(w, cfg)
+    dt = 0.02
+    _, g, pi = tparams(w)
+    st = {k: v.clone().requires_grad_(True) for k, v in T.to_torch(s).items()}
+    g = g.clone().requires_grad_(True)
+    pi = pi.clone().requires_grad_(True)
+    m = torch.as_tensor(s["m"])
+    mat = torch.as_tensor(s["mat"]).long()
+    out = T.step_torch(st, m, mat, list(w.eos), g, pi, T.pairs_of(cfg, s), w.kappa * w.h, dt)
+    rng = np.random.default_rng(seed + 40)
+    lam = {k: rng.standard_normal(w.n) for k in F8}
+    J = sum((out[k] * torch.as_tensor(lam[k])).sum() for k in F8)
+    grads = torch.autograd.grad(J, [st[k] for k in F8] + [g, pi])
+    assert float(grads[9][1]) == 0.0  # the solid has no p_inf
+    for trial in range(3):
+        d = {k: rng.standard_normal(w.n) for k in F8}
+        dg = rng.standard_normal(len(w.eos))
+        dpi = np.zeros(len(w.eos))
+        pred = sum(float((grads[a].numpy() * d[k]).sum()) for a, k in enumerate(F8))
+        pred += float((grads[8].numpy() * dg).sum())
+        eps = 1e-6
+
+        def J_at(sign):
+            s2 = {k: (s[k] + sign * eps * d[k]) if k in d else s[k] for k in s}
+            c2 = O.make_cfg(_eos_shifted(w.eos, sign, eps, dg, dpi), h=w.h, kappa=w.kappa,
+                            cfl=0.0)
+            s1, _, _, _ = O.step(c2, s2, 0.0, dt_in=dt)
+            return sum(float((s1[k] * lam[k]).sum()) for k in F8)
+
+        fd = (J_at(1) - J_at(-1)) / (2 * eps)
+        assert abs(fd - pred) <= 1e-6 * max(abs(pred), 1.0), (trial, fd, pred)
+
+
+def test_init_energy_with_mie_grueneisen_matches_oracle():
+    """E0 of the solid from (rho, p): value against the C oracle, and d/d(rho, Gamma) against
+    central differences of it."""
+    w = mg_system(seed=9)
+    cfg = O.cfg_for(w)
+    E_ref = O.init_energy(cfg, w.rho, w.p, w.vx, w.vy, w.vz, w.mat)
+    _, g, pi = tparams(w)
+    g = g.clone().requires_grad_(True)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float64))
+    rho = t(w.rho).clone().requires_grad_(True)
+    mat = torch.as_tensor(w.mat).long()
+    E = T.init_energy_torch(rho, t(w.p), t(w.vx), t(w.vy), t(w.vz), mat, list(w.eos), g, pi)
+    assert np.abs(E.detach().numpy() - E_ref).max() <= 1e-13 * np.abs(E_ref).max()
+    lam = np.random.default_rng(3).standard_normal(w.n)
+    grho, gg = torch.autograd.grad((E * t(lam)).sum(), [rho, g])
+    eps = 1e-7
+    dr = np.random.default_rng(4).standard_normal(w.n)
+    for k in range(len(w.eos)):
+        def Jg(sign):
+            eos2 = [list(e) for e in w.eos]
+            eos2[k][1] += sign * eps
+            E2 = O.init_energy(O.make_cfg([tuple(e) for e in eos2]), w.rho, w.p, w.vx, w.vy,
+                               w.vz, w.mat)
+            return float((E2 * lam).sum())
+
+        fd = (Jg(1) - Jg(-1)) / (2 * eps)
+        assert abs(fd - float(gg[k])) <= 1e-6 * max(1.0, abs(fd)), k
+
+    def Jr(sign):
+        E2 = O.init_energy(cfg, w.rho + sign * eps * dr, w.p, w.vx, w.vy, w.vz, w.mat)
+        return float((E2 * lam).sum())
+
+    fd = (Jr(1) - Jr(-1)) / (2 * eps)
+    pred = float((grho.numpy() * dr).sum())
+    assert abs(fd - pred) <= 1e-6 * max(1.0, abs(pred))

@@ -485,3 +485,139 @@ def test_rollout_with_the_piston_matches_reference_and_fd():
         pred = sum(float((grads[a].cpu().numpy() * d[a]).sum()) for a in range(3)) + \
             float((grads[3].cpu().numpy() * dg).sum())
         assert abs(fd - pred) <= 1e-4 * max(abs(pred), 1e-8), (trial, fd, pred)
+
+
+def mg_system(n=8, seed=7):
+    """An ideal gas and a Mie-Grueneisen solid (aluminium-like constants) side by side, the
+    solid compressed by 0-8 % or expanded by up to 3 % against rho0."""
+    w = system(n=n, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    solid = w.mat == 1
+    w.rho = np.where(solid, ci.MG_ALUMINIUM[3] * rng.uniform(0.97, 1.08, w.n), w.rho)
+    w.m = w.rho.copy()
+    w.eos = [(0, 1.4, 0.0), ci.MG_ALUMINIUM]
+    return w
+
+
+def test_rates_and_step_vjp_with_mie_grueneisen_match_autograd():
+    """The EOS chain through the Mie-Grueneisen pressure and sound speed (forward-mode partials
+    on the GPU) against autograd of the FP64 reference; d/dGamma in the gamma slot, 0 in the
+    p_inf slot of the solid."""
+    w = mg_system()
+    params = P.Params.from_workload(w, reorder=False)
+    g = P.state_from_workload(w, params, DEV)
+    s = _np_state(g, w)
+    et = list(w.eos)
+    rng = np.random.default_rng(22)
+    cot = {k: rng.standard_normal(w.n) for k in ("drho", "dvx", "dvy", "dvz", "dE")}
+    gs, ge = P.csph_rates_vjp(g, params, {k: torch.as_tensor(v, device=DEV) for k, v in cot.items()})
+    _, gg, pi = tparams(w, True)
+    st = {k: torch.as_tensor(s[k]).clone().requires_grad_(True) for k in F8}
+    pairs = T.pairs_of(O.cfg_for(w), s)
+    out = T.rates_torch(st, torch.as_tensor(w.m), torch.as_tensor(w.mat).long(), et, gg, pi,
+                        pairs, w.kappa * w.h)
+    J = sum((o * torch.as_tensor(cot[k])).sum()
+            for o, k in zip(out, ("drho", "dvx", "dvy", "dvz", "dE")))
+    ref = torch.autograd.grad(J, [st[k] for k in F8] + [gg])
+    for a, k in enumerate(F8):
+        assert relmax(gs[k].cpu().numpy(), ref[a].numpy()) <= 1e-10, k
+    ge = ge.cpu().numpy()
+    assert relmax(ge[0::2], ref[8].numpy()) <= 1e-10
+    assert ge[3] == 0.0
+    dt = 0.02
+    lam = {k: rng.standard_normal(w.n) for k in F8}
+    gn = {k: torch.as_tensor(v, device=DEV).clone() for k, v in lam.items()}
+    gp, ge = P.csph_step_vjp(g, params, dt, gn, g_prev={k: torch.empty_like(v) for k, v in gn.items()})
+    st = {k: torch.as_tensor(s[k]).clone().requires_grad_(True) for k in F8}
+    out = T.step_torch(st, torch.as_tensor(w.m), torch.as_tensor(w.mat).long(), et, gg, pi,
+                       pairs, w.kappa * w.h, dt)
+    J = sum((out[k] * torch.as_tensor(lam[k])).sum() for k in F8)
+    ref = torch.autograd.grad(J, [st[k] for k in F8] + [gg])
+    for a, k in enumerate(F8):
+        assert relmax(gp[k].cpu().numpy(), ref[a].numpy()) <= 1e-10, k
+    assert relmax(ge.cpu().numpy()[0::2], ref[8].numpy()) <= 1e-10
+
+
+def test_init_energy_vjp_with_mie_grueneisen_matches_autograd():
+    w = mg_system(seed=9)
+    w.p = np.where(w.mat == 1, np.random.default_rng(9).uniform(-0.5, 3.0, w.n), w.p)
+    params = P.Params.from_workload(w)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float64), device=DEV)
+    gE = np.random.default_rng(10).standard_normal(w.n)
+    gv = [torch.zeros(w.n, dtype=torch.float64, device=DEV) for _ in range(3)]
+    grho = torch.zeros(w.n, dtype=torch.float64, device=DEV)
+    geos = torch.zeros(4, dtype=torch.float64, device=DEV)
+    P.csph_init_energy_vjp(t(w.rho), t(w.p), t(w.vx), t(w.vy), t(w.vz),
+                           torch.as_tensor(w.mat, device=DEV), params, t(gE), g_v=gv, g_rho=grho,
+                           g_eos=geos)
+    _, gg, pi = tparams(w, True)
+    vx = torch.as_tensor(w.vx).clone().requires_grad_(True)
+    rho = torch.as_tensor(w.rho).clone().requires_grad_(True)
+    E = T.init_energy_torch(rho, torch.as_tensor(w.p), vx, torch.as_tensor(w.vy),
+                            torch.as_tensor(w.vz), torch.as_tensor(w.mat).long(), list(w.eos),
+                            gg, pi)
+    ref = torch.autograd.grad((E * torch.as_tensor(gE)).sum(), [vx, rho, gg])
+    assert relmax(gv[0].cpu().numpy(), ref[0].numpy()) <= 1e-13
+    assert relmax(grho.cpu().numpy(), ref[1].numpy()) <= 1e-12
+    assert relmax(geos.cpu().numpy()[0::2], ref[2].numpy()) <= 1e-12
+    assert geos.cpu().numpy()[3] == 0.0
+
+
+def test_rollout_plate_impact_mie_grueneisen_reference_and_fd():
+    """Aluminium plate onto lead (8 x 8 x 4 lattices each, Mie-Grueneisen), 12 FP64 CFL steps,
+    checkpoint every 5: d/d(v0, Gamma) of the z-momentum of the aluminium against the FP64 CPU
+    reference (autograd over the same dt sequence) and central differences of the GPU
+    forward."""
+    w = ci.mg_plates(8, 8, 4, gap=2.0, v_impact=0.5, seed=3)
+    print(f"[case] mg plates rollout n={w.n}", flush=True)
+    params = P.Params.from_workload(w, cfl=0.3)
+    base = _base(w, params)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float64), device=DEV)
+    v0 = [t(w.vx).requires_grad_(True), t(w.vy).requires_grad_(True), t(w.vz).requires_grad_(True)]
+    gamma = torch.tensor([e[1] for e in w.eos], dtype=torch.float64, device=DEV,
+                         requires_grad=True)
+    nsteps, every = 12, 5
+    info = {}
+    P.rollout(*v0, gamma, base, params, nsteps, every, info=info)
+    dts = info["dts"]
+    out = P.rollout(*v0, gamma, base, params, nsteps, every, dts=dts)
+    mask = torch.as_tensor(w.mat == 1, device=DEV)
+    J = (out["vz"][mask] * base["m"][mask]).sum()
+    grads = torch.autograd.grad(J, v0 + [gamma])
+    cfg = O.cfg_for(w)
+    _, gg, pi = tparams(w, True)
+    gg = gg.clone().detach().requires_grad_(True)
+    mat = torch.as_tensor(w.mat).long()
+    m = torch.as_tensor(w.m)
+    vr = [torch.as_tensor(a).clone().requires_grad_(True) for a in (w.vx, w.vy, w.vz)]
+    E0 = T.init_energy_torch(torch.as_tensor(w.rho), torch.as_tensor(w.p), *vr, mat,
+                             list(w.eos), gg, pi)
+    st = {"x": torch.as_tensor(w.x), "y": torch.as_tensor(w.y), "z": torch.as_tensor(w.z),
+          "vx": vr[0], "vy": vr[1], "vz": vr[2], "rho": torch.as_tensor(w.rho), "E": E0}
+    for k in range(nsteps):
+        pairs = T.pairs_of(cfg, {kk: st[kk].detach().numpy() for kk in ("x", "y", "z")})
+        st = T.step_torch(st, m, mat, list(w.eos), gg, pi, pairs, w.kappa * w.h, dts[k])
+    mref = torch.as_tensor(w.mat == 1)
+    Jr = (st["vz"][mref] * m[mref]).sum()
+    ref = torch.autograd.grad(Jr, vr + [gg])
+    assert abs(float(J.detach()) - float(Jr.detach())) <= 1e-11 * abs(float(Jr.detach()))
+    for a in range(3):
+        assert relmax(grads[a].cpu().numpy(), ref[a].numpy()) <= 1e-9, a
+    assert relmax(grads[3].cpu().numpy(), ref[3].numpy()) <= 1e-9
+    assert float(np.abs(ref[3].numpy()).min()) > 0.0  # both Gammas matter
+    rng = np.random.default_rng(17)
+    for trial in range(4):
+        d = [rng.standard_normal(w.n) for _ in range(3)]
+        dg = rng.standard_normal(len(w.eos))
+        eps = 1e-6
+
+        def Jat(sign):
+            vv = [v0[a].detach() + sign * eps * t(d[a]) for a in range(3)]
+            gm = gamma.detach() + sign * eps * t(dg)
+            o = P.rollout(*vv, gm, base, params, nsteps, every, dts=dts)
+            return float((o["vz"][mask] * base["m"][mask]).sum())
+
+        fd = (Jat(1) - Jat(-1)) / (2 * eps)
+        pred = sum(float((grads[a].cpu().numpy() * d[a]).sum()) for a in range(3)) + \
+            float((grads[3].cpu().numpy() * dg).sum())
+        assert abs(fd - pred) <= 1e-4 * max(abs(pred), 1e-8), (trial, fd, pred)
