@@ -27,26 +27,49 @@ import oracle as O
 FIELDS8 = ("x", "y", "z", "vx", "vy", "vz", "rho", "E")
 
 
-def pairs_of(cfg, s) -> Tuple[torch.Tensor, torch.Tensor]:
-    """Directed pair list (i, j), j in N(i), from the oracle's neighbour sets."""
+def pairs_of(cfg, s):
+    """Directed pair list (i, j), j in N(i), from the oracle's neighbour sets.  With periodic
+    axes, (i, j, shift): shift[p, a] = k_a L_a of the image through which j is i's partner (the
+    offset is (x_j - x_i) - k L, as the oracle forms it); with each period above twice the
+    support that image is the one nearest i, k_a = round((x_j - x_i) / L_a)."""
     off, idx = O.neighbors(cfg, np.ascontiguousarray(s["x"]), np.ascontiguousarray(s["y"]),
                            np.ascontiguousarray(s["z"]))
     i = np.repeat(np.arange(len(off) - 1), np.diff(off))
-    return torch.as_tensor(i, dtype=torch.long), torch.as_tensor(idx.astype(np.int64))
+    j = idx.astype(np.int64)
+    ti, tj = torch.as_tensor(i, dtype=torch.long), torch.as_tensor(j)
+    if not cfg.periodic:
+        return ti, tj
+    shift = np.zeros((len(i), 3))
+    for a, k in enumerate(("x", "y", "z")):
+        if (cfg.periodic >> a) & 1:
+            L = cfg.box_hi[a] - cfg.box_lo[a]
+            v = np.asarray(s[k], np.float64)
+            shift[:, a] = np.round((v[j] - v[i]) / L) * L
+    return ti, tj, torch.as_tensor(shift)
 
 
-def mirror_pairs_of(s, H: float, xw: float) -> Tuple[torch.Tensor, torch.Tensor]:
+def mirror_pairs_of(s, H: float, xw: float, box=None, periodic: int = 0):
     """Directed mirror pairs (i, j), j = i included: the reflected position of j,
     (2 xw - x_j, y_j, z_j), within the support of i; brute force over all j, the squared
-    distance formed as the oracle forms it (((dx dx) + (dy dy)) + dz dz, dx = xg - x_i)."""
+    distance formed as the oracle forms it (((dx dx) + (dy dy)) + dz dz, dx = xg - x_i).
+    With periodic axes y and z (the wall's axis x is never periodic), the image of the
+    reflected j nearest i, and (i, j, shift) as from ``pairs_of``."""
     x, y, z = (np.asarray(s[k], np.float64) for k in ("x", "y", "z"))
     xg = 2.0 * xw - x
     dx = xg[None, :] - x[:, None]
-    dy = y[None, :] - y[:, None]
-    dz = z[None, :] - z[:, None]
-    r2 = ((dx * dx) + (dy * dy)) + (dz * dz)
+    d = [dx, y[None, :] - y[:, None], z[None, :] - z[:, None]]
+    sh = [np.zeros_like(dx) for _ in range(3)]
+    for a in (1, 2):
+        if (periodic >> a) & 1:
+            L = box[1][a] - box[0][a]
+            sh[a] = np.round(d[a] / L) * L
+            d[a] = d[a] - sh[a]
+    r2 = ((d[0] * d[0]) + (d[1] * d[1])) + (d[2] * d[2])
     i, j = np.nonzero(r2 < H * H)
-    return torch.as_tensor(i.astype(np.int64)), torch.as_tensor(j.astype(np.int64))
+    ti, tj = torch.as_tensor(i.astype(np.int64)), torch.as_tensor(j.astype(np.int64))
+    if not periodic:
+        return ti, tj
+    return ti, tj, torch.as_tensor(np.stack([sh[a][i, j] for a in range(3)], axis=1))
 
 
 def _materials(eos_type, mat):
@@ -110,10 +133,13 @@ def init_energy_torch(rho, p, vx, vy, vz, mat, eos_type, gamma, pinf):
     return e + 0.5 * ((vx * vx + vy * vy) + vz * vz)
 
 
-def _pair_sums(x, y, z, vx, vy, vz, P, Z, V, i, j, xj, vxj, H: float):
+def _pair_sums(x, y, z, vx, vy, vz, P, Z, V, i, j, xj, vxj, H: float, shift=None):
     """Per-pair terms of i's sums for partners j whose position's x and velocity's x are
-    ``xj`` and ``vxj`` (the particle's own, or its mirror image's)."""
+    ``xj`` and ``vxj`` (the particle's own, or its mirror image's), through the periodic
+    images ``shift`` (k L per pair and axis) when given."""
     dx, dy, dz = xj - x[i], y[j] - y[i], z[j] - z[i]
+    if shift is not None:
+        dx, dy, dz = dx - shift[:, 0], dy - shift[:, 1], dz - shift[:, 2]
     r2 = (dx * dx + dy * dy) + dz * dz
     nz = r2 > 0
     r = torch.sqrt(torch.where(nz, r2, torch.ones_like(r2)))
@@ -145,14 +171,16 @@ def rates_torch(st: Dict[str, torch.Tensor], m, mat, eos_type, gamma, pinf, pair
     n = x.shape[0]
     z0 = torch.zeros(n, dtype=x.dtype)
     sums = [z0] * 5
-    i, j = pairs
-    for k, t in enumerate(_pair_sums(x, y, z, vx, vy, vz, P, Z, V, i, j, x[j], vx[j], H)):
+    i, j = pairs[0], pairs[1]
+    shift = pairs[2] if len(pairs) > 2 else None
+    for k, t in enumerate(_pair_sums(x, y, z, vx, vy, vz, P, Z, V, i, j, x[j], vx[j], H,
+                                     shift)):
         sums[k] = sums[k].index_add(0, i, t)
     if mirror is not None:
         xw, vw = wall
-        i, j = mirror
+        i, j = mirror[0], mirror[1]
         terms = _pair_sums(x, y, z, vx, vy, vz, P, Z, V, i, j, 2.0 * xw - x[j],
-                           2.0 * vw - vx[j], H)
+                           2.0 * vw - vx[j], H, mirror[2] if len(mirror) > 2 else None)
         for k, t in enumerate(terms):
             sums[k] = sums[k].index_add(0, i, t)
     s_rho, s_vx, s_vy, s_vz, s_E = sums
@@ -161,12 +189,13 @@ def rates_torch(st: Dict[str, torch.Tensor], m, mat, eos_type, gamma, pinf, pair
 
 
 def step_torch(st, m, mat, eos_type, gamma, pinf, pairs, H: float, dt: float, mirror=None,
-               wall=None, t: float = 0.0):
+               wall=None, t: float = 0.0, box=None, periodic: int = 0):
     """Symplectic Euler with frozen dt: v, E, rho += dt rates, then r += dt v_new.  With the
     piston wall = (x_w0, v_w): mirror pairs at x_w(t), and a particle whose new x lies behind
     x_w(t + dt) is reflected (x <- 2 x_w - x, v_x <- 2 v_w - v_x, E changed by the kinetic
     energy difference); which particles reflect is decided on the values (a fixed branch for
-    the gradient)."""
+    the gradient).  Periodic axes (bit mask, box = (lo, hi)): a new position at or above hi
+    moves down by the period, one below lo up by it, after the reflection."""
     w_now = None if wall is None else (wall[0] + wall[1] * t, wall[1])
     drho, dvx, dvy, dvz, dE = rates_torch(st, m, mat, eos_type, gamma, pinf, pairs, H,
                                           mirror=mirror, wall=w_now)
@@ -182,7 +211,15 @@ def step_torch(st, m, mat, eos_type, gamma, pinf, pairs, H: float, dt: float, mi
         E = torch.where(behind, E + 0.5 * ((vr * vr) - (vx * vx)), E)
         vx = torch.where(behind, vr, vx)
         x = torch.where(behind, 2.0 * xw - x, x)
-    return {"x": x, "y": st["y"] + dt * vy, "z": st["z"] + dt * vz,
+    pos = [x, st["y"] + dt * vy, st["z"] + dt * vz]
+    for a in range(3):
+        if (periodic >> a) & 1:
+            lo, hi = float(box[0][a]), float(box[1][a])
+            L = hi - lo
+            p = pos[a]
+            up, down = (p >= hi).detach(), (p < lo).detach()
+            pos[a] = torch.where(up, p - L, torch.where(down, p + L, p))
+    return {"x": pos[0], "y": pos[1], "z": pos[2],
             "vx": vx, "vy": vy, "vz": vz, "rho": st["rho"] + dt * drho, "E": E}
 
 
