@@ -453,8 +453,8 @@ csph_status csph_init_energy(const double *rho, const double *pres, const double
                              const double *vy, const double *vz, const int32_t *mat, int64_t n,
                              const csph_params *p, double *E, csph_stream stream);
 
-/* Adjoint (vector-Jacobian products).  Fixed-h mode, open boundaries or the
- * piston, every material (CSPH_EINVAL otherwise: pair-h mode, periodic axes);
+/* Adjoint (vector-Jacobian products).  Fixed-h mode (CSPH_EINVAL in pair-h
+ * mode), every boundary (open, the piston, periodic axes) and every material;
  * FP64 arithmetic in both precisions (it differentiates the FP64 map).  A
  * gradient struct holds 8 FP64 arrays in the state's order.  The EOS-parameter
  * gradients are those of gamma and p_inf; for a Mie-Grueneisen material the
@@ -470,10 +470,12 @@ typedef struct {
  * dJ/d gamma_k, g_eos[2k+1] += dJ/d p_inf_k (device, 2*n_eos doubles,
  * optional).  The rates' dependence on (rho, E, v) through the EOS is
  * included; masses, materials and the piston's motion are constants.
- * Gather form: it relies on j in N(i) <=> i in N(j), and with the piston on
- * j's mirror image lying within the support of i <=> i's within that of j
- * (sec. 7.1).  Where c = 0 the derivative of c with respect to c^2 is taken
- * as 0.  Synchronises once (mesh bounds). */
+ * Gather form: it relies on j in N(i) <=> i in N(j), with the piston on j's
+ * mirror image lying within the support of i <=> i's within that of j
+ * (sec. 7.1), and on periodic axes on j's image x_j - kL lying within the
+ * support of i <=> i's image x_i + kL within that of j.  Where c = 0 the
+ * derivative of c with respect to c^2 is taken as 0.  Synchronises once
+ * (mesh bounds). */
 csph_status csph_rates_vjp(const csph_state *s, const csph_params *p, double t,
                            csph_rates_out a, csph_grad g_state, double *g_eos, void *ws,
                            size_t ws_bytes, size_t *ws_needed, csph_stream stream);
@@ -486,7 +488,8 @@ csph_status csph_rates_vjp(const csph_state *s, const csph_params *p, double t,
  * With the piston, the particles the step reflected off the wall at t + dt
  * are found again from an FP64 evaluation of the rates at t (the step's own
  * test, x + dt (v_x + dt R_vx) < x_w(t + dt)), and the reflection's Jacobian is
- * applied to their cotangents; the branch itself is not differentiated. */
+ * applied to their cotangents; the branch itself is not differentiated.  The
+ * periodic wrap is a translation (identity Jacobian). */
 csph_status csph_step_vjp(const csph_state *s_n, const csph_params *p, double t, double dt,
                           csph_grad g_next, csph_grad g_prev, double *g_eos, void *ws,
                           size_t ws_bytes, size_t *ws_needed, csph_stream stream);

@@ -1166,7 +1166,6 @@ csph_status csph_init_energy(const double *rho, const double *pres, const double
 
 static csph_status check_vjp_params(const csph_params *p) {
     if (p->h_mode != CSPH_H_FIXED) return fail(CSPH_EINVAL, "the adjoint supports fixed-h mode only");
-    if (p->periodic) return fail(CSPH_EINVAL, "the adjoint does not support periodic boundaries");
     return CSPH_OK;
 }
 

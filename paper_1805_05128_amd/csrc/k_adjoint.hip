@@ -207,8 +207,12 @@ __device__ __forceinline__ void vjp_pair(bool use, double dx, double dy, double 
 // support chord, partners queued per lane in LDS, drained with all lanes
 // busy); partners are j != i with 0 < r_ij^2 < H^2 in FP64 without
 // contraction, as in the forward pass.  WALL: a second walk, around i's
-// mirror image, for the lanes within the wall's band.
-template <bool WALL>
+// mirror image, for the lanes within the wall's band.  PER: walks around the
+// periodic images i has (image_faces), with offsets (x_j - x_i) - k L formed
+// as the forward pass forms them; j is a partner of i through shift k exactly
+// when i is one of j through -k (the offset negates exactly), so the gather
+// stays complete.  With both, the mirror image's periodic images too.
+template <bool WALL, bool PER>
 __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
                                                   const int32_t *__restrict__ perm,
                                                   const int32_t *__restrict__ cs, GridDev g,
@@ -241,22 +245,29 @@ __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
     const double4 d0 = make_double4(0.0, 0.0, 0.0, 0.0);
     VjpAcc acc, accm;  // accm: the pairs (j, image of i), in the image's q
     int qw = 0, qr = 0;
-    auto drain = [&](bool ghost) {
+    // (sx, sy, sz): the walk's periodic shift k L (0 off the periodic walks)
+    auto drain = [&](bool ghost, double sx, double sy, double sz) {
         const bool has = qr < qw;
         const int j = has ? qj[qr & (kQ - 1)][tid] : 0;
         qr += has ? 1 : 0;
         const double4 aj = ld(in.A, j), bj = ld(in.B, j), dj = ld(in.Dw, j);
         const double2 zj = ld(in.C, j);
         const double bEj = ld(in.Ew, j);
-        const double dx = aj.x - ai.x, dz = aj.z - ai.z;
+        double dx = aj.x - ai.x, dz = aj.z - ai.z;
+        if (PER) {
+            dx = dx - sx;
+            dz = dz - sz;
+        }
         if (!ghost) {
-            const double dy = aj.y - ai.y;
+            double dy = aj.y - ai.y;
+            if (PER) dy = dy - sy;
             const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
             vjp_pair(has, dx, dy, dz, r2, ai, bi, zi, di, bEi, aj, bj, zj, dj, bEj, invH, dwc,
                      acc);
             return;
         }
-        // (i, image of j): offset (2 y_w - y_j) - y_i, as the forward pass forms it
+        // (i, image of j): offset (2 y_w - y_j) - y_i, as the forward pass forms it (the
+        // wall's axis y is never periodic: no shift along it)
         const double dya = (2.0 * wl.yw - aj.y) - ai.y;
         const double r2a = ((dx * dx) + (dya * dya)) + (dz * dz);
         const double4 bjm = make_double4(bj.x, wl.vw2 - bj.y, bj.z, bj.w);
@@ -269,13 +280,15 @@ __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
                  zj, dj, bEj, invH, dwc, accm);
     };
     // one walk over stencil st (ghost: the stencil around i's mirror image, whose partners
-    // are tested as both kinds of mirror pair), every entry drained before it returns
-    auto walk = [&](const Stencil &st, bool ghost, bool on) {
+    // are tested as both kinds of mirror pair; img: around a periodic image point, shift
+    // (sx, sy, sz)), every entry drained before it returns
+    auto walk = [&](const Stencil &st, bool ghost, bool img, bool on, double sx, double sy,
+                    double sz) {
         int oy = st.R, oz = -st.R - 1;
         int k = 0, j0 = 0, len = 0, jlast = 0;
         for (;;) {
             if (__any(qw - qr > kQ - kU)) {
-                drain(ghost);
+                drain(ghost, sx, sy, sz);
                 continue;
             }
             if (!__any(k < len)) {
@@ -296,12 +309,17 @@ __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 const int j = j0 + k + u;
-                const double dx = aj[u].x - ai.x, dz = aj[u].z - ai.z;
+                double dx = aj[u].x - ai.x, dz = aj[u].z - ai.z;
+                if (PER) {
+                    dx = dx - sx;
+                    dz = dz - sz;
+                }
                 bool ok;
                 if (!ghost) {
-                    const double dy = aj[u].y - ai.y;
+                    double dy = aj[u].y - ai.y;
+                    if (PER) dy = dy - sy;
                     const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
-                    ok = (k + u < len) && j != self && r2 < H2 && r2 != 0.0;
+                    ok = (k + u < len) && (img || j != self) && r2 < H2 && r2 != 0.0;
                 } else {
                     const double dya = (2.0 * wl.yw - aj[u].y) - ai.y, dyb = aj[u].y - yim;
                     const double dxz = (dx * dx);
@@ -314,12 +332,30 @@ __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
             }
             k += kU;
         }
-        while (__any(qr < qw)) drain(ghost);
+        while (__any(qr < qw)) drain(ghost, sx, sy, sz);
     };
-    walk(t, false, live);
+    // the walks around the periodic images of point (px, py, pz) (i, or its mirror image) for
+    // the lanes in `on`, stencil base st
+    const int nf = PER ? image_faces(pc, ai.x, ai.y, ai.z) : 0;
+    auto images = [&](const Stencil &base, bool ghost, bool on, double py) {
+        for (int m = 1; m < 8; ++m) {
+            const bool onm = on && (nf & m) == m;
+            if (!__any(onm)) continue;
+            const double sx = image_shift(pc, nf, m, 0), sy = image_shift(pc, nf, m, 1),
+                         sz = image_shift(pc, nf, m, 2);
+            const Stencil sm = shifted_stencil(g, base, m, ai.x + sx, py + sy, ai.z + sz);
+            walk(sm, ghost, true, onm, sx, sy, sz);
+        }
+    };
+    walk(t, false, false, live, 0.0, 0.0, 0.0);
+    if (PER) images(t, false, live, ai.y);
     if (WALL) {
         const bool near = live && mirror_band(g, ai.y, wl.yw, pc.H);
-        if (__any(near)) walk(image_stencil(g, t, yim), true, near);
+        if (__any(near)) {
+            const Stencil ti = image_stencil(g, t, yim);
+            walk(ti, true, false, near, 0.0, 0.0, 0.0);
+            if (PER) images(ti, true, near, yim);
+        }
         // the image's q back to i's: y and v_y change sign, P, Z and V are i's own
         acc.gr0 += accm.gr0;
         acc.gr1 -= accm.gr1;
@@ -462,10 +498,15 @@ hipError_t launch_vjp(int64_t n, const int32_t *perm, const int32_t *cs, const G
     in.mat = mat_sorted;
     for (int k = 0; k < 5; ++k) in.a[k] = w.rate[k];
     const VjpWall wl{yw, 2.0 * vw};
-    if (wall)
-        k_vjp64<true><<<nb, kBlock, 0, st>>>(n, in, o, perm, cs, g, pc, eos, eos.n, wl);
+    const bool per = pc.per != 0;
+    if (wall && per)
+        k_vjp64<true, true><<<nb, kBlock, 0, st>>>(n, in, o, perm, cs, g, pc, eos, eos.n, wl);
+    else if (wall)
+        k_vjp64<true, false><<<nb, kBlock, 0, st>>>(n, in, o, perm, cs, g, pc, eos, eos.n, wl);
+    else if (per)
+        k_vjp64<false, true><<<nb, kBlock, 0, st>>>(n, in, o, perm, cs, g, pc, eos, eos.n, wl);
     else
-        k_vjp64<false><<<nb, kBlock, 0, st>>>(n, in, o, perm, cs, g, pc, eos, eos.n, wl);
+        k_vjp64<false, false><<<nb, kBlock, 0, st>>>(n, in, o, perm, cs, g, pc, eos, eos.n, wl);
     if (g_eos) k_eos_grad_final<<<1, kBlock, 0, st>>>(w.eos_part, (int64_t)nb, 2 * eos.n, g_eos);
     return hipGetLastError();
 }

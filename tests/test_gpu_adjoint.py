@@ -621,3 +621,138 @@ def test_rollout_plate_impact_mie_grueneisen_reference_and_fd():
         pred = sum(float((grads[a].cpu().numpy() * d[a]).sum()) for a in range(3)) + \
             float((grads[3].cpu().numpy() * dg).sum())
         assert abs(fd - pred) <= 1e-4 * max(abs(pred), 1e-8), (trial, fd, pred)
+
+
+@pytest.mark.parametrize("periodic,wall", [(7, None), (5, None), (6, (0.2, 0.4))],
+                         ids=["xyz", "xz", "yz+piston"])
+def test_rates_and_step_vjp_periodic_match_autograd(periodic, wall):
+    """Image partners (and, with the piston on periodic sides, mirror partners through the
+    images): the GPU VJPs of the rates at t and of a step that carries particles through the
+    faces, against autograd of the FP64 reference, and the dot-product test against the GPU's
+    own forward step.  Periodic x with an open y hands the kernels the axes exchanged."""
+    from test_adjoint_ref import periodic_system
+    w = periodic_system(periodic, seed=12, wall=wall)
+    print(f"[case] periodic vjp {periodic} wall={wall} n={w.n}", flush=True)
+    t, dt = 0.3, 0.2
+    H = w.kappa * w.h
+    params = P.Params.from_workload(w, reorder=False)
+    g = P.state_from_workload(w, params, DEV)
+    s = _np_state(g, w)
+    cfg = O.cfg_for(w)
+    pairs = T.pairs_of(cfg, s)
+    mir, wt = None, None
+    if wall is not None:
+        mir = T.mirror_pairs_of(s, H, wall[0] + wall[1] * t, box=w.box, periodic=periodic)
+        wt = (wall[0] + wall[1] * t, wall[1])
+    et, gg, pi = tparams(w, True)
+    m, mat = torch.as_tensor(w.m), torch.as_tensor(w.mat).long()
+    rng = np.random.default_rng(periodic + 60)
+    cot = {k: rng.standard_normal(w.n) for k in ("drho", "dvx", "dvy", "dvz", "dE")}
+    gs, ge = P.csph_rates_vjp(g, params, {k: torch.as_tensor(v, device=DEV) for k, v in cot.items()},
+                              t=t)
+    st = {k: torch.as_tensor(s[k]).clone().requires_grad_(True) for k in F8}
+    out = T.rates_torch(st, m, mat, et, gg, pi, pairs, H, mirror=mir, wall=wt)
+    J = sum((o * torch.as_tensor(cot[k])).sum()
+            for o, k in zip(out, ("drho", "dvx", "dvy", "dvz", "dE")))
+    ref = torch.autograd.grad(J, [st[k] for k in F8] + [gg, pi])
+    for a, k in enumerate(F8):
+        assert relmax(gs[k].cpu().numpy(), ref[a].numpy()) <= 1e-10, ("rates", k)
+    assert relmax(ge.cpu().numpy()[0::2], ref[8].numpy()) <= 1e-10
+    # the step
+    replay = P.Params.from_workload(w, reorder=False, cfl=0.0)
+
+    def fwd(delta=None, eps=0.0):
+        tt = {k: g[k] + (eps * torch.as_tensor(delta[k], device=DEV) if delta else 0.0)
+              for k in F8}
+        tt["m"] = g["m"]
+        st2 = P.State(tt, g.mat)
+        P.csph_step(st2, replay, P.StepScalars(DEV, t0=t), s_out=st2, dt_in=dt)
+        return {k: st2[k].cpu().numpy() for k in F8}
+
+    base = fwd()
+    crossed = sum(int(np.sum(np.abs(base[k] - s[k]) > 4.0)) for a, k in enumerate("xyz")
+                  if (periodic >> a) & 1)
+    assert crossed > 3  # particles crossed a face
+    lam = {k: rng.standard_normal(w.n) for k in F8}
+    gn = {k: torch.as_tensor(v, device=DEV).clone() for k, v in lam.items()}
+    gp, ge = P.csph_step_vjp(g, params, dt, gn, g_prev={k: torch.empty_like(v) for k, v in gn.items()},
+                             t=t)
+    st = {k: torch.as_tensor(s[k]).clone().requires_grad_(True) for k in F8}
+    out = T.step_torch(st, m, mat, et, gg, pi, pairs, H, dt, mirror=mir, wall=wall, t=t,
+                       box=w.box, periodic=periodic)
+    for k in F8:
+        assert np.abs(out[k].detach().numpy() - base[k]).max() <= 1e-12 * (1 + np.abs(base[k]).max()), k
+    J = sum((out[k] * torch.as_tensor(lam[k])).sum() for k in F8)
+    ref = torch.autograd.grad(J, [st[k] for k in F8] + [gg, pi])
+    for a, k in enumerate(F8):
+        assert relmax(gp[k].cpu().numpy(), ref[a].numpy()) <= 1e-10, ("step", k)
+    d = {k: rng.standard_normal(w.n) for k in F8}
+    eps = 1e-6
+    fp, fm = fwd(d, eps), fwd(d, -eps)
+    jvp = sum(float(((fp[k] - fm[k]) / (2 * eps) * lam[k]).sum()) for k in F8)
+    vjp = sum(float((gp[k].cpu().numpy() * d[k]).sum()) for k in F8)
+    assert abs(jvp - vjp) <= 1e-7 * max(abs(vjp), 1.0), (jvp, vjp)
+
+
+def test_rollout_periodic_box_reference_and_fd():
+    """A closed periodic box (8 x 9 x 8), 10 FP64 CFL steps with particles crossing the faces,
+    checkpoint every 4: d/d(v0, gamma) of the x-momentum of the particles in the upper half
+    (in z) at the end, against the FP64 CPU reference and central differences of the GPU
+    forward."""
+    w = ci.periodic_block(8, 9, 8, seed=14, periodic=7, amp=0.3)
+    rng = np.random.default_rng(14)
+    w.vx, w.vy, w.vz = (rng.uniform(-0.6, 0.6, w.n) for _ in range(3))
+    w.vy = w.vy + 1.0
+    w.p = rng.uniform(0.5, 1.5, w.n)
+    params = P.Params.from_workload(w, cfl=0.3)
+    base = _base(w, params)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float64), device=DEV)
+    v0 = [t(w.vx).requires_grad_(True), t(w.vy).requires_grad_(True), t(w.vz).requires_grad_(True)]
+    gamma = torch.tensor([e[1] for e in w.eos], dtype=torch.float64, device=DEV,
+                         requires_grad=True)
+    nsteps, every = 10, 4
+    info = {}
+    P.rollout(*v0, gamma, base, params, nsteps, every, info=info)
+    dts = info["dts"]
+    out = P.rollout(*v0, gamma, base, params, nsteps, every, dts=dts)
+    mask = out["z"].detach() > 4.0
+    J = _objective(out, mask, base["m"])
+    grads = torch.autograd.grad(J, v0 + [gamma])
+    cfg = O.cfg_for(w)
+    et, gg, pi = tparams(w, True)
+    gg = gg.clone().detach().requires_grad_(True)
+    mat = torch.as_tensor(w.mat).long()
+    m = torch.as_tensor(w.m)
+    vr = [torch.as_tensor(a).clone().requires_grad_(True) for a in (w.vx, w.vy, w.vz)]
+    E0 = T.init_energy_torch(torch.as_tensor(w.rho), torch.as_tensor(w.p), *vr, mat, et, gg, pi)
+    st = {"x": torch.as_tensor(w.x), "y": torch.as_tensor(w.y), "z": torch.as_tensor(w.z),
+          "vx": vr[0], "vy": vr[1], "vz": vr[2], "rho": torch.as_tensor(w.rho), "E": E0}
+    y0 = w.y.copy()
+    for k in range(nsteps):
+        pairs = T.pairs_of(cfg, {kk: st[kk].detach().numpy() for kk in ("x", "y", "z")})
+        st = T.step_torch(st, m, mat, et, gg, pi, pairs, w.kappa * w.h, dts[k], box=w.box,
+                          periodic=7)
+    assert np.sum(st["y"].detach().numpy() < y0 - 4.0) > 10  # wrapped through the top face
+    mref = st["z"].detach() > 4.0
+    assert torch.equal(mref, mask.cpu())
+    Jr = (st["vx"][mref] * m[mref]).sum()
+    ref = torch.autograd.grad(Jr, vr + [gg])
+    assert abs(float(J.detach()) - float(Jr.detach())) <= 1e-11 * max(abs(float(Jr.detach())), 1e-3)
+    for a in range(3):
+        assert relmax(grads[a].cpu().numpy(), ref[a].numpy()) <= 1e-9, a
+    assert relmax(grads[3].cpu().numpy(), ref[3].numpy()) <= 1e-9
+    for trial in range(4):
+        d = [rng.standard_normal(w.n) for _ in range(3)]
+        dg = rng.standard_normal(len(w.eos))
+        eps = 1e-6
+
+        def Jat(sign):
+            vv = [v0[a].detach() + sign * eps * t(d[a]) for a in range(3)]
+            gm = gamma.detach() + sign * eps * t(dg)
+            o = P.rollout(*vv, gm, base, params, nsteps, every, dts=dts)
+            return float(_objective(o, mask, base["m"]))
+
+        fd = (Jat(1) - Jat(-1)) / (2 * eps)
+        pred = sum(float((grads[a].cpu().numpy() * d[a]).sum()) for a in range(3)) + \
+            float((grads[3].cpu().numpy() * dg).sum())
+        assert abs(fd - pred) <= 1e-4 * max(abs(pred), 1e-8), (trial, fd, pred)
