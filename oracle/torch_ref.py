@@ -10,7 +10,8 @@ a brute-force test of the reflected positions written as the oracle writes it,
 and the step reflects the particles that cross the plane.  The materials are
 ideal gas, stiffened gas, or Mie-Grueneisen (eqs. mie_gruneisen_eos,
 mie_gruneisen_reference, with the sound speed the oracle derives from them).
-The time step dt is an input (frozen), fixed-h mode only.
+The time step dt is an input (frozen); in pair-h mode the particle sizes d are
+constants of the map.
 
 Only the tests may import this module.
 """
@@ -27,13 +28,25 @@ import oracle as O
 FIELDS8 = ("x", "y", "z", "vx", "vy", "vz", "rho", "E")
 
 
+def _support(H, pair_h, i, j):
+    """The support of each pair: H (fixed-h mode), or kappa (d_i + d_j)/2 with pair_h =
+    (kappa, d) (pair-h mode, d held fixed)."""
+    if pair_h is None:
+        return H
+    kappa, d = pair_h
+    d = torch.as_tensor(np.asarray(d, np.float64))
+    return kappa * (0.5 * (d[i] + d[j]))
+
+
 def pairs_of(cfg, s):
     """Directed pair list (i, j), j in N(i), from the oracle's neighbour sets.  With periodic
     axes, (i, j, shift): shift[p, a] = k_a L_a of the image through which j is i's partner (the
     offset is (x_j - x_i) - k L, as the oracle forms it); with each period above twice the
     support that image is the one nearest i, k_a = round((x_j - x_i) / L_a)."""
+    d = s.get("d") if cfg.h_mode == 1 else None
     off, idx = O.neighbors(cfg, np.ascontiguousarray(s["x"]), np.ascontiguousarray(s["y"]),
-                           np.ascontiguousarray(s["z"]))
+                           np.ascontiguousarray(s["z"]),
+                           None if d is None else np.ascontiguousarray(d, np.float64))
     i = np.repeat(np.arange(len(off) - 1), np.diff(off))
     j = idx.astype(np.int64)
     ti, tj = torch.as_tensor(i, dtype=torch.long), torch.as_tensor(j)
@@ -48,12 +61,13 @@ def pairs_of(cfg, s):
     return ti, tj, torch.as_tensor(shift)
 
 
-def mirror_pairs_of(s, H: float, xw: float, box=None, periodic: int = 0):
+def mirror_pairs_of(s, H: float, xw: float, box=None, periodic: int = 0, pair_h=None):
     """Directed mirror pairs (i, j), j = i included: the reflected position of j,
     (2 xw - x_j, y_j, z_j), within the support of i; brute force over all j, the squared
     distance formed as the oracle forms it (((dx dx) + (dy dy)) + dz dz, dx = xg - x_i).
     With periodic axes y and z (the wall's axis x is never periodic), the image of the
-    reflected j nearest i, and (i, j, shift) as from ``pairs_of``."""
+    reflected j nearest i, and (i, j, shift) as from ``pairs_of``.  pair_h = (kappa, d): the
+    support kappa (d_i + d_j)/2 of each pair instead of H."""
     x, y, z = (np.asarray(s[k], np.float64) for k in ("x", "y", "z"))
     xg = 2.0 * xw - x
     dx = xg[None, :] - x[:, None]
@@ -65,7 +79,13 @@ def mirror_pairs_of(s, H: float, xw: float, box=None, periodic: int = 0):
             sh[a] = np.round(d[a] / L) * L
             d[a] = d[a] - sh[a]
     r2 = ((d[0] * d[0]) + (d[1] * d[1])) + (d[2] * d[2])
-    i, j = np.nonzero(r2 < H * H)
+    if pair_h is None:
+        i, j = np.nonzero(r2 < H * H)
+    else:
+        kappa, dd = pair_h
+        dd = np.asarray(dd, np.float64)
+        Hij = kappa * (0.5 * (dd[:, None] + dd[None, :]))
+        i, j = np.nonzero(r2 < Hij * Hij)
     ti, tj = torch.as_tensor(i.astype(np.int64)), torch.as_tensor(j.astype(np.int64))
     if not periodic:
         return ti, tj
@@ -160,10 +180,11 @@ def _pair_sums(x, y, z, vx, vy, vz, P, Z, V, i, j, xj, vxj, H: float, shift=None
 
 
 def rates_torch(st: Dict[str, torch.Tensor], m, mat, eos_type, gamma, pinf, pairs, H: float,
-                mirror=None, wall=None):
+                mirror=None, wall=None, pair_h=None):
     """(drho, dvx, dvy, dvz, dE) of every particle for the directed pair list, plus, with the
     piston wall = (x_w, v_w) at the evaluation time, the directed mirror pairs: j's mirror image
-    at 2 x_w - x_j with x-velocity 2 v_w - vx_j and j's other fields."""
+    at 2 x_w - x_j with x-velocity 2 v_w - vx_j and j's other fields.  pair_h = (kappa, d):
+    pair-h mode, each pair's support kappa (d_i + d_j)/2 (d constant)."""
     x, y, z, vx, vy, vz, rho, E = (st[k] for k in FIELDS8)
     P, c = eos_torch(rho, E, vx, vy, vz, mat, eos_type, gamma, pinf)
     Z = rho * c
@@ -173,14 +194,15 @@ def rates_torch(st: Dict[str, torch.Tensor], m, mat, eos_type, gamma, pinf, pair
     sums = [z0] * 5
     i, j = pairs[0], pairs[1]
     shift = pairs[2] if len(pairs) > 2 else None
-    for k, t in enumerate(_pair_sums(x, y, z, vx, vy, vz, P, Z, V, i, j, x[j], vx[j], H,
-                                     shift)):
+    for k, t in enumerate(_pair_sums(x, y, z, vx, vy, vz, P, Z, V, i, j, x[j], vx[j],
+                                     _support(H, pair_h, i, j), shift)):
         sums[k] = sums[k].index_add(0, i, t)
     if mirror is not None:
         xw, vw = wall
         i, j = mirror[0], mirror[1]
         terms = _pair_sums(x, y, z, vx, vy, vz, P, Z, V, i, j, 2.0 * xw - x[j],
-                           2.0 * vw - vx[j], H, mirror[2] if len(mirror) > 2 else None)
+                           2.0 * vw - vx[j], _support(H, pair_h, i, j),
+                           mirror[2] if len(mirror) > 2 else None)
         for k, t in enumerate(terms):
             sums[k] = sums[k].index_add(0, i, t)
     s_rho, s_vx, s_vy, s_vz, s_E = sums
@@ -189,7 +211,7 @@ def rates_torch(st: Dict[str, torch.Tensor], m, mat, eos_type, gamma, pinf, pair
 
 
 def step_torch(st, m, mat, eos_type, gamma, pinf, pairs, H: float, dt: float, mirror=None,
-               wall=None, t: float = 0.0, box=None, periodic: int = 0):
+               wall=None, t: float = 0.0, box=None, periodic: int = 0, pair_h=None):
     """Symplectic Euler with frozen dt: v, E, rho += dt rates, then r += dt v_new.  With the
     piston wall = (x_w0, v_w): mirror pairs at x_w(t), and a particle whose new x lies behind
     x_w(t + dt) is reflected (x <- 2 x_w - x, v_x <- 2 v_w - v_x, E changed by the kinetic
@@ -198,7 +220,7 @@ def step_torch(st, m, mat, eos_type, gamma, pinf, pairs, H: float, dt: float, mi
     moves down by the period, one below lo up by it, after the reflection."""
     w_now = None if wall is None else (wall[0] + wall[1] * t, wall[1])
     drho, dvx, dvy, dvz, dE = rates_torch(st, m, mat, eos_type, gamma, pinf, pairs, H,
-                                          mirror=mirror, wall=w_now)
+                                          mirror=mirror, wall=w_now, pair_h=pair_h)
     vx = st["vx"] + dt * dvx
     vy = st["vy"] + dt * dvy
     vz = st["vz"] + dt * dvz

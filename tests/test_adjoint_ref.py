@@ -397,3 +397,82 @@ def test_step_periodic_gradient_matches_oracle_finite_differences(periodic, wall
 
         fd = (J_at(1) - J_at(-1)) / (2 * eps)
         assert abs(fd - pred) <= 1e-6 * max(abs(pred), 1.0), (trial, fd, pred)
+
+
+def pair_h_system(seed=21, wall=None):
+    """Pair-h mode (support kappa (d_i + d_j)/2, kappa = 1.936) with particle sizes 0.8-1.3."""
+    w = system(n=6, seed=seed)
+    rng = np.random.default_rng(seed + 3)
+    d = rng.uniform(0.8, 1.3, w.n)
+    if wall is not None:
+        w.vx = w.vx - 0.5
+        w.wall = wall
+    return w, d
+
+
+@pytest.mark.parametrize("wall", [None, (0.2, 0.4)], ids=["open", "piston"])
+def test_torch_rates_pair_h_match_c_oracle(wall):
+    w, d = pair_h_system(wall=wall)
+    cfg = O.cfg_for(w, h_mode=1, kappa=1.936)
+    s = O.state_from(w, cfg)
+    s["d"] = d
+    t = 0.3
+    ref = O.rates(cfg, s, t=t, d=d)
+    et, g, pi = tparams(w)
+    ph = (1.936, d)
+    mir, wt = None, None
+    if wall is not None:
+        xw = wall[0] + wall[1] * t
+        mir = T.mirror_pairs_of(s, 0.0, xw, pair_h=ph)
+        assert len(mir[0]) > 10
+        wt = (xw, wall[1])
+    out = T.rates_torch(T.to_torch(s), torch.as_tensor(s["m"]), torch.as_tensor(s["mat"]).long(),
+                        et, g, pi, T.pairs_of(cfg, s), 0.0, mirror=mir, wall=wt, pair_h=ph)
+    for k, v in zip(("drho", "dvx", "dvy", "dvz", "dE"), out):
+        scale = np.abs(ref[k]).max()
+        assert np.abs(v.numpy() - ref[k]).max() <= 1e-13 * scale, k
+
+
+@pytest.mark.parametrize("wall", [None, (0.2, 0.4)], ids=["open", "piston"])
+def test_step_pair_h_gradient_matches_oracle_finite_differences(wall):
+    """Pair-h mode (each pair's own support, d held fixed): the reference's gradient against
+    central differences of the C oracle's step."""
+    w, d = pair_h_system(seed=22, wall=wall)
+    cfg = O.cfg_for(w, h_mode=1, kappa=1.936, cfl=0.0)
+    s = O.state_from(w, cfg)
+    s["d"] = d
+    t, dt = 0.3, 0.1
+    ph = (1.936, d)
+    et, g, pi = tparams(w)
+    st = {k: v.clone().requires_grad_(True) for k, v in T.to_torch(s).items()}
+    g = g.clone().requires_grad_(True)
+    pi = pi.clone().requires_grad_(True)
+    m = torch.as_tensor(s["m"])
+    mat = torch.as_tensor(s["mat"]).long()
+    mir = None if wall is None else T.mirror_pairs_of(s, 0.0, wall[0] + wall[1] * t, pair_h=ph)
+    out = T.step_torch(st, m, mat, et, g, pi, T.pairs_of(cfg, s), 0.0, dt, mirror=mir,
+                       wall=wall, t=t, pair_h=ph)
+    s1_base, _, _, _ = O.step(cfg, s, t, dt_in=dt, d=d)
+    for k in F8:
+        assert np.abs(out[k].detach().numpy() - s1_base[k]).max() <= 1e-13 * (1 + np.abs(s1_base[k]).max()), k
+    rng = np.random.default_rng(70)
+    lam = {k: rng.standard_normal(w.n) for k in F8}
+    J = sum((out[k] * torch.as_tensor(lam[k])).sum() for k in F8)
+    grads = torch.autograd.grad(J, [st[k] for k in F8] + [g, pi])
+    for trial in range(3):
+        dd = {k: rng.standard_normal(w.n) for k in F8}
+        dg = rng.standard_normal(len(w.eos))
+        dpi = rng.standard_normal(len(w.eos)) * np.array([0.0 if e[0] == 0 else 1.0 for e in w.eos])
+        pred = sum(float((grads[a].numpy() * dd[k]).sum()) for a, k in enumerate(F8))
+        pred += float((grads[8].numpy() * dg).sum()) + float((grads[9].numpy() * dpi).sum())
+        eps = 1e-6
+
+        def J_at(sign):
+            s2 = {k: (s[k] + sign * eps * dd[k]) if k in dd else s[k] for k in s}
+            c2 = O.make_cfg(_eos_shifted(w.eos, sign, eps, dg, dpi), h=w.h, kappa=1.936,
+                            h_mode=1, cfl=0.0, wall=wall)
+            s1, _, _, _ = O.step(c2, s2, t, dt_in=dt, d=d)
+            return sum(float((s1[k] * lam[k]).sum()) for k in F8)
+
+        fd = (J_at(1) - J_at(-1)) / (2 * eps)
+        assert abs(fd - pred) <= 1e-6 * max(abs(pred), 1.0), (trial, fd, pred)
