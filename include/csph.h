@@ -453,9 +453,10 @@ csph_status csph_init_energy(const double *rho, const double *pres, const double
                              const double *vy, const double *vz, const int32_t *mat, int64_t n,
                              const csph_params *p, double *E, csph_stream stream);
 
-/* Adjoint (vector-Jacobian products).  Fixed-h mode (CSPH_EINVAL in pair-h
- * mode), every boundary (open, the piston, periodic axes) and every material;
- * FP64 arithmetic in both precisions (it differentiates the FP64 map).  A
+/* Adjoint (vector-Jacobian products).  Both smoothing-length modes (in pair-h
+ * mode the sizes d are constants of the map: no gradient is returned for them),
+ * every boundary (open, the piston, periodic axes) and every material; FP64
+ * arithmetic in both precisions (it differentiates the FP64 map).  A
  * gradient struct holds 8 FP64 arrays in the state's order.  The EOS-parameter
  * gradients are those of gamma and p_inf; for a Mie-Grueneisen material the
  * gamma slot holds d/dGamma and the p_inf slot stays 0 (rho0, c_a and s_a are

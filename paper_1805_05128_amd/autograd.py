@@ -26,9 +26,10 @@ STATE8 = A.GRAD_FIELDS
 
 
 def _clone_state(s: A.State) -> A.State:
-    """Copy of the evolving fields; mass and material are shared (constant)."""
+    """Copy of the evolving fields; mass, material and (pair-h mode) the particle sizes are
+    shared (constant)."""
     t = {k: (v if k == "m" else v.clone()) for k, v in s.t.items()}
-    return A.State(t, s.mat, None, None)
+    return A.State(t, s.mat, s.d, None)
 
 
 def _with_gamma(params: A.Params, gamma: List[float]) -> A.Params:
@@ -41,8 +42,8 @@ def _with_gamma(params: A.Params, gamma: List[float]) -> A.Params:
 class CSPHRollout(torch.autograd.Function):
     """(vx0, vy0, vz0, gamma) -> final state (x, y, z, vx, vy, vz, rho, E).
 
-    ``base`` holds the device tensors x, y, z, rho, m, mat of the initial
-    state and either p (the initial energy is then E0 = e(rho, p; gamma) +
+    ``base`` holds the device tensors x, y, z, rho, m, mat (and, in pair-h
+    mode, the particle sizes d, held fixed) of the initial state and either p (the initial energy is then E0 = e(rho, p; gamma) +
     |v0|^2/2, differentiated) or E (a window that starts from a state of a
     longer run: E is held fixed, so the gradient is the partial derivative
     at fixed specific total energy); ``params`` the run parameters (its
@@ -67,7 +68,7 @@ class CSPHRollout(torch.autograd.Function):
         st = A.State({"x": base["x"].clone(), "y": base["y"].clone(), "z": base["z"].clone(),
                       "vx": vx0.detach().clone(), "vy": vy0.detach().clone(),
                       "vz": vz0.detach().clone(), "rho": base["rho"].clone(), "E": E0,
-                      "m": base["m"]}, base["mat"])
+                      "m": base["m"]}, base["mat"], base.get("d"))
         sc = A.StepScalars(vx0.device, t0=t0)
         ckpts = []
         dt_dev, t_dev = [], []

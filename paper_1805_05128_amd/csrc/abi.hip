@@ -1164,11 +1164,6 @@ csph_status csph_init_energy(const double *rho, const double *pres, const double
     return CSPH_OK;
 }
 
-static csph_status check_vjp_params(const csph_params *p) {
-    if (p->h_mode != CSPH_H_FIXED) return fail(CSPH_EINVAL, "the adjoint supports fixed-h mode only");
-    return CSPH_OK;
-}
-
 static bool grad_ok(const csph_grad &g) {
     return g.x && g.y && g.z && g.vx && g.vy && g.vz && g.rho && g.E;
 }
@@ -1194,9 +1189,7 @@ static csph_status vjp_common(const csph_state *s_in, const csph_params *p, doub
     const csph_state *s = s_in;
     if (!state_ok(s) || s->n >= INT32_MAX) return fail(CSPH_EINVAL, "bad state");
     if (s->n >= kMaxPairN) return fail(CSPH_EINVAL, "n >= 2^27 particles");
-    csph_status r = check_params(p, false, nullptr);
-    if (r) return r;
-    r = check_vjp_params(p);
+    csph_status r = check_params(p, s->n > 0, s->d);
     if (r) return r;
     int64_t n = s->n;
     if (n > 0 && !grad_ok(gout_in)) return fail(CSPH_EINVAL, "gradient outputs must not be NULL");
@@ -1223,7 +1216,9 @@ static csph_status vjp_common(const csph_state *s_in, const csph_params *p, doub
     }
     csph_grid g;
     double dmax, ymin;
-    r = make_grid(s->x, s->y, s->z, nullptr, n, p, ws, ws_bytes, st, &g, &dmax, &ymin, true);
+    const bool pair = p->h_mode == CSPH_H_PAIR;
+    r = make_grid(s->x, s->y, s->z, pair ? s->d : nullptr, n, p, ws, ws_bytes, st, &g, &dmax,
+                  &ymin, true);
     if (r) return r;
     r = need_ws(ws_bytes, n, g.ncell, ws_needed);
     if (r) return r;
@@ -1234,8 +1229,9 @@ static csph_status vjp_common(const csph_state *s_in, const csph_params *p, doub
     PairConst pc = pair_const(p, dmax);
     EosDev eos = eos_dev(p);
     ProfScope pr(CSPH_PROF_ADJOINT, st);
+    double *const dsrt = pair ? w.srt_d : nullptr;  // pair-h mode: the sizes in cell order
     CSPH_HIP(launch_bin(s->x, s->y, s->z, n, gd, w, w.perm, nullptr, w.cs, st));
-    CSPH_HIP(launch_pack(*s, n, w.perm, eos, 0, gd, w, w.srt, w.srt_mat, nullptr, nullptr,
+    CSPH_HIP(launch_pack(*s, n, w.perm, eos, 0, gd, w, w.srt, w.srt_mat, dsrt, nullptr,
                          nullptr, nullptr, st));
     double *go[8] = {gout.x, gout.y, gout.z, gout.vx, gout.vy, gout.vz, gout.rho, gout.E};
     const double *gn[8];
@@ -1247,11 +1243,11 @@ static csph_status vjp_common(const csph_state *s_in, const csph_params *p, doub
     const bool wall = p->wall != 0;
     if (wall && gnext) {
         // the step's reflections, found again from the FP64 rates at t; the cotangents of the
-        // pre-reflection y and v_y go to two arrays the adjoint leaves unused otherwise (it
-        // packs no smoothing lengths or ids)
+        // pre-reflection y and v_y go to two arrays the adjoint leaves unused otherwise (the
+        // signal speeds this evaluation wrote, which nothing reads, and the ids it packs not)
         CSPH_HIP(launch_fill_u64(w.dtmin, 0x7ff0000000000000ull, 2, st));
-        CSPH_HIP(launch_rates(n, 0, gd, pc, w, w.srt, nullptr, nullptr, t, 0, st));
-        double *gy = w.srt_d, *gvy = (double *)w.srt_id;
+        CSPH_HIP(launch_rates(n, 0, gd, pc, w, w.srt, dsrt, nullptr, t, 0, st));
+        double *gy = w.sig, *gvy = (double *)w.srt_id;
         const double yw1 = p->wall_x0 + p->wall_v * (t + dt);
         CSPH_HIP(launch_vjp_reflect(n, w.perm, w.srt[1], w.srt[4], w.rate[2], dt, yw1, p->wall_v,
                                     gn[1], gn[4], gn[7], gy, gvy, st));
@@ -1260,7 +1256,8 @@ static csph_status vjp_common(const csph_state *s_in, const csph_params *p, doub
     }
     const double yw = wall ? p->wall_x0 + p->wall_v * t : 0.0;
     CSPH_HIP(launch_vjp(n, w.perm, w.cs, gd, pc, eos, w, w.srt, w.srt_mat, a, go,
-                        gnext ? gn : nullptr, dt, accumulate, g_eos, wall, yw, p->wall_v, st));
+                        gnext ? gn : nullptr, dt, accumulate, g_eos, dsrt, wall, yw, p->wall_v,
+                        st));
     return CSPH_OK;
 }
 

@@ -346,7 +346,7 @@ hipError_t launch_vjp(int64_t n, const int32_t *perm, const int32_t *cs, const G
                       double *const sorted[9], const int32_t *mat_sorted,
                       const double *const a_in[5], double *const gout[8],
                       const double *const gnext[8], double dt, int accumulate, double *g_eos,
-                      int wall, double yw, double vw, hipStream_t st);
+                      const double *d_sorted, int wall, double yw, double vw, hipStream_t st);
 // Step VJP with the piston: the cotangents of the pre-reflection y and v_y (input order) from
 // the next state's (the state and its rates in cell order; yw1 the wall at the step's end).
 hipError_t launch_vjp_reflect(int64_t n, const int32_t *perm, const double *y_s,

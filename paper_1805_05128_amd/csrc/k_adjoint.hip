@@ -34,6 +34,7 @@ struct VjpIn {
     const double *rho, *E, *m;  // sorted state
     const int32_t *mat;
     const double *a[5]; // rate cotangents (cell order): rho vx vy vz E
+    const double *dsz;  // pair-h mode: particle sizes d (cell order, constants of the map)
 };
 
 // The piston at the time of the rates: position along the kernels' y, twice its velocity.
@@ -211,8 +212,11 @@ __device__ __forceinline__ void vjp_pair(bool use, double dx, double dy, double 
 // periodic images i has (image_faces), with offsets (x_j - x_i) - k L formed
 // as the forward pass forms them; j is a partner of i through shift k exactly
 // when i is one of j through -k (the offset negates exactly), so the gather
-// stays complete.  With both, the mirror image's periodic images too.
-template <bool WALL, bool PER>
+// stays complete.  With both, the mirror image's periodic images too.  PAIR:
+// each pair's support H_ij = kappa (d_i + d_j)/2 (symmetric to the bit; d
+// held fixed), the walk testing candidates against the largest support and
+// the pop deciding membership with the pair's own.
+template <bool WALL, bool PER, bool PAIR>
 __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
                                                   const int32_t *__restrict__ perm,
                                                   const int32_t *__restrict__ cs, GridDev g,
@@ -236,7 +240,8 @@ __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
         bEi = in.Ew[s];
     }
     const Stencil t = make_stencil(g, ai.x, ai.y, ai.z, pc.H);
-    const double invH = pc.invH, dwc = pc.dwc, H2 = pc.H2;
+    const double H2 = pc.H2;  // the largest support (pair-h mode), squared
+    const double dself = PAIR && live ? in.dsz[s] : 0.0;
     const int self = (int)s;
     // i's mirror image (its y, and its velocity record with the normal component mirrored),
     // zero weights for the side of a pair that has no rate
@@ -253,6 +258,14 @@ __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
         const double4 aj = ld(in.A, j), bj = ld(in.B, j), dj = ld(in.Dw, j);
         const double2 zj = ld(in.C, j);
         const double bEj = ld(in.Ew, j);
+        double invH = pc.invH, dwc = pc.dwc, H2p = H2;
+        if (PAIR) {  // the pair's own support, as the forward pass forms it
+            const double H = pc.kappa * (0.5 * (dself + ld(in.dsz, j)));
+            H2p = H * H;
+            invH = 1.0 / (H > 0.0 ? H : 1.0);
+            const double i2 = invH * invH;
+            dwc = (210.0 / M_PI) * (i2 * i2);
+        }
         double dx = aj.x - ai.x, dz = aj.z - ai.z;
         if (PER) {
             dx = dx - sx;
@@ -262,8 +275,8 @@ __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
             double dy = aj.y - ai.y;
             if (PER) dy = dy - sy;
             const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
-            vjp_pair(has, dx, dy, dz, r2, ai, bi, zi, di, bEi, aj, bj, zj, dj, bEj, invH, dwc,
-                     acc);
+            vjp_pair(has && (!PAIR || r2 < H2p), dx, dy, dz, r2, ai, bi, zi, di, bEi, aj, bj, zj,
+                     dj, bEj, invH, dwc, acc);
             return;
         }
         // (i, image of j): offset (2 y_w - y_j) - y_i, as the forward pass forms it (the
@@ -271,13 +284,13 @@ __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
         const double dya = (2.0 * wl.yw - aj.y) - ai.y;
         const double r2a = ((dx * dx) + (dya * dya)) + (dz * dz);
         const double4 bjm = make_double4(bj.x, wl.vw2 - bj.y, bj.z, bj.w);
-        vjp_pair(has && r2a < H2 && r2a != 0.0, dx, dya, dz, r2a, ai, bi, zi, di, bEi, aj, bjm,
-                 zj, d0, 0.0, invH, dwc, acc);
+        vjp_pair(has && r2a < H2p && r2a != 0.0, dx, dya, dz, r2a, ai, bi, zi, di, bEi, aj,
+                 bjm, zj, d0, 0.0, invH, dwc, acc);
         // (j, image of i): j's forward offset (2 y_w - y_i) - y_j, negated exactly
         const double dyb = aj.y - yim;
         const double r2b = ((dx * dx) + (dyb * dyb)) + (dz * dz);
-        vjp_pair(has && r2b < H2 && r2b != 0.0, dx, dyb, dz, r2b, ai, bim, zi, d0, 0.0, aj, bj,
-                 zj, dj, bEj, invH, dwc, accm);
+        vjp_pair(has && r2b < H2p && r2b != 0.0, dx, dyb, dz, r2b, ai, bim, zi, d0, 0.0, aj,
+                 bj, zj, dj, bEj, invH, dwc, accm);
     };
     // one walk over stencil st (ghost: the stencil around i's mirror image, whose partners
     // are tested as both kinds of mirror pair; img: around a periodic image point, shift
@@ -470,7 +483,7 @@ hipError_t launch_vjp(int64_t n, const int32_t *perm, const int32_t *cs, const G
                       double *const sorted[9], const int32_t *mat_sorted,
                       const double *const a_in[5], double *const gout[8],
                       const double *const gnext[8], double dt, int accumulate, double *g_eos,
-                      int wall, double yw, double vw, hipStream_t st) {
+                      const double *d_sorted, int wall, double yw, double vw, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
     VjpOut o;
@@ -497,16 +510,21 @@ hipError_t launch_vjp(int64_t n, const int32_t *perm, const int32_t *cs, const G
     in.m = sorted[8];
     in.mat = mat_sorted;
     for (int k = 0; k < 5; ++k) in.a[k] = w.rate[k];
+    in.dsz = d_sorted;
     const VjpWall wl{yw, 2.0 * vw};
-    const bool per = pc.per != 0;
-    if (wall && per)
-        k_vjp64<true, true><<<nb, kBlock, 0, st>>>(n, in, o, perm, cs, g, pc, eos, eos.n, wl);
-    else if (wall)
-        k_vjp64<true, false><<<nb, kBlock, 0, st>>>(n, in, o, perm, cs, g, pc, eos, eos.n, wl);
-    else if (per)
-        k_vjp64<false, true><<<nb, kBlock, 0, st>>>(n, in, o, perm, cs, g, pc, eos, eos.n, wl);
-    else
-        k_vjp64<false, false><<<nb, kBlock, 0, st>>>(n, in, o, perm, cs, g, pc, eos, eos.n, wl);
+    const bool per = pc.per != 0, pair = pc.pair_mode != 0;
+#define CSPH_VJP_CASE(W, X, Q)                                                              \
+    if (wall == W && per == X && pair == Q)                                                 \
+        k_vjp64<W, X, Q><<<nb, kBlock, 0, st>>>(n, in, o, perm, cs, g, pc, eos, eos.n, wl);
+    CSPH_VJP_CASE(false, false, false)
+    CSPH_VJP_CASE(false, false, true)
+    CSPH_VJP_CASE(false, true, false)
+    CSPH_VJP_CASE(false, true, true)
+    CSPH_VJP_CASE(true, false, false)
+    CSPH_VJP_CASE(true, false, true)
+    CSPH_VJP_CASE(true, true, false)
+    CSPH_VJP_CASE(true, true, true)
+#undef CSPH_VJP_CASE
     if (g_eos) k_eos_grad_final<<<1, kBlock, 0, st>>>(w.eos_part, (int64_t)nb, 2 * eos.n, g_eos);
     return hipGetLastError();
 }

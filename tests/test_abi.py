@@ -186,7 +186,7 @@ def test_list_step_needs_its_control_block():
 def test_periodic_params_checked_on_the_host():
     """Periodic boundaries: an unknown axis mask, an empty box, a periodic wall axis, and the
     calls that do not take periodic boundaries (Verlet lists) are refused before any device
-    work; so is the adjoint in pair-h mode."""
+    work; so is the adjoint in pair-h mode without the sizes d."""
     L = N.load()
     box = ((0.0, 0.0, 0.0), (10.0, 10.0, 10.0))
     for kw, msg in ((dict(periodic=9, box=box), b"periodic mask"),
@@ -210,9 +210,9 @@ def test_periodic_params_checked_on_the_host():
                            dev(1 << 22, C.c_double), C.c_void_p(1 << 23), None, 0, None, None)
     assert st == N.CSPH_EINVAL and b"periodic" in L.csph_last_error()
     g = N.CsphGrad(*[dev((1 << 25) + 1024 * k, C.c_double) for k in range(8)])
-    p = P.Params(periodic=7, box=box, h_mode="pair").c()  # the adjoint: fixed h only
+    p = P.Params(periodic=7, box=box, h_mode="pair").c()  # the adjoint in pair-h mode needs d
     st = L.csph_step_vjp(C.byref(a), C.byref(p), 0.0, 0.1, g, g, None, None, 0, None, None)
-    assert st == N.CSPH_EINVAL and b"fixed-h" in L.csph_last_error()
+    assert st == N.CSPH_EINVAL and b"particle size array d" in L.csph_last_error()
 
 
 def test_integrator_checked_on_the_host():

@@ -756,3 +756,141 @@ def test_rollout_periodic_box_reference_and_fd():
         pred = sum(float((grads[a].cpu().numpy() * d[a]).sum()) for a in range(3)) + \
             float((grads[3].cpu().numpy() * dg).sum())
         assert abs(fd - pred) <= 1e-4 * max(abs(pred), 1e-8), (trial, fd, pred)
+
+
+@pytest.mark.parametrize("wall", [None, (0.2, 0.4)], ids=["open", "piston"])
+def test_rates_and_step_vjp_pair_h_match_autograd(wall):
+    """Pair-h mode (each pair's support kappa (d_i + d_j)/2, kappa = 1.936, d held fixed): the
+    GPU VJPs of the rates and of the step against autograd of the FP64 reference, and the
+    dot-product test against the GPU's own forward step."""
+    w = system(n=8, seed=23)
+    rng = np.random.default_rng(23)
+    d = rng.uniform(0.8, 1.3, w.n)
+    if wall is not None:
+        w.vx = w.vx - 0.5
+        w.wall = wall
+    print(f"[case] pair-h vjp wall={wall} n={w.n}", flush=True)
+    t, dt = 0.3, 0.1
+    params = P.Params.from_workload(w, reorder=False, h_mode="pair", kappa=1.936, cell_size=0.0)
+    g = P.state_from_workload(w, params, DEV)
+    g.d = torch.as_tensor(d, device=DEV)
+    s = _np_state(g, w)
+    s["d"] = d
+    ph = (1.936, d)
+    cfg = O.cfg_for(w, h_mode=1, kappa=1.936)
+    pairs = T.pairs_of(cfg, s)
+    mir, wt = None, None
+    if wall is not None:
+        mir = T.mirror_pairs_of(s, 0.0, wall[0] + wall[1] * t, pair_h=ph)
+        wt = (wall[0] + wall[1] * t, wall[1])
+    et, gg, pi = tparams(w, True)
+    m, mat = torch.as_tensor(w.m), torch.as_tensor(w.mat).long()
+    cot = {k: rng.standard_normal(w.n) for k in ("drho", "dvx", "dvy", "dvz", "dE")}
+    gs, ge = P.csph_rates_vjp(g, params, {k: torch.as_tensor(v, device=DEV) for k, v in cot.items()},
+                              t=t)
+    st = {k: torch.as_tensor(s[k]).clone().requires_grad_(True) for k in F8}
+    out = T.rates_torch(st, m, mat, et, gg, pi, pairs, 0.0, mirror=mir, wall=wt, pair_h=ph)
+    J = sum((o * torch.as_tensor(cot[k])).sum()
+            for o, k in zip(out, ("drho", "dvx", "dvy", "dvz", "dE")))
+    ref = torch.autograd.grad(J, [st[k] for k in F8] + [gg, pi])
+    for a, k in enumerate(F8):
+        assert relmax(gs[k].cpu().numpy(), ref[a].numpy()) <= 1e-10, ("rates", k)
+    assert relmax(ge.cpu().numpy()[0::2], ref[8].numpy()) <= 1e-10
+    replay = P.Params.from_workload(w, reorder=False, h_mode="pair", kappa=1.936, cell_size=0.0,
+                                    cfl=0.0)
+
+    def fwd(delta=None, eps=0.0):
+        tt = {k: g[k] + (eps * torch.as_tensor(delta[k], device=DEV) if delta else 0.0)
+              for k in F8}
+        tt["m"] = g["m"]
+        st2 = P.State(tt, g.mat, g.d)
+        P.csph_step(st2, replay, P.StepScalars(DEV, t0=t), s_out=st2, dt_in=dt)
+        return {k: st2[k].cpu().numpy() for k in F8}
+
+    base = fwd()
+    lam = {k: rng.standard_normal(w.n) for k in F8}
+    gn = {k: torch.as_tensor(v, device=DEV).clone() for k, v in lam.items()}
+    gp, ge = P.csph_step_vjp(g, params, dt, gn, g_prev={k: torch.empty_like(v) for k, v in gn.items()},
+                             t=t)
+    st = {k: torch.as_tensor(s[k]).clone().requires_grad_(True) for k in F8}
+    out = T.step_torch(st, m, mat, et, gg, pi, pairs, 0.0, dt, mirror=mir, wall=wall, t=t,
+                       pair_h=ph)
+    for k in F8:
+        assert np.abs(out[k].detach().numpy() - base[k]).max() <= 1e-12 * (1 + np.abs(base[k]).max()), k
+    J = sum((out[k] * torch.as_tensor(lam[k])).sum() for k in F8)
+    ref = torch.autograd.grad(J, [st[k] for k in F8] + [gg, pi])
+    for a, k in enumerate(F8):
+        assert relmax(gp[k].cpu().numpy(), ref[a].numpy()) <= 1e-10, ("step", k)
+    dd = {k: rng.standard_normal(w.n) for k in F8}
+    eps = 1e-6
+    fp, fm = fwd(dd, eps), fwd(dd, -eps)
+    jvp = sum(float(((fp[k] - fm[k]) / (2 * eps) * lam[k]).sum()) for k in F8)
+    vjp = sum(float((gp[k].cpu().numpy() * dd[k]).sum()) for k in F8)
+    assert abs(jvp - vjp) <= 1e-7 * max(abs(vjp), 1.0), (jvp, vjp)
+
+
+def test_rollout_paper_mode_plates_reference_and_fd():
+    """The paper's material mode on a small plate impact: aluminium onto lead (8 x 8 x 4 each,
+    Mie-Grueneisen), pair-h support with kappa = 1.936 and sizes d of 0.95-1.15 held fixed,
+    12 FP64 CFL steps, checkpoint every 5: d/d(v0, Gamma) of the aluminium's z-momentum against
+    the FP64 CPU reference and central differences of the GPU forward."""
+    w = ci.mg_plates(8, 8, 4, gap=1.5, v_impact=0.5, seed=4)
+    d = np.random.default_rng(4).uniform(0.95, 1.15, w.n)
+    print(f"[case] paper-mode plates rollout n={w.n}", flush=True)
+    params = P.Params.from_workload(w, cfl=0.3, h_mode="pair", kappa=1.936, cell_size=0.0)
+    base = _base(w, params)
+    base["d"] = torch.as_tensor(d, device=DEV)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float64), device=DEV)
+    v0 = [t(w.vx).requires_grad_(True), t(w.vy).requires_grad_(True), t(w.vz).requires_grad_(True)]
+    gamma = torch.tensor([e[1] for e in w.eos], dtype=torch.float64, device=DEV,
+                         requires_grad=True)
+    nsteps, every = 12, 5
+    info = {}
+    P.rollout(*v0, gamma, base, params, nsteps, every, info=info)
+    dts = info["dts"]
+    out = P.rollout(*v0, gamma, base, params, nsteps, every, dts=dts)
+    mask = torch.as_tensor(w.mat == 1, device=DEV)
+    J = (out["vz"][mask] * base["m"][mask]).sum()
+    grads = torch.autograd.grad(J, v0 + [gamma])
+    cfg = O.cfg_for(w, h_mode=1, kappa=1.936)
+    _, gg, pi = tparams(w, True)
+    gg = gg.clone().detach().requires_grad_(True)
+    mat = torch.as_tensor(w.mat).long()
+    m = torch.as_tensor(w.m)
+    vr = [torch.as_tensor(a).clone().requires_grad_(True) for a in (w.vx, w.vy, w.vz)]
+    E0 = T.init_energy_torch(torch.as_tensor(w.rho), torch.as_tensor(w.p), *vr, mat,
+                             list(w.eos), gg, pi)
+    st = {"x": torch.as_tensor(w.x), "y": torch.as_tensor(w.y), "z": torch.as_tensor(w.z),
+          "vx": vr[0], "vy": vr[1], "vz": vr[2], "rho": torch.as_tensor(w.rho), "E": E0}
+    npairs = 0
+    for k in range(nsteps):
+        sn = {kk: st[kk].detach().numpy() for kk in ("x", "y", "z")}
+        sn["d"] = d
+        pairs = T.pairs_of(cfg, sn)
+        npairs += len(pairs[0])
+        st = T.step_torch(st, m, mat, list(w.eos), gg, pi, pairs, 0.0, dts[k],
+                          pair_h=(1.936, d))
+    assert npairs > 12 * 4 * w.n  # a few partners each within kappa (d_i + d_j)/2
+    mref = torch.as_tensor(w.mat == 1)
+    Jr = (st["vz"][mref] * m[mref]).sum()
+    ref = torch.autograd.grad(Jr, vr + [gg])
+    assert abs(float(J.detach()) - float(Jr.detach())) <= 1e-11 * abs(float(Jr.detach()))
+    for a in range(3):
+        assert relmax(grads[a].cpu().numpy(), ref[a].numpy()) <= 1e-9, a
+    assert relmax(grads[3].cpu().numpy(), ref[3].numpy()) <= 1e-9
+    rng = np.random.default_rng(19)
+    for trial in range(4):
+        dv = [rng.standard_normal(w.n) for _ in range(3)]
+        dg = rng.standard_normal(len(w.eos))
+        eps = 1e-6
+
+        def Jat(sign):
+            vv = [v0[a].detach() + sign * eps * t(dv[a]) for a in range(3)]
+            gm = gamma.detach() + sign * eps * t(dg)
+            o = P.rollout(*vv, gm, base, params, nsteps, every, dts=dts)
+            return float((o["vz"][mask] * base["m"][mask]).sum())
+
+        fd = (Jat(1) - Jat(-1)) / (2 * eps)
+        pred = sum(float((grads[a].cpu().numpy() * dv[a]).sum()) for a in range(3)) + \
+            float((grads[3].cpu().numpy() * dg).sum())
+        assert abs(fd - pred) <= 1e-4 * max(abs(pred), 1e-8), (trial, fd, pred)
