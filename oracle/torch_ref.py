@@ -210,6 +210,37 @@ def rates_torch(st: Dict[str, torch.Tensor], m, mat, eos_type, gamma, pinf, pair
             (2.0 / rho) * s_E)
 
 
+def cfl_dt_torch(st, m, mat, eos_type, gamma, pinf, pairs, H: float, cfl: float, h: float,
+                 mirror=None, wall=None, pair_h=None):
+    """The CFL time step as a differentiable function of the state and EOS parameters:
+    dt = cfl min_i min(h_i / s_i, rho_i / |drho_i|), h_i = h (fixed) or d_i (pair h), the
+    signal speed s_i = max(c_i, max over partners (mirror partners included) of
+    max(c_i, c_j) + max(0, v_L - v_R)) with v_L - v_R = (v_i - v_j).e, e pointing from i to
+    j (wall = (x_w, v_w) at the evaluation time).  The minimum and the maxima pass their
+    gradients to the particle and the partner that attain them."""
+    x, y, z, vx, vy, vz, rho, E = (st[k] for k in FIELDS8)
+    P, c = eos_torch(rho, E, vx, vy, vz, mat, eos_type, gamma, pinf)
+    drho = rates_torch(st, m, mat, eos_type, gamma, pinf, pairs, H, mirror=mirror, wall=wall,
+                       pair_h=pair_h)[0]
+    sig = c
+    lists = [(pairs, x, vx, pairs[2] if len(pairs) > 2 else None)]
+    if mirror is not None:
+        xw, vw = wall
+        lists.append((mirror, 2.0 * xw - x, 2.0 * vw - vx, mirror[2] if len(mirror) > 2 else None))
+    for pr, xs, vxs, shift in lists:
+        i, j = pr[0], pr[1]
+        dx, dy, dz = xs[j] - x[i], y[j] - y[i], z[j] - z[i]
+        if shift is not None:
+            dx, dy, dz = dx - shift[:, 0], dy - shift[:, 1], dz - shift[:, 2]
+        r = torch.sqrt((dx * dx + dy * dy) + dz * dz)
+        closing = ((vx[i] - vxs[j]) * dx + (vy[i] - vy[j]) * dy + (vz[i] - vz[j]) * dz) / r
+        sp = torch.maximum(c[i], c[j]) + torch.clamp(closing, min=0.0)
+        sig = sig.scatter_reduce(0, i, sp, reduce="amax", include_self=True)
+    hi = h if pair_h is None else torch.as_tensor(np.asarray(pair_h[1], np.float64))
+    tau = torch.minimum(hi / sig, rho / torch.abs(drho))
+    return cfl * torch.min(tau)
+
+
 def step_torch(st, m, mat, eos_type, gamma, pinf, pairs, H: float, dt: float, mirror=None,
                wall=None, t: float = 0.0, box=None, periodic: int = 0, pair_h=None):
     """Symplectic Euler with frozen dt: v, E, rho += dt rates, then r += dt v_new.  With the

@@ -476,3 +476,74 @@ def test_step_pair_h_gradient_matches_oracle_finite_differences(wall):
 
         fd = (J_at(1) - J_at(-1)) / (2 * eps)
         assert abs(fd - pred) <= 1e-6 * max(abs(pred), 1.0), (trial, fd, pred)
+
+
+def expanding_system(seed=34):
+    """A gas cube expanding from its centre (v = 2 (r - r_c)): the density-change limit sets
+    the time step, not the Courant limit."""
+    w = system(n=6, seed=seed)
+    for k in ("x", "y", "z"):
+        v = getattr(w, k)
+        setattr(w, "v" + k, 2.0 * (v - v.mean()))
+    return w
+
+
+@pytest.mark.parametrize("case", ["gas", "piston", "mg", "expanding"])
+def test_cfl_step_gradient_matches_oracle_finite_differences(case):
+    """The CFL time step differentiated with the step: dt = cfl min_i min(h / s_i,
+    rho_i / |drho_i|) from the reference (the minimum and the signal speed's maxima pass
+    their gradients to the particle and partner that attain them) against central
+    differences of the C oracle's step, which recomputes dt on every perturbed state."""
+    w = {"gas": lambda: system(n=6, seed=31), "piston": lambda: wall_system(seed=32),
+         "mg": lambda: mg_system(seed=33), "expanding": expanding_system}[case]()
+    cfg = O.cfg_for(w, cfl=0.3)
+    s = O.state_from(w, cfg)
+    t = 0.3 if w.wall is not None else 0.0
+    et = list(w.eos)
+    _, g, pi = tparams(w)
+    st = {k: v.clone().requires_grad_(True) for k, v in T.to_torch(s).items()}
+    g = g.clone().requires_grad_(True)
+    pi = pi.clone().requires_grad_(True)
+    m = torch.as_tensor(s["m"])
+    mat = torch.as_tensor(s["mat"]).long()
+    H = w.kappa * w.h
+    pairs = T.pairs_of(cfg, s)
+    mir, wt = None, None
+    if w.wall is not None:
+        xw = w.wall[0] + w.wall[1] * t
+        mir = T.mirror_pairs_of(s, H, xw)
+        wt = (xw, w.wall[1])
+    dt = T.cfl_dt_torch(st, m, mat, et, g, pi, pairs, H, 0.3, w.h, mirror=mir, wall=wt)
+    s1_base, _, dt_o, _ = O.step(cfg, s, t)
+    assert abs(float(dt.detach()) - dt_o) <= 1e-14 * dt_o
+    out = T.step_torch(st, m, mat, et, g, pi, pairs, H, dt, mirror=mir, wall=w.wall, t=t)
+    for k in F8:
+        assert np.abs(out[k].detach().numpy() - s1_base[k]).max() <= 1e-13 * (1 + np.abs(s1_base[k]).max()), k
+    rng = np.random.default_rng(80)
+    lam = {k: rng.standard_normal(w.n) for k in F8}
+    J = sum((out[k] * torch.as_tensor(lam[k])).sum() for k in F8)
+    grads = torch.autograd.grad(J, [st[k] for k in F8] + [g, pi])
+    # the dt term is not small: the frozen-dt gradient differs
+    st0 = {k: v.detach().clone().requires_grad_(True) for k, v in T.to_torch(s).items()}
+    out0 = T.step_torch(st0, m, mat, et, g.detach(), pi.detach(), pairs, H, float(dt.detach()),
+                        mirror=mir, wall=w.wall, t=t)
+    J0 = sum((out0[k] * torch.as_tensor(lam[k])).sum() for k in F8)
+    g0 = torch.autograd.grad(J0, [st0[k] for k in F8])
+    assert max(float((g0[a] - grads[a]).abs().max()) for a in range(8)) > 1e-3
+    for trial in range(3):
+        d = {k: rng.standard_normal(w.n) for k in F8}
+        dg = rng.standard_normal(len(w.eos))
+        dpi = np.zeros(len(w.eos))
+        pred = sum(float((grads[a].numpy() * d[k]).sum()) for a, k in enumerate(F8))
+        pred += float((grads[8].numpy() * dg).sum())
+        eps = 1e-7
+
+        def J_at(sign):
+            s2 = {k: (s[k] + sign * eps * d[k]) if k in d else s[k] for k in s}
+            c2 = O.make_cfg(_eos_shifted(w.eos, sign, eps, dg, dpi), h=w.h, kappa=w.kappa,
+                            cfl=0.3, wall=w.wall)
+            s1, _, _, _ = O.step(c2, s2, t)
+            return sum(float((s1[k] * lam[k]).sum()) for k in F8)
+
+        fd = (J_at(1) - J_at(-1)) / (2 * eps)
+        assert abs(fd - pred) <= 1e-6 * max(abs(pred), 1.0), (trial, fd, pred)
