@@ -591,6 +591,17 @@ def adjoint_ratio(P, torch, ci):
         r = {"ratio": info["backward_s"] / info["forward_s"], "forward_s": info["forward_s"],
              "backward_s": info["backward_s"]}
         best = r
+    # the same rollout differentiated with its CFL steps (csph_step_vjp_cfl: one more FP64
+    # rate evaluation and one host synchronisation per step)
+    for _ in range(2):
+        v0 = [t(a).requires_grad_(True) for a in (w.vx, w.vy, w.vz)]
+        info = {}
+        with collector_off():
+            out = P.rollout(*v0, gamma, base, params, w.steps, 10, info=info, cfl_adjoint=True)
+            mask = out["x"].detach() > 48.0
+            J = (out["vx"][mask] * base["m"][mask]).sum()
+            torch.autograd.grad(J, v0 + [gamma])
+        best["ratio_cfl_adjoint"] = info["backward_s"] / info["forward_s"]
     return {"workload": w.name, "particles": w.n, "steps": w.steps, "checkpoint_every": 10,
             "precision": "fp64", **{k: round(v, 5) for k, v in best.items()}}
 

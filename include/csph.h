@@ -495,6 +495,22 @@ csph_status csph_step_vjp(const csph_state *s_n, const csph_params *p, double t,
                           csph_grad g_next, csph_grad g_prev, double *g_eos, void *ws,
                           size_t ws_bytes, size_t *ws_needed, csph_stream stream);
 
+/* VJP of one Euler csph_step taken at time t whose time step came from the
+ * CFL rule (p->cfl > 0; CSPH_EINVAL otherwise): dt = cfl min_i min(h_i/s_i,
+ * rho_i/|drho_i|) is recomputed from s_n in FP64 (*dt_used, host, optional)
+ * and its dependence on the state and the EOS parameters is included, so that
+ * g_prev is the gradient of the step as csph_step takes it.  The minimum passes
+ * dt's gradient to the particle that sets it: through its signal speed s_i
+ * (the Courant limit; s_i is the maximum over its partners of max(c_i, c_j)
+ * plus the closing speed, or c_i, and the maximum passes it on to the sound
+ * speed, velocities and positions that attain it) or through rho_i/|drho_i|
+ * (the density-change limit).  Arguments as in csph_step_vjp.  Synchronises
+ * twice (mesh bounds, dt).  A state whose CFL step is not finite and positive
+ * is CSPH_EINVAL. */
+csph_status csph_step_vjp_cfl(const csph_state *s_n, const csph_params *p, double t,
+                              csph_grad g_next, csph_grad g_prev, double *g_eos, double *dt_used,
+                              void *ws, size_t ws_bytes, size_t *ws_needed, csph_stream stream);
+
 /* VJP of csph_init_energy: with gE the cotangent of E, accumulates
  * g_vx/g_vy/g_vz += gE v, g_rho += gE de/drho (each optional) and
  * g_eos (2*n_eos, optional) += the gamma / p_inf parts. */

@@ -151,6 +151,9 @@ def load():
     L.csph_step_vjp.restype = C.c_int32
     L.csph_step_vjp.argtypes = [C.POINTER(CsphState), C.POINTER(CsphParams), C.c_double,
                                 C.c_double, CsphGrad, CsphGrad, _dp, vp, sz, szp, vp]
+    L.csph_step_vjp_cfl.restype = C.c_int32
+    L.csph_step_vjp_cfl.argtypes = [C.POINTER(CsphState), C.POINTER(CsphParams), C.c_double,
+                                    CsphGrad, CsphGrad, _dp, _dp, vp, sz, szp, vp]
     L.csph_init_energy_vjp.restype = C.c_int32
     L.csph_init_energy_vjp.argtypes = [_dp, _dp, _dp, _dp, _dp, _ip, C.c_int64,
                                        C.POINTER(CsphParams), _dp, _dp, _dp, _dp, _dp, _dp, vp,

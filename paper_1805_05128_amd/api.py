@@ -507,6 +507,30 @@ def csph_step_vjp(s_n: State, params: Params, dt: float, g_next: Dict[str, torch
     return g_prev, g_eos
 
 
+def csph_step_vjp_cfl(s_n: State, params: Params, g_next: Dict[str, torch.Tensor],
+                      g_prev: Optional[Dict[str, torch.Tensor]] = None,
+                      g_eos: Optional[torch.Tensor] = None, ws: Optional[Workspace] = None,
+                      stream=None, t: float = 0.0):
+    """Cotangent of s_n from that of the state after one step taken at time ``t`` with the CFL
+    time step (params.cfl > 0), the step's dependence through dt included; returns
+    (g_prev, g_eos, dt), dt the step recomputed in FP64."""
+    L = N.load()
+    dev = s_n["x"].device
+    ws = ws or default_workspace(dev)
+    if g_prev is None:
+        g_prev = g_next
+    if g_eos is None:
+        g_eos = torch.zeros(2 * len(params.eos), dtype=torch.float64, device=dev)
+    s = s_n.c()
+    p = params.c()
+    gn, gp = _grad_struct(g_next), _grad_struct(g_prev)
+    dt = C.c_double(0.0)
+    _with_ws(lambda w, b, nd: L.csph_step_vjp_cfl(C.byref(s), C.byref(p), float(t), gn, gp,
+                                                  _dp(g_eos), C.byref(dt), w, b, nd,
+                                                  _stream(stream)), ws, "csph_step_vjp_cfl")
+    return g_prev, g_eos, dt.value
+
+
 def csph_init_energy_vjp(rho, pres, vx, vy, vz, mat, params: Params, gE, g_v=None, g_rho=None,
                          g_eos=None, ws: Optional[Workspace] = None, stream=None):
     L = N.load()

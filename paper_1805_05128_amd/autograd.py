@@ -49,17 +49,22 @@ class CSPHRollout(torch.autograd.Function):
     at fixed specific total energy); ``params`` the run parameters (its
     gammas are replaced by the ``gamma`` tensor); ``dts``, if given, is the
     list of time steps to use instead of the CFL rule; ``t0`` the start time
-    (the piston's position).  After the call, ``info['dts']`` holds the dt
-    sequence and ``info['forward_s']`` the forward wall time.
+    (the piston's position); ``cfl_adjoint`` differentiates the CFL time steps
+    too (csph_step_vjp_cfl; only without ``dts``), so that the gradient is that
+    of the rollout as run rather than of the map at its recorded steps.  After
+    the call, ``info['dts']`` holds the dt sequence and ``info['forward_s']``
+    the forward wall time.
     """
 
     @staticmethod
     def forward(ctx, vx0, vy0, vz0, gamma, base: Dict[str, torch.Tensor], params: A.Params,
                 nsteps: int, every: int, dts: Optional[List[float]], info: dict,
-                t0: float = 0.0):
+                t0: float = 0.0, cfl_adjoint: bool = False):
         import time
         torch.cuda.synchronize()
         tic = time.perf_counter()
+        if cfl_adjoint and (dts is not None or not params.cfl > 0.0):
+            raise ValueError("cfl_adjoint needs the CFL rule (cfl > 0) and no dts")
         pg = _with_gamma(params, gamma.detach().cpu().tolist())
         if "p" in base:
             E0 = A.csph_init_energy(base["rho"], base["p"], vx0, vy0, vz0, base["mat"], pg)
@@ -90,6 +95,7 @@ class CSPHRollout(torch.autograd.Function):
         ctx.ckpts = ckpts
         ctx.dts = dt_list
         ctx.ts = t_list
+        ctx.cfl_adjoint = cfl_adjoint
         ctx.params = pg
         ctx.every = every
         ctx.nsteps = nsteps
@@ -124,8 +130,15 @@ class CSPHRollout(torch.autograd.Function):
                 A.csph_step(s, replay, sc, s_out=s, dt_in=ctx.dts[k], totals=False)
                 states.append(_clone_state(s))
             for k in reversed(range(k0, k1)):
-                A.csph_step_vjp(states[k - k0], pg, ctx.dts[k], g, g_prev=g, g_eos=g_eos,
-                                t=ctx.ts[k])
+                if ctx.cfl_adjoint:
+                    _, _, dt = A.csph_step_vjp_cfl(states[k - k0], pg, g, g_prev=g, g_eos=g_eos,
+                                                   t=ctx.ts[k])
+                    if dt != ctx.dts[k]:
+                        raise RuntimeError(f"step {k}: the CFL step recomputed for its adjoint "
+                                           f"({dt!r}) differs from the forward's ({ctx.dts[k]!r})")
+                else:
+                    A.csph_step_vjp(states[k - k0], pg, ctx.dts[k], g, g_prev=g, g_eos=g_eos,
+                                    t=ctx.ts[k])
             states.clear()
         b = ctx.base
         if "p" in b:
@@ -134,18 +147,21 @@ class CSPHRollout(torch.autograd.Function):
         torch.cuda.synchronize()
         ctx.info["backward_s"] = time.perf_counter() - tic
         return (g["vx"], g["vy"], g["vz"], g_eos[0::2].clone(), None, None, None, None, None,
-                None, None)
+                None, None, None)
 
 
 def rollout(vx0, vy0, vz0, gamma, base, params, nsteps, every=10, dts=None, info=None,
-            t0: float = 0.0):
+            t0: float = 0.0, cfl_adjoint: bool = False):
     """Functional form of CSPHRollout.apply; returns a dict of final-state tensors.
 
     The gradient is that of the rollout at a FIXED time-step sequence: the forward records
     the CFL time steps it took (or takes ``dts``), and the backward differentiates the map
     with those steps held constant.  The dependence of the CFL step on the state and on
     gamma (through c, the closing speeds and rho/|drho/dt|) is not differentiated, so a
-    finite-difference check must replay the same steps."""
+    finite-difference check must replay the same steps.  With ``cfl_adjoint`` the CFL steps
+    are differentiated too (the forward must take them: no ``dts``), and a finite-difference
+    check reruns the CFL rule."""
     info = {} if info is None else info
-    out = CSPHRollout.apply(vx0, vy0, vz0, gamma, base, params, nsteps, every, dts, info, t0)
+    out = CSPHRollout.apply(vx0, vy0, vz0, gamma, base, params, nsteps, every, dts, info, t0,
+                            cfl_adjoint)
     return dict(zip(STATE8, out))

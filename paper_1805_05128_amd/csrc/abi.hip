@@ -1181,11 +1181,13 @@ static csph_grad kernel_view(const csph_grad &gr, const Axes &ax) {
     return v;
 }
 
-// shared body of csph_rates_vjp / csph_step_vjp (t: the time of the rates)
+// shared body of csph_rates_vjp / csph_step_vjp / csph_step_vjp_cfl (t: the time of the
+// rates; cfl_dt: the step's dt is the CFL rule's, recomputed here and differentiated)
 static csph_status vjp_common(const csph_state *s_in, const csph_params *p, double t,
                               const double *const a_in[5], const csph_grad *gnext_in, double dt,
                               csph_grad gout_in, int accumulate, double *g_eos, void *ws,
-                              size_t ws_bytes, size_t *ws_needed, hipStream_t st) {
+                              size_t ws_bytes, size_t *ws_needed, hipStream_t st,
+                              bool cfl_dt = false, double *dt_used = nullptr) {
     const csph_state *s = s_in;
     if (!state_ok(s) || s->n >= INT32_MAX) return fail(CSPH_EINVAL, "bad state");
     if (s->n >= kMaxPairN) return fail(CSPH_EINVAL, "n >= 2^27 particles");
@@ -1230,6 +1232,8 @@ static csph_status vjp_common(const csph_state *s_in, const csph_params *p, doub
     EosDev eos = eos_dev(p);
     ProfScope pr(CSPH_PROF_ADJOINT, st);
     double *const dsrt = pair ? w.srt_d : nullptr;  // pair-h mode: the sizes in cell order
+    // dt minimum and Z flag (the pack clears the flag where an impedance is zero)
+    CSPH_HIP(launch_fill_u64(w.dtmin, 0x7ff0000000000000ull, 2, st));
     CSPH_HIP(launch_bin(s->x, s->y, s->z, n, gd, w, w.perm, nullptr, w.cs, st));
     CSPH_HIP(launch_pack(*s, n, w.perm, eos, 0, gd, w, w.srt, w.srt_mat, dsrt, nullptr,
                          nullptr, nullptr, st));
@@ -1241,13 +1245,33 @@ static csph_status vjp_common(const csph_state *s_in, const csph_params *p, doub
         for (int k = 0; k < 8; ++k) gn[k] = tn[k];
     }
     const bool wall = p->wall != 0;
+    // the step's FP64 rates at t: for the reflections off the piston, and for the CFL step its
+    // signal speeds and dt
+    if (gnext && (wall || cfl_dt))
+        CSPH_HIP(launch_rates(n, 0, gd, pc, w, w.srt, dsrt, nullptr, t, cfl_dt ? 1 : 0, st));
+    DtInfo *info = nullptr;
+    if (cfl_dt) {
+        unsigned long long bits = 0;
+        CSPH_HIP(hipMemcpyAsync(&bits, w.dtmin, sizeof(bits), hipMemcpyDeviceToHost, st));
+        CSPH_HIP(hipStreamSynchronize(st));
+        double tau;
+        memcpy(&tau, &bits, sizeof(tau));
+        dt = p->cfl * tau;
+        if (!(dt > 0.0) || !std::isfinite(dt))
+            return fail(CSPH_EINVAL, "the CFL time step of this state is %g (not finite and > 0)",
+                        dt);
+        if (dt_used) *dt_used = dt;
+        // the binding slot and J's cotangent of dt (from the next state's cotangent as given,
+        // before the reflection's transpose below)
+        info = (DtInfo *)w.tot_part;
+        CSPH_HIP(launch_fill_u64(&info->arg, ~0ull, 1, st));
+        CSPH_HIP(launch_dt_adjoint(n, w.perm, w.srt, w, dsrt, p->h, gn, dt, wall,
+                                   p->wall_x0 + p->wall_v * (t + dt), p->wall_v, info, st));
+    }
     if (wall && gnext) {
-        // the step's reflections, found again from the FP64 rates at t; the cotangents of the
-        // pre-reflection y and v_y go to two arrays the adjoint leaves unused otherwise (the
-        // signal speeds this evaluation wrote, which nothing reads, and the ids it packs not)
-        CSPH_HIP(launch_fill_u64(w.dtmin, 0x7ff0000000000000ull, 2, st));
-        CSPH_HIP(launch_rates(n, 0, gd, pc, w, w.srt, dsrt, nullptr, t, 0, st));
-        double *gy = w.sig, *gvy = (double *)w.srt_id;
+        // the cotangents of the pre-reflection y and v_y go to the FP32 candidate records,
+        // which only the rate evaluation above reads (2 n + 4 doubles)
+        double *gy = (double *)w.recF, *gvy = gy + n;
         const double yw1 = p->wall_x0 + p->wall_v * (t + dt);
         CSPH_HIP(launch_vjp_reflect(n, w.perm, w.srt[1], w.srt[4], w.rate[2], dt, yw1, p->wall_v,
                                     gn[1], gn[4], gn[7], gy, gvy, st));
@@ -1255,9 +1279,10 @@ static csph_status vjp_common(const csph_state *s_in, const csph_params *p, doub
         gn[4] = gvy;
     }
     const double yw = wall ? p->wall_x0 + p->wall_v * t : 0.0;
+    const DtAdj da{info, p->cfl};
     CSPH_HIP(launch_vjp(n, w.perm, w.cs, gd, pc, eos, w, w.srt, w.srt_mat, a, go,
                         gnext ? gn : nullptr, dt, accumulate, g_eos, dsrt, wall, yw, p->wall_v,
-                        st));
+                        st, cfl_dt ? &da : nullptr));
     return CSPH_OK;
 }
 
@@ -1282,6 +1307,21 @@ csph_status csph_step_vjp(const csph_state *s_n, const csph_params *p, double t,
         return fail(CSPH_EINVAL, "the step's adjoint is that of the Euler step only");
     return vjp_common(s_n, p, t, nullptr, &g_next, dt, g_prev, 0, g_eos, ws, ws_bytes,
                       ws_needed, (hipStream_t)stream);
+}
+
+csph_status csph_step_vjp_cfl(const csph_state *s_n, const csph_params *p, double t,
+                              csph_grad g_next, csph_grad g_prev, double *g_eos, double *dt_used,
+                              void *ws, size_t ws_bytes, size_t *ws_needed,
+                              csph_stream stream) {
+    g_err[0] = 0;
+    if (s_n && s_n->n > 0 && !grad_ok(g_next)) return fail(CSPH_EINVAL, "g_next has NULL arrays");
+    if (p && p->integrator != CSPH_INT_EULER)
+        return fail(CSPH_EINVAL, "the step's adjoint is that of the Euler step only");
+    if (p && !(p->cfl > 0.0))
+        return fail(CSPH_EINVAL, "the CFL step's adjoint needs cfl > 0");
+    if (dt_used) *dt_used = 0.0;
+    return vjp_common(s_n, p, t, nullptr, &g_next, 0.0, g_prev, 0, g_eos, ws, ws_bytes,
+                      ws_needed, (hipStream_t)stream, true, dt_used);
 }
 
 csph_status csph_init_energy_vjp(const double *rho, const double *pres, const double *vx,

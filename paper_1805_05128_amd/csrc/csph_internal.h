@@ -341,12 +341,32 @@ hipError_t launch_init_energy(const double *rho, const double *pres, const doubl
                               const EosDev &eos, double *E, hipStream_t st);
 
 // k_adjoint.hip
+// The CFL time step's adjoint (csph_step_vjp_cfl): the slot whose tau = min(h/sig,
+// rho/|drho|) sets the step, which limit binds, and J's cotangent of dt.
+struct DtInfo {
+    unsigned long long arg;  // binding slot (cell order); ~0 before k_dt_argmin
+    int courant;             // 1: the Courant limit binds, 2: the density-change limit
+    int pad;
+    double rho, drho, sig, h;  // the binding slot's density, density rate, signal speed, h
+    double gdt;              // J's cotangent of dt
+};
+struct DtAdj {
+    DtInfo *info;
+    double cfl;
+};
+// Finds the binding slot (the FP64 rates and signal speeds of the step's state in w.rate,
+// w.sig, the minimum in w.dtmin) and g_dt from the next state's cotangent (input order).
+hipError_t launch_dt_adjoint(int64_t n, const int32_t *perm, double *const sorted[9],
+                             const Ws &w, const double *d_sorted, double h,
+                             const double *const gnext[8], double dt, int wall, double yw1,
+                             double vw, DtInfo *info, hipStream_t st);
 hipError_t launch_vjp(int64_t n, const int32_t *perm, const int32_t *cs, const GridDev &g,
                       const PairConst &pc, const EosDev &eos, const Ws &w,
                       double *const sorted[9], const int32_t *mat_sorted,
                       const double *const a_in[5], double *const gout[8],
                       const double *const gnext[8], double dt, int accumulate, double *g_eos,
-                      const double *d_sorted, int wall, double yw, double vw, hipStream_t st);
+                      const double *d_sorted, int wall, double yw, double vw, hipStream_t st,
+                      const DtAdj *dta = nullptr);
 // Step VJP with the piston: the cotangents of the pre-reflection y and v_y (input order) from
 // the next state's (the state and its rates in cell order; yw1 the wall at the step's end).
 hipError_t launch_vjp_reflect(int64_t n, const int32_t *perm, const double *y_s,

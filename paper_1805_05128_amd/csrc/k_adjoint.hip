@@ -478,12 +478,323 @@ __global__ __launch_bounds__(kBlock) void k_eos_grad_final(const double *__restr
     }
 }
 
+// ------------------------------------------------------------------ the CFL time step
+struct State8c {
+    const double *f[8];
+};
+struct Rates5c {
+    const double *f[5];
+};
+// What the binding particle's direct terms need (k_dt_fix): the state in cell order, its
+// sound speeds (C records), materials, sizes (pair h), the gradients (input order).
+struct DtFix {
+    const DtInfo *info;
+    double cfl;
+    const int32_t *perm, *cs;
+    const double *srt[8];
+    const int32_t *mat;
+    const double2 *C;
+    const double *dsz;
+    double *g[8];
+    double *g_eos;
+    double yw, vw2;  // the piston at the rates' time (kernels' y), twice its velocity
+    int wall;
+};
+
+// Adjoint of dt = cfl min_s tau_s, tau_s = min(h_s / sig_s, rho_s / |drho_s|), the FP64 rate
+// kernel's own expression, recomputed bit for bit from the rates and signal speeds it wrote.
+// J's cotangent of dt, g_dt, is a sum over all particles; dt's gradient is that of the one
+// tau that binds: through the signal speed (the Courant limit: sig_s = max(c_s, max over the
+// partners of max(c_s, c_j) + max(0, v_L - v_R)), whose maximum passes the gradient to the
+// partner attaining it) or through rho_s / |drho_s| (the density-change limit: the rate's
+// part enters the rate cotangent of that particle before the gather).
+
+// The slot that sets the step: tau_s equal to the minimum the rate kernel found (the
+// smallest such slot).
+__global__ __launch_bounds__(kBlock) void k_dt_argmin(int64_t n, const double *__restrict__ rho_s,
+                                                      const double *__restrict__ drho_s,
+                                                      const double *__restrict__ sig_s,
+                                                      const double *__restrict__ d_s, double h,
+                                                      const unsigned long long *dtmin,
+                                                      DtInfo *info) {
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    const double tau = fmin((d_s ? d_s[s] : h) / sig_s[s], rho_s[s] / fabs(drho_s[s]));
+    if (dbits(tau) == *dtmin) atomicMin(&info->arg, (unsigned long long)s);
+}
+
+// The binding particle's data, kept before the gather's weights overwrite the rates.
+__global__ void k_dt_pick(const double *__restrict__ rho_s, const double *__restrict__ drho_s,
+                          const double *__restrict__ sig_s, const double *__restrict__ d_s,
+                          double h, DtInfo *info) {
+    if (threadIdx.x != 0) return;
+    const unsigned long long s = info->arg;
+    info->courant = 0;
+    if (s == ~0ull) return;
+    info->rho = rho_s[s];
+    info->drho = drho_s[s];
+    info->sig = sig_s[s];
+    info->h = d_s ? d_s[s] : h;
+    info->courant = info->h / info->sig <= info->rho / fabs(info->drho) ? 1 : 2;
+}
+
+// g_dt = sum_i g_i . dU_i'/d dt over the Euler step v' = v + dt R_v, E' = E + dt R_E,
+// rho' = rho + dt R_rho, r' = r + dt v' (dr'/d dt = v + 2 dt R_v), the reflection off the
+// piston at yw1 = y_w(t + dt) transposed as in k_vjp_reflect, plus its explicit 2 v_w g_y''.
+// Per-block partial sums (fixed order).
+__global__ __launch_bounds__(kBlock) void k_dt_cot(int64_t n, const int32_t *__restrict__ perm,
+                                                   State8c u, Rates5c r, VjpOut o, int wall,
+                                                   double yw1, double vw,
+                                                   double *__restrict__ part) {
+    const double dt = o.dt;
+    double acc = 0.0;
+    for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < n;
+         s += (int64_t)gridDim.x * kBlock) {
+        const int i = perm[s];
+        const double Fr = r.f[0][s], Fx = r.f[1][s], Fy = r.f[2][s], Fz = r.f[3][s],
+                     FE = r.f[4][s];
+        double gy = o.gn[1][i], gvy = o.gn[4][i], extra = 0.0;
+        const double gE = o.gn[7][i];
+        if (wall && u.f[1][s] + dt * (u.f[4][s] + dt * Fy) < yw1) {
+            extra = 2.0 * vw * gy;
+            gvy = -gvy - 2.0 * vw * gE;
+            gy = -gy;
+        }
+        acc += ((o.gn[0][i] * (u.f[3][s] + 2.0 * dt * Fx) + gy * (u.f[4][s] + 2.0 * dt * Fy)) +
+                o.gn[2][i] * (u.f[5][s] + 2.0 * dt * Fz)) +
+               ((o.gn[3][i] * Fx + gvy * Fy) + o.gn[5][i] * Fz) +
+               (o.gn[6][i] * Fr + gE * FE) + extra;
+    }
+    __shared__ double sh[kBlock];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// info->gdt = sum of the partial sums, fixed order.
+__global__ __launch_bounds__(kBlock) void k_dt_cot_final(const double *__restrict__ part, int nb,
+                                                         DtInfo *info) {
+    __shared__ double sh[kBlock];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) acc += part[b];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) info->gdt = sh[0];
+}
+
+// The density-change limit binds: d tau/d drho = -rho sgn(drho) / drho^2 joins the rate
+// cotangent a_rho (and its pair weight b_rho = -2 rho a_rho) of the binding slot.
+__global__ void k_dt_fix_weights(const DtInfo *info, double cfl, const double *__restrict__ rho_s,
+                                 double *a0, double4 *Dw) {
+    if (threadIdx.x != 0 || info->courant != 2) return;
+    const unsigned long long s = info->arg;
+    const double dr = info->drho;
+    const double x = cfl * info->gdt * (-info->rho * (dr > 0.0 ? 1.0 : -1.0) / (dr * dr));
+    a0[s] += x;
+    Dw[s].x -= 2.0 * rho_s[s] * x;
+}
+
+// Partials of c^2 in (rho, e, gamma, p_inf) of material k.
+__device__ void c2_partials(const EosDev &eos, int k, double rho, double e, double &dr,
+                            double &de, double &dg, double &dpi) {
+    const double g = eos.gamma[k];
+    dpi = 0.0;
+    if (eos.type[k] == CSPH_EOS_MIE_GRUNEISEN) {
+        Dual3 P, c2;
+        mg_eos_dual(eos, k, rho, e, P, c2);
+        dr = c2.dr;
+        de = c2.de;
+        dg = c2.dg;
+    } else if (eos.type[k] == CSPH_EOS_STIFFENED) {
+        // c^2 = g (g-1) (e - p_inf/rho)
+        const double pinf = eos.pinf[k];
+        dr = g * (g - 1.0) * pinf / (rho * rho);
+        de = g * (g - 1.0);
+        dg = (2.0 * g - 1.0) * (e - pinf / rho);
+        dpi = -g * (g - 1.0) / rho;
+    } else {
+        // c^2 = g (g-1) e
+        dr = 0.0;
+        de = g * (g - 1.0);
+        dg = (2.0 * g - 1.0) * e;
+    }
+}
+
+// gc (a cotangent of c_s) through the EOS: c = sqrt(c^2(rho, e)), e = E - |v|^2/2.
+__device__ void c_chain(const DtFix &f, const EosDev &eos, int64_t s, double gc) {
+    const double c = f.C[s].y;
+    if (!(c > 0.0) || gc == 0.0) return;
+    int k = f.mat ? f.mat[s] : 0;
+    if (k < 0 || k >= eos.n) k = 0;
+    const double rho = f.srt[6][s], E = f.srt[7][s];
+    const double vx = f.srt[3][s], vy = f.srt[4][s], vz = f.srt[5][s];
+    const double e = E - 0.5 * ((vx * vx + vy * vy) + vz * vz);
+    double dr, de, dg, dpi;
+    c2_partials(eos, k, rho, e, dr, de, dg, dpi);
+    const double g2 = gc / (2.0 * c);
+    const int i = f.perm[s];
+    f.g[6][i] += g2 * dr;
+    f.g[7][i] += g2 * de;
+    f.g[3][i] -= g2 * de * vx;
+    f.g[4][i] -= g2 * de * vy;
+    f.g[5][i] -= g2 * de * vz;
+    if (f.g_eos) {
+        f.g_eos[2 * k] += g2 * dg;
+        f.g_eos[2 * k + 1] += g2 * dpi;
+    }
+}
+
+// Visits the particles of the cells within the reach of point p (cells off the mesh skipped).
+template <class F>
+__device__ void visit_cells(const GridDev &g, const int32_t *cs, double px, double py, double pz,
+                            F fn) {
+    const int cx = free_cell(px, g.ox, g.inv), cy = free_cell(py, g.oy, g.inv),
+              cz = free_cell(pz, g.oz, g.inv);
+    for (int zz = cz - g.reach; zz <= cz + g.reach; ++zz) {
+        if (zz < 0 || zz >= g.dz) continue;
+        for (int yy = cy - g.reach; yy <= cy + g.reach; ++yy) {
+            if (yy < 0 || yy >= g.dy) continue;
+            for (int xx = max(cx - g.reach, 0); xx <= min(cx + g.reach, g.dx - 1); ++xx) {
+                const uint32_t key = cell_key(g, xx, yy, zz);
+                for (int j = cs[key]; j < cs[key + 1]; ++j) fn(j);
+            }
+        }
+    }
+}
+
+// After the gather: the binding particle's direct terms.  Density-change limit: d tau/d rho =
+// 1/|drho|.  Courant limit: tau = h/sig, d tau/d sig = -h/sig^2; the signal speed's maximum
+// is found again over the particle's partners (real, periodic images, mirror images; the
+// forward pass's membership), and its gradient goes to the sound speed that attains
+// max(c_s, c_j) and, when the pair closes, to both velocities and positions through
+// v_L - v_R = (v_s - v_j).e (a mirror partner's y and v_y mapped back to j's).  One thread.
+__global__ void k_dt_fix(DtFix f, GridDev g, PairConst pc, EosDev eos) {
+    if (threadIdx.x != 0) return;
+    const DtInfo &in = *f.info;
+    if (in.courant == 0) return;
+    const int64_t s = (int64_t)in.arg;
+    const int i = f.perm[s];
+    const double G0 = f.cfl * in.gdt;
+    if (in.courant == 2) {
+        f.g[6][i] += G0 / fabs(in.drho);
+        return;
+    }
+    const double G = G0 * (-in.h / (in.sig * in.sig));
+    const double xi = f.srt[0][s], yi = f.srt[1][s], zi = f.srt[2][s];
+    const double vxi = f.srt[3][s], vyi = f.srt[4][s], vzi = f.srt[5][s];
+    const double ci = f.C[s].y;
+    const double di = f.dsz ? f.dsz[s] : 0.0;
+    // the best partner: slot, mirror flag, offsets
+    double best = ci;
+    int64_t bj = -1;
+    bool bghost = false;
+    double bd[3] = {0.0, 0.0, 0.0};
+    auto consider = [&](int j, bool ghost, double dx, double dy, double dz) {
+        double H2 = pc.H2;
+        if (pc.pair_mode) {
+            const double H = pc.kappa * (0.5 * (di + f.dsz[j]));
+            H2 = H * H;
+        }
+        const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
+        if (!(r2 < H2) || r2 == 0.0 || (!ghost && j == s)) return;
+        const double vyj = ghost ? f.vw2 - f.srt[4][j] : f.srt[4][j];
+        const double r = sqrt(r2);
+        const double vrel = (((vxi - f.srt[3][j]) * dx + (vyi - vyj) * dy) + (vzi - f.srt[5][j]) * dz) / r;
+        const double sp = fmax(ci, f.C[j].y) + (vrel > 0.0 ? vrel : 0.0);
+        if (sp > best) {
+            best = sp;
+            bj = j;
+            bghost = ghost;
+            bd[0] = dx;
+            bd[1] = dy;
+            bd[2] = dz;
+        }
+    };
+    const int nf = pc.per ? image_faces(pc, xi, yi, zi) : 0;
+    for (int m = 0; m < 8; ++m) {
+        if ((nf & m) != m) continue;
+        const double sx = image_shift(pc, nf, m, 0), sy = image_shift(pc, nf, m, 1),
+                     sz = image_shift(pc, nf, m, 2);
+        visit_cells(g, f.cs, xi + sx, yi + sy, zi + sz, [&](int j) {
+            consider(j, false, (f.srt[0][j] - xi) - sx, (f.srt[1][j] - yi) - sy,
+                     (f.srt[2][j] - zi) - sz);
+        });
+        if (f.wall) {  // mirror partners (the wall's axis y is never periodic)
+            visit_cells(g, f.cs, xi + sx, 2.0 * f.yw - yi, zi + sz, [&](int j) {
+                consider(j, true, (f.srt[0][j] - xi) - sx, (2.0 * f.yw - f.srt[1][j]) - yi,
+                         (f.srt[2][j] - zi) - sz);
+            });
+        }
+    }
+    if (bj < 0) {  // no partner exceeds c_s: sig = c_s
+        c_chain(f, eos, s, G);
+        return;
+    }
+    const double cj = f.C[bj].y;
+    if (ci >= cj)
+        c_chain(f, eos, s, G);
+    else
+        c_chain(f, eos, bj, G);
+    const double vyj = bghost ? f.vw2 - f.srt[4][bj] : f.srt[4][bj];
+    const double dv[3] = {vxi - f.srt[3][bj], vyi - vyj, vzi - f.srt[5][bj]};
+    const double r = sqrt(((bd[0] * bd[0]) + (bd[1] * bd[1])) + (bd[2] * bd[2]));
+    const double vrel = ((dv[0] * bd[0] + dv[1] * bd[1]) + dv[2] * bd[2]) / r;
+    if (!(vrel > 0.0)) return;
+    const int jj = f.perm[bj];
+    const double fy = bghost ? -1.0 : 1.0;  // j's y and v_y enter a mirror partner negated
+    for (int a = 0; a < 3; ++a) {
+        const double e = bd[a] / r;
+        const double q = (dv[a] - vrel * e) / r;  // d vrel / d (offset)
+        const double sj = a == 1 ? fy : 1.0;
+        f.g[3 + a][i] += G * e;
+        f.g[3 + a][jj] -= G * e * sj;
+        f.g[a][i] -= G * q;
+        f.g[a][jj] += G * q * sj;
+    }
+}
+
+hipError_t launch_dt_adjoint(int64_t n, const int32_t *perm, double *const sorted[9],
+                             const Ws &w, const double *d_sorted, double h,
+                             const double *const gnext[8], double dt, int wall, double yw1,
+                             double vw, DtInfo *info, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    k_dt_argmin<<<nb, kBlock, 0, st>>>(n, sorted[6], w.rate[0], w.sig, d_sorted, h, w.dtmin,
+                                       info);
+    k_dt_pick<<<1, 64, 0, st>>>(sorted[6], w.rate[0], w.sig, d_sorted, h, info);
+    State8c u;
+    for (int k = 0; k < 8; ++k) u.f[k] = sorted[k];
+    Rates5c r;
+    for (int k = 0; k < 5; ++k) r.f[k] = w.rate[k];
+    VjpOut o;
+    for (int k = 0; k < 8; ++k) {
+        o.g[k] = nullptr;
+        o.gn[k] = gnext[k];
+    }
+    o.dt = dt;
+    o.accumulate = 0;
+    o.eos_part = nullptr;
+    const unsigned nr = (unsigned)kReduceBlocks;
+    k_dt_cot<<<nr, kBlock, 0, st>>>(n, perm, u, r, o, wall, yw1, vw, w.bounds_part);
+    k_dt_cot_final<<<1, kBlock, 0, st>>>(w.bounds_part, (int)nr, info);
+    return hipGetLastError();
+}
+
 hipError_t launch_vjp(int64_t n, const int32_t *perm, const int32_t *cs, const GridDev &g,
                       const PairConst &pc, const EosDev &eos, const Ws &w,
                       double *const sorted[9], const int32_t *mat_sorted,
                       const double *const a_in[5], double *const gout[8],
                       const double *const gnext[8], double dt, int accumulate, double *g_eos,
-                      const double *d_sorted, int wall, double yw, double vw, hipStream_t st) {
+                      const double *d_sorted, int wall, double yw, double vw, hipStream_t st,
+                      const DtAdj *dta) {
     if (n <= 0) return hipSuccess;
     unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
     VjpOut o;
@@ -499,6 +810,9 @@ hipError_t launch_vjp(int64_t n, const int32_t *perm, const int32_t *cs, const G
                                          a_in ? a_in[3] : nullptr, a_in ? a_in[4] : nullptr,
                                          w.rate[0], w.rate[1], w.rate[2], w.rate[3], w.rate[4],
                                          (double4 *)w.recD, w.recE);
+    if (dta)  // the density-change limit's term, in the rate cotangent of the binding particle
+        k_dt_fix_weights<<<1, 64, 0, st>>>(dta->info, dta->cfl, sorted[6], w.rate[0],
+                                           (double4 *)w.recD);
     VjpIn in;
     in.A = (const double4 *)w.recA;
     in.B = (const double4 *)w.recB;
@@ -526,6 +840,23 @@ hipError_t launch_vjp(int64_t n, const int32_t *perm, const int32_t *cs, const G
     CSPH_VJP_CASE(true, true, true)
 #undef CSPH_VJP_CASE
     if (g_eos) k_eos_grad_final<<<1, kBlock, 0, st>>>(w.eos_part, (int64_t)nb, 2 * eos.n, g_eos);
+    if (dta) {
+        DtFix f;
+        f.info = dta->info;
+        f.cfl = dta->cfl;
+        f.perm = perm;
+        f.cs = cs;
+        for (int k = 0; k < 8; ++k) f.srt[k] = sorted[k];
+        f.mat = mat_sorted;
+        f.C = (const double2 *)w.recC;
+        f.dsz = d_sorted;
+        for (int k = 0; k < 8; ++k) f.g[k] = gout[k];
+        f.g_eos = g_eos;
+        f.yw = yw;
+        f.vw2 = 2.0 * vw;
+        f.wall = wall;
+        k_dt_fix<<<1, 64, 0, st>>>(f, g, pc, eos);
+    }
     return hipGetLastError();
 }
 

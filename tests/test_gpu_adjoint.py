@@ -894,3 +894,158 @@ def test_rollout_paper_mode_plates_reference_and_fd():
         pred = sum(float((grads[a].cpu().numpy() * dv[a]).sum()) for a in range(3)) + \
             float((grads[3].cpu().numpy() * dg).sum())
         assert abs(fd - pred) <= 1e-4 * max(abs(pred), 1e-8), (trial, fd, pred)
+
+
+def _cfl_case(name):
+    """(workload, t, extra Params fields, pair_h or None)"""
+    from test_adjoint_ref import periodic_system
+    if name == "gas":
+        return system(n=8, seed=41), 0.0, {}, None
+    if name == "piston":
+        return piston_system(seed=42), 0.3, {}, None
+    if name == "mg":
+        return mg_system(seed=43), 0.0, {}, None
+    if name == "expanding":  # the density-change limit binds
+        w = system(n=8, seed=44)
+        for k in ("x", "y", "z"):
+            v = getattr(w, k)
+            setattr(w, "v" + k, 2.0 * (v - v.mean()))
+        return w, 0.0, {}, None
+    if name == "periodic":
+        return periodic_system(7, seed=45), 0.0, {}, None
+    w = system(n=8, seed=46)  # pair h
+    d = np.random.default_rng(46).uniform(0.8, 1.3, w.n)
+    return w, 0.0, dict(h_mode="pair", kappa=1.936, cell_size=0.0), d
+
+
+@pytest.mark.parametrize("name", ["gas", "piston", "mg", "expanding", "periodic", "pair-h"])
+def test_step_vjp_cfl_matches_autograd_and_dot_product(name):
+    """The CFL step's adjoint (csph_step_vjp_cfl): dt recomputed in FP64 equals the GPU step's
+    and the oracle's; the gradient, with dt's dependence on the state and the EOS parameters
+    (the Courant limit through the signal speed's maximum, or the density-change limit),
+    against autograd of the FP64 reference; the dot-product test against the GPU's own CFL
+    steps, dt recomputed on every perturbed state."""
+    w, t, extra, d = _cfl_case(name)
+    print(f"[case] cfl vjp {name} n={w.n}", flush=True)
+    params = P.Params.from_workload(w, reorder=False, cfl=0.3, **extra)
+    g = P.state_from_workload(w, params, DEV)
+    if d is not None:
+        g.d = torch.as_tensor(d, device=DEV)
+    s = _np_state(g, w)
+    H = w.kappa * w.h
+    hmode = dict(h_mode=1, kappa=1.936) if d is not None else {}
+    cfg = O.cfg_for(w, cfl=0.3, **hmode)
+    if d is not None:
+        s["d"] = d
+    ph = None if d is None else (1.936, d)
+
+    def fwd(delta=None, eps=0.0):
+        tt = {k: g[k] + (eps * torch.as_tensor(delta[k], device=DEV) if delta else 0.0)
+              for k in F8}
+        tt["m"] = g["m"]
+        st2 = P.State(tt, g.mat, g.d)
+        sc = P.StepScalars(DEV, t0=t)
+        P.csph_step(st2, params, sc, s_out=st2)
+        return {k: st2[k].cpu().numpy() for k in F8}, float(sc.dt.item())
+
+    base, dt_gpu = fwd()
+    rng = np.random.default_rng(90)
+    lam = {k: rng.standard_normal(w.n) for k in F8}
+    gn = {k: torch.as_tensor(v, device=DEV).clone() for k, v in lam.items()}
+    gp, ge, dt = P.csph_step_vjp_cfl(g, params, gn, g_prev={k: torch.empty_like(v) for k, v in gn.items()},
+                                     t=t)
+    assert dt == dt_gpu
+    _, _, dt_o, _ = O.step(cfg, s, t, d=d)
+    assert abs(dt - dt_o) <= 1e-14 * dt_o
+    et = list(w.eos)
+    _, gg, pi = tparams(w, True)
+    m, mat = torch.as_tensor(w.m), torch.as_tensor(w.mat).long()
+    st = {k: torch.as_tensor(s[k]).clone().requires_grad_(True) for k in F8}
+    pairs = T.pairs_of(cfg, s)
+    mir, wt = None, None
+    if w.wall is not None:
+        xw = w.wall[0] + w.wall[1] * t
+        mir = T.mirror_pairs_of(s, H, xw, pair_h=ph)
+        wt = (xw, w.wall[1])
+    dtt = T.cfl_dt_torch(st, m, mat, et, gg, pi, pairs, H, 0.3, w.h, mirror=mir, wall=wt,
+                         pair_h=ph)
+    per = getattr(w, "periodic", 0)
+    out = T.step_torch(st, m, mat, et, gg, pi, pairs, H, dtt, mirror=mir, wall=w.wall, t=t,
+                       box=w.box, periodic=per, pair_h=ph)
+    for k in F8:
+        assert np.abs(out[k].detach().numpy() - base[k]).max() <= 1e-12 * (1 + np.abs(base[k]).max()), k
+    J = sum((out[k] * torch.as_tensor(lam[k])).sum() for k in F8)
+    ref = torch.autograd.grad(J, [st[k] for k in F8] + [gg, pi])
+    for a, k in enumerate(F8):
+        assert relmax(gp[k].cpu().numpy(), ref[a].numpy()) <= 1e-10, k
+    ge = ge.cpu().numpy()
+    assert relmax(ge[0::2], ref[8].numpy()) <= 1e-10
+    if w.eos[-1][0] == 1:
+        assert abs(ge[-1] - float(ref[9][-1])) <= 1e-10 * max(abs(float(ref[9][-1])), 1e-12)
+    dd = {k: rng.standard_normal(w.n) for k in F8}
+    eps = 1e-7
+    (fp, _), (fm, _) = fwd(dd, eps), fwd(dd, -eps)
+    jvp = sum(float(((fp[k] - fm[k]) / (2 * eps) * lam[k]).sum()) for k in F8)
+    vjp = sum(float((gp[k].cpu().numpy() * dd[k]).sum()) for k in F8)
+    assert abs(jvp - vjp) <= 1e-6 * max(abs(vjp), 1.0), (jvp, vjp)
+
+
+def test_rollout_cfl_adjoint_fd_with_the_cfl_rule():
+    """A rollout differentiated with its CFL steps (cfl_adjoint): central differences of the
+    GPU rollout that reruns the CFL rule on every perturbed start agree with the gradient, and
+    the FP64 CPU reference (autograd through dt) gives the same gradient; the frozen-dt
+    gradient of the same run does not."""
+    w = system(n=8, seed=47)
+    params = P.Params.from_workload(w, cfl=0.3)
+    base = _base(w, params)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float64), device=DEV)
+    v0 = [t(w.vx).requires_grad_(True), t(w.vy).requires_grad_(True), t(w.vz).requires_grad_(True)]
+    gamma = torch.tensor([e[1] for e in w.eos], dtype=torch.float64, device=DEV,
+                         requires_grad=True)
+    nsteps, every = 8, 3
+    info = {}
+    out = P.rollout(*v0, gamma, base, params, nsteps, every, info=info, cfl_adjoint=True)
+    mask = out["x"].detach() > 4.0
+    J = _objective(out, mask, base["m"])
+    grads = torch.autograd.grad(J, v0 + [gamma])
+    out0 = P.rollout(*v0, gamma, base, params, nsteps, every, dts=info["dts"])
+    g0 = torch.autograd.grad(_objective(out0, mask, base["m"]), v0 + [gamma])
+    assert relmax(g0[3].cpu().numpy(), grads[3].cpu().numpy()) > 1e-3  # dt's part matters
+    cfg = O.cfg_for(w)
+    et, gg, pi = tparams(w, True)
+    gg = gg.clone().detach().requires_grad_(True)
+    mat = torch.as_tensor(w.mat).long()
+    m = torch.as_tensor(w.m)
+    vr = [torch.as_tensor(a).clone().requires_grad_(True) for a in (w.vx, w.vy, w.vz)]
+    E0 = T.init_energy_torch(torch.as_tensor(w.rho), torch.as_tensor(w.p), *vr, mat, et, gg, pi)
+    st = {"x": torch.as_tensor(w.x), "y": torch.as_tensor(w.y), "z": torch.as_tensor(w.z),
+          "vx": vr[0], "vy": vr[1], "vz": vr[2], "rho": torch.as_tensor(w.rho), "E": E0}
+    H = w.kappa * w.h
+    for k in range(nsteps):
+        pairs = T.pairs_of(cfg, {kk: st[kk].detach().numpy() for kk in ("x", "y", "z")})
+        dtt = T.cfl_dt_torch(st, m, mat, et, gg, pi, pairs, H, 0.3, w.h)
+        assert abs(float(dtt.detach()) - info["dts"][k]) <= 1e-13 * info["dts"][k]
+        st = T.step_torch(st, m, mat, et, gg, pi, pairs, H, dtt)
+    mref = st["x"].detach() > 4.0
+    assert torch.equal(mref, mask.cpu())
+    Jr = (st["vx"][mref] * m[mref]).sum()
+    ref = torch.autograd.grad(Jr, vr + [gg])
+    for a in range(3):
+        assert relmax(grads[a].cpu().numpy(), ref[a].numpy()) <= 1e-9, a
+    assert relmax(grads[3].cpu().numpy(), ref[3].numpy()) <= 1e-9
+    rng = np.random.default_rng(48)
+    for trial in range(4):
+        dv = [rng.standard_normal(w.n) for _ in range(3)]
+        dg = rng.standard_normal(len(w.eos))
+        eps = 1e-7
+
+        def Jat(sign):
+            vv = [v0[a].detach() + sign * eps * t(dv[a]) for a in range(3)]
+            gm = gamma.detach() + sign * eps * t(dg)
+            o = P.rollout(*vv, gm, base, params, nsteps, every)  # the CFL rule, rerun
+            return float(_objective(o, mask, base["m"]))
+
+        fd = (Jat(1) - Jat(-1)) / (2 * eps)
+        pred = sum(float((grads[a].cpu().numpy() * dv[a]).sum()) for a in range(3)) + \
+            float((grads[3].cpu().numpy() * dg).sum())
+        assert abs(fd - pred) <= 1e-4 * max(abs(pred), 1e-8), (trial, fd, pred)
