@@ -7,9 +7,11 @@ reverse: it restores a segment's checkpoint, recomputes the segment's
 states with the recorded time steps (bit-identical to the forward), then
 applies csph_step_vjp step by step and finally the VJP of the initial
 energy E0 = e(rho, p; gamma) + |v0|^2/2 when the rollout starts from
-(rho, p) (a window that starts from (rho, E) holds E fixed).  The time
-steps are held fixed (replayed), i.e. the gradient is that of the map at
-the recorded dt sequence.  The start time of every step is recorded too:
+(rho, p) (a window that starts from (rho, E) holds E fixed).  By default
+the time steps are held fixed (replayed), i.e. the gradient is that of the
+map at the recorded dt sequence; with ``cfl_adjoint`` each step's VJP is
+csph_step_vjp_cfl, which differentiates the CFL step as well.  The start
+time of every step is recorded too:
 with the piston, the segments are replayed from their own start times and
 each step's VJP places the wall where the step did.
 """
@@ -154,7 +156,7 @@ def rollout(vx0, vy0, vz0, gamma, base, params, nsteps, every=10, dts=None, info
             t0: float = 0.0, cfl_adjoint: bool = False):
     """Functional form of CSPHRollout.apply; returns a dict of final-state tensors.
 
-    The gradient is that of the rollout at a FIXED time-step sequence: the forward records
+    By default the gradient is that of the rollout at a FIXED time-step sequence: the forward records
     the CFL time steps it took (or takes ``dts``), and the backward differentiates the map
     with those steps held constant.  The dependence of the CFL step on the state and on
     gamma (through c, the closing speeds and rho/|drho/dt|) is not differentiated, so a
