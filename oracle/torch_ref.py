@@ -276,6 +276,63 @@ def step_torch(st, m, mat, eos_type, gamma, pinf, pairs, H: float, dt: float, mi
             "vx": vx, "vy": vy, "vz": vz, "rho": st["rho"] + dt * drho, "E": E}
 
 
+def step_rk2_torch(st, m, mat, eos_type, gamma, pinf, pairs_at, H: float, dt: float,
+                   mirror_at=None, wall=None, t: float = 0.0, box=None, periodic: int = 0,
+                   pair_h=None):
+    """The two-stage Runge-Kutta step with frozen dt, as the oracle takes it (Shu and Osher's
+    convex form): U1 = U + dt F(U, t), r1 = r + dt v; U' = U/2 + (U1 + dt F(U1, t + dt))/2,
+    r' = r/2 + (r1 + dt v1)/2; the second evaluation sees r1 wrapped into a periodic box (and
+    the piston at x_w(t + dt)); then the reflection and the wrap of the Euler step.
+    ``pairs_at(pos)`` and ``mirror_at(pos, x_w)`` give the pair lists of a set of positions
+    (numpy arrays x, y, z), taken at the values (fixed for the gradient)."""
+    def wrap(pos):
+        out = list(pos)
+        for a in range(3):
+            if (periodic >> a) & 1:
+                lo, hi = float(box[0][a]), float(box[1][a])
+                L = hi - lo
+                p = out[a]
+                up, down = (p >= hi).detach(), (p < lo).detach()
+                out[a] = torch.where(up, p - L, torch.where(down, p + L, p))
+        return out
+
+    def npos(q):
+        return {k: v.detach().numpy() for k, v in zip(("x", "y", "z"), q)}
+
+    def rates_at(u, pos, tt):
+        xw = None if wall is None else wall[0] + wall[1] * tt
+        mir = None if wall is None else mirror_at(npos(pos), xw)
+        su = {"x": pos[0], "y": pos[1], "z": pos[2], "vx": u["vx"], "vy": u["vy"],
+              "vz": u["vz"], "rho": u["rho"], "E": u["E"]}
+        return rates_torch(su, m, mat, eos_type, gamma, pinf, pairs_at(npos(pos)), H,
+                           mirror=mir, wall=None if wall is None else (xw, wall[1]),
+                           pair_h=pair_h)
+
+    r0 = [st["x"], st["y"], st["z"]]
+    f0 = rates_at(st, r0, t)
+    u1 = {"vx": st["vx"] + dt * f0[1], "vy": st["vy"] + dt * f0[2], "vz": st["vz"] + dt * f0[3],
+          "E": st["E"] + dt * f0[4], "rho": st["rho"] + dt * f0[0]}
+    r1 = [st[k] + dt * st["v" + k] for k in ("x", "y", "z")]
+    f1 = rates_at(u1, wrap(r1), t + dt)
+    vx = 0.5 * st["vx"] + 0.5 * (u1["vx"] + dt * f1[1])
+    vy = 0.5 * st["vy"] + 0.5 * (u1["vy"] + dt * f1[2])
+    vz = 0.5 * st["vz"] + 0.5 * (u1["vz"] + dt * f1[3])
+    E = 0.5 * st["E"] + 0.5 * (u1["E"] + dt * f1[4])
+    rho = 0.5 * st["rho"] + 0.5 * (u1["rho"] + dt * f1[0])
+    pos = [0.5 * r0[a] + 0.5 * (r1[a] + dt * u1["v" + k]) for a, k in enumerate("xyz")]
+    x = pos[0]
+    if wall is not None:
+        xw = wall[0] + wall[1] * (t + dt)
+        behind = (x < xw).detach()
+        vr = 2.0 * wall[1] - vx
+        E = torch.where(behind, E + 0.5 * ((vr * vr) - (vx * vx)), E)
+        vx = torch.where(behind, vr, vx)
+        x = torch.where(behind, 2.0 * xw - x, x)
+    pos = wrap([x, pos[1], pos[2]])
+    return {"x": pos[0], "y": pos[1], "z": pos[2], "vx": vx, "vy": vy, "vz": vz, "rho": rho,
+            "E": E}
+
+
 def to_torch(s) -> Dict[str, torch.Tensor]:
     return {k: torch.as_tensor(np.asarray(s[k], np.float64)) for k in FIELDS8}
 

@@ -547,3 +547,71 @@ def test_cfl_step_gradient_matches_oracle_finite_differences(case):
 
         fd = (J_at(1) - J_at(-1)) / (2 * eps)
         assert abs(fd - pred) <= 1e-6 * max(abs(pred), 1.0), (trial, fd, pred)
+
+
+@pytest.mark.parametrize("case", ["gas", "piston", "periodic", "pair-h"])
+def test_rk2_step_gradient_matches_oracle_finite_differences(case):
+    """The two-stage Runge-Kutta step (second evaluation at U1 and t + dt, wrapped positions,
+    the piston's mirror partners there): the reference's forward against the C oracle's RK2
+    step and its gradient against central differences of it."""
+    d, ph, hm = None, None, {}
+    if case == "gas":
+        w, t, dt = system(n=6, seed=51), 0.0, 0.1
+    elif case == "piston":
+        w, t, dt = wall_system(seed=52), 0.3, 0.2
+    elif case == "periodic":
+        w, t, dt = periodic_system(7, seed=53), 0.0, 0.2
+    else:
+        w, d = pair_h_system(seed=54)
+        t, dt, ph, hm = 0.0, 0.1, (1.936, d), dict(h_mode=1, kappa=1.936)
+    cfg = O.cfg_for(w, cfl=0.0, integrator=1, **hm)
+    s = O.state_from(w, cfg)
+    if d is not None:
+        s["d"] = d
+    H = w.kappa * w.h
+    per = getattr(w, "periodic", 0)
+    box = getattr(w, "box", None)
+
+    def pairs_at(pos):
+        q = dict(pos)
+        if d is not None:
+            q["d"] = d
+        return T.pairs_of(cfg, q)
+
+    def mirror_at(pos, xw):
+        return T.mirror_pairs_of(pos, H, xw, box=box, periodic=per, pair_h=ph)
+
+    et, g, pi = tparams(w)
+    st = {k: v.clone().requires_grad_(True) for k, v in T.to_torch(s).items()}
+    g = g.clone().requires_grad_(True)
+    pi = pi.clone().requires_grad_(True)
+    m = torch.as_tensor(s["m"])
+    mat = torch.as_tensor(s["mat"]).long()
+    out = T.step_rk2_torch(st, m, mat, et, g, pi, pairs_at, H, dt, mirror_at=mirror_at,
+                           wall=w.wall, t=t, box=box, periodic=per, pair_h=ph)
+    s1_base, _, _, _ = O.step(cfg, s, t, dt_in=dt, d=d)
+    for k in F8:
+        assert np.abs(out[k].detach().numpy() - s1_base[k]).max() <= 1e-13 * (1 + np.abs(s1_base[k]).max()), k
+    rng = np.random.default_rng(100)
+    lam = {k: rng.standard_normal(w.n) for k in F8}
+    J = sum((out[k] * torch.as_tensor(lam[k])).sum() for k in F8)
+    grads = torch.autograd.grad(J, [st[k] for k in F8] + [g, pi])
+    for trial in range(3):
+        dd = {k: rng.standard_normal(w.n) for k in F8}
+        dg = rng.standard_normal(len(w.eos))
+        dpi = rng.standard_normal(len(w.eos)) * np.array([0.0 if e[0] == 0 else 1.0 for e in w.eos])
+        pred = sum(float((grads[a].numpy() * dd[k]).sum()) for a, k in enumerate(F8))
+        pred += float((grads[8].numpy() * dg).sum()) + float((grads[9].numpy() * dpi).sum())
+        eps = 1e-6
+
+        def J_at(sign):
+            s2 = {k: (s[k] + sign * eps * dd[k]) if k in dd else s[k] for k in s}
+            kw = dict(h=w.h, kappa=w.kappa, cfl=0.0, wall=w.wall, periodic=per, box=box,
+                      integrator=1)
+            kw.update(hm)
+            c2 = O.make_cfg(_eos_shifted(w.eos, sign, eps, dg, dpi), **kw)
+            s1, _, _, _ = O.step(c2, s2, t, dt_in=dt, d=d)
+            return sum(float((s1[k] * lam[k]).sum()) for k in F8)
+
+        fd = (J_at(1) - J_at(-1)) / (2 * eps)
+        assert abs(fd - pred) <= 1e-6 * max(abs(pred), 1.0), (trial, fd, pred)
