@@ -147,9 +147,9 @@ typedef struct {
                           else CSPH_EINVAL.  Not taken by the Verlet-list and adjoint calls
                           (CSPH_EINVAL).  0: open boundaries */
     double box_lo[3], box_hi[3]; /* the periodic box (read on the periodic axes only) */
-    int32_t integrator; /* CSPH_INT_EULER | CSPH_INT_RK2 (csph_step, csph_step_static; the
-                           Voronoi, Verlet-list and adjoint steps take EULER only, else
-                           CSPH_EINVAL) */
+    int32_t integrator; /* CSPH_INT_EULER | CSPH_INT_RK2 (csph_step, csph_step_static,
+                           csph_step_mesh, csph_step_vjp; the Voronoi, Verlet-list and
+                           CFL-adjoint steps take EULER only, else CSPH_EINVAL) */
     int32_t pad2;
 } csph_params;
 
@@ -481,8 +481,8 @@ csph_status csph_rates_vjp(const csph_state *s, const csph_params *p, double t,
                            csph_rates_out a, csph_grad g_state, double *g_eos, void *ws,
                            size_t ws_bytes, size_t *ws_needed, csph_stream stream);
 
-/* VJP of one Euler csph_step taken at time t with the time step dt held
- * fixed (the step's own dt, replayed): s_n is the state the step started
+/* VJP of one csph_step (either integrator) taken at time t with the time
+ * step dt held fixed (the step's own dt, replayed): s_n is the state the step started
  * from, g_next the cotangent of the state after it (same particle order,
  * i.e. a step taken with reorder = 0), g_prev receives (d s_{n+1} / d s_n)^T
  * g_next (it may alias g_next), g_eos is accumulated as in csph_rates_vjp.
@@ -490,7 +490,11 @@ csph_status csph_rates_vjp(const csph_state *s, const csph_params *p, double t,
  * are found again from an FP64 evaluation of the rates at t (the step's own
  * test, x + dt (v_x + dt R_vx) < x_w(t + dt)), and the reflection's Jacobian is
  * applied to their cotangents; the branch itself is not differentiated.  The
- * periodic wrap is a translation (identity Jacobian). */
+ * periodic wrap is a translation (identity Jacobian).  The RK2 step's VJP is
+ * composed of the rate VJPs of its two evaluations (U1 = U + dt F(U, t), the
+ * second at U1 and t + dt) and an FP64 rate evaluation that forms U1; it takes
+ * 28 n doubles of workspace beyond those calls' own (CSPH_ECAPACITY reports
+ * the total) and synchronises three times. */
 csph_status csph_step_vjp(const csph_state *s_n, const csph_params *p, double t, double dt,
                           csph_grad g_next, csph_grad g_prev, double *g_eos, void *ws,
                           size_t ws_bytes, size_t *ws_needed, csph_stream stream);

@@ -1297,14 +1297,101 @@ csph_status csph_rates_vjp(const csph_state *s, const csph_params *p, double t,
                       (hipStream_t)stream);
 }
 
+// The RK2 step's VJP (dt fixed), composed of the two evaluations' rate VJPs and the
+// elementwise parts of launch_rk2_vjp_stage2/1 (whose comment gives the algebra): a forward
+// FP64 rate evaluation at U gives U1; the rate VJP at U1 (time t + dt) completes g_U1; the one
+// at U (time t) completes g_U.  Scratch arrays take the workspace's first 28 n doubles; the
+// rate calls lay theirs out after them.
+static csph_status step_vjp_rk2(const csph_state *s, const csph_params *p, double t, double dt,
+                                csph_grad gn, csph_grad gp, double *g_eos, void *ws,
+                                size_t ws_bytes, size_t *ws_needed, hipStream_t st) {
+    if (!state_ok(s) || s->n >= INT32_MAX) return fail(CSPH_EINVAL, "bad state");
+    csph_status r = check_params(p, s->n > 0, s->d);
+    if (r) return r;
+    const int64_t n = s->n;
+    if (n > 0 && (!grad_ok(gp) || !grad_ok(gn)))
+        return fail(CSPH_EINVAL, "gradient arrays must not be NULL");
+    if (!std::isfinite(t)) return fail(CSPH_EINVAL, "t not finite");
+    const size_t arr = align256(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    const size_t off = 28 * arr;
+    if (ws_bytes < off) {
+        const size_t need = off + ws_layout(nullptr, nullptr, n, 1);
+        if (ws_needed) *ws_needed = need;
+        return fail(CSPH_ECAPACITY, "workspace needs at least %zu bytes, got %zu", need, ws_bytes);
+    }
+    if (n == 0) {
+        if (ws_needed) *ws_needed = off;
+        return CSPH_OK;
+    }
+    char *b = (char *)ws;
+    auto take = [&](int k) { return (double *)(b + (size_t)k * arr); };
+    Rk2Vjp q;
+    const double *sv[8] = {s->x, s->y, s->z, s->vx, s->vy, s->vz, s->rho, s->E};
+    const double *gv[8] = {gn.x, gn.y, gn.z, gn.vx, gn.vy, gn.vz, gn.rho, gn.E};
+    for (int k = 0; k < 8; ++k) {
+        q.s[k] = sv[k];
+        q.gn[k] = gv[k];
+        q.u1[k] = take(k);
+        q.gu1[k] = take(15 + k);
+    }
+    double *F[5];
+    for (int k = 0; k < 5; ++k) {
+        F[k] = take(8 + k);
+        q.F[k] = F[k];
+        q.a[k] = take(23 + k);
+    }
+    q.gx = take(13);
+    q.gvx = take(14);
+    q.dt = dt;
+    q.wall = p->wall != 0;
+    q.vw = p->wall_v;
+    q.xw1 = p->wall_x0 + p->wall_v * (t + dt);
+    q.per = p->periodic;
+    for (int a = 0; a < 3; ++a) {
+        q.lo[a] = p->box_lo[a];
+        q.hi[a] = p->box_hi[a];
+    }
+    csph_params pf = *p;  // the FP64 map
+    pf.precision = CSPH_FP64;
+    pf.integrator = CSPH_INT_EULER;
+    void *wr = b + off;
+    const size_t wrb = ws_bytes - off;
+    size_t need = 0;
+    auto sized = [&](csph_status rs) {
+        if (rs == CSPH_ECAPACITY && ws_needed) *ws_needed = off + need;
+        return rs;
+    };
+    // F(U) at t
+    r = csph_rates(s, &pf, t, csph_rates_out{F[0], F[1], F[2], F[3], F[4]}, nullptr, nullptr,
+                   nullptr, wr, wrb, &need, st);
+    if (r) return sized(r);
+    CSPH_HIP(launch_rk2_vjp_stage2(n, q, st));
+    // g_U1 += F(U1)^T (dt/2) g'_(rho, v, E), at t + dt with U1's wrapped positions
+    const csph_state u1{n, q.u1[0], q.u1[1], q.u1[2], q.u1[3], q.u1[4], q.u1[5], q.u1[6],
+                        q.u1[7], s->m, s->mat, s->d, nullptr};
+    const csph_grad g1{q.gu1[0], q.gu1[1], q.gu1[2], q.gu1[3], q.gu1[4], q.gu1[5], q.gu1[6],
+                       q.gu1[7]};
+    const csph_rates_out a{q.a[0], q.a[1], q.a[2], q.a[3], q.a[4]};
+    r = csph_rates_vjp(&u1, &pf, t + dt, a, g1, g_eos, wr, wrb, &need, st);
+    if (r) return sized(r);
+    double *gpv[8] = {gp.x, gp.y, gp.z, gp.vx, gp.vy, gp.vz, gp.rho, gp.E};
+    CSPH_HIP(launch_rk2_vjp_stage1(n, q, gpv, st));
+    // g_U += F(U)^T dt g_U1,(rho, v, E), at t
+    r = csph_rates_vjp(s, &pf, t, a, gp, g_eos, wr, wrb, &need, st);
+    if (r) return sized(r);
+    if (ws_needed) *ws_needed = off + need;
+    return CSPH_OK;
+}
+
 csph_status csph_step_vjp(const csph_state *s_n, const csph_params *p, double t, double dt,
                           csph_grad g_next, csph_grad g_prev, double *g_eos, void *ws,
                           size_t ws_bytes, size_t *ws_needed, csph_stream stream) {
     g_err[0] = 0;
     if (!std::isfinite(dt) || dt < 0.0) return fail(CSPH_EINVAL, "dt must be finite and >= 0");
     if (s_n && s_n->n > 0 && !grad_ok(g_next)) return fail(CSPH_EINVAL, "g_next has NULL arrays");
-    if (p && p->integrator != CSPH_INT_EULER)
-        return fail(CSPH_EINVAL, "the step's adjoint is that of the Euler step only");
+    if (p && p->integrator == CSPH_INT_RK2)
+        return step_vjp_rk2(s_n, p, t, dt, g_next, g_prev, g_eos, ws, ws_bytes, ws_needed,
+                            (hipStream_t)stream);
     return vjp_common(s_n, p, t, nullptr, &g_next, dt, g_prev, 0, g_eos, ws, ws_bytes,
                       ws_needed, (hipStream_t)stream);
 }

@@ -369,6 +369,23 @@ hipError_t launch_vjp(int64_t n, const int32_t *perm, const int32_t *cs, const G
                       const DtAdj *dta = nullptr);
 // Step VJP with the piston: the cotangents of the pre-reflection y and v_y (input order) from
 // the next state's (the state and its rates in cell order; yw1 the wall at the step's end).
+// The RK2 step's VJP: its elementwise parts (k_adjoint.hip), in input order and the caller's
+// axes.
+struct Rk2Vjp {
+    const double *s[8];   // U: x y z vx vy vz rho E
+    const double *F[5];   // F(U): drho dvx dvy dvz dE
+    const double *gn[8];  // the cotangent of the step's output
+    double *u1[8];        // U1, its positions wrapped into the periodic box
+    double *gx, *gvx;     // g' of x and v_x (the piston's reflection transposed)
+    double *gu1[8];       // g_U1
+    double *a[5];         // rate cotangents (rho vx vy vz E)
+    double dt, xw1, vw;   // xw1: the piston at t + dt
+    int wall, per;        // per: periodic axes (caller's), box [lo, hi)
+    double lo[3], hi[3];
+};
+hipError_t launch_rk2_vjp_stage2(int64_t n, const Rk2Vjp &q, hipStream_t st);
+hipError_t launch_rk2_vjp_stage1(int64_t n, const Rk2Vjp &q, double *const gp[8],
+                                 hipStream_t st);
 hipError_t launch_vjp_reflect(int64_t n, const int32_t *perm, const double *y_s,
                               const double *vy_s, const double *dvy_s, double dt, double yw1,
                               double vw, const double *gy, const double *gvy, const double *gE,

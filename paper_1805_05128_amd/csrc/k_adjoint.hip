@@ -893,6 +893,101 @@ hipError_t launch_vjp_reflect(int64_t n, const int32_t *perm, const double *y_s,
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ the RK2 step
+// The two-stage step U1 = U + dt F(U, t), r1 = r + dt v; U' = U/2 + (U1 + dt F(U1, t + dt))/2,
+// r' = r/2 + (r1 + dt v1)/2, then the reflection off the piston at t + dt and the wrap.  With
+// g' the cotangent of (r', U') (the reflection transposed; the wrap is a translation):
+//   g_U1 = (g'_r/2, g'_v/2 + (dt/2) g'_r, g'_rho/2, g'_E/2) + F(U1)^T (dt/2) g'_(rho, v, E)
+//   g_U  = g'/2 + (g_U1,r, g_U1,v + dt g_U1,r, g_U1,rho, g_U1,E) + F(U)^T dt g_U1,(rho, v, E)
+// The F^T terms are rate VJPs (the library's own); these kernels form the rest, elementwise
+// in input order and the caller's axes (the piston is normal to x).
+__device__ __forceinline__ double wrap_box(const Rk2Vjp &q, int a, double v) {
+    if (!((q.per >> a) & 1)) return v;
+    if (v >= q.hi[a]) return v - (q.hi[a] - q.lo[a]);
+    if (v < q.lo[a]) return v + (q.hi[a] - q.lo[a]);
+    return v;
+}
+
+// U1 (formed as the forward step forms it), g' (the reflection transposed, tested on
+// x' = x/2 + (x1 + dt v1x)/2 as the step tests it), the direct part of g_U1 and the rate
+// cotangents (dt/2) g'_(rho, v, E) of the second evaluation.
+__global__ __launch_bounds__(kBlock) void k_rk2_vjp_stage2(int64_t n, Rk2Vjp q) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double dt = q.dt;
+    double v1[3], r1[3];
+    for (int a = 0; a < 3; ++a) {
+        v1[a] = q.s[3 + a][i] + dt * q.F[1 + a][i];
+        r1[a] = q.s[a][i] + dt * q.s[3 + a][i];
+        q.u1[a][i] = wrap_box(q, a, r1[a]);
+        q.u1[3 + a][i] = v1[a];
+    }
+    q.u1[6][i] = q.s[6][i] + dt * q.F[0][i];
+    q.u1[7][i] = q.s[7][i] + dt * q.F[4][i];
+    double g[8];
+    for (int k = 0; k < 8; ++k) g[k] = q.gn[k][i];
+    if (q.wall && 0.5 * q.s[0][i] + 0.5 * (r1[0] + dt * v1[0]) < q.xw1) {
+        g[3] = -g[3] - 2.0 * q.vw * g[7];
+        g[0] = -g[0];
+    }
+    q.gx[i] = g[0];
+    q.gvx[i] = g[3];
+    const double h = 0.5 * dt;
+    for (int a = 0; a < 3; ++a) {
+        q.gu1[a][i] = 0.5 * g[a];
+        q.gu1[3 + a][i] = 0.5 * g[3 + a] + h * g[a];
+        q.a[1 + a][i] = h * g[3 + a];
+    }
+    q.gu1[6][i] = 0.5 * g[6];
+    q.gu1[7][i] = 0.5 * g[7];
+    q.a[0][i] = h * g[6];
+    q.a[4][i] = h * g[7];
+}
+
+// After the rate VJP at U1 has completed g_U1: the rate cotangents dt g_U1,(rho, v, E) of the
+// first evaluation and g_U's direct part (gp may alias the output's cotangent: each element
+// is read before it is written).
+__global__ __launch_bounds__(kBlock) void k_rk2_vjp_stage1(int64_t n, Rk2Vjp q, double *gp0,
+                                                           double *gp1, double *gp2,
+                                                           double *gp3, double *gp4,
+                                                           double *gp5, double *gp6,
+                                                           double *gp7) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double dt = q.dt;
+    double g[8], u[8];
+    for (int k = 0; k < 8; ++k) {
+        g[k] = q.gn[k][i];
+        u[k] = q.gu1[k][i];
+    }
+    g[0] = q.gx[i];
+    g[3] = q.gvx[i];
+    double *gp[8] = {gp0, gp1, gp2, gp3, gp4, gp5, gp6, gp7};
+    for (int a = 0; a < 3; ++a) {
+        gp[a][i] = 0.5 * g[a] + u[a];
+        gp[3 + a][i] = 0.5 * g[3 + a] + (u[3 + a] + dt * u[a]);
+        q.a[1 + a][i] = dt * u[3 + a];
+    }
+    gp[6][i] = 0.5 * g[6] + u[6];
+    gp[7][i] = 0.5 * g[7] + u[7];
+    q.a[0][i] = dt * u[6];
+    q.a[4][i] = dt * u[7];
+}
+
+hipError_t launch_rk2_vjp_stage2(int64_t n, const Rk2Vjp &q, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_rk2_vjp_stage2<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(n, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_rk2_vjp_stage1(int64_t n, const Rk2Vjp &q, double *const gp[8],
+                                 hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_rk2_vjp_stage1<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+        n, q, gp[0], gp[1], gp[2], gp[3], gp[4], gp[5], gp[6], gp[7]);
+    return hipGetLastError();
+}
+
 // dE0/d(gamma, p_inf, v, rho) of E0 = e0(rho, p; gamma, p_inf) + |v|^2/2,
 // e0 = p/((g-1) rho) (ideal), (p + g p_inf)/((g-1) rho) (stiffened), or
 // e_r + (p - P_r)/(Gamma rho) (Mie-Grueneisen: d/dGamma in the gamma slot).

@@ -217,7 +217,7 @@ def test_periodic_params_checked_on_the_host():
 
 def test_integrator_checked_on_the_host():
     """An unknown integrator, and the two-stage Runge-Kutta step where only the Euler step is
-    taken (Verlet-list steps, the step's adjoint), are refused before any device work; the
+    taken (Verlet-list steps, the CFL step's adjoint), are refused before any device work; the
     workspace of a Runge-Kutta step is larger."""
     L = N.load()
     p = P.Params().c()
@@ -232,7 +232,7 @@ def test_integrator_checked_on_the_host():
                            dev(1 << 22, C.c_double), C.c_void_p(1 << 23), None, 0, None, None)
     assert st == N.CSPH_EINVAL and b"Euler" in L.csph_last_error()
     g = N.CsphGrad(*[dev((1 << 25) + 1024 * k, C.c_double) for k in range(8)])
-    st = L.csph_step_vjp(C.byref(a), C.byref(p), 0.0, 0.1, g, g, None, None, 0, None, None)
+    st = L.csph_step_vjp_cfl(C.byref(a), C.byref(p), 0.0, g, g, None, None, None, 0, None, None)
     assert st == N.CSPH_EINVAL and b"Euler" in L.csph_last_error()
     assert P.workspace_size(1000, 100, P.Params(integrator="rk2")) > \
         P.workspace_size(1000, 100, P.Params()) + 1000 * 150

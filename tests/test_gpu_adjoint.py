@@ -1049,3 +1049,116 @@ def test_rollout_cfl_adjoint_fd_with_the_cfl_rule():
         pred = sum(float((grads[a].cpu().numpy() * dv[a]).sum()) for a in range(3)) + \
             float((grads[3].cpu().numpy() * dg).sum())
         assert abs(fd - pred) <= 1e-4 * max(abs(pred), 1e-8), (trial, fd, pred)
+
+
+def _rk2_case(name):
+    """(workload, t, dt, extra Params fields, d or None)"""
+    from test_adjoint_ref import periodic_system
+    if name == "gas":
+        return system(n=8, seed=61), 0.0, 0.08, {}, None
+    if name == "piston":
+        return piston_system(seed=62), 0.3, 0.2, {}, None
+    if name == "periodic":
+        return periodic_system(7, seed=63), 0.0, 0.2, {}, None
+    w = system(n=8, seed=64)
+    d = np.random.default_rng(64).uniform(0.8, 1.3, w.n)
+    return w, 0.0, 0.08, dict(h_mode="pair", kappa=1.936, cell_size=0.0), d
+
+
+@pytest.mark.parametrize("name", ["gas", "piston", "periodic", "pair-h"])
+def test_rk2_step_vjp_matches_autograd_and_dot_product(name):
+    """The RK2 step's VJP (two rate VJPs composed, dt fixed): against autograd of the FP64
+    reference's RK2 step, and the dot-product test against the GPU's own RK2 steps."""
+    w, t, dt, extra, d = _rk2_case(name)
+    print(f"[case] rk2 vjp {name} n={w.n}", flush=True)
+    params = P.Params.from_workload(w, reorder=False, integrator="rk2", **extra)
+    replay = P.Params.from_workload(w, reorder=False, integrator="rk2", cfl=0.0, **extra)
+    g = P.state_from_workload(w, params, DEV)
+    if d is not None:
+        g.d = torch.as_tensor(d, device=DEV)
+    s = _np_state(g, w)
+    H = w.kappa * w.h
+    ph = None if d is None else (1.936, d)
+    hm = dict(h_mode=1, kappa=1.936) if d is not None else {}
+    cfg = O.cfg_for(w, **hm)
+    per = getattr(w, "periodic", 0)
+    box = getattr(w, "box", None)
+
+    def fwd(delta=None, eps=0.0):
+        tt = {k: g[k] + (eps * torch.as_tensor(delta[k], device=DEV) if delta else 0.0)
+              for k in F8}
+        tt["m"] = g["m"]
+        st2 = P.State(tt, g.mat, g.d)
+        P.csph_step(st2, replay, P.StepScalars(DEV, t0=t), s_out=st2, dt_in=dt)
+        return {k: st2[k].cpu().numpy() for k in F8}
+
+    base = fwd()
+    rng = np.random.default_rng(110)
+    lam = {k: rng.standard_normal(w.n) for k in F8}
+    gn = {k: torch.as_tensor(v, device=DEV).clone() for k, v in lam.items()}
+    gp, ge = P.csph_step_vjp(g, params, dt, gn, g_prev={k: torch.empty_like(v) for k, v in gn.items()},
+                             t=t)
+
+    def pairs_at(pos):
+        q = dict(pos)
+        if d is not None:
+            q["d"] = d
+        return T.pairs_of(cfg, q)
+
+    def mirror_at(pos, xw):
+        return T.mirror_pairs_of(pos, H, xw, box=box, periodic=per, pair_h=ph)
+
+    et, gg, pi = tparams(w, True)
+    m, mat = torch.as_tensor(w.m), torch.as_tensor(w.mat).long()
+    st = {k: torch.as_tensor(s[k]).clone().requires_grad_(True) for k in F8}
+    out = T.step_rk2_torch(st, m, mat, et, gg, pi, pairs_at, H, dt, mirror_at=mirror_at,
+                           wall=w.wall, t=t, box=box, periodic=per, pair_h=ph)
+    for k in F8:
+        assert np.abs(out[k].detach().numpy() - base[k]).max() <= 1e-12 * (1 + np.abs(base[k]).max()), k
+    J = sum((out[k] * torch.as_tensor(lam[k])).sum() for k in F8)
+    ref = torch.autograd.grad(J, [st[k] for k in F8] + [gg, pi])
+    for a, k in enumerate(F8):
+        assert relmax(gp[k].cpu().numpy(), ref[a].numpy()) <= 1e-10, k
+    assert relmax(ge.cpu().numpy()[0::2], ref[8].numpy()) <= 1e-10
+    dd = {k: rng.standard_normal(w.n) for k in F8}
+    eps = 1e-6
+    fp, fm = fwd(dd, eps), fwd(dd, -eps)
+    jvp = sum(float(((fp[k] - fm[k]) / (2 * eps) * lam[k]).sum()) for k in F8)
+    vjp = sum(float((gp[k].cpu().numpy() * dd[k]).sum()) for k in F8)
+    assert abs(jvp - vjp) <= 1e-7 * max(abs(vjp), 1.0), (jvp, vjp)
+
+
+def test_rollout_rk2_piston_fd():
+    """A rollout of RK2 steps with the piston (porous 10^3 sample, 8 FP64 CFL steps replayed,
+    checkpoint every 3) against central differences of the GPU forward."""
+    w = ci.config2(nside=10)
+    params = P.Params.from_workload(w, cfl=0.3, integrator="rk2")
+    base = _base(w, params)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float64), device=DEV)
+    v0 = [t(w.vx).requires_grad_(True), t(w.vy).requires_grad_(True), t(w.vz).requires_grad_(True)]
+    gamma = torch.tensor([e[1] for e in w.eos], dtype=torch.float64, device=DEV,
+                         requires_grad=True)
+    nsteps, every, t0 = 8, 3, 0.05
+    info = {}
+    P.rollout(*v0, gamma, base, params, nsteps, every, info=info, t0=t0)
+    dts = info["dts"]
+    out = P.rollout(*v0, gamma, base, params, nsteps, every, dts=dts, t0=t0)
+    mask = out["x"].detach() > float(np.median(w.x))
+    J = _objective(out, mask, base["m"])
+    grads = torch.autograd.grad(J, v0 + [gamma])
+    rng = np.random.default_rng(111)
+    for trial in range(4):
+        dv = [rng.standard_normal(w.n) for _ in range(3)]
+        dg = rng.standard_normal(len(w.eos))
+        eps = 1e-6
+
+        def Jat(sign):
+            vv = [v0[a].detach() + sign * eps * t(dv[a]) for a in range(3)]
+            gm = gamma.detach() + sign * eps * t(dg)
+            o = P.rollout(*vv, gm, base, params, nsteps, every, dts=dts, t0=t0)
+            return float(_objective(o, mask, base["m"]))
+
+        fd = (Jat(1) - Jat(-1)) / (2 * eps)
+        pred = sum(float((grads[a].cpu().numpy() * dv[a]).sum()) for a in range(3)) + \
+            float((grads[3].cpu().numpy() * dg).sum())
+        assert abs(fd - pred) <= 1e-4 * max(abs(pred), 1e-8), (trial, fd, pred)
