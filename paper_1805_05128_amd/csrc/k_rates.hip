@@ -137,8 +137,11 @@ constexpr int kRing = kQ * kSlot;                        // bytes per wave's rin
 constexpr int kRate64Block = kBlock;
 constexpr int kSlot64 = kRate64Block * (int)sizeof(int);  // FP64 kernel: bytes per ring row
 // workgroups per die chunk (xcd_block; measured on the porous shock's 100 steps, where the
-// wall band's costly waves made one die the last to finish): ~33 k / ~16 k particles
-constexpr unsigned kRate32Chunk = 512;
+// wall band's costly waves made one die the last to finish): ~131 k / ~16 k particles.  The
+// FP32 kernel's 2 048-wave chunks read 1.86 GB per launch beyond L2 (512: 2.31 GB, 1 024:
+// 2.01 GB) in the same time; 4 096 leaves an eighth of the waves outside the whole rounds of
+// chunks, unmapped, and reads 4.1 GB.
+constexpr unsigned kRate32Chunk = 2048;
 constexpr unsigned kRate64Chunk = 64;
 
 // min over the wave of v >= 0 into *dst (bits of a non-negative double); the atomic is
