@@ -137,12 +137,13 @@ constexpr int kRing = kQ * kSlot;                        // bytes per wave's rin
 constexpr int kRate64Block = kBlock;
 constexpr int kSlot64 = kRate64Block * (int)sizeof(int);  // FP64 kernel: bytes per ring row
 // workgroups per die chunk (xcd_block; measured on the porous shock's 100 steps, where the
-// wall band's costly waves made one die the last to finish): ~131 k / ~16 k particles.  The
+// wall band's costly waves made one die the last to finish): ~131 k / ~65 k particles.  The
 // FP32 kernel's 2 048-wave chunks read 1.86 GB per launch beyond L2 (512: 2.31 GB, 1 024:
 // 2.01 GB) in the same time; 4 096 leaves an eighth of the waves outside the whole rounds of
-// chunks, unmapped, and reads 4.1 GB.
+// chunks, unmapped, and reads 4.1 GB.  The FP64 kernel's 256 four-wave groups read 3.51 GB
+// (64: 4.73 GB, 512: 3.22 GB), again in the same time.
 constexpr unsigned kRate32Chunk = 2048;
-constexpr unsigned kRate64Chunk = 64;
+constexpr unsigned kRate64Chunk = 256;
 
 // min over the wave of v >= 0 into *dst (bits of a non-negative double); the atomic is
 // skipped when it cannot lower the current value
