@@ -1162,3 +1162,52 @@ def test_rollout_rk2_piston_fd():
         pred = sum(float((grads[a].cpu().numpy() * dv[a]).sum()) for a in range(3)) + \
             float((grads[3].cpu().numpy() * dg).sum())
         assert abs(fd - pred) <= 1e-4 * max(abs(pred), 1e-8), (trial, fd, pred)
+
+
+def test_vjp_empty_and_lone_particle():
+    """Edge cases: every VJP entry point on an empty state (nothing written, g_eos unchanged);
+    the CFL step's VJP for one moving particle without partners, where s = c and dt =
+    cfl h / c(e), e = E - |v|^2/2 (ideal gas: c^2 = gamma (gamma - 1) e), against the closed
+    form of the gradient of J = lam . U' (U' = U except r' = r + dt v)."""
+    params = P.Params(eos=[(0, 1.4, 0.0)])
+    e0 = P.State.empty(0, DEV)
+    z = {k: torch.zeros(0, dtype=torch.float64, device=DEV) for k in F8}
+    ge = torch.zeros(2, dtype=torch.float64, device=DEV)
+    cot = {k: torch.zeros(0, dtype=torch.float64, device=DEV) for k in ("drho", "dvx", "dvy", "dvz", "dE")}
+    P.csph_rates_vjp(e0, params, cot, g_state=dict(z), g_eos=ge)
+    P.csph_step_vjp(e0, params, 0.1, dict(z), g_eos=ge)
+    P.csph_step_vjp(e0, P.Params(eos=[(0, 1.4, 0.0)], integrator="rk2"), 0.1, dict(z), g_eos=ge)
+    P.csph_step_vjp_cfl(e0, params, dict(z), g_eos=ge)
+    torch.cuda.synchronize()
+    assert ge.abs().sum().item() == 0.0
+    # one particle moving at v = (0.3, -0.2, 0.1)
+    g, h, cfl = 1.4, 1.5, 0.3
+    v = np.array([0.3, -0.2, 0.1])
+    rho, p = 1.2, 0.8
+    e = p / ((g - 1.0) * rho)
+    E = e + 0.5 * float(v @ v)
+    t1 = lambda a: torch.tensor([a], dtype=torch.float64, device=DEV)
+    st = P.State({"x": t1(1.0), "y": t1(2.0), "z": t1(3.0), "vx": t1(v[0]), "vy": t1(v[1]),
+                  "vz": t1(v[2]), "rho": t1(rho), "E": t1(E), "m": t1(rho)},
+                 torch.zeros(1, dtype=torch.int32, device=DEV))
+    prm = P.Params(eos=[(0, g, 0.0)], h=h, cfl=cfl, reorder=False)
+    lam = {k: float(x) for k, x in zip(F8, np.random.default_rng(120).standard_normal(8))}
+    gn = {k: t1(lam[k]) for k in F8}
+    ge = torch.zeros(2, dtype=torch.float64, device=DEV)
+    gp, ge, dt = P.csph_step_vjp_cfl(st, prm, gn, g_prev={k: t1(0.0) for k in F8}, g_eos=ge)
+    c = np.sqrt(g * (g - 1.0) * e)
+    assert abs(dt - cfl * h / c) <= 1e-15 * dt
+    gdt = lam["x"] * v[0] + lam["y"] * v[1] + lam["z"] * v[2]   # dJ/d dt
+    dtdc = -cfl * h / (c * c)
+    dcde = g * (g - 1.0) / (2.0 * c)
+    expect = {"x": lam["x"], "y": lam["y"], "z": lam["z"],
+              "vx": lam["vx"] + dt * lam["x"] - gdt * dtdc * dcde * v[0],
+              "vy": lam["vy"] + dt * lam["y"] - gdt * dtdc * dcde * v[1],
+              "vz": lam["vz"] + dt * lam["z"] - gdt * dtdc * dcde * v[2],
+              "rho": lam["rho"], "E": lam["E"] + gdt * dtdc * dcde}
+    for k in F8:
+        got = float(gp[k].item())
+        assert abs(got - expect[k]) <= 1e-12 * max(1.0, abs(expect[k])), (k, got, expect[k])
+    # d dt/d gamma through c^2 = gamma (gamma - 1) e
+    dgamma = gdt * dtdc * (2.0 * g - 1.0) * e / (2.0 * c)
+    assert abs(float(ge[0].item()) - dgamma) <= 1e-12 * max(1.0, abs(dgamma))
