@@ -358,3 +358,60 @@ def test_collision64m_adjoint_last5_steps():
               flush=True)
         assert abs(fd - pred) <= 1e-4 * abs(pred), (trial, fd, pred)
         del dvz
+
+
+def test_porous256_piston_adjoint_window():
+    """The porous shock 256^3 with the piston: 45 mixed steps, then the adjoint of an FP64
+    window of 5 steps from that state and time (mirror partners, reflections off the piston),
+    checked by central differences along 4 directions on the band next to the piston."""
+    w = ci.config2()
+    print(f"[case] {w.name} piston adjoint of steps 46-50 n={w.n}", flush=True)
+    n = w.n
+    params = P.Params.from_workload(w, precision="mixed", reorder=True)
+    window = P.Params.from_workload(w, precision="fp64")
+    g = P.state_from_workload(w, params, DEV, with_id=False)
+    gamma = torch.tensor([e[1] for e in w.eos], dtype=torch.float64, device=DEV)
+    x0, vw = w.wall
+    del w
+    sc = P.StepScalars(DEV)
+    other = g.like()
+    ws = P.Workspace(DEV)
+    for _ in range(45):
+        g, other = P.csph_step(g, params, sc, s_out=other, ws=ws, totals=False), g
+    torch.cuda.synchronize()
+    t45 = float(sc.t.item())
+    del other, ws
+    torch.cuda.empty_cache()
+    base = {k: g.t[k] for k in ("x", "y", "z", "rho", "E", "m")}
+    base["mat"] = g.mat
+    m = base["m"]
+    v0 = [g.t[k].clone().requires_grad_(True) for k in ("vx", "vy", "vz")]
+    info = {}
+    out = P.rollout(*v0, gamma, base, window, 5, 5, info=info, t0=t45)
+    dts = info["dts"]
+    xw_end = x0 + vw * (t45 + sum(dts))
+    assert float(out["x"].detach().min()) >= xw_end  # the piston holds in the window
+    near = out["x"].detach() < xw_end + 6.0  # objective: x-momentum of the band at the piston
+    J = (out["vx"][near] * m[near]).sum()
+    grads = torch.autograd.grad(J, v0)
+    print("window dts", dts, "adjoint/forward %.2f" % (info["backward_s"] / info["forward_s"]),
+          flush=True)
+    del out
+    x = base["x"]
+    band = (x < x0 + vw * t45 + 10.0).to(torch.float64)
+    gen = torch.Generator(device=DEV).manual_seed(2025)
+    eps = 1e-6
+    for trial in range(4):
+        d = [torch.randn(n, generator=gen, dtype=torch.float64, device=DEV) * band
+             for _ in range(3)]
+        pred = sum(float((grads[a] * d[a]).sum()) for a in range(3))
+
+        def vx_at(sign):
+            vv = [v0[a].detach() + sign * eps * d[a] for a in range(3)]
+            return P.rollout(*vv, gamma, base, window, 5, 5, dts=dts, t0=t45)["vx"]
+
+        dvx = vx_at(1) - vx_at(-1)
+        fd = float((m * dvx)[near].sum()) / (2 * eps)
+        print(f"trial {trial}: fd {fd:.10e} adjoint {pred:.10e}", flush=True)
+        assert abs(fd - pred) <= 1e-4 * abs(pred), (trial, fd, pred)
+        del dvx
