@@ -192,10 +192,11 @@ def default_workspace(device="cuda") -> Workspace:
 
 
 def _with_ws(fn, ws: Workspace, where: str, accept=()):
-    """Call fn(ws_ptr, ws_bytes, needed_ptr); grow the workspace once on CSPH_ECAPACITY.
+    """Call fn(ws_ptr, ws_bytes, needed_ptr); grow the workspace on CSPH_ECAPACITY (a call
+    that bins twice, such as an RK2 step or its VJP, can learn its needs one mesh at a time).
     Statuses in ``accept`` are returned instead of raised."""
     needed = C.c_size_t(0)
-    for _ in range(3):
+    for _ in range(4):
         st = fn(ws.ptr, ws.nbytes, C.byref(needed))
         if st == N.CSPH_ECAPACITY and needed.value > ws.nbytes:
             ws.ensure(needed.value)

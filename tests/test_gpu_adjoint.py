@@ -1211,3 +1211,24 @@ def test_vjp_empty_and_lone_particle():
     # d dt/d gamma through c^2 = gamma (gamma - 1) e
     dgamma = gdt * dtdc * (2.0 * g - 1.0) * e / (2.0 * c)
     assert abs(float(ge[0].item()) - dgamma) <= 1e-12 * max(1.0, abs(dgamma))
+
+
+def test_rk2_step_vjp_grows_a_fresh_workspace():
+    """The RK2 step's VJP on a fresh, small workspace: it learns its scratch and both meshes'
+    needs over the binding's retries and returns the same gradient as with a large one."""
+    w, t, dt, extra, d = _rk2_case("piston")
+    params = P.Params.from_workload(w, reorder=False, integrator="rk2", **extra)
+    g = P.state_from_workload(w, params, DEV)
+    rng = np.random.default_rng(130)
+    gn = {k: torch.as_tensor(rng.standard_normal(w.n), device=DEV) for k in F8}
+    big = P.Workspace(DEV)
+    big.ensure(1 << 28)
+    ga, ea = P.csph_step_vjp(g, params, dt, gn, g_prev={k: torch.empty_like(v) for k, v in gn.items()},
+                             ws=big, t=t)
+    small = P.Workspace(DEV)
+    gb, eb = P.csph_step_vjp(g, params, dt, gn, g_prev={k: torch.empty_like(v) for k, v in gn.items()},
+                             ws=small, t=t)
+    torch.cuda.synchronize()
+    for k in F8:
+        assert torch.equal(ga[k], gb[k]), k
+    assert torch.equal(ea, eb)
