@@ -104,6 +104,19 @@ __device__ __forceinline__ int64_t xcd_block(unsigned b, unsigned nb) {
     return ((int64_t)(t / C) * kXcd + x) * C + t % C;
 }
 
+// The same with chunks of at most C workgroups, smaller in a launch of fewer than four
+// rounds of such chunks (whose groups would otherwise keep their numbers, spread over the
+// dies): C' = min(C, nb / (4 kXcd)), at least 1.  Wave-uniform, so the compiler keeps it in
+// scalar registers.
+__device__ __forceinline__ int64_t xcd_block_upto(unsigned b, unsigned nb, unsigned C) {
+    unsigned c = nb / (4u * kXcd);
+    c = c < 1u ? 1u : (c < C ? c : C);
+    const unsigned round = kXcd * c, full = nb / round * round;
+    if (b >= full) return b;
+    const unsigned x = b % kXcd, t = b / kXcd;
+    return ((int64_t)(t / c) * kXcd + x) * c + t % c;
+}
+
 // Per-call constants of the pair interaction.
 struct PairConst {
     double H;        // support (fixed mode)

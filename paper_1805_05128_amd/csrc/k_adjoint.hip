@@ -224,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
                                                   VjpWall wl) {
     __shared__ int qj[kQ][kBlock];
     const int tid = threadIdx.x;
-    const int64_t blk = xcd_block<256>(blockIdx.x, gridDim.x);  // as the FP64 rate kernel
+    const int64_t blk = xcd_block_upto(blockIdx.x, gridDim.x, 256);  // as the FP64 rate kernel
     const int64_t s = blk * kBlock + tid;
     const bool live = s < n;
     double ge_gamma = 0.0, ge_pinf = 0.0;

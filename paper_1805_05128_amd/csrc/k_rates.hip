@@ -136,8 +136,9 @@ constexpr int kSlot = kRate32Block * (int)sizeof(float4);  // bytes per ring row
 constexpr int kRing = kQ * kSlot;                        // bytes per wave's rings
 constexpr int kRate64Block = kBlock;
 constexpr int kSlot64 = kRate64Block * (int)sizeof(int);  // FP64 kernel: bytes per ring row
-// workgroups per die chunk (xcd_block; measured on the porous shock's 100 steps, where the
-// wall band's costly waves made one die the last to finish): ~131 k / ~65 k particles.  The
+// most workgroups per die chunk (xcd_block_upto; measured on the porous shock's 100 steps,
+// where the wall band's costly waves made one die the last to finish): ~131 k / ~65 k
+// particles, fewer in launches too small for four rounds of such chunks.  The
 // FP32 kernel's 2 048-wave chunks read 1.86 GB per launch beyond L2 (512: 2.31 GB, 1 024:
 // 2.01 GB) in the same time; 4 096 leaves an eighth of the waves outside the whole rounds of
 // chunks, unmapped, and reads 4.1 GB.  The FP64 kernel's 256 four-wave groups read 3.51 GB
@@ -520,7 +521,8 @@ __global__ __launch_bounds__(kRate64Block, 4) void k_rates64(int64_t n, const do
     k.cs = cs;
     k.g = g;
     k.pc = pc;
-    const int64_t s = xcd_block<kRate64Chunk>(blockIdx.x, gridDim.x) * kRate64Block + threadIdx.x;
+    const int64_t s =
+        xcd_block_upto(blockIdx.x, gridDim.x, kRate64Chunk) * kRate64Block + threadIdx.x;
     k.self32 = (uint32_t)s * (uint32_t)sizeof(double4);
     k.live = s < n;
     k.a = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -916,7 +918,8 @@ __global__ __launch_bounds__(kRate32Block) void k_rates32(int64_t n, const float
     k.pc = pc;
     k.qb = (char *)&qd[0][0];
     k.lane16 = threadIdx.x * (int)sizeof(float4);
-    const int64_t s = xcd_block<kRate32Chunk>(blockIdx.x, gridDim.x) * kRate32Block + threadIdx.x;
+    const int64_t s =
+        xcd_block_upto(blockIdx.x, gridDim.x, kRate32Chunk) * kRate32Block + threadIdx.x;
     k.self16 = (uint32_t)s * (uint32_t)sizeof(float4);
     k.live = s < n;
     k.a = make_float4(0.f, 0.f, 0.f, 0.f);
