@@ -487,9 +487,12 @@ csph_status csph_rates_vjp(const csph_state *s, const csph_params *p, double t,
  * i.e. a step taken with reorder = 0), g_prev receives (d s_{n+1} / d s_n)^T
  * g_next (it may alias g_next), g_eos is accumulated as in csph_rates_vjp.
  * With the piston, the particles the step reflected off the wall at t + dt
- * are found again from an FP64 evaluation of the rates at t (the step's own
- * test, x + dt (v_x + dt R_vx) < x_w(t + dt)), and the reflection's Jacobian is
- * applied to their cotangents; the branch itself is not differentiated.  The
+ * are found again by the step's own test, x + dt (v_x + dt R_vx) < x_w(t + dt),
+ * with R_vx in FP64 (the Euler step takes it from the sums its gather forms, in
+ * another order than the rate kernel's: a particle ending within rounding of
+ * the plane may be taken differently; the RK2 step evaluates the FP64 rates),
+ * and the reflection's Jacobian is applied to their cotangents; the branch
+ * itself is not differentiated.  The
  * periodic wrap is a translation (identity Jacobian).  The RK2 step's VJP is
  * composed of the rate VJPs of its two evaluations (U1 = U + dt F(U, t), the
  * second at U1 and t + dt) and an FP64 rate evaluation that forms U1; it takes

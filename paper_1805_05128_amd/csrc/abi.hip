@@ -7,6 +7,7 @@
 #include <utility>
 #include <vector>
 
+#include "adjoint.h"
 #include "csph_internal.h"
 
 namespace csph {
@@ -1245,10 +1246,38 @@ static csph_status vjp_common(const csph_state *s_in, const csph_params *p, doub
         for (int k = 0; k < 8; ++k) gn[k] = tn[k];
     }
     const bool wall = p->wall != 0;
-    // the step's FP64 rates at t: for the reflections off the piston, and for the CFL step its
-    // signal speeds and dt
-    if (gnext && (wall || cfl_dt))
-        CSPH_HIP(launch_rates(n, 0, gd, pc, w, w.srt, dsrt, nullptr, t, cfl_dt ? 1 : 0, st));
+    const double yw = wall ? p->wall_x0 + p->wall_v * t : 0.0;
+    if (wall && gnext && !cfl_dt) {
+        // the step's reflections, found from each particle's own rate sums that the gathers
+        // form (first pass, the cotangent as given), then the gather of the change the
+        // reflection's transpose makes to the flagged particles' cotangents, over the wall
+        // band only
+        const double yw1 = p->wall_x0 + p->wall_v * (t + dt);
+        int32_t *flag = w.bin_tmp;             // free after the binning
+        unsigned long long *reach = w.yenc;    // unused without a caller's mesh
+        // the change a reflection would make, formed before the first pass writes g (which
+        // may alias the cotangent), in the FP32 candidate records the adjoint does not read;
+        // the signal-speed array (no rate evaluation here) takes the rate sums, then zeros
+        double *dy = (double *)w.recF, *dvy = dy + n, *svy = w.sig;
+        CSPH_HIP(launch_reflect_delta(n, gn[1], gn[4], gn[7], p->wall_v, dy, dvy, st));
+        CSPH_HIP(launch_fill_u64(reach, 0ull, 1, st));
+        CSPH_HIP(launch_vjp_wall(n, w.perm, w.cs, gd, pc, eos, w, w.srt, w.srt_mat, nullptr, go,
+                                 gn, dt, 0, g_eos, dsrt, yw, p->wall_v,
+                                 WallPass{svy, nullptr}, st));
+        CSPH_HIP(launch_wall_flags(n, w.perm, w.srt, svy, dt, yw1, yw, flag, reach, st));
+        // kept for the flagged particles; zeros for the other fields
+        CSPH_HIP(launch_keep_flagged(n, flag, dy, dvy, st));
+        CSPH_HIP(launch_fill_u64((unsigned long long *)svy, 0ull, n, st));
+        const double *zero = svy;
+        const double *dn[8] = {zero, dy, zero, zero, dvy, zero, zero, zero};
+        CSPH_HIP(launch_vjp_wall(n, w.perm, w.cs, gd, pc, eos, w, w.srt, w.srt_mat, nullptr, go,
+                                 dn, dt, 1, g_eos, dsrt, yw, p->wall_v,
+                                 WallPass{nullptr, reach}, st));
+        return CSPH_OK;
+    }
+    // the CFL step's FP64 rates at t: its signal speeds, dt and (with the piston) reflections
+    if (gnext && cfl_dt)
+        CSPH_HIP(launch_rates(n, 0, gd, pc, w, w.srt, dsrt, nullptr, t, 1, st));
     DtInfo *info = nullptr;
     if (cfl_dt) {
         unsigned long long bits = 0;
@@ -1269,8 +1298,8 @@ static csph_status vjp_common(const csph_state *s_in, const csph_params *p, doub
                                    p->wall_x0 + p->wall_v * (t + dt), p->wall_v, info, st));
     }
     if (wall && gnext) {
-        // the cotangents of the pre-reflection y and v_y go to the FP32 candidate records,
-        // which only the rate evaluation above reads (2 n + 4 doubles)
+        // (the CFL step) the cotangents of the pre-reflection y and v_y go to the FP32
+        // candidate records, which only the rate evaluation above reads (2 n + 4 doubles)
         double *gy = (double *)w.recF, *gvy = gy + n;
         const double yw1 = p->wall_x0 + p->wall_v * (t + dt);
         CSPH_HIP(launch_vjp_reflect(n, w.perm, w.srt[1], w.srt[4], w.rate[2], dt, yw1, p->wall_v,
@@ -1278,7 +1307,6 @@ static csph_status vjp_common(const csph_state *s_in, const csph_params *p, doub
         gn[1] = gy;
         gn[4] = gvy;
     }
-    const double yw = wall ? p->wall_x0 + p->wall_v * t : 0.0;
     const DtAdj da{info, p->cfl};
     CSPH_HIP(launch_vjp(n, w.perm, w.cs, gd, pc, eos, w, w.srt, w.srt_mat, a, go,
                         gnext ? gn : nullptr, dt, accumulate, g_eos, dsrt, wall, yw, p->wall_v,

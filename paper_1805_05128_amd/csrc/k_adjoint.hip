@@ -20,6 +20,7 @@
 // both the pairs (i, image of j), differentiated in q_i directly, and the pairs (j, image of
 // i), differentiated in the image's q and mapped back (y and v_y change sign).  Each of the
 // two is a member under the forward pass's own rounding of its offset.
+#include "adjoint.h"
 #include "csph_internal.h"
 #include "stencil.h"
 
@@ -40,6 +41,7 @@ struct VjpIn {
 // The piston at the time of the rates: position along the kernels' y, twice its velocity.
 struct VjpWall {
     double yw, vw2;
+    WallPass p;  // the rate sums of the first pass, or the band of the correction pass
 };
 
 struct VjpOut {
@@ -215,8 +217,11 @@ __device__ __forceinline__ void vjp_pair(bool use, double dx, double dy, double 
 // stays complete.  With both, the mirror image's periodic images too.  PAIR:
 // each pair's support H_ij = kappa (d_i + d_j)/2 (symmetric to the bit; d
 // held fixed), the walk testing candidates against the largest support and
-// the pop deciding membership with the pair's own.
-template <bool WALL, bool PER, bool PAIR>
+// the pop deciding membership with the pair's own.  MIRONLY (with WALL): only the mirror
+// walks, for the workgroups holding wall-band particles, their contributions added to the
+// outputs of a gather without the wall (which keeps that gather's register budget, and its
+// occupancy, for every other particle).
+template <bool WALL, bool PER, bool PAIR, bool MIRONLY = false>
 __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
                                                   const int32_t *__restrict__ perm,
                                                   const int32_t *__restrict__ cs, GridDev g,
@@ -239,6 +244,18 @@ __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
         zi = in.C[s];
         bEi = in.Ew[s];
     }
+    if (wl.p.band) {
+        // correction pass: a workgroup without a particle within the support of the band's
+        // reach adds nothing (a NaN reach, no flagged particle, admits none)
+        const double thr = order_dec(*wl.p.band) + pc.H * (1.0 + 1e-9);
+        if (!__syncthreads_or(live && ai.y <= thr)) {
+            if (!MIRONLY && (int)threadIdx.x < 2 * n_eos)
+                o.eos_part[blk * 2 * CSPH_MAX_EOS + threadIdx.x] = 0.0;
+            return;
+        }
+    }
+    // the mirror-only gather: workgroups without a wall-band particle add nothing
+    if (MIRONLY && !__syncthreads_or(live && mirror_band(g, ai.y, wl.yw, pc.H))) return;
     const Stencil t = make_stencil(g, ai.x, ai.y, ai.z, pc.H);
     const double H2 = pc.H2;  // the largest support (pair-h mode), squared
     const double dself = PAIR && live ? in.dsz[s] : 0.0;
@@ -360,8 +377,10 @@ __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
             walk(sm, ghost, true, onm, sx, sy, sz);
         }
     };
-    walk(t, false, false, live, 0.0, 0.0, 0.0);
-    if (PER) images(t, false, live, ai.y);
+    if (!MIRONLY) {
+        walk(t, false, false, live, 0.0, 0.0, 0.0);
+        if (PER) images(t, false, live, ai.y);
+    }
     if (WALL) {
         const bool near = live && mirror_band(g, ai.y, wl.yw, pc.H);
         if (__any(near)) {
@@ -427,7 +446,13 @@ __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
         gv2 -= ge * bi.z;
         double res[8] = {gr0, gr1, gr2, gv0, gv1, gv2, grho, gEo};
         int i = perm[s];
-        if (o.gn[0]) {
+        if (wl.p.svy) {  // this gather's part of the y-momentum rate sum (k_wall_flags)
+            if (MIRONLY)
+                wl.p.svy[s] += Sv1;
+            else
+                wl.p.svy[s] = Sv1;
+        }
+        if (!MIRONLY && o.gn[0]) {
             // identity part of the step: r' = r + dt v', v' = v + dt dv, ...
             double gnx = o.gn[0][i], gny = o.gn[1][i], gnz = o.gn[2][i];
             res[0] += gnx;
@@ -455,8 +480,10 @@ __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
             for (int k = 0; k < 2 * n_eos; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
         __syncthreads();
     }
-    if ((int)threadIdx.x < 2 * n_eos)
-        o.eos_part[blk * 2 * CSPH_MAX_EOS + threadIdx.x] = sh[threadIdx.x][0];
+    if ((int)threadIdx.x < 2 * n_eos) {
+        double *e = o.eos_part + blk * 2 * CSPH_MAX_EOS + threadIdx.x;
+        *e = MIRONLY ? *e + sh[threadIdx.x][0] : sh[threadIdx.x][0];
+    }
 }
 
 // g_eos[k] += sum over blocks of part[b][k], fixed order.
@@ -788,6 +815,32 @@ hipError_t launch_dt_adjoint(int64_t n, const int32_t *perm, double *const sorte
     return hipGetLastError();
 }
 
+// The gather's launches.  With the piston: the gather without the wall for every particle,
+// then the mirror walks for the workgroups holding wall-band particles, added to its outputs
+// (the epilogue is linear in the walks' sums, so the two launches give the one-walk gather's
+// result up to the order of the additions).  The wall's walks and state take some 60 more
+// VGPRs, which in one kernel would hold every workgroup to two waves per SIMD instead of three.
+static void vjp_gather(unsigned nb, int64_t n, const VjpIn &in, const VjpOut &o,
+                       const int32_t *perm, const int32_t *cs, const GridDev &g,
+                       const PairConst &pc, const EosDev &eos, bool wall, const VjpWall &wl,
+                       hipStream_t st) {
+    VjpOut om = o;  // the mirror-only gather adds to the first one's outputs
+    om.accumulate = 1;
+    const bool per = pc.per != 0, pair = pc.pair_mode != 0;
+#define CSPH_VJP_CASE(X, Q)                                                                  \
+    if (per == X && pair == Q) {                                                             \
+        k_vjp64<false, X, Q><<<nb, kBlock, 0, st>>>(n, in, o, perm, cs, g, pc, eos, eos.n, wl); \
+        if (wall)                                                                            \
+            k_vjp64<true, X, Q, true><<<nb, kBlock, 0, st>>>(n, in, om, perm, cs, g, pc, eos, \
+                                                             eos.n, wl);                      \
+    }
+    CSPH_VJP_CASE(false, false)
+    CSPH_VJP_CASE(false, true)
+    CSPH_VJP_CASE(true, false)
+    CSPH_VJP_CASE(true, true)
+#undef CSPH_VJP_CASE
+}
+
 hipError_t launch_vjp(int64_t n, const int32_t *perm, const int32_t *cs, const GridDev &g,
                       const PairConst &pc, const EosDev &eos, const Ws &w,
                       double *const sorted[9], const int32_t *mat_sorted,
@@ -825,20 +878,8 @@ hipError_t launch_vjp(int64_t n, const int32_t *perm, const int32_t *cs, const G
     in.mat = mat_sorted;
     for (int k = 0; k < 5; ++k) in.a[k] = w.rate[k];
     in.dsz = d_sorted;
-    const VjpWall wl{yw, 2.0 * vw};
-    const bool per = pc.per != 0, pair = pc.pair_mode != 0;
-#define CSPH_VJP_CASE(W, X, Q)                                                              \
-    if (wall == W && per == X && pair == Q)                                                 \
-        k_vjp64<W, X, Q><<<nb, kBlock, 0, st>>>(n, in, o, perm, cs, g, pc, eos, eos.n, wl);
-    CSPH_VJP_CASE(false, false, false)
-    CSPH_VJP_CASE(false, false, true)
-    CSPH_VJP_CASE(false, true, false)
-    CSPH_VJP_CASE(false, true, true)
-    CSPH_VJP_CASE(true, false, false)
-    CSPH_VJP_CASE(true, false, true)
-    CSPH_VJP_CASE(true, true, false)
-    CSPH_VJP_CASE(true, true, true)
-#undef CSPH_VJP_CASE
+    const VjpWall wl{yw, 2.0 * vw, WallPass{nullptr, nullptr}};
+    vjp_gather(nb, n, in, o, perm, cs, g, pc, eos, wall != 0, wl, st);
     if (g_eos) k_eos_grad_final<<<1, kBlock, 0, st>>>(w.eos_part, (int64_t)nb, 2 * eos.n, g_eos);
     if (dta) {
         DtFix f;
@@ -857,6 +898,112 @@ hipError_t launch_vjp(int64_t n, const int32_t *perm, const int32_t *cs, const G
         f.wall = wall;
         k_dt_fix<<<1, 64, 0, st>>>(f, g, pc, eos);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_vjp_wall(int64_t n, const int32_t *perm, const int32_t *cs, const GridDev &g,
+                           const PairConst &pc, const EosDev &eos, const Ws &w,
+                           double *const sorted[9], const int32_t *mat_sorted,
+                           const double *const a_in[5], double *const gout[8],
+                           const double *const gnext[8], double dt, int accumulate,
+                           double *g_eos, const double *d_sorted, double yw, double vw,
+                           const WallPass &wp, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    VjpOut o;
+    for (int k = 0; k < 8; ++k) {
+        o.g[k] = gout[k];
+        o.gn[k] = gnext ? gnext[k] : nullptr;
+    }
+    o.dt = dt;
+    o.accumulate = accumulate;
+    o.eos_part = w.eos_part;
+    k_vjp_weights<<<nb, kBlock, 0, st>>>(n, perm, sorted[6], o, a_in ? a_in[0] : nullptr,
+                                         a_in ? a_in[1] : nullptr, a_in ? a_in[2] : nullptr,
+                                         a_in ? a_in[3] : nullptr, a_in ? a_in[4] : nullptr,
+                                         w.rate[0], w.rate[1], w.rate[2], w.rate[3], w.rate[4],
+                                         (double4 *)w.recD, w.recE);
+    VjpIn in;
+    in.A = (const double4 *)w.recA;
+    in.B = (const double4 *)w.recB;
+    in.C = (const double2 *)w.recC;
+    in.Dw = (const double4 *)w.recD;
+    in.Ew = w.recE;
+    in.rho = sorted[6];
+    in.E = sorted[7];
+    in.m = sorted[8];
+    in.mat = mat_sorted;
+    for (int k = 0; k < 5; ++k) in.a[k] = w.rate[k];
+    in.dsz = d_sorted;
+    const VjpWall wl{yw, 2.0 * vw, wp};
+    vjp_gather(nb, n, in, o, perm, cs, g, pc, eos, true, wl, st);
+    if (g_eos) k_eos_grad_final<<<1, kBlock, 0, st>>>(w.eos_part, (int64_t)nb, 2 * eos.n, g_eos);
+    return hipGetLastError();
+}
+
+// The step's reflection test, y + dt (v_y + dt R_vy) < yw1 (kernels' y, cell order, R_vy =
+// (2/rho) S_vy from the gathers' sums), flag[i] in input order, and reach = max(y, 2 y_w - y)
+// over the flagged particles.
+__global__ __launch_bounds__(kBlock) void k_wall_flags(int64_t n, const int32_t *__restrict__ perm,
+                                                       const double *__restrict__ y_s,
+                                                       const double *__restrict__ vy_s,
+                                                       const double *__restrict__ rho_s,
+                                                       const double *__restrict__ svy,
+                                                       double dt, double yw1, double yw,
+                                                       int32_t *__restrict__ flag,
+                                                       unsigned long long *reach) {
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    const double y = y_s[s];
+    const double vy1 = vy_s[s] + dt * ((2.0 / rho_s[s]) * svy[s]);
+    const bool f = y + dt * vy1 < yw1;
+    flag[perm[s]] = f ? 1 : 0;
+    if (f) atomicMax(reach, order_enc(fmax(y, 2.0 * yw - y)));
+}
+
+hipError_t launch_wall_flags(int64_t n, const int32_t *perm, double *const sorted[9],
+                             const double *svy, double dt, double yw1, double yw, int32_t *flag,
+                             unsigned long long *reach, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_wall_flags<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+        n, perm, sorted[1], sorted[4], sorted[6], svy, dt, yw1, yw, flag, reach);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_reflect_delta(int64_t n,
+                                                          const double *__restrict__ gy,
+                                                          const double *__restrict__ gvy,
+                                                          const double *__restrict__ gE,
+                                                          double vw, double *__restrict__ dy,
+                                                          double *__restrict__ dvy) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    dy[i] = -2.0 * gy[i];
+    dvy[i] = -2.0 * gvy[i] - 2.0 * vw * gE[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_keep_flagged(int64_t n,
+                                                         const int32_t *__restrict__ flag,
+                                                         double *__restrict__ dy,
+                                                         double *__restrict__ dvy) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n || flag[i] != 0) return;
+    dy[i] = 0.0;
+    dvy[i] = 0.0;
+}
+
+hipError_t launch_reflect_delta(int64_t n, const double *gy, const double *gvy, const double *gE,
+                                double vw, double *dy, double *dvy, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_reflect_delta<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(n, gy, gvy, gE, vw,
+                                                                             dy, dvy);
+    return hipGetLastError();
+}
+
+hipError_t launch_keep_flagged(int64_t n, const int32_t *flag, double *dy, double *dvy,
+                               hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_keep_flagged<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(n, flag, dy, dvy);
     return hipGetLastError();
 }
 
