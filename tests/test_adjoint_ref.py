@@ -615,3 +615,36 @@ def test_rk2_step_gradient_matches_oracle_finite_differences(case):
 
         fd = (J_at(1) - J_at(-1)) / (2 * eps)
         assert abs(fd - pred) <= 1e-6 * max(abs(pred), 1.0), (trial, fd, pred)
+
+
+def test_torch_rates_pair_h_periodic_piston_match_c_oracle():
+    """Pair-h mode on periodic sides with the piston (each pair's own support, image and
+    mirror partners through the images): the reference's rates against the C oracle's."""
+    w = periodic_system(6, seed=13, wall=(0.2, 0.4))
+    d = np.random.default_rng(14).uniform(0.8, 1.3, w.n)
+    cfg = O.cfg_for(w, h_mode=1, kappa=1.936)
+    s = O.state_from(w, cfg)
+    s["d"] = d
+    t = 0.3
+    ref = O.rates(cfg, s, t=t, d=d)
+    et, g, pi = tparams(w)
+    ph = (1.936, d)
+    pairs = T.pairs_of(cfg, s)
+    assert float(pairs[2].abs().max()) > 0.0  # image partners present
+    xw = 0.2 + 0.4 * t
+    mir = T.mirror_pairs_of(s, 0.0, xw, box=w.box, periodic=6, pair_h=ph)
+    assert float(mir[2].abs().max()) > 0.0  # mirror partners through the images
+    out = T.rates_torch(T.to_torch(s), torch.as_tensor(s["m"]), torch.as_tensor(s["mat"]).long(),
+                        et, g, pi, pairs, 0.0, mirror=mir, wall=(xw, 0.4), pair_h=ph)
+    for k, v in zip(("drho", "dvx", "dvy", "dvz", "dE"), out):
+        scale = np.abs(ref[k]).max()
+        assert np.abs(v.numpy() - ref[k]).max() <= 1e-13 * scale, k
+    # the step (reflections, the wrap across the periodic faces)
+    dt = 0.2
+    cfg0 = O.cfg_for(w, h_mode=1, kappa=1.936, cfl=0.0)
+    s1, _, _, _ = O.step(cfg0, s, t, dt_in=dt, d=d)
+    out = T.step_torch(T.to_torch(s), torch.as_tensor(s["m"]), torch.as_tensor(s["mat"]).long(),
+                       et, g, pi, pairs, 0.0, dt, mirror=mir, wall=(0.2, 0.4), t=t, box=w.box,
+                       periodic=6, pair_h=ph)
+    for k in F8:
+        assert np.abs(out[k].numpy() - s1[k]).max() <= 1e-13 * (1 + np.abs(s1[k]).max()), k

@@ -829,6 +829,75 @@ def test_rates_and_step_vjp_pair_h_match_autograd(wall):
     assert abs(jvp - vjp) <= 1e-7 * max(abs(vjp), 1.0), (jvp, vjp)
 
 
+def test_rates_and_step_vjp_pair_h_periodic_piston_match_autograd():
+    """Pair-h mode on periodic sides with the piston (pair supports, image partners, mirror
+    partners through the images, reflections and the wrap): the GPU VJPs of the rates and of
+    the step against autograd of the FP64 reference, and the dot-product test against the
+    GPU's own forward step."""
+    from test_adjoint_ref import periodic_system
+    w = periodic_system(6, seed=13, wall=(0.2, 0.4))
+    d = np.random.default_rng(14).uniform(0.8, 1.3, w.n)
+    print(f"[case] pair-h periodic piston vjp n={w.n}", flush=True)
+    t, dt = 0.3, 0.2
+    params = P.Params.from_workload(w, reorder=False, h_mode="pair", kappa=1.936, cell_size=0.0)
+    g = P.state_from_workload(w, params, DEV)
+    g.d = torch.as_tensor(d, device=DEV)
+    s = _np_state(g, w)
+    s["d"] = d
+    ph = (1.936, d)
+    cfg = O.cfg_for(w, h_mode=1, kappa=1.936)
+    pairs = T.pairs_of(cfg, s)
+    mir = T.mirror_pairs_of(s, 0.0, 0.2 + 0.4 * t, box=w.box, periodic=6, pair_h=ph)
+    wt = (0.2 + 0.4 * t, 0.4)
+    et, gg, pi = tparams(w, True)
+    m, mat = torch.as_tensor(w.m), torch.as_tensor(w.mat).long()
+    rng = np.random.default_rng(66)
+    cot = {k: rng.standard_normal(w.n) for k in ("drho", "dvx", "dvy", "dvz", "dE")}
+    gs, ge = P.csph_rates_vjp(g, params, {k: torch.as_tensor(v, device=DEV) for k, v in cot.items()},
+                              t=t)
+    st = {k: torch.as_tensor(s[k]).clone().requires_grad_(True) for k in F8}
+    out = T.rates_torch(st, m, mat, et, gg, pi, pairs, 0.0, mirror=mir, wall=wt, pair_h=ph)
+    J = sum((o * torch.as_tensor(cot[k])).sum()
+            for o, k in zip(out, ("drho", "dvx", "dvy", "dvz", "dE")))
+    ref = torch.autograd.grad(J, [st[k] for k in F8] + [gg, pi])
+    for a, k in enumerate(F8):
+        assert relmax(gs[k].cpu().numpy(), ref[a].numpy()) <= 1e-10, ("rates", k)
+    assert relmax(ge.cpu().numpy()[0::2], ref[8].numpy()) <= 1e-10
+    replay = P.Params.from_workload(w, reorder=False, h_mode="pair", kappa=1.936, cell_size=0.0,
+                                    cfl=0.0)
+
+    def fwd(delta=None, eps=0.0):
+        tt = {k: g[k] + (eps * torch.as_tensor(delta[k], device=DEV) if delta else 0.0)
+              for k in F8}
+        tt["m"] = g["m"]
+        st2 = P.State(tt, g.mat, g.d)
+        P.csph_step(st2, replay, P.StepScalars(DEV, t0=t), s_out=st2, dt_in=dt)
+        return {k: st2[k].cpu().numpy() for k in F8}
+
+    base = fwd()
+    crossed = sum(int(np.sum(np.abs(base[k] - s[k]) > 4.0)) for k in ("y", "z"))
+    assert crossed > 3  # particles crossed a periodic face
+    lam = {k: rng.standard_normal(w.n) for k in F8}
+    gn = {k: torch.as_tensor(v, device=DEV).clone() for k, v in lam.items()}
+    gp, ge = P.csph_step_vjp(g, params, dt, gn, g_prev={k: torch.empty_like(v) for k, v in gn.items()},
+                             t=t)
+    st = {k: torch.as_tensor(s[k]).clone().requires_grad_(True) for k in F8}
+    out = T.step_torch(st, m, mat, et, gg, pi, pairs, 0.0, dt, mirror=mir, wall=w.wall, t=t,
+                       box=w.box, periodic=6, pair_h=ph)
+    for k in F8:
+        assert np.abs(out[k].detach().numpy() - base[k]).max() <= 1e-12 * (1 + np.abs(base[k]).max()), k
+    J = sum((out[k] * torch.as_tensor(lam[k])).sum() for k in F8)
+    ref = torch.autograd.grad(J, [st[k] for k in F8] + [gg, pi])
+    for a, k in enumerate(F8):
+        assert relmax(gp[k].cpu().numpy(), ref[a].numpy()) <= 1e-10, ("step", k)
+    dd = {k: rng.standard_normal(w.n) for k in F8}
+    eps = 1e-6
+    fp, fm = fwd(dd, eps), fwd(dd, -eps)
+    jvp = sum(float(((fp[k] - fm[k]) / (2 * eps) * lam[k]).sum()) for k in F8)
+    vjp = sum(float((gp[k].cpu().numpy() * dd[k]).sum()) for k in F8)
+    assert abs(jvp - vjp) <= 1e-7 * max(abs(vjp), 1.0), (jvp, vjp)
+
+
 def test_rollout_paper_mode_plates_reference_and_fd():
     """The paper's material mode on a small plate impact: aluminium onto lead (8 x 8 x 4 each,
     Mie-Grueneisen), pair-h support with kappa = 1.936 and sizes d of 0.95-1.15 held fixed,
