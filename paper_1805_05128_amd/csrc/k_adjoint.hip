@@ -679,39 +679,50 @@ __device__ void c_chain(const DtFix &f, const EosDev &eos, int64_t s, double gc)
     }
 }
 
-// Visits the particles of the cells within the reach of point p (cells off the mesh skipped).
-template <class F>
-__device__ void visit_cells(const GridDev &g, const int32_t *cs, double px, double py, double pz,
-                            F fn) {
-    const int cx = free_cell(px, g.ox, g.inv), cy = free_cell(py, g.oy, g.inv),
-              cz = free_cell(pz, g.oz, g.inv);
-    for (int zz = cz - g.reach; zz <= cz + g.reach; ++zz) {
-        if (zz < 0 || zz >= g.dz) continue;
-        for (int yy = cy - g.reach; yy <= cy + g.reach; ++yy) {
-            if (yy < 0 || yy >= g.dy) continue;
-            for (int xx = max(cx - g.reach, 0); xx <= min(cx + g.reach, g.dx - 1); ++xx) {
-                const uint32_t key = cell_key(g, xx, yy, zz);
-                for (int j = cs[key]; j < cs[key + 1]; ++j) fn(j);
-            }
-        }
-    }
-}
-
 // After the gather: the binding particle's direct terms.  Density-change limit: d tau/d rho =
 // 1/|drho|.  Courant limit: tau = h/sig, d tau/d sig = -h/sig^2; the signal speed's maximum
 // is found again over the particle's partners (real, periodic images, mirror images; the
 // forward pass's membership), and its gradient goes to the sound speed that attains
 // max(c_s, c_j) and, when the pair closes, to both velocities and positions through
-// v_L - v_R = (v_s - v_j).e (a mirror partner's y and v_y mapped back to j's).  One thread.
-__global__ void k_dt_fix(DtFix f, GridDev g, PairConst pc, EosDev eos) {
-    if (threadIdx.x != 0) return;
+// v_L - v_R = (v_s - v_j).e (a mirror partner's y and v_y mapped back to j's).  The
+// workgroup searches the partners: the candidates come in a fixed order (image m, then the
+// real cells before the mirror ones, cells z-, y-, then x-major within the reach, slots
+// ascending), each thread takes every kBlock-th (image, kind, cell) task, and the partner
+// kept is the first in that order that attains the largest speed above c_s (the one a walk
+// in that order with a strict comparison keeps).  Thread 0 applies the terms.
+// Task tk of the search: its image m, kind (mirror or real) and shift, and the key of its
+// cell (-1 when the image is not one i has, or the cell is off the mesh).
+__device__ __forceinline__ void dt_task(const GridDev &g, const PairConst &pc, const DtFix &f,
+                                        int nf, int NC, int W, int tk, double xi, double yi,
+                                        double zi, int &m, bool &ghost, double &sx, double &sy,
+                                        double &sz, int &key) {
+    m = tk / (2 * NC);
+    ghost = ((tk / NC) & 1) != 0;
+    const int c = tk % NC;
+    key = -1;
+    if ((nf & m) != m || (ghost && !f.wall)) return;
+    sx = image_shift(pc, nf, m, 0);
+    sy = image_shift(pc, nf, m, 1);
+    sz = image_shift(pc, nf, m, 2);
+    // the wall's axis y is never periodic: the mirror point is 2 y_w - y_i
+    const double px = xi + sx, py = ghost ? 2.0 * f.yw - yi : yi + sy, pz = zi + sz;
+    const int zz = free_cell(pz, g.oz, g.inv) - g.reach + c / (W * W);
+    const int yy = free_cell(py, g.oy, g.inv) - g.reach + (c / W) % W;
+    const int xx = free_cell(px, g.ox, g.inv) - g.reach + c % W;
+    if (zz < 0 || zz >= g.dz || yy < 0 || yy >= g.dy || xx < 0 || xx >= g.dx) return;
+    key = (int)cell_key(g, xx, yy, zz);
+}
+
+__global__ __launch_bounds__(kBlock) void k_dt_fix(DtFix f, GridDev g, PairConst pc,
+                                                   EosDev eos) {
     const DtInfo &in = *f.info;
-    if (in.courant == 0) return;
+    const int courant = in.courant;
+    if (courant == 0) return;
     const int64_t s = (int64_t)in.arg;
     const int i = f.perm[s];
     const double G0 = f.cfl * in.gdt;
-    if (in.courant == 2) {
-        f.g[6][i] += G0 / fabs(in.drho);
+    if (courant == 2) {
+        if (threadIdx.x == 0) f.g[6][i] += G0 / fabs(in.drho);
         return;
     }
     const double G = G0 * (-in.h / (in.sig * in.sig));
@@ -719,52 +730,75 @@ __global__ void k_dt_fix(DtFix f, GridDev g, PairConst pc, EosDev eos) {
     const double vxi = f.srt[3][s], vyi = f.srt[4][s], vzi = f.srt[5][s];
     const double ci = f.C[s].y;
     const double di = f.dsz ? f.dsz[s] : 0.0;
-    // the best partner: slot, mirror flag, offsets
-    double best = ci;
-    int64_t bj = -1;
-    bool bghost = false;
-    double bd[3] = {0.0, 0.0, 0.0};
-    auto consider = [&](int j, bool ghost, double dx, double dy, double dz) {
-        double H2 = pc.H2;
-        if (pc.pair_mode) {
-            const double H = pc.kappa * (0.5 * (di + f.dsz[j]));
-            H2 = H * H;
-        }
-        const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
-        if (!(r2 < H2) || r2 == 0.0 || (!ghost && j == s)) return;
-        const double vyj = ghost ? f.vw2 - f.srt[4][j] : f.srt[4][j];
-        const double r = sqrt(r2);
-        const double vrel = (((vxi - f.srt[3][j]) * dx + (vyi - vyj) * dy) + (vzi - f.srt[5][j]) * dz) / r;
-        const double sp = fmax(ci, f.C[j].y) + (vrel > 0.0 ? vrel : 0.0);
-        if (sp > best) {
-            best = sp;
-            bj = j;
-            bghost = ghost;
-            bd[0] = dx;
-            bd[1] = dy;
-            bd[2] = dz;
-        }
-    };
     const int nf = pc.per ? image_faces(pc, xi, yi, zi) : 0;
-    for (int m = 0; m < 8; ++m) {
-        if ((nf & m) != m) continue;
-        const double sx = image_shift(pc, nf, m, 0), sy = image_shift(pc, nf, m, 1),
-                     sz = image_shift(pc, nf, m, 2);
-        visit_cells(g, f.cs, xi + sx, yi + sy, zi + sz, [&](int j) {
-            consider(j, false, (f.srt[0][j] - xi) - sx, (f.srt[1][j] - yi) - sy,
-                     (f.srt[2][j] - zi) - sz);
-        });
-        if (f.wall) {  // mirror partners (the wall's axis y is never periodic)
-            visit_cells(g, f.cs, xi + sx, 2.0 * f.yw - yi, zi + sz, [&](int j) {
-                consider(j, true, (f.srt[0][j] - xi) - sx, (2.0 * f.yw - f.srt[1][j]) - yi,
-                         (f.srt[2][j] - zi) - sz);
-            });
+    const int W = 2 * g.reach + 1, NC = W * W * W;
+    // the offsets of candidate j in (image m, kind) as the forward pass forms them
+    auto offsets = [&](int64_t j, bool ghost, double sx, double sy, double sz, double &dx,
+                       double &dy, double &dz) {
+        dx = (f.srt[0][j] - xi) - sx;
+        dy = ghost ? (2.0 * f.yw - f.srt[1][j]) - yi : (f.srt[1][j] - yi) - sy;
+        dz = (f.srt[2][j] - zi) - sz;
+    };
+    double best = ci;
+    unsigned long long bkey = ~0ull;  // (task << 32) | slot of the kept candidate
+    for (int tk = threadIdx.x; tk < 16 * NC; tk += kBlock) {
+        int m, key;
+        bool ghost;
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        dt_task(g, pc, f, nf, NC, W, tk, xi, yi, zi, m, ghost, sx, sy, sz, key);
+        if (key < 0) continue;
+        for (int j = f.cs[key]; j < f.cs[key + 1]; ++j) {
+            double dx, dy, dz;
+            offsets(j, ghost, sx, sy, sz, dx, dy, dz);
+            double H2 = pc.H2;
+            if (pc.pair_mode) {
+                const double H = pc.kappa * (0.5 * (di + f.dsz[j]));
+                H2 = H * H;
+            }
+            const double r2 = ((dx * dx) + (dy * dy)) + (dz * dz);
+            if (!(r2 < H2) || r2 == 0.0 || (!ghost && j == s)) continue;
+            const double vyj = ghost ? f.vw2 - f.srt[4][j] : f.srt[4][j];
+            const double r = sqrt(r2);
+            const double vrel =
+                (((vxi - f.srt[3][j]) * dx + (vyi - vyj) * dy) + (vzi - f.srt[5][j]) * dz) / r;
+            const double sp = fmax(ci, f.C[j].y) + (vrel > 0.0 ? vrel : 0.0);
+            if (sp > best) {
+                best = sp;
+                bkey = ((unsigned long long)tk << 32) | (unsigned)j;
+            }
         }
     }
-    if (bj < 0) {  // no partner exceeds c_s: sig = c_s
+    // the largest speed, first in the order among equals
+    __shared__ double shs[kBlock];
+    __shared__ unsigned long long shk[kBlock];
+    shs[threadIdx.x] = best;
+    shk[threadIdx.x] = bkey;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const double a = shs[threadIdx.x], b = shs[threadIdx.x + w];
+            const unsigned long long ka = shk[threadIdx.x], kb = shk[threadIdx.x + w];
+            if (b > a || (b == a && kb < ka)) {
+                shs[threadIdx.x] = b;
+                shk[threadIdx.x] = kb;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const unsigned long long k = shk[0];
+    if (k == ~0ull) {  // no partner exceeds c_s: sig = c_s
         c_chain(f, eos, s, G);
         return;
     }
+    const int tk = (int)(k >> 32);
+    const int64_t bj = (int64_t)(k & 0xffffffffull);
+    int m, key;
+    bool bghost;
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    dt_task(g, pc, f, nf, NC, W, tk, xi, yi, zi, m, bghost, sx, sy, sz, key);
+    double bd[3];
+    offsets(bj, bghost, sx, sy, sz, bd[0], bd[1], bd[2]);
     const double cj = f.C[bj].y;
     if (ci >= cj)
         c_chain(f, eos, s, G);
@@ -896,7 +930,7 @@ hipError_t launch_vjp(int64_t n, const int32_t *perm, const int32_t *cs, const G
         f.yw = yw;
         f.vw2 = 2.0 * vw;
         f.wall = wall;
-        k_dt_fix<<<1, 64, 0, st>>>(f, g, pc, eos);
+        k_dt_fix<<<1, kBlock, 0, st>>>(f, g, pc, eos);
     }
     return hipGetLastError();
 }
