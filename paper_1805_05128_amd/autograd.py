@@ -34,6 +34,12 @@ def _clone_state(s: A.State) -> A.State:
     return A.State(t, s.mat, s.d, None)
 
 
+def _fresh_like(s: A.State) -> A.State:
+    """Uninitialised evolving fields for a step's output; mass, material and sizes shared."""
+    t = {k: (v if k == "m" else torch.empty_like(v)) for k, v in s.t.items()}
+    return A.State(t, s.mat, s.d, None)
+
+
 def _with_gamma(params: A.Params, gamma: List[float]) -> A.Params:
     """The run's parameters with each material's gamma (Grueneisen Gamma for a Mie-Grueneisen
     material) replaced; its other constants kept."""
@@ -126,11 +132,12 @@ class CSPHRollout(torch.autograd.Function):
             # the segment's replay starts at its recorded time; t + dt then repeats the
             # forward's times bit for bit
             sc = A.StepScalars(dev, t0=ctx.ts[k0])
+            # each replayed step writes a fresh state (no copies; the checkpoint is only read)
             states = [ctx.ckpts[seg]]
-            s = _clone_state(ctx.ckpts[seg])
             for k in range(k0, k1 - 1):
-                A.csph_step(s, replay, sc, s_out=s, dt_in=ctx.dts[k], totals=False)
-                states.append(_clone_state(s))
+                s = _fresh_like(states[-1])
+                A.csph_step(states[-1], replay, sc, s_out=s, dt_in=ctx.dts[k], totals=False)
+                states.append(s)
             for k in reversed(range(k0, k1)):
                 if ctx.cfl_adjoint:
                     _, _, dt = A.csph_step_vjp_cfl(states[k - k0], pg, g, g_prev=g, g_eos=g_eos,

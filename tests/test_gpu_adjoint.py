@@ -1282,6 +1282,50 @@ def test_vjp_empty_and_lone_particle():
     assert abs(float(ge[0].item()) - dgamma) <= 1e-12 * max(1.0, abs(dgamma))
 
 
+def test_step_vjp_lone_particle_reflected_by_the_piston():
+    """A particle without partners (more than a support from the piston at t) that crosses
+    it in one Euler step: the step reflects it, x'' = 2 x_w(t + dt) - (x + dt v_x),
+    v_x'' = 2 v_w - v_x, E'' = E + (v_x''^2 - v_x^2)/2 (the rates vanish), and the VJP is the
+    closed-form transpose of that map.  Also the empty state with the piston."""
+    t, dt, xw0, vw = 0.2, 0.2, 0.0, 0.5
+    prm = P.Params(eos=[(0, 1.4, 0.0)], h=1.5, cfl=0.0, reorder=False, wall=(xw0, vw))
+    e0 = P.State.empty(0, DEV)
+    z = {k: torch.zeros(0, dtype=torch.float64, device=DEV) for k in F8}
+    cot = {k: torch.zeros(0, dtype=torch.float64, device=DEV) for k in ("drho", "dvx", "dvy", "dvz", "dE")}
+    ge = torch.zeros(2, dtype=torch.float64, device=DEV)
+    P.csph_rates_vjp(e0, prm, cot, g_state=dict(z), g_eos=ge, t=t)
+    P.csph_step_vjp(e0, prm, dt, dict(z), g_eos=ge, t=t)
+    torch.cuda.synchronize()
+    assert ge.abs().sum().item() == 0.0
+    v = np.array([-40.0, 0.3, -0.2])
+    x0, rho, E = xw0 + vw * t + 6.0, 1.1, 2.5
+    t1 = lambda a: torch.tensor([a], dtype=torch.float64, device=DEV)
+    st = P.State({"x": t1(x0), "y": t1(2.0), "z": t1(3.0), "vx": t1(v[0]), "vy": t1(v[1]),
+                  "vz": t1(v[2]), "rho": t1(rho), "E": t1(E), "m": t1(rho)},
+                 torch.zeros(1, dtype=torch.int32, device=DEV))
+    out = P.State.empty(1, DEV, True, False, False)
+    P.csph_step(st, prm, P.StepScalars(DEV, t0=t), s_out=out, dt_in=dt, totals=False)
+    xw1 = xw0 + vw * (t + dt)
+    vx2 = 2.0 * vw - v[0]
+    want = {"x": 2.0 * xw1 - (x0 + dt * v[0]), "y": 2.0 + dt * v[1], "z": 3.0 + dt * v[2],
+            "vx": vx2, "vy": v[1], "vz": v[2], "rho": rho,
+            "E": E + 0.5 * (vx2 * vx2 - v[0] * v[0])}
+    for k in F8:
+        assert abs(float(out[k].item()) - want[k]) <= 1e-13 * max(1.0, abs(want[k])), k
+    lam = {k: float(x) for k, x in zip(F8, np.random.default_rng(121).standard_normal(8))}
+    gn = {k: t1(lam[k]) for k in F8}
+    gp, ge = P.csph_step_vjp(st, prm, dt, gn, g_prev={k: t1(0.0) for k in F8},
+                             g_eos=torch.zeros(2, dtype=torch.float64, device=DEV), t=t)
+    expect = {"x": -lam["x"], "y": lam["y"], "z": lam["z"],
+              "vx": -dt * lam["x"] - lam["vx"] - 2.0 * vw * lam["E"],
+              "vy": lam["vy"] + dt * lam["y"], "vz": lam["vz"] + dt * lam["z"],
+              "rho": lam["rho"], "E": lam["E"]}
+    for k in F8:
+        got = float(gp[k].item())
+        assert abs(got - expect[k]) <= 1e-13 * max(1.0, abs(expect[k])), (k, got, expect[k])
+    assert float(ge.abs().sum().item()) == 0.0
+
+
 def test_rk2_step_vjp_grows_a_fresh_workspace():
     """The RK2 step's VJP on a fresh, small workspace: it learns its scratch and both meshes'
     needs over the binding's retries and returns the same gradient as with a large one."""
