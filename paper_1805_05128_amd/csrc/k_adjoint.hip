@@ -467,22 +467,22 @@ __global__ __launch_bounds__(kBlock) void k_vjp64(int64_t n, VjpIn in, VjpOut o,
 #pragma unroll
         for (int k = 0; k < 8; ++k) o.g[k][i] = o.accumulate ? o.g[k][i] + res[k] : res[k];
     }
-    // deterministic per-block sums of the EOS-parameter gradients
-    __shared__ double sh[2 * CSPH_MAX_EOS][kBlock];
-    for (int k = 0; k < 2 * n_eos; ++k) sh[k][threadIdx.x] = 0.0;
-    if (s < n) {
-        sh[2 * mt][threadIdx.x] = ge_gamma;
-        sh[2 * mt + 1][threadIdx.x] = ge_pinf;
+    // deterministic per-block sums of the EOS-parameter gradients: a butterfly within each
+    // wave, then the waves' sums in a fixed order (a few hundred bytes of LDS, which leaves
+    // the workgroups per CU to the register budget)
+    __shared__ double sh[kBlock / 64][2 * CSPH_MAX_EOS];
+    for (int k = 0; k < 2 * n_eos; ++k) {
+        double v = (s < n && mt == (k >> 1)) ? ((k & 1) ? ge_pinf : ge_gamma) : 0.0;
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6][k] = v;
     }
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int k = 0; k < 2 * n_eos; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
-        __syncthreads();
-    }
     if ((int)threadIdx.x < 2 * n_eos) {
-        double *e = o.eos_part + blk * 2 * CSPH_MAX_EOS + threadIdx.x;
-        *e = MIRONLY ? *e + sh[threadIdx.x][0] : sh[threadIdx.x][0];
+        const int k = threadIdx.x;
+        static_assert(kBlock == 256, "four waves per workgroup");
+        const double v = (sh[0][k] + sh[1][k]) + (sh[2][k] + sh[3][k]);
+        double *e = o.eos_part + blk * 2 * CSPH_MAX_EOS + k;
+        *e = MIRONLY ? *e + v : v;
     }
 }
 
