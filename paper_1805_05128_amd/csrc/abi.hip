@@ -812,6 +812,9 @@ static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const cs
     if (r) return r;
     Ws w;
     ws_layout(&w, ws, n, g.ncell, rk2);
+    // the Euler step in cell order writes the neighbour counts where the caller wants them
+    // (the output order is the rate kernel's), instead of copying them there at the end
+    if (p->reorder && !rk2 && nbr_count) w.cnt = nbr_count;
     GridDev gd = grid_dev(g, true, ymin);
     // on a given mesh the binning finds the wall band's minimum y on the device and counts the
     // particles off the mesh (or outside a periodic box)
@@ -937,7 +940,7 @@ static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const cs
     ProfScope pro(CSPH_PROF_REORDER, st, prof);
     if (n > 0) {
         if (p->reorder) {
-            if (nbr_count)
+            if (nbr_count && cnt_out != nbr_count)
                 CSPH_HIP(hipMemcpyAsync(nbr_count, cnt_out, sizeof(int32_t) * n,
                                         hipMemcpyDeviceToDevice, st));
         } else {
