@@ -9,6 +9,7 @@
 
 #include "adjoint.h"
 #include "csph_internal.h"
+#include "hostsync.h"
 
 namespace csph {
 
@@ -375,6 +376,66 @@ static int morton_bits(const int32_t dims[3]) {
     return b;
 }
 
+// ---------------------------------------------------------------- bounds to the host
+//
+// Each host thread keeps, per device, one pinned fine-grained slot that the bounds kernel
+// writes, and a sequence number per call; make_grid is done with the slot before it returns,
+// so a thread's calls never share it while in flight.  The host spins on the sequence
+// number (asking the stream every ~1 000 spins whether it failed or drained without it),
+// which returns a few microseconds after the kernel's store, where a copy to pageable
+// memory and a stream synchronisation left the GPU idle for ~70 us per step.
+constexpr int kPollDevices = 64;
+struct PollSlots {
+    HostBounds *host[kPollDevices] = {};
+    HostBounds *dev[kPollDevices] = {};
+    unsigned long long seq = 0;
+};
+static thread_local PollSlots g_poll;
+
+// *done = false (nothing launched) when no slot can be had: the caller copies and
+// synchronises instead.
+static csph_status bounds_polled(const double *x, const double *y, const double *z,
+                                 const double *d, int64_t n, double *part, double *out,
+                                 hipStream_t st, double b[7], bool *done) {
+    *done = false;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kPollDevices) return CSPH_OK;
+    if (!g_poll.host[dev]) {
+        void *hp = nullptr, *dp = nullptr;
+        if (hipHostMalloc(&hp, sizeof(HostBounds), hipHostMallocCoherent) != hipSuccess ||
+            !hp) {
+            (void)hipGetLastError();
+            return CSPH_OK;
+        }
+        if (hipHostGetDevicePointer(&dp, hp, 0) != hipSuccess || !dp) {
+            (void)hipGetLastError();
+            (void)hipHostFree(hp);
+            return CSPH_OK;
+        }
+        __atomic_store_n(&((HostBounds *)hp)->seq, 0ull, __ATOMIC_RELEASE);
+        g_poll.host[dev] = (HostBounds *)hp;
+        g_poll.dev[dev] = (HostBounds *)dp;
+    }
+    HostBounds *hb = g_poll.host[dev];
+    const unsigned long long want = ++g_poll.seq;
+    CSPH_HIP(launch_bounds_host(x, y, z, d, n, part, out, g_poll.dev[dev], want, st));
+    for (unsigned it = 1; __atomic_load_n(&hb->seq, __ATOMIC_ACQUIRE) != want; ++it) {
+        if ((it & 1023) == 0) {
+            const hipError_t q = hipStreamQuery(st);
+            if (q == hipSuccess) {
+                if (__atomic_load_n(&hb->seq, __ATOMIC_ACQUIRE) == want) break;
+                return fail(CSPH_EDEVICE, "mesh bounds: the stream drained without them");
+            }
+            if (q != hipErrorNotReady)
+                return fail(CSPH_EDEVICE, "mesh bounds: %s", hipGetErrorString(q));
+        }
+        __builtin_ia32_pause();
+    }
+    for (int k = 0; k < 7; ++k) b[k] = ((volatile const double *)hb->b)[k];
+    *done = true;
+    return CSPH_OK;
+}
+
 // Mesh from device bounds (synchronises `st`); also returns max d and the minimum y.
 // snap = false: the mesh of sec. 4.2 as csph_grid_build defines it (origin = the minimum
 // position).  snap = true (the library's own passes): the origin is moved down to a whole
@@ -383,21 +444,32 @@ static int morton_bits(const int32_t dims[3]) {
 // would otherwise move every particle's cell index and scatter the next step's gather).
 // Results do not depend on the mesh: membership is decided by exact FP64 distances.
 // snap = true also checks the periodic box against the bounds (the arrays are then in the
-// kernels' axes, x and y swapped when p has a wall).
+// kernels' axes, x and y swapped when p has a wall).  poll: the bounds come through the
+// calling thread's pinned slot (bounds_polled; the entry point that allocates nothing keeps
+// the copy and the synchronisation).
 static csph_status make_grid(const double *x, const double *y, const double *z, const double *d,
                              int64_t n, const csph_params *p, void *ws, size_t ws_bytes,
                              hipStream_t st, csph_grid *g, double *dmax, double *ymin,
-                             bool snap) {
+                             bool snap, bool poll = false) {
     if (ws_bytes < ws_prefix() || !ws)
         return fail(CSPH_ECAPACITY, "workspace smaller than %zu bytes", ws_prefix());
     double b[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (n > 0) {
         Ws w;
         ws_layout(&w, ws, 0, 0);
-        CSPH_HIP(launch_bounds(x, y, z, p->h_mode == CSPH_H_PAIR ? d : nullptr, n, w.bounds_part,
-                               w.bounds_out, st));
-        CSPH_HIP(hipMemcpyAsync(b, w.bounds_out, sizeof(double) * 7, hipMemcpyDeviceToHost, st));
-        CSPH_HIP(hipStreamSynchronize(st));
+        const double *dd = p->h_mode == CSPH_H_PAIR ? d : nullptr;
+        bool done = false;
+        if (poll) {
+            csph_status r = bounds_polled(x, y, z, dd, n, w.bounds_part, w.bounds_out, st, b,
+                                          &done);
+            if (r) return r;
+        }
+        if (!done) {
+            CSPH_HIP(launch_bounds(x, y, z, dd, n, w.bounds_part, w.bounds_out, st));
+            CSPH_HIP(hipMemcpyAsync(b, w.bounds_out, sizeof(double) * 7, hipMemcpyDeviceToHost,
+                                    st));
+            CSPH_HIP(hipStreamSynchronize(st));
+        }
     }
     for (int k = 0; k < 7; ++k)
         if (!std::isfinite(b[k])) return fail(CSPH_EINVAL, "non-finite particle positions or sizes");
@@ -805,7 +877,8 @@ static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const cs
             g.dims[a] = mesh->dims[ax.k[a]];
         }
     } else {
-        r = make_grid(vin.x, vin.y, vin.z, vin.d, n, p, ws, ws_bytes, st, &g, &dmax, &ymin, true);
+        r = make_grid(vin.x, vin.y, vin.z, vin.d, n, p, ws, ws_bytes, st, &g, &dmax, &ymin, true,
+                      prof);
         if (r) return r;
     }
     r = need_ws(ws_bytes, n, g.ncell, ws_needed, rk2);
@@ -883,7 +956,7 @@ static csph_status step_impl(const csph_state *s_in, csph_state *s_out, const cs
         double dmax2 = dmax, ymin2 = ymin;
         if (!mesh) {
             r = make_grid(w.stg[0], w.stg[1], w.stg[2], d1, n, p, ws, ws_bytes, st, &g2, &dmax2,
-                          &ymin2, true);
+                          &ymin2, true, prof);
             if (r) return r;
         }
         r = need_ws(ws_bytes, n, g.ncell, ws_needed, true, g2.ncell);

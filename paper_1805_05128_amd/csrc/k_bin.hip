@@ -9,6 +9,7 @@
 // particles with a smaller input index, so the order is exactly the stable
 // order by (key, input index) whatever order the atomics ran in.
 #include "csph_internal.h"
+#include "hostsync.h"
 
 namespace csph {
 
@@ -93,6 +94,48 @@ __global__ __launch_bounds__(kBlock) void k_bounds_final(const double *__restric
         for (int q = 1; q < kBlock / 64; ++q) r = k < 3 ? fmin(r, sh[q][k]) : fmax(r, sh[q][k]);
         out[k] = r;
     }
+}
+
+// k_bounds_final, also writing the result to the host's pinned slot: each value with a
+// system-scope fence, then (after the workgroup barrier) the sequence number with a
+// system-scope release, which the host polls.
+__global__ __launch_bounds__(kBlock) void k_bounds_final_host(const double *__restrict__ part,
+                                                              int nblocks,
+                                                              double *__restrict__ out,
+                                                              HostBounds *hb,
+                                                              unsigned long long seq) {
+    double v[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += kBlock)
+        for (int k = 0; k < 7; ++k)
+            v[k] = k < 3 ? fmin(v[k], part[b * 8 + k]) : fmax(v[k], part[b * 8 + k]);
+    __shared__ double sh[kBlock / 64][7];
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int k = 0; k < 7; ++k) {
+        double r = k < 3 ? wave_min(v[k]) : wave_max(v[k]);
+        if (lane == 0) sh[wid][k] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < 7) {
+        int k = threadIdx.x;
+        double r = sh[0][k];
+        for (int q = 1; q < kBlock / 64; ++q) r = k < 3 ? fmin(r, sh[q][k]) : fmax(r, sh[q][k]);
+        out[k] = r;
+        hb->b[k] = r;
+        __threadfence_system();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(&hb->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+hipError_t launch_bounds_host(const double *x, const double *y, const double *z,
+                              const double *d, int64_t n, double *part, double *out,
+                              HostBounds *hb, unsigned long long seq, hipStream_t st) {
+    int64_t want = (n + kBlock - 1) / kBlock;
+    int nb = (int)(want < 1 ? 1 : (want > kReduceBlocks ? kReduceBlocks : want));
+    k_bounds<<<nb, kBlock, 0, st>>>(x, y, z, d, n, part);
+    k_bounds_final_host<<<1, kBlock, 0, st>>>(part, nb, out, hb, seq);
+    return hipGetLastError();
 }
 
 hipError_t launch_bounds(const double *x, const double *y, const double *z, const double *d,
