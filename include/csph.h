@@ -551,6 +551,11 @@ typedef struct {
 
 csph_status csph_profile_enable(int32_t on);
 csph_status csph_profile_read(csph_profile *out /* host */);
+/* Which groups record events while timing is enabled: bit g of mask for group g (default
+ * all).  A benchmark that times only the pair-rate kernel inside its timed steps
+ * (1 << CSPH_PROF_RATES) leaves the other groups' event records, and the idle stream
+ * around them, out of those steps.  Never fails. */
+csph_status csph_profile_groups(uint32_t mask);
 
 #ifdef __cplusplus
 }

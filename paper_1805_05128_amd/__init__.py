@@ -5,7 +5,7 @@ from ._native import (CSPH_OK, CSPH_EINVAL, CSPH_ECAPACITY, CSPH_EDEVICE,  # noq
                       CSPH_ENONPHYS, CsphError, NonPhysicalState)
 from .api import (EOS_IDEAL, EOS_STIFFENED, EOS_MIE_GRUNEISEN, Params, State, StepScalars, Workspace,  # noqa: F401
                   csph_bin, csph_grid_build, csph_init_energy, csph_neighbors, csph_rates,
-                  csph_step, default_workspace, profile_enable, profile_read, state_from_workload, version, voronoi_assign,
+                  csph_step, default_workspace, profile_enable, profile_groups, profile_read, state_from_workload, version, voronoi_assign,
                   workspace_size, csph_rates_vjp, csph_step_vjp, csph_step_vjp_cfl,
                   csph_init_energy_vjp,
                   zeros_grad, GRAD_FIELDS, BalanceParams, csph_balance_stats,

@@ -176,6 +176,8 @@ def load():
                                     _dp, _dp, vp]
     L.csph_profile_enable.restype = C.c_int32
     L.csph_profile_enable.argtypes = [C.c_int32]
+    L.csph_profile_groups.restype = C.c_int32
+    L.csph_profile_groups.argtypes = [C.c_uint32]
     L.csph_profile_read.restype = C.c_int32
     L.csph_profile_read.argtypes = [C.POINTER(CsphProfile)]
     _lib = L

@@ -213,6 +213,17 @@ def profile_enable(on: bool = True):
     N.check(N.load().csph_profile_enable(1 if on else 0), "csph_profile_enable")
 
 
+def profile_groups(groups=None):
+    """Time only the named groups (names of PROF_GROUPS; None: all) while timing is on."""
+    if groups is None:
+        mask = 0xFFFFFFFF
+    else:
+        mask = 0
+        for g in groups:
+            mask |= 1 << N.PROF_GROUPS.index(g)
+    N.check(N.load().csph_profile_groups(mask), "csph_profile_groups")
+
+
 def profile_read() -> Dict[str, Tuple[int, float]]:
     """{group: (launches, total ms)} since the previous read (waits for the events)."""
     pr = N.CsphProfile()

@@ -40,6 +40,7 @@ struct ProfRec {
 };
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
+static uint32_t g_prof_mask = ~0u;  // groups that record events while timing is on
 static std::vector<ProfRec> g_prof_pending;
 static std::vector<hipEvent_t> g_prof_pool;
 static csph_profile g_prof_acc;
@@ -72,7 +73,7 @@ struct ProfScope {
     ProfScope(int g, hipStream_t s, bool on = true) : group(g), st(s) {
         if (!on) return;
         std::lock_guard<std::mutex> lk(g_prof_mu);
-        if (!g_prof_on) return;
+        if (!g_prof_on || !((g_prof_mask >> group) & 1u)) return;
         a = prof_event();
         if (a && hipEventRecord(a, st) != hipSuccess) {
             g_prof_pool.push_back(a);
@@ -1554,6 +1555,12 @@ csph_status csph_profile_enable(int32_t on) {
         if (prof_event_create(&e) != hipSuccess) return fail(CSPH_EDEVICE, "hipEventCreate failed");
         g_prof_pool.push_back(e);
     }
+    return CSPH_OK;
+}
+
+csph_status csph_profile_groups(uint32_t mask) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_mask = mask;
     return CSPH_OK;
 }
 
