@@ -31,30 +31,8 @@ __global__ __launch_bounds__(kBlock) void k_bounds(const double *__restrict__ x,
                                                    const double *__restrict__ d, int64_t n,
                                                    double *__restrict__ part) {
     double v[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0};
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    // four grid strides per iteration: twelve independent loads in flight per lane (one
-    // stride at a time left the kernel waiting on each load's latency, at ~3.8 TB/s)
-    constexpr int kSU = 4;
-    for (; i + (kSU - 1) * stride < n; i += kSU * stride) {
-        double a[kSU], b[kSU], c[kSU];
-#pragma unroll
-        for (int u = 0; u < kSU; ++u) {
-            a[u] = x[i + u * stride];
-            b[u] = y[i + u * stride];
-            c[u] = z[i + u * stride];
-        }
-#pragma unroll
-        for (int u = 0; u < kSU; ++u) {
-            v[0] = fmin(v[0], a[u]); v[1] = fmin(v[1], b[u]); v[2] = fmin(v[2], c[u]);
-            v[3] = fmax(v[3], a[u]); v[4] = fmax(v[4], b[u]); v[5] = fmax(v[5], c[u]);
-        }
-        if (d) {
-#pragma unroll
-            for (int u = 0; u < kSU; ++u) v[6] = fmax(v[6], d[i + u * stride]);
-        }
-    }
-    for (; i < n; i += stride) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
         double a = x[i], b = y[i], c = z[i];
         v[0] = fmin(v[0], a); v[1] = fmin(v[1], b); v[2] = fmin(v[2], c);
         v[3] = fmax(v[3], a); v[4] = fmax(v[4], b); v[5] = fmax(v[5], c);
