@@ -446,12 +446,12 @@ static csph_status bounds_polled(const double *x, const double *y, const double 
 // Results do not depend on the mesh: membership is decided by exact FP64 distances.
 // snap = true also checks the periodic box against the bounds (the arrays are then in the
 // kernels' axes, x and y swapped when p has a wall).  poll: the bounds come through the
-// calling thread's pinned slot (bounds_polled; the entry point that allocates nothing keeps
-// the copy and the synchronisation).
+// calling thread's pinned slot (bounds_polled); the entry point that allocates nothing passes
+// false and keeps the copy and the synchronisation.
 static csph_status make_grid(const double *x, const double *y, const double *z, const double *d,
                              int64_t n, const csph_params *p, void *ws, size_t ws_bytes,
                              hipStream_t st, csph_grid *g, double *dmax, double *ymin,
-                             bool snap, bool poll = false) {
+                             bool snap, bool poll = true) {
     if (ws_bytes < ws_prefix() || !ws)
         return fail(CSPH_ECAPACITY, "workspace smaller than %zu bytes", ws_prefix());
     double b[8] = {0, 0, 0, 0, 0, 0, 0, 0};
