@@ -393,47 +393,82 @@ struct PollSlots {
 };
 static thread_local PollSlots g_poll;
 
+// The calling thread's slot on the current device (allocated on first use), or nullptr when
+// none can be had; *dev_slot receives its device address.
+static HostBounds *host_slot(HostBounds **dev_slot) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kPollDevices) return nullptr;
+    if (!g_poll.host[dev]) {
+        void *hp = nullptr, *dp = nullptr;
+        if (hipHostMalloc(&hp, sizeof(HostBounds), hipHostMallocCoherent) != hipSuccess ||
+            !hp) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        if (hipHostGetDevicePointer(&dp, hp, 0) != hipSuccess || !dp) {
+            (void)hipGetLastError();
+            (void)hipHostFree(hp);
+            return nullptr;
+        }
+        __atomic_store_n(&((HostBounds *)hp)->seq, 0ull, __ATOMIC_RELEASE);
+        g_poll.host[dev] = (HostBounds *)hp;
+        g_poll.dev[dev] = (HostBounds *)dp;
+    }
+    *dev_slot = g_poll.dev[dev];
+    return g_poll.host[dev];
+}
+
+// Spins until the slot holds sequence number `want` (asking the stream every ~1 000 spins
+// whether it failed, or drained without it).
+static csph_status poll_slot(HostBounds *hb, unsigned long long want, hipStream_t st,
+                             const char *what) {
+    for (unsigned it = 1; __atomic_load_n(&hb->seq, __ATOMIC_ACQUIRE) != want; ++it) {
+        if ((it & 1023) == 0) {
+            const hipError_t q = hipStreamQuery(st);
+            if (q == hipSuccess) {
+                if (__atomic_load_n(&hb->seq, __ATOMIC_ACQUIRE) == want) break;
+                return fail(CSPH_EDEVICE, "%s: the stream drained without them", what);
+            }
+            if (q != hipErrorNotReady)
+                return fail(CSPH_EDEVICE, "%s: %s", what, hipGetErrorString(q));
+        }
+        __builtin_ia32_pause();
+    }
+    return CSPH_OK;
+}
+
 // *done = false (nothing launched) when no slot can be had: the caller copies and
 // synchronises instead.
 static csph_status bounds_polled(const double *x, const double *y, const double *z,
                                  const double *d, int64_t n, double *part, double *out,
                                  hipStream_t st, double b[7], bool *done) {
     *done = false;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kPollDevices) return CSPH_OK;
-    if (!g_poll.host[dev]) {
-        void *hp = nullptr, *dp = nullptr;
-        if (hipHostMalloc(&hp, sizeof(HostBounds), hipHostMallocCoherent) != hipSuccess ||
-            !hp) {
-            (void)hipGetLastError();
-            return CSPH_OK;
-        }
-        if (hipHostGetDevicePointer(&dp, hp, 0) != hipSuccess || !dp) {
-            (void)hipGetLastError();
-            (void)hipHostFree(hp);
-            return CSPH_OK;
-        }
-        __atomic_store_n(&((HostBounds *)hp)->seq, 0ull, __ATOMIC_RELEASE);
-        g_poll.host[dev] = (HostBounds *)hp;
-        g_poll.dev[dev] = (HostBounds *)dp;
-    }
-    HostBounds *hb = g_poll.host[dev];
+    HostBounds *dslot = nullptr, *hb = host_slot(&dslot);
+    if (!hb) return CSPH_OK;
     const unsigned long long want = ++g_poll.seq;
-    CSPH_HIP(launch_bounds_host(x, y, z, d, n, part, out, g_poll.dev[dev], want, st));
-    for (unsigned it = 1; __atomic_load_n(&hb->seq, __ATOMIC_ACQUIRE) != want; ++it) {
-        if ((it & 1023) == 0) {
-            const hipError_t q = hipStreamQuery(st);
-            if (q == hipSuccess) {
-                if (__atomic_load_n(&hb->seq, __ATOMIC_ACQUIRE) == want) break;
-                return fail(CSPH_EDEVICE, "mesh bounds: the stream drained without them");
-            }
-            if (q != hipErrorNotReady)
-                return fail(CSPH_EDEVICE, "mesh bounds: %s", hipGetErrorString(q));
-        }
-        __builtin_ia32_pause();
-    }
+    CSPH_HIP(launch_bounds_host(x, y, z, d, n, part, out, dslot, want, st));
+    csph_status r = poll_slot(hb, want, st, "mesh bounds");
+    if (r) return r;
     for (int k = 0; k < 7; ++k) b[k] = ((volatile const double *)hb->b)[k];
     *done = true;
+    return CSPH_OK;
+}
+
+// A 64-bit device word to the host: through the thread's slot when it can be had (the word
+// as b[0]'s bits), else a copy and a synchronisation.
+static csph_status word_to_host(const unsigned long long *src, unsigned long long *out,
+                                hipStream_t st) {
+    HostBounds *dslot = nullptr, *hb = host_slot(&dslot);
+    if (hb) {
+        const unsigned long long want = ++g_poll.seq;
+        CSPH_HIP(launch_word_host(src, dslot, want, st));
+        csph_status r = poll_slot(hb, want, st, "device word");
+        if (r) return r;
+        *out = ((volatile const unsigned long long *)hb->b)[0];
+        return CSPH_OK;
+    }
+    CSPH_HIP(hipMemcpyAsync(out, src, sizeof(*out), hipMemcpyDeviceToHost, st));
+    CSPH_HIP(hipStreamSynchronize(st));
     return CSPH_OK;
 }
 
@@ -1366,8 +1401,8 @@ static csph_status vjp_common(const csph_state *s_in, const csph_params *p, doub
     DtInfo *info = nullptr;
     if (cfl_dt) {
         unsigned long long bits = 0;
-        CSPH_HIP(hipMemcpyAsync(&bits, w.dtmin, sizeof(bits), hipMemcpyDeviceToHost, st));
-        CSPH_HIP(hipStreamSynchronize(st));
+        r = word_to_host(w.dtmin, &bits, st);
+        if (r) return r;
         double tau;
         memcpy(&tau, &bits, sizeof(tau));
         dt = p->cfl * tau;

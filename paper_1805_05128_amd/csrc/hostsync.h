@@ -1,5 +1,6 @@
-// The mesh bounds handed to the host through pinned memory that the host polls (k_bin.hip),
-// instead of a device-to-host copy and a stream synchronisation.
+// Small results handed to the host through pinned memory that the host polls (k_bin.hip):
+// the mesh bounds, and single device words (the CFL step's minimum), instead of a
+// device-to-host copy and a stream synchronisation.
 #pragma once
 
 #include "csph_internal.h"
@@ -17,5 +18,9 @@ struct alignas(64) HostBounds {
 hipError_t launch_bounds_host(const double *x, const double *y, const double *z,
                               const double *d, int64_t n, double *part, double *out,
                               HostBounds *hb, unsigned long long seq, hipStream_t st);
+
+// One 64-bit word to the slot (as b[0]'s bits), then `seq`, as launch_bounds_host does.
+hipError_t launch_word_host(const unsigned long long *src, HostBounds *hb,
+                            unsigned long long seq, hipStream_t st);
 
 }  // namespace csph

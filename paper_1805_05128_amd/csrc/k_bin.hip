@@ -116,6 +116,19 @@ hipError_t launch_bounds_host(const double *x, const double *y, const double *z,
     return hipGetLastError();
 }
 
+__global__ void k_word_host(const unsigned long long *__restrict__ src, HostBounds *hb,
+                            unsigned long long seq) {
+    if (threadIdx.x != 0) return;
+    ((unsigned long long *)hb->b)[0] = *src;
+    __hip_atomic_store(&hb->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+hipError_t launch_word_host(const unsigned long long *src, HostBounds *hb,
+                            unsigned long long seq, hipStream_t st) {
+    k_word_host<<<1, 64, 0, st>>>(src, hb, seq);
+    return hipGetLastError();
+}
+
 hipError_t launch_bounds(const double *x, const double *y, const double *z, const double *d,
                          int64_t n, double *part, double *out, hipStream_t st) {
     int64_t want = (n + kBlock - 1) / kBlock;
