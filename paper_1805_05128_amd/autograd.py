@@ -27,13 +27,6 @@ from . import api as A
 STATE8 = A.GRAD_FIELDS
 
 
-def _clone_state(s: A.State) -> A.State:
-    """Copy of the evolving fields; mass, material and (pair-h mode) the particle sizes are
-    shared (constant)."""
-    t = {k: (v if k == "m" else v.clone()) for k, v in s.t.items()}
-    return A.State(t, s.mat, s.d, None)
-
-
 def _fresh_like(s: A.State) -> A.State:
     """Uninitialised evolving fields for a step's output; mass, material and sizes shared."""
     t = {k: (v if k == "m" else torch.empty_like(v)) for k, v in s.t.items()}
@@ -84,19 +77,28 @@ class CSPHRollout(torch.autograd.Function):
                       "m": base["m"]}, base["mat"], base.get("d"))
         sc = A.StepScalars(vx0.device, t0=t0)
         ckpts = []
-        dt_dev, t_dev = [], []
+        # each step writes its dt straight into the record (sc.dt a view of one slot); the
+        # start times follow on the host, t_{k+1} = t_k + dt_k, the step's own FP64 addition
+        dt_rec = torch.empty(nsteps, dtype=torch.float64, device=vx0.device)
         replay = dataclasses.replace(pg, cfl=0.0)
+        # every step writes a fresh state, so a checkpoint is the state itself (no copies)
         for k in range(nsteps):
             if k % every == 0:
-                ckpts.append(_clone_state(st))
-            t_dev.append(sc.t.clone())
+                ckpts.append(st)
+            nxt = _fresh_like(st)
+            sc.dt = dt_rec[k:k + 1]
             if dts is None:
-                A.csph_step(st, pg, sc, s_out=st, totals=False)
+                A.csph_step(st, pg, sc, s_out=nxt, totals=False)
             else:
-                A.csph_step(st, replay, sc, s_out=st, dt_in=float(dts[k]), totals=False)
-            dt_dev.append(sc.dt.clone())
-        dt_list = torch.cat(dt_dev).cpu().tolist() if nsteps else []
-        t_list = torch.cat(t_dev).cpu().tolist() if nsteps else []
+                A.csph_step(st, replay, sc, s_out=nxt, dt_in=float(dts[k]), totals=False)
+            st = nxt
+        dt_list = dt_rec.cpu().tolist()
+        t_list, tk = [], float(t0)
+        for dt in dt_list:
+            t_list.append(tk)
+            tk = tk + dt
+        if nsteps and tk != float(sc.t.item()):
+            raise RuntimeError("the recorded start times do not reproduce the device's time")
         torch.cuda.synchronize()
         info["dts"] = dt_list
         info["forward_s"] = time.perf_counter() - tic
