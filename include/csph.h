@@ -33,8 +33,13 @@
  *               per-particle records of up to 32 bytes with 32-bit offsets.
  *   Streams.    Work is enqueued on `stream` (a hipStream_t; NULL = default
  *               stream).  Calls that must learn a size on the host (mesh
- *               dimensions, neighbour count) synchronise that stream; the
- *               others return as soon as the work is enqueued.
+ *               dimensions, neighbour count) wait for that stream; the
+ *               others return as soon as the work is enqueued.  The mesh
+ *               bounds (and the CFL step's minimum in its VJP) reach the
+ *               host through a small pinned buffer per host thread and
+ *               device, allocated on first use and held until the process
+ *               ends, which the host polls (csph_step_static copies and
+ *               synchronises instead).
  *   Errors.     Every call returns a csph_status.  CSPH_EINVAL: a bad
  *               argument (NULL where required, n < 0, bad parameters);
  *               CSPH_ECAPACITY: an output or workspace is too small;
