@@ -1,6 +1,8 @@
 """The library's Sod tube against the oracle's (and so against the exact Riemann solution the
-oracle is checked on): 160 x 7 x 7 particles, periodic across, fixed h, the CFL rule, to
-t ~ 12 (57 steps) in FP64 and in mixed precision, particle order kept."""
+oracle is checked on): 160 x 7 x 7 particles, periodic across, the CFL rule, to t ~ 12, particle
+order kept; fixed h (57 steps) in FP64 and in mixed precision, and the paper's pair-h mode
+(kappa = 1.936) with the sizes d = (m/rho)^(1/3) formed on the host before every step, as a
+caller does, in FP64."""
 import numpy as np
 import pytest
 import torch
@@ -52,3 +54,26 @@ def test_sod_tube_matches_the_oracle(oracle_run, prec, tol):
     for k, scale in (("x", 1.0), ("vx", 1.0), ("rho", 1.0), ("E", 1.0)):
         err = np.abs(to_np(g[k]) - s_ref[k]).max()
         assert err <= tol * scale, (k, err)
+
+
+def test_sod_tube_pair_h_matches_the_oracle():
+    w = _tube()
+    cfg = O.cfg_for(w, search=1, h_mode=1, kappa=1.936)
+    s = O.state_from(w, cfg)
+    t, nsteps = 0.0, 0
+    while t < T_END:
+        s, t, _, _ = O.step(cfg, s, t, d=np.cbrt(s["m"] / s["rho"]))
+        nsteps += 1
+    print(f"[case] sod tube pair-h n={w.n} steps={nsteps}", flush=True)
+    params = P.Params.from_workload(w, reorder=False, h_mode="pair", kappa=1.936, cell_size=0.0)
+    g = P.state_from_workload(w, params, DEV)
+    m = to_np(g["m"])
+    sc = P.StepScalars(DEV)
+    for _ in range(nsteps):
+        g.d = torch.as_tensor(np.cbrt(m / to_np(g["rho"])), device=DEV)
+        P.csph_step(g, params, sc, s_out=g, totals=False)
+    torch.cuda.synchronize()
+    assert abs(to_np(sc.t)[0] - t) <= 1e-12 * t
+    for k in ("x", "vx", "rho", "E"):
+        err = np.abs(to_np(g[k]) - s[k]).max()
+        assert err <= 1e-9, (k, err)
