@@ -633,7 +633,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "decomposition is described in DESIGN.md, not built", file=sys.stderr)
+              "decomposition (one Voronoi subdomain per GPU) is designed, not built", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
