@@ -2,7 +2,7 @@
 oracle is checked on): 160 x 7 x 7 particles, periodic across, the CFL rule, to t ~ 12, particle
 order kept; fixed h (57 steps) in FP64 and in mixed precision, and the paper's pair-h mode
 (kappa = 1.936) with the sizes d = (m/rho)^(1/3) formed on the host before every step, as a
-caller does, in FP64."""
+caller does, in FP64, and the two-stage Runge-Kutta step in FP64."""
 import numpy as np
 import pytest
 import torch
@@ -71,6 +71,27 @@ def test_sod_tube_pair_h_matches_the_oracle():
     sc = P.StepScalars(DEV)
     for _ in range(nsteps):
         g.d = torch.as_tensor(np.cbrt(m / to_np(g["rho"])), device=DEV)
+        P.csph_step(g, params, sc, s_out=g, totals=False)
+    torch.cuda.synchronize()
+    assert abs(to_np(sc.t)[0] - t) <= 1e-12 * t
+    for k in ("x", "vx", "rho", "E"):
+        err = np.abs(to_np(g[k]) - s[k]).max()
+        assert err <= 1e-9, (k, err)
+
+
+def test_sod_tube_rk2_matches_the_oracle():
+    w = _tube()
+    cfg = O.cfg_for(w, search=1, integrator=1)
+    s = O.state_from(w, cfg)
+    t, nsteps = 0.0, 0
+    while t < T_END:
+        s, t, _, _ = O.step(cfg, s, t)
+        nsteps += 1
+    print(f"[case] sod tube rk2 n={w.n} steps={nsteps}", flush=True)
+    params = P.Params.from_workload(w, reorder=False, integrator="rk2")
+    g = P.state_from_workload(w, params, DEV)
+    sc = P.StepScalars(DEV)
+    for _ in range(nsteps):
         P.csph_step(g, params, sc, s_out=g, totals=False)
     torch.cuda.synchronize()
     assert abs(to_np(sc.t)[0] - t) <= 1e-12 * t
